@@ -1,0 +1,211 @@
+"""Plain FP64 CPU oracle of randomized Block Krylov Iteration.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import, call or execute anything under
+``oracle/``.  It shares no code with the GPU library and imports nothing from
+it.
+
+What it computes: the output of Algorithm 2 (Block Krylov Iteration, Section
+2.1 of Musco & Musco, "Randomized Block Krylov Methods for Stronger and Faster
+Approximate Singular Value Decomposition") for a given A, sketch Pi, rank k and
+depth q, in float64 with NumPy/LAPACK:
+
+  K  = [A Pi, (A A^T) A Pi, ..., (A A^T)^q A Pi]          (step 2)
+  Q  = an orthonormal basis of span(K), n x (q+1)k         (step 3)
+  M  = Q^T A A^T Q                                         (step 4)
+  U_k = the top-k eigenvectors of the PSD matrix M         (step 5; SVD = eig)
+  Z  = Q U_k,  Ritz values sigma_i = sqrt(theta_i)          (step 6, Lemma 1)
+
+Readings of the paper taken here (each also listed in the design notes):
+* q+1 blocks, so m = (q+1)k (step 2 lists q+1 blocks; steps 3-4 print "qk").
+* The orthonormalization method is free: only span(K) matters (Section 4.2,
+  the explicit-K-then-QR variant, and per-block reorthonormalization "gives an
+  equivalent algorithm in exact arithmetic").  Route A orthonormalizes block
+  by block (block classical Gram-Schmidt twice + Householder QR); route B forms
+  the literally per-block-normalized K and QR's it at once; route C replaces
+  the eigen-solve of M by the SVD of Q^T A (Lemma 1).
+* Top-k: eigenvalues descending, ties to the lower index; each column of Z is
+  signed so that its largest-magnitude entry (lowest row on ties) is positive.
+* Ritz values are sigma_i = sqrt(max(theta_i, 0)) (Lemma 1: M = U S^2 U^T).
+* Breakdown: block 0 numerically rank deficient -> RankError; a later block
+  whose projected residual has a singular value <= tau * (its norm before the
+  projection) stops the iteration there (q_eff = i - 1), which is exact when
+  the Krylov space has become invariant.
+* Centering (footnote on PCA in Section 1): rows mean-centred implicitly,
+  A_c = A - mu 1^T with mu the row means, applied as rank-1 corrections.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+__all__ = [
+    "RankError", "BKIResult", "LinearOperator", "validate",
+    "block_krylov", "block_krylov_route_b", "rayleigh_ritz_svd",
+    "rayleigh_ritz", "simultaneous_iteration", "sign_normalize",
+]
+
+
+class RankError(ValueError):
+    """A Pi is numerically rank deficient (A = 0 or rank(A) < k)."""
+
+
+@dataclasses.dataclass
+class BKIResult:
+    Z: np.ndarray          # n x k, orthonormal columns
+    sigma: np.ndarray      # k Ritz values, descending
+    theta: np.ndarray      # all m' eigenvalues of M, descending
+    Q: np.ndarray          # n x m' orthonormal basis of the Krylov space
+    Ubar: np.ndarray       # m' x m' eigenvectors of M (columns, descending)
+    q_eff: int             # number of (A A^T) applications actually used
+
+
+class LinearOperator:
+    """A (dense ndarray or scipy.sparse matrix), optionally row-centred.
+
+    mul(X)  = A X   - mu (1^T X)
+    tmul(Y) = A^T Y - 1 (mu^T Y)      (mu = row means when centred, else 0)."""
+
+    def __init__(self, A, center: bool = False):
+        self.A = A
+        self.n, self.d = A.shape
+        self.center = center
+        if center:
+            rs = np.asarray(A.sum(axis=1), dtype=np.float64).reshape(-1)
+            self.mu = rs / self.d
+        else:
+            self.mu = None
+
+    def mul(self, X):
+        out = np.asarray(self.A @ X, dtype=np.float64)
+        if self.center:
+            out = out - np.outer(self.mu, X.sum(axis=0))
+        return out
+
+    def tmul(self, Y):
+        out = np.asarray(self.A.T @ Y, dtype=np.float64)
+        if self.center:
+            out = out - np.outer(np.ones(self.d), self.mu @ Y)
+        return out
+
+
+def validate(n: int, d: int, k: int, q: int) -> None:
+    """Argument rules shared with the library's boundary (ValueError here)."""
+    if k < 1 or q < 0:
+        raise ValueError("need k >= 1 and q >= 0")
+    if k > min(n, d):
+        raise ValueError("need k <= min(n, d)")
+    if (q + 1) * k > min(n, d):
+        raise ValueError("need (q+1) k <= min(n, d); use a dense SVD instead")
+
+
+def sign_normalize(Z: np.ndarray) -> np.ndarray:
+    """Flip each column so its largest-|.| entry (lowest index on ties) is > 0."""
+    idx = np.argmax(np.abs(Z), axis=0)          # argmax returns the first maximum
+    s = np.sign(Z[idx, np.arange(Z.shape[1])])
+    s[s == 0] = 1.0
+    return Z * s
+
+
+def _qr_pos(B: np.ndarray):
+    """Householder thin QR with diag(R) >= 0."""
+    Qb, Rb = np.linalg.qr(B)
+    s = np.sign(np.diag(Rb))
+    s[s == 0] = 1.0
+    return Qb * s, Rb * s[:, None]
+
+
+def rayleigh_ritz(op: LinearOperator, Q: np.ndarray, k: int):
+    """Steps 4-6 of Algorithm 2 on a given orthonormal basis Q.
+
+    Forms W = A^T Q explicitly, M = W^T W (= Q^T A A^T Q), its eigenpairs in
+    descending order, Z = Q U_k and sigma = sqrt(theta_1..k)."""
+    W = op.tmul(Q)
+    M = W.T @ W
+    M = 0.5 * (M + M.T)
+    theta, U = np.linalg.eigh(M)                # ascending
+    order = np.argsort(-theta, kind="stable")   # descending, ties -> lower index
+    theta = theta[order]
+    U = U[:, order]
+    Z = sign_normalize(Q @ U[:, :k])
+    sigma = np.sqrt(np.maximum(theta[:k], 0.0))
+    return Z, sigma, theta, U
+
+
+def block_krylov(A, Pi, k: int, q: int, *, center: bool = False,
+                 tau: float = 1e-12) -> BKIResult:
+    """Route A: Algorithm 2 with the blocks orthonormalized as they are formed.
+
+    B_0 = A Pi;  Q_0 = QR(B_0).
+    For i = 1..q:  B_i = A (A^T Q_{i-1})  -- a vector of span{(A A^T)^i A Pi}
+                   plus lower powers, so span{Q_0..Q_i} = span{K_0..K_i};
+                   B_i <- (I - Q_<i Q_<i^T) B_i, done twice;
+                   Q_i = QR(B_i).
+    Then Rayleigh-Ritz on Q = [Q_0 .. Q_q]."""
+    op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
+    n, d = op.n, op.d
+    validate(n, d, k, q)
+    Pi = np.asarray(Pi, dtype=np.float64)
+    if Pi.shape != (d, k):
+        raise ValueError(f"Pi must be {d} x {k}")
+    B = op.mul(Pi)
+    sv = np.linalg.svd(B, compute_uv=False)
+    if not np.all(np.isfinite(B)):
+        raise ValueError("non-finite entries")
+    if sv[-1] <= tau * max(np.linalg.norm(B), np.finfo(float).tiny):
+        raise RankError("A Pi is numerically rank deficient")
+    blocks = [_qr_pos(B)[0]]
+    q_eff = q
+    for i in range(1, q + 1):
+        B = op.mul(op.tmul(blocks[-1]))
+        before = np.linalg.norm(B)
+        P = np.hstack(blocks)
+        for _ in range(2):
+            B = B - P @ (P.T @ B)
+        sv = np.linalg.svd(B, compute_uv=False)
+        if sv[-1] <= tau * before:
+            q_eff = i - 1
+            break
+        blocks.append(_qr_pos(B)[0])
+    Q = np.hstack(blocks)
+    Z, sigma, theta, U = rayleigh_ritz(op, Q, k)
+    return BKIResult(Z, sigma, theta, Q, U, q_eff)
+
+
+def block_krylov_route_b(A, Pi, k: int, q: int, *, center: bool = False) -> BKIResult:
+    """Route B: the literal K = [K_0 .. K_q] with K_0 = orth(A Pi) and
+    K_i = orth(A A^T K_{i-1}) (within-block normalization only, which keeps
+    span K_i = span (A A^T)^i A Pi), then one Householder QR of all of K and
+    the same Rayleigh-Ritz step.  For small q and well-conditioned inputs."""
+    op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
+    validate(op.n, op.d, k, q)
+    Kb = [_qr_pos(op.mul(np.asarray(Pi, dtype=np.float64)))[0]]
+    for _ in range(q):
+        Kb.append(_qr_pos(op.mul(op.tmul(Kb[-1])))[0])
+    Q = _qr_pos(np.hstack(Kb))[0]
+    Z, sigma, theta, U = rayleigh_ritz(op, Q, k)
+    return BKIResult(Z, sigma, theta, Q, U, q)
+
+
+def rayleigh_ritz_svd(A, Q: np.ndarray, k: int, *, center: bool = False):
+    """Route C (Lemma 1): Z = Q * (top-k left singular vectors of Q^T A),
+    sigma = the top-k singular values of Q^T A.  No eigen-solve of M."""
+    op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
+    QtA = op.tmul(Q).T                       # (A^T Q)^T = Q^T A, m x d
+    Ub, s, _ = np.linalg.svd(QtA, full_matrices=False)
+    Z = sign_normalize(Q @ Ub[:, :k])
+    return Z, s[:k]
+
+
+def simultaneous_iteration(A, Pi, k: int, q: int, *, center: bool = False) -> BKIResult:
+    """Algorithm 1: K = (A A^T)^q A Pi, re-orthonormalized after every
+    application of A A^T (Section 4.1), then the same Rayleigh-Ritz on the
+    k-dimensional span."""
+    op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
+    validate(op.n, op.d, k, 0)
+    X = _qr_pos(op.mul(np.asarray(Pi, dtype=np.float64)))[0]
+    for _ in range(q):
+        X = _qr_pos(op.mul(op.tmul(X)))[0]
+    Z, sigma, theta, U = rayleigh_ritz(op, X, k)
+    return BKIResult(Z, sigma, theta, X, U, q)

@@ -1,0 +1,68 @@
+"""Error measures of the paper, in float64 (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
+leg may import this.
+
+* Frobenius-norm error, eq. (1):  ||A - Z Z^T A||_F / ||A - A_k||_F, computed
+  through the matrix Pythagorean theorem of Section 3.2,
+  ||A - Z Z^T A||_F^2 = ||A||_F^2 - ||Z^T A||_F^2.
+* Spectral-norm error, eq. (2):   ||A - Z Z^T A||_2 / sigma_{k+1}.
+* Per-vector error, eq. (3), reported as in Section 7 (largest deviation over
+  the top k, relative to sigma_{k+1}^2):
+  max_i |sigma_i^2 - z_i^T A A^T z_i| / sigma_{k+1}^2.
+* Largest principal angle between two k-dimensional subspaces.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["frobenius_ratio", "spectral_ratio", "per_vector_error",
+           "principal_angle", "principal_angle_sin"]
+
+
+def _op(A):
+    from .bki import LinearOperator
+    return A if isinstance(A, LinearOperator) else LinearOperator(A)
+
+
+def frobenius_ratio(A, Z, sigma_true, k: int) -> float:
+    op = _op(A)
+    ZtA = op.tmul(Z).T
+    if hasattr(op.A, "multiply"):
+        fro2 = float(op.A.multiply(op.A).sum())
+    else:
+        fro2 = float(np.sum(np.asarray(op.A, dtype=np.float64) ** 2))
+    if op.center:
+        # ||A - mu 1^T||_F^2 = ||A||_F^2 - d ||mu||^2
+        fro2 -= op.d * float(op.mu @ op.mu)
+    tail = float(np.sum(np.asarray(sigma_true[k:], dtype=np.float64) ** 2))
+    return float(np.sqrt(max(fro2 - np.sum(ZtA ** 2), 0.0) / tail))
+
+
+def spectral_ratio(A, Z, sigma_true, k: int) -> float:
+    """Dense: needs A as an ndarray (small inputs)."""
+    A = np.asarray(A, dtype=np.float64)
+    R = A - Z @ (Z.T @ A)
+    return float(np.linalg.norm(R, 2) / sigma_true[k])
+
+
+def per_vector_error(A, Z, sigma_true, k: int) -> float:
+    op = _op(A)
+    W = op.tmul(Z)                       # A^T z_i in column i
+    captured = np.sum(W ** 2, axis=0)    # z_i^T A A^T z_i
+    s2 = np.asarray(sigma_true[:k], dtype=np.float64) ** 2
+    return float(np.max(np.abs(s2 - captured)) / sigma_true[k] ** 2)
+
+
+def principal_angle_sin(Z1, Z2) -> float:
+    """sin of the largest principal angle between span(Z1) and span(Z2),
+    both with orthonormal columns: ||Z2 - Z1 (Z1^T Z2)||_2 (accurate for small
+    angles, unlike arccos of the smallest cosine)."""
+    Z1 = np.asarray(Z1, dtype=np.float64)
+    Z2 = np.asarray(Z2, dtype=np.float64)
+    R = Z2 - Z1 @ (Z1.T @ Z2)
+    return float(min(np.linalg.norm(R, 2), 1.0))
+
+
+def principal_angle(Z1, Z2) -> float:
+    return float(np.arcsin(principal_angle_sin(Z1, Z2)))

@@ -1,0 +1,217 @@
+"""Pins of the oracle's Block Krylov Iteration against what the paper and the
+mathematics fix (not against the oracle itself):
+
+* exact special cases that reduce to a dense SVD (numpy.linalg.svd);
+* three independently coded span routes (Section 4.2: any orthonormalization
+  of K gives the same result in exact arithmetic; Lemma 1 route);
+* Ritz-value interlacing (proof of Theorem 10) and nestedness in q;
+* Lemma 1's identity and Z^T Z = I;
+* the matrix Pythagorean identity of Section 3.2;
+* planted spectra with known sigma; breakdown / argument rules."""
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse as sp
+
+import workloads
+from oracle import bki, metrics, philox
+
+
+def _rand(n, d, seed):
+    return np.random.default_rng(seed).standard_normal((n, d))
+
+
+def _proj_dist(Z1, Z2):
+    return np.linalg.norm(Z1 @ Z1.T - Z2 @ Z2.T, 2)
+
+
+def test_exact_when_krylov_space_holds_column_space():
+    # rank(A) = 12 <= m = (q+1)k: span Q = col(A), so Z = U_k and the Ritz
+    # values are the true singular values (brute force: numpy SVD).
+    A = workloads.planted_dense(40, 30, np.linspace(3.0, 0.5, 12), seed=1)
+    k, q = 3, 3
+    res = bki.block_krylov(A, philox.gaussian(11, 30, k), k, q)
+    U, s, _ = np.linalg.svd(A)
+    assert np.allclose(res.sigma, s[:k], rtol=1e-12, atol=0)
+    assert _proj_dist(res.Z, U[:, :k]) < 1e-10
+
+
+def test_exact_full_rank_square_space():
+    # m = (q+1)k = min(n, d) = 30 with a generic full-rank A
+    A = _rand(40, 30, 2)
+    k, q = 3, 9
+    res = bki.block_krylov(A, philox.gaussian(12, 30, k), k, q)
+    U, s, _ = np.linalg.svd(A)
+    assert res.q_eff == q
+    assert np.allclose(res.sigma, s[:k], rtol=1e-10)
+    assert _proj_dist(res.Z, U[:, :k]) < 1e-8
+
+
+def test_rank_k_input_exact_at_q0():
+    sig = np.array([5.0, 2.0, 1.0, 0.5])
+    A = workloads.planted_dense(50, 35, sig, seed=3)
+    res = bki.block_krylov(A, philox.gaussian(13, 35, 4), 4, 0)
+    assert np.allclose(res.sigma, sig, rtol=1e-12)
+    U, _, _ = np.linalg.svd(A)
+    assert _proj_dist(res.Z, U[:, :4]) < 1e-12
+
+
+def test_routes_agree():
+    A = workloads.planted_dense(300, 200, workloads.spectrum("inv_sqrt", 200), seed=4)
+    Pi = philox.gaussian(14, 200, 6)
+    a = bki.block_krylov(A, Pi, 6, 4)
+    b = bki.block_krylov_route_b(A, Pi, 6, 4)
+    zc, sc = bki.rayleigh_ritz_svd(A, a.Q, 6)
+    assert np.allclose(a.sigma, b.sigma, rtol=1e-10)
+    assert np.allclose(a.sigma, sc, rtol=1e-12)
+    assert metrics.principal_angle(a.Z, b.Z) < 1e-7
+    assert metrics.principal_angle(a.Z, zc) < 1e-10
+    # the bases themselves span the same space
+    assert np.linalg.norm(a.Q - b.Q @ (b.Q.T @ a.Q), 2) < 1e-8
+
+
+def test_interlacing_and_ritz_identity():
+    A = _rand(120, 90, 5) * np.linspace(2.0, 0.1, 90)
+    res = bki.block_krylov(A, philox.gaussian(15, 90, 5), 5, 3)
+    s = np.linalg.svd(A, compute_uv=False)
+    assert np.all(res.sigma <= s[:5] * (1 + 1e-12))
+    # sigma_i = ||A^T z_i|| (z_i^T A A^T z_i = theta_i, proof of Theorem 10)
+    assert np.allclose(np.linalg.norm(A.T @ res.Z, axis=0), res.sigma, rtol=1e-12)
+    # Z^T Z = I (Lemma 1) and Z^T A A^T Z is diagonal with theta
+    assert np.allclose(res.Z.T @ res.Z, np.eye(5), atol=1e-13)
+    G = (A.T @ res.Z).T @ (A.T @ res.Z)
+    assert np.allclose(G, np.diag(res.sigma ** 2), atol=1e-12 * s[0] ** 2)
+
+
+def test_lemma1_projection_identity():
+    A = _rand(80, 60, 6)
+    res = bki.block_krylov(A, philox.gaussian(16, 60, 4), 4, 2)
+    Q = res.Q
+    Ub, sb, Vb = np.linalg.svd(Q.T @ A, full_matrices=False)
+    best = Q @ ((Ub[:, :4] * sb[:4]) @ Vb[:4])          # Q (Q^T A)_k
+    assert np.allclose(res.Z @ (res.Z.T @ A), best, atol=1e-12)
+
+
+def test_nested_in_q():
+    A = workloads.planted_dense(200, 150, workloads.spectrum("inv", 150), seed=7)
+    Pi = philox.gaussian(17, 150, 5)
+    prev = None
+    for q in range(0, 6):
+        s = bki.block_krylov(A, Pi, 5, q).sigma
+        if prev is not None:
+            assert np.all(s >= prev * (1 - 1e-13))
+        prev = s
+
+
+def test_block_krylov_dominates_simultaneous_iteration():
+    # span (A A^T)^q A Pi  is inside the Krylov space of the same Pi, so by
+    # Courant-Fischer BKI's Ritz values are >= SI's at equal q (Section 2).
+    A = workloads.planted_dense(300, 200, workloads.spectrum("inv_sqrt", 200), seed=8)
+    Pi = philox.gaussian(18, 200, 8)
+    for q in (0, 2, 4):
+        b = bki.block_krylov(A, Pi, 8, q)
+        s = bki.simultaneous_iteration(A, Pi, 8, q)
+        assert np.all(b.sigma >= s.sigma * (1 - 1e-12))
+        if q == 0:
+            assert np.allclose(b.sigma, s.sigma, rtol=1e-12)
+    sv = workloads.spectrum("inv_sqrt", 200)
+    pv_b = metrics.per_vector_error(A, bki.block_krylov(A, Pi, 8, 4).Z, sv, 8)
+    pv_s = metrics.per_vector_error(A, bki.simultaneous_iteration(A, Pi, 8, 4).Z, sv, 8)
+    assert pv_b < pv_s
+
+
+def test_metrics_on_exact_singular_vectors():
+    sv = workloads.spectrum("inv_sqrt", 60)
+    A = workloads.planted_dense(90, 60, sv, seed=9)
+    U, s, _ = np.linalg.svd(A)
+    Uk = U[:, :6]
+    assert np.allclose(s, sv, rtol=1e-12)
+    assert metrics.per_vector_error(A, Uk, sv, 6) < 1e-12
+    assert abs(metrics.spectral_ratio(A, Uk, sv, 6) - 1.0) < 1e-12
+    assert abs(metrics.frobenius_ratio(A, Uk, sv, 6) - 1.0) < 1e-12
+
+
+def test_frobenius_pythagoras_matches_direct():
+    sv = workloads.spectrum("inv", 50)
+    A = workloads.planted_dense(70, 50, sv, seed=10)
+    Z = bki.block_krylov(A, philox.gaussian(20, 50, 4), 4, 1).Z
+    direct = np.linalg.norm(A - Z @ (Z.T @ A), "fro") / np.sqrt(np.sum(sv[4:] ** 2))
+    assert abs(metrics.frobenius_ratio(A, Z, sv, 4) - direct) < 1e-12
+
+
+def test_principal_angle_against_scipy():
+    rng = np.random.default_rng(11)
+    Z1 = np.linalg.qr(rng.standard_normal((50, 5)))[0]
+    Z2 = np.linalg.qr(Z1 + 1e-3 * rng.standard_normal((50, 5)))[0]
+    want = np.max(scipy.linalg.subspace_angles(Z1, Z2))
+    assert abs(metrics.principal_angle(Z1, Z2) - want) < 1e-12
+
+
+def test_error_measures_shrink_with_q():
+    # eq. (1) and eq. (3) errors are non-increasing in q (nested spaces)
+    w = workloads.scaled(workloads.WORKLOADS["dense1"], 400, 200, k=10, q=0)
+    sv = workloads.spectrum(w.spectrum, 200)
+    A = workloads.planted_dense(w.n, w.d, sv, seed=w.seed_matrix)
+    Pi = philox.gaussian(w.seed_sketch, w.d, w.k)
+    fr, pv = [], []
+    for q in range(0, 6):
+        Z = bki.block_krylov(A, Pi, w.k, q).Z
+        fr.append(metrics.frobenius_ratio(A, Z, sv, w.k))
+        pv.append(metrics.per_vector_error(A, Z, sv, w.k))
+    assert all(f >= 1 - 1e-12 for f in fr)
+    assert all(b <= a * (1 + 1e-9) + 1e-14 for a, b in zip(fr, fr[1:]))
+    assert all(b <= a * (1 + 1e-9) + 1e-14 for a, b in zip(pv, pv[1:]))
+    assert pv[-1] < 0.1 * pv[0]
+
+
+def test_breakdown_stops_at_invariant_space():
+    # rank(A) = 2k exactly: block 1 completes the column space, block 2's
+    # projected residual is rounding noise -> q_eff = 1, result exact.
+    k = 4
+    sig = np.linspace(4.0, 1.0, 2 * k)
+    A = workloads.planted_dense(60, 45, sig, seed=12)
+    res = bki.block_krylov(A, philox.gaussian(22, 45, k), k, 4)
+    assert res.q_eff == 1
+    assert res.Q.shape[1] == 2 * k
+    assert np.allclose(res.sigma, sig[:k], rtol=1e-12)
+
+
+def test_rank_error_and_validation():
+    A = workloads.low_rank_dense(30, 20, 2, seed=13)
+    with pytest.raises(bki.RankError):
+        bki.block_krylov(A, philox.gaussian(1, 20, 3), 3, 0)
+    with pytest.raises(bki.RankError):
+        bki.block_krylov(np.zeros((30, 20)), philox.gaussian(1, 20, 2), 2, 1)
+    B = _rand(30, 20, 14)
+    for k, q in [(0, 1), (21, 0), (5, -1), (5, 4)]:
+        with pytest.raises(ValueError):
+            bki.block_krylov(B, philox.gaussian(1, 20, max(k, 1)), k, q)
+    with pytest.raises(ValueError):
+        bki.block_krylov(B, philox.gaussian(1, 19, 2), 2, 1)
+
+
+def test_centered_operator_matches_explicit_centering():
+    rp, ci, va = workloads.term_document_csr(300, 2000, seed=15, median_len=20)
+    A = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(300, 2000))
+    dense = A.toarray()
+    Ac = dense - dense.mean(axis=1, keepdims=True)
+    Pi = philox.gaussian(23, 2000, 5)
+    r1 = bki.block_krylov(A, Pi, 5, 3, center=True)
+    r2 = bki.block_krylov(Ac, Pi, 5, 3)
+    assert np.allclose(r1.sigma, r2.sigma, rtol=1e-11)
+    assert metrics.principal_angle(r1.Z, r2.Z) < 1e-8
+    # the centred rows sum to zero, so 1 is orthogonal to every A_c^T direction
+    assert abs(np.sum(Ac @ np.ones(2000))) < 1e-8
+    sv = np.linalg.svd(Ac, compute_uv=False)
+    assert np.all(r1.sigma <= sv[:5] * (1 + 1e-12))
+    fr_direct = np.linalg.norm(Ac - r1.Z @ (r1.Z.T @ Ac)) / np.sqrt(np.sum(sv[5:] ** 2))
+    op = bki.LinearOperator(A, center=True)
+    assert abs(metrics.frobenius_ratio(op, r1.Z, sv, 5) - fr_direct) < 1e-10
+
+
+def test_sign_normalization():
+    Z = np.array([[0.6, -0.8], [-0.8, 0.6]])
+    out = bki.sign_normalize(Z)
+    assert np.allclose(out, [[-0.6, 0.8], [0.8, -0.6]])
+    tie = bki.sign_normalize(np.array([[-0.5], [0.5]]))
+    assert tie[0, 0] > 0                      # tie -> the lower row decides
