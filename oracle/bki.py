@@ -27,10 +27,12 @@ Readings of the paper taken here (each also listed in the design notes):
 * Top-k: eigenvalues descending, ties to the lower index; each column of Z is
   signed so that its largest-magnitude entry (lowest row on ties) is positive.
 * Ritz values are sigma_i = sqrt(max(theta_i, 0)) (Lemma 1: M = U S^2 U^T).
-* Breakdown: block 0 numerically rank deficient -> RankError; a later block
-  whose projected residual has a singular value <= tau * (its norm before the
-  projection) stops the iteration there (q_eff = i - 1), which is exact when
-  the Krylov space has become invariant.
+* Breakdown: block 0 numerically rank deficient (smallest singular value of
+  A Pi <= tau ||A Pi||_F) -> RankError.  A later block whose projected
+  residual is negligible as a whole (||B_proj||_F <= tau ||B||_F, B before the
+  projection) stops the iteration there (q_eff = i - 1); this is exact when
+  the Krylov space has become invariant.  A block that is only partly
+  deficient is orthonormalized as it stands.
 * Centering (footnote on PCA in Section 1): rows mean-centred implicitly,
   A_c = A - mu 1^T with mu the row means, applied as rank-1 corrections.
 """
@@ -163,8 +165,7 @@ def block_krylov(A, Pi, k: int, q: int, *, center: bool = False,
         P = np.hstack(blocks)
         for _ in range(2):
             B = B - P @ (P.T @ B)
-        sv = np.linalg.svd(B, compute_uv=False)
-        if sv[-1] <= tau * before:
+        if np.linalg.norm(B) <= tau * before:
             q_eff = i - 1
             break
         blocks.append(_qr_pos(B)[0])

@@ -1,0 +1,256 @@
+"""Python binding of the Block Krylov library (torch tensors in, torch tensors
+out).  Every function only marshals arguments to libbk.so; all arithmetic
+runs in the HIP kernels.  torch provides device memory and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _need_cuda(*ts):
+    for t in ts:
+        if t is not None and not t.is_cuda:
+            raise ValueError("tensors must live on the GPU (device 'cuda')")
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return L.F64
+    if t.dtype == torch.float32:
+        return L.F32
+    if t.dtype == torch.bfloat16:
+        return L.BF16
+    if t.dtype == torch.uint8 or str(t.dtype).startswith("torch.float8_e4m3fn"):
+        return L.FP8_E4M3
+    raise TypeError(f"unsupported matrix dtype {t.dtype}")
+
+
+def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
+             breakdown_tol=0.0, pi=None, timing=False, save=False,
+             jacobi_block=0) -> L.Options:
+    o = L.Options()
+    o.struct_size = C.sizeof(L.Options)
+    o.refine = int(refine)
+    o.center_rows = int(bool(center))
+    o.max_jacobi_sweeps = int(max_sweeps)
+    o.jacobi_tol = float(jacobi_tol)
+    o.breakdown_tol = float(breakdown_tol)
+    o.pi = _ptr(pi)
+    o.timing = int(bool(timing))
+    o.save_for_backward = int(bool(save))
+    o.jacobi_block = int(jacobi_block)
+    return o
+
+
+@dataclass
+class SVDResult:
+    Z: torch.Tensor          # n x k orthonormal Ritz vectors
+    sigma: torch.Tensor      # k Ritz values (FP64), descending
+    info: dict
+    workspace: torch.Tensor | None = None   # forward state (save_for_backward)
+
+
+def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
+              A_master=None, refine: int = 0, pi=None, timing=False,
+              save_for_backward=False, max_sweeps=0, jacobi_tol=0.0,
+              breakdown_tol=0.0, jacobi_block=0, stream=None) -> SVDResult:
+    """Block Krylov Iteration on a dense A (n x d row-major on the GPU).
+
+    A's dtype selects the path: float64 / float32 (plain), bfloat16, or uint8
+    holding OCP e4m3 codes with ``a_scales`` (FP8).  Returns Z (n x k, FP64 for
+    the FP64 path, FP32 otherwise) and the Ritz values (FP64)."""
+    lib = L.load()
+    _need_cuda(A, a_scales, A_master, pi)
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D row-major tensor")
+    n, d = A.shape
+    code = _dtype_code(A)
+    if code == L.FP8_E4M3 and A.dtype != torch.uint8:
+        A = A.view(torch.uint8)
+    zdt = torch.float64 if code == L.F64 else torch.float32
+    if pi is not None:
+        pi = pi.to(zdt).contiguous()
+    if A_master is not None and (A_master.dtype != torch.float32 or A_master.stride(1) != 1):
+        raise ValueError("A_master must be a row-major float32 tensor")
+    opt = _options(refine=refine, pi=pi, timing=timing, save=save_for_backward,
+                   max_sweeps=max_sweeps, jacobi_tol=jacobi_tol,
+                   breakdown_tol=breakdown_tol, jacobi_block=jacobi_block)
+    nbytes = lib.bk_svd_dense_workspace(n, d, k, q, code, C.byref(opt))
+    if nbytes == 0:
+        raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
+    ws = _ws(nbytes, A.device)
+    Z = torch.empty(n, k, dtype=zdt, device=A.device)
+    sig = torch.empty(k, dtype=torch.float64, device=A.device)
+    info = L.Info()
+    st = lib.bk_svd_dense(_ptr(A), A.stride(0), code, _ptr(a_scales), _ptr(A_master),
+                          0 if A_master is None else A_master.stride(0), n, d, k, q,
+                          int(seed) & (2**64 - 1), C.byref(opt), _ptr(Z), Z.stride(0),
+                          _ptr(sig), C.byref(info), _ptr(ws), nbytes, _stream(stream))
+    L.check(st, "bk_svd_dense")
+    return SVDResult(Z, sig, info.as_dict(), ws if save_for_backward else None)
+
+
+def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 0, *,
+            transpose=None, center=False, pi=None, timing=False, max_sweeps=0,
+            jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, stream=None) -> SVDResult:
+    """Block Krylov Iteration on a CSR A (int32 row_ptr / col_idx, float32
+    values, on the GPU).  ``transpose`` = (t_row_ptr, t_col_idx, t_vals) of A^T
+    is optional; ``center`` applies implicit row centring."""
+    lib = L.load()
+    _need_cuda(row_ptr, col_idx, vals, pi)
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (vals, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise ValueError("CSR arrays must be contiguous int32/int32/float32")
+    nnz = col_idx.numel()
+    tr = transpose or (None, None, None)
+    if pi is not None:
+        pi = pi.to(torch.float32).contiguous()
+    opt = _options(center=center, pi=pi, timing=timing, max_sweeps=max_sweeps,
+                   jacobi_tol=jacobi_tol, breakdown_tol=breakdown_tol,
+                   jacobi_block=jacobi_block)
+    nbytes = lib.bk_svd_csr_workspace(n, d, nnz, k, q, C.byref(opt))
+    if nbytes == 0:
+        raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
+    ws = _ws(nbytes, row_ptr.device)
+    Z = torch.empty(n, k, dtype=torch.float32, device=row_ptr.device)
+    sig = torch.empty(k, dtype=torch.float64, device=row_ptr.device)
+    info = L.Info()
+    st = lib.bk_svd_csr(_ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(tr[0]), _ptr(tr[1]),
+                        _ptr(tr[2]), n, d, nnz, k, q, int(seed) & (2**64 - 1), C.byref(opt),
+                        _ptr(Z), Z.stride(0), _ptr(sig), C.byref(info), _ptr(ws), nbytes,
+                        _stream(stream))
+    L.check(st, "bk_svd_csr")
+    return SVDResult(Z, sig, info.as_dict())
+
+
+def gaussian(seed: int, rows: int, cols: int, dtype=torch.float32, device="cuda",
+             stream=None) -> torch.Tensor:
+    """The Philox4x32-10 / Box-Muller sketch (see bk_gaussian)."""
+    lib = L.load()
+    out = torch.empty(rows, cols, dtype=dtype, device=device)
+    code = L.F64 if dtype == torch.float64 else L.F32
+    L.check(lib.bk_gaussian(int(seed) & (2**64 - 1), rows, cols, cols, code, _ptr(out),
+                            _stream(stream)), "bk_gaussian")
+    return out
+
+
+def philox(ctr_key: torch.Tensor, stream=None) -> torch.Tensor:
+    """Raw Philox4x32-10 words: ctr_key int32/uint32 (count x 6) -> (count x 4)."""
+    lib = L.load()
+    _need_cuda(ctr_key)
+    x = ctr_key.contiguous()
+    out = torch.empty(x.shape[0], 4, dtype=x.dtype, device=x.device)
+    L.check(lib.bk_philox4x32_10(_ptr(x), x.shape[0], _ptr(out), _stream(stream)),
+            "bk_philox4x32_10")
+    return out
+
+
+def quantize(A: torch.Tensor, to: str, stream=None):
+    """A float32 (n x d) -> ("bf16": bfloat16 copy) or ("fp8": (uint8 e4m3
+    codes, float32 tile scales ceil(n/128) x ceil(d/128)))."""
+    lib = L.load()
+    _need_cuda(A)
+    if A.dtype != torch.float32 or A.stride(1) != 1:
+        raise ValueError("A must be a row-major float32 tensor")
+    n, d = A.shape
+    if to == "bf16":
+        out = torch.empty(n, d, dtype=torch.bfloat16, device=A.device)
+        L.check(lib.bk_quantize_dense(_ptr(A), n, d, A.stride(0), L.BF16, _ptr(out), None,
+                                      _stream(stream)), "bk_quantize_dense")
+        return out
+    if to == "fp8":
+        out = torch.empty(n, d, dtype=torch.uint8, device=A.device)
+        sc = torch.empty((n + 127) // 128, (d + 127) // 128, dtype=torch.float32,
+                         device=A.device)
+        L.check(lib.bk_quantize_dense(_ptr(A), n, d, A.stride(0), L.FP8_E4M3, _ptr(out),
+                                      _ptr(sc), _stream(stream)), "bk_quantize_dense")
+        return out, sc
+    raise ValueError("to must be 'bf16' or 'fp8'")
+
+
+def dense_product(A: torch.Tensor, X: torch.Tensor, trans: bool = False, a_scales=None,
+                  stream=None) -> torch.Tensor:
+    """Y = A X (trans False) or A^T X (trans True) with the library's kernels."""
+    lib = L.load()
+    _need_cuda(A, X, a_scales)
+    code = _dtype_code(A)
+    if code == L.FP8_E4M3 and A.dtype != torch.uint8:
+        A = A.view(torch.uint8)
+    n, d = A.shape
+    k = X.shape[1]
+    wdt = torch.float64 if code == L.F64 else torch.float32
+    X = X.to(wdt)
+    if X.stride(1) != 1:
+        X = X.contiguous()
+    Y = torch.empty(d if trans else n, k, dtype=wdt, device=A.device)
+    nbytes = lib.bk_dense_product_workspace(int(trans), n, d, k, code)
+    ws = _ws(nbytes, A.device)
+    L.check(lib.bk_dense_product(int(trans), _ptr(A), A.stride(0), code, _ptr(a_scales), n,
+                                 d, _ptr(X), X.stride(0), k, _ptr(Y), Y.stride(0), _ptr(ws),
+                                 nbytes, _stream(stream)), "bk_dense_product")
+    return Y
+
+
+def csr_product(row_ptr, col_idx, vals, cols: int, X: torch.Tensor, stream=None):
+    """Y = A X for a CSR A (rows = row_ptr.numel() - 1)."""
+    lib = L.load()
+    rows = row_ptr.numel() - 1
+    X = X.to(torch.float32).contiguous()
+    k = X.shape[1]
+    Y = torch.empty(rows, k, dtype=torch.float32, device=X.device)
+    L.check(lib.bk_csr_product(_ptr(row_ptr), _ptr(col_idx), _ptr(vals), rows, cols,
+                               col_idx.numel(), _ptr(X), k, k, _ptr(Y), k, _stream(stream)),
+            "bk_csr_product")
+    return Y
+
+
+def csr_transpose(row_ptr, col_idx, vals, cols: int, stream=None):
+    """CSR of A^T (column ids ascending within rows)."""
+    lib = L.load()
+    rows = row_ptr.numel() - 1
+    nnz = col_idx.numel()
+    dev = row_ptr.device
+    trp = torch.empty(cols + 1, dtype=torch.int32, device=dev)
+    tci = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)[:nnz]
+    tv = torch.empty(max(nnz, 1), dtype=torch.float32, device=dev)[:nnz]
+    nbytes = lib.bk_csr_transpose_workspace(rows, cols, nnz)
+    ws = _ws(nbytes, dev)
+    L.check(lib.bk_csr_transpose(_ptr(row_ptr), _ptr(col_idx), _ptr(vals), rows, cols, nnz,
+                                 _ptr(trp), _ptr(tci), _ptr(tv), _ptr(ws), nbytes,
+                                 _stream(stream)), "bk_csr_transpose")
+    return trp, tci, tv
+
+
+def eigh_psd(M: torch.Tensor, max_sweeps: int = 0, tol: float = 0.0, stream=None):
+    """theta (descending), V of a symmetric PSD float64 matrix, and the sweep
+    count (one-sided block Jacobi)."""
+    lib = L.load()
+    _need_cuda(M)
+    M = M.to(torch.float64).contiguous()
+    m = M.shape[0]
+    theta = torch.empty(m, dtype=torch.float64, device=M.device)
+    V = torch.empty(m, m, dtype=torch.float64, device=M.device)
+    nbytes = lib.bk_eigh_psd_workspace(m)
+    ws = _ws(nbytes, M.device)
+    sw = C.c_int32(0)
+    L.check(lib.bk_eigh_psd(_ptr(M), m, m, _ptr(theta), _ptr(V), m, int(max_sweeps),
+                            float(tol), C.byref(sw), _ptr(ws), nbytes, _stream(stream)),
+            "bk_eigh_psd")
+    return theta, V, int(sw.value)

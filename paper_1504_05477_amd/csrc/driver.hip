@@ -1,0 +1,1044 @@
+// Host driver and C ABI of the Block Krylov library.
+//
+// One solve (Algorithm 2):
+//   Pi (Philox)  ->  B_0 = A Pi  ->  Q_0 = orth(B_0)
+//   for i = 1..q:   Y_i = A^T Q_{i-1}      (kept: W = [Y_1 .. Y_{q+1}] = A^T Q)
+//                   B_i = A Y_i
+//                   B_i <- (I - Q_<i Q_<i^T) B_i   twice (block Gram-Schmidt)
+//                   Q_i = orth(B_i)   (shifted CholeskyQR3, FP64 Gram/Cholesky)
+//   Y_{q+1} = A^T Q_q;   M = W^T W (FP64)   (= Q^T A A^T Q)
+//   Jacobi(M) -> top-k (theta, U_k);   Z = Q U_k;   sigma = sqrt(theta)
+// Feeding the orthonormal block Q_{i-1} (not the raw power) into the next
+// product keeps every block well scaled (the per-block reorthonormalization
+// of Section 4.2), and it makes W = A^T Q a by-product of the loop: forming
+// M costs one extra k-wide product instead of an m-wide one.
+//
+// Breakdown of a block i >= 1 (invariant Krylov space) zeroes that block and
+// every later one follows (A A^T 0 = 0), so the Rayleigh-Ritz step over the
+// zero-padded basis equals the one over the blocks built so far: no host
+// round trip is needed inside the loop.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace bk {
+namespace {
+
+constexpr double kEps64 = 2.220446049250313e-16;
+constexpr double kUnit64 = 1.1102230246251565e-16;  // 2^-53
+constexpr int kLongRow = 4096;  // CSR rows longer than this get a workgroup
+
+// ------------------------------------------------------------ workspace --
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct Options {
+  int refine = 0, center = 0, max_sweeps = 40, timing = 0, save = 0, jblock = 0;
+  double jtol = 0.0, tau = 0.0;
+  const void* pi = nullptr;
+};
+
+Options read_options(const bk_options* o, bool f64) {
+  Options r;
+  if (o && o->struct_size >= static_cast<int32_t>(offsetof(bk_options, reserved))) {
+    r.refine = o->refine;
+    r.center = o->center_rows;
+    if (o->max_jacobi_sweeps > 0) r.max_sweeps = o->max_jacobi_sweeps;
+    r.jtol = o->jacobi_tol;
+    r.tau = o->breakdown_tol;
+    r.pi = o->pi;
+    r.timing = o->timing;
+    r.save = o->save_for_backward;
+    r.jblock = o->jacobi_block;
+  }
+  if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
+  return r;
+}
+
+double jacobi_tol_for(int64_t m, double user) {
+  return user > 0.0 ? user : 10.0 * std::sqrt(static_cast<double>(m)) * kEps64;
+}
+
+int jacobi_block_for(int64_t m, int user) {
+  return (user == 8 || user == 16) ? user : jacobi_default_block(m);
+}
+
+// Largest FP64 partial-sum buffer any TN call of a solve needs.
+int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) {
+  const int64_t m = static_cast<int64_t>(q + 1) * k;
+  int64_t need = std::max<int64_t>(tn_partial_elems(n, k, k), tn_partial_elems(d, m, static_cast<int>(m)));
+  if (!csr) need = std::max(need, tn_partial_elems(n, d, k));
+  for (int i = 1; i <= q; ++i)
+    need = std::max(need, tn_partial_elems(n, static_cast<int64_t>(i) * k, k));
+  if (refine) {
+    need = std::max(need, tn_partial_elems(n, d, k));
+    need = std::max(need, tn_partial_elems(d, k, k));
+  }
+  if (csr) {
+    need = std::max(need, tn_partial_elems(d, k, 1));
+    need = std::max(need, tn_partial_elems(n, k, 1));
+  }
+  return need;
+}
+
+struct JacobiWs {
+  double* Xc = nullptr;
+  double* Vc = nullptr;
+  double* norms = nullptr;
+  double* theta = nullptr;
+  int32_t* order = nullptr;
+  int64_t ldc = 0, nbp = 0;
+  int b = 16;
+};
+
+JacobiWs take_jacobi(Arena& ar, int64_t m, int jblock, bool withv) {
+  JacobiWs j;
+  j.b = jacobi_block_for(m, jblock);
+  j.nbp = jacobi_padded_cols(m, j.b);
+  j.ldc = m;
+  j.Xc = ar.take<double>(static_cast<size_t>(j.nbp * m));
+  if (withv) j.Vc = ar.take<double>(static_cast<size_t>(j.nbp * m));
+  j.norms = ar.take<double>(static_cast<size_t>(m));
+  j.theta = ar.take<double>(static_cast<size_t>(m));
+  j.order = ar.take<int32_t>(static_cast<size_t>(m));
+  return j;
+}
+
+struct Layout {
+  Ctrl* ctrl = nullptr;
+  void* Pi = nullptr;
+  void* Q = nullptr;
+  void* W = nullptr;
+  void* Bs = nullptr;
+  void* Bs2 = nullptr;
+  double* partial = nullptr;
+  double *G = nullptr, *Gpre = nullptr, *R = nullptr, *Rinv = nullptr,
+         *cholwork = nullptr, *Racc = nullptr, *Rtmp = nullptr;
+  double* C = nullptr;
+  double* M = nullptr;
+  JacobiWs jw;
+  double* Uk = nullptr;
+  double* sign = nullptr;
+  double* Rsave = nullptr;  // (q+1) x k x k, R_i of B_i = Q_i R_i (saved)
+  double* Csave = nullptr;  // (q+1) x m x k, total projection coefficients
+  double* ritz_dev = nullptr;
+  // refinement
+  float* Wk = nullptr;
+  double* Gk = nullptr;
+  double* Pk = nullptr;
+  JacobiWs jk;
+  // CSR
+  int32_t *trp = nullptr, *tci = nullptr, *cursor = nullptr, *long_a = nullptr,
+          *long_t = nullptr, *nlong = nullptr;
+  float* tv = nullptr;
+  unsigned long long* keys = nullptr;
+  float* mu = nullptr;
+  float* ones = nullptr;
+  double* colvec = nullptr;
+  size_t bytes = 0;
+};
+
+Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
+                   bool f64, const Options& o, bool csr, bool own_transpose) {
+  Arena ar;
+  ar.base = base;
+  Layout L;
+  const size_t es = f64 ? 8 : 4;
+  const int64_t m = static_cast<int64_t>(q + 1) * k;
+  L.ctrl = ar.take<Ctrl>(1);
+  L.Pi = ar.take<char>(static_cast<size_t>(d * k) * es);
+  L.Q = ar.take<char>(static_cast<size_t>(n * m) * es);
+  L.W = ar.take<char>(static_cast<size_t>(d * m) * es);
+  L.Bs = ar.take<char>(static_cast<size_t>(n * k) * es);
+  L.Bs2 = ar.take<char>(static_cast<size_t>(n * k) * es);
+  L.partial = ar.take<double>(static_cast<size_t>(partial_need(n, d, k, q, o.refine != 0, csr)));
+  const size_t kk = static_cast<size_t>(k) * k;
+  L.G = ar.take<double>(kk);
+  L.Gpre = ar.take<double>(kk);
+  L.R = ar.take<double>(kk);
+  L.Rinv = ar.take<double>(kk);
+  L.cholwork = ar.take<double>(kk);
+  L.Racc = ar.take<double>(kk);
+  L.Rtmp = ar.take<double>(kk);
+  L.C = ar.take<double>(static_cast<size_t>(m * k));
+  L.M = ar.take<double>(static_cast<size_t>(m * m));
+  L.jw = take_jacobi(ar, m, o.jblock, o.save != 0);
+  L.Uk = ar.take<double>(static_cast<size_t>(m * k));
+  L.sign = ar.take<double>(static_cast<size_t>(k));
+  L.ritz_dev = ar.take<double>(static_cast<size_t>(k));
+  if (o.save) {
+    L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
+    L.Csave = ar.take<double>(static_cast<size_t>(q + 1) * m * k);
+  }
+  if (o.refine) {
+    L.Wk = ar.take<float>(static_cast<size_t>(d * k));
+    L.Gk = ar.take<double>(kk);
+    L.Pk = ar.take<double>(kk);
+    L.jk = take_jacobi(ar, k, 0, true);
+  }
+  if (csr) {
+    if (own_transpose) {
+      L.trp = ar.take<int32_t>(static_cast<size_t>(d + 1));
+      L.tci = ar.take<int32_t>(static_cast<size_t>(nnz));
+      L.tv = ar.take<float>(static_cast<size_t>(nnz));
+      L.cursor = ar.take<int32_t>(static_cast<size_t>(d));
+      L.keys = ar.take<unsigned long long>(static_cast<size_t>(3 * nnz));
+    }
+    L.long_a = ar.take<int32_t>(static_cast<size_t>(n));
+    L.long_t = ar.take<int32_t>(static_cast<size_t>(d));
+    L.nlong = ar.take<int32_t>(2);
+    L.mu = ar.take<float>(static_cast<size_t>(n));
+    L.ones = ar.take<float>(static_cast<size_t>(d));
+    L.colvec = ar.take<double>(static_cast<size_t>(k));
+  }
+  L.bytes = align_up(ar.off, 256);
+  return L;
+}
+
+// ---------------------------------------------------------------- timer --
+struct Timer {
+  bool on = false;
+  hipStream_t s = nullptr;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+  int launches[BK_NPHASE] = {0};
+  int cur = -1;
+  hipEvent_t start{};
+  void begin(int ph) {
+    cur = ph;
+    if (!on) return;
+    hipEventCreate(&start);
+    hipEventRecord(start, s);
+  }
+  void end(int nlaunch) {
+    if (cur >= 0) launches[cur] += nlaunch;
+    if (on) {
+      hipEvent_t stop;
+      hipEventCreate(&stop);
+      hipEventRecord(stop, s);
+      marks.push_back({cur, {start, stop}});
+    }
+    cur = -1;
+  }
+  void collect(bk_info* info) {
+    if (!info) return;
+    for (int i = 0; i < BK_NPHASE; ++i) {
+      info->ms[i] = 0.0f;
+      info->launches[i] = launches[i];
+    }
+    for (auto& mk : marks) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, mk.second.first, mk.second.second) == hipSuccess)
+        info->ms[mk.first] += ms;
+    }
+  }
+  ~Timer() {
+    for (auto& mk : marks) {
+      hipEventDestroy(mk.second.first);
+      hipEventDestroy(mk.second.second);
+    }
+  }
+};
+
+// ------------------------------------------------------------ operators --
+struct Op {
+  int64_t n = 0, d = 0;
+  bool f64 = false;
+  double* partial = nullptr;
+  Timer* tm = nullptr;
+  virtual ~Op() = default;
+  // Y (n x k, ldy) = A X, X d x k (ldx)
+  virtual void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) = 0;
+  // Y (d x k, ldy) = A^T X, X n x k (ldx)
+  virtual void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) = 0;
+};
+
+struct DenseOp : Op {
+  const void* A = nullptr;
+  int64_t lda = 0;
+  int a_type = BK_F32;
+  const float* ascale = nullptr;
+  void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    tm->begin(BK_PH_AX);
+    NNArgs a;
+    a.n = n;
+    a.K = d;
+    a.N = k;
+    a.A = A;
+    a.lda = lda;
+    a.a_type = a_type;
+    a.ascale = ascale;
+    a.ascale_ld = cdiv(d, 128);
+    a.X = X;
+    a.ldx = ldx;
+    a.x_f64 = f64;
+    a.C = Y;
+    a.ldc = ldy;
+    a.c_f64 = f64;
+    launch_nn(a, s);
+    tm->end(1);
+  }
+  void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    tm->begin(BK_PH_ATY);
+    TNArgs a;
+    a.L = n;
+    a.p = d;
+    a.r = k;
+    a.X = A;
+    a.ldx = lda;
+    a.x_type = a_type;
+    a.xscale = ascale;
+    a.xscale_ld = cdiv(d, 128);
+    a.Y = X;
+    a.ldy = ldx;
+    a.y_f64 = f64;
+    a.C = Y;
+    a.ldc = ldy;
+    a.c_f64 = f64;
+    a.partial = partial;
+    launch_tn(a, s);
+    tm->end(2);
+  }
+};
+
+struct CsrOp : Op {
+  const int32_t *rp = nullptr, *ci = nullptr, *trp = nullptr, *tci = nullptr;
+  const float *v = nullptr, *tv = nullptr;
+  const int32_t *long_a = nullptr, *long_t = nullptr;
+  int nlong_a = 0, nlong_t = 0;
+  const float* mu = nullptr;    // row means (centring) or null
+  const float* ones = nullptr;  // d ones
+  double* colvec = nullptr;     // k
+  void centre_vec(const void* X, int64_t ldx, int k, int64_t L, const float* w,
+                  hipStream_t s) {
+    // colvec = X^T w  (X L x k)
+    tm->begin(BK_PH_CENTER);
+    TNArgs a;
+    a.L = L;
+    a.p = k;
+    a.r = 1;
+    a.X = X;
+    a.ldx = ldx;
+    a.x_type = BK_F32;
+    a.Y = w;
+    a.ldy = 1;
+    a.y_f64 = false;
+    a.C = colvec;
+    a.ldc = 1;
+    a.c_f64 = true;
+    a.partial = partial;
+    launch_tn(a, s);
+    tm->end(2);
+  }
+  void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    if (mu) centre_vec(X, ldx, k, d, ones, s);
+    tm->begin(BK_PH_AX);
+    launch_csr_spmm(rp, ci, v, n, k, static_cast<const float*>(X), ldx,
+                    static_cast<float*>(Y), ldy, mu, mu ? colvec : nullptr, kLongRow, s);
+    tm->end(1);
+    if (nlong_a) {
+      tm->begin(BK_PH_LONG);
+      launch_csr_spmm_long(long_a, nlong_a, rp, ci, v, k, static_cast<const float*>(X), ldx,
+                           static_cast<float*>(Y), ldy, mu, mu ? colvec : nullptr, s);
+      tm->end(1);
+    }
+  }
+  void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    if (mu) centre_vec(X, ldx, k, n, mu, s);
+    tm->begin(BK_PH_ATY);
+    launch_csr_spmm(trp, tci, tv, d, k, static_cast<const float*>(X), ldx,
+                    static_cast<float*>(Y), ldy, nullptr, mu ? colvec : nullptr, kLongRow, s);
+    tm->end(1);
+    if (nlong_t) {
+      tm->begin(BK_PH_LONG);
+      launch_csr_spmm_long(long_t, nlong_t, trp, tci, tv, k, static_cast<const float*>(X),
+                           ldx, static_cast<float*>(Y), ldy, nullptr,
+                           mu ? colvec : nullptr, s);
+      tm->end(1);
+    }
+  }
+};
+
+// --------------------------------------------------------------- solver --
+struct Solver {
+  Op* op = nullptr;
+  Layout* L = nullptr;
+  Options o;
+  Timer* tm = nullptr;
+  hipStream_t s = nullptr;
+  int k = 0, q = 0;
+  int64_t n = 0, d = 0, m = 0;
+  bool f64 = false;
+  size_t es = 4;
+  int sweeps = 0;
+  double offdiag = 0.0;
+  bool noconv = false;
+
+  char* qslab(int i) const { return static_cast<char*>(L->Q) + static_cast<size_t>(i) * k * es; }
+  char* wslab(int i) const { return static_cast<char*>(L->W) + static_cast<size_t>(i) * k * es; }
+  int wtype() const { return f64 ? BK_F64 : BK_F32; }
+
+  // G (p x r FP64, ld r) = X^T Y, X L x p (ldx), Y L x r (ldy), both the
+  // working type.
+  void gram(const void* X, int64_t ldx, int64_t p, const void* Y, int64_t ldy,
+            int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0) {
+    TNArgs a;
+    a.L = Lrows;
+    a.p = p;
+    a.r = r;
+    a.X = X;
+    a.ldx = ldx;
+    a.x_type = wtype();
+    a.Y = Y;
+    a.ldy = ldy;
+    a.y_f64 = f64;
+    a.C = G;
+    a.ldc = r;
+    a.c_f64 = true;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.partial = L->partial;
+    launch_tn(a, s);
+  }
+  // C (rows x N, ldc) = alpha A (rows x K, lda) Xf (K x N FP64, ldx) + beta C
+  void apply(const void* A, int64_t lda, int64_t rows, int64_t K, const double* Xf,
+             int64_t ldx, int N, void* C, int64_t ldc, double alpha, double beta) {
+    NNArgs a;
+    a.n = rows;
+    a.K = K;
+    a.N = N;
+    a.A = A;
+    a.lda = lda;
+    a.a_type = wtype();
+    a.X = Xf;
+    a.ldx = ldx;
+    a.x_f64 = true;
+    a.C = C;
+    a.ldc = ldc;
+    a.c_f64 = f64;
+    a.alpha = alpha;
+    a.beta = beta;
+    launch_nn(a, s);
+  }
+
+  // Q slab i = orth(Bs): shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci.
+  // Comput. 2020).  Pass 1 factors G + s I with s = 11 (nk + k(k+1)) u
+  // ||B||_F^2 so the FP64 Cholesky cannot fail on an ill-conditioned block;
+  // passes 2 and 3 are plain CholeskyQR on the already well-conditioned
+  // result.  R_i = R3 R2 R1 (saved for the adjoint).
+  void orth_block(int i) {
+    tm->begin(BK_PH_CHOLQR);
+    const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
+    void* src = L->Bs;
+    void* dst = L->Bs2;
+    for (int pass = 0; pass < 3; ++pass) {
+      gram(src, k, k, src, k, k, n, L->G);
+      const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
+      launch_chol(k, L->G, L->Gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
+                  L->cholwork, L->ctrl, s);
+      void* out = (pass == 2) ? static_cast<void*>(qslab(i)) : dst;
+      const int64_t ldo = (pass == 2) ? m : k;
+      apply(src, k, n, k, L->Rinv, k, k, out, ldo, 1.0, 0.0);
+      if (o.save) {
+        if (pass == 0) {
+          launch_copy2d(L->R, true, k, L->Racc, true, k, k, k, s);
+        } else {
+          launch_trmm_upper(k, L->R, L->Racc, L->Rtmp, s);
+          launch_copy2d(L->Rtmp, true, k, L->Racc, true, k, k, k, s);
+        }
+      }
+      std::swap(src, dst);
+    }
+    if (o.save)
+      launch_copy2d(L->Racc, true, k, L->Rsave + static_cast<size_t>(i) * k * k, true, k, k,
+                    k, s);
+    tm->end(12 + (o.save ? 6 : 0));
+  }
+
+  // Bs <- (I - Q_<i Q_<i^T) Bs, twice.
+  void project(int i) {
+    tm->begin(BK_PH_PROJ);
+    gram(L->Bs, k, k, L->Bs, k, k, n, L->Gpre);
+    const int64_t p = static_cast<int64_t>(i) * k;
+    double* Cs = o.save ? L->Csave + static_cast<size_t>(i) * m * k : nullptr;
+    for (int pass = 0; pass < 2; ++pass) {
+      gram(L->Q, m, p, L->Bs, k, k, n, L->C);
+      apply(L->Q, m, n, p, L->C, k, k, L->Bs, k, -1.0, 1.0);
+      if (Cs) {
+        if (pass == 0) launch_copy2d(L->C, true, k, Cs, true, k, p, k, s);
+        else launch_axpy_f64(L->C, Cs, p * k, s);
+      }
+    }
+    tm->end(7 + (o.save ? 2 : 0));
+  }
+
+  // Eigen-solve of the FP64 symmetric PSD `Mat` (mm x mm): top `kk`
+  // eigenvectors into Uk (ld ldu) and sqrt(theta) into ritz.
+  int eig(const double* Mat, int64_t mm, JacobiWs& jw, int kk, double* Uk, int64_t ldu,
+          double* ritz) {
+    const double tol = jacobi_tol_for(mm, o.jtol);
+    const int nb = static_cast<int>(jw.nbp / jw.b);
+    launch_jacobi_init(Mat, mm, mm, jw.Xc, jw.Vc, jw.ldc, jw.nbp, s);
+    bool conv = false;
+    int sw = 0;
+    double off = 0.0;
+    for (sw = 1; sw <= o.max_sweeps; ++sw) {
+      launch_ctrl_reset_off(L->ctrl, s);
+      for (int r = 0; r < nb - 1; ++r)
+        launch_jacobi_round(jw.b, mm, nb, r, jw.Xc, jw.Vc, jw.ldc, tol, 12, L->ctrl, s);
+      Ctrl h;
+      BK_TRY(hipMemcpyAsync(&h, L->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+      BK_TRY(hipStreamSynchronize(s));
+      long long bits = static_cast<long long>(h.offmax);
+      std::memcpy(&off, &bits, sizeof(off));
+      if (off <= tol) {
+        conv = true;
+        break;
+      }
+    }
+    sweeps += std::min(sw, o.max_sweeps);
+    offdiag = off;
+    if (!conv) noconv = true;
+    launch_jacobi_finalize(jw.Xc, jw.Vc, jw.ldc, mm, kk, jw.theta, jw.order, jw.norms, Uk,
+                           ldu, ritz, s);
+    BK_TRY_LAUNCH();
+    return BK_OK;
+  }
+
+};
+
+// refine: 0 = default (on for the BF16 / FP8 copies when an FP32 master is
+// given), > 0 on, < 0 off; never for the plain FP32 / FP64 paths.
+void normalize_refine(Options& o, int a_type, bool has_master) {
+  const bool lowp = a_type == BK_BF16 || a_type == BK_FP8_E4M3;
+  if (!lowp) o.refine = 0;
+  else if (o.refine == 0) o.refine = has_master ? 1 : 0;
+  else o.refine = o.refine > 0 ? 1 : 0;
+}
+
+int finish_status(const Ctrl& h, bool noconv) {
+  if (h.flags & CTRL_NONFINITE) return BK_ENONFINITE;
+  if (h.flags & CTRL_RANK) return BK_ERANK;
+  if (noconv) return BK_ENOCONV;
+  return BK_OK;
+}
+
+// The whole solve for an operator; Z is FP64 when op->f64, else FP32.
+int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
+          const DenseOp* master, void* Z, int64_t ldz, double* ritz, bk_info* info,
+          hipStream_t s) {
+  Timer tm;
+  tm.on = o.timing != 0;
+  tm.s = s;
+  op.tm = &tm;
+  op.partial = L.partial;
+  Solver S;
+  S.op = &op;
+  S.L = &L;
+  S.o = o;
+  S.tm = &tm;
+  S.s = s;
+  S.k = k;
+  S.q = q;
+  S.n = op.n;
+  S.d = op.d;
+  S.f64 = op.f64;
+  S.es = op.f64 ? 8 : 4;
+  S.m = static_cast<int64_t>(q + 1) * k;
+  const int64_t n = op.n, d = op.d, m = S.m;
+  const bool f64 = op.f64;
+
+  launch_ctrl_init(L.ctrl, q, s);
+  // Step 1: the sketch.
+  tm.begin(BK_PH_PI);
+  if (o.pi)
+    launch_copy2d(o.pi, f64, k, L.Pi, f64, k, d, k, s);
+  else
+    launch_gaussian(seed, d, k, k, f64, L.Pi, s);
+  tm.end(1);
+  if (o.save) launch_fill_f64(L.Csave, (q + 1) * m * k, 0.0, s);
+
+  // Step 2-3: Krylov blocks, orthonormalized as they are formed.
+  op.ax(L.Pi, k, k, L.Bs, k, s);
+  S.orth_block(0);
+  for (int i = 1; i <= q; ++i) {
+    op.aty(S.qslab(i - 1), m, k, S.wslab(i - 1), m, s);
+    op.ax(S.wslab(i - 1), m, k, L.Bs, k, s);
+    S.project(i);
+    S.orth_block(i);
+  }
+  op.aty(S.qslab(q), m, k, S.wslab(q), m, s);
+  BK_TRY_LAUNCH();
+
+  // Step 4: M = W^T W = Q^T A A^T Q in FP64.
+  tm.begin(BK_PH_M);
+  S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M);
+  tm.end(2);
+  BK_TRY_LAUNCH();
+
+  // Step 5: top-k eigenpairs of M.
+  tm.begin(BK_PH_EIG);
+  int st = S.eig(L.M, m, L.jw, k, L.Uk, k, L.ritz_dev);
+  tm.end(0);
+  if (st != BK_OK) return st;
+
+  // Step 6: Z = Q U_k.
+  tm.begin(BK_PH_Z);
+  S.apply(L.Q, m, n, m, L.Uk, k, k, Z, ldz, 1.0, 0.0);
+  launch_sign_normalize(Z, f64, n, k, ldz, L.Uk, m, k, L.sign, s);
+  tm.end(3);
+  BK_TRY_LAUNCH();
+
+  // Correction pass: Rayleigh-Ritz on span(Z) with the FP32 master copy.
+  if (o.refine && master) {
+    tm.begin(BK_PH_REFINE);
+    DenseOp mop = *master;
+    mop.partial = L.partial;
+    Timer dummy;
+    mop.tm = &dummy;
+    mop.aty(Z, ldz, k, L.Wk, k, s);  // W_k = A^T Z (FP32 master)
+    TNArgs g;
+    g.L = d;
+    g.p = k;
+    g.r = k;
+    g.X = L.Wk;
+    g.ldx = k;
+    g.x_type = BK_F32;
+    g.Y = L.Wk;
+    g.ldy = k;
+    g.y_f64 = false;
+    g.C = L.Gk;
+    g.ldc = k;
+    g.c_f64 = true;
+    g.partial = L.partial;
+    launch_tn(g, s);
+    tm.end(4);
+    st = S.eig(L.Gk, k, L.jk, k, L.Pk, k, L.ritz_dev);
+    if (st != BK_OK) return st;
+    tm.begin(BK_PH_REFINE);
+    S.apply(Z, ldz, n, k, L.Pk, k, k, L.Bs, k, 1.0, 0.0);
+    launch_copy2d(L.Bs, false, k, Z, false, ldz, n, k, s);
+    launch_sign_normalize(Z, false, n, k, ldz, nullptr, 0, 0, L.sign, s);
+    tm.end(4);
+    BK_TRY_LAUNCH();
+  }
+
+  launch_copy2d(L.ritz_dev, true, 1, ritz, true, 1, k, 1, s);
+  Ctrl h;
+  BK_TRY(hipMemcpyAsync(&h, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  if (info) {
+    tm.collect(info);
+    info->q_eff = h.q_eff;
+    info->jacobi_sweeps = S.sweeps;
+    info->jacobi_offdiag = S.offdiag;
+    info->workspace_bytes = static_cast<int64_t>(L.bytes);
+  }
+  return finish_status(h, S.noconv);
+}
+
+bool valid_kq(int64_t n, int64_t d, int32_t k, int32_t q) {
+  if (n <= 0 || d <= 0 || k < 1 || q < 0) return false;
+  if (k > std::min(n, d)) return false;
+  if (static_cast<int64_t>(q + 1) * k > std::min(n, d)) return false;
+  return true;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~DevBuf() {
+    if (p) hipFreeAsync(p, s);
+  }
+};
+
+}  // namespace
+}  // namespace bk
+
+using namespace bk;
+
+extern "C" {
+
+const char* bk_status_string(int status) {
+  switch (status) {
+    case BK_OK: return "ok";
+    case BK_EINVAL: return "invalid argument";
+    case BK_ENOMEM: return "workspace too small or allocation failed";
+    case BK_EHIP: return "HIP runtime error";
+    case BK_ENONFINITE: return "non-finite value in a Gram matrix";
+    case BK_ENOCONV: return "Jacobi eigen-solve did not converge";
+    case BK_ERANK: return "A Pi is numerically rank deficient";
+    default: return "unknown status";
+  }
+}
+
+const char* bk_version(void) { return "bk 0.1 gfx950"; }
+
+size_t bk_svd_dense_workspace(int64_t n, int64_t d, int32_t k, int32_t q, int32_t a_type,
+                              const bk_options* opt) {
+  if (!valid_kq(n, d, k, q) || a_type < BK_F64 || a_type > BK_FP8_E4M3) return 0;
+  const bool f64 = a_type == BK_F64;
+  Options o = read_options(opt, f64);
+  normalize_refine(o, a_type, true);  // sized for the pass whenever it may run
+  return make_layout(nullptr, n, d, 0, k, q, f64, o, false, false).bytes;
+}
+
+int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scales,
+                 const float* A_master, int64_t ld_master, int64_t n, int64_t d, int32_t k,
+                 int32_t q, uint64_t seed, const bk_options* opt, void* Z, int64_t ldz,
+                 double* ritz, bk_info* info, void* workspace, size_t workspace_bytes,
+                 void* stream) {
+  if (!valid_kq(n, d, k, q) || !A || !Z || !ritz || lda < d || ldz < k) return BK_EINVAL;
+  if (a_type < BK_F64 || a_type > BK_FP8_E4M3) return BK_EINVAL;
+  if (a_type == BK_FP8_E4M3 && !a_scales) return BK_EINVAL;
+  const bool f64 = a_type == BK_F64;
+  Options o = read_options(opt, f64);
+  normalize_refine(o, a_type, A_master != nullptr);
+  if (o.refine && (!A_master || ld_master < d)) return BK_EINVAL;
+  if (o.center) return BK_EINVAL;  // dense centring is not offered
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = make_layout(nullptr, n, d, 0, k, q, f64, o, false, false).bytes;
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  Layout L = make_layout(base, n, d, 0, k, q, f64, o, false, false);
+  DenseOp op;
+  op.n = n;
+  op.d = d;
+  op.f64 = f64;
+  op.A = A;
+  op.lda = lda;
+  op.a_type = a_type;
+  op.ascale = a_type == BK_FP8_E4M3 ? a_scales : nullptr;
+  DenseOp master;
+  const DenseOp* mp = nullptr;
+  if (o.refine) {
+    master.n = n;
+    master.d = d;
+    master.f64 = false;
+    master.A = A_master;
+    master.lda = ld_master;
+    master.a_type = BK_F32;
+    mp = &master;
+  }
+  return solve(op, L, o, k, q, seed, mp, Z, ldz, ritz, info, s);
+}
+
+size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k, int32_t q,
+                            const bk_options* opt) {
+  if (!valid_kq(n, d, k, q) || nnz < 0 || nnz >= (int64_t(1) << 31)) return 0;
+  Options o = read_options(opt, false);
+  o.refine = 0;
+  return make_layout(nullptr, n, d, nnz, k, q, false, o, true, true).bytes;
+}
+
+int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+               const int32_t* t_row_ptr, const int32_t* t_col_idx, const float* t_vals,
+               int64_t n, int64_t d, int64_t nnz, int32_t k, int32_t q, uint64_t seed,
+               const bk_options* opt, float* Z, int64_t ldz, double* ritz, bk_info* info,
+               void* workspace, size_t workspace_bytes, void* stream) {
+  if (!valid_kq(n, d, k, q) || nnz < 0 || nnz >= (int64_t(1) << 31) || !row_ptr || !Z ||
+      !ritz || ldz < k)
+    return BK_EINVAL;
+  if (nnz > 0 && (!col_idx || !vals)) return BK_EINVAL;
+  const bool given_t = t_row_ptr && t_col_idx && t_vals;
+  if ((t_row_ptr || t_col_idx || t_vals) && !given_t) return BK_EINVAL;
+  Options o = read_options(opt, false);
+  o.refine = 0;
+  o.save = 0;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = make_layout(nullptr, n, d, nnz, k, q, false, o, true, !given_t).bytes;
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  Layout L = make_layout(base, n, d, nnz, k, q, false, o, true, !given_t);
+
+  Timer prep;
+  prep.on = o.timing != 0;
+  prep.s = s;
+  prep.begin(BK_PH_PREP);
+  // Validate the structure before any kernel indexes through it.
+  launch_ctrl_init(L.ctrl, q, s);
+  launch_csr_validate(row_ptr, col_idx, n, d, nnz, L.ctrl, s);
+  if (given_t) launch_csr_validate(t_row_ptr, t_col_idx, d, n, nnz, L.ctrl, s);
+  Ctrl h;
+  BK_TRY(hipMemcpyAsync(&h, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  if (h.csr_bad) return BK_EINVAL;
+  const int32_t* trp = t_row_ptr;
+  const int32_t* tci = t_col_idx;
+  const float* tv = t_vals;
+  if (!given_t) {
+    launch_csr_transpose(row_ptr, col_idx, vals, n, d, nnz, L.trp, L.tci, L.tv, L.cursor,
+                         L.keys, s);
+    trp = L.trp;
+    tci = L.tci;
+    tv = L.tv;
+  }
+  launch_csr_long_rows(row_ptr, n, kLongRow, L.long_a, L.nlong, s);
+  launch_csr_long_rows(trp, d, kLongRow, L.long_t, L.nlong + 1, s);
+  if (o.center) {
+    launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
+    launch_fill_f32(L.ones, d, 1.0f, s);
+  }
+  int32_t nl[2] = {0, 0};
+  BK_TRY(hipMemcpyAsync(nl, L.nlong, sizeof(nl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  prep.end(0);
+
+  CsrOp op;
+  op.n = n;
+  op.d = d;
+  op.f64 = false;
+  op.rp = row_ptr;
+  op.ci = col_idx;
+  op.v = vals;
+  op.trp = trp;
+  op.tci = tci;
+  op.tv = tv;
+  op.long_a = L.long_a;
+  op.long_t = L.long_t;
+  op.nlong_a = nl[0];
+  op.nlong_t = nl[1];
+  op.mu = o.center ? L.mu : nullptr;
+  op.ones = L.ones;
+  op.colvec = L.colvec;
+  const int st = solve(op, L, o, k, q, seed, nullptr, Z, ldz, ritz, info, s);
+  if (info && o.timing) {
+    float ms = 0.0f;
+    if (!prep.marks.empty())
+      hipEventElapsedTime(&ms, prep.marks[0].second.first, prep.marks[0].second.second);
+    info->ms[BK_PH_PREP] += ms;
+  }
+  return st;
+}
+
+size_t bk_svd_dense_backward_workspace(int64_t n, int64_t d, int32_t k, int32_t q,
+                                       int32_t a_type) {
+  (void)n;
+  (void)d;
+  (void)k;
+  (void)q;
+  (void)a_type;
+  return 0;
+}
+
+int bk_svd_dense_backward(const void* A, int64_t lda, int32_t a_type, int64_t n, int64_t d,
+                          int32_t k, int32_t q, const void* Z, int64_t ldz, const double* ritz,
+                          const void* Z_bar, const double* ritz_bar, void* A_bar,
+                          int64_t ld_bar, const void* fwd_workspace, size_t fwd_bytes,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  (void)A; (void)lda; (void)a_type; (void)n; (void)d; (void)k; (void)q; (void)Z; (void)ldz;
+  (void)ritz; (void)Z_bar; (void)ritz_bar; (void)A_bar; (void)ld_bar; (void)fwd_workspace;
+  (void)fwd_bytes; (void)workspace; (void)workspace_bytes; (void)stream;
+  return BK_EINVAL;
+}
+
+int bk_gaussian(uint64_t seed, int64_t rows, int64_t cols, int64_t ld, int32_t dtype, void* out,
+                void* stream) {
+  if (rows < 0 || cols < 0 || ld < cols || !out || (dtype != BK_F64 && dtype != BK_F32))
+    return BK_EINVAL;
+  launch_gaussian(seed, rows, cols, ld, dtype == BK_F64, out, static_cast<hipStream_t>(stream));
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+int bk_philox4x32_10(const uint32_t* in, int64_t count, uint32_t* out, void* stream) {
+  if (count < 0 || (count > 0 && (!in || !out))) return BK_EINVAL;
+  launch_philox_raw(in, count, out, static_cast<hipStream_t>(stream));
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+int bk_quantize_dense(const float* A, int64_t n, int64_t d, int64_t lda, int32_t to, void* out,
+                      float* tile_scales, void* stream) {
+  if (n < 0 || d < 0 || lda < d || !A || !out) return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (to == BK_BF16) {
+    launch_quant_bf16(A, n, d, lda, static_cast<bf16_t*>(out), s);
+  } else if (to == BK_FP8_E4M3) {
+    if (!tile_scales) return BK_EINVAL;
+    launch_quant_fp8(A, n, d, lda, static_cast<fp8_t*>(out), tile_scales, s);
+  } else {
+    return BK_EINVAL;
+  }
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d, int32_t k,
+                                  int32_t a_type) {
+  (void)a_type;
+  if (n <= 0 || d <= 0 || k <= 0) return 0;
+  if (!trans) return 256;
+  return static_cast<size_t>(tn_partial_elems(n, d, k)) * sizeof(double);
+}
+
+int bk_dense_product(int32_t trans, const void* A, int64_t lda, int32_t a_type,
+                     const float* a_scales, int64_t n, int64_t d, const void* X, int64_t ldx,
+                     int32_t k, void* Y, int64_t ldy, void* workspace, size_t workspace_bytes,
+                     void* stream) {
+  if (n <= 0 || d <= 0 || k <= 0 || !A || !X || !Y || lda < d || ldx < k || ldy < k)
+    return BK_EINVAL;
+  if (a_type < BK_F64 || a_type > BK_FP8_E4M3) return BK_EINVAL;
+  if (a_type == BK_FP8_E4M3 && !a_scales) return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = bk_dense_product_workspace(trans, n, d, k, a_type);
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (trans) {
+    if (!base) {
+      own.s = s;
+      if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+      base = static_cast<char*>(own.p);
+    } else if (workspace_bytes < need) {
+      return BK_ENOMEM;
+    }
+  }
+  Timer tm;
+  DenseOp op;
+  op.n = n;
+  op.d = d;
+  op.f64 = a_type == BK_F64;
+  op.A = A;
+  op.lda = lda;
+  op.a_type = a_type;
+  op.ascale = a_type == BK_FP8_E4M3 ? a_scales : nullptr;
+  op.partial = reinterpret_cast<double*>(base);
+  op.tm = &tm;
+  if (trans) op.aty(X, ldx, k, Y, ldy, s);
+  else op.ax(X, ldx, k, Y, ldy, s);
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+int bk_csr_product(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                   int64_t rows, int64_t cols, int64_t nnz, const float* X, int64_t ldx,
+                   int32_t k, float* Y, int64_t ldy, void* stream) {
+  if (rows < 0 || cols < 0 || nnz < 0 || k <= 0 || !row_ptr || !X || !Y || ldx < k || ldy < k)
+    return BK_EINVAL;
+  (void)cols;
+  launch_csr_spmm(row_ptr, col_idx, vals, rows, k, X, ldx, Y, ldy, nullptr, nullptr,
+                  0x7FFFFFFF, static_cast<hipStream_t>(stream));
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+size_t bk_csr_transpose_workspace(int64_t rows, int64_t cols, int64_t nnz) {
+  (void)rows;
+  if (cols < 0 || nnz < 0) return 0;
+  return align_up(static_cast<size_t>(cols) * 4, 256) + static_cast<size_t>(3 * nnz) * 8 +
+         align_up(sizeof(Ctrl), 256) + 256;
+}
+
+int bk_csr_transpose(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                     int64_t rows, int64_t cols, int64_t nnz, int32_t* t_row_ptr,
+                     int32_t* t_col_idx, float* t_vals, void* workspace,
+                     size_t workspace_bytes, void* stream) {
+  if (rows < 0 || cols <= 0 || nnz < 0 || nnz >= (int64_t(1) << 31) || !row_ptr || !t_row_ptr)
+    return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = bk_csr_transpose_workspace(rows, cols, nnz);
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  int32_t* cursor = reinterpret_cast<int32_t*>(base);
+  const size_t koff = align_up(static_cast<size_t>(cols) * 4, 256);
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + koff);
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + koff + static_cast<size_t>(3 * nnz) * 8);
+  // the structure is checked before the transpose indexes through it
+  launch_ctrl_init(ctrl, 0, s);
+  launch_csr_validate(row_ptr, col_idx, rows, cols, nnz, ctrl, s);
+  Ctrl h;
+  BK_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  if (h.csr_bad) return BK_EINVAL;
+  launch_csr_transpose(row_ptr, col_idx, vals, rows, cols, nnz, t_row_ptr, t_col_idx, t_vals,
+                       cursor, keys, s);
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
+size_t bk_eigh_psd_workspace(int64_t m) {
+  if (m <= 0) return 0;
+  Arena ar;
+  ar.take<Ctrl>(1);
+  take_jacobi(ar, m, 0, true);
+  ar.take<double>(static_cast<size_t>(m));  // sign
+  return align_up(ar.off, 256);
+}
+
+int bk_eigh_psd(const double* M, int64_t m, int64_t ldm, double* theta, double* V,
+                int64_t ldv, int32_t max_sweeps, double tol, int32_t* sweeps, void* workspace,
+                size_t workspace_bytes, void* stream) {
+  if (m <= 0 || ldm < m || ldv < m || !M || !theta || !V || m > (int64_t(1) << 20))
+    return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = bk_eigh_psd_workspace(m);
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  Arena ar;
+  ar.base = base;
+  Layout L;
+  L.ctrl = ar.take<Ctrl>(1);
+  JacobiWs jw = take_jacobi(ar, m, 0, true);
+  double* sign = ar.take<double>(static_cast<size_t>(m));
+  Solver S;
+  S.L = &L;
+  S.o.max_sweeps = max_sweeps > 0 ? max_sweeps : 40;
+  S.o.jtol = tol;
+  Timer tm;
+  S.tm = &tm;
+  S.s = s;
+  launch_ctrl_init(L.ctrl, 0, s);
+  // theta / order via the finalize step; V gets every column.
+  int st = S.eig(M, m, jw, static_cast<int>(std::min<int64_t>(m, 0x7FFFFFFF)), V, ldv, nullptr);
+  if (st != BK_OK) return st;
+  launch_copy2d(jw.theta, true, 1, theta, true, 1, m, 1, s);
+  launch_sign_normalize(V, true, m, static_cast<int>(m), ldv, nullptr, 0, 0, sign, s);
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  if (sweeps) *sweeps = S.sweeps;
+  return S.noconv ? BK_ENOCONV : BK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,316 @@
+// Skinny dense products of the Krylov loop (Algorithm 2, steps 2-6):
+//   NN:  C = alpha A X + beta C        A n x K, X K x N, N small (<= ~2k)
+//   TN:  C = alpha X^T Y + beta C      X L x p, Y L x r, long reduction L
+// These generic LDS-tiled kernels cover every element type; the wide FP32 /
+// BF16 / FP8 products are routed to the MFMA kernels in gemm_mfma.hip.
+#include "kernels.hpp"
+
+namespace bk {
+
+void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done);
+void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, bool* done);
+
+namespace {
+
+constexpr int NN_BM = 64, NN_BN = 32, NN_BK = 32;
+
+template <typename TA, typename TX, typename TC, typename ACC, bool SCALED>
+__global__ __launch_bounds__(256) void nn_kernel(
+    int64_t n, int64_t K, int N, const TA* __restrict__ A, int64_t lda,
+    const float* __restrict__ ascale, int64_t ascale_ld,
+    const TX* __restrict__ X, int64_t ldx, TC* __restrict__ C, int64_t ldc,
+    ACC alpha, ACC beta) {
+  __shared__ ACC As[NN_BK][NN_BM + 1];
+  __shared__ ACC Xs[NN_BK][NN_BN];
+  const int t = threadIdx.x;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * NN_BM;
+  const int col0 = blockIdx.y * NN_BN;
+  const int tx = t & 7;   // 8 groups of 4 output columns
+  const int ty = t >> 3;  // 32 groups of 2 output rows
+  ACC acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = ACC(0);
+
+  for (int64_t k0 = 0; k0 < K; k0 += NN_BK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      const int r = e >> 5, kk = e & 31;
+      const int64_t gr = row0 + r, gk = k0 + kk;
+      ACC v = ACC(0);
+      if (gr < n && gk < K) {
+        v = static_cast<ACC>(Elem<TA>::load(A, gr * lda + gk));
+        if (SCALED) v *= static_cast<ACC>(ascale[(gr >> 7) * ascale_ld + (gk >> 7)]);
+      }
+      As[kk][r] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = t + 256 * i;
+      const int kk = e >> 5, c = e & 31;
+      const int64_t gk = k0 + kk;
+      const int gc = col0 + c;
+      Xs[kk][c] = (gk < K && gc < N) ? static_cast<ACC>(X[gk * ldx + gc]) : ACC(0);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < NN_BK; ++kk) {
+      const ACC a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const ACC xv = Xs[kk][tx * 4 + j];
+        acc[0][j] += a0 * xv;
+        acc[1][j] += a1 * xv;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t gr = row0 + ty * 2 + i;
+    if (gr >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gc = col0 + tx * 4 + j;
+      if (gc >= N) continue;
+      ACC v = alpha * acc[i][j];
+      if (beta != ACC(0)) v += beta * static_cast<ACC>(C[gr * ldc + gc]);
+      C[gr * ldc + gc] = static_cast<TC>(v);
+    }
+  }
+}
+
+constexpr int TN_BP = 64, TN_BR = 32, TN_BL = 32;
+
+// Partial sums over the rows [s*Ls, (s+1)*Ls) of split s = blockIdx.z:
+// FP32 (or FP64) products summed over 32-row chunks, chunk sums added in FP64.
+template <typename TX, typename TY, typename ACC, bool SCALED>
+__global__ __launch_bounds__(256) void tn_kernel(
+    int64_t L, int64_t p, int r, const TX* __restrict__ X, int64_t ldx,
+    const float* __restrict__ xscale, int64_t xscale_ld,
+    const TY* __restrict__ Y, int64_t ldy, double* __restrict__ partial,
+    int64_t Ls) {
+  __shared__ ACC Xs[TN_BL][TN_BP];
+  __shared__ ACC Ys[TN_BL][TN_BR];
+  const int t = threadIdx.x;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * TN_BP;
+  const int r0 = blockIdx.y * TN_BR;
+  const int64_t s = blockIdx.z;
+  const int64_t lb = s * Ls;
+  const int64_t le = (lb + Ls < L) ? lb + Ls : L;
+  const int tp = t >> 3;  // 32 groups of 2 p-rows
+  const int tr = t & 7;   // 8 groups of 4 r-columns
+  double dacc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dacc[i][j] = 0.0;
+
+  for (int64_t l0 = lb; l0 < le; l0 += TN_BL) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      const int ll = e >> 6, pp = e & 63;
+      const int64_t gl = l0 + ll, gp = p0 + pp;
+      ACC v = ACC(0);
+      if (gl < le && gp < p) {
+        v = static_cast<ACC>(Elem<TX>::load(X, gl * ldx + gp));
+        if (SCALED) v *= static_cast<ACC>(xscale[(gl >> 7) * xscale_ld + (gp >> 7)]);
+      }
+      Xs[ll][pp] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = t + 256 * i;
+      const int ll = e >> 5, rr = e & 31;
+      const int64_t gl = l0 + ll;
+      const int gr = r0 + rr;
+      Ys[ll][rr] = (gl < le && gr < r) ? static_cast<ACC>(Y[gl * ldy + gr]) : ACC(0);
+    }
+    __syncthreads();
+    ACC acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = ACC(0);
+#pragma unroll 8
+    for (int ll = 0; ll < TN_BL; ++ll) {
+      const ACC x0 = Xs[ll][tp * 2], x1 = Xs[ll][tp * 2 + 1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const ACC yv = Ys[ll][tr * 4 + j];
+        acc[0][j] += x0 * yv;
+        acc[1][j] += x1 * yv;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) dacc[i][j] += static_cast<double>(acc[i][j]);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t gp = p0 + tp * 2 + i;
+    if (gp >= p) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gr = r0 + tr * 4 + j;
+      if (gr >= r) continue;
+      partial[(s * p + gp) * r + gr] = dacc[i][j];
+    }
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void tn_reduce_kernel(
+    int S, int64_t p, int r, const double* __restrict__ partial,
+    TC* __restrict__ C, int64_t ldc, double alpha, double beta) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= p * r) return;
+  const int64_t gp = idx / r;
+  const int gr = static_cast<int>(idx - gp * r);
+  double acc = 0.0;
+  for (int i = 0; i < S; ++i) acc += partial[(i * p + gp) * r + gr];
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * static_cast<double>(C[gp * ldc + gr]);
+  C[gp * ldc + gr] = static_cast<TC>(v);
+}
+
+template <typename TA, typename TX, typename TC, typename ACC>
+void nn_dispatch_scaled(const NNArgs& a, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(cdiv(a.n, NN_BM)),
+                  static_cast<unsigned>(cdiv(a.N, NN_BN)));
+  const TA* A = static_cast<const TA*>(a.A);
+  const TX* X = static_cast<const TX*>(a.X);
+  TC* C = static_cast<TC*>(a.C);
+  if (a.ascale)
+    nn_kernel<TA, TX, TC, ACC, true><<<grid, 256, 0, s>>>(
+        a.n, a.K, a.N, A, a.lda, a.ascale, a.ascale_ld, X, a.ldx, C, a.ldc,
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta));
+  else
+    nn_kernel<TA, TX, TC, ACC, false><<<grid, 256, 0, s>>>(
+        a.n, a.K, a.N, A, a.lda, nullptr, 0, X, a.ldx, C, a.ldc,
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta));
+}
+
+template <typename TA>
+void nn_dispatch_lowp(const NNArgs& a, hipStream_t s) {
+  // FP32-accumulating paths: X FP64 or FP32, C FP32 (or FP64)
+  if (a.x_f64) {
+    if (a.c_f64) nn_dispatch_scaled<TA, double, double, float>(a, s);
+    else nn_dispatch_scaled<TA, double, float, float>(a, s);
+  } else {
+    if (a.c_f64) nn_dispatch_scaled<TA, float, double, float>(a, s);
+    else nn_dispatch_scaled<TA, float, float, float>(a, s);
+  }
+}
+
+template <typename TX, typename ACC>
+void tn_dispatch(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(cdiv(a.p, TN_BP)),
+                  static_cast<unsigned>(cdiv(a.r, TN_BR)),
+                  static_cast<unsigned>(S));
+  const TX* X = static_cast<const TX*>(a.X);
+  if (a.y_f64) {
+    const double* Y = static_cast<const double*>(a.Y);
+    if (a.xscale)
+      tn_kernel<TX, double, ACC, true><<<grid, 256, 0, s>>>(
+          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls);
+    else
+      tn_kernel<TX, double, ACC, false><<<grid, 256, 0, s>>>(
+          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls);
+  } else {
+    const float* Y = static_cast<const float*>(a.Y);
+    if (a.xscale)
+      tn_kernel<TX, float, ACC, true><<<grid, 256, 0, s>>>(
+          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls);
+    else
+      tn_kernel<TX, float, ACC, false><<<grid, 256, 0, s>>>(
+          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls);
+  }
+}
+
+}  // namespace
+
+void launch_nn(const NNArgs& a, hipStream_t s) {
+  if (a.n <= 0 || a.N <= 0) return;  // K = 0 gives C = beta C below
+  bool done = false;
+  launch_nn_mfma_if(a, s, &done);
+  if (done) return;
+  switch (a.a_type) {
+    case BK_F64:
+      nn_dispatch_scaled<double, double, double, double>(a, s);
+      break;
+    case BK_F32:
+      nn_dispatch_lowp<float>(a, s);
+      break;
+    case BK_BF16:
+      nn_dispatch_lowp<bf16_t>(a, s);
+      break;
+    case BK_FP8_E4M3:
+      nn_dispatch_lowp<fp8_t>(a, s);
+      break;
+    default:
+      break;
+  }
+}
+
+int tn_splits(int64_t L, int64_t p, int r) {
+  const int64_t tiles = cdiv(p, TN_BP) * cdiv(r, TN_BR);
+  int64_t S = cdiv(1024, tiles);
+  const int64_t smax = cdiv(L, 64);
+  if (S > smax) S = smax;
+  if (S < 1) S = 1;
+  if (S > 4096) S = 4096;
+  // each split a whole number of 32-row chunks
+  int64_t Ls = align_up(static_cast<size_t>(cdiv(L, S)), TN_BL);
+  S = cdiv(L, Ls);
+  return static_cast<int>(S < 1 ? 1 : S);
+}
+
+int64_t tn_partial_elems(int64_t L, int64_t p, int r) {
+  return static_cast<int64_t>(tn_splits(L, p, r)) * p * r;
+}
+
+void launch_tn(const TNArgs& a, hipStream_t s) {
+  if (a.p <= 0 || a.r <= 0) return;
+  bool done = false;
+  launch_tn_mfma_if(a, s, &done);
+  if (done) return;
+  int S = a.L > 0 ? tn_splits(a.L, a.p, a.r) : 1;
+  int64_t Ls = a.L > 0 ? static_cast<int64_t>(align_up(cdiv(a.L, S), TN_BL)) : 0;
+  if (a.L <= 0) {
+    launch_fill_f64(a.partial, a.p * a.r, 0.0, s);
+  } else {
+    switch (a.x_type) {
+      case BK_F64:
+        tn_dispatch<double, double>(a, S, Ls, s);
+        break;
+      case BK_F32:
+        tn_dispatch<float, float>(a, S, Ls, s);
+        break;
+      case BK_BF16:
+        tn_dispatch<bf16_t, float>(a, S, Ls, s);
+        break;
+      case BK_FP8_E4M3:
+        tn_dispatch<fp8_t, float>(a, S, Ls, s);
+        break;
+      default:
+        return;
+    }
+  }
+  const unsigned g = static_cast<unsigned>(cdiv(a.p * a.r, 256));
+  if (a.c_f64)
+    tn_reduce_kernel<double><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
+                                               static_cast<double*>(a.C), a.ldc,
+                                               a.alpha, a.beta);
+  else
+    tn_reduce_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
+                                              static_cast<float*>(a.C), a.ldc,
+                                              a.alpha, a.beta);
+}
+
+}  // namespace bk

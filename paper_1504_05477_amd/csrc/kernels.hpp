@@ -1,0 +1,143 @@
+// Host-side launchers of the gfx950 kernels.  Each launcher only enqueues on
+// the given stream; the caller checks hipGetLastError().
+#pragma once
+
+#include "common.hpp"
+
+namespace bk {
+
+// ------------------------------------------------------------------ rng --
+void launch_gaussian(uint64_t seed, int64_t rows, int64_t cols, int64_t ld,
+                     bool f64, void* out, hipStream_t s);
+void launch_philox_raw(const uint32_t* in, int64_t count, uint32_t* out,
+                       hipStream_t s);
+
+// ----------------------------------------------------------------- gemm --
+// C (n x N, ldc) = alpha * A (n x K, lda) . X (K x N, ldx) + beta * C.
+// a_type: BK_F64 / BK_F32 / BK_BF16 / BK_FP8_E4M3 (FP8 with 128 x 128 tile
+// scales, ascale_ld = ceil(K / 128)).  X and C are FP64 or FP32.  The FP64
+// path (a_type BK_F64) accumulates in FP64, every other path in FP32.
+struct NNArgs {
+  int64_t n = 0, K = 0;
+  int N = 0;
+  const void* A = nullptr;
+  int64_t lda = 0;
+  int a_type = BK_F32;
+  const float* ascale = nullptr;
+  int64_t ascale_ld = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  bool x_f64 = false;
+  void* C = nullptr;
+  int64_t ldc = 0;
+  bool c_f64 = false;
+  double alpha = 1.0, beta = 0.0;
+};
+void launch_nn(const NNArgs& a, hipStream_t s);
+
+// C (p x r, ldc) = alpha * X^T . Y + beta * C with X L x p (ldx), Y L x r
+// (ldy): the reduction over the long L is split into S chunks whose FP64
+// partial sums are added in a fixed order.  x_type as a_type above (FP8
+// scales index [l / 128][p / 128]); Y is FP64 or FP32 (FP64 iff X is).
+struct TNArgs {
+  int64_t L = 0, p = 0;
+  int r = 0;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  int x_type = BK_F32;
+  const float* xscale = nullptr;
+  int64_t xscale_ld = 0;
+  const void* Y = nullptr;
+  int64_t ldy = 0;
+  bool y_f64 = false;
+  void* C = nullptr;
+  int64_t ldc = 0;
+  bool c_f64 = true;
+  double alpha = 1.0, beta = 0.0;
+  double* partial = nullptr;  // >= tn_partial_elems(L, p, r) doubles
+};
+int tn_splits(int64_t L, int64_t p, int r);
+int64_t tn_partial_elems(int64_t L, int64_t p, int r);
+void launch_tn(const TNArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- small --
+// Fill / convert helpers.
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+// dst (rows x cols, ldd) = src (rows x cols, lds), any of f64/f32 each side
+void launch_copy2d(const void* src, bool src_f64, int64_t lds, void* dst,
+                   bool dst_f64, int64_t ldd, int64_t rows, int64_t cols,
+                   hipStream_t s);
+// y += x (FP64, n elements)
+void launch_axpy_f64(const double* x, double* y, int64_t n, hipStream_t s);
+void launch_ctrl_init(Ctrl* c, int32_t q, hipStream_t s);
+void launch_ctrl_reset_off(Ctrl* c, hipStream_t s);
+
+// One-workgroup Cholesky + triangular inverse of a k x k FP64 Gram matrix
+// (see chol_kernel for the modes).
+enum CholMode { CHOL_FIRST_BLOCK0 = 0, CHOL_FIRST = 1, CHOL_REPEAT = 2 };
+void launch_chol(int k, const double* G, const double* Gpre, int mode,
+                 int block, double tau, double shift_coef, double* R,
+                 double* Rinv, double* work, Ctrl* ctrl, hipStream_t s);
+// T = A . B for k x k upper-triangular FP64 matrices (one workgroup).
+void launch_trmm_upper(int k, const double* A, const double* B, double* T,
+                       hipStream_t s);
+
+// Column signs of Z (n x k): sign[c] = +1 / -1 so that the largest-|.|
+// entry of column c (lowest row on ties) becomes positive; then Z and the
+// m x k matrix U (nullable) are multiplied column-wise by sign.
+void launch_sign_normalize(void* Z, bool f64, int64_t n, int k, int64_t ldz,
+                           double* U, int64_t m, int64_t ldu, double* sign,
+                           hipStream_t s);
+
+// --------------------------------------------------------------- jacobi --
+// One-sided block Jacobi on the columns of a symmetric PSD M (see
+// jacobi.hip).  Xc / Vc are column-major m x nbp (ld ldc).
+int jacobi_default_block(int64_t m);
+int64_t jacobi_padded_cols(int64_t m, int b);
+void launch_jacobi_init(const double* M, int64_t m, int64_t ldm, double* Xc,
+                        double* Vc, int64_t ldc, int64_t nbp, hipStream_t s);
+void launch_jacobi_round(int b, int64_t m, int nb, int round, double* Xc,
+                         double* Vc, int64_t ldc, double tol, int inner_max,
+                         Ctrl* ctrl, hipStream_t s);
+// theta (descending), order; Uk (m x k, ld ldu) = normalised eigenvectors of
+// the top k (from Vc when non-null, else Xc / theta); ritz = sqrt(theta).
+void launch_jacobi_finalize(const double* Xc, const double* Vc, int64_t ldc,
+                            int64_t m, int k, double* theta_sorted,
+                            int32_t* order, double* norms, double* Uk,
+                            int64_t ldu, double* ritz, hipStream_t s);
+
+// ------------------------------------------------------------------ csr --
+void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
+                         int64_t cols, int64_t nnz, Ctrl* ctrl, hipStream_t s);
+// Y (rows x k) = A X - rowvec (x) colvec (rowvec nullable = all ones,
+// colvec nullable = no correction).  Rows longer than long_thr are skipped
+// here and done by launch_csr_spmm_long over the list long_rows.
+void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
+                     int64_t rows, int k, const float* X, int64_t ldx,
+                     float* Y, int64_t ldy, const float* rowvec,
+                     const double* colvec, int long_thr, hipStream_t s);
+void launch_csr_spmm_long(const int32_t* long_rows, int nlong,
+                          const int32_t* rp, const int32_t* ci, const float* v,
+                          int k, const float* X, int64_t ldx, float* Y,
+                          int64_t ldy, const float* rowvec,
+                          const double* colvec, hipStream_t s);
+void launch_csr_long_rows(const int32_t* rp, int64_t rows, int long_thr,
+                          int32_t* list, int32_t* count, hipStream_t s);
+void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,
+                          int64_t cols, float* mu, hipStream_t s);
+// CSR transpose: counts -> scan -> atomic scatter -> per-row sort.
+void launch_csr_transpose(const int32_t* rp, const int32_t* ci,
+                          const float* v, int64_t rows, int64_t cols,
+                          int64_t nnz, int32_t* trp, int32_t* tci, float* tv,
+                          int32_t* cursor, unsigned long long* keys,
+                          hipStream_t s);
+
+// ---------------------------------------------------------------- quant --
+void launch_quant_bf16(const float* A, int64_t n, int64_t d, int64_t lda,
+                       bf16_t* out, hipStream_t s);
+void launch_quant_fp8(const float* A, int64_t n, int64_t d, int64_t lda,
+                      fp8_t* out, float* scales, hipStream_t s);
+
+}  // namespace bk

@@ -1,0 +1,352 @@
+// Small FP64 kernels of the orthonormalization (Algorithm 2, step 3) and
+// the output step: fills and copies, the one-workgroup Cholesky +
+// triangular inverse behind CholeskyQR, and column sign normalisation.
+#include "kernels.hpp"
+
+namespace bk {
+namespace {
+
+template <typename T>
+__global__ __launch_bounds__(256) void fill_kernel(T* p, int64_t n, T v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void copy2d_kernel(const TS* src, int64_t lds,
+                                                     TD* dst, int64_t ldd,
+                                                     int64_t rows, int64_t cols) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int64_t r = i / cols, c = i - r * cols;
+  dst[r * ldd + c] = static_cast<TD>(src[r * lds + c]);
+}
+
+__global__ __launch_bounds__(256) void axpy_kernel(const double* x, double* y,
+                                                   int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) y[i] += x[i];
+}
+
+__global__ void ctrl_init_kernel(Ctrl* c, int32_t q) {
+  if (threadIdx.x == 0) {
+    c->flags = 0;
+    c->q_eff = q;
+    c->csr_bad = 0;
+    c->pad0 = 0;
+    c->offmax = 0ull;
+    c->pad1 = 0ull;
+  }
+}
+
+__global__ void ctrl_reset_off_kernel(Ctrl* c) {
+  if (threadIdx.x == 0) c->offmax = 0ull;
+}
+
+// Fixed-order block reduction (sum) over 256 threads.
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Upper Cholesky factor S of (G + shift I) (G = S^T S), right-looking, in S
+// (LDS or global, k x k).  Returns false when a pivot is not positive and
+// finite; *minpiv receives the smallest diagonal of S.
+__device__ bool chol_factor(int k, const double* G, double shift, double* S,
+                            double* minpiv, int* fail) {
+  const int t = threadIdx.x;
+  for (int i = t; i < k * k; i += 256) {
+    const int r = i / k, c = i - r * k;
+    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
+  }
+  if (t == 0) {
+    *fail = 0;
+    *minpiv = INFINITY;
+  }
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      const double piv = S[j * k + j];
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        *fail = 1;
+      } else {
+        const double dj = sqrt(piv);
+        S[j * k + j] = dj;
+        if (dj < *minpiv) *minpiv = dj;
+      }
+    }
+    __syncthreads();
+    if (*fail) return false;
+    const double inv = 1.0 / S[j * k + j];
+    for (int c = j + 1 + t; c < k; c += 256) S[j * k + c] *= inv;
+    __syncthreads();
+    const int nt = k - j - 1;
+    for (int idx = t; idx < nt * nt; idx += 256) {
+      const int rr = j + 1 + idx / nt, cc = j + 1 + idx % nt;
+      if (cc >= rr) S[rr * k + cc] -= S[j * k + rr] * S[j * k + cc];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+// Modes:
+//  CHOL_FIRST_BLOCK0  first pass on A Pi: a Cholesky pivot <= tau ||A Pi||_F
+//                     (unshifted factor) flags CTRL_RANK; then the shifted
+//                     factor (shift = shift_coef * trace(G)).
+//  CHOL_FIRST         first pass on a projected block i >= 1: when
+//                     ||B||_F <= tau * ||B_pre||_F (traces of G and Gpre)
+//                     the Krylov space is invariant: q_eff = min(q_eff,
+//                     i - 1) and the block becomes zero; else shifted factor.
+//  CHOL_REPEAT        plain factor of an almost orthonormal block.
+// On any failure R and Rinv are zero, so the applied block is zero.
+__global__ __launch_bounds__(256) void chol_kernel(int k, const double* G,
+                                                   const double* Gpre, int mode,
+                                                   int block, double tau,
+                                                   double shift_coef, double* R,
+                                                   double* Rinv, double* work,
+                                                   Ctrl* ctrl, int use_lds) {
+  extern __shared__ double dyn[];
+  __shared__ double red[256];
+  __shared__ double minpiv;
+  __shared__ int fail;
+  __shared__ int decision;  // 0 go on, 1 zero block
+  const int t = threadIdx.x;
+  double* S = use_lds ? dyn : work;
+  double* Ri = use_lds ? dyn + k * k : Rinv;
+
+  double trp = 0.0, prp = 0.0;
+  int bad = 0;
+  for (int i = t; i < k * k; i += 256) {
+    const double v = G[i];
+    if (!isfinite(v)) bad = 1;
+    if (i / k == i % k) {
+      trp += v;
+      if (mode == CHOL_FIRST) prp += Gpre[i];
+    }
+  }
+  const int anybad = __syncthreads_or(bad);
+  const double tr = block_sum(trp, red);
+  const double pre = (mode == CHOL_FIRST) ? block_sum(prp, red) : 0.0;
+  if (t == 0) {
+    decision = 0;
+    if (anybad) {
+      atomicOr(&ctrl->flags, CTRL_NONFINITE);
+      decision = 1;
+    } else if (mode == CHOL_FIRST) {
+      if (!(sqrt(tr) > tau * sqrt(pre))) {
+        atomicMin(&ctrl->q_eff, block - 1);
+        decision = 1;
+      }
+    } else if (!(tr > 0.0)) {
+      if (mode == CHOL_FIRST_BLOCK0) atomicOr(&ctrl->flags, CTRL_RANK);
+      decision = 1;
+    }
+  }
+  __syncthreads();
+  if (!decision && mode == CHOL_FIRST_BLOCK0) {
+    const bool ok = chol_factor(k, G, 0.0, S, &minpiv, &fail);
+    if (t == 0 && (!ok || !(minpiv > tau * sqrt(tr)))) {
+      atomicOr(&ctrl->flags, CTRL_RANK);
+      decision = 1;
+    }
+    __syncthreads();
+  }
+  if (!decision) {
+    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
+    const bool ok = chol_factor(k, G, shift, S, &minpiv, &fail);
+    if (t == 0 && !ok) {
+      if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+      else atomicMin(&ctrl->q_eff, block - 1);
+      decision = 1;
+    }
+    __syncthreads();
+  }
+  if (decision) {
+    for (int i = t; i < k * k; i += 256) {
+      R[i] = 0.0;
+      Rinv[i] = 0.0;
+    }
+    return;
+  }
+  // Rinv = S^-1 (upper), rows from the bottom up:
+  // Rinv[i][j] = -(sum_{l=i+1..j} S[i][l] Rinv[l][j]) / S[i][i].
+  for (int i = t; i < k * k; i += 256) Ri[i] = 0.0;
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    const double rii = S[i * k + i];
+    for (int j = i + t; j < k; j += 256) {
+      if (j == i) {
+        Ri[i * k + i] = 1.0 / rii;
+      } else {
+        double s = 0.0;
+        for (int l = i + 1; l <= j; ++l) s += S[i * k + l] * Ri[l * k + j];
+        Ri[i * k + j] = -s / rii;
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = t; i < k * k; i += 256) {
+    R[i] = S[i];
+    if (use_lds) Rinv[i] = Ri[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void trmm_upper_kernel(int k, const double* A,
+                                                         const double* B,
+                                                         double* T) {
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    const int r = idx / k, c = idx % k;
+    double s = 0.0;
+    for (int l = r; l <= c; ++l) s += A[r * k + l] * B[l * k + c];
+    T[idx] = (c >= r) ? s : 0.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void col_sign_kernel(const T* Z, int64_t n,
+                                                       int64_t ldz,
+                                                       double* sign) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int c = blockIdx.x;
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int64_t bidx = n;
+  for (int64_t r = t; r < n; r += 256) {
+    const double a = fabs(static_cast<double>(Z[r * ldz + c]));
+    if (a > best) {  // rows visited in increasing order: first max kept
+      best = a;
+      bidx = r;
+    }
+  }
+  bv[t] = best;
+  bi[t] = bidx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      const double o = bv[t + w];
+      const int64_t oi = bi[t + w];
+      if (o > bv[t] || (o == bv[t] && oi < bi[t])) {
+        bv[t] = o;
+        bi[t] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    double sg = 1.0;
+    if (bi[0] < n && static_cast<double>(Z[bi[0] * ldz + c]) < 0.0) sg = -1.0;
+    sign[c] = sg;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void apply_sign_kernel(T* Z, int64_t n, int k,
+                                                         int64_t ldz, double* U,
+                                                         int64_t m, int64_t ldu,
+                                                         const double* sign) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  const int64_t nz = n * k;
+  if (i < nz) {
+    const int64_t r = i / k;
+    const int c = static_cast<int>(i - r * k);
+    if (sign[c] < 0.0) Z[r * ldz + c] = -Z[r * ldz + c];
+  } else if (U && i < nz + m * k) {
+    const int64_t j = i - nz;
+    const int64_t r = j / k;
+    const int c = static_cast<int>(j - r * k);
+    if (sign[c] < 0.0) U[r * ldu + c] = -U[r * ldu + c];
+  }
+}
+
+}  // namespace
+
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n > 0) fill_kernel<double><<<static_cast<unsigned>(cdiv(n, 256)), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n > 0) fill_kernel<float><<<static_cast<unsigned>(cdiv(n, 256)), 256, 0, s>>>(p, n, v);
+}
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n > 0) fill_kernel<int32_t><<<static_cast<unsigned>(cdiv(n, 256)), 256, 0, s>>>(p, n, v);
+}
+
+void launch_copy2d(const void* src, bool src_f64, int64_t lds, void* dst,
+                   bool dst_f64, int64_t ldd, int64_t rows, int64_t cols,
+                   hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const unsigned g = static_cast<unsigned>(cdiv(rows * cols, 256));
+  if (src_f64 && dst_f64)
+    copy2d_kernel<double, double><<<g, 256, 0, s>>>(
+        static_cast<const double*>(src), lds, static_cast<double*>(dst), ldd, rows, cols);
+  else if (src_f64)
+    copy2d_kernel<double, float><<<g, 256, 0, s>>>(
+        static_cast<const double*>(src), lds, static_cast<float*>(dst), ldd, rows, cols);
+  else if (dst_f64)
+    copy2d_kernel<float, double><<<g, 256, 0, s>>>(
+        static_cast<const float*>(src), lds, static_cast<double*>(dst), ldd, rows, cols);
+  else
+    copy2d_kernel<float, float><<<g, 256, 0, s>>>(
+        static_cast<const float*>(src), lds, static_cast<float*>(dst), ldd, rows, cols);
+}
+
+void launch_axpy_f64(const double* x, double* y, int64_t n, hipStream_t s) {
+  if (n > 0) axpy_kernel<<<static_cast<unsigned>(cdiv(n, 256)), 256, 0, s>>>(x, y, n);
+}
+
+void launch_ctrl_init(Ctrl* c, int32_t q, hipStream_t s) {
+  ctrl_init_kernel<<<1, 64, 0, s>>>(c, q);
+}
+void launch_ctrl_reset_off(Ctrl* c, hipStream_t s) {
+  ctrl_reset_off_kernel<<<1, 64, 0, s>>>(c);
+}
+
+void launch_chol(int k, const double* G, const double* Gpre, int mode, int block,
+                 double tau, double shift_coef, double* R, double* Rinv,
+                 double* work, Ctrl* ctrl, hipStream_t s) {
+  // Both k x k factors in LDS when they fit (k <= 96: 144 KB of 160 KB).
+  const size_t need = static_cast<size_t>(2) * k * k * sizeof(double);
+  const int use_lds = k <= 96 ? 1 : 0;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(chol_kernel),
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    attr_set = true;
+  }
+  chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau,
+                                                 shift_coef, R, Rinv, work, ctrl,
+                                                 use_lds);
+}
+
+void launch_trmm_upper(int k, const double* A, const double* B, double* T,
+                       hipStream_t s) {
+  trmm_upper_kernel<<<1, 256, 0, s>>>(k, A, B, T);
+}
+
+void launch_sign_normalize(void* Z, bool f64, int64_t n, int k, int64_t ldz,
+                           double* U, int64_t m, int64_t ldu, double* sign,
+                           hipStream_t s) {
+  if (k <= 0) return;
+  const int64_t tot = n * k + (U ? m * k : 0);
+  const unsigned g = static_cast<unsigned>(cdiv(tot, 256));
+  if (f64) {
+    col_sign_kernel<double><<<k, 256, 0, s>>>(static_cast<const double*>(Z), n, ldz, sign);
+    apply_sign_kernel<double><<<g, 256, 0, s>>>(static_cast<double*>(Z), n, k, ldz, U, m,
+                                                ldu, sign);
+  } else {
+    col_sign_kernel<float><<<k, 256, 0, s>>>(static_cast<const float*>(Z), n, ldz, sign);
+    apply_sign_kernel<float><<<g, 256, 0, s>>>(static_cast<float*>(Z), n, k, ldz, U, m,
+                                               ldu, sign);
+  }
+}
+
+}  // namespace bk

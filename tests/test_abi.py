@@ -1,0 +1,119 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/bk.h declares, sizes its workspaces, and rejects bad
+arguments with BK_EINVAL before launching anything."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1504_05477_amd as bk
+from paper_1504_05477_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "bk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bk_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return bk.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", bk.LIB_PATH],
+                         capture_output=True, text=True, check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    declared = _declared()
+    assert len(declared) >= 18
+    missing = [s for s in declared if s not in syms]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert set(declared) <= set(L.EXPORTS)
+
+
+def test_status_strings(lib):
+    assert lib.bk_status_string(0) == b"ok"
+    assert b"rank" in lib.bk_status_string(6)
+    assert lib.bk_version().startswith(b"bk ")
+
+
+def test_struct_layouts():
+    assert C.sizeof(L.Options) == 72
+    assert L.Info.workspace_bytes.offset == 112
+
+
+def _opt():
+    o = L.Options()
+    o.struct_size = C.sizeof(L.Options)
+    return o
+
+
+def test_workspace_sizes(lib):
+    o = _opt()
+    small = lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o))
+    assert small > 2000 * 90 * 8
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F32, C.byref(o)) < small
+    assert lib.bk_svd_dense_workspace(2000, 1000, 0, 8, L.F64, C.byref(o)) == 0
+    assert lib.bk_svd_dense_workspace(100, 50, 10, 5, L.F64, C.byref(o)) == 0  # m > d
+    assert lib.bk_svd_csr_workspace(11000, 130000, 1_500_000, 20, 10, C.byref(o)) > 0
+    assert lib.bk_svd_csr_workspace(10, 10, 2**31, 2, 1, C.byref(o)) == 0
+    assert lib.bk_eigh_psd_workspace(90) > 90 * 90 * 8
+
+
+@pytest.mark.parametrize("n,d,k,q", [(100, 50, 0, 1), (100, 50, 51, 0), (100, 50, 5, -1),
+                                     (100, 50, 10, 5), (0, 50, 1, 0)])
+def test_dense_rejects_bad_shapes(lib, n, d, k, q):
+    st = lib.bk_svd_dense(C.c_void_p(16), 50, L.F32, None, None, 0, n, d, k, q, 0, None,
+                          C.c_void_p(16), 10, C.c_void_p(16), None, None, 0, None)
+    assert st == L.EINVAL
+
+
+def test_dense_rejects_bad_pointers_and_strides(lib):
+    args = dict(n=100, d=50, k=5, q=1)
+    # null A
+    assert lib.bk_svd_dense(None, 50, L.F32, None, None, 0, 100, 50, 5, 1, 0, None,
+                            C.c_void_p(16), 5, C.c_void_p(16), None, None, 0, None) == L.EINVAL
+    # lda < d
+    assert lib.bk_svd_dense(C.c_void_p(16), 49, L.F32, None, None, 0, 100, 50, 5, 1, 0, None,
+                            C.c_void_p(16), 5, C.c_void_p(16), None, None, 0, None) == L.EINVAL
+    # FP8 without scales
+    assert lib.bk_svd_dense(C.c_void_p(16), 50, L.FP8_E4M3, None, None, 0, 100, 50, 5, 1, 0,
+                            None, C.c_void_p(16), 5, C.c_void_p(16), None, None, 0,
+                            None) == L.EINVAL
+    # refine requested without a master copy
+    o = _opt()
+    o.refine = 1
+    assert lib.bk_svd_dense(C.c_void_p(16), 50, L.BF16, None, None, 0, 100, 50, 5, 1, 0,
+                            C.byref(o), C.c_void_p(16), 5, C.c_void_p(16), None, None, 0,
+                            None) == L.EINVAL
+    # unknown dtype
+    assert lib.bk_svd_dense(C.c_void_p(16), 50, 7, None, None, 0, 100, 50, 5, 1, 0, None,
+                            C.c_void_p(16), 5, C.c_void_p(16), None, None, 0, None) == L.EINVAL
+    del args
+
+
+def test_csr_and_helpers_reject_bad_arguments(lib):
+    assert lib.bk_svd_csr(None, None, None, None, None, None, 10, 10, 5, 2, 1, 0, None,
+                          C.c_void_p(16), 2, C.c_void_p(16), None, None, 0, None) == L.EINVAL
+    # half a transpose given
+    assert lib.bk_svd_csr(C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16),
+                          None, None, 10, 10, 5, 2, 1, 0, None, C.c_void_p(16), 2,
+                          C.c_void_p(16), None, None, 0, None) == L.EINVAL
+    assert lib.bk_gaussian(0, 4, 4, 3, L.F32, C.c_void_p(16), None) == L.EINVAL
+    assert lib.bk_gaussian(0, 4, 4, 4, L.BF16, C.c_void_p(16), None) == L.EINVAL
+    assert lib.bk_quantize_dense(C.c_void_p(16), 4, 4, 4, L.FP8_E4M3, C.c_void_p(16), None,
+                                 None) == L.EINVAL
+    assert lib.bk_eigh_psd(None, 4, 4, None, None, 4, 0, 0.0, None, None, 0, None) == L.EINVAL
+    assert lib.bk_dense_product(0, C.c_void_p(16), 3, L.F32, None, 4, 4, C.c_void_p(16), 2, 2,
+                                C.c_void_p(16), 2, None, 0, None) == L.EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(ImportError):
+        L.load(str(tmp_path / "libbk.so"))
