@@ -1,0 +1,307 @@
+"""Benchmark of the Block Krylov hot path on one MI355X.
+
+A step is one whole solve (sketch, Krylov products, projection,
+CholeskyQR, M = W^T W, Jacobi eigen-solve, Z = Q U_k) on one synthetic input
+already resident in HBM.  Default workload: the term-document CSR matrix
+(11000 x 130000, ~1.47M nonzeros, log-normal row lengths, Zipf(1.1) terms,
+log(1+tf)*idf values), k = 20, q = 10, implicit row centring, FP32.
+
+Metric: GB/s of the Krylov block products A.X / A^T.Y, i.e. the algorithmic
+bytes those products must move in one solve divided by the time of the whole
+solve.  The roofline object reports the dominant product kernel alone:
+algorithmic bytes per launch / its average launch time (HIP events recorded
+on the solve's stream inside the timed steps) against the 8 TB/s HBM peak.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--workload csr2|dense1|dense3|dense4|dense5] [--precision plain|bf16|fp8]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+METRIC = ("Krylov A·X/Aᵀ·Y GB/s or TFLOP/s & time-to-ε "
+          "(BF16/FP8 vs FP32), 1 GPU")
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFS = 157.3
+DESCR = {
+    "csr2": "term-document CSR 11000x130000 (~1.47M nnz, log-normal rows, Zipf(1.1) "
+            "terms, log(1+tf)*idf), k=20, q=10, implicit row centring",
+    "dense1": "dense planted sigma_i=i^-1/2 2000x1000, k=10, q=8, FP64",
+    "dense3": "dense planted sigma_i=exp(-i/200)+1e-3 (+1e-4 noise) 65536x16384, k=100, q=12",
+    "dense4": "dense planted sigma_i=1/i 8192x4096, k=32, q=10",
+    "dense5": "dense planted sigma_i=i^-0.8 131072x32768, k=256, q=8",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------- inputs --
+def make_csr(w):
+    rp, ci, va = workloads.term_document_csr(w.n, w.d, w.seed_matrix)
+    return rp, ci, va
+
+
+def csr_product_bytes(n, d, nnz, k):
+    """Algorithmic bytes of one A.X and one A^T.Y (CSR of A^T): values and
+    column ids once, row pointers once, the dense input block once, the
+    output block once."""
+    ax = nnz * 8 + (n + 1) * 4 + d * k * 4 + n * k * 4
+    aty = nnz * 8 + (d + 1) * 4 + n * k * 4 + d * k * 4
+    return ax, aty
+
+
+def dense_product_bytes(n, d, k, a_bytes, x_bytes):
+    ax = n * d * a_bytes + d * k * x_bytes + n * k * x_bytes
+    aty = n * d * a_bytes + n * k * x_bytes + d * k * x_bytes
+    return ax, aty
+
+
+def source_sha(names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_1504_05477_amd", "csrc", nm), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_key, sha):
+    """HBM bytes per launch from the committed rocprofv3 counter summary of
+    this kernel, if it was taken on the current source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_key}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                key, v = line.split(":", 1)
+                vals[key.strip()] = v.strip()
+    if vals.get("source_sha") != sha:
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---------------------------------------------------------------- main --
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="csr2", choices=sorted(workloads.WORKLOADS))
+    ap.add_argument("--precision", default="plain", choices=["plain", "bf16", "fp8"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1504_05477_amd as bk
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    bk.load()
+    dev = torch.device("cuda:0")
+    w = workloads.WORKLOADS[args.workload]
+    k, q = w.k, w.q
+    t_gen = time.perf_counter()
+    host_inputs = {}
+    if w.kind == "csr":
+        rp, ci, va = make_csr(w)
+        host_inputs = {"rp": rp, "ci": ci, "va": va}
+        g_rp = torch.from_numpy(rp).to(dev)
+        g_ci = torch.from_numpy(ci).to(dev)
+        g_va = torch.from_numpy(va).to(dev)
+        nnz = int(ci.size)
+        bx, by = csr_product_bytes(w.n, w.d, nnz, k)
+        dtype = "f32"
+
+        def step():
+            return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
+                              center=w.center, timing=True)
+        kern_src = ["csr.hip"]
+        kern_names = {"ax": "csr_spmm_kernel (A.X, CSR of A)",
+                      "aty": "csr_spmm_kernel (A^T.Y, CSR of A^T)"}
+    else:
+        sv = workloads.spectrum(w.spectrum, min(w.n, w.d))
+        if w.n * w.d <= 4_000_000:
+            A64 = workloads.planted_dense(w.n, w.d, sv, w.seed_matrix)
+            host_inputs = {"A": A64}
+            A = torch.from_numpy(A64).to(dev)
+            if w.dtype != "f64":
+                A = A.float()
+        else:
+            A = workloads.planted_dense_torch(w.n, w.d, sv, w.seed_matrix, device=dev,
+                                              noise=w.noise, noise_seed=w.seed_noise)
+        if w.dtype == "f64":
+            A = A.double()
+        kw = {}
+        a_bytes = A.element_size()
+        dtype = "f64" if A.dtype == torch.float64 else "f32"
+        if args.precision == "bf16":
+            kw = {"A_master": A}
+            A_in = bk.quantize(A, "bf16")
+            a_bytes, dtype = 2, "bf16"
+        elif args.precision == "fp8":
+            codes, sc = bk.quantize(A, "fp8")
+            kw = {"A_master": A, "a_scales": sc}
+            A_in = codes
+            a_bytes, dtype = 1, "fp8"
+        else:
+            A_in = A
+        x_bytes = 8 if A.dtype == torch.float64 else 4
+        bx, by = dense_product_bytes(w.n, w.d, k, a_bytes, x_bytes)
+
+        def step():
+            return bk.svd_dense(A_in, k, q, seed=w.seed_sketch, timing=True, **kw)
+        kern_src = ["gemm.hip", "gemm_mfma.hip"]
+        kern_names = {"ax": "A.X product kernel", "aty": "A^T.Y product kernel"}
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s ({args.workload})")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = step()
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    bytes_per_solve = (q + 1) * (bx + by)
+    value = bytes_per_solve / (ms_step * 1e-3) / 1e9
+
+    def tot(key, what="ms"):
+        return sum(float(i[what][key]) for i in infos)
+    ph = {p: tot(p) / args.steps for p in infos[0]["ms"]}
+    if args.breakdown:
+        log("phase ms/step: " + ", ".join(f"{p}={v:.3f}" for p, v in ph.items()))
+        log(f"launches/step: {infos[0]['launches']}")
+    dom = "ax" if tot("ax") >= tot("aty") else "aty"
+    nl = tot(dom, "launches")
+    avg_ms = tot(dom) / max(nl, 1)
+    per_launch = bx if dom == "ax" else by
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    sha = source_sha(kern_src)
+    kernel_key = f"{'csr_spmm' if w.kind == 'csr' else 'dense_product'}_{dom}_{args.workload}"
+    traffic = read_traffic(kernel_key, sha)
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "kernel": kern_names[dom],
+            "avg_launch_ms": round(avg_ms, 5),
+            "algorithmic_bytes_per_launch": int(per_launch), "source_sha": sha}
+    if w.kind == "dense" and args.precision == "plain":
+        flops = 2.0 * w.n * w.d * k
+        tf = flops / (avg_ms * 1e-3) / 1e12
+        if flops / per_launch > FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9):
+            roof.update({"bound": "mfma", "achieved": round(tf, 3),
+                         "peak": FP32_PEAK_TFS if dtype == "f32" else 78.6,
+                         "unit": "TFLOP/s", "frac": round(tf / (FP32_PEAK_TFS if dtype == "f32" else 78.6), 4)})
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {DESCR[args.workload]}",
+                   "n": w.n, "d": w.d, "k": k, "q": q,
+                   "precision": args.precision,
+                   "product_bytes_per_solve": int(bytes_per_solve)},
+        "roofline": roof,
+        "phases_ms_per_step": {p: round(v, 4) for p, v in ph.items()},
+        "q_eff": infos[-1]["q_eff"],
+        "jacobi_sweeps": infos[-1]["jacobi_sweeps"],
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["parity"] = cpu_baseline(args, w, host_inputs, r,
+                                                          bytes_per_solve)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(args, w, host, res, bytes_per_solve):
+    """The oracle, as it stands, on the host cores: whole solves of the same
+    input repeated for about --cpu-seconds (the sample), in the same unit."""
+    import scipy.sparse as sp
+    from threadpoolctl import threadpool_info
+
+    from oracle import bki, metrics, philox
+
+    k, q = w.k, w.q
+    Pi = philox.gaussian(w.seed_sketch, w.d, k)
+    if w.kind == "csr":
+        A = sp.csr_matrix((host["va"].astype(np.float64), host["ci"], host["rp"]),
+                          shape=(w.n, w.d))
+        Pi = Pi.astype(np.float32).astype(np.float64)
+        tau = 1e-5
+    elif "A" in host:
+        A = host["A"] if w.dtype == "f64" else host["A"].astype(np.float32).astype(np.float64)
+        if w.dtype != "f64":
+            Pi = Pi.astype(np.float32).astype(np.float64)
+        tau = 1e-11 if w.dtype == "f64" else 1e-5
+    else:
+        return ({"value": None, "unit": "GB/s", "cores": 0, "kind": "oracle",
+                 "sample": "skipped: matrix generated on the GPU only"}, None)
+    times = []
+    ref = None
+    t_end = time.perf_counter() + args.cpu_seconds
+    while time.perf_counter() < t_end or not times:
+        t0 = time.perf_counter()
+        ref = bki.block_krylov(A, Pi, k, q, center=w.center, tau=tau)
+        times.append(time.perf_counter() - t0)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    per = float(np.median(times))
+    base = {"value": round(bytes_per_solve / per / 1e9, 4), "unit": "GB/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": f"{len(times)} whole solves of the same input "
+                      f"(median {per * 1e3:.1f} ms/solve, NumPy/SciPy float64; sparse "
+                      f"products single-threaded, dense BLAS on {threads} threads)",
+            "ms_per_solve": round(per * 1e3, 2)}
+    Zg = res.Z.double().cpu().numpy()
+    sg = res.sigma.cpu().numpy()
+    rel = float(np.max(np.abs(sg - ref.sigma) / ref.sigma))
+    j = 0   # widest leading subspace with relative Ritz gap >= 1e-2
+    for jj in range(1, k + 1):
+        if (ref.theta[jj - 1] - ref.theta[jj]) / ref.theta[0] >= 1e-2:
+            j = jj
+    ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j]) if j else None
+    parity = {"ritz_rel_max": rel, "principal_angle_rad": ang, "gap_separated_j": j,
+              "angle_at_k_rad": metrics.principal_angle(ref.Z, Zg)}
+    return base, parity
+
+
+if __name__ == "__main__":
+    main()

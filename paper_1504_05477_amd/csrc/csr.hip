@@ -26,99 +26,151 @@ __global__ __launch_bounds__(256) void csr_validate_kernel(const int32_t* rp,
   if (bad) atomicAdd(&ctrl->csr_bad, 1);
 }
 
-// One wavefront per row.  KC lanes cover KC output columns and the 64 / KC
-// lane groups ("slots") walk the row's nonzeros with stride 64 / KC; the
-// slots are then added with a fixed butterfly, so the sum order is fixed.
-template <int KC>
+// Lane layout shared by the product kernels: a wavefront is split into
+// SLOTS = 64 / KC slots of KC lanes (KC = min(k, 64)); lane c of a slot owns
+// output column c0 + c.  A slot walks a run of nonzeros in chunks of KC: the
+// chunk's (column id, value) pairs are loaded with one coalesced access (one
+// per lane, next chunk prefetched), then broadcast inside the slot with
+// shuffles while eight independent X-row gathers are in flight.
+__device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
+                                          const float* __restrict__ v,
+                                          const float* __restrict__ X, int64_t ldx,
+                                          int32_t b, int32_t e, int32_t step, int KC,
+                                          int base, int c, int col, bool colok) {
+  float acc = 0.0f;
+  int32_t j = b + c;
+  int32_t nci = (j < e && c < KC) ? ci[j] : 0;
+  float nv = (j < e && c < KC) ? v[j] : 0.0f;
+  for (int32_t j0 = b; j0 < e; j0 += step) {
+    const int32_t myci = nci;
+    const float myv = nv;
+    const int cnt = (e - j0 < KC) ? (e - j0) : KC;
+    const int32_t jn = j0 + step + c;
+    nci = (jn < e) ? ci[jn] : 0;
+    nv = (jn < e) ? v[jn] : 0.0f;
+    int t = 0;
+    for (; t + 8 <= cnt; t += 8) {
+      int32_t cc[8];
+      float vv[8], xx[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        cc[u] = __shfl(myci, base + t + u);
+        vv[u] = __shfl(myv, base + t + u);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += vv[u] * xx[u];
+    }
+    for (; t < cnt; ++t) {
+      const int32_t c1 = __shfl(myci, base + t);
+      const float v1 = __shfl(myv, base + t);
+      const float x1 = colok ? X[static_cast<int64_t>(c1) * ldx + col] : 0.0f;
+      acc += v1 * x1;
+    }
+  }
+  return acc;
+}
+
+// Rows of at most short_thr nonzeros: one slot per row (SLOTS rows per
+// wavefront).  Longer rows are left to the piece kernels.
 __global__ __launch_bounds__(256) void csr_spmm_kernel(
-    int64_t rows, int k, const int32_t* __restrict__ rp,
+    int64_t rows, int k, int KC, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ ci, const float* __restrict__ v,
     const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
     const float* __restrict__ rowvec, const double* __restrict__ colvec,
-    int long_thr) {
-  constexpr int SLOTS = 64 / KC;
-  const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (row >= rows) return;
+    int short_thr) {
+  const int SLOTS = 64 / KC;
+  const int64_t wave = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int slot = lane / KC, c = lane % KC;
-  const int32_t beg = rp[row], end = rp[row + 1];
-  if (end - beg > long_thr) return;
-  const float rv = rowvec ? rowvec[row] : 1.0f;
+  const int s = lane / KC, c = lane - s * KC;
+  const int64_t row = wave * SLOTS + s;
+  const bool valid = s < SLOTS && row < rows;
+  int32_t beg = 0, end = 0;
+  bool own = false;
+  if (valid) {
+    beg = rp[row];
+    end = rp[row + 1];
+    own = end - beg <= short_thr;
+    if (!own) end = beg;  // the piece kernels take this row
+  }
+  const float rv = (valid && rowvec) ? rowvec[row] : 1.0f;
   for (int c0 = 0; c0 < k; c0 += KC) {
     const int col = c0 + c;
-    float acc = 0.0f;
-    if (col < k) {
-      int32_t j = beg + slot;
-      // two nonzeros in flight per slot
-      for (; j + SLOTS < end; j += 2 * SLOTS) {
-        const int32_t c1 = ci[j], c2 = ci[j + SLOTS];
-        const float v1 = v[j], v2 = v[j + SLOTS];
-        const float x1 = X[static_cast<int64_t>(c1) * ldx + col];
-        const float x2 = X[static_cast<int64_t>(c2) * ldx + col];
-        acc += v1 * x1;
-        acc += v2 * x2;
-      }
-      if (j < end) acc += v[j] * X[static_cast<int64_t>(ci[j]) * ldx + col];
-    }
-#pragma unroll
-    for (int off = KC; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-    if (slot == 0 && col < k) {
+    const bool colok = valid && col < k;
+    float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok);
+    if (own && col < k) {
       if (colvec) acc -= rv * static_cast<float>(colvec[col]);
       Y[row * ldy + col] = acc;
     }
   }
 }
 
-// One 1024-thread workgroup per long row: 16 waves take contiguous segments,
-// wave partial sums are added in wave order.
-template <int KC>
-__global__ __launch_bounds__(1024) void csr_spmm_long_kernel(
-    const int32_t* __restrict__ list, const int32_t* __restrict__ rp,
-    const int32_t* __restrict__ ci, const float* __restrict__ v, int k,
-    const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
-    const float* __restrict__ rowvec, const double* __restrict__ colvec) {
-  constexpr int SLOTS = 64 / KC;
-  __shared__ float part[16][KC];
-  const int64_t row = list[blockIdx.x];
-  const int wave = threadIdx.x >> 6;
-  const int lane = threadIdx.x & 63;
-  const int slot = lane / KC, c = lane % KC;
-  const int32_t beg = rp[row], end = rp[row + 1];
-  const int32_t seg = (end - beg + 15) / 16;
-  const int32_t sb = beg + wave * seg;
-  const int32_t se = (sb + seg < end) ? sb + seg : end;
-  const float rv = rowvec ? rowvec[row] : 1.0f;
+// Long rows are cut into pieces of kPiece nonzeros; blockIdx = (long row i,
+// piece p), one wavefront.  Its slots take interleaved chunks of the piece
+// and are added in slot order; the piece sum goes to part[poff[i] + p].
+__global__ __launch_bounds__(64) void csr_pieces_kernel(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ npc,
+    const int32_t* __restrict__ poff, int k, int KC, int piece,
+    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const float* __restrict__ v, const float* __restrict__ X, int64_t ldx,
+    float* __restrict__ part) {
+  const int i = blockIdx.x;
+  const int p = blockIdx.y;
+  if (p >= npc[i]) return;
+  const int SLOTS = 64 / KC;
+  const int lane = threadIdx.x;
+  const int s = lane / KC, c = lane - s * KC;
+  const int64_t row = list[i];
+  const int32_t b = rp[row] + p * piece;
+  const int32_t e = (b + piece < rp[row + 1]) ? b + piece : rp[row + 1];
   for (int c0 = 0; c0 < k; c0 += KC) {
     const int col = c0 + c;
-    float acc = 0.0f;
-    if (col < k)
-      for (int32_t j = sb + slot; j < se; j += SLOTS)
-        acc += v[j] * X[static_cast<int64_t>(ci[j]) * ldx + col];
-#pragma unroll
-    for (int off = KC; off < 64; off <<= 1) acc += __shfl_xor(acc, off);
-    if (slot == 0) part[wave][c] = acc;
-    __syncthreads();
-    if (threadIdx.x < KC && c0 + static_cast<int>(threadIdx.x) < k) {
-      float s = 0.0f;
-      for (int w = 0; w < 16; ++w) s += part[w][threadIdx.x];
-      const int cc = c0 + threadIdx.x;
-      if (colvec) s -= rv * static_cast<float>(colvec[cc]);
-      Y[row * ldy + cc] = s;
-    }
-    __syncthreads();
+    const bool colok = s < SLOTS && col < k;
+    const int32_t bs = (s < SLOTS) ? b + s * KC : e;
+    float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok);
+    float tot = 0.0f;
+    for (int ss = 0; ss < SLOTS; ++ss) tot += __shfl(acc, ss * KC + c);
+    if (s == 0 && col < k) part[(static_cast<int64_t>(poff[i]) + p) * k + col] = tot;
   }
 }
 
-__global__ __launch_bounds__(256) void csr_long_rows_kernel(const int32_t* rp,
-                                                            int64_t rows,
-                                                            int long_thr,
-                                                            int32_t* list,
-                                                            int32_t* count) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= rows) return;
-  if (rp[i + 1] - rp[i] > long_thr) {
-    const int32_t pos = atomicAdd(count, 1);
-    list[pos] = static_cast<int32_t>(i);
+// Y[row] = sum of the row's piece sums in piece order (- centring).
+__global__ __launch_bounds__(256) void csr_combine_kernel(
+    const int32_t* __restrict__ list, const int32_t* __restrict__ npc,
+    const int32_t* __restrict__ poff, int nlong, int k,
+    const float* __restrict__ part, float* __restrict__ Y, int64_t ldy,
+    const float* __restrict__ rowvec, const double* __restrict__ colvec) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= nlong) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = list[i];
+  const float rv = rowvec ? rowvec[row] : 1.0f;
+  for (int col = lane; col < k; col += 64) {
+    float acc = 0.0f;
+    for (int p = 0; p < npc[i]; ++p) acc += part[(static_cast<int64_t>(poff[i]) + p) * k + col];
+    if (colvec) acc -= rv * static_cast<float>(colvec[col]);
+    Y[row * ldy + col] = acc;
+  }
+}
+
+// Rows longer than short_thr: list them with their piece counts; counters[0]
+// = number of listed rows, counters[1] = largest piece count.
+__global__ __launch_bounds__(256) void csr_classify_kernel(const int32_t* rp,
+                                                           int64_t rows,
+                                                           int short_thr, int piece,
+                                                           int32_t* list, int32_t* npc,
+                                                           int32_t* counters) {
+  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (r >= rows) return;
+  const int32_t len = rp[r + 1] - rp[r];
+  if (len > short_thr) {
+    const int32_t pos = atomicAdd(&counters[0], 1);
+    const int32_t np = (len + piece - 1) / piece;
+    list[pos] = static_cast<int32_t>(r);
+    npc[pos] = np;
+    atomicMax(&counters[1], np);
   }
 }
 
@@ -235,12 +287,7 @@ __global__ __launch_bounds__(256) void sort_rows_kernel(const int32_t* trp,
   }
 }
 
-int kc_for(int k) {
-  if (k <= 8) return 8;
-  if (k <= 16) return 16;
-  if (k <= 32) return 32;
-  return 64;
-}
+int kc_for(int k) { return k < 64 ? k : 64; }
 
 }  // namespace
 
@@ -254,60 +301,38 @@ void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
                      int64_t rows, int k, const float* X, int64_t ldx, float* Y,
                      int64_t ldy, const float* rowvec, const double* colvec,
-                     int long_thr, hipStream_t s) {
+                     int short_thr, hipStream_t s) {
   if (rows <= 0 || k <= 0) return;
-  const dim3 grid(static_cast<unsigned>(cdiv(rows, 4)));
-  switch (kc_for(k)) {
-    case 8:
-      csr_spmm_kernel<8><<<grid, 256, 0, s>>>(rows, k, rp, ci, v, X, ldx, Y, ldy,
-                                              rowvec, colvec, long_thr);
-      break;
-    case 16:
-      csr_spmm_kernel<16><<<grid, 256, 0, s>>>(rows, k, rp, ci, v, X, ldx, Y, ldy,
-                                               rowvec, colvec, long_thr);
-      break;
-    case 32:
-      csr_spmm_kernel<32><<<grid, 256, 0, s>>>(rows, k, rp, ci, v, X, ldx, Y, ldy,
-                                               rowvec, colvec, long_thr);
-      break;
-    default:
-      csr_spmm_kernel<64><<<grid, 256, 0, s>>>(rows, k, rp, ci, v, X, ldx, Y, ldy,
-                                               rowvec, colvec, long_thr);
-      break;
-  }
+  const int KC = kc_for(k);
+  const int64_t waves = cdiv(rows, 64 / KC);
+  csr_spmm_kernel<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
+      rows, k, KC, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec, short_thr);
 }
 
-void launch_csr_spmm_long(const int32_t* list, int nlong, const int32_t* rp,
-                          const int32_t* ci, const float* v, int k, const float* X,
-                          int64_t ldx, float* Y, int64_t ldy, const float* rowvec,
-                          const double* colvec, hipStream_t s) {
-  if (nlong <= 0 || k <= 0) return;
-  switch (kc_for(k)) {
-    case 8:
-      csr_spmm_long_kernel<8><<<nlong, 1024, 0, s>>>(list, rp, ci, v, k, X, ldx, Y,
-                                                     ldy, rowvec, colvec);
-      break;
-    case 16:
-      csr_spmm_long_kernel<16><<<nlong, 1024, 0, s>>>(list, rp, ci, v, k, X, ldx, Y,
-                                                      ldy, rowvec, colvec);
-      break;
-    case 32:
-      csr_spmm_long_kernel<32><<<nlong, 1024, 0, s>>>(list, rp, ci, v, k, X, ldx, Y,
-                                                      ldy, rowvec, colvec);
-      break;
-    default:
-      csr_spmm_long_kernel<64><<<nlong, 1024, 0, s>>>(list, rp, ci, v, k, X, ldx, Y,
-                                                      ldy, rowvec, colvec);
-      break;
-  }
-}
-
-void launch_csr_long_rows(const int32_t* rp, int64_t rows, int long_thr,
-                          int32_t* list, int32_t* count, hipStream_t s) {
-  launch_fill_i32(count, 1, 0, s);
+void launch_csr_classify(const int32_t* rp, int64_t rows, int short_thr,
+                         int32_t* list, int32_t* npc, int32_t* counters,
+                         hipStream_t s) {
+  launch_fill_i32(counters, 2, 0, s);
   if (rows > 0)
-    csr_long_rows_kernel<<<static_cast<unsigned>(cdiv(rows, 256)), 256, 0, s>>>(
-        rp, rows, long_thr, list, count);
+    csr_classify_kernel<<<static_cast<unsigned>(cdiv(rows, 256)), 256, 0, s>>>(
+        rp, rows, short_thr, kCsrPiece, list, npc, counters);
+}
+
+void launch_csr_pieces(const CsrPieces& pl, const int32_t* rp, const int32_t* ci,
+                       const float* v, int k, const float* X, int64_t ldx, float* Y,
+                       int64_t ldy, const float* rowvec, const double* colvec,
+                       hipStream_t s) {
+  if (pl.nlong <= 0 || k <= 0) return;
+  const int KC = kc_for(k);
+  const dim3 grid(static_cast<unsigned>(pl.nlong), static_cast<unsigned>(pl.maxp));
+  csr_pieces_kernel<<<grid, 64, 0, s>>>(pl.list, pl.npc, pl.poff, k, KC, kCsrPiece, rp, ci,
+                                        v, X, ldx, pl.part);
+  csr_combine_kernel<<<static_cast<unsigned>(cdiv(pl.nlong, 4)), 256, 0, s>>>(
+      pl.list, pl.npc, pl.poff, pl.nlong, k, pl.part, Y, ldy, rowvec, colvec);
+}
+
+void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s) {
+  scan_kernel<<<1, 1024, 0, s>>>(cnt, n, out);
 }
 
 void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,

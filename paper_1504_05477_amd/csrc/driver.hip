@@ -29,7 +29,6 @@ namespace {
 
 constexpr double kEps64 = 2.220446049250313e-16;
 constexpr double kUnit64 = 1.1102230246251565e-16;  // 2^-53
-constexpr int kLongRow = 4096;  // CSR rows longer than this get a workgroup
 
 // ------------------------------------------------------------ workspace --
 struct Arena {
@@ -141,7 +140,9 @@ struct Layout {
   JacobiWs jk;
   // CSR
   int32_t *trp = nullptr, *tci = nullptr, *cursor = nullptr, *long_a = nullptr,
-          *long_t = nullptr, *nlong = nullptr;
+          *long_t = nullptr, *npc_a = nullptr, *npc_t = nullptr, *poff_a = nullptr,
+          *poff_t = nullptr, *counters = nullptr;
+  float* part = nullptr;
   float* tv = nullptr;
   unsigned long long* keys = nullptr;
   float* mu = nullptr;
@@ -197,8 +198,14 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
       L.keys = ar.take<unsigned long long>(static_cast<size_t>(3 * nnz));
     }
     L.long_a = ar.take<int32_t>(static_cast<size_t>(n));
+    L.npc_a = ar.take<int32_t>(static_cast<size_t>(n));
+    L.poff_a = ar.take<int32_t>(static_cast<size_t>(n + 1));
     L.long_t = ar.take<int32_t>(static_cast<size_t>(d));
-    L.nlong = ar.take<int32_t>(2);
+    L.npc_t = ar.take<int32_t>(static_cast<size_t>(d));
+    L.poff_t = ar.take<int32_t>(static_cast<size_t>(d + 1));
+    L.counters = ar.take<int32_t>(4);
+    L.part = ar.take<float>(static_cast<size_t>(nnz / kCsrPiece + std::max(n, d) + 1) *
+                            static_cast<size_t>(k));
     L.mu = ar.take<float>(static_cast<size_t>(n));
     L.ones = ar.take<float>(static_cast<size_t>(d));
     L.colvec = ar.take<double>(static_cast<size_t>(k));
@@ -208,26 +215,45 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
 }
 
 // ---------------------------------------------------------------- timer --
+// Events are recycled through a per-thread pool: timing a solve costs one
+// hipEventRecord per phase boundary, no creation.
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  hipEvent_t get() {
+    if (used == ev.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[used++];
+  }
+};
+thread_local EventPool g_events;
+
 struct Timer {
   bool on = false;
   hipStream_t s = nullptr;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
   int launches[BK_NPHASE] = {0};
   int cur = -1;
+  size_t pool_mark = 0;
   hipEvent_t start{};
   void begin(int ph) {
     cur = ph;
     if (!on) return;
-    hipEventCreate(&start);
-    hipEventRecord(start, s);
+    if (marks.empty()) pool_mark = g_events.used;
+    start = g_events.get();
+    if (start) hipEventRecord(start, s);
   }
   void end(int nlaunch) {
     if (cur >= 0) launches[cur] += nlaunch;
-    if (on) {
-      hipEvent_t stop;
-      hipEventCreate(&stop);
-      hipEventRecord(stop, s);
-      marks.push_back({cur, {start, stop}});
+    if (on && start) {
+      hipEvent_t stop = g_events.get();
+      if (stop) {
+        hipEventRecord(stop, s);
+        marks.push_back({cur, {start, stop}});
+      }
     }
     cur = -1;
   }
@@ -244,10 +270,9 @@ struct Timer {
     }
   }
   ~Timer() {
-    for (auto& mk : marks) {
-      hipEventDestroy(mk.second.first);
-      hipEventDestroy(mk.second.second);
-    }
+    // the events go back to the pool once their times have been read (the
+    // solve synchronizes the stream before collect())
+    if (on && !marks.empty()) g_events.used = pool_mark;
   }
 };
 
@@ -315,8 +340,7 @@ struct DenseOp : Op {
 struct CsrOp : Op {
   const int32_t *rp = nullptr, *ci = nullptr, *trp = nullptr, *tci = nullptr;
   const float *v = nullptr, *tv = nullptr;
-  const int32_t *long_a = nullptr, *long_t = nullptr;
-  int nlong_a = 0, nlong_t = 0;
+  CsrPieces pa, pt;             // rows longer than kCsrShort of A and A^T
   const float* mu = nullptr;    // row means (centring) or null
   const float* ones = nullptr;  // d ones
   double* colvec = nullptr;     // k
@@ -341,32 +365,28 @@ struct CsrOp : Op {
     launch_tn(a, s);
     tm->end(2);
   }
+  void product(const int32_t* r_, const int32_t* c_, const float* v_, int64_t rows,
+               const CsrPieces& pl, int phase, const void* X, int64_t ldx, int k, void* Y,
+               int64_t ldy, const float* rowvec, hipStream_t s) {
+    const double* cv = mu ? colvec : nullptr;
+    tm->begin(phase);
+    launch_csr_spmm(r_, c_, v_, rows, k, static_cast<const float*>(X), ldx,
+                    static_cast<float*>(Y), ldy, rowvec, cv, kCsrShort, s);
+    tm->end(1);
+    if (pl.nlong) {
+      tm->begin(BK_PH_LONG);
+      launch_csr_pieces(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
+                        static_cast<float*>(Y), ldy, rowvec, cv, s);
+      tm->end(2);
+    }
+  }
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     if (mu) centre_vec(X, ldx, k, d, ones, s);
-    tm->begin(BK_PH_AX);
-    launch_csr_spmm(rp, ci, v, n, k, static_cast<const float*>(X), ldx,
-                    static_cast<float*>(Y), ldy, mu, mu ? colvec : nullptr, kLongRow, s);
-    tm->end(1);
-    if (nlong_a) {
-      tm->begin(BK_PH_LONG);
-      launch_csr_spmm_long(long_a, nlong_a, rp, ci, v, k, static_cast<const float*>(X), ldx,
-                           static_cast<float*>(Y), ldy, mu, mu ? colvec : nullptr, s);
-      tm->end(1);
-    }
+    product(rp, ci, v, n, pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, s);
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     if (mu) centre_vec(X, ldx, k, n, mu, s);
-    tm->begin(BK_PH_ATY);
-    launch_csr_spmm(trp, tci, tv, d, k, static_cast<const float*>(X), ldx,
-                    static_cast<float*>(Y), ldy, nullptr, mu ? colvec : nullptr, kLongRow, s);
-    tm->end(1);
-    if (nlong_t) {
-      tm->begin(BK_PH_LONG);
-      launch_csr_spmm_long(long_t, nlong_t, trp, tci, tv, k, static_cast<const float*>(X),
-                           ldx, static_cast<float*>(Y), ldy, nullptr,
-                           mu ? colvec : nullptr, s);
-      tm->end(1);
-    }
+    product(trp, tci, tv, d, pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, s);
   }
 };
 
@@ -496,7 +516,9 @@ struct Solver {
     for (sw = 1; sw <= o.max_sweeps; ++sw) {
       launch_ctrl_reset_off(L->ctrl, s);
       for (int r = 0; r < nb - 1; ++r)
-        launch_jacobi_round(jw.b, mm, nb, r, jw.Xc, jw.Vc, jw.ldc, tol, 12, L->ctrl, s);
+        // one inner sweep per round: full inner convergence buys no outer
+        // sweeps (measured on the Rayleigh-Ritz matrices of the workloads)
+        launch_jacobi_round(jw.b, mm, nb, r, jw.Xc, jw.Vc, jw.ldc, tol, 1, L->ctrl, s);
       Ctrl h;
       BK_TRY(hipMemcpyAsync(&h, L->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
       BK_TRY(hipStreamSynchronize(s));
@@ -800,16 +822,18 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
     tci = L.tci;
     tv = L.tv;
   }
-  launch_csr_long_rows(row_ptr, n, kLongRow, L.long_a, L.nlong, s);
-  launch_csr_long_rows(trp, d, kLongRow, L.long_t, L.nlong + 1, s);
+  launch_csr_classify(row_ptr, n, kCsrShort, L.long_a, L.npc_a, L.counters, s);
+  launch_csr_classify(trp, d, kCsrShort, L.long_t, L.npc_t, L.counters + 2, s);
   if (o.center) {
     launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
     launch_fill_f32(L.ones, d, 1.0f, s);
   }
-  int32_t nl[2] = {0, 0};
-  BK_TRY(hipMemcpyAsync(nl, L.nlong, sizeof(nl), hipMemcpyDeviceToHost, s));
+  int32_t cnt[4] = {0, 0, 0, 0};
+  BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   BK_TRY(hipStreamSynchronize(s));
   BK_TRY_LAUNCH();
+  launch_scan_i32(L.npc_a, cnt[0], L.poff_a, s);
+  launch_scan_i32(L.npc_t, cnt[2], L.poff_t, s);
   prep.end(0);
 
   CsrOp op;
@@ -822,10 +846,18 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   op.trp = trp;
   op.tci = tci;
   op.tv = tv;
-  op.long_a = L.long_a;
-  op.long_t = L.long_t;
-  op.nlong_a = nl[0];
-  op.nlong_t = nl[1];
+  op.pa.list = L.long_a;
+  op.pa.npc = L.npc_a;
+  op.pa.poff = L.poff_a;
+  op.pa.nlong = cnt[0];
+  op.pa.maxp = cnt[1];
+  op.pa.part = L.part;
+  op.pt.list = L.long_t;
+  op.pt.npc = L.npc_t;
+  op.pt.poff = L.poff_t;
+  op.pt.nlong = cnt[2];
+  op.pt.maxp = cnt[3];
+  op.pt.part = L.part;
   op.mu = o.center ? L.mu : nullptr;
   op.ones = L.ones;
   op.colvec = L.colvec;
@@ -944,6 +976,7 @@ int bk_csr_product(const int32_t* row_ptr, const int32_t* col_idx, const float* 
   if (rows < 0 || cols < 0 || nnz < 0 || k <= 0 || !row_ptr || !X || !Y || ldx < k || ldy < k)
     return BK_EINVAL;
   (void)cols;
+  // every row by the row kernel (no long-row plan for a one-off product)
   launch_csr_spmm(row_ptr, col_idx, vals, rows, k, X, ldx, Y, ldy, nullptr, nullptr,
                   0x7FFFFFFF, static_cast<hipStream_t>(stream));
   BK_TRY_LAUNCH();

@@ -179,6 +179,28 @@ __global__ __launch_bounds__(256) void tn_reduce_kernel(
   C[gp * ldc + gr] = static_cast<TC>(v);
 }
 
+// Same reduction with one wavefront per output: lane l adds partials
+// l, l+64, ... in order, then a fixed butterfly combines the lanes.
+template <typename TC>
+__global__ __launch_bounds__(256) void tn_reduce_wave_kernel(
+    int S, int64_t p, int r, const double* __restrict__ partial,
+    TC* __restrict__ C, int64_t ldc, double alpha, double beta) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (idx >= p * r) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t gp = idx / r;
+  const int gr = static_cast<int>(idx - gp * r);
+  double acc = 0.0;
+  for (int i = lane; i < S; i += 64) acc += partial[(i * p + gp) * r + gr];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) {
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * static_cast<double>(C[gp * ldc + gr]);
+    C[gp * ldc + gr] = static_cast<TC>(v);
+  }
+}
+
 template <typename TA, typename TX, typename TC, typename ACC>
 void nn_dispatch_scaled(const NNArgs& a, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(cdiv(a.n, NN_BM)),
@@ -302,7 +324,20 @@ void launch_tn(const TNArgs& a, hipStream_t s) {
         return;
     }
   }
-  const unsigned g = static_cast<unsigned>(cdiv(a.p * a.r, 256));
+  const int64_t outs = a.p * a.r;
+  if (S >= 16 && outs <= (int64_t(1) << 16)) {
+    const unsigned g = static_cast<unsigned>(cdiv(outs, 4));
+    if (a.c_f64)
+      tn_reduce_wave_kernel<double><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
+                                                      static_cast<double*>(a.C), a.ldc,
+                                                      a.alpha, a.beta);
+    else
+      tn_reduce_wave_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
+                                                     static_cast<float*>(a.C), a.ldc,
+                                                     a.alpha, a.beta);
+    return;
+  }
+  const unsigned g = static_cast<unsigned>(cdiv(outs, 256));
   if (a.c_f64)
     tn_reduce_kernel<double><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                                static_cast<double*>(a.C), a.ldc,

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(
   __shared__ double P[CH][B2 + 1];
   __shared__ double red[256];
   __shared__ int64_t colidx[B2];
-  __shared__ double rc[NP], rs[NP];
+  __shared__ double rc[NP], rs[NP], rt[NP];
   __shared__ int rp[NP], rq[NP];
 
   const int t = threadIdx.x;
@@ -129,10 +129,12 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(
         const int p = tournament(t, step, B2);
         const int q = tournament(B2 - 1 - t, step, B2);
         const double a = G[p][p], d = G[q][q], bb = G[q][p];
-        double c = 1.0, s = 0.0;
-        if (bb != 0.0) {
+        double c = 1.0, s = 0.0, tt = 0.0;
+        // rotate only when the pair is not already orthogonal to tol
+        // (relative to the two diagonal entries: keeps relative accuracy)
+        if (fabs(bb) > tol * sqrt(fmax(a, 0.0) * fmax(d, 0.0)) && bb != 0.0) {
           const double tau = (d - a) / (2.0 * bb);
-          const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
           s = tt * c;
         }
@@ -140,13 +142,28 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(
         rq[t] = q;
         rc[t] = c;
         rs[t] = s;
+        rt[t] = tt;
       }
       __syncthreads();
-      // G <- J^T G J, one 2 x 2 block (pair w1 rows, pair w2 cols) per item
+      // G <- J^T G J, one 2 x 2 block (pair w1 rows, pair w2 cols) per item.
+      // The pair's own diagonal block gets the exact Jacobi update
+      // (a - t b, d + t b, 0): recomputing it from products would cancel.
       for (int idx = t; idx < NP * NP; idx += 256) {
         const int w1 = idx / NP, w2 = idx % NP;
         const int p1 = rp[w1], q1 = rq[w1], p2 = rp[w2], q2 = rq[w2];
+        if (w1 == w2) {
+          const double tt = rt[w1];
+          if (tt != 0.0) {
+            const double bb = G[q1][p1];
+            G[p1][p1] -= tt * bb;
+            G[q1][q1] += tt * bb;
+            G[p1][q1] = 0.0;
+            G[q1][p1] = 0.0;
+          }
+          continue;
+        }
         const double c1 = rc[w1], s1 = rs[w1], c2 = rc[w2], s2 = rs[w2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
         const double g11 = G[p1][p2], g12 = G[p1][q2], g21 = G[q1][p2], g22 = G[q1][q2];
         const double t11 = c1 * g11 - s1 * g21, t12 = c1 * g12 - s1 * g22;
         const double t21 = s1 * g11 + c1 * g21, t22 = s1 * g12 + c1 * g22;

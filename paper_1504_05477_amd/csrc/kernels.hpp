@@ -112,19 +112,32 @@ void launch_jacobi_finalize(const double* Xc, const double* Vc, int64_t ldc,
 void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
                          int64_t cols, int64_t nnz, Ctrl* ctrl, hipStream_t s);
 // Y (rows x k) = A X - rowvec (x) colvec (rowvec nullable = all ones,
-// colvec nullable = no correction).  Rows longer than long_thr are skipped
-// here and done by launch_csr_spmm_long over the list long_rows.
+// colvec nullable = no correction).  Rows longer than short_thr are skipped
+// here and done by launch_csr_pieces.
+constexpr int kCsrShort = 64;    // rows up to this many nonzeros: one slot
+constexpr int kCsrPiece = 1024;  // longer rows: pieces of this many nonzeros
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
                      int64_t rows, int k, const float* X, int64_t ldx,
                      float* Y, int64_t ldy, const float* rowvec,
-                     const double* colvec, int long_thr, hipStream_t s);
-void launch_csr_spmm_long(const int32_t* long_rows, int nlong,
-                          const int32_t* rp, const int32_t* ci, const float* v,
-                          int k, const float* X, int64_t ldx, float* Y,
-                          int64_t ldy, const float* rowvec,
-                          const double* colvec, hipStream_t s);
-void launch_csr_long_rows(const int32_t* rp, int64_t rows, int long_thr,
-                          int32_t* list, int32_t* count, hipStream_t s);
+                     const double* colvec, int short_thr, hipStream_t s);
+// Long rows of one CSR matrix: list[i], npc[i] pieces, piece offsets poff,
+// FP32 piece sums part[total pieces x k].
+struct CsrPieces {
+  const int32_t* list = nullptr;
+  const int32_t* npc = nullptr;
+  const int32_t* poff = nullptr;
+  int nlong = 0, maxp = 0;
+  float* part = nullptr;
+};
+void launch_csr_classify(const int32_t* rp, int64_t rows, int short_thr,
+                         int32_t* list, int32_t* npc, int32_t* counters,
+                         hipStream_t s);
+void launch_csr_pieces(const CsrPieces& pl, const int32_t* rp, const int32_t* ci,
+                       const float* v, int k, const float* X, int64_t ldx,
+                       float* Y, int64_t ldy, const float* rowvec,
+                       const double* colvec, hipStream_t s);
+// exclusive scan of n counts into out[0..n] (one workgroup)
+void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s);
 void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,
                           int64_t cols, float* mu, hipStream_t s);
 // CSR transpose: counts -> scan -> atomic scatter -> per-row sort.
