@@ -4,11 +4,11 @@ torch binding.  Build the library with ``python -m paper_1504_05477_amd.build``.
 """
 from ._lib import (BKError, RankDeficient, EXPORTS, LIB_PATH, load,
                    status_string)
-from .api import (SVDResult, csr_product, csr_transpose, dense_product,
+from .api import (BKSVD, SVDResult, csr_product, svd_dense_backward, csr_transpose, dense_product,
                   eigh_psd, gaussian, philox, quantize, svd_csr, svd_dense)
 
 __all__ = [
     "BKError", "RankDeficient", "EXPORTS", "LIB_PATH", "load", "status_string",
-    "SVDResult", "csr_product", "csr_transpose", "dense_product", "eigh_psd",
+    "BKSVD", "SVDResult", "svd_dense_backward", "csr_product", "csr_transpose", "dense_product", "eigh_psd",
     "gaussian", "philox", "quantize", "svd_csr", "svd_dense",
 ]

@@ -107,6 +107,60 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
     return SVDResult(Z, sig, info.as_dict(), ws if save_for_backward else None)
 
 
+def svd_dense_backward(A: torch.Tensor, k: int, q: int, fwd: SVDResult, Z_bar=None,
+                       sigma_bar=None, stream=None) -> torch.Tensor:
+    """Gradient of a loss L(Z, sigma) with respect to A (FP32 / FP64 plain
+    paths), for a forward run with ``save_for_backward=True``.  The loss must
+    be unchanged by rotations inside span(Z) (e.g. sum of the Ritz values,
+    ||Z Z^T A||_F^2 through Z)."""
+    lib = L.load()
+    if fwd.workspace is None:
+        raise ValueError("the forward must be run with save_for_backward=True")
+    code = _dtype_code(A)
+    if code not in (L.F64, L.F32):
+        raise ValueError("the adjoint covers the FP32 and FP64 paths")
+    n, d = A.shape
+    zdt = torch.float64 if code == L.F64 else torch.float32
+    if Z_bar is not None:
+        Z_bar = Z_bar.to(zdt).contiguous()
+        _need_cuda(Z_bar)
+    if sigma_bar is not None:
+        sigma_bar = sigma_bar.to(torch.float64).contiguous()
+        _need_cuda(sigma_bar)
+    A_bar = torch.empty(n, d, dtype=A.dtype, device=A.device)
+    nbytes = lib.bk_svd_dense_backward_workspace(n, d, k, q, code)
+    ws = _ws(nbytes, A.device)
+    st = lib.bk_svd_dense_backward(_ptr(A), A.stride(0), code, n, d, k, q, _ptr(fwd.Z), k,
+                                   _ptr(fwd.sigma), _ptr(Z_bar), _ptr(sigma_bar), _ptr(A_bar),
+                                   A_bar.stride(0), _ptr(fwd.workspace),
+                                   fwd.workspace.numel(), _ptr(ws), nbytes, _stream(stream))
+    L.check(st, "bk_svd_dense_backward")
+    return A_bar
+
+
+class BKSVD(torch.autograd.Function):
+    """(Z, sigma) = BKSVD.apply(A, k, q, seed): differentiable Block Krylov
+    Iteration on a dense FP32 / FP64 A.  The backward is the library's adjoint
+    (Krylov blocks recomputed from the saved orthonormal blocks); it is exact
+    for losses invariant under rotations inside span(Z)."""
+
+    @staticmethod
+    def forward(ctx, A, k: int, q: int, seed: int = 0):
+        A = A.contiguous()
+        res = svd_dense(A, k, q, seed, save_for_backward=True)
+        ctx.save_for_backward(A)
+        ctx.fwd = res
+        ctx.kq = (k, q)
+        return res.Z, res.sigma
+
+    @staticmethod
+    def backward(ctx, Z_bar, sigma_bar):
+        (A,) = ctx.saved_tensors
+        k, q = ctx.kq
+        A_bar = svd_dense_backward(A, k, q, ctx.fwd, Z_bar, sigma_bar)
+        return A_bar, None, None, None
+
+
 def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 0, *,
             transpose=None, center=False, pi=None, timing=False, max_sweeps=0,
             jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, stream=None) -> SVDResult:

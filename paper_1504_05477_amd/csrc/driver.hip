@@ -131,7 +131,6 @@ struct Layout {
   double* Uk = nullptr;
   double* sign = nullptr;
   double* Rsave = nullptr;  // (q+1) x k x k, R_i of B_i = Q_i R_i (saved)
-  double* Csave = nullptr;  // (q+1) x m x k, total projection coefficients
   double* ritz_dev = nullptr;
   // refinement
   float* Wk = nullptr;
@@ -179,10 +178,7 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.Uk = ar.take<double>(static_cast<size_t>(m * k));
   L.sign = ar.take<double>(static_cast<size_t>(k));
   L.ritz_dev = ar.take<double>(static_cast<size_t>(k));
-  if (o.save) {
-    L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
-    L.Csave = ar.take<double>(static_cast<size_t>(q + 1) * m * k);
-  }
+  if (o.save) L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
   if (o.refine) {
     L.Wk = ar.take<float>(static_cast<size_t>(d * k));
     L.Gk = ar.take<double>(kk);
@@ -491,16 +487,11 @@ struct Solver {
     tm->begin(BK_PH_PROJ);
     gram(L->Bs, k, k, L->Bs, k, k, n, L->Gpre);
     const int64_t p = static_cast<int64_t>(i) * k;
-    double* Cs = o.save ? L->Csave + static_cast<size_t>(i) * m * k : nullptr;
     for (int pass = 0; pass < 2; ++pass) {
       gram(L->Q, m, p, L->Bs, k, k, n, L->C);
       apply(L->Q, m, n, p, L->C, k, k, L->Bs, k, -1.0, 1.0);
-      if (Cs) {
-        if (pass == 0) launch_copy2d(L->C, true, k, Cs, true, k, p, k, s);
-        else launch_axpy_f64(L->C, Cs, p * k, s);
-      }
     }
-    tm->end(7 + (o.save ? 2 : 0));
+    tm->end(7);
   }
 
   // Eigen-solve of the FP64 symmetric PSD `Mat` (mm x mm): top `kk`
@@ -589,7 +580,6 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   else
     launch_gaussian(seed, d, k, k, f64, L.Pi, s);
   tm.end(1);
-  if (o.save) launch_fill_f64(L.Csave, (q + 1) * m * k, 0.0, s);
 
   // Step 2-3: Krylov blocks, orthonormalized as they are formed.
   op.ax(L.Pi, k, k, L.Bs, k, s);
@@ -669,6 +659,207 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     info->workspace_bytes = static_cast<int64_t>(L.bytes);
   }
   return finish_status(h, S.noconv);
+}
+
+// ------------------------------------------------------------- adjoint --
+// Reverse mode of the forward above for the plain FP32 / FP64 paths, for a
+// loss L(Z, sigma) unchanged by rotations inside span(Z).  With the thin-QR
+// adjoint (Q_i R_i = P_i, R_i unused elsewhere):
+//   P_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T
+// the projection P_i = (I - Q_< Q_<^T) B_i:
+//   B_bar = P_bar - Q_< (Q_<^T P_bar),  Q_<bar -= P_bar C^T + B (Q_<^T P_bar)^T
+// the symmetric eigen-decomposition M = U diag(theta) U^T:
+//   M_bar = sym(U [diag(theta_bar) + F o (U^T U_bar)] U^T),
+//   F_ij = 1 / (theta_j - theta_i), zero inside the top-k block
+// and W = A^T Q, M = W^T W, B_i = A Y_i, Y_i = A^T Q_{i-1}.  B_i is recomputed
+// from the saved Y_i; A_bar is gathered as two n x d x m products.
+struct BwdLayout {
+  double* partial = nullptr;
+  void *Qbar = nullptr, *Wbar = nullptr, *Bbar = nullptr, *Bi = nullptr, *Pbar = nullptr,
+       *RtA = nullptr, *RtB = nullptr;
+  double *Ufull = nullptr, *Ubk = nullptr, *UkT = nullptr, *H = nullptr, *Gk = nullptr,
+         *T1 = nullptr, *Mbar = nullptr, *S = nullptr, *Cu = nullptr, *RinvT = nullptr,
+         *work = nullptr, *D = nullptr, *C = nullptr, *DT = nullptr, *CT = nullptr;
+  size_t bytes = 0;
+};
+
+BwdLayout make_bwd_layout(char* base, int64_t n, int64_t d, int k, int q, bool f64) {
+  Arena ar;
+  ar.base = base;
+  BwdLayout B;
+  const size_t es = f64 ? 8 : 4;
+  const int64_t m = static_cast<int64_t>(q + 1) * k;
+  int64_t need = std::max<int64_t>(tn_partial_elems(n, m, k), tn_partial_elems(m, m, k));
+  need = std::max(need, tn_partial_elems(n, k, k));
+  need = std::max(need, tn_partial_elems(n, d, k));
+  for (int i = 1; i <= q; ++i) need = std::max(need, tn_partial_elems(n, static_cast<int64_t>(i) * k, k));
+  B.partial = ar.take<double>(static_cast<size_t>(need));
+  B.Qbar = ar.take<char>(static_cast<size_t>(n * m) * es);
+  B.Wbar = ar.take<char>(static_cast<size_t>(d * m) * es);
+  B.Bbar = ar.take<char>(static_cast<size_t>(n * m) * es);
+  B.Bi = ar.take<char>(static_cast<size_t>(n * k) * es);
+  B.Pbar = ar.take<char>(static_cast<size_t>(n * k) * es);
+  B.RtA = ar.take<char>(static_cast<size_t>(m * d) * es);
+  B.RtB = ar.take<char>(static_cast<size_t>(m * d) * es);
+  const size_t mm = static_cast<size_t>(m) * m, mk = static_cast<size_t>(m) * k,
+               kk = static_cast<size_t>(k) * k;
+  B.Ufull = ar.take<double>(mm);
+  B.Mbar = ar.take<double>(mm);
+  B.Ubk = ar.take<double>(mk);
+  B.UkT = ar.take<double>(mk);
+  B.H = ar.take<double>(mk);
+  B.Gk = ar.take<double>(mk);
+  B.T1 = ar.take<double>(mk);
+  B.D = ar.take<double>(mk);
+  B.C = ar.take<double>(mk);
+  B.DT = ar.take<double>(mk);
+  B.CT = ar.take<double>(mk);
+  B.S = ar.take<double>(kk);
+  B.Cu = ar.take<double>(kk);
+  B.RinvT = ar.take<double>(kk);
+  B.work = ar.take<double>(kk);
+  B.bytes = align_up(ar.off, 256);
+  return B;
+}
+
+Options backward_fwd_options(bool f64) {
+  Options o;
+  o.save = 1;
+  o.tau = f64 ? 1e-11 : 1e-5;
+  return o;
+}
+
+int backward_dense(const DenseOp& op, int k, int q, const Layout& F, const BwdLayout& B,
+                   const void* Zbar, int64_t ldzb, const double* ritz_bar, void* Abar,
+                   int64_t ld_bar, hipStream_t s) {
+  const int64_t n = op.n, d = op.d, m = static_cast<int64_t>(q + 1) * k;
+  const bool f64 = op.f64;
+  const size_t es = f64 ? 8 : 4;
+  const int wt = f64 ? BK_F64 : BK_F32;
+  auto slab = [&](void* base, int i) {
+    return static_cast<char*>(base) + static_cast<size_t>(i) * k * es;
+  };
+  auto cslab = [&](const void* base, int i) {
+    return static_cast<const char*>(base) + static_cast<size_t>(i) * k * es;
+  };
+  // C (rows x N) = alpha A (rows x K) X (K x N) + beta C; xf64 marks X FP64
+  auto nn = [&](const void* A, int atype, int64_t lda, int64_t rows, int64_t K, const void* X,
+                bool xf64, int64_t ldx, int N, void* C, bool cf64, int64_t ldc, double alpha,
+                double beta) {
+    NNArgs a;
+    a.n = rows;
+    a.K = K;
+    a.N = N;
+    a.A = A;
+    a.lda = lda;
+    a.a_type = atype;
+    a.X = X;
+    a.ldx = ldx;
+    a.x_f64 = xf64;
+    a.C = C;
+    a.ldc = ldc;
+    a.c_f64 = cf64;
+    a.alpha = alpha;
+    a.beta = beta;
+    launch_nn(a, s);
+  };
+  // C (p x r) = alpha X^T Y + beta C, X rows x p, Y rows x r
+  auto tn = [&](const void* X, int xtype, int64_t ldx, int64_t rows, int64_t p, const void* Y,
+                bool yf64, int64_t ldy, int r, void* C, bool cf64, int64_t ldc, double beta) {
+    TNArgs a;
+    a.L = rows;
+    a.p = p;
+    a.r = r;
+    a.X = X;
+    a.ldx = ldx;
+    a.x_type = xtype;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.y_f64 = yf64;
+    a.C = C;
+    a.ldc = ldc;
+    a.c_f64 = cf64;
+    a.beta = beta;
+    a.partial = B.partial;
+    launch_tn(a, s);
+  };
+
+  Ctrl h;
+  BK_TRY(hipMemcpyAsync(&h, F.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  if (h.flags) return BK_EINVAL;  // the forward did not succeed
+  const int qe = std::min(std::max(h.q_eff, 0), q);
+
+  // Eigenvectors in the forward's order and signs; U_k^T.
+  launch_gather_vectors(F.jw.Vc, F.jw.ldc, m, F.jw.order, F.sign, k, B.Ufull, s);
+  launch_transpose(F.Uk, true, k, B.UkT, true, m, m, k, s);
+  // Z = Q U_k:  U_k_bar = Q^T Z_bar,  Q_bar = Z_bar U_k^T.
+  if (Zbar) {
+    tn(F.Q, wt, m, n, m, Zbar, f64, ldzb, k, B.Ubk, true, k, 0.0);
+    nn(Zbar, wt, ldzb, n, k, B.UkT, true, m, static_cast<int>(m), B.Qbar, f64, m, 1.0, 0.0);
+  } else {
+    launch_fill_f64(B.Ubk, m * k, 0.0, s);
+    if (f64) launch_fill_f64(static_cast<double*>(B.Qbar), n * m, 0.0, s);
+    else launch_fill_f32(static_cast<float*>(B.Qbar), n * m, 0.0f, s);
+  }
+  // M_bar = sym(U G U_k^T),  G = diag(theta_bar) + F o (U^T U_k_bar).
+  tn(B.Ufull, BK_F64, m, m, m, B.Ubk, true, k, k, B.H, true, k, 0.0);
+  launch_eig_adjoint(m, k, F.jw.theta, B.H, F.ritz_dev, ritz_bar, B.Gk, s);
+  nn(B.Ufull, BK_F64, m, m, m, B.Gk, true, k, k, B.T1, true, k, 1.0, 0.0);
+  nn(B.T1, BK_F64, k, m, k, B.UkT, true, m, static_cast<int>(m), B.Mbar, true, m, 1.0, 0.0);
+  launch_symmetrize(m, B.Mbar, s);
+  // W_bar = 2 W M_bar  (W = [Y_1 .. Y_{q+1}]).
+  nn(F.W, wt, m, d, m, B.Mbar, true, m, static_cast<int>(m), B.Wbar, f64, m, 2.0, 0.0);
+  // B_bar slots: i - 1 for block i >= 1, q for block 0; unused ones stay 0.
+  if (f64) launch_fill_f64(static_cast<double*>(B.Bbar), n * m, 0.0, s);
+  else launch_fill_f32(static_cast<float*>(B.Bbar), n * m, 0.0f, s);
+  // Y_{qe+1} = A^T Q_qe feeds only W:  Q_qe_bar += A W_bar_qe.
+  nn(op.A, op.a_type, op.lda, n, d, cslab(B.Wbar, qe), f64, m, k, slab(B.Qbar, qe), f64, m,
+     1.0, 1.0);
+  BK_TRY_LAUNCH();
+
+  for (int i = qe; i >= 0; --i) {
+    void* Qbi = slab(B.Qbar, i);
+    const void* Qi = cslab(F.Q, i);
+    // thin-QR adjoint: P_bar = (Q_bar + Q copyltu(-Q_bar^T Q)) R^-T
+    tn(Qbi, wt, m, n, k, Qi, f64, m, k, B.S, true, k, 0.0);
+    launch_copyltu_neg(k, B.S, B.Cu, s);
+    nn(Qi, wt, m, n, k, B.Cu, true, k, k, Qbi, f64, m, 1.0, 1.0);
+    launch_trinv_t(k, F.Rsave + static_cast<size_t>(i) * k * k, B.work, B.RinvT, s);
+    nn(Qbi, wt, m, n, k, B.RinvT, true, k, k, B.Pbar, f64, k, 1.0, 0.0);
+    if (i == 0) {  // B_0 = A Pi: A_bar += P_bar Pi^T
+      launch_copy2d(B.Pbar, f64, k, slab(B.Bbar, q), f64, m, n, k, s);
+      break;
+    }
+    // recompute B_i = A Y_i from the saved Y_i
+    nn(op.A, op.a_type, op.lda, n, d, cslab(F.W, i - 1), f64, m, k, B.Bi, f64, k, 1.0, 0.0);
+    const int64_t p = static_cast<int64_t>(i) * k;
+    // projection adjoint, C = Q_<^T B_i and D = Q_<^T P_bar
+    tn(F.Q, wt, m, n, p, B.Bi, f64, k, k, B.C, true, k, 0.0);
+    tn(F.Q, wt, m, n, p, B.Pbar, f64, k, k, B.D, true, k, 0.0);
+    launch_transpose(B.C, true, k, B.CT, true, p, p, k, s);
+    launch_transpose(B.D, true, k, B.DT, true, p, p, k, s);
+    nn(B.Pbar, wt, k, n, k, B.CT, true, p, static_cast<int>(p), B.Qbar, f64, m, -1.0, 1.0);
+    nn(B.Bi, wt, k, n, k, B.DT, true, p, static_cast<int>(p), B.Qbar, f64, m, -1.0, 1.0);
+    nn(F.Q, wt, m, n, p, B.D, true, k, k, B.Pbar, f64, k, -1.0, 1.0);  // -> B_bar_i
+    launch_copy2d(B.Pbar, f64, k, slab(B.Bbar, i - 1), f64, m, n, k, s);
+    // B_i = A Y_i:   Y_bar_i = W_bar_{i-1} + A^T B_bar_i
+    tn(op.A, op.a_type, op.lda, n, d, B.Pbar, f64, k, k, slab(B.Wbar, i - 1), f64, m, 1.0);
+    // Y_i = A^T Q_{i-1}:   Q_bar_{i-1} += A Y_bar_i
+    nn(op.A, op.a_type, op.lda, n, d, cslab(B.Wbar, i - 1), f64, m, k, slab(B.Qbar, i - 1), f64,
+       m, 1.0, 1.0);
+    BK_TRY_LAUNCH();
+  }
+  // A_bar = Q [Y_bar_1 .. Y_bar_{q+1}]^T + [B_bar_1 .. B_bar_q, B_bar_0] [Y_1 .. Y_q, Pi]^T
+  launch_transpose(B.Wbar, f64, m, B.RtA, f64, d, d, m, s);
+  if (q > 0) launch_transpose(F.W, f64, m, B.RtB, f64, d, d, static_cast<int64_t>(q) * k, s);
+  launch_transpose(F.Pi, f64, k, static_cast<char*>(B.RtB) + static_cast<size_t>(q) * k * d * es,
+                   f64, d, d, k, s);
+  nn(F.Q, wt, m, n, m, B.RtA, f64, d, static_cast<int>(d), Abar, f64, ld_bar, 1.0, 0.0);
+  nn(B.Bbar, wt, m, n, m, B.RtB, f64, d, static_cast<int>(d), Abar, f64, ld_bar, 1.0, 1.0);
+  BK_TRY_LAUNCH();
+  BK_TRY(hipStreamSynchronize(s));
+  return BK_OK;
 }
 
 bool valid_kq(int64_t n, int64_t d, int32_t k, int32_t q) {
@@ -873,12 +1064,8 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
 
 size_t bk_svd_dense_backward_workspace(int64_t n, int64_t d, int32_t k, int32_t q,
                                        int32_t a_type) {
-  (void)n;
-  (void)d;
-  (void)k;
-  (void)q;
-  (void)a_type;
-  return 0;
+  if (!valid_kq(n, d, k, q) || (a_type != BK_F64 && a_type != BK_F32)) return 0;
+  return make_bwd_layout(nullptr, n, d, k, q, a_type == BK_F64).bytes;
 }
 
 int bk_svd_dense_backward(const void* A, int64_t lda, int32_t a_type, int64_t n, int64_t d,
@@ -886,10 +1073,36 @@ int bk_svd_dense_backward(const void* A, int64_t lda, int32_t a_type, int64_t n,
                           const void* Z_bar, const double* ritz_bar, void* A_bar,
                           int64_t ld_bar, const void* fwd_workspace, size_t fwd_bytes,
                           void* workspace, size_t workspace_bytes, void* stream) {
-  (void)A; (void)lda; (void)a_type; (void)n; (void)d; (void)k; (void)q; (void)Z; (void)ldz;
-  (void)ritz; (void)Z_bar; (void)ritz_bar; (void)A_bar; (void)ld_bar; (void)fwd_workspace;
-  (void)fwd_bytes; (void)workspace; (void)workspace_bytes; (void)stream;
-  return BK_EINVAL;
+  (void)Z;
+  (void)ritz;
+  if (!valid_kq(n, d, k, q) || (a_type != BK_F64 && a_type != BK_F32) || !A || !A_bar ||
+      !fwd_workspace || lda < d || ld_bar < d || (Z_bar && ldz < k))
+    return BK_EINVAL;
+  const bool f64 = a_type == BK_F64;
+  const Options fo = backward_fwd_options(f64);
+  const Layout F = make_layout(static_cast<char*>(const_cast<void*>(fwd_workspace)), n, d, 0, k,
+                               q, f64, fo, false, false);
+  if (fwd_bytes < F.bytes) return BK_EINVAL;  // not a save_for_backward workspace
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t need = make_bwd_layout(nullptr, n, d, k, q, f64).bytes;
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  const BwdLayout B = make_bwd_layout(base, n, d, k, q, f64);
+  DenseOp op;
+  op.n = n;
+  op.d = d;
+  op.f64 = f64;
+  op.A = A;
+  op.lda = lda;
+  op.a_type = a_type;
+  return backward_dense(op, k, q, F, B, Z_bar, ldz, ritz_bar, A_bar, ld_bar, s);
 }
 
 int bk_gaussian(uint64_t seed, int64_t rows, int64_t cols, int64_t ld, int32_t dtype, void* out,

@@ -84,6 +84,26 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode,
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,
                        hipStream_t s);
 
+// Helpers of the adjoint.
+// dst (cols x rows) = src (rows x cols)^T, FP64/FP32 either side.
+void launch_transpose(const void* src, bool src_f64, int64_t lds, void* dst,
+                      bool dst_f64, int64_t ldd, int64_t rows, int64_t cols,
+                      hipStream_t s);
+// out = copyltu(-S) (symmetric, lower triangle of -S mirrored), k x k.
+void launch_copyltu_neg(int k, const double* S, double* out, hipStream_t s);
+// G (m x k) of the eigen-decomposition adjoint (see small.hip).
+void launch_eig_adjoint(int64_t m, int k, const double* theta, const double* H,
+                        const double* ritz, const double* ritz_bar, double* G,
+                        hipStream_t s);
+void launch_symmetrize(int64_t m, double* M, hipStream_t s);
+// out = (R^-1)^T of an upper-triangular k x k R; work: k x k scratch.
+void launch_trinv_t(int k, const double* R, double* work, double* out, hipStream_t s);
+// U (m x m) = eigenvector columns in descending order (order[]), first k
+// columns multiplied by sign[].
+void launch_gather_vectors(const double* Vc, int64_t ldc, int64_t m,
+                           const int32_t* order, const double* sign, int k,
+                           double* U, hipStream_t s);
+
 // Column signs of Z (n x k): sign[c] = +1 / -1 so that the largest-|.|
 // entry of column c (lowest row on ties) becomes positive; then Z and the
 // m x k matrix U (nullable) are multiplied column-wise by sign.

@@ -211,6 +211,103 @@ __global__ __launch_bounds__(256) void trmm_upper_kernel(int k, const double* A,
   }
 }
 
+// dst (cols x rows, ldd) = src (rows x cols, lds)^T through a 32 x 33 tile.
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void transpose_kernel(const TS* __restrict__ src, int64_t lds,
+                                                        TD* __restrict__ dst, int64_t ldd,
+                                                        int64_t rows, int64_t cols) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 32, c0 = static_cast<int64_t>(blockIdx.x) * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t r = r0 + i, c = c0 + tx;
+    tile[i][tx] = (r < rows && c < cols) ? static_cast<double>(src[r * lds + c]) : 0.0;
+  }
+  __syncthreads();
+  for (int i = ty; i < 32; i += 8) {
+    const int64_t c = c0 + i, r = r0 + tx;
+    if (c < cols && r < rows) dst[c * ldd + r] = static_cast<TD>(tile[tx][i]);
+  }
+}
+
+// out = copyltu(-S): the symmetric matrix whose lower triangle is -S's.
+__global__ __launch_bounds__(256) void copyltu_neg_kernel(int k, const double* S, double* out) {
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    const int i = idx / k, j = idx % k;
+    out[idx] = (i >= j) ? -S[i * k + j] : -S[j * k + i];
+  }
+}
+
+// Eigen adjoint core: G (m x k) with G[j][j] = theta_bar_j and, for i >= k,
+// G[i][j] = H[i][j] / (theta_j - theta_i); entries with i, j < k stay zero
+// (they cancel for losses invariant under rotations inside span Z).
+__global__ __launch_bounds__(256) void eig_adjoint_kernel(int64_t m, int k, const double* theta,
+                                                          const double* H, const double* ritz,
+                                                          const double* ritz_bar, double* G) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= m * k) return;
+  const int64_t i = idx / k;
+  const int j = static_cast<int>(idx - i * k);
+  double v = 0.0;
+  if (i == j) {
+    const double sb = ritz_bar ? ritz_bar[j] : 0.0;
+    v = ritz[j] > 0.0 ? sb / (2.0 * ritz[j]) : 0.0;  // d sigma / d theta
+  } else if (i >= k) {
+    const double gap = theta[j] - theta[i];
+    if (fabs(gap) > 1e-14 * fabs(theta[0])) v = H[idx] / gap;
+  }
+  G[idx] = v;
+}
+
+__global__ __launch_bounds__(256) void symmetrize_kernel(int64_t m, double* M) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t i = idx / m, j = idx - i * m;
+  if (j <= i) return;
+  const double v = 0.5 * (M[i * m + j] + M[j * m + i]);
+  M[i * m + j] = v;
+  M[j * m + i] = v;
+}
+
+// out = (R^-1)^T for an upper-triangular k x k R (one workgroup).
+__global__ __launch_bounds__(256) void trinv_t_kernel(int k, const double* R, double* Ri,
+                                                      double* out) {
+  for (int i = threadIdx.x; i < k * k; i += 256) Ri[i] = 0.0;
+  __syncthreads();
+  for (int i = k - 1; i >= 0; --i) {
+    const double rii = R[i * k + i];
+    for (int j = i + threadIdx.x; j < k; j += 256) {
+      if (j == i) {
+        Ri[i * k + i] = rii != 0.0 ? 1.0 / rii : 0.0;
+      } else {
+        double s = 0.0;
+        for (int l = i + 1; l <= j; ++l) s += R[i * k + l] * Ri[l * k + j];
+        Ri[i * k + j] = rii != 0.0 ? -s / rii : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < k * k; idx += 256) {
+    const int i = idx / k, j = idx % k;
+    out[idx] = Ri[j * k + i];
+  }
+}
+
+// U (m x m, ld m) = eigenvectors in descending order: column c is column
+// order[c] of V, times sign[c] for c < k (the signs applied to Z).
+__global__ __launch_bounds__(256) void gather_vectors_kernel(const double* Vc, int64_t ldc,
+                                                             int64_t m, const int32_t* order,
+                                                             const double* sign, int k,
+                                                             double* U) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= m * m) return;
+  const int64_t r = idx / m, c = idx - r * m;
+  int64_t j = order[c];
+  j = j < 0 ? 0 : (j >= m ? m - 1 : j);
+  const double sg = (c < k && sign) ? sign[c] : 1.0;
+  U[idx] = sg * Vc[j * ldc + r];
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void col_sign_kernel(const T* Z, int64_t n,
                                                        int64_t ldz,
@@ -330,6 +427,48 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,
                        hipStream_t s) {
   trmm_upper_kernel<<<1, 256, 0, s>>>(k, A, B, T);
+}
+
+void launch_transpose(const void* src, bool src_f64, int64_t lds, void* dst, bool dst_f64,
+                      int64_t ldd, int64_t rows, int64_t cols, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  const dim3 grid(static_cast<unsigned>(cdiv(cols, 32)), static_cast<unsigned>(cdiv(rows, 32)));
+  if (src_f64 && dst_f64)
+    transpose_kernel<double, double><<<grid, 256, 0, s>>>(static_cast<const double*>(src), lds,
+                                                          static_cast<double*>(dst), ldd, rows, cols);
+  else if (src_f64)
+    transpose_kernel<double, float><<<grid, 256, 0, s>>>(static_cast<const double*>(src), lds,
+                                                         static_cast<float*>(dst), ldd, rows, cols);
+  else if (dst_f64)
+    transpose_kernel<float, double><<<grid, 256, 0, s>>>(static_cast<const float*>(src), lds,
+                                                         static_cast<double*>(dst), ldd, rows, cols);
+  else
+    transpose_kernel<float, float><<<grid, 256, 0, s>>>(static_cast<const float*>(src), lds,
+                                                        static_cast<float*>(dst), ldd, rows, cols);
+}
+
+void launch_copyltu_neg(int k, const double* S, double* out, hipStream_t s) {
+  copyltu_neg_kernel<<<1, 256, 0, s>>>(k, S, out);
+}
+
+void launch_eig_adjoint(int64_t m, int k, const double* theta, const double* H,
+                        const double* ritz, const double* ritz_bar, double* G, hipStream_t s) {
+  eig_adjoint_kernel<<<static_cast<unsigned>(cdiv(m * k, 256)), 256, 0, s>>>(m, k, theta, H, ritz,
+                                                                           ritz_bar, G);
+}
+
+void launch_symmetrize(int64_t m, double* M, hipStream_t s) {
+  symmetrize_kernel<<<static_cast<unsigned>(cdiv(m * m, 256)), 256, 0, s>>>(m, M);
+}
+
+void launch_trinv_t(int k, const double* R, double* work, double* out, hipStream_t s) {
+  trinv_t_kernel<<<1, 256, 0, s>>>(k, R, work, out);
+}
+
+void launch_gather_vectors(const double* Vc, int64_t ldc, int64_t m, const int32_t* order,
+                           const double* sign, int k, double* U, hipStream_t s) {
+  gather_vectors_kernel<<<static_cast<unsigned>(cdiv(m * m, 256)), 256, 0, s>>>(Vc, ldc, m, order,
+                                                                              sign, k, U);
 }
 
 void launch_sign_normalize(void* Z, bool f64, int64_t n, int k, int64_t ldz,
