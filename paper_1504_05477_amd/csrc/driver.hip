@@ -115,6 +115,13 @@ JacobiWs take_jacobi(Arena& ar, int64_t m, int jblock, bool withv) {
   return j;
 }
 
+// The Rayleigh-Ritz eigen-solve goes through the tridiagonal reduction for
+// moderate m unless every eigenvector is kept (adjoint) or Jacobi is asked
+// for explicitly (jacobi_block).
+bool use_tridiag(int64_t m, const Options& o) {
+  return !o.save && o.jblock == 0 && m <= kTridiagMax;
+}
+
 struct Layout {
   Ctrl* ctrl = nullptr;
   void* Pi = nullptr;
@@ -129,6 +136,7 @@ struct Layout {
   double* M = nullptr;
   JacobiWs jw;
   double* Uk = nullptr;
+  double* tri = nullptr;  // tridiagonal eigen-solve scratch (when used)
   double* sign = nullptr;
   double* Rsave = nullptr;  // (q+1) x k x k, R_i of B_i = Q_i R_i (saved)
   double* ritz_dev = nullptr;
@@ -176,6 +184,7 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.M = ar.take<double>(static_cast<size_t>(m * m));
   L.jw = take_jacobi(ar, m, o.jblock, o.save != 0);
   L.Uk = ar.take<double>(static_cast<size_t>(m * k));
+  if (use_tridiag(m, o)) L.tri = ar.take<double>(static_cast<size_t>(tridiag_scratch_doubles(m, k)));
   L.sign = ar.take<double>(static_cast<size_t>(k));
   L.ritz_dev = ar.take<double>(static_cast<size_t>(k));
   if (o.save) L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
@@ -497,7 +506,12 @@ struct Solver {
   // Eigen-solve of the FP64 symmetric PSD `Mat` (mm x mm): top `kk`
   // eigenvectors into Uk (ld ldu) and sqrt(theta) into ritz.
   int eig(const double* Mat, int64_t mm, JacobiWs& jw, int kk, double* Uk, int64_t ldu,
-          double* ritz) {
+          double* ritz, double* tri = nullptr) {
+    if (tri) {  // tridiagonal reduction path: top-k only
+      launch_tridiag_topk(Mat, mm, mm, kk, tri, jw.theta, Uk, ldu, ritz, s);
+      BK_TRY_LAUNCH();
+      return BK_OK;
+    }
     const double tol = jacobi_tol_for(mm, o.jtol);
     const int nb = static_cast<int>(jw.nbp / jw.b);
     launch_jacobi_init(Mat, mm, mm, jw.Xc, jw.Vc, jw.ldc, jw.nbp, s);
@@ -601,7 +615,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
 
   // Step 5: top-k eigenpairs of M.
   tm.begin(BK_PH_EIG);
-  int st = S.eig(L.M, m, L.jw, k, L.Uk, k, L.ritz_dev);
+  int st = S.eig(L.M, m, L.jw, k, L.Uk, k, L.ritz_dev, L.tri);
   tm.end(0);
   if (st != BK_OK) return st;
 

@@ -128,6 +128,17 @@ void launch_jacobi_finalize(const double* Xc, const double* Vc, int64_t ldc,
                             int32_t* order, double* norms, double* Uk,
                             int64_t ldu, double* ritz, hipStream_t s);
 
+// ------------------------------------------------------------ tridiagonal --
+// Top-k eigenpairs of a symmetric m x m FP64 matrix through Householder
+// tridiagonalisation, multisection + inverse iteration, back-transformation
+// (tridiag.hip).  theta: k values descending; Uk m x k (ld ldu); ritz
+// (nullable) = sqrt(max(theta, 0)).  scratch: tridiag_scratch_doubles(m, k).
+constexpr int64_t kTridiagMax = 1024;
+int64_t tridiag_scratch_doubles(int64_t m, int k);
+void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k,
+                         double* scratch, double* theta, double* Uk, int64_t ldu,
+                         double* ritz, hipStream_t s);
+
 // ------------------------------------------------------------------ csr --
 void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
                          int64_t cols, int64_t nnz, Ctrl* ctrl, hipStream_t s);

@@ -43,12 +43,12 @@ __global__ void ctrl_reset_off_kernel(Ctrl* c) {
   if (threadIdx.x == 0) c->offmax = 0ull;
 }
 
-// Fixed-order block reduction (sum) over 256 threads.
+// Fixed-order block reduction (sum) over blockDim.x (a power of two) threads.
 __device__ double block_sum(double v, double* red) {
   const int t = threadIdx.x;
   red[t] = v;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = static_cast<int>(blockDim.x) / 2; w > 0; w >>= 1) {
     if (t < w) red[t] += red[t + w];
     __syncthreads();
   }
@@ -63,10 +63,12 @@ __device__ double block_sum(double v, double* red) {
 __device__ bool chol_factor(int k, const double* G, double shift, double* S,
                             double* minpiv, int* fail) {
   const int t = threadIdx.x;
-  for (int i = t; i < k * k; i += 256) {
-    const int r = i / k, c = i - r * k;
-    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
-  }
+  const int NT = static_cast<int>(blockDim.x);
+  // 2-D thread layout: 16 columns x NT / 16 rows (no integer division in loops)
+  const int tx = t & 15, ty = t >> 4, NY = NT >> 4;
+  for (int r = ty; r < k; r += NY)
+    for (int c = tx; c < k; c += 16)
+      S[r * k + c] = (c >= r) ? G[r * k + c] + (r == c ? shift : 0.0) : 0.0;
   if (t == 0) {
     *fail = 0;
     *minpiv = INFINITY;
@@ -86,12 +88,11 @@ __device__ bool chol_factor(int k, const double* G, double shift, double* S,
     __syncthreads();
     if (*fail) return false;
     const double inv = 1.0 / S[j * k + j];
-    for (int c = j + 1 + t; c < k; c += 256) S[j * k + c] *= inv;
+    for (int c = j + 1 + t; c < k; c += NT) S[j * k + c] *= inv;
     __syncthreads();
-    const int nt = k - j - 1;
-    for (int idx = t; idx < nt * nt; idx += 256) {
-      const int rr = j + 1 + idx / nt, cc = j + 1 + idx % nt;
-      if (cc >= rr) S[rr * k + cc] -= S[j * k + rr] * S[j * k + cc];
+    for (int rr = j + 1 + ty; rr < k; rr += NY) {
+      const double srj = S[j * k + rr];
+      for (int cc = rr + tx; cc < k; cc += 16) S[rr * k + cc] -= srj * S[j * k + cc];
     }
     __syncthreads();
   }
@@ -120,18 +121,17 @@ __global__ __launch_bounds__(256) void chol_kernel(int k, const double* G,
   __shared__ int fail;
   __shared__ int decision;  // 0 go on, 1 zero block
   const int t = threadIdx.x;
+  const int NT = static_cast<int>(blockDim.x);
   double* S = use_lds ? dyn : work;
   double* Ri = use_lds ? dyn + k * k : Rinv;
 
   double trp = 0.0, prp = 0.0;
   int bad = 0;
-  for (int i = t; i < k * k; i += 256) {
-    const double v = G[i];
-    if (!isfinite(v)) bad = 1;
-    if (i / k == i % k) {
-      trp += v;
-      if (mode == CHOL_FIRST) prp += Gpre[i];
-    }
+  for (int i = t; i < k * k; i += NT)
+    if (!isfinite(G[i])) bad = 1;
+  for (int i = t; i < k; i += NT) {
+    trp += G[i * k + i];
+    if (mode == CHOL_FIRST) prp += Gpre[i * k + i];
   }
   const int anybad = __syncthreads_or(bad);
   const double tr = block_sum(trp, red);
@@ -171,30 +171,25 @@ __global__ __launch_bounds__(256) void chol_kernel(int k, const double* G,
     __syncthreads();
   }
   if (decision) {
-    for (int i = t; i < k * k; i += 256) {
+    for (int i = t; i < k * k; i += NT) {
       R[i] = 0.0;
       Rinv[i] = 0.0;
     }
     return;
   }
-  // Rinv = S^-1 (upper), rows from the bottom up:
-  // Rinv[i][j] = -(sum_{l=i+1..j} S[i][l] Rinv[l][j]) / S[i][i].
-  for (int i = t; i < k * k; i += 256) Ri[i] = 0.0;
-  __syncthreads();
-  for (int i = k - 1; i >= 0; --i) {
-    const double rii = S[i * k + i];
-    for (int j = i + t; j < k; j += 256) {
-      if (j == i) {
-        Ri[i * k + i] = 1.0 / rii;
-      } else {
-        double s = 0.0;
-        for (int l = i + 1; l <= j; ++l) s += S[i * k + l] * Ri[l * k + j];
-        Ri[i * k + j] = -s / rii;
-      }
+  // Rinv = S^-1 (upper), one column per thread by back substitution
+  // (no barriers): Rinv[i][j] = -(sum_{l=i+1..j} S[i][l] Rinv[l][j]) / S[i][i].
+  for (int j = t; j < k; j += NT) {
+    for (int i = j + 1; i < k; ++i) Ri[i * k + j] = 0.0;
+    Ri[j * k + j] = 1.0 / S[j * k + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int l = i + 1; l <= j; ++l) s += S[i * k + l] * Ri[l * k + j];
+      Ri[i * k + j] = -s / S[i * k + i];
     }
-    __syncthreads();
   }
-  for (int i = t; i < k * k; i += 256) {
+  __syncthreads();
+  for (int i = t; i < k * k; i += NT) {
     R[i] = S[i];
     if (use_lds) Rinv[i] = Ri[i];
   }
@@ -419,7 +414,9 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
                         hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     attr_set = true;
   }
-  chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau,
+  // one wavefront for small blocks: its barriers cost almost nothing
+  const int threads = k <= 64 ? 64 : 256;
+  chol_kernel<<<1, threads, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau,
                                                  shift_coef, R, Rinv, work, ctrl,
                                                  use_lds);
 }

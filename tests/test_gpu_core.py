@@ -137,6 +137,23 @@ def test_eigh_psd(m):
     assert np.abs(M @ V - V * theta).max() <= 1e-12 * ref[0] * max(1, np.sqrt(m))
 
 
+@pytest.mark.parametrize("m_k", [(220, 20), (90, 10), (12, 3)])
+def test_eigen_solvers_agree(m_k):
+    """The Rayleigh-Ritz step through the tridiagonal reduction (default for
+    moderate m) and through one-sided Jacobi (jacobi_block set) agree."""
+    m, k = m_k
+    q = m // k - 1
+    n, d = 3 * m + 17, 2 * m + 5
+    A = workloads.planted_dense(n, d, workloads.spectrum("inv_sqrt", min(n, d)), 31 + m)
+    ref = bki.block_krylov(A, philox.gaussian(5, d, k), k, q)
+    Ag = _cuda(A)
+    r1 = bk.svd_dense(Ag, k, q, seed=5)
+    r2 = bk.svd_dense(Ag, k, q, seed=5, jacobi_block=16)
+    compare(r1.Z.cpu().numpy(), r1.sigma.cpu().numpy(), ref, k, 1e-10, 1e-8)
+    compare(r2.Z.cpu().numpy(), r2.sigma.cpu().numpy(), ref, k, 1e-10, 1e-8)
+    assert r2.info["jacobi_sweeps"] >= 1 and r1.info["jacobi_sweeps"] == 0
+
+
 # ------------------------------------------------------------- solve FP64 --
 def test_svd_dense_f64_config1_full_size():
     w = workloads.WORKLOADS["dense1"]
