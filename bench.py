@@ -109,7 +109,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (the reference "
+                         "kernel that scales the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,8 +159,8 @@ def main():
             return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
                               center=w.center, transpose=tr, timing=True)
         kern_src = ["csr.hip"]
-        kern_names = {"ax": "csr_spmm_kernel (A.X, CSR of A)",
-                      "aty": "csr_spmm_kernel (A^T.Y, CSR of A^T)"}
+        kern_names = {"ax": "csr_product_kernel (A.X, CSR of A)",
+                      "aty": "csr_product_kernel (A^T.Y, CSR of A^T)"}
     else:
         sv = workloads.spectrum(w.spectrum, min(w.n, w.d))
         if w.n * w.d <= 4_000_000:
@@ -257,6 +263,7 @@ def main():
                    "product_bytes_per_solve": int(bytes_per_solve)},
         "roofline": roof,
         "phases_ms_per_step": {p: round(v, 4) for p, v in ph.items()},
+        "products_all_kernels": products_all_kernels(ph, infos[-1]["q_eff"], bx, by),
         "input_prep_ms_untimed": prep_ms,
         "q_eff": infos[-1]["q_eff"],
         "jacobi_sweeps": infos[-1]["jacobi_sweeps"],
@@ -266,6 +273,33 @@ def main():
         out["cpu_baseline"], out["parity"] = cpu_baseline(args, w, host_inputs, r,
                                                           bytes_per_solve)
     print(json.dumps(out), flush=True)
+
+
+def products_all_kernels(ph, q_eff, bx, by):
+    """Rate of the block products counting every kernel they launch (CSR:
+    product, combine of rows cut into pieces, centring sums)."""
+    nprod = q_eff + 1
+    ms = ph["ax"] + ph["aty"] + ph.get("long", 0.0) + ph.get("center", 0.0)
+    per = ms / (2 * nprod)
+    return {"ms_per_product": round(per, 5),
+            "GBps": round((bx + by) / 2 / (per * 1e-3) / 1e9, 2),
+            "products_per_step": 2 * nprod}
+
+
+def copy_calibration(mib):
+    """Plain device-to-device copies of a known size: under rocprofv3 --pmc
+    the FETCH_SIZE / WRITE_SIZE they read give the factor from counter KiB
+    to bytes moved (each copy reads and writes mib MiB)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n * 4,
+                      "copy_bytes_written_per_launch": n * 4, "launches": 5}), flush=True)
 
 
 def cpu_baseline(args, w, host, res, bytes_per_solve):

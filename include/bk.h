@@ -104,9 +104,9 @@ enum {
   BK_PH_EIG = 6,     /* Jacobi eigen-solve + top-k                     */
   BK_PH_Z = 7,       /* Z = Q U_k, sign normalisation                  */
   BK_PH_REFINE = 8,  /* FP32 correction pass                           */
-  BK_PH_PREP = 9,    /* CSR validation / transpose / long-row lists    */
+  BK_PH_PREP = 9,    /* CSR validation / transpose / work plans        */
   BK_PH_CENTER = 10, /* centring vectors 1^T X and mu^T Y (CSR)        */
-  BK_PH_LONG = 11,   /* CSR rows too long for one wavefront            */
+  BK_PH_LONG = 11,   /* CSR: combine of rows cut into several pieces  */
   BK_NPHASE = 12
 };
 

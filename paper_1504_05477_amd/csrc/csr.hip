@@ -107,70 +107,291 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(
   }
 }
 
-// Long rows are cut into pieces of kPiece nonzeros; blockIdx = (long row i,
-// piece p), one wavefront.  Its slots take interleaved chunks of the piece
-// and are added in slot order; the piece sum goes to part[poff[i] + p].
-__global__ __launch_bounds__(64) void csr_pieces_kernel(
-    const int32_t* __restrict__ list, const int32_t* __restrict__ npc,
-    const int32_t* __restrict__ poff, int k, int KC, int piece,
-    const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-    const float* __restrict__ v, const float* __restrict__ X, int64_t ldx,
-    float* __restrict__ part) {
-  const int i = blockIdx.x;
-  const int p = blockIdx.y;
-  if (p >= npc[i]) return;
+// ------------------------------------------------------------ plan --
+constexpr int kPlanRows = 1024;  // rows per plan workgroup (256 threads x 4)
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Per chunk of kPlanRows rows: number of short rows, of long-row pieces and
+// of rows cut into more than one piece.
+__global__ __launch_bounds__(256) void csr_plan_count_kernel(const int32_t* __restrict__ rp,
+                                                             int64_t rows, int piece,
+                                                             int32_t* cnt_s, int32_t* cnt_p,
+                                                             int32_t* cnt_m) {
+  __shared__ int32_t red[3][4];
+  const int t = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanRows + t * 4;
+  int32_t ns = 0, np = 0, nm = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = r0 + u;
+    if (r < rows) {
+      const int32_t len = rp[r + 1] - rp[r];
+      if (len <= kCsrShort) {
+        ++ns;
+      } else {
+        np += (len + piece - 1) / piece;
+        if (len > piece) ++nm;
+      }
+    }
+  }
+  ns = wave_sum_i32(ns);
+  np = wave_sum_i32(np);
+  nm = wave_sum_i32(nm);
+  if ((t & 63) == 0) {
+    red[0][t >> 6] = ns;
+    red[1][t >> 6] = np;
+    red[2][t >> 6] = nm;
+  }
+  __syncthreads();
+  if (t == 0) {
+    cnt_s[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    cnt_p[blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    cnt_m[blockIdx.x] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+  }
+}
+
+// Writes, in row order, the short-row list, the piece table and the list
+// of rows cut into several pieces (with their first piece).
+__global__ __launch_bounds__(256) void csr_plan_write_kernel(
+    const int32_t* __restrict__ rp, int64_t rows, int piece, const int32_t* __restrict__ off_s,
+    const int32_t* __restrict__ off_p, const int32_t* __restrict__ off_m, int32_t* short_rows,
+    int32_t* piece_row, int32_t* piece_first, int32_t* multi_row, int32_t* multi_first) {
+  __shared__ int32_t ss[256], sp[256], sm[256];
+  const int t = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanRows + t * 4;
+  int32_t len[4];
+  int32_t ns = 0, np = 0, nm = 0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t r = r0 + u;
+    len[u] = (r < rows) ? rp[r + 1] - rp[r] : -1;
+    if (len[u] >= 0) {
+      if (len[u] <= kCsrShort) {
+        ++ns;
+      } else {
+        np += (len[u] + piece - 1) / piece;
+        if (len[u] > piece) ++nm;
+      }
+    }
+  }
+  ss[t] = ns;
+  sp[t] = np;
+  sm[t] = nm;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {  // inclusive scans
+    const int32_t a = t >= off ? ss[t - off] : 0;
+    const int32_t b = t >= off ? sp[t - off] : 0;
+    const int32_t c = t >= off ? sm[t - off] : 0;
+    __syncthreads();
+    ss[t] += a;
+    sp[t] += b;
+    sm[t] += c;
+    __syncthreads();
+  }
+  int32_t os = off_s[blockIdx.x] + ss[t] - ns;
+  int32_t op = off_p[blockIdx.x] + sp[t] - np;
+  int32_t om = off_m[blockIdx.x] + sm[t] - nm;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (len[u] < 0) continue;
+    const int32_t r = static_cast<int32_t>(r0 + u);
+    if (len[u] <= kCsrShort) {
+      short_rows[os++] = r;
+    } else {
+      const int32_t npc = (len[u] + piece - 1) / piece;
+      for (int32_t j = 0; j < npc; ++j) {
+        piece_row[op + j] = r;
+        piece_first[op + j] = op;
+      }
+      if (npc > 1) {
+        multi_row[om] = r;
+        multi_first[om] = op;
+        ++om;
+      }
+      op += npc;
+    }
+  }
+}
+
+__global__ void csr_plan_totals_kernel(const int32_t* off_s, const int32_t* off_p,
+                                       const int32_t* off_m, int64_t nchunk,
+                                       int32_t* totals) {
+  if (threadIdx.x == 0) {
+    totals[0] = off_s[nchunk];
+    totals[1] = off_p[nchunk];
+    totals[2] = off_m[nchunk];
+  }
+}
+
+// One product Y = A X (- rowvec c^T, c the centring vector) over a plan.
+// Wavefront w < nsw takes SLOTS short rows (one slot each); wavefront
+// nsw + p takes piece p: its slots walk interleaved chunks of the piece and
+// are added in slot order.  A single-piece row is written at once; the sums
+// of a row cut into several pieces go to part[p] and are added by
+// csr_combine_kernel.  OPERAND (0: A, 1: A^T) only names the instance, so
+// that profiles tell the two products apart.
+template <int OPERAND>
+__global__ __launch_bounds__(256) void csr_product_kernel(
+    int k, int KC, int piece, int nshort, int npieces, const int32_t* __restrict__ short_rows,
+    const int32_t* __restrict__ piece_row, const int32_t* __restrict__ piece_first,
+    float* __restrict__ part, const int32_t* __restrict__ rp,
+    const int32_t* __restrict__ ci, const float* __restrict__ v,
+    const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
+    const float* __restrict__ rowvec, const double* __restrict__ colvec) {
   const int SLOTS = 64 / KC;
-  const int lane = threadIdx.x;
+  const int nsw = (nshort + SLOTS - 1) / SLOTS;
+  const int w = static_cast<int>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   const int s = lane / KC, c = lane - s * KC;
-  const int64_t row = list[i];
-  const int32_t b = rp[row] + p * piece;
-  const int32_t e = (b + piece < rp[row + 1]) ? b + piece : rp[row + 1];
+  if (w < nsw) {
+    const int idx = w * SLOTS + s;
+    const bool valid = s < SLOTS && idx < nshort;
+    int64_t row = 0;
+    int32_t beg = 0, end = 0;
+    if (valid) {
+      row = short_rows[idx];
+      beg = rp[row];
+      end = rp[row + 1];
+    }
+    const float rv = (valid && rowvec) ? rowvec[row] : 1.0f;
+    for (int c0 = 0; c0 < k; c0 += KC) {
+      const int col = c0 + c;
+      const bool colok = valid && col < k;
+      float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok);
+      if (colok) {
+        if (colvec) acc -= rv * static_cast<float>(colvec[col]);
+        Y[row * ldy + col] = acc;
+      }
+    }
+    return;
+  }
+  const int p = w - nsw;
+  if (p >= npieces) return;
+  const int64_t row = piece_row[p];
+  const int first = piece_first[p];
+  const int32_t rb = rp[row], re = rp[row + 1];
+  const bool single = re - rb <= piece;
+  const int32_t b = rb + (p - first) * piece;
+  const int32_t e = (b + piece < re) ? b + piece : re;
+  const float rv = rowvec ? rowvec[row] : 1.0f;
   for (int c0 = 0; c0 < k; c0 += KC) {
     const int col = c0 + c;
     const bool colok = s < SLOTS && col < k;
     const int32_t bs = (s < SLOTS) ? b + s * KC : e;
-    float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok);
+    const float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok);
     float tot = 0.0f;
-    for (int ss = 0; ss < SLOTS; ++ss) tot += __shfl(acc, ss * KC + c);
-    if (s == 0 && col < k) part[(static_cast<int64_t>(poff[i]) + p) * k + col] = tot;
+    for (int q = 0; q < SLOTS; ++q) tot += __shfl(acc, q * KC + c);
+    if (s == 0 && col < k) {
+      if (single) {
+        if (colvec) tot -= rv * static_cast<float>(colvec[col]);
+        Y[row * ldy + col] = tot;
+      } else {
+        part[static_cast<int64_t>(p) * k + col] = tot;
+      }
+    }
   }
 }
 
-// Y[row] = sum of the row's piece sums in piece order (- centring).
+// Rows cut into several pieces: Y[row] = sum of the piece sums in piece
+// order (- centring), one wavefront per row.
 __global__ __launch_bounds__(256) void csr_combine_kernel(
-    const int32_t* __restrict__ list, const int32_t* __restrict__ npc,
-    const int32_t* __restrict__ poff, int nlong, int k,
+    int nmulti, int k, int piece, const int32_t* __restrict__ multi_row,
+    const int32_t* __restrict__ multi_first, const int32_t* __restrict__ rp,
     const float* __restrict__ part, float* __restrict__ Y, int64_t ldy,
     const float* __restrict__ rowvec, const double* __restrict__ colvec) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
-  if (i >= nlong) return;
+  const int i = static_cast<int>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (i >= nmulti) return;
   const int lane = threadIdx.x & 63;
-  const int64_t row = list[i];
+  const int64_t row = multi_row[i];
+  const int first = multi_first[i];
+  const int npc = (rp[row + 1] - rp[row] + piece - 1) / piece;
   const float rv = rowvec ? rowvec[row] : 1.0f;
   for (int col = lane; col < k; col += 64) {
+    const float* pp = part + static_cast<int64_t>(first) * k + col;
     float acc = 0.0f;
-    for (int p = 0; p < npc[i]; ++p) acc += part[(static_cast<int64_t>(poff[i]) + p) * k + col];
+    int j = 0;
+    for (; j + 8 <= npc; j += 8) {  // eight loads in flight, added in order
+      float t[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) t[u] = pp[static_cast<int64_t>(j + u) * k];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += t[u];
+    }
+    for (; j < npc; ++j) acc += pp[static_cast<int64_t>(j) * k];
     if (colvec) acc -= rv * static_cast<float>(colvec[col]);
     Y[row * ldy + col] = acc;
   }
 }
 
-// Rows longer than short_thr: list them with their piece counts; counters[0]
-// = number of listed rows, counters[1] = largest piece count.
-__global__ __launch_bounds__(256) void csr_classify_kernel(const int32_t* rp,
-                                                           int64_t rows,
-                                                           int short_thr, int piece,
-                                                           int32_t* list, int32_t* npc,
-                                                           int32_t* counters) {
-  const int64_t r = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (r >= rows) return;
-  const int32_t len = rp[r + 1] - rp[r];
-  if (len > short_thr) {
-    const int32_t pos = atomicAdd(&counters[0], 1);
-    const int32_t np = (len + piece - 1) / piece;
-    list[pos] = static_cast<int32_t>(r);
-    npc[pos] = np;
-    atomicMax(&counters[1], np);
+// Block partials of the weighted column sums w^T X (FP64): block b sums
+// its contiguous row range by slots of KC lanes and adds the slots in slot
+// order into colpart[b].
+__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ X, int64_t ldx,
+                                                     int64_t L, int k, int KC,
+                                                     const float* __restrict__ w,
+                                                     double* __restrict__ colpart) {
+  __shared__ double red[4 * 64];
+  const int t = threadIdx.x;
+  const int SLOTS = 64 / KC;
+  const int lane = t & 63;
+  const int s = lane / KC, c = lane - s * KC;
+  const int slot = (t >> 6) * SLOTS + s;
+  const int NSL = 4 * SLOTS;
+  const int64_t per = (L + gridDim.x - 1) / gridDim.x;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t re = (rb + per < L) ? rb + per : L;
+  for (int c0 = 0; c0 < k; c0 += KC) {
+    const int col = c0 + c;
+    const bool ok = s < SLOTS && col < k;
+    if (ok) {
+      double acc = 0.0;
+#pragma unroll 8
+      for (int64_t r = rb + slot; r < re; r += NSL) {
+        const double wr = w ? static_cast<double>(w[r]) : 1.0;
+        acc += wr * static_cast<double>(X[r * ldx + col]);
+      }
+      red[slot * KC + c] = acc;
+    }
+    __syncthreads();
+    if (t < KC && c0 + t < k) {
+      double sum = 0.0;
+      for (int q = 0; q < NSL; ++q) sum += red[q * KC + t];
+      colpart[static_cast<int64_t>(blockIdx.x) * k + c0 + t] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+// colvec[c] = sum of the nb block partials of column c: slots take every
+// NSL-th block, then the slots are added in slot order.
+__global__ __launch_bounds__(256) void colsum_final_kernel(const double* __restrict__ colpart,
+                                                           int nb, int k, int KC,
+                                                           double* __restrict__ colvec) {
+  __shared__ double red[4 * 64];
+  const int t = threadIdx.x;
+  const int SLOTS = 64 / KC;
+  const int lane = t & 63;
+  const int s = lane / KC, c = lane - s * KC;
+  const int slot = (t >> 6) * SLOTS + s;
+  const int NSL = 4 * SLOTS;
+  for (int c0 = 0; c0 < k; c0 += KC) {
+    const int col = c0 + c;
+    if (s < SLOTS && col < k) {
+      double acc = 0.0;
+      for (int b = slot; b < nb; b += NSL) acc += colpart[static_cast<int64_t>(b) * k + col];
+      red[slot * KC + c] = acc;
+    }
+    __syncthreads();
+    if (t < KC && c0 + t < k) {
+      double sum = 0.0;
+      for (int q = 0; q < NSL; ++q) sum += red[q * KC + t];
+      colvec[c0 + t] = sum;
+    }
+    __syncthreads();
   }
 }
 
@@ -301,34 +522,82 @@ void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
                      int64_t rows, int k, const float* X, int64_t ldx, float* Y,
                      int64_t ldy, const float* rowvec, const double* colvec,
-                     int short_thr, hipStream_t s) {
+                     hipStream_t s) {
   if (rows <= 0 || k <= 0) return;
   const int KC = kc_for(k);
   const int64_t waves = cdiv(rows, 64 / KC);
   csr_spmm_kernel<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
-      rows, k, KC, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec, short_thr);
+      rows, k, KC, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec, 0x7FFFFFFF);
 }
 
-void launch_csr_classify(const int32_t* rp, int64_t rows, int short_thr,
-                         int32_t* list, int32_t* npc, int32_t* counters,
-                         hipStream_t s) {
-  launch_fill_i32(counters, 2, 0, s);
-  if (rows > 0)
-    csr_classify_kernel<<<static_cast<unsigned>(cdiv(rows, 256)), 256, 0, s>>>(
-        rp, rows, short_thr, kCsrPiece, list, npc, counters);
+int csr_piece_len(int k) { return (64 / kc_for(k)) * kCsrShort; }
+
+int64_t csr_max_pieces(int64_t nnz, int64_t rows) {
+  // a row of len > kCsrShort nonzeros has at most len / kCsrShort + 1
+  // pieces, and at most nnz / kCsrShort rows are that long
+  const int64_t longrows = std::min(rows, nnz / kCsrShort);
+  return nnz / kCsrShort + longrows + 1;
 }
 
-void launch_csr_pieces(const CsrPieces& pl, const int32_t* rp, const int32_t* ci,
-                       const float* v, int k, const float* X, int64_t ldx, float* Y,
-                       int64_t ldy, const float* rowvec, const double* colvec,
-                       hipStream_t s) {
-  if (pl.nlong <= 0 || k <= 0) return;
+int64_t csr_plan_chunks(int64_t rows) { return cdiv(rows, kPlanRows); }
+
+void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl, int32_t* totals,
+                     hipStream_t s) {
+  const int64_t nb = csr_plan_chunks(rows);
+  int32_t* cnt_s = pl.blk;
+  int32_t* cnt_p = pl.blk + (nb + 1);
+  int32_t* cnt_m = pl.blk + 2 * (nb + 1);
+  int32_t* off_s = pl.blk + 3 * (nb + 1);
+  int32_t* off_p = pl.blk + 4 * (nb + 1);
+  int32_t* off_m = pl.blk + 5 * (nb + 1);
+  pl.rows = rows;
+  const int piece = csr_piece_len(k);  // pl.operand is set by the caller
+  if (nb > 0)
+    csr_plan_count_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(rp, rows, piece, cnt_s,
+                                                                   cnt_p, cnt_m);
+  scan_kernel<<<1, 1024, 0, s>>>(cnt_s, nb, off_s);
+  scan_kernel<<<1, 1024, 0, s>>>(cnt_p, nb, off_p);
+  scan_kernel<<<1, 1024, 0, s>>>(cnt_m, nb, off_m);
+  if (nb > 0)
+    csr_plan_write_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(
+        rp, rows, piece, off_s, off_p, off_m, pl.short_rows, pl.piece_row, pl.piece_first,
+        pl.multi_row, pl.multi_first);
+  csr_plan_totals_kernel<<<1, 64, 0, s>>>(off_s, off_p, off_m, nb, totals);
+}
+
+void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
+                        const float* v, int k, const float* X, int64_t ldx, float* Y,
+                        int64_t ldy, const float* rowvec, const double* colvec,
+                        hipStream_t s) {
+  if (k <= 0) return;
   const int KC = kc_for(k);
-  const dim3 grid(static_cast<unsigned>(pl.nlong), static_cast<unsigned>(pl.maxp));
-  csr_pieces_kernel<<<grid, 64, 0, s>>>(pl.list, pl.npc, pl.poff, k, KC, kCsrPiece, rp, ci,
-                                        v, X, ldx, pl.part);
-  csr_combine_kernel<<<static_cast<unsigned>(cdiv(pl.nlong, 4)), 256, 0, s>>>(
-      pl.list, pl.npc, pl.poff, pl.nlong, k, pl.part, Y, ldy, rowvec, colvec);
+  const int64_t nsw = cdiv(pl.nshort, 64 / KC);
+  const int64_t waves = nsw + pl.npieces;
+  if (waves <= 0) return;
+  auto kern = pl.operand ? csr_product_kernel<1> : csr_product_kernel<0>;
+  kern<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
+      k, KC, csr_piece_len(k), pl.nshort, pl.npieces, pl.short_rows, pl.piece_row,
+      pl.piece_first, pl.part, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec);
+}
+
+void launch_csr_combine(const CsrPlan& pl, const int32_t* rp, int k, float* Y, int64_t ldy,
+                        const float* rowvec, const double* colvec, hipStream_t s) {
+  if (pl.nmulti > 0 && k > 0)
+    csr_combine_kernel<<<static_cast<unsigned>(cdiv(pl.nmulti, 4)), 256, 0, s>>>(
+        pl.nmulti, k, csr_piece_len(k), pl.multi_row, pl.multi_first, rp, pl.part, Y, ldy,
+        rowvec, colvec);
+}
+
+int colsum_blocks(int64_t L) {
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kColsumBlocks, cdiv(L, 256))));
+}
+
+void launch_colsum(const float* X, int64_t ldx, int64_t L, int k, const float* w,
+                   double* colpart, double* colvec, hipStream_t s) {
+  if (k <= 0) return;
+  const int nb = colsum_blocks(L);
+  colsum_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(X, ldx, L, k, kc_for(k), w, colpart);
+  colsum_final_kernel<<<1, 256, 0, s>>>(colpart, nb, k, kc_for(k), colvec);
 }
 
 void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s) {

@@ -146,14 +146,12 @@ struct Layout {
   double* Pk = nullptr;
   JacobiWs jk;
   // CSR
-  int32_t *trp = nullptr, *tci = nullptr, *cursor = nullptr, *long_a = nullptr,
-          *long_t = nullptr, *npc_a = nullptr, *npc_t = nullptr, *poff_a = nullptr,
-          *poff_t = nullptr, *counters = nullptr;
-  float* part = nullptr;
+  int32_t *trp = nullptr, *tci = nullptr, *cursor = nullptr, *counters = nullptr;
+  CsrPlan plan_a, plan_t;       // work plans of A and A^T (shared part)
+  double* colpart = nullptr;    // kColsumBlocks x k block sums of the centring
   float* tv = nullptr;
   unsigned long long* keys = nullptr;
   float* mu = nullptr;
-  float* ones = nullptr;
   double* colvec = nullptr;
   size_t bytes = 0;
 };
@@ -202,17 +200,23 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
       L.cursor = ar.take<int32_t>(static_cast<size_t>(d));
       L.keys = ar.take<unsigned long long>(static_cast<size_t>(3 * nnz));
     }
-    L.long_a = ar.take<int32_t>(static_cast<size_t>(n));
-    L.npc_a = ar.take<int32_t>(static_cast<size_t>(n));
-    L.poff_a = ar.take<int32_t>(static_cast<size_t>(n + 1));
-    L.long_t = ar.take<int32_t>(static_cast<size_t>(d));
-    L.npc_t = ar.take<int32_t>(static_cast<size_t>(d));
-    L.poff_t = ar.take<int32_t>(static_cast<size_t>(d + 1));
-    L.counters = ar.take<int32_t>(4);
-    L.part = ar.take<float>(static_cast<size_t>(nnz / kCsrPiece + std::max(n, d) + 1) *
-                            static_cast<size_t>(k));
+    const int64_t pmax = csr_max_pieces(nnz, std::max(n, d));
+    float* part = ar.take<float>(static_cast<size_t>(pmax) * static_cast<size_t>(k));
+    CsrPlan* plans[2] = {&L.plan_a, &L.plan_t};
+    const int64_t prow[2] = {n, d};
+    for (int i = 0; i < 2; ++i) {
+      CsrPlan& pl = *plans[i];
+      pl.short_rows = ar.take<int32_t>(static_cast<size_t>(prow[i]));
+      pl.piece_row = ar.take<int32_t>(static_cast<size_t>(pmax));
+      pl.piece_first = ar.take<int32_t>(static_cast<size_t>(pmax));
+      pl.multi_row = ar.take<int32_t>(static_cast<size_t>(pmax));
+      pl.multi_first = ar.take<int32_t>(static_cast<size_t>(pmax));
+      pl.blk = ar.take<int32_t>(static_cast<size_t>(6 * (csr_plan_chunks(prow[i]) + 1)));
+      pl.part = part;
+    }
+    L.counters = ar.take<int32_t>(6);
+    L.colpart = ar.take<double>(static_cast<size_t>(kColsumBlocks) * k);
     L.mu = ar.take<float>(static_cast<size_t>(n));
-    L.ones = ar.take<float>(static_cast<size_t>(d));
     L.colvec = ar.take<double>(static_cast<size_t>(k));
   }
   L.bytes = align_up(ar.off, 256);
@@ -345,53 +349,39 @@ struct DenseOp : Op {
 struct CsrOp : Op {
   const int32_t *rp = nullptr, *ci = nullptr, *trp = nullptr, *tci = nullptr;
   const float *v = nullptr, *tv = nullptr;
-  CsrPieces pa, pt;             // rows longer than kCsrShort of A and A^T
+  const CsrPlan* pa = nullptr;  // work plans of A and A^T
+  const CsrPlan* pt = nullptr;
   const float* mu = nullptr;    // row means (centring) or null
-  const float* ones = nullptr;  // d ones
+  double* colpart = nullptr;    // kColsumBlocks x k
   double* colvec = nullptr;     // k
-  void centre_vec(const void* X, int64_t ldx, int k, int64_t L, const float* w,
-                  hipStream_t s) {
-    // colvec = X^T w  (X L x k)
-    tm->begin(BK_PH_CENTER);
-    TNArgs a;
-    a.L = L;
-    a.p = k;
-    a.r = 1;
-    a.X = X;
-    a.ldx = ldx;
-    a.x_type = BK_F32;
-    a.Y = w;
-    a.ldy = 1;
-    a.y_f64 = false;
-    a.C = colvec;
-    a.ldc = 1;
-    a.c_f64 = true;
-    a.partial = partial;
-    launch_tn(a, s);
-    tm->end(2);
-  }
-  void product(const int32_t* r_, const int32_t* c_, const float* v_, int64_t rows,
-               const CsrPieces& pl, int phase, const void* X, int64_t ldx, int k, void* Y,
-               int64_t ldy, const float* rowvec, hipStream_t s) {
-    const double* cv = mu ? colvec : nullptr;
-    tm->begin(phase);
-    launch_csr_spmm(r_, c_, v_, rows, k, static_cast<const float*>(X), ldx,
-                    static_cast<float*>(Y), ldy, rowvec, cv, kCsrShort, s);
-    tm->end(1);
-    if (pl.nlong) {
-      tm->begin(BK_PH_LONG);
-      launch_csr_pieces(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
-                        static_cast<float*>(Y), ldy, rowvec, cv, s);
+  // Centred products (footnote on PCA, Section 1): with Abar = A - mu 1^T,
+  //   Abar X   = A X   - mu (1^T X)    and   Abar^T Y = A^T Y - 1 (mu^T Y),
+  // the k-vector (1^T X or mu^T Y) first, then the product with the rank-1
+  // correction in its epilogue.
+  void product(const int32_t* r_, const int32_t* c_, const float* v_, const CsrPlan& pl,
+               int phase, const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
+               const float* rowvec, const float* colw, int64_t Lc, hipStream_t s) {
+    if (mu) {
+      tm->begin(BK_PH_CENTER);
+      launch_colsum(static_cast<const float*>(X), ldx, Lc, k, colw, colpart, colvec, s);
       tm->end(2);
+    }
+    tm->begin(phase);
+    launch_csr_product(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
+                       static_cast<float*>(Y), ldy, rowvec, mu ? colvec : nullptr, s);
+    tm->end(1);
+    if (pl.nmulti > 0) {
+      tm->begin(BK_PH_LONG);
+      launch_csr_combine(pl, r_, k, static_cast<float*>(Y), ldy, rowvec, mu ? colvec : nullptr,
+                         s);
+      tm->end(1);
     }
   }
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
-    if (mu) centre_vec(X, ldx, k, d, ones, s);
-    product(rp, ci, v, n, pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, s);
+    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s);
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
-    if (mu) centre_vec(X, ldx, k, n, mu, s);
-    product(trp, tci, tv, d, pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, s);
+    product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s);
   }
 };
 
@@ -1027,18 +1017,20 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
     tci = L.tci;
     tv = L.tv;
   }
-  launch_csr_classify(row_ptr, n, kCsrShort, L.long_a, L.npc_a, L.counters, s);
-  launch_csr_classify(trp, d, kCsrShort, L.long_t, L.npc_t, L.counters + 2, s);
-  if (o.center) {
-    launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
-    launch_fill_f32(L.ones, d, 1.0f, s);
-  }
-  int32_t cnt[4] = {0, 0, 0, 0};
+  launch_csr_plan(row_ptr, n, k, L.plan_a, L.counters, s);
+  launch_csr_plan(trp, d, k, L.plan_t, L.counters + 3, s);
+  if (o.center) launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
+  int32_t cnt[6] = {0, 0, 0, 0, 0, 0};
   BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   BK_TRY(hipStreamSynchronize(s));
   BK_TRY_LAUNCH();
-  launch_scan_i32(L.npc_a, cnt[0], L.poff_a, s);
-  launch_scan_i32(L.npc_t, cnt[2], L.poff_t, s);
+  L.plan_t.operand = 1;
+  L.plan_a.nshort = cnt[0];
+  L.plan_a.npieces = cnt[1];
+  L.plan_a.nmulti = cnt[2];
+  L.plan_t.nshort = cnt[3];
+  L.plan_t.npieces = cnt[4];
+  L.plan_t.nmulti = cnt[5];
   prep.end(0);
 
   CsrOp op;
@@ -1051,20 +1043,10 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   op.trp = trp;
   op.tci = tci;
   op.tv = tv;
-  op.pa.list = L.long_a;
-  op.pa.npc = L.npc_a;
-  op.pa.poff = L.poff_a;
-  op.pa.nlong = cnt[0];
-  op.pa.maxp = cnt[1];
-  op.pa.part = L.part;
-  op.pt.list = L.long_t;
-  op.pt.npc = L.npc_t;
-  op.pt.poff = L.poff_t;
-  op.pt.nlong = cnt[2];
-  op.pt.maxp = cnt[3];
-  op.pt.part = L.part;
+  op.pa = &L.plan_a;
+  op.pt = &L.plan_t;
   op.mu = o.center ? L.mu : nullptr;
-  op.ones = L.ones;
+  op.colpart = L.colpart;
   op.colvec = L.colvec;
   const int st = solve(op, L, o, k, q, seed, nullptr, Z, ldz, ritz, info, s);
   if (info && o.timing) {
@@ -1205,7 +1187,7 @@ int bk_csr_product(const int32_t* row_ptr, const int32_t* col_idx, const float* 
   (void)cols;
   // every row by the row kernel (no long-row plan for a one-off product)
   launch_csr_spmm(row_ptr, col_idx, vals, rows, k, X, ldx, Y, ldy, nullptr, nullptr,
-                  0x7FFFFFFF, static_cast<hipStream_t>(stream));
+                  static_cast<hipStream_t>(stream));
   BK_TRY_LAUNCH();
   return BK_OK;
 }

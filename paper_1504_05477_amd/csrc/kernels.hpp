@@ -143,30 +143,56 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k,
 void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
                          int64_t cols, int64_t nnz, Ctrl* ctrl, hipStream_t s);
 // Y (rows x k) = A X - rowvec (x) colvec (rowvec nullable = all ones,
-// colvec nullable = no correction).  Rows longer than short_thr are skipped
-// here and done by launch_csr_pieces.
-constexpr int kCsrShort = 64;    // rows up to this many nonzeros: one slot
-constexpr int kCsrPiece = 1024;  // longer rows: pieces of this many nonzeros
+// colvec nullable = no correction), every row by one slot of KC lanes
+// (no work plan: the one-off product of the public helper).
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
                      int64_t rows, int k, const float* X, int64_t ldx,
                      float* Y, int64_t ldy, const float* rowvec,
-                     const double* colvec, int short_thr, hipStream_t s);
-// Long rows of one CSR matrix: list[i], npc[i] pieces, piece offsets poff,
-// FP32 piece sums part[total pieces x k].
-struct CsrPieces {
-  const int32_t* list = nullptr;
-  const int32_t* npc = nullptr;
-  const int32_t* poff = nullptr;
-  int nlong = 0, maxp = 0;
-  float* part = nullptr;
+                     const double* colvec, hipStream_t s);
+
+// Work plan of one CSR operand for the Krylov products.  Rows of at most
+// kCsrShort nonzeros are listed in row order and taken SLOTS = 64 / KC to a
+// wavefront; longer rows are cut into pieces of csr_piece_len(k) nonzeros,
+// one wavefront each; a row of several pieces is finished by a combine
+// kernel that adds its piece sums in piece order (deterministic).  The plan
+// depends only on the sparsity structure and k.
+constexpr int kCsrShort = 64;
+int csr_piece_len(int k);
+// upper bound on the number of pieces of any matrix with nnz nonzeros
+int64_t csr_max_pieces(int64_t nnz, int64_t rows);
+struct CsrPlan {
+  int32_t* short_rows = nullptr;   // rows: short rows, row order
+  int32_t* piece_row = nullptr;    // max pieces: row of piece p
+  int32_t* piece_first = nullptr;  // max pieces: first piece of that row
+  int32_t* multi_row = nullptr;    // max pieces: rows of several pieces
+  int32_t* multi_first = nullptr;  // max pieces: their first piece
+  int32_t* blk = nullptr;          // 6 * (row chunks + 1): counts and offsets
+  float* part = nullptr;           // max pieces * k piece sums
+  int64_t rows = 0;
+  int nshort = 0, npieces = 0, nmulti = 0;
+  int operand = 0;                 // 0: A, 1: A^T (names the kernel instance)
 };
-void launch_csr_classify(const int32_t* rp, int64_t rows, int short_thr,
-                         int32_t* list, int32_t* npc, int32_t* counters,
-                         hipStream_t s);
-void launch_csr_pieces(const CsrPieces& pl, const int32_t* rp, const int32_t* ci,
-                       const float* v, int k, const float* X, int64_t ldx,
-                       float* Y, int64_t ldy, const float* rowvec,
-                       const double* colvec, hipStream_t s);
+int64_t csr_plan_chunks(int64_t rows);
+// builds the plan on the stream; totals[0..2] = short rows, pieces, rows of
+// several pieces (device, read back by the caller before launch_csr_product)
+void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl,
+                     int32_t* totals, hipStream_t s);
+// Y = A X - rowvec colvec^T (rowvec nullable = ones, colvec nullable = no
+// centring term).
+void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
+                        const float* v, int k, const float* X, int64_t ldx,
+                        float* Y, int64_t ldy, const float* rowvec,
+                        const double* colvec, hipStream_t s);
+// finishes the rows of several pieces (after launch_csr_product)
+void launch_csr_combine(const CsrPlan& pl, const int32_t* rp, int k, float* Y, int64_t ldy,
+                        const float* rowvec, const double* colvec, hipStream_t s);
+// colvec[c] = sum_r w[r] X[r][c] (FP64) over L rows (w nullable = ones):
+// colsum_blocks(L) blocks sum contiguous row ranges into colpart (blocks x k)
+// and a one-block kernel adds those in block order (fixed order throughout).
+constexpr int kColsumBlocks = 256;
+int colsum_blocks(int64_t L);
+void launch_colsum(const float* X, int64_t ldx, int64_t L, int k, const float* w,
+                   double* colpart, double* colvec, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (one workgroup)
 void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s);
 void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,

@@ -195,6 +195,124 @@ __global__ __launch_bounds__(256) void chol_kernel(int k, const double* G,
   }
 }
 
+__device__ __forceinline__ double lane_f64(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+// Upper Cholesky factor of (G + shift I) in registers of one wavefront:
+// lane c holds column c (a[r] = S[r][c], rows r <= c meaningful), the k x k
+// problem padded to K with the identity.  Right-looking: the pivot and the
+// scaled row j are broadcast from their lanes with readlane.  rinv[j] =
+// 1 / S[j][j].  Returns false on a non-positive or non-finite pivot.
+template <int K>
+__device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)[K],
+                          double (&rinv)[K], double& minpiv) {
+  const int c = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < K; ++r)
+    a[r] = (c < k) ? ((r <= c) ? g[r] + (r == c ? shift : 0.0) : 0.0) : (r == c ? 1.0 : 0.0);
+  minpiv = INFINITY;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const double d = lane_f64(a[j], j);
+    if (!(d > 0.0) || !isfinite(d)) return false;
+    const double rd = sqrt(d);
+    const double inv = 1.0 / rd;
+    if (j < k) minpiv = fmin(minpiv, rd);
+    rinv[j] = inv;
+    a[j] = (c == j) ? rd : a[j] * inv;  // row j of the factor (lanes c >= j)
+#pragma unroll
+    for (int r = j + 1; r < K; ++r) a[r] -= lane_f64(a[j], r) * a[j];
+  }
+  return true;
+}
+
+// CholeskyQR factor for k <= 64 in one wavefront (same modes and outputs as
+// chol_kernel): R = chol(G [+ shift]) and Rinv = R^-1 by back substitution,
+// lane c forming column c of Rinv.
+template <int K>
+__global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __restrict__ G,
+                                                       const double* __restrict__ Gpre, int mode,
+                                                       int block, double tau,
+                                                       double shift_coef, double* __restrict__ R,
+                                                       double* __restrict__ Rinv, Ctrl* ctrl) {
+  const int c = threadIdx.x;
+  double g[K];
+  int bad = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const double x = (r < k && c < k) ? G[r * k + c] : 0.0;
+    if (!isfinite(x)) bad = 1;
+    g[r] = x;
+  }
+  const double tr = wave_sum_f64(c < k ? G[c * k + c] : 0.0);
+  const double pre = (mode == CHOL_FIRST) ? wave_sum_f64(c < k ? Gpre[c * k + c] : 0.0) : 0.0;
+  bool zero = false;
+  if (__any(bad)) {
+    if (c == 0) atomicOr(&ctrl->flags, CTRL_NONFINITE);
+    zero = true;
+  } else if (mode == CHOL_FIRST) {
+    if (!(sqrt(tr) > tau * sqrt(pre))) {
+      if (c == 0) atomicMin(&ctrl->q_eff, block - 1);
+      zero = true;
+    }
+  } else if (!(tr > 0.0)) {
+    if (mode == CHOL_FIRST_BLOCK0 && c == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+    zero = true;
+  }
+  double a[K], rinv[K];
+  double minpiv = 0.0;
+  if (!zero && mode == CHOL_FIRST_BLOCK0) {
+    const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv);
+    if (!ok || !(minpiv > tau * sqrt(tr))) {
+      if (c == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+      zero = true;
+    }
+  }
+  if (!zero) {
+    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
+    if (!chol_regs<K>(k, g, shift, a, rinv, minpiv)) {
+      if (c == 0) {
+        if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+        else atomicMin(&ctrl->q_eff, block - 1);
+      }
+      zero = true;
+    }
+  }
+  if (zero) {
+    for (int i = c; i < k * k; i += 64) {
+      R[i] = 0.0;
+      Rinv[i] = 0.0;
+    }
+    return;
+  }
+  // x = column c of R^-1: x_i = (delta_ic - sum_{l > i} R[i][l] x_l) / R[i][i]
+  double x[K];
+#pragma unroll
+  for (int i = K - 1; i >= 0; --i) {
+    double sum = 0.0;
+#pragma unroll
+    for (int l = i + 1; l < K; ++l) sum += lane_f64(a[i], l) * x[l];
+    x[i] = ((i == c ? 1.0 : 0.0) - sum) * rinv[i];
+  }
+  if (c < k) {
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      if (r < k) {
+        R[r * k + c] = (r <= c) ? a[r] : 0.0;
+        Rinv[r * k + c] = (r <= c) ? x[r] : 0.0;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void trmm_upper_kernel(int k, const double* A,
                                                          const double* B,
                                                          double* T) {
@@ -414,11 +532,22 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
                         hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     attr_set = true;
   }
-  // one wavefront for small blocks: its barriers cost almost nothing
-  const int threads = k <= 64 ? 64 : 256;
-  chol_kernel<<<1, threads, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau,
-                                                 shift_coef, R, Rinv, work, ctrl,
-                                                 use_lds);
+  // k <= 64: the factor lives in the registers of one wavefront
+#define BK_CHOL_WAVE(KK)                                                                   \
+  if (k <= KK) {                                                                           \
+    chol_wave_kernel<KK><<<1, 64, 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R, Rinv, \
+                                          ctrl);                                          \
+    return;                                                                                \
+  }
+  BK_CHOL_WAVE(8)
+  BK_CHOL_WAVE(16)
+  BK_CHOL_WAVE(24)
+  BK_CHOL_WAVE(32)
+  BK_CHOL_WAVE(48)
+  BK_CHOL_WAVE(64)
+#undef BK_CHOL_WAVE
+  chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
+                                                 Rinv, work, ctrl, use_lds);
 }
 
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,

@@ -132,6 +132,41 @@ def low_rank_dense(n: int, d: int, rank: int, seed: int) -> np.ndarray:
     return planted_dense(n, d, 1.0 / np.arange(1, rank + 1), seed)
 
 
+# Factors of at least 2^31 entries are not handed to one library QR (its
+# 32-bit indexing does not reach them); they are built row block by row
+# block instead.
+_BIG = 1 << 31
+_ROWBLK = 8192
+
+
+def _orth_blocked(rows, cols, g, device):
+    """Q factor (positive diagonal of R) of a seeded N(0,1) rows x cols
+    matrix drawn in row blocks, by CholeskyQR2 in FP64: with G = X^T X =
+    R^T R (Cholesky), Q = X R^-1, repeated once on Q.  In exact arithmetic
+    this is the Householder Q made unique by diag(R) > 0; a Gaussian matrix
+    with rows >= 2 cols is well conditioned, so two passes reach FP64
+    orthogonality.  Every library call sees at most _ROWBLK x cols entries."""
+    import torch
+
+    q = torch.empty(rows, cols, dtype=torch.float64, device=device)
+    for r0 in range(0, rows, _ROWBLK):
+        r1 = min(rows, r0 + _ROWBLK)
+        q[r0:r1] = torch.randn(r1 - r0, cols, generator=g, device=device,
+                               dtype=torch.float64)
+    for _ in range(2):
+        gram = torch.zeros(cols, cols, dtype=torch.float64, device=device)
+        for r0 in range(0, rows, _ROWBLK):
+            blk = q[r0:min(rows, r0 + _ROWBLK)]
+            gram += blk.t() @ blk
+        rfac = torch.linalg.cholesky(gram, upper=True)
+        del gram
+        for r0 in range(0, rows, _ROWBLK):
+            r1 = min(rows, r0 + _ROWBLK)
+            q[r0:r1] = torch.linalg.solve_triangular(rfac, q[r0:r1], upper=True, left=False)
+        del rfac
+    return q
+
+
 def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
                         out_dtype=None, noise: float = 0.0,
                         noise_seed: int | None = None, return_factors=False):
@@ -149,12 +184,14 @@ def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
     g.manual_seed(seed)
 
     def orth(rows, cols):
-        x = torch.randn(rows, cols, generator=g, device=device, dtype=torch.float64)
-        qm, rm = torch.linalg.qr(x)
-        s = torch.sign(torch.diagonal(rm))
-        s[s == 0] = 1
-        del rm, x
-        return qm * s
+        if rows * cols < _BIG:
+            x = torch.randn(rows, cols, generator=g, device=device, dtype=torch.float64)
+            qm, rm = torch.linalg.qr(x)
+            s = torch.sign(torch.diagonal(rm))
+            s[s == 0] = 1
+            del rm, x
+            return qm * s
+        return _orth_blocked(rows, cols, g, device)
 
     u = orth(n, r)
     v = orth(d, r)
