@@ -217,12 +217,20 @@ int bk_philox4x32_10(const uint32_t* in, int64_t count, uint32_t* out,
 int bk_quantize_dense(const float* A, int64_t n, int64_t d, int64_t lda,
                       int32_t to, void* out, float* tile_scales, void* stream);
 
-/* The block products on their own (the Krylov loop's A.X and A^T.Y):
+/* The block products on their own (the Krylov loop's A.X and A^T.Y,
+ * Algorithm 2, steps 2-3):
  * trans = 0: Y (n x k, ld ldy) = A X, X d x k (ld ldx);
  * trans = 1: Y (d x k, ld ldy) = A^T X, X n x k (ld ldx).
  * X and Y are FP64 for a_type BK_F64, FP32 otherwise.  The A^T X form uses a
- * split reduction with FP64 partial sums; it needs a workspace of
- * bk_dense_product_workspace(...) bytes (NULL: allocated in the call). */
+ * split reduction with FP64 partial sums.  Workspace:
+ * bk_dense_product_workspace(...) bytes (NULL: allocated in the call).
+ * Matrix cores: for FP32 / BF16 / FP8 A whose rows are 16-byte aligned and
+ * whose reduction length is a multiple of 128 bytes of A's type (A X) or
+ * whose column count is a multiple of 16 bytes (A^T X), and for products of
+ * at least 1e8 (A X) or 1e9 (A^T X) flops, X is packed in A's type (BF16:
+ * round to nearest even; FP8: one scale amax / 448 per 128 rows of X) and
+ * the product runs on MFMA with FP32 chunk sums; other shapes run on the
+ * vector units with X in FP32. */
 size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d,
                                   int32_t k, int32_t a_type);
 int bk_dense_product(int32_t trans, const void* A, int64_t lda, int32_t a_type,

@@ -130,6 +130,8 @@ struct Layout {
   void* Bs = nullptr;
   void* Bs2 = nullptr;
   double* partial = nullptr;
+  void* pack = nullptr;  // matrix-core operand packing of the dense products
+  size_t pack_bytes = 0;
   double *G = nullptr, *Gpre = nullptr, *R = nullptr, *Rinv = nullptr,
          *cholwork = nullptr, *Racc = nullptr, *Rtmp = nullptr;
   double* C = nullptr;
@@ -170,6 +172,12 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.Bs = ar.take<char>(static_cast<size_t>(n * k) * es);
   L.Bs2 = ar.take<char>(static_cast<size_t>(n * k) * es);
   L.partial = ar.take<double>(static_cast<size_t>(partial_need(n, d, k, q, o.refine != 0, csr)));
+  if (!csr && !f64) {
+    // X^T of A X in FP32 (the widest type), Y^T of A^T Y in BF16 / FP8
+    L.pack_bytes = static_cast<size_t>(std::max(mfma_pack_bytes(d, k, BK_F32),
+                                                mfma_pack_bytes(n, k, BK_BF16)));
+    L.pack = ar.take<char>(L.pack_bytes);
+  }
   const size_t kk = static_cast<size_t>(k) * k;
   L.G = ar.take<double>(kk);
   L.Gpre = ar.take<double>(kk);
@@ -303,6 +311,8 @@ struct DenseOp : Op {
   int64_t lda = 0;
   int a_type = BK_F32;
   const float* ascale = nullptr;
+  void* pack = nullptr;  // matrix-core operand packing (nullable)
+  size_t pack_bytes = 0;
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     tm->begin(BK_PH_AX);
     NNArgs a;
@@ -320,8 +330,9 @@ struct DenseOp : Op {
     a.C = Y;
     a.ldc = ldy;
     a.c_f64 = f64;
-    launch_nn(a, s);
-    tm->end(1);
+    a.work = pack;
+    a.work_bytes = pack_bytes;
+    tm->end(launch_nn(a, s));
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     tm->begin(BK_PH_ATY);
@@ -341,8 +352,9 @@ struct DenseOp : Op {
     a.ldc = ldy;
     a.c_f64 = f64;
     a.partial = partial;
-    launch_tn(a, s);
-    tm->end(2);
+    a.work = pack;
+    a.work_bytes = pack_bytes;
+    tm->end(launch_tn(a, s));
   }
 };
 
@@ -560,6 +572,10 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   tm.s = s;
   op.tm = &tm;
   op.partial = L.partial;
+  if (DenseOp* dop = dynamic_cast<DenseOp*>(&op)) {
+    dop->pack = L.pack;
+    dop->pack_bytes = L.pack_bytes;
+  }
   Solver S;
   S.op = &op;
   S.L = &L;
@@ -621,6 +637,8 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     tm.begin(BK_PH_REFINE);
     DenseOp mop = *master;
     mop.partial = L.partial;
+    mop.pack = L.pack;
+    mop.pack_bytes = L.pack_bytes;
     Timer dummy;
     mop.tm = &dummy;
     mop.aty(Z, ldz, k, L.Wk, k, s);  // W_k = A^T Z (FP32 master)
@@ -1135,10 +1153,15 @@ int bk_quantize_dense(const float* A, int64_t n, int64_t d, int64_t lda, int32_t
 
 size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d, int32_t k,
                                   int32_t a_type) {
-  (void)a_type;
   if (n <= 0 || d <= 0 || k <= 0) return 0;
-  if (!trans) return 256;
-  return static_cast<size_t>(tn_partial_elems(n, d, k)) * sizeof(double);
+  // FP64 partials (A^T X) + the matrix-core packing of X (FP32 / BF16 / FP8)
+  const size_t part =
+      trans ? align_up(static_cast<size_t>(tn_partial_elems(n, d, k)) * sizeof(double), 256)
+            : 256;
+  const size_t pack = (a_type == BK_F64)
+                          ? 0
+                          : static_cast<size_t>(mfma_pack_bytes(trans ? n : d, k, a_type));
+  return part + pack;
 }
 
 int bk_dense_product(int32_t trans, const void* A, int64_t lda, int32_t a_type,
@@ -1153,15 +1176,16 @@ int bk_dense_product(int32_t trans, const void* A, int64_t lda, int32_t a_type,
   const size_t need = bk_dense_product_workspace(trans, n, d, k, a_type);
   DevBuf own;
   char* base = static_cast<char*>(workspace);
-  if (trans) {
-    if (!base) {
-      own.s = s;
-      if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
-      base = static_cast<char*>(own.p);
-    } else if (workspace_bytes < need) {
-      return BK_ENOMEM;
-    }
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
   }
+  const size_t part =
+      trans ? align_up(static_cast<size_t>(tn_partial_elems(n, d, k)) * sizeof(double), 256)
+            : 256;
   Timer tm;
   DenseOp op;
   op.n = n;
@@ -1172,6 +1196,10 @@ int bk_dense_product(int32_t trans, const void* A, int64_t lda, int32_t a_type,
   op.a_type = a_type;
   op.ascale = a_type == BK_FP8_E4M3 ? a_scales : nullptr;
   op.partial = reinterpret_cast<double*>(base);
+  if (a_type != BK_F64) {
+    op.pack = base + part;
+    op.pack_bytes = need - part;
+  }
   op.tm = &tm;
   if (trans) op.aty(X, ldx, k, Y, ldy, s);
   else op.ax(X, ldx, k, Y, ldy, s);

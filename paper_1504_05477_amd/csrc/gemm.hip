@@ -7,9 +7,6 @@
 
 namespace bk {
 
-void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done);
-void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, bool* done);
-
 namespace {
 
 constexpr int NN_BM = 64, NN_BN = 32, NN_BK = 32;
@@ -257,11 +254,11 @@ void tn_dispatch(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
 
 }  // namespace
 
-void launch_nn(const NNArgs& a, hipStream_t s) {
-  if (a.n <= 0 || a.N <= 0) return;  // K = 0 gives C = beta C below
+int launch_nn(const NNArgs& a, hipStream_t s) {
+  if (a.n <= 0 || a.N <= 0) return 0;  // K = 0 gives C = beta C below
   bool done = false;
   launch_nn_mfma_if(a, s, &done);
-  if (done) return;
+  if (done) return 2;
   switch (a.a_type) {
     case BK_F64:
       nn_dispatch_scaled<double, double, double, double>(a, s);
@@ -276,8 +273,9 @@ void launch_nn(const NNArgs& a, hipStream_t s) {
       nn_dispatch_lowp<fp8_t>(a, s);
       break;
     default:
-      break;
+      return 0;
   }
+  return 1;
 }
 
 int tn_splits(int64_t L, int64_t p, int r) {
@@ -294,17 +292,20 @@ int tn_splits(int64_t L, int64_t p, int r) {
 }
 
 int64_t tn_partial_elems(int64_t L, int64_t p, int r) {
-  return static_cast<int64_t>(tn_splits(L, p, r)) * p * r;
+  const int S = std::max(tn_splits(L, p, r), tn_mfma_splits(L, p, r));
+  return static_cast<int64_t>(S) * p * r;
 }
 
-void launch_tn(const TNArgs& a, hipStream_t s) {
-  if (a.p <= 0 || a.r <= 0) return;
-  bool done = false;
-  launch_tn_mfma_if(a, s, &done);
-  if (done) return;
-  int S = a.L > 0 ? tn_splits(a.L, a.p, a.r) : 1;
+int launch_tn(const TNArgs& a, hipStream_t s) {
+  if (a.p <= 0 || a.r <= 0) return 0;
+  int S = 0;
+  launch_tn_mfma_if(a, s, &S);
+  const bool mfma = S > 0;
+  if (!mfma) S = a.L > 0 ? tn_splits(a.L, a.p, a.r) : 1;
   int64_t Ls = a.L > 0 ? static_cast<int64_t>(align_up(cdiv(a.L, S), TN_BL)) : 0;
-  if (a.L <= 0) {
+  if (mfma) {
+    // partials written by the matrix-core kernel
+  } else if (a.L <= 0) {
     launch_fill_f64(a.partial, a.p * a.r, 0.0, s);
   } else {
     switch (a.x_type) {
@@ -321,9 +322,11 @@ void launch_tn(const TNArgs& a, hipStream_t s) {
         tn_dispatch<fp8_t, float>(a, S, Ls, s);
         break;
       default:
-        return;
+        return 0;
     }
   }
+  // kernels before the reduction: fill, VALU split kernel, or pack + MFMA
+  const int before = mfma ? (a.x_type == BK_F32 ? 1 : 2) : 1;
   const int64_t outs = a.p * a.r;
   if (S >= 16 && outs <= (int64_t(1) << 16)) {
     const unsigned g = static_cast<unsigned>(cdiv(outs, 4));
@@ -335,7 +338,7 @@ void launch_tn(const TNArgs& a, hipStream_t s) {
       tn_reduce_wave_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                                      static_cast<float*>(a.C), a.ldc,
                                                      a.alpha, a.beta);
-    return;
+    return before + 1;
   }
   const unsigned g = static_cast<unsigned>(cdiv(outs, 256));
   if (a.c_f64)
@@ -346,6 +349,7 @@ void launch_tn(const TNArgs& a, hipStream_t s) {
     tn_reduce_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                               static_cast<float*>(a.C), a.ldc,
                                               a.alpha, a.beta);
+  return before + 1;
 }
 
 }  // namespace bk

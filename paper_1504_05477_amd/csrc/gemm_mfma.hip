@@ -1,19 +1,588 @@
-// MFMA kernels for the wide dense products (filled in below); the hooks
-// report "not handled" for shapes they do not cover.
+// Matrix-core (MFMA) forms of the dense block products of the Krylov loop
+// (Algorithm 2, steps 2-6) and of the wide reductions around them:
+//   NN:  C (n x N, FP32) = A X,   A n x K row-major in FP32 / BF16 / FP8 e4m3
+//   TN:  partial_s (p x r, FP64) = sum over rows of split s of X^T Y,
+//        X L x p row-major in FP32 / BF16 / FP8, Y L x r
+// Element types and instructions (lane layouts checked on gfx950):
+//   FP32  v_mfma_f32_32x32x2_f32        1 value per lane and step
+//   BF16  v_mfma_f32_32x32x16_bf16      8 values per lane and step
+//   FP8   v_mfma_f32_32x32x16_fp8_fp8   8 values (OCP e4m3) per lane and step
+// The reduction dimension is walked in chunks of 128 bytes per row (32 FP32,
+// 64 BF16 or 128 FP8 values; for FP8 one chunk is one 128-wide scale tile).
+// Inside a chunk, lanes 0-31 supply bytes 0-63 and lanes 32-63 bytes
+// 64-127 of their row; A and B operands use the same assignment, so each
+// chunk is summed exactly once.  Partial sums of a chunk are formed in FP32
+// and, for FP8, multiplied by the product of the two operand scales before
+// they are added to the running sum.  The TN running sum is FP64 (as the
+// VALU kernels do over 32-row chunks).
 #include "kernels.hpp"
 
 namespace bk {
+namespace {
 
-void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done) {
-  (void)a;
-  (void)s;
-  *done = false;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+
+constexpr int LDS_ROW = 36;  // 32-bit words per staged row: 128 bytes + 16 pad
+
+template <typename T>
+struct Mf;
+template <>
+struct Mf<float> {
+  static constexpr int KC = 32;     // values per 128-byte chunk
+  static constexpr int STEPS = 16;  // MFMA steps per chunk
+  static constexpr int LW = 1;      // 32-bit words per lane and step
+};
+template <>
+struct Mf<bf16_t> {
+  static constexpr int KC = 64;
+  static constexpr int STEPS = 4;
+  static constexpr int LW = 4;
+};
+template <>
+struct Mf<fp8_t> {
+  static constexpr int KC = 128;
+  static constexpr int STEPS = 8;
+  static constexpr int LW = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ f32x16 mfma_step(const uint32_t* a, const uint32_t* b, f32x16 c);
+template <>
+__device__ __forceinline__ f32x16 mfma_step<float>(const uint32_t* a, const uint32_t* b,
+                                                   f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a[0]), __uint_as_float(b[0]), c,
+                                              0, 0, 0);
+}
+template <>
+__device__ __forceinline__ f32x16 mfma_step<bf16_t>(const uint32_t* a, const uint32_t* b,
+                                                    f32x16 c) {
+  const uint4 ua = make_uint4(a[0], a[1], a[2], a[3]);
+  const uint4 ub = make_uint4(b[0], b[1], b[2], b[3]);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ua),
+                                                 __builtin_bit_cast(bf16x8, ub), c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ f32x16 mfma_step<fp8_t>(const uint32_t* a, const uint32_t* b,
+                                                   f32x16 c) {
+  const long la = static_cast<long>(static_cast<uint64_t>(a[0]) | (static_cast<uint64_t>(a[1]) << 32));
+  const long lb = static_cast<long>(static_cast<uint64_t>(b[0]) | (static_cast<uint64_t>(b[1]) << 32));
+  return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(la, lb, c, 0, 0, 0);
 }
 
-void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, bool* done) {
-  (void)a;
-  (void)s;
+// LDS words of the lane's operand for step q: row `row` of a staged tile.
+template <typename T>
+__device__ __forceinline__ void lds_operand(const uint32_t* tile, int row, int h, int q,
+                                            uint32_t* out) {
+  const uint32_t* p = tile + row * LDS_ROW + 16 * h + q * Mf<T>::LW;
+  if constexpr (Mf<T>::LW == 4) {
+    const uint4 v = *reinterpret_cast<const uint4*>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
+  } else if constexpr (Mf<T>::LW == 2) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    out[0] = v.x;
+    out[1] = v.y;
+  } else {
+    out[0] = p[0];
+  }
+}
+
+// Output element (row, col) of a 32 x 32 tile held by lane `lane` in
+// accumulator register v.
+__device__ __forceinline__ int out_row(int lane, int v) {
+  return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+}
+
+// ------------------------------------------------------------------ NN --
+// Workgroup: 128 rows of C x 128 columns (4 wavefronts of 32 rows); the
+// rows of A go straight from memory into the operand registers (the next
+// chunk in flight while the current one is multiplied), the packed X^T
+// chunk (128 columns x 128 bytes) is staged in LDS, double-buffered.
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
+    int64_t n, int64_t K, int N, const T* __restrict__ A, int64_t lda,
+    const float* __restrict__ ascale, int64_t ascale_ld, const T* __restrict__ Xt,
+    int64_t ldxt, const float* __restrict__ xscale, float* __restrict__ C, int64_t ldc) {
+  constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
+  __shared__ uint32_t Bs[2][128 * LDS_ROW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 128;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.y) * 128;
+  const int nt = static_cast<int>((N - col0 + 31) / 32 < 4 ? (N - col0 + 31) / 32 : 4);
+  const int64_t row = row0 + 32 * w + r32;
+  const uint4* arow = reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h;
+  const int bc = t >> 1, bh = t & 1;  // staging: packed column bc, half bh
+  const bool bload = bc < 32 * nt;
+  const uint4* xrow =
+      reinterpret_cast<const uint4*>(Xt + (col0 + (bload ? bc : 0)) * ldxt) + 4 * bh;
+  const int64_t nch = K / KC;
+  f32x16 acc[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x16{};
+  uint4 acur[4], anxt[4], bst[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    acur[i] = arow[i];
+    bst[i] = bload ? xrow[i] : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    *reinterpret_cast<uint4*>(&Bs[0][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
+  __syncthreads();
+  for (int64_t c = 0; c < nch; ++c) {
+    const bool more = c + 1 < nch;
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        anxt[i] = arow[(c + 1) * 8 + i];
+        bst[i] = bload ? xrow[(c + 1) * 8 + i] : make_uint4(0, 0, 0, 0);
+      }
+    }
+    uint32_t aw[16];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      aw[4 * i] = acur[i].x;
+      aw[4 * i + 1] = acur[i].y;
+      aw[4 * i + 2] = acur[i].z;
+      aw[4 * i + 3] = acur[i].w;
+    }
+    const uint32_t* tile = Bs[c & 1];
+    f32x16 tmp[4];
+    if (SCALED) {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
+    }
+#pragma unroll
+    for (int q = 0; q < STEPS; ++q) {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        if (tt < nt) {
+          uint32_t bw[LW];
+          lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
+          if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
+          else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
+        }
+      }
+    }
+    if (SCALED) {
+      // 32-row groups never straddle a 128-row scale tile; chunk c is
+      // scale column c
+      const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c] * xscale[c];
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) acc[tt] += sc * tmp[tt];
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        acur[i] = anxt[i];
+        *reinterpret_cast<uint4*>(&Bs[(c + 1) & 1][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const int64_t gc = col0 + 32 * tt + r32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gr = row0 + 32 * w + out_row(lane, v);
+      if (gr < n && gc < N) C[gr * ldc + gc] = acc[tt][v];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ TN --
+// Transposing load of one chunk (KC rows x 128 columns) of a row-major
+// L x cols matrix into the staged layout [column][128 bytes of rows]; rows
+// at or beyond `le` read as zero, columns beyond `cols` are clamped (they
+// only feed outputs that are not stored).
+template <typename T>
+struct TLoad;
+template <>
+struct TLoad<float> {  // thread: 4 rows x 4 columns (16 bytes per row)
+  uint4 v[4];
+  __device__ void load(const float* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
+                       int64_t cols, int t) {
+    const int cg = t & 31, rg = t >> 5;
+    int64_t c = c0 + 4 * cg;
+    if (c + 4 > cols) c = cols - 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t l = l0 + 4 * rg + i;
+      v[i] = (l < le) ? *reinterpret_cast<const uint4*>(X + l * ldx + c) : make_uint4(0, 0, 0, 0);
+    }
+  }
+  __device__ void store(uint32_t* tile, int t) const {
+    const int cg = t & 31, rg = t >> 5;
+    const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w},
+                              {v[1].x, v[1].y, v[1].z, v[1].w},
+                              {v[2].x, v[2].y, v[2].z, v[2].w},
+                              {v[3].x, v[3].y, v[3].z, v[3].w}};
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      *reinterpret_cast<uint4*>(&tile[(4 * cg + e) * LDS_ROW + 4 * rg]) =
+          make_uint4(w[0][e], w[1][e], w[2][e], w[3][e]);
+  }
+};
+template <>
+struct TLoad<bf16_t> {  // thread: 4 rows x 8 columns
+  uint4 v[4];
+  __device__ void load(const bf16_t* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
+                       int64_t cols, int t) {
+    const int cg = t & 15, rg = t >> 4;
+    int64_t c = c0 + 8 * cg;
+    if (c + 8 > cols) c = cols - 8;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t l = l0 + 4 * rg + i;
+      v[i] = (l < le) ? *reinterpret_cast<const uint4*>(X + l * ldx + c) : make_uint4(0, 0, 0, 0);
+    }
+  }
+  __device__ void store(uint32_t* tile, int t) const {
+    const int cg = t & 15, rg = t >> 4;
+    uint32_t w[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      w[i][0] = v[i].x;
+      w[i][1] = v[i].y;
+      w[i][2] = v[i].z;
+      w[i][3] = v[i].w;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int sh = (e & 1) * 16;
+      uint32_t h16[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) h16[i] = (w[i][e >> 1] >> sh) & 0xFFFFu;
+      *reinterpret_cast<uint2*>(&tile[(8 * cg + e) * LDS_ROW + 2 * rg]) =
+          make_uint2(h16[0] | (h16[1] << 16), h16[2] | (h16[3] << 16));
+    }
+  }
+};
+template <>
+struct TLoad<fp8_t> {  // thread: 8 rows x 8 columns
+  uint2 v[8];
+  __device__ void load(const fp8_t* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
+                       int64_t cols, int t) {
+    const int cg = t & 15, rg = t >> 4;
+    int64_t c = c0 + 8 * cg;
+    if (c + 8 > cols) c = cols - 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t l = l0 + 8 * rg + i;
+      v[i] = (l < le) ? *reinterpret_cast<const uint2*>(X + l * ldx + c) : make_uint2(0, 0);
+    }
+  }
+  __device__ void store(uint32_t* tile, int t) const {
+    const int cg = t & 15, rg = t >> 4;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int sh = (e & 3) * 8;
+      uint32_t b[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) b[i] = (((e < 4) ? v[i].x : v[i].y) >> sh) & 0xFFu;
+      *reinterpret_cast<uint2*>(&tile[(8 * cg + e) * LDS_ROW + 2 * rg]) =
+          make_uint2(b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24),
+                     b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24));
+    }
+  }
+};
+
+// Direct load of one chunk of a packed operand (rows of 128 bytes along the
+// reduction): thread t stages half bh of row bc.
+struct PLoad {
+  uint4 v[4];
+  __device__ void load(const uint4* rowp, bool ok, int64_t chunk) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = ok ? rowp[chunk * 8 + i] : make_uint4(0, 0, 0, 0);
+  }
+  __device__ void store(uint32_t* tile, int bc, int bh) const {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<uint4*>(&tile[bc * LDS_ROW + 16 * bh + 4 * i]) = v[i];
+  }
+};
+
+// Workgroup: 128 columns of X (4 wavefronts of 32) x up to 128 columns of Y,
+// rows [s Ls, (s+1) Ls) of split s = blockIdx.z.  Y is either raw FP32
+// (row-major L x r, transposing load; T = float only) or packed
+// (r_pad x L_pad in T, zero padded, with FP8 scales per 128 rows).
+template <typename T, bool SCALED, bool PACKED_Y>
+__global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
+    int64_t L, int64_t p, int r, const T* __restrict__ X, int64_t ldx,
+    const float* __restrict__ xscale, int64_t xscale_ld, const float* __restrict__ Yraw,
+    int64_t ldy, const T* __restrict__ Yt, int64_t ldyt, const float* __restrict__ yscale,
+    double* __restrict__ partial, int64_t Ls) {
+  constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
+  __shared__ uint32_t As[2][128 * LDS_ROW];
+  __shared__ uint32_t Bs[2][128 * LDS_ROW];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
+  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 128;
+  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 128;
+  const int64_t sidx = blockIdx.z;
+  const int64_t lb = sidx * Ls;
+  const int64_t le = (lb + Ls < L) ? lb + Ls : L;
+  const int nt = static_cast<int>((r - r0 + 31) / 32 < 4 ? (r - r0 + 31) / 32 : 4);
+  const int64_t nch = (le - lb + KC - 1) / KC;
+  double acc[4][16];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[tt][v] = 0.0;
+  TLoad<T> xa;
+  TLoad<float> ya;
+  PLoad yp;
+  const int bc = t >> 1, bh = t & 1;
+  const bool bload = bc < 32 * nt;
+  const uint4* yrow = nullptr;
+  if (PACKED_Y)
+    yrow = reinterpret_cast<const uint4*>(Yt + (r0 + (bload ? bc : 0)) * ldyt + lb) + 4 * bh;
+  auto load = [&](int64_t c) {
+    xa.load(X, ldx, lb + c * KC, le, p0, p, t);
+    if (PACKED_Y) yp.load(yrow, bload, c);
+    else ya.load(Yraw, ldy, lb + c * KC, le, r0, r, t);
+  };
+  auto store = [&](int buf) {
+    xa.store(As[buf], t);
+    if (PACKED_Y) yp.store(Bs[buf], bc, bh);
+    else ya.store(Bs[buf], t);
+  };
+  if (nch > 0) {
+    load(0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t c = 0; c < nch; ++c) {
+    const bool more = c + 1 < nch;
+    if (more) load(c + 1);
+    const uint32_t* at = As[c & 1];
+    const uint32_t* bt = Bs[c & 1];
+    double sc = 1.0;
+    if (SCALED) {
+      const int64_t lt = (lb + c * KC) >> 7;  // 128-row scale tile of this chunk
+      sc = static_cast<double>(xscale[lt * xscale_ld + (p0 >> 7)]) *
+           static_cast<double>(yscale[lt]);
+    }
+    // chunk sums two output tiles at a time (fewer live FP32 registers)
+#pragma unroll
+    for (int pr = 0; pr < 2; ++pr) {
+      if (2 * pr < nt) {
+        f32x16 tmp[2] = {f32x16{}, f32x16{}};
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+          uint32_t aw[LW];
+          lds_operand<T>(at, 32 * w + r32, h, q, aw);
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (2 * pr + u < nt) {
+              uint32_t bw[LW];
+              lds_operand<T>(bt, 32 * (2 * pr + u) + r32, h, q, bw);
+              tmp[u] = mfma_step<T>(aw, bw, tmp[u]);
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int v = 0; v < 16; ++v)
+            acc[2 * pr + u][v] += sc * static_cast<double>(tmp[u][v]);
+      }
+    }
+    if (more) store((c + 1) & 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const int64_t gc = r0 + 32 * tt + r32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gp = p0 + 32 * w + out_row(lane, v);
+      if (gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = acc[tt][v];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- pack --
+// Dst (cols_pad x rows_pad, T, ld rows_pad) = Src^T for Src rows x cols
+// FP32 (ld lds), zero padded; FP8: one scale per 128 source rows,
+// s = amax / 448 over those rows and all columns, values e4m3(x / s).
+template <typename T>
+__device__ __forceinline__ T to_elem(float x, float inv_unused);
+template <>
+__device__ __forceinline__ float to_elem<float>(float x, float) { return x; }
+template <>
+__device__ __forceinline__ bf16_t to_elem<bf16_t>(float x, float) { return f32_to_bf16(x); }
+
+template <typename T>
+__global__ __launch_bounds__(256) void pack_t_kernel(const float* __restrict__ src, int64_t lds,
+                                                     int64_t rows, int64_t cols,
+                                                     T* __restrict__ dst, int64_t rows_pad,
+                                                     int64_t cols_pad, float* __restrict__ scales) {
+  __shared__ float tile[128][33];
+  __shared__ float red[256];
+  const int t = threadIdx.x;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * 128;
+  float sc = 1.0f;
+  if constexpr (sizeof(T) == 1) {
+    float am = 0.0f;
+    for (int64_t i = t; i < 128 * cols; i += 256) {
+      const int64_t rr = rb + i / cols, cc = i % cols;
+      if (rr < rows) am = fmaxf(am, fabsf(src[rr * lds + cc]));
+    }
+    red[t] = am;
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+      if (t < s2) red[t] = fmaxf(red[t], red[t + s2]);
+      __syncthreads();
+    }
+    sc = red[0] > 0.0f ? __fdiv_rn(red[0], 448.0f) : 1.0f;
+    if (t == 0) scales[blockIdx.x] = sc;
+  }
+  for (int64_t c0 = 0; c0 < cols_pad; c0 += 32) {
+    // load 128 rows x 32 columns (coalesced along columns)
+    for (int i = t; i < 128 * 32; i += 256) {
+      const int rr = i >> 5, cc = i & 31;
+      const int64_t gr = rb + rr, gc = c0 + cc;
+      tile[rr][cc] = (gr < rows && gc < cols) ? src[gr * lds + gc] : 0.0f;
+    }
+    __syncthreads();
+    // write 32 destination rows of 128 values (coalesced along rows)
+    for (int i = t; i < 128 * 32; i += 256) {
+      const int cc = i >> 7, rr = i & 127;
+      const float x = tile[rr][cc];
+      T y;
+      if constexpr (sizeof(T) == 1) y = f32_to_e4m3(__fdiv_rn(x, sc));
+      else y = to_elem<T>(x, 0.0f);
+      dst[(c0 + cc) * rows_pad + rb + rr] = y;
+    }
+    __syncthreads();
+  }
+}
+
+int esize(int type) { return type == BK_F32 ? 4 : (type == BK_BF16 ? 2 : 1); }
+int chunk_vals(int type) { return 128 / esize(type); }
+
+}  // namespace
+
+int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type) {
+  const int64_t lp = align_up(static_cast<size_t>(lred), 128);
+  const int64_t cp = align_up(static_cast<size_t>(cols), 32);
+  return static_cast<int64_t>(align_up(static_cast<size_t>(cp * lp * esize(type)), 256)) +
+         (lp / 128) * 4 + 256;
+}
+
+int tn_mfma_splits(int64_t L, int64_t p, int r) {
+  const int64_t tiles = cdiv(p, 128) * cdiv(r, 128);
+  int64_t S = cdiv(512, tiles);
+  const int64_t smax = std::max<int64_t>(1, cdiv(L, 128));
+  if (S > smax) S = smax;
+  if (S > 64) S = 64;
+  if (S < 1) S = 1;
+  const int64_t Ls = align_up(static_cast<size_t>(cdiv(L, S)), 128);
+  return static_cast<int>(cdiv(L, Ls));
+}
+
+// Packs Y (L x cols FP32) for a TN product or X^T for an NN product.
+template <typename T>
+static void pack_t(const float* src, int64_t lds, int64_t rows, int64_t cols, void* work,
+                   int64_t* rows_pad, int64_t* cols_pad, float** scales, hipStream_t s) {
+  *rows_pad = align_up(static_cast<size_t>(rows), 128);
+  *cols_pad = align_up(static_cast<size_t>(cols), 32);
+  T* dst = static_cast<T*>(work);
+  const size_t body = align_up(static_cast<size_t>(*rows_pad * *cols_pad) * sizeof(T), 256);
+  *scales = reinterpret_cast<float*>(static_cast<char*>(work) + body);
+  pack_t_kernel<T><<<static_cast<unsigned>(*rows_pad / 128), 256, 0, s>>>(
+      src, lds, rows, cols, dst, *rows_pad, *cols_pad, *scales);
+}
+
+template <typename T, bool SCALED>
+static void nn_run(const NNArgs& a, hipStream_t s) {
+  int64_t kp = 0, np = 0;
+  float* xs = nullptr;
+  pack_t<T>(static_cast<const float*>(a.X), a.ldx, a.K, a.N, a.work, &kp, &np, &xs, s);
+  const dim3 grid(static_cast<unsigned>(cdiv(a.n, 128)), static_cast<unsigned>(cdiv(a.N, 128)));
+  nn_mfma_kernel<T, SCALED><<<grid, 256, 0, s>>>(
+      a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,
+      static_cast<const T*>(a.work), kp, xs, static_cast<float*>(a.C), a.ldc);
+}
+
+void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done) {
   *done = false;
+  if (!a.work || a.x_f64 || a.c_f64 || a.alpha != 1.0 || a.beta != 0.0) return;
+  if (a.a_type != BK_F32 && a.a_type != BK_BF16 && a.a_type != BK_FP8_E4M3) return;
+  const int es = esize(a.a_type);
+  if (a.K <= 0 || a.K % chunk_vals(a.a_type) != 0 || (a.lda * es) % 16 != 0 ||
+      (reinterpret_cast<uintptr_t>(a.A) & 15) != 0)
+    return;
+  if (a.a_type == BK_FP8_E4M3 && !a.ascale) return;
+  if (static_cast<int64_t>(a.work_bytes) < mfma_pack_bytes(a.K, a.N, a.a_type)) return;
+  // only products large enough to pay for the packing launch
+  if (2.0 * static_cast<double>(a.n) * static_cast<double>(a.K) * a.N < 1e8) return;
+  switch (a.a_type) {
+    case BK_F32:
+      nn_run<float, false>(a, s);
+      break;
+    case BK_BF16:
+      nn_run<bf16_t, false>(a, s);
+      break;
+    default:
+      nn_run<fp8_t, true>(a, s);
+      break;
+  }
+  *done = true;
+}
+
+template <typename T, bool SCALED, bool PACKED>
+static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
+  const T* Yt = nullptr;
+  float* ys = nullptr;
+  int64_t lp = 0, rp = 0;
+  if (PACKED) {
+    pack_t<T>(static_cast<const float*>(a.Y), a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
+    Yt = static_cast<const T*>(a.work);
+  }
+  const dim3 grid(static_cast<unsigned>(cdiv(a.p, 128)), static_cast<unsigned>(cdiv(a.r, 128)),
+                  static_cast<unsigned>(S));
+  tn_mfma_kernel<T, SCALED, PACKED><<<grid, 256, 0, s>>>(
+      a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,
+      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls);
+}
+
+void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
+  *splits = 0;
+  if (a.y_f64 || a.L <= 0) return;
+  if (a.x_type != BK_F32 && a.x_type != BK_BF16 && a.x_type != BK_FP8_E4M3) return;
+  const int es = esize(a.x_type);
+  const int vec = 16 / es;  // values per 16-byte load of X
+  if (a.p < vec || a.p % vec != 0 || (a.ldx * es) % 16 != 0 ||
+      (reinterpret_cast<uintptr_t>(a.X) & 15) != 0)
+    return;
+  if (a.r < 8) return;
+  if (2.0 * static_cast<double>(a.L) * static_cast<double>(a.p) * a.r < 1e9) return;
+  const bool packed = a.x_type != BK_F32;
+  if (packed) {
+    if (!a.work || static_cast<int64_t>(a.work_bytes) < mfma_pack_bytes(a.L, a.r, a.x_type)) return;
+    if (a.x_type == BK_FP8_E4M3 && !a.xscale) return;
+  } else if (a.r % 4 != 0 || a.ldy % 4 != 0 || (reinterpret_cast<uintptr_t>(a.Y) & 15) != 0) {
+    return;
+  }
+  const int S = tn_mfma_splits(a.L, a.p, a.r);
+  const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
+  switch (a.x_type) {
+    case BK_F32:
+      tn_run<float, false, false>(a, S, Ls, s);
+      break;
+    case BK_BF16:
+      tn_run<bf16_t, false, true>(a, S, Ls, s);
+      break;
+    default:
+      tn_run<fp8_t, true, true>(a, S, Ls, s);
+      break;
+  }
+  *splits = S;
 }
 
 }  // namespace bk

@@ -32,8 +32,12 @@ struct NNArgs {
   int64_t ldc = 0;
   bool c_f64 = false;
   double alpha = 1.0, beta = 0.0;
+  // scratch for the matrix-core path (X^T packed in A's type), nullable
+  void* work = nullptr;
+  size_t work_bytes = 0;
 };
-void launch_nn(const NNArgs& a, hipStream_t s);
+// returns the number of kernels launched
+int launch_nn(const NNArgs& a, hipStream_t s);
 
 // C (p x r, ldc) = alpha * X^T . Y + beta * C with X L x p (ldx), Y L x r
 // (ldy): the reduction over the long L is split into S chunks whose FP64
@@ -55,10 +59,23 @@ struct TNArgs {
   bool c_f64 = true;
   double alpha = 1.0, beta = 0.0;
   double* partial = nullptr;  // >= tn_partial_elems(L, p, r) doubles
+  // scratch for the matrix-core path (Y^T packed in X's type), nullable
+  void* work = nullptr;
+  size_t work_bytes = 0;
 };
 int tn_splits(int64_t L, int64_t p, int r);
 int64_t tn_partial_elems(int64_t L, int64_t p, int r);
-void launch_tn(const TNArgs& a, hipStream_t s);
+int launch_tn(const TNArgs& a, hipStream_t s);  // kernels launched
+
+// Matrix-core paths (gemm_mfma.hip): taken for FP32 / BF16 / FP8 operands
+// of aligned, large enough products; otherwise the VALU kernels run.
+// Bytes of scratch to pack an lred x cols FP32 operand in `type`.
+int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type);
+int tn_mfma_splits(int64_t L, int64_t p, int r);
+// *done: the product ran on matrix cores (2 launches: pack, product)
+void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done);
+// *splits = number of FP64 partials written (0: not handled)
+void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits);
 
 // ---------------------------------------------------------------- small --
 // Fill / convert helpers.

@@ -16,9 +16,8 @@ namespace bk {
 namespace {
 
 constexpr int TRI_THREADS = 1024;
-constexpr int TRI_WAVES = TRI_THREADS / 64;
-constexpr int64_t TRI_LDS_DOUBLES = 150 * 1024 / 8;  // dynamic LDS of the reduction
-constexpr int TRI_VR = 16;                           // back-transformation: m <= 64 * TRI_VR
+constexpr int TRI_LDS_BLOCK = 120;  // trailing blocks up to this order live in LDS
+constexpr int TRI_VR = 16;          // back-transformation: m <= 64 * TRI_VR
 
 __device__ double block_sum_1024(double v, double* red) {
   const int t = threadIdx.x;
@@ -27,86 +26,58 @@ __device__ double block_sum_1024(double v, double* red) {
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   double s = 0.0;
-  for (int w = 0; w < TRI_WAVES; ++w) s += red[w];
+  for (int w = 0; w < TRI_THREADS / 64; ++w) s += red[w];
   __syncthreads();
   return s;
 }
 
-__device__ __forceinline__ int64_t tri_off(int64_t r) { return r * (r + 1) / 2; }
-
-__device__ __forceinline__ double readlane_f64(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// Householder tridiagonalisation of the symmetric A (m x m, ld m;
-// m <= TRI_THREADS).  Outputs: reflector j (rows j+1..m-1) in column j of Vh
+// A (m x m, ld m, a symmetric copy of M, m <= TRI_THREADS) is reduced in
+// place.  Outputs: reflector j (rows j+1..m-1) in column j of Vh
 // (column-major, ld m), beta[j], diagonal dg[0..m), off-diagonal eo[0..m-1).
-//
-// Step j forms the reflector (v, beta) of column j, p = beta A' v and
-// w = p - (beta v^T p / 2) v for the trailing block A', whose update
-// A' -= v w^T + w v^T is left pending: step j+1 applies it to each element
-// as it reads it for its own product and writes the element back once.
-// Threads own columns of A' (RG groups of rows, added in group order), and
-// the rows of a group sit in registers of the wavefront (lane u: row
-// R0 + u) from where v_i, and the pending v_i, w_i, are broadcast.
-// While A' is in global memory both triangles are kept and a column is
-// read top to bottom.  Once its order is <= sb its lower triangle moves to
-// LDS, packed by rows: a thread then reads row l left of the diagonal
-// (pass A, read only) and, after a barrier, column l from the diagonal down
-// (pass B, written back).
+// The symmetric product and the rank-2 update run with threads owning
+// columns of the trailing block (coalesced rows) and RG groups of rows whose
+// partial sums are added in group order.
 __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
-    double* __restrict__ A, int64_t m, int64_t sb, double* __restrict__ Vh,
+    double* __restrict__ A, int64_t m, double* __restrict__ Vh,
     double* __restrict__ beta, double* __restrict__ dg, double* __restrict__ eo) {
-  extern __shared__ double sm[];
-  __shared__ double red[TRI_WAVES];
+  extern __shared__ double sm[];  // v, p, w: 3 m doubles; then the LDS block
+  __shared__ double red[TRI_THREADS / 64];
   __shared__ double part[TRI_THREADS];
-  __shared__ double s_beta, s_diag;
-  double* v = sm;           // reflector of this step (absolute row index)
-  double* vp = sm + m;      // pending update of the previous step: v, w
-  double* wp = sm + 2 * m;
-  double* pv = sm + 3 * m;  // p
-  double* P = sm + 4 * m;   // packed lower triangle of the trailing block
+  __shared__ double s_beta;
+  double* v = sm;
+  double* p = sm + m;
+  double* w = sm + 2 * m;
+  double* blk = sm + 3 * m;  // TRI_LDS_BLOCK^2 doubles
   const int t = threadIdx.x;
-  const int lane = t & 63, wave = t >> 6;
-  for (int64_t i = t; i < m; i += TRI_THREADS) {
-    v[i] = 0.0;
-    vp[i] = 0.0;
-    wp[i] = 0.0;
-    pv[i] = 0.0;
-  }
-  bool inlds = false, pend = false;
-  int64_t o = 0;
-  __syncthreads();
+  // Element (i, l) of the trailing matrix lives at base[(i - off) ld + l - off]:
+  // in A (global, off 0) until it fits in LDS, then in blk.
+  double* base = A;
+  int64_t ld = m, off = 0;
   for (int64_t j = 0; j + 2 < m; ++j) {
     const int64_t j1 = j + 1;
     const int s = static_cast<int>(m - j1);
-    if (!inlds && m - j <= sb) {
-      for (int64_t r = wave; r < m - j; r += TRI_WAVES)
-        for (int64_t c = lane; c <= r; c += 64) P[tri_off(r) + c] = A[(j + r) * m + j + c];
-      inlds = true;
-      o = j;
-      __syncthreads();
-    }
-    // column j of the current matrix: stored value minus the pending update
-    double nrm2 = 0.0;
-    {
-      const double vpj = vp[j], wpj = wp[j];
-      for (int64_t i = j + t; i < m; i += TRI_THREADS) {
-        const double e = inlds ? P[tri_off(i - o) + (j - o)] : A[i * m + j];
-        const double x = e - vp[i] * wpj - wp[i] * vpj;
-        if (i == j) {
-          s_diag = x;
-        } else {
-          v[i] = x;
-          nrm2 += x * x;
-        }
+    if (base == A && m - j <= TRI_LDS_BLOCK) {
+      const int64_t sb = m - j;
+      for (int64_t idx = t; idx < sb * sb; idx += TRI_THREADS) {
+        const int64_t r = idx / sb, c = idx - r * sb;
+        blk[idx] = A[(j + r) * m + j + c];
       }
+      __syncthreads();
+      base = blk;
+      ld = sb;
+      off = j;
+    }
+    double* rowj = base + (j - off) * ld + (j1 - off);
+    // x = column j below the diagonal = row j right of it (symmetric)
+    double nrm2 = 0.0;
+    for (int i = t; i < s; i += TRI_THREADS) {
+      const double x = rowj[i];
+      v[i] = x;
+      nrm2 += x * x;
     }
     nrm2 = block_sum_1024(nrm2, red);
     if (t == 0) {
-      const double x0 = v[j1];
+      const double x0 = v[0];
       const double nx = sqrt(nrm2);
       double b = 0.0, alpha = x0;
       if (nx > 0.0 && nrm2 - x0 * x0 > 0.0) {
@@ -114,160 +85,77 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
         const double v0 = x0 - alpha;
         const double vtv = nrm2 - x0 * x0 + v0 * v0;
         b = vtv > 0.0 ? 2.0 / vtv : 0.0;
-        v[j1] = v0;
+        v[0] = v0;
       }
       s_beta = b;
-      dg[j] = s_diag;
+      dg[j] = base[(j - off) * ld + (j - off)];
       eo[j] = alpha;
       beta[j] = b;
     }
     __syncthreads();
     const double b = s_beta;
-    for (int64_t i = j1 + t; i < m; i += TRI_THREADS) {
-      Vh[j * m + i] = v[i];
-      if (b == 0.0) v[i] = 0.0;  // identity reflector: no product
-    }
-    if (b == 0.0 && !pend) {  // nothing to apply, nothing to form (uniform)
+    for (int i = t; i < s; i += TRI_THREADS) Vh[j * m + j1 + i] = v[i];
+    if (b == 0.0) {  // column already reduced (uniform branch)
       __syncthreads();
       continue;
     }
-    __syncthreads();
     const int RG = (s <= TRI_THREADS / 4) ? 4 : ((s <= TRI_THREADS / 2) ? 2 : 1);
     const int CW = TRI_THREADS / RG;
     const int grp = t / CW, tc = t - grp * CW;
     const int rlen = (s + RG - 1) / RG;
-    const int64_t R0 = j1 + static_cast<int64_t>(grp) * rlen;
-    const int64_t R1 = (R0 + rlen < m) ? R0 + rlen : m;
-    const int64_t l = j1 + tc;
-    const bool colok = tc < s;
-    const double vpl = colok ? vp[l] : 0.0, wpl = colok ? wp[l] : 0.0;
-    const int64_t lw = j1 + (tc - lane);  // first column of this wavefront
+    const int r0 = grp * rlen;
+    const int r1 = (r0 + rlen < s) ? r0 + rlen : s;
+    // p = b M' v, p_l = sum_i M'[i][l] v_i
     double acc = 0.0;
-    for (int64_t c0 = R0; c0 < R1; c0 += 64) {  // chunks of 64 rows
-      const int64_t ir = c0 + lane;
-      const double qv = ir < R1 ? v[ir] : 0.0;
-      const double qvp = ir < R1 ? vp[ir] : 0.0;
-      const double qwp = ir < R1 ? wp[ir] : 0.0;
-      const int cn = __builtin_amdgcn_readfirstlane(
-          static_cast<int>((R1 - c0 < 64) ? R1 - c0 : 64));
-      if (!inlds) {
-        // whole column l (both triangles stored), written back; eight
-        // loads in flight
-        double* e = A + c0 * m + l;
-        int u = 0;
-        for (; u + 8 <= cn; u += 8, e += 8 * m) {
-          double ev[8];
+    if (tc < s) {
+      const double* col = base + (j1 + r0 - off) * ld + (j1 - off) + tc;
+      int i = r0;
+      // eight independent loads in flight per thread
+      for (; i + 8 <= r1; i += 8, col += 8 * ld) {
+        double a[8];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) ev[q] = colok ? e[q * m] : 0.0;
+        for (int u = 0; u < 8; ++u) a[u] = col[u * ld];
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const double nv = ev[q] - readlane_f64(qvp, u + q) * wpl - readlane_f64(qwp, u + q) * vpl;
-            if (colok && pend) e[q * m] = nv;
-            acc += nv * readlane_f64(qv, u + q);
-          }
-        }
-        for (; u < cn; ++u, e += m) {
-          const double ev = colok ? *e : 0.0;
-          const double nv = ev - readlane_f64(qvp, u) * wpl - readlane_f64(qwp, u) * vpl;
-          if (colok && pend) *e = nv;
-          acc += nv * readlane_f64(qv, u);
-        }
-      } else {
-        // pass A: row l left of the diagonal, i < l (read only)
-        const int ua = __builtin_amdgcn_readfirstlane(static_cast<int>(
-            (lw + 63 - c0 < cn) ? ((lw + 63 - c0 > 0) ? lw + 63 - c0 : 0) : cn));
-        const double* ra = P + tri_off(l - o) + (c0 - o);
-        int u = 0;
-        for (; u + 8 <= ua; u += 8) {
-          double ev[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) ev[q] = (colok && c0 + u + q < l) ? ra[u + q] : 0.0;
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            acc += (ev[q] - vpl * readlane_f64(qwp, u + q) - wpl * readlane_f64(qvp, u + q)) *
-                   ((c0 + u + q < l) ? readlane_f64(qv, u + q) : 0.0);
-        }
-        for (; u < ua; ++u) {
-          if (colok && c0 + u < l)
-            acc += (ra[u] - vpl * readlane_f64(qwp, u) - wpl * readlane_f64(qvp, u)) *
-                   readlane_f64(qv, u);
-        }
+        for (int u = 0; u < 8; ++u) acc += a[u] * v[i + u];
       }
-    }
-    if (inlds) {
-      __syncthreads();  // every pass-A read before any pass-B write
-      for (int64_t c0 = R0; c0 < R1; c0 += 64) {
-        const int64_t ir = c0 + lane;
-        const double qv = ir < R1 ? v[ir] : 0.0;
-        const double qvp = ir < R1 ? vp[ir] : 0.0;
-        const double qwp = ir < R1 ? wp[ir] : 0.0;
-        const int cn = __builtin_amdgcn_readfirstlane(
-            static_cast<int>((R1 - c0 < 64) ? R1 - c0 : 64));
-        // pass B: column l from the diagonal down, i >= l, written back
-        const int ub = __builtin_amdgcn_readfirstlane(
-            static_cast<int>((lw > c0) ? ((lw - c0 < cn) ? lw - c0 : cn) : 0));
-        int64_t r = c0 + ub - o;
-        double* e = P + tri_off(r) + (l - o);
-        int u = ub;
-        for (; u + 8 <= cn; u += 8) {
-          double* ep[8];
-          double ev[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            ep[q] = e;
-            ++r;
-            e += r;  // next packed row: offset grows by the row length
-          }
-#pragma unroll
-          for (int q = 0; q < 8; ++q) ev[q] = (colok && c0 + u + q >= l) ? *ep[q] : 0.0;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const double nv = ev[q] - readlane_f64(qvp, u + q) * wpl - readlane_f64(qwp, u + q) * vpl;
-            if (colok && c0 + u + q >= l) {
-              if (pend) *ep[q] = nv;
-              acc += nv * readlane_f64(qv, u + q);
-            }
-          }
-        }
-        for (; u < cn; ++u) {
-          if (colok && c0 + u >= l) {
-            const double nv = *e - readlane_f64(qvp, u) * wpl - readlane_f64(qwp, u) * vpl;
-            if (pend) *e = nv;
-            acc += nv * readlane_f64(qv, u);
-          }
-          ++r;
-          e += r;
-        }
-      }
+      for (; i < r1; ++i, col += ld) acc += *col * v[i];
     }
     part[t] = acc;
     __syncthreads();
     if (t < s) {
       double sum = 0.0;
       for (int g = 0; g < RG; ++g) sum += part[g * CW + t];
-      pv[j1 + t] = b * sum;
+      p[t] = b * sum;
     }
     __syncthreads();
-    double vtp = 0.0;
-    for (int64_t i = j1 + t; i < m; i += TRI_THREADS) vtp += v[i] * pv[i];
-    vtp = block_sum_1024(vtp, red);
-    const double K = 0.5 * b * vtp;
-    for (int64_t i = j1 + t; i < m; i += TRI_THREADS) {
-      wp[i] = pv[i] - K * v[i];
-      vp[i] = v[i];
+    double vp = 0.0;
+    for (int i = t; i < s; i += TRI_THREADS) vp += v[i] * p[i];
+    vp = block_sum_1024(vp, red);
+    const double K = 0.5 * b * vp;
+    for (int i = t; i < s; i += TRI_THREADS) w[i] = p[i] - K * v[i];
+    __syncthreads();
+    // M' -= v w^T + w v^T
+    if (tc < s) {
+      const double vl = v[tc], wl = w[tc];
+      double* col = base + (j1 + r0 - off) * ld + (j1 - off) + tc;
+      int i = r0;
+      for (; i + 8 <= r1; i += 8, col += 8 * ld) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = col[u * ld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) col[u * ld] = a[u] - (v[i + u] * wl + w[i + u] * vl);
+      }
+      for (; i < r1; ++i, col += ld) *col -= v[i] * wl + w[i] * vl;
     }
-    pend = b != 0.0;
     __syncthreads();
   }
   if (t == 0) {
-    auto el = [&](int64_t i, int64_t c) {  // i >= c
-      return inlds ? P[tri_off(i - o) + (c - o)] : A[i * m + c];
-    };
+    auto el = [&](int64_t i, int64_t l) { return base[(i - off) * ld + (l - off)]; };
     if (m >= 2) {
-      const int64_t a = m - 2, c = m - 1;
-      dg[a] = el(a, a) - 2.0 * vp[a] * wp[a];
-      dg[c] = el(c, c) - 2.0 * vp[c] * wp[c];
-      eo[a] = el(c, a) - vp[c] * wp[a] - wp[c] * vp[a];
+      dg[m - 2] = el(m - 2, m - 2);
+      dg[m - 1] = el(m - 1, m - 1);
+      eo[m - 2] = el(m - 1, m - 2);
     } else {
       dg[0] = A[0];
     }
@@ -572,11 +460,9 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   }
   sym_copy_kernel<<<static_cast<unsigned>(cdiv(m * m, 256)), 256, 0, s>>>(M, m, ldm, A);
   launch_fill_f64(Vh, m * m, 0.0, s);
-  // largest trailing order whose packed lower triangle fits beside 4 m doubles
-  int64_t sb = 0;
-  while (sb < m && 4 * m + (sb + 1) * (sb + 2) / 2 <= TRI_LDS_DOUBLES) ++sb;
-  const size_t lds = static_cast<size_t>(4 * m + sb * (sb + 1) / 2) * sizeof(double);
-  tridiag_reduce_kernel<<<1, TRI_THREADS, lds, s>>>(A, m, sb, Vh, beta, dg, eo);
+  const int64_t sb = m < TRI_LDS_BLOCK ? m : TRI_LDS_BLOCK;
+  tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + sb * sb) * sizeof(double), s>>>(A, m, Vh, beta,
+                                                                                  dg, eo);
   tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 2 * k) * sizeof(double), s>>>(dg, eo, m, k,
                                                                              theta, X, sol, piv);
   tridiag_back_kernel<<<static_cast<unsigned>(cdiv(k, 4)), 256, 0, s>>>(Vh, beta, m, k, X, Uk,
