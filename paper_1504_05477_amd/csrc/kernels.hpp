@@ -150,7 +150,7 @@ void launch_jacobi_finalize(const double* Xc, const double* Vc, int64_t ldc,
 // tridiagonalisation, multisection + inverse iteration, back-transformation
 // (tridiag.hip).  theta: k values descending; Uk m x k (ld ldu); ritz
 // (nullable) = sqrt(max(theta, 0)).  scratch: tridiag_scratch_doubles(m, k).
-constexpr int64_t kTridiagMax = 1024;
+constexpr int64_t kTridiagMax = 2560;
 int64_t tridiag_scratch_doubles(int64_t m, int k);
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k,
                          double* scratch, double* theta, double* Uk, int64_t ldu,

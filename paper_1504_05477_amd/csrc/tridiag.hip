@@ -17,7 +17,7 @@ namespace {
 
 constexpr int TRI_THREADS = 1024;
 constexpr int TRI_LDS_BLOCK = 120;  // trailing blocks up to this order live in LDS
-constexpr int TRI_VR = 16;          // back-transformation: m <= 64 * TRI_VR
+constexpr int TRI_SMALL = 512;      // one-workgroup reduction up to this order
 
 __device__ double block_sum_1024(double v, double* red) {
   const int t = threadIdx.x;
@@ -369,6 +369,7 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
 
 // U_k (m x k, row-major ld ldu) = H_0 ... H_{m-3} X, X column-major (ld m);
 // one wavefront per column, reflectors applied from the last to the first.
+template <int VR>
 __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restrict__ Vh,
                                                            const double* __restrict__ beta,
                                                            int64_t m, int k,
@@ -383,25 +384,25 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
   if (ritz && lane == 0) ritz[c] = sqrt(fmax(theta[c], 0.0));
   const double* x = X + static_cast<int64_t>(c) * m;
   // column in registers (row lane + 64 u); next reflector prefetched
-  double xr[TRI_VR], vc[TRI_VR], vn[TRI_VR];
+  double xr[VR], vc[VR], vn[VR];
 #pragma unroll
-  for (int u = 0; u < TRI_VR; ++u) {
+  for (int u = 0; u < VR; ++u) {
     const int64_t i = lane + 64 * u;
     xr[u] = i < m ? x[i] : 0.0;
   }
   int64_t j = m - 3;
 #pragma unroll
-  for (int u = 0; u < TRI_VR; ++u) {
+  for (int u = 0; u < VR; ++u) {
     const int64_t i = lane + 64 * u;
     vn[u] = (j >= 0 && i > j && i < m) ? Vh[j * m + i] : 0.0;
   }
   for (; j >= 0; --j) {
 #pragma unroll
-    for (int u = 0; u < TRI_VR; ++u) vc[u] = vn[u];
+    for (int u = 0; u < VR; ++u) vc[u] = vn[u];
     const double b = beta[j];
     if (j > 0) {
 #pragma unroll
-      for (int u = 0; u < TRI_VR; ++u) {
+      for (int u = 0; u < VR; ++u) {
         const int64_t i = lane + 64 * u;
         vn[u] = (i > j - 1 && i < m) ? Vh[(j - 1) * m + i] : 0.0;
       }
@@ -409,17 +410,142 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
     if (b == 0.0) continue;
     double dot = 0.0;
 #pragma unroll
-    for (int u = 0; u < TRI_VR; ++u) dot += vc[u] * xr[u];
+    for (int u = 0; u < VR; ++u) dot += vc[u] * xr[u];
     for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
     const double f = b * dot;
 #pragma unroll
-    for (int u = 0; u < TRI_VR; ++u) xr[u] -= f * vc[u];
+    for (int u = 0; u < VR; ++u) xr[u] -= f * vc[u];
   }
 #pragma unroll
-  for (int u = 0; u < TRI_VR; ++u) {
+  for (int u = 0; u < VR; ++u) {
     const int64_t i = lane + 64 * u;
     if (i < m) Uk[i * ldu + c] = xr[u];
   }
+}
+
+// ------------------------------------------------- large m (> TRI_SMALL) --
+// The same reduction with the trailing block in global memory and the work
+// of a step spread over the chip, in two launches per step:
+//   tribig_step_kernel (one workgroup): finishes step j-1 (p = beta A' v
+//     from the column partial sums, w = p - (beta v^T p / 2) v, which become
+//     the pending update) and forms reflector j from column j with that
+//     update applied (row j of the symmetric square, read contiguously);
+//   tribig_update_kernel (grid): applies the pending update to the trailing
+//     square (both triangles, a thread per column, 64-row groups) and
+//     writes the partial sums of A' v_j per row group, added in group order
+//     by the next step kernel.
+constexpr int TBG_ROWS = 64;
+constexpr int TBG_COLS = 256;
+
+__global__ __launch_bounds__(1024) void tribig_step_kernel(
+    double* __restrict__ A, int64_t m, int64_t j, double* __restrict__ v,
+    double* __restrict__ vp, double* __restrict__ wp, const double* __restrict__ part, int G,
+    double* __restrict__ Vh, double* __restrict__ beta, double* __restrict__ dg,
+    double* __restrict__ eo) {
+  extern __shared__ double p_s[];  // m
+  __shared__ double red[TRI_THREADS / 64];
+  __shared__ double s_diag;
+  const int t = threadIdx.x;
+  if (j >= 1) {
+    // finish step j-1 over rows / columns j .. m-1
+    const double bprev = beta[j - 1];
+    double vtp = 0.0;
+    for (int64_t l = j + t; l < m; l += TRI_THREADS) {
+      double sum = 0.0;
+      for (int g = 0; g < G; ++g) sum += part[g * m + l];
+      const double pl = bprev * sum;
+      p_s[l] = pl;
+      vtp += v[l] * pl;
+    }
+    vtp = block_sum_1024(vtp, red);
+    const double K = 0.5 * bprev * vtp;
+    for (int64_t l = j + t; l < m; l += TRI_THREADS) {
+      const double vl = v[l];
+      vp[l] = vl;
+      wp[l] = p_s[l] - K * vl;
+    }
+    __syncthreads();
+  }
+  const double vpj = vp[j], wpj = wp[j];
+  if (j + 2 >= m) {  // last 2 x 2 block: its entries with the update applied
+    if (t == 0) {
+      const int64_t a = m - 2, c = m - 1;
+      dg[a] = A[a * m + a] - 2.0 * vp[a] * wp[a];
+      dg[c] = A[c * m + c] - 2.0 * vp[c] * wp[c];
+      eo[a] = A[c * m + a] - vp[c] * wp[a] - wp[c] * vp[a];
+    }
+    return;
+  }
+  const int64_t j1 = j + 1;
+  double nrm2 = 0.0;
+  for (int64_t i = j + t; i < m; i += TRI_THREADS) {
+    const double x = A[j * m + i] - vp[i] * wpj - wp[i] * vpj;
+    if (i == j) {
+      s_diag = x;
+    } else {
+      v[i] = x;
+      nrm2 += x * x;
+    }
+  }
+  nrm2 = block_sum_1024(nrm2, red);
+  if (t == 0) {
+    const double x0 = v[j1];
+    const double nx = sqrt(nrm2);
+    double b = 0.0, alpha = x0;
+    if (nx > 0.0 && nrm2 - x0 * x0 > 0.0) {
+      alpha = x0 >= 0.0 ? -nx : nx;
+      const double v0 = x0 - alpha;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+      b = vtv > 0.0 ? 2.0 / vtv : 0.0;
+      v[j1] = v0;
+    }
+    dg[j] = s_diag;
+    eo[j] = alpha;
+    beta[j] = b;
+  }
+  __syncthreads();
+  for (int64_t i = j1 + t; i < m; i += TRI_THREADS) Vh[j * m + i] = v[i];
+}
+
+__global__ __launch_bounds__(TBG_COLS) void tribig_update_kernel(
+    double* __restrict__ A, int64_t m, int64_t j, const double* __restrict__ v,
+    const double* __restrict__ vp, const double* __restrict__ wp, double* __restrict__ part) {
+  __shared__ double rv[TBG_ROWS], rvp[TBG_ROWS], rwp[TBG_ROWS];
+  const int t = threadIdx.x;
+  const int64_t j1 = j + 1;
+  const int64_t r0 = j1 + static_cast<int64_t>(blockIdx.y) * TBG_ROWS;
+  const int64_t r1 = (r0 + TBG_ROWS < m) ? r0 + TBG_ROWS : m;
+  if (t < TBG_ROWS) {
+    const int64_t i = r0 + t;
+    rv[t] = i < m ? v[i] : 0.0;
+    rvp[t] = i < m ? vp[i] : 0.0;
+    rwp[t] = i < m ? wp[i] : 0.0;
+  }
+  __syncthreads();
+  const int64_t l = j1 + static_cast<int64_t>(blockIdx.x) * TBG_COLS + t;
+  if (l >= m) return;
+  const double vpl = vp[l], wpl = wp[l];
+  double* e = A + r0 * m + l;
+  const int nr = static_cast<int>(r1 - r0);
+  double acc = 0.0;
+  int u = 0;
+  for (; u + 8 <= nr; u += 8) {
+    double ev[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ev[q] = e[(u + q) * m];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double nv = ev[q] - rvp[u + q] * wpl - rwp[u + q] * vpl;
+      e[(u + q) * m] = nv;
+      acc += nv * rv[u + q];
+    }
+  }
+  for (; u < nr; ++u) {
+    const double nv = e[u * m] - rvp[u] * wpl - rwp[u] * vpl;
+    e[u * m] = nv;
+    acc += nv * rv[u];
+  }
+  part[blockIdx.y * m + l] = acc;
 }
 
 __global__ __launch_bounds__(256) void sym_copy_kernel(const double* __restrict__ M, int64_t m,
@@ -433,10 +559,12 @@ __global__ __launch_bounds__(256) void sym_copy_kernel(const double* __restrict_
 }  // namespace
 
 int64_t tridiag_scratch_doubles(int64_t m, int k) {
-  // A copy + Vh + beta/dg/eo + X + solver scratch (5 m per eigenvalue) + ints
+  // A copy + Vh + beta/dg/eo + X + solver scratch (5 m per eigenvalue) +
+  // pivots (k m ints) + (large m) v, vp, wp and the row-group partials
+  const int64_t groups = cdiv(m, TBG_ROWS);
   return 2 * m * m + 3 * m + static_cast<int64_t>(k) * m +
          std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024) +
-         static_cast<int64_t>(k) * m / 2 + 64;
+         (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 64;
 }
 
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double* scratch,
@@ -448,8 +576,13 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   double* eo = dg + m;
   double* X = eo + m;
   double* sol = X + static_cast<int64_t>(k) * m;
-  int* piv = reinterpret_cast<int*>(
-      sol + std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024));
+  double* pivd = sol + std::max<int64_t>(static_cast<int64_t>(k) * 5 * m,
+                                         static_cast<int64_t>(k) * 1024);
+  int* piv = reinterpret_cast<int*>(pivd);
+  double* v = pivd + (static_cast<int64_t>(k) * m + 1) / 2;
+  double* vp = v + m;
+  double* wp = vp + m;
+  double* part = wp + m;
   static bool attr = false;
   if (!attr) {
     hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_reduce_kernel),
@@ -460,13 +593,34 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   }
   sym_copy_kernel<<<static_cast<unsigned>(cdiv(m * m, 256)), 256, 0, s>>>(M, m, ldm, A);
   launch_fill_f64(Vh, m * m, 0.0, s);
-  const int64_t sb = m < TRI_LDS_BLOCK ? m : TRI_LDS_BLOCK;
-  tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + sb * sb) * sizeof(double), s>>>(A, m, Vh, beta,
-                                                                                  dg, eo);
+  if (m <= TRI_SMALL) {
+    const int64_t sb = m < TRI_LDS_BLOCK ? m : TRI_LDS_BLOCK;
+    tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + sb * sb) * sizeof(double), s>>>(
+        A, m, Vh, beta, dg, eo);
+  } else {
+    launch_fill_f64(v, 3 * m, 0.0, s);  // v, vp, wp
+    int G = 0;
+    for (int64_t j = 0; j + 2 < m; ++j) {
+      tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, j, v, vp, wp, part, G,
+                                                                    Vh, beta, dg, eo);
+      const int64_t sj = m - j - 1;
+      G = static_cast<int>(cdiv(sj, TBG_ROWS));
+      tribig_update_kernel<<<dim3(static_cast<unsigned>(cdiv(sj, TBG_COLS)),
+                                  static_cast<unsigned>(G)),
+                             TBG_COLS, 0, s>>>(A, m, j, v, vp, wp, part);
+    }
+    tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, m - 2, v, vp, wp, part,
+                                                                  G, Vh, beta, dg, eo);
+  }
   tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 2 * k) * sizeof(double), s>>>(dg, eo, m, k,
                                                                              theta, X, sol, piv);
-  tridiag_back_kernel<<<static_cast<unsigned>(cdiv(k, 4)), 256, 0, s>>>(Vh, beta, m, k, X, Uk,
-                                                                       ldu, theta, ritz);
+  const unsigned gb = static_cast<unsigned>(cdiv(k, 4));
+  if (m <= 1024)
+    tridiag_back_kernel<16><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else if (m <= 2048)
+    tridiag_back_kernel<32><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else  // m <= kTridiagMax = 64 * 40
+    tridiag_back_kernel<40><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
 }
 
 }  // namespace bk
