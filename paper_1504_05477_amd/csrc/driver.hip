@@ -183,7 +183,7 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.Gpre = ar.take<double>(kk);
   L.R = ar.take<double>(kk);
   L.Rinv = ar.take<double>(kk);
-  L.cholwork = ar.take<double>(kk);
+  L.cholwork = ar.take<double>(static_cast<size_t>(chol_work_doubles(k)));
   L.Racc = ar.take<double>(kk);
   L.Rtmp = ar.take<double>(kk);
   L.C = ar.take<double>(static_cast<size_t>(m * k));

@@ -93,6 +93,11 @@ void launch_ctrl_reset_off(Ctrl* c, hipStream_t s);
 
 // One-workgroup Cholesky + triangular inverse of a k x k FP64 Gram matrix
 // (see chol_kernel for the modes).
+// Cholesky of CholeskyQR: registers of one wavefront for k <= 64, blocked
+// by 32 in one workgroup for k <= kCholBlockedMax (work: k k + 4096
+// doubles), else one workgroup step by step.
+constexpr int kCholBlockedMax = 512;
+inline int64_t chol_work_doubles(int k) { return static_cast<int64_t>(k) * k + 4096; }
 enum CholMode { CHOL_FIRST_BLOCK0 = 0, CHOL_FIRST = 1, CHOL_REPEAT = 2 };
 void launch_chol(int k, const double* G, const double* Gpre, int mode,
                  int block, double tau, double shift_coef, double* R,

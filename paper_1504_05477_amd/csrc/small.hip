@@ -219,10 +219,14 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
   for (int r = 0; r < K; ++r)
     a[r] = (c < k) ? ((r <= c) ? g[r] + (r == c ? shift : 0.0) : 0.0) : (r == c ? 1.0 : 0.0);
   minpiv = INFINITY;
+  bool ok = true;
 #pragma unroll
-  for (int j = 0; j < K; ++j) {
-    const double d = lane_f64(a[j], j);
-    if (!(d > 0.0) || !isfinite(d)) return false;
+  for (int j = 0; j < K; ++j) {  // no early exit: the loop stays unrolled
+    double d = lane_f64(a[j], j);
+    if (!(d > 0.0) || !isfinite(d)) {
+      ok = false;
+      d = 1.0;
+    }
     const double rd = sqrt(d);
     const double inv = 1.0 / rd;
     if (j < k) minpiv = fmin(minpiv, rd);
@@ -231,7 +235,7 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
 #pragma unroll
     for (int r = j + 1; r < K; ++r) a[r] -= lane_f64(a[j], r) * a[j];
   }
-  return true;
+  return ok;
 }
 
 // CholeskyQR factor for k <= 64 in one wavefront (same modes and outputs as
@@ -310,6 +314,232 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
         Rinv[r * k + c] = (r <= c) ? x[r] : 0.0;
       }
     }
+  }
+}
+
+// CholeskyQR factor for 64 < k <= 512 (same modes and outputs as
+// chol_kernel), blocked by 32 in one workgroup of 256 threads, with S in
+// global scratch (k x k, upper triangle used) and T (32 x 32) beside it:
+// for each diagonal block, one wavefront factors it in registers and
+// inverts it (R_kk, R_kk^-1 into R and Rinv), the panel right of it becomes
+// R_kb,j = R_kk^-T S_kb,j (a thread per column, the column in registers)
+// and the trailing upper triangle takes S_ij -= sum_r R_ri R_rj.  The
+// off-diagonal blocks of R^-1 follow by blocked back substitution,
+// Rinv_IJ = -Rinv_II sum_{L=I+1..J} R_IL Rinv_LJ.
+constexpr int CB = 32;
+constexpr int CB_THREADS = 256;
+
+__device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restrict__ G, double shift,
+                                    double* __restrict__ S, double* __restrict__ Rinv,
+                                    double* minpiv, int* fail) {
+  const int t = threadIdx.x;
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
+    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
+    Rinv[i] = 0.0;
+  }
+  if (t == 0) {
+    *fail = 0;
+    *minpiv = INFINITY;
+  }
+  __syncthreads();
+  const int nb = (k + CB - 1) / CB;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int o = kb * CB;
+    const int bs = (k - o < CB) ? k - o : CB;
+    if (t < 64) {  // diagonal block in the registers of wavefront 0 (lane c: column c)
+      const int c = t;
+      double a[CB];
+#pragma unroll
+      for (int r = 0; r < CB; ++r)
+        a[r] = (c < bs) ? ((r < bs) ? S[(o + r) * k + o + c] : 0.0) : (r == c ? 1.0 : 0.0);
+      bool ok = true;
+      double mp = INFINITY;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) {  // no early exit: the loop stays unrolled
+        double d = lane_f64(a[j], j);
+        if (!(d > 0.0) || !isfinite(d)) {
+          ok = false;
+          d = 1.0;
+        }
+        const double rd = sqrt(d);
+        if (j < bs) mp = fmin(mp, rd);
+        a[j] = (c == j) ? rd : a[j] * (1.0 / rd);
+#pragma unroll
+        for (int r = j + 1; r < CB; ++r) a[r] -= lane_f64(a[j], r) * a[j];
+      }
+      if (ok) {
+        // x = column c of R_kk^-1 by back substitution
+        double x[CB];
+#pragma unroll
+        for (int i = CB - 1; i >= 0; --i) {
+          double sum = 0.0;
+#pragma unroll
+          for (int l = i + 1; l < CB; ++l) sum += lane_f64(a[i], l) * x[l];
+          x[i] = ((i == c ? 1.0 : 0.0) - sum) / lane_f64(a[i], i);
+        }
+        if (c < bs) {
+#pragma unroll
+          for (int r = 0; r < CB; ++r) {
+            if (r <= c) {
+              S[(o + r) * k + o + c] = a[r];
+              Rinv[(o + r) * k + o + c] = x[r];
+            }
+          }
+        }
+      }
+      if (c == 0) {
+        if (!ok) *fail = 1;
+        else if (mp < *minpiv) *minpiv = mp;
+      }
+    }
+    __syncthreads();
+    if (*fail) return false;
+    const int rest = k - o - bs;
+    if (rest > 0) {
+      // panel: R[o + r][j] = sum_{l <= r} Rinv[o + l][o + r] S[o + l][j]
+      for (int jj = t; jj < rest; jj += CB_THREADS) {
+        const int j = o + bs + jj;
+        double col[CB];
+#pragma unroll
+        for (int l = 0; l < CB; ++l) col[l] = (l < bs) ? S[(o + l) * k + j] : 0.0;
+#pragma unroll
+        for (int r = CB - 1; r >= 0; --r) {
+          if (r < bs) {
+            double sum = 0.0;
+#pragma unroll
+            for (int l = 0; l <= r; ++l) sum += Rinv[(o + l) * k + o + r] * col[l];
+            col[r] = sum;  // col[l < r] still hold S
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < CB; ++r)
+          if (r < bs) S[(o + r) * k + j] = col[r];
+      }
+      __syncthreads();
+      // trailing upper triangle: S[i][j] -= sum_r R[o + r][i] R[o + r][j]
+      const int64_t tri = static_cast<int64_t>(rest) * (rest + 1) / 2;
+      for (int64_t e = t; e < tri; e += CB_THREADS) {
+        // e -> (ii, jj), ii <= jj, row-major over the upper triangle; row ii
+        // starts at off(ii) = ii rest - ii (ii - 1) / 2
+        const double b2 = 2.0 * rest + 1.0;
+        int ii = static_cast<int>((b2 - sqrt(b2 * b2 - 8.0 * static_cast<double>(e))) / 2.0);
+        if (ii < 0) ii = 0;
+        if (ii > rest - 1) ii = rest - 1;
+        while (ii > 0 && static_cast<int64_t>(ii) * rest - static_cast<int64_t>(ii) * (ii - 1) / 2 > e)
+          --ii;
+        while (ii + 1 < rest &&
+               static_cast<int64_t>(ii + 1) * rest - static_cast<int64_t>(ii + 1) * ii / 2 <= e)
+          ++ii;
+        const int jj = ii + static_cast<int>(e - (static_cast<int64_t>(ii) * rest -
+                                                  static_cast<int64_t>(ii) * (ii - 1) / 2));
+        const int i = o + bs + ii, j = o + bs + jj;
+        double sum = 0.0;
+        for (int r = 0; r < bs; ++r) sum += S[(o + r) * k + i] * S[(o + r) * k + j];
+        S[i * k + j] -= sum;
+      }
+      __syncthreads();
+    }
+  }
+  return true;
+}
+
+// Off-diagonal blocks of Rinv = R^-1 (diagonal blocks already in Rinv):
+// for each block column J, I = J-1 .. 0: T = sum_{L=I+1..J} R_IL Rinv_LJ,
+// Rinv_IJ = -Rinv_II T.
+__device__ __forceinline__ void chol_blocked_inverse(int k, const double* __restrict__ S,
+                                     double* __restrict__ Rinv, double* __restrict__ T) {
+  const int t = threadIdx.x;
+  const int nb = (k + CB - 1) / CB;
+  for (int J = 1; J < nb; ++J) {
+    const int oj = J * CB, bj = (k - oj < CB) ? k - oj : CB;
+    for (int I = J - 1; I >= 0; --I) {
+      const int oi = I * CB;  // full block (only the last block is short)
+      for (int e = t; e < CB * bj; e += CB_THREADS) {
+        const int r = e / bj, c = e - (e / bj) * bj;
+        double sum = 0.0;
+        for (int l = oi + CB; l < oj + bj; ++l) sum += S[(oi + r) * k + l] * Rinv[l * k + oj + c];
+        T[r * CB + c] = sum;
+      }
+      __syncthreads();
+      for (int e = t; e < CB * bj; e += CB_THREADS) {
+        const int r = e / bj, c = e - (e / bj) * bj;
+        double sum = 0.0;
+        for (int l = r; l < CB; ++l) sum += Rinv[(oi + r) * k + oi + l] * T[l * CB + c];
+        Rinv[(oi + r) * k + oj + c] = -sum;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
+    int k, const double* __restrict__ G, const double* __restrict__ Gpre, int mode, int block,
+    double tau, double shift_coef, double* __restrict__ R, double* __restrict__ Rinv,
+    double* __restrict__ work, Ctrl* ctrl) {
+  __shared__ double red[CB_THREADS];
+  __shared__ double minpiv;
+  __shared__ int fail;
+  __shared__ int decision;
+  const int t = threadIdx.x;
+  double* S = work;
+  double* T = work + static_cast<int64_t>(k) * k;
+  double trp = 0.0, prp = 0.0;
+  int bad = 0;
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS)
+    if (!isfinite(G[i])) bad = 1;
+  for (int i = t; i < k; i += CB_THREADS) {
+    trp += G[static_cast<int64_t>(i) * k + i];
+    if (mode == CHOL_FIRST) prp += Gpre[static_cast<int64_t>(i) * k + i];
+  }
+  const int anybad = __syncthreads_or(bad);
+  const double tr = block_sum(trp, red);
+  const double pre = (mode == CHOL_FIRST) ? block_sum(prp, red) : 0.0;
+  if (t == 0) {
+    decision = 0;
+    if (anybad) {
+      atomicOr(&ctrl->flags, CTRL_NONFINITE);
+      decision = 1;
+    } else if (mode == CHOL_FIRST) {
+      if (!(sqrt(tr) > tau * sqrt(pre))) {
+        atomicMin(&ctrl->q_eff, block - 1);
+        decision = 1;
+      }
+    } else if (!(tr > 0.0)) {
+      if (mode == CHOL_FIRST_BLOCK0) atomicOr(&ctrl->flags, CTRL_RANK);
+      decision = 1;
+    }
+  }
+  __syncthreads();
+  if (!decision && mode == CHOL_FIRST_BLOCK0) {
+    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail);
+    if (t == 0 && (!ok || !(minpiv > tau * sqrt(tr)))) {
+      atomicOr(&ctrl->flags, CTRL_RANK);
+      decision = 1;
+    }
+    __syncthreads();
+  }
+  if (!decision) {
+    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
+    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail);
+    if (t == 0 && !ok) {
+      if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+      else atomicMin(&ctrl->q_eff, block - 1);
+      decision = 1;
+    }
+    __syncthreads();
+  }
+  if (decision) {
+    for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
+      R[i] = 0.0;
+      Rinv[i] = 0.0;
+    }
+    return;
+  }
+  chol_blocked_inverse(k, S, Rinv, T);
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
+    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+    R[i] = (c >= r) ? S[i] : 0.0;
   }
 }
 
@@ -546,6 +776,11 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
   BK_CHOL_WAVE(48)
   BK_CHOL_WAVE(64)
 #undef BK_CHOL_WAVE
+  if (k <= kCholBlockedMax) {
+    chol_blocked_kernel<<<1, CB_THREADS, 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
+                                                 Rinv, work, ctrl);
+    return;
+  }
   chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
                                                  Rinv, work, ctrl, use_lds);
 }

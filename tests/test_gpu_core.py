@@ -179,6 +179,17 @@ def test_svd_dense_f64_ragged(n, d, k, q):
     compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-10, 1e-8)
 
 
+@pytest.mark.parametrize("n,d,k,q", [(2400, 1200, 150, 2), (3000, 1600, 256, 1)])
+def test_svd_dense_f64_wide_blocks(n, d, k, q):
+    """Blocks wider than one wavefront: the blocked Cholesky of CholeskyQR
+    (32-column blocks, a ragged last block for k = 150)."""
+    A = workloads.planted_dense(n, d, workloads.spectrum("inv_sqrt", min(n, d)), 71 + k)
+    ref = bki.block_krylov(A, philox.gaussian(81 + k, d, k), k, q)
+    res = bk.svd_dense(_cuda(A), k, q, seed=81 + k)
+    assert res.info["q_eff"] == ref.q_eff
+    compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-10, 1e-8)
+
+
 # ------------------------------------------------------------- solve FP32 --
 @pytest.mark.parametrize("n,d,k,q,spec", [(1500, 700, 16, 5, "inv"), (2048, 1024, 32, 10, "inv"),
                                           (777, 1999, 10, 7, "exp200")])
