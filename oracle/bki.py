@@ -92,14 +92,19 @@ class LinearOperator:
         return out
 
 
-def validate(n: int, d: int, k: int, q: int) -> None:
-    """Argument rules shared with the library's boundary (ValueError here)."""
+def validate(n: int, d: int, k: int, q: int, p: int | None = None) -> None:
+    """Argument rules shared with the library's boundary (ValueError here).
+    p is the block width (the sketch has p >= k columns, Section 6); the
+    Krylov space has (q+1) p columns."""
+    p = k if p is None else p
     if k < 1 or q < 0:
         raise ValueError("need k >= 1 and q >= 0")
+    if p < k:
+        raise ValueError("need block width p >= k")
     if k > min(n, d):
         raise ValueError("need k <= min(n, d)")
-    if (q + 1) * k > min(n, d):
-        raise ValueError("need (q+1) k <= min(n, d); use a dense SVD instead")
+    if (q + 1) * p > min(n, d):
+        raise ValueError("need (q+1) p <= min(n, d); use a dense SVD instead")
 
 
 def sign_normalize(Z: np.ndarray) -> np.ndarray:
@@ -144,13 +149,15 @@ def block_krylov(A, Pi, k: int, q: int, *, center: bool = False,
                    plus lower powers, so span{Q_0..Q_i} = span{K_0..K_i};
                    B_i <- (I - Q_<i Q_<i^T) B_i, done twice;
                    Q_i = QR(B_i).
-    Then Rayleigh-Ritz on Q = [Q_0 .. Q_q]."""
+    Then Rayleigh-Ritz on Q = [Q_0 .. Q_q].  A sketch of p > k columns
+    (oversampling, Section 6) makes every block p wide; Rayleigh-Ritz still
+    returns the top k."""
     op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
     n, d = op.n, op.d
-    validate(n, d, k, q)
     Pi = np.asarray(Pi, dtype=np.float64)
-    if Pi.shape != (d, k):
-        raise ValueError(f"Pi must be {d} x {k}")
+    if Pi.ndim != 2 or Pi.shape[0] != d:
+        raise ValueError(f"Pi must be {d} x p")
+    validate(n, d, k, q, Pi.shape[1])
     B = op.mul(Pi)
     sv = np.linalg.svd(B, compute_uv=False)
     if not np.all(np.isfinite(B)):
@@ -180,8 +187,9 @@ def block_krylov_route_b(A, Pi, k: int, q: int, *, center: bool = False) -> BKIR
     span K_i = span (A A^T)^i A Pi), then one Householder QR of all of K and
     the same Rayleigh-Ritz step.  For small q and well-conditioned inputs."""
     op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
-    validate(op.n, op.d, k, q)
-    Kb = [_qr_pos(op.mul(np.asarray(Pi, dtype=np.float64)))[0]]
+    Pi = np.asarray(Pi, dtype=np.float64)
+    validate(op.n, op.d, k, q, Pi.shape[1])
+    Kb = [_qr_pos(op.mul(Pi))[0]]
     for _ in range(q):
         Kb.append(_qr_pos(op.mul(op.tmul(Kb[-1])))[0])
     Q = _qr_pos(np.hstack(Kb))[0]
@@ -202,10 +210,11 @@ def rayleigh_ritz_svd(A, Q: np.ndarray, k: int, *, center: bool = False):
 def simultaneous_iteration(A, Pi, k: int, q: int, *, center: bool = False) -> BKIResult:
     """Algorithm 1: K = (A A^T)^q A Pi, re-orthonormalized after every
     application of A A^T (Section 4.1), then the same Rayleigh-Ritz on the
-    k-dimensional span."""
+    p-dimensional span (p = columns of Pi >= k), top k returned."""
     op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
-    validate(op.n, op.d, k, 0)
-    X = _qr_pos(op.mul(np.asarray(Pi, dtype=np.float64)))[0]
+    Pi = np.asarray(Pi, dtype=np.float64)
+    validate(op.n, op.d, k, 0, Pi.shape[1])
+    X = _qr_pos(op.mul(Pi))[0]
     for _ in range(q):
         X = _qr_pos(op.mul(op.tmul(X)))[0]
     Z, sigma, theta, U = rayleigh_ritz(op, X, k)

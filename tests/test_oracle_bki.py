@@ -120,6 +120,43 @@ def test_block_krylov_dominates_simultaneous_iteration():
     assert pv_b < pv_s
 
 
+def test_oversampled_sketch_dominates_its_leading_columns():
+    # Oversampling (Section 6): with Pi_k the first k columns of Pi_p, every
+    # Krylov block of Pi_p contains the matching block of Pi_k, so the
+    # space is nested and by Courant-Fischer the top-k Ritz values cannot
+    # decrease; the oversampled per-vector error is no worse here.
+    sv = workloads.spectrum("inv_sqrt", 200)
+    A = workloads.planted_dense(300, 200, sv, seed=31)
+    k, q = 6, 3
+    Pp = philox.gaussian(41, 200, 10)
+    rk = bki.block_krylov(A, Pp[:, :k], k, q)
+    rp = bki.block_krylov(A, Pp, k, q)
+    assert rp.Q.shape[1] == (q + 1) * 10 and rp.Z.shape[1] == k
+    assert np.all(rp.sigma >= rk.sigma * (1 - 1e-13))
+    assert np.all(rp.sigma <= sv[:k] * (1 + 1e-12))   # interlacing still holds
+    assert (metrics.per_vector_error(A, rp.Z, sv, k)
+            <= metrics.per_vector_error(A, rk.Z, sv, k) * (1 + 1e-9))
+    # the same for Simultaneous Iteration
+    sk = bki.simultaneous_iteration(A, Pp[:, :k], k, q)
+    sp_ = bki.simultaneous_iteration(A, Pp, k, q)
+    assert np.all(sp_.sigma >= sk.sigma * (1 - 1e-12))
+    # BKI on the wider sketch still dominates SI on it
+    assert np.all(rp.sigma >= sp_.sigma * (1 - 1e-12))
+
+
+def test_oversampled_exact_span():
+    # (q+1) p >= rank(A): the Krylov space holds the column space (exact)
+    A = workloads.planted_dense(60, 40, np.linspace(4.0, 1.0, 15), seed=32)
+    U, s, _ = np.linalg.svd(A)
+    res = bki.block_krylov(A, philox.gaussian(42, 40, 5), 3, 2)   # k=3, p=5, m=15
+    assert np.allclose(res.sigma, s[:3], rtol=1e-12)
+    assert _proj_dist(res.Z, U[:, :3]) < 1e-10
+    with pytest.raises(ValueError):
+        bki.block_krylov(A, philox.gaussian(42, 40, 2), 3, 2)     # p < k
+    with pytest.raises(ValueError):
+        bki.block_krylov(A, philox.gaussian(42, 40, 14), 3, 2)    # (q+1) p > min(n, d)
+
+
 def test_metrics_on_exact_singular_vectors():
     sv = workloads.spectrum("inv_sqrt", 60)
     A = workloads.planted_dense(90, 60, sv, seed=9)
