@@ -90,8 +90,21 @@ typedef struct bk_options {
                                 in the workspace for bk_svd_dense_backward   */
   int32_t jacobi_block;      /* column block of the eigen-solve (default by
                                 size); a test knob                           */
-  int32_t reserved[5];
+  int32_t block_size;        /* p: columns of the sketch and of every Krylov
+                                block, p >= k (oversampling, Section 6);
+                                0 = k.  Rayleigh-Ritz still returns the top
+                                k.  The Krylov space has (q+1) p columns
+                                (BK_METHOD_BLOCK_KRYLOV) or p (simultaneous
+                                iteration); needs save_for_backward = 0 when
+                                p != k                                      */
+  int32_t method;            /* BK_METHOD_BLOCK_KRYLOV (0, Algorithm 2) or
+                                BK_METHOD_SIMULTANEOUS (1, Algorithm 1: the
+                                block is replaced by orth(A A^T block) q
+                                times, Rayleigh-Ritz on the last one)       */
+  int32_t reserved[3];
 } bk_options;
+
+enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1 };
 
 /* Phases of bk_info.ms[] / launches[]. */
 enum {
@@ -131,7 +144,9 @@ size_t bk_svd_dense_workspace(int64_t n, int64_t d, int32_t k, int32_t q,
  *          FP32 tile scales, row-major (A[i][j] ~ scale[i/128][j/128] * q_ij).
  * A_master nullable FP32 n x d copy (ld ld_master) used by the correction
  *          pass (opt->refine) of the BF16 / FP8 paths.
- * k, q     rank and depth: 1 <= k, 0 <= q, (q+1) k <= min(n, d).
+ * k, q     rank and depth: 1 <= k, 0 <= q, (q+1) p <= min(n, d) with p
+ *          the block width (opt->block_size, default k; for simultaneous
+ *          iteration p <= min(n, d)).
  * seed     Philox4x32-10 key of the sketch (see bk_gaussian).
  * Z        n x k output, ld ldz >= k; FP64 for BK_F64, FP32 otherwise.
  *          Column i is the i-th Ritz vector, signed so that its

@@ -27,7 +27,9 @@ class Options(C.Structure):
         ("timing", C.c_int32),
         ("save_for_backward", C.c_int32),
         ("jacobi_block", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("block_size", C.c_int32),
+        ("method", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 

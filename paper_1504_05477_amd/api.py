@@ -42,9 +42,12 @@ def _dtype_code(t: torch.Tensor) -> int:
     raise TypeError(f"unsupported matrix dtype {t.dtype}")
 
 
+_METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1}
+
+
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
              breakdown_tol=0.0, pi=None, timing=False, save=False,
-             jacobi_block=0) -> L.Options:
+             jacobi_block=0, block_size=0, method="bki") -> L.Options:
     o = L.Options()
     o.struct_size = C.sizeof(L.Options)
     o.refine = int(refine)
@@ -56,6 +59,10 @@ def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
     o.timing = int(bool(timing))
     o.save_for_backward = int(bool(save))
     o.jacobi_block = int(jacobi_block)
+    o.block_size = int(block_size or 0)
+    if method not in _METHODS:
+        raise ValueError(f"method must be one of {sorted(_METHODS)}")
+    o.method = _METHODS[method]
     return o
 
 
@@ -70,12 +77,15 @@ class SVDResult:
 def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
               A_master=None, refine: int = 0, pi=None, timing=False,
               save_for_backward=False, max_sweeps=0, jacobi_tol=0.0,
-              breakdown_tol=0.0, jacobi_block=0, stream=None) -> SVDResult:
+              breakdown_tol=0.0, jacobi_block=0, block_size=0, method="bki",
+              stream=None) -> SVDResult:
     """Block Krylov Iteration on a dense A (n x d row-major on the GPU).
 
     A's dtype selects the path: float64 / float32 (plain), bfloat16, or uint8
     holding OCP e4m3 codes with ``a_scales`` (FP8).  Returns Z (n x k, FP64 for
-    the FP64 path, FP32 otherwise) and the Ritz values (FP64)."""
+    the FP64 path, FP32 otherwise) and the Ritz values (FP64).
+    ``block_size`` = p >= k oversamples the sketch (0: p = k);
+    ``method`` = "si" runs Simultaneous Iteration instead."""
     lib = L.load()
     _need_cuda(A, a_scales, A_master, pi)
     if A.dim() != 2 or A.stride(1) != 1:
@@ -91,7 +101,8 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
         raise ValueError("A_master must be a row-major float32 tensor")
     opt = _options(refine=refine, pi=pi, timing=timing, save=save_for_backward,
                    max_sweeps=max_sweeps, jacobi_tol=jacobi_tol,
-                   breakdown_tol=breakdown_tol, jacobi_block=jacobi_block)
+                   breakdown_tol=breakdown_tol, jacobi_block=jacobi_block,
+                   block_size=block_size, method=method)
     nbytes = lib.bk_svd_dense_workspace(n, d, k, q, code, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
@@ -163,7 +174,8 @@ class BKSVD(torch.autograd.Function):
 
 def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 0, *,
             transpose=None, center=False, pi=None, timing=False, max_sweeps=0,
-            jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, stream=None) -> SVDResult:
+            jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, block_size=0,
+            method="bki", stream=None) -> SVDResult:
     """Block Krylov Iteration on a CSR A (int32 row_ptr / col_idx, float32
     values, on the GPU).  ``transpose`` = (t_row_ptr, t_col_idx, t_vals) of A^T
     is optional; ``center`` applies implicit row centring."""
@@ -178,7 +190,7 @@ def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 
         pi = pi.to(torch.float32).contiguous()
     opt = _options(center=center, pi=pi, timing=timing, max_sweeps=max_sweeps,
                    jacobi_tol=jacobi_tol, breakdown_tol=breakdown_tol,
-                   jacobi_block=jacobi_block)
+                   jacobi_block=jacobi_block, block_size=block_size, method=method)
     nbytes = lib.bk_svd_csr_workspace(n, d, nnz, k, q, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")

@@ -45,6 +45,8 @@ struct Arena {
 
 struct Options {
   int refine = 0, center = 0, max_sweeps = 40, timing = 0, save = 0, jblock = 0;
+  int p = 0;   // block width (0: k), oversampling of Section 6
+  int si = 0;  // 1: simultaneous iteration (Algorithm 1)
   double jtol = 0.0, tau = 0.0;
   const void* pi = nullptr;
 };
@@ -61,6 +63,8 @@ Options read_options(const bk_options* o, bool f64) {
     r.timing = o->timing;
     r.save = o->save_for_backward;
     r.jblock = o->jacobi_block;
+    r.p = o->block_size;
+    r.si = o->method == BK_METHOD_SIMULTANEOUS ? 1 : 0;
   }
   if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
   return r;
@@ -164,7 +168,7 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   ar.base = base;
   Layout L;
   const size_t es = f64 ? 8 : 4;
-  const int64_t m = static_cast<int64_t>(q + 1) * k;
+  const int64_t m = o.si ? k : static_cast<int64_t>(q + 1) * k;  // k: block width here
   L.ctrl = ar.take<Ctrl>(1);
   L.Pi = ar.take<char>(static_cast<size_t>(d * k) * es);
   L.Q = ar.take<char>(static_cast<size_t>(n * m) * es);
@@ -464,7 +468,7 @@ struct Solver {
   // ||B||_F^2 so the FP64 Cholesky cannot fail on an ill-conditioned block;
   // passes 2 and 3 are plain CholeskyQR on the already well-conditioned
   // result.  R_i = R3 R2 R1 (saved for the adjoint).
-  void orth_block(int i) {
+  void orth_block(int i, int slab) {
     tm->begin(BK_PH_CHOLQR);
     const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
     void* src = L->Bs;
@@ -474,7 +478,7 @@ struct Solver {
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
       launch_chol(k, L->G, L->Gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
                   L->cholwork, L->ctrl, s);
-      void* out = (pass == 2) ? static_cast<void*>(qslab(i)) : dst;
+      void* out = (pass == 2) ? static_cast<void*>(qslab(slab)) : dst;
       const int64_t ldo = (pass == 2) ? m : k;
       apply(src, k, n, k, L->Rinv, k, k, out, ldo, 1.0, 0.0);
       if (o.save) {
@@ -582,13 +586,16 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   S.o = o;
   S.tm = &tm;
   S.s = s;
-  S.k = k;
+  // p: width of the sketch and of every block (p >= k, Section 6); the
+  // Rayleigh-Ritz step below returns the top k
+  const int pw = o.p > 0 ? o.p : k;
+  S.k = pw;
   S.q = q;
   S.n = op.n;
   S.d = op.d;
   S.f64 = op.f64;
   S.es = op.f64 ? 8 : 4;
-  S.m = static_cast<int64_t>(q + 1) * k;
+  S.m = o.si ? pw : static_cast<int64_t>(q + 1) * pw;
   const int64_t n = op.n, d = op.d, m = S.m;
   const bool f64 = op.f64;
 
@@ -596,21 +603,34 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   // Step 1: the sketch.
   tm.begin(BK_PH_PI);
   if (o.pi)
-    launch_copy2d(o.pi, f64, k, L.Pi, f64, k, d, k, s);
+    launch_copy2d(o.pi, f64, pw, L.Pi, f64, pw, d, pw, s);
   else
-    launch_gaussian(seed, d, k, k, f64, L.Pi, s);
+    launch_gaussian(seed, d, pw, pw, f64, L.Pi, s);
   tm.end(1);
 
   // Step 2-3: Krylov blocks, orthonormalized as they are formed.
-  op.ax(L.Pi, k, k, L.Bs, k, s);
-  S.orth_block(0);
-  for (int i = 1; i <= q; ++i) {
-    op.aty(S.qslab(i - 1), m, k, S.wslab(i - 1), m, s);
-    op.ax(S.wslab(i - 1), m, k, L.Bs, k, s);
-    S.project(i);
-    S.orth_block(i);
+  op.ax(L.Pi, pw, pw, L.Bs, pw, s);
+  S.orth_block(0, 0);
+  if (!o.si) {
+    for (int i = 1; i <= q; ++i) {
+      op.aty(S.qslab(i - 1), m, pw, S.wslab(i - 1), m, s);
+      op.ax(S.wslab(i - 1), m, pw, L.Bs, pw, s);
+      S.project(i);
+      S.orth_block(i, i);
+    }
+    op.aty(S.qslab(q), m, pw, S.wslab(q), m, s);
+  } else {
+    // Algorithm 1: the single block is replaced by orth(A A^T block)
+    for (int i = 1; i <= q; ++i) {
+      op.aty(S.qslab(0), m, pw, S.wslab(0), m, s);
+      op.ax(S.wslab(0), m, pw, L.Bs, pw, s);
+      tm.begin(BK_PH_PROJ);
+      S.gram(L.Bs, pw, pw, L.Bs, pw, pw, n, L.Gpre);  // trace for the breakdown test
+      tm.end(2);
+      S.orth_block(i, 0);
+    }
+    op.aty(S.qslab(0), m, pw, S.wslab(0), m, s);
   }
-  op.aty(S.qslab(q), m, k, S.wslab(q), m, s);
   BK_TRY_LAUNCH();
 
   // Step 4: M = W^T W = Q^T A A^T Q in FP64.
@@ -891,6 +911,17 @@ bool valid_kq(int64_t n, int64_t d, int32_t k, int32_t q) {
   return true;
 }
 
+// Block width of a solve (Section 6 oversampling): p >= k; the Krylov space
+// has (q+1) p columns, or p for simultaneous iteration.  0 on invalid input.
+int32_t block_width(int64_t n, int64_t d, int32_t k, int32_t q, const Options& o) {
+  if (n <= 0 || d <= 0 || k < 1 || q < 0 || o.p < 0) return 0;
+  const int32_t p = o.p > 0 ? o.p : k;
+  if (p < k || p > std::min(n, d)) return 0;
+  if (!o.si && static_cast<int64_t>(q + 1) * p > std::min(n, d)) return 0;
+  if (o.save && (p != k || o.si)) return 0;
+  return p;
+}
+
 struct DevBuf {
   void* p = nullptr;
   hipStream_t s = nullptr;
@@ -923,11 +954,13 @@ const char* bk_version(void) { return "bk 0.1 gfx950"; }
 
 size_t bk_svd_dense_workspace(int64_t n, int64_t d, int32_t k, int32_t q, int32_t a_type,
                               const bk_options* opt) {
-  if (!valid_kq(n, d, k, q) || a_type < BK_F64 || a_type > BK_FP8_E4M3) return 0;
+  if (a_type < BK_F64 || a_type > BK_FP8_E4M3) return 0;
   const bool f64 = a_type == BK_F64;
   Options o = read_options(opt, f64);
+  const int32_t pw = block_width(n, d, k, q, o);
+  if (!pw) return 0;
   normalize_refine(o, a_type, true);  // sized for the pass whenever it may run
-  return make_layout(nullptr, n, d, 0, k, q, f64, o, false, false).bytes;
+  return make_layout(nullptr, n, d, 0, pw, q, f64, o, false, false).bytes;
 }
 
 int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scales,
@@ -935,16 +968,18 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
                  int32_t q, uint64_t seed, const bk_options* opt, void* Z, int64_t ldz,
                  double* ritz, bk_info* info, void* workspace, size_t workspace_bytes,
                  void* stream) {
-  if (!valid_kq(n, d, k, q) || !A || !Z || !ritz || lda < d || ldz < k) return BK_EINVAL;
+  if (!A || !Z || !ritz || lda < d || ldz < k) return BK_EINVAL;
   if (a_type < BK_F64 || a_type > BK_FP8_E4M3) return BK_EINVAL;
   if (a_type == BK_FP8_E4M3 && !a_scales) return BK_EINVAL;
   const bool f64 = a_type == BK_F64;
   Options o = read_options(opt, f64);
+  const int32_t pw = block_width(n, d, k, q, o);
+  if (!pw) return BK_EINVAL;
   normalize_refine(o, a_type, A_master != nullptr);
   if (o.refine && (!A_master || ld_master < d)) return BK_EINVAL;
   if (o.center) return BK_EINVAL;  // dense centring is not offered
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = make_layout(nullptr, n, d, 0, k, q, f64, o, false, false).bytes;
+  const size_t need = make_layout(nullptr, n, d, 0, pw, q, f64, o, false, false).bytes;
   DevBuf own;
   char* base = static_cast<char*>(workspace);
   if (!base) {
@@ -954,7 +989,7 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
   } else if (workspace_bytes < need) {
     return BK_ENOMEM;
   }
-  Layout L = make_layout(base, n, d, 0, k, q, f64, o, false, false);
+  Layout L = make_layout(base, n, d, 0, pw, q, f64, o, false, false);
   DenseOp op;
   op.n = n;
   op.d = d;
@@ -979,10 +1014,13 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
 
 size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k, int32_t q,
                             const bk_options* opt) {
-  if (!valid_kq(n, d, k, q) || nnz < 0 || nnz >= (int64_t(1) << 31)) return 0;
+  if (nnz < 0 || nnz >= (int64_t(1) << 31)) return 0;
   Options o = read_options(opt, false);
   o.refine = 0;
-  return make_layout(nullptr, n, d, nnz, k, q, false, o, true, true).bytes;
+  o.save = 0;
+  const int32_t pw = block_width(n, d, k, q, o);
+  if (!pw) return 0;
+  return make_layout(nullptr, n, d, nnz, pw, q, false, o, true, true).bytes;
 }
 
 int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
@@ -990,8 +1028,7 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
                int64_t n, int64_t d, int64_t nnz, int32_t k, int32_t q, uint64_t seed,
                const bk_options* opt, float* Z, int64_t ldz, double* ritz, bk_info* info,
                void* workspace, size_t workspace_bytes, void* stream) {
-  if (!valid_kq(n, d, k, q) || nnz < 0 || nnz >= (int64_t(1) << 31) || !row_ptr || !Z ||
-      !ritz || ldz < k)
+  if (nnz < 0 || nnz >= (int64_t(1) << 31) || !row_ptr || !Z || !ritz || ldz < k)
     return BK_EINVAL;
   if (nnz > 0 && (!col_idx || !vals)) return BK_EINVAL;
   const bool given_t = t_row_ptr && t_col_idx && t_vals;
@@ -999,8 +1036,10 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   Options o = read_options(opt, false);
   o.refine = 0;
   o.save = 0;
+  const int32_t pw = block_width(n, d, k, q, o);
+  if (!pw) return BK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = make_layout(nullptr, n, d, nnz, k, q, false, o, true, !given_t).bytes;
+  const size_t need = make_layout(nullptr, n, d, nnz, pw, q, false, o, true, !given_t).bytes;
   DevBuf own;
   char* base = static_cast<char*>(workspace);
   if (!base) {
@@ -1010,7 +1049,7 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   } else if (workspace_bytes < need) {
     return BK_ENOMEM;
   }
-  Layout L = make_layout(base, n, d, nnz, k, q, false, o, true, !given_t);
+  Layout L = make_layout(base, n, d, nnz, pw, q, false, o, true, !given_t);
 
   Timer prep;
   prep.on = o.timing != 0;
@@ -1035,8 +1074,8 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
     tci = L.tci;
     tv = L.tv;
   }
-  launch_csr_plan(row_ptr, n, k, L.plan_a, L.counters, s);
-  launch_csr_plan(trp, d, k, L.plan_t, L.counters + 3, s);
+  launch_csr_plan(row_ptr, n, pw, L.plan_a, L.counters, s);
+  launch_csr_plan(trp, d, pw, L.plan_t, L.counters + 3, s);
   if (o.center) launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
   int32_t cnt[6] = {0, 0, 0, 0, 0, 0};
   BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));

@@ -331,7 +331,8 @@ constexpr int CB_THREADS = 256;
 
 __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restrict__ G, double shift,
                                     double* __restrict__ S, double* __restrict__ Rinv,
-                                    double* minpiv, int* fail) {
+                                    double* minpiv, int* fail, double* __restrict__ rkk,
+                                    double* __restrict__ pan) {
   const int t = threadIdx.x;
   for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
     const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
@@ -397,24 +398,28 @@ __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restr
     if (*fail) return false;
     const int rest = k - o - bs;
     if (rest > 0) {
-      // panel: R[o + r][j] = sum_{l <= r} Rinv[o + l][o + r] S[o + l][j]
+      // R_kk^-1 of this block into LDS (zero outside the block)
+      for (int e = t; e < CB * CB; e += CB_THREADS) {
+        const int l = e / CB, r = e % CB;
+        rkk[e] = (l < bs && r < bs && l <= r) ? Rinv[(o + l) * k + o + r] : 0.0;
+      }
+      __syncthreads();
+      // panel: R[o + r][j] = sum_{l <= r} Rinv_kk[l][r] S[o + l][j], kept in
+      // LDS (pan[r][jj]) for the trailing update
       for (int jj = t; jj < rest; jj += CB_THREADS) {
         const int j = o + bs + jj;
         double col[CB];
 #pragma unroll
         for (int l = 0; l < CB; ++l) col[l] = (l < bs) ? S[(o + l) * k + j] : 0.0;
+        // rkk is zero below its diagonal: full-length dot products
+#pragma unroll 1
+        for (int r = 0; r < CB; ++r) {
+          double sum = 0.0;
 #pragma unroll
-        for (int r = CB - 1; r >= 0; --r) {
-          if (r < bs) {
-            double sum = 0.0;
-#pragma unroll
-            for (int l = 0; l <= r; ++l) sum += Rinv[(o + l) * k + o + r] * col[l];
-            col[r] = sum;  // col[l < r] still hold S
-          }
+          for (int l = 0; l < CB; ++l) sum += rkk[l * CB + r] * col[l];
+          pan[r * kCholBlockedMax + jj] = sum;
+          if (r < bs) S[(o + r) * k + j] = sum;
         }
-#pragma unroll
-        for (int r = 0; r < CB; ++r)
-          if (r < bs) S[(o + r) * k + j] = col[r];
       }
       __syncthreads();
       // trailing upper triangle: S[i][j] -= sum_r R[o + r][i] R[o + r][j]
@@ -435,7 +440,8 @@ __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restr
                                                   static_cast<int64_t>(ii) * (ii - 1) / 2));
         const int i = o + bs + ii, j = o + bs + jj;
         double sum = 0.0;
-        for (int r = 0; r < bs; ++r) sum += S[(o + r) * k + i] * S[(o + r) * k + j];
+#pragma unroll 8
+        for (int r = 0; r < CB; ++r) sum += pan[r * kCholBlockedMax + ii] * pan[r * kCholBlockedMax + jj];
         S[i * k + j] -= sum;
       }
       __syncthreads();
@@ -481,6 +487,9 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   __shared__ double minpiv;
   __shared__ int fail;
   __shared__ int decision;
+  extern __shared__ double cb_dyn[];  // R_kk^-1 (CB x CB), panel (CB x kCholBlockedMax)
+  double* rkk = cb_dyn;
+  double* pan = cb_dyn + CB * CB;
   const int t = threadIdx.x;
   double* S = work;
   double* T = work + static_cast<int64_t>(k) * k;
@@ -512,7 +521,7 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   }
   __syncthreads();
   if (!decision && mode == CHOL_FIRST_BLOCK0) {
-    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail);
+    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail, rkk, pan);
     if (t == 0 && (!ok || !(minpiv > tau * sqrt(tr)))) {
       atomicOr(&ctrl->flags, CTRL_RANK);
       decision = 1;
@@ -521,7 +530,7 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   }
   if (!decision) {
     const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
-    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail);
+    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail, rkk, pan);
     if (t == 0 && !ok) {
       if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
       else atomicMin(&ctrl->q_eff, block - 1);
@@ -777,8 +786,15 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
   BK_CHOL_WAVE(64)
 #undef BK_CHOL_WAVE
   if (k <= kCholBlockedMax) {
-    chol_blocked_kernel<<<1, CB_THREADS, 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
-                                                 Rinv, work, ctrl);
+    static bool battr = false;
+    const size_t lds = static_cast<size_t>(CB * CB + CB * kCholBlockedMax) * sizeof(double);
+    if (!battr) {
+      hipFuncSetAttribute(reinterpret_cast<const void*>(chol_blocked_kernel),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      battr = true;
+    }
+    chol_blocked_kernel<<<1, CB_THREADS, lds, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
+                                                   Rinv, work, ctrl);
     return;
   }
   chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,

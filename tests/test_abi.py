@@ -66,6 +66,29 @@ def test_workspace_sizes(lib):
     assert lib.bk_eigh_psd_workspace(90) > 90 * 90 * 8
 
 
+def test_block_size_and_method_rules(lib):
+    """Oversampling (block width p >= k) and Simultaneous Iteration are
+    validated at the boundary: the workspace query returns 0 on a bad p."""
+    base = lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(_opt()))
+    o = _opt()
+    o.block_size = 12
+    wide = lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o))
+    assert wide > base                                    # 9 blocks of 12 columns
+    o.block_size = 9                                      # p < k
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) == 0
+    o.block_size = 200                                    # (q+1) p > min(n, d)
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) == 0
+    o.method = 1                                          # Algorithm 1: p <= min(n, d)
+    si = lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o))
+    assert si > 0
+    o.save_for_backward = 1                               # no adjoint for Algorithm 1
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) == 0
+    o = _opt()
+    o.block_size = 30
+    assert lib.bk_svd_csr_workspace(11000, 130000, 1_500_000, 20, 10, C.byref(o)) > \
+        lib.bk_svd_csr_workspace(11000, 130000, 1_500_000, 20, 10, C.byref(_opt()))
+
+
 @pytest.mark.parametrize("n,d,k,q", [(100, 50, 0, 1), (100, 50, 51, 0), (100, 50, 5, -1),
                                      (100, 50, 10, 5), (0, 50, 1, 0)])
 def test_dense_rejects_bad_shapes(lib, n, d, k, q):

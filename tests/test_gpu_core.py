@@ -297,6 +297,46 @@ def test_svd_csr_rejects_malformed():
         bk.svd_csr(_cuda(rp), _cuda(ci), _cuda(va), 3, 3, 1, 0)
 
 
+# ------------------------------------------- oversampling, Algorithm 1 --
+@pytest.mark.parametrize("p", [8, 13])
+def test_oversampling_and_simultaneous_iteration_f64(p):
+    """A p-column sketch (Section 6, p >= k) for Block Krylov Iteration and
+    for Simultaneous Iteration (Algorithm 1), each against the oracle on the
+    same p-column sketch; Block Krylov's Ritz values dominate Simultaneous
+    Iteration's at equal q and p (Courant-Fischer on nested spaces)."""
+    n, d, k, q = 1500, 800, 8, 4
+    sv = workloads.spectrum("inv_sqrt", d)
+    A = workloads.planted_dense(n, d, sv, 61)
+    Pi = philox.gaussian(91, d, p)
+    Ag = _cuda(A)
+    rb = bk.svd_dense(Ag, k, q, seed=91, block_size=p)
+    ref_b = bki.block_krylov(A, Pi, k, q)
+    compare(rb.Z.cpu().numpy(), rb.sigma.cpu().numpy(), ref_b, k, 1e-10, 1e-8)
+    rs = bk.svd_dense(Ag, k, q, seed=91, block_size=p, method="si")
+    ref_s = bki.simultaneous_iteration(A, Pi, k, q)
+    compare(rs.Z.cpu().numpy(), rs.sigma.cpu().numpy(), ref_s, k, 1e-10, 1e-8)
+    assert np.all(rb.sigma.cpu().numpy() >= rs.sigma.cpu().numpy() * (1 - 1e-12))
+    assert rb.Z.shape == (n, k) and rs.Z.shape == (n, k)
+
+
+def test_oversampled_csr_f32():
+    (rp, ci, va), M = _termdoc(1200, 20000, 7)
+    k, p, q = 8, 12, 4
+    ref = bki.block_krylov(M, _pi32(79, 20000, p), k, q, center=True, tau=1e-5)
+    res = bk.svd_csr(_cuda(rp), _cuda(ci), _cuda(va), 1200, 20000, k, q, seed=79,
+                     center=True, block_size=p)
+    compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-5, 1e-4)
+
+
+def test_block_size_validation():
+    A = _cuda(workloads.planted_dense(200, 100, workloads.spectrum("inv", 100), 3))
+    with pytest.raises(ValueError):
+        bk.svd_dense(A, 8, 2, block_size=4)        # p < k
+    with pytest.raises(ValueError):
+        bk.svd_dense(A, 8, 4, block_size=30)       # (q+1) p > min(n, d)
+    bk.svd_dense(A, 8, 4, block_size=30, method="si")   # fine for Algorithm 1
+
+
 # --------------------------------------------------------- low precision --
 def test_quantize_matches_reference():
     rng = np.random.default_rng(4)
