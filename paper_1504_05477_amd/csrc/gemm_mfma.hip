@@ -90,6 +90,20 @@ __device__ __forceinline__ void lds_operand(const uint32_t* tile, int row, int h
   }
 }
 
+// Workgroups go to the eight XCDs in turn (id mod 8).  The column blocks
+// of one row block read the same rows of A, so they get ids on the same
+// XCD, one after another (its L2 then serves the second read):
+// id = 8 (rb_local * ncb + cb) + rb mod 8 with rb_local = rb / 8.  One
+// column block gives id = rb.  Ids past the last row block do nothing.
+__device__ __forceinline__ bool xcd_tile(int64_t id, int64_t nrb, int64_t ncb, int64_t* rb,
+                                         int64_t* cb) {
+  const int64_t xcd = id & 7, slot = id >> 3;
+  *rb = (slot / ncb) * 8 + xcd;
+  *cb = slot % ncb;
+  return *rb < nrb;
+}
+inline int64_t xcd_grid(int64_t nrb, int64_t ncb) { return ((nrb + 7) / 8) * 8 * ncb; }
+
 // Output element (row, col) of a 32 x 32 tile held by lane `lane` in
 // accumulator register v.
 __device__ __forceinline__ int out_row(int lane, int v) {
@@ -109,8 +123,10 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * 128;
-  const int64_t col0 = static_cast<int64_t>(blockIdx.y) * 128;
+  int64_t rb, cb;
+  if (!xcd_tile(blockIdx.x, (n + 127) / 128, (N + 127) / 128, &rb, &cb)) return;
+  const int64_t row0 = rb * 128;
+  const int64_t col0 = cb * 128;
   const int nt = static_cast<int>((N - col0 + 31) / 32 < 4 ? (N - col0 + 31) / 32 : 4);
   const int64_t row = row0 + 32 * w + r32;
   const uint4* arow = reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h;
@@ -320,9 +336,11 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   __shared__ uint32_t As[2][128 * LDS_ROW];
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
-  const int64_t p0 = static_cast<int64_t>(blockIdx.x) * 128;
-  const int64_t r0 = static_cast<int64_t>(blockIdx.y) * 128;
-  const int64_t sidx = blockIdx.z;
+  int64_t pb, rbk;
+  if (!xcd_tile(blockIdx.x, (p + 127) / 128, (r + 127) / 128, &pb, &rbk)) return;
+  const int64_t p0 = pb * 128;
+  const int64_t r0 = rbk * 128;
+  const int64_t sidx = blockIdx.y;
   const int64_t lb = sidx * Ls;
   const int64_t le = (lb + Ls < L) ? lb + Ls : L;
   const int nt = static_cast<int>((r - r0 + 31) / 32 < 4 ? (r - r0 + 31) / 32 : 4);
@@ -503,7 +521,7 @@ static void nn_run(const NNArgs& a, hipStream_t s) {
   int64_t kp = 0, np = 0;
   float* xs = nullptr;
   pack_t<T>(static_cast<const float*>(a.X), a.ldx, a.K, a.N, a.work, &kp, &np, &xs, s);
-  const dim3 grid(static_cast<unsigned>(cdiv(a.n, 128)), static_cast<unsigned>(cdiv(a.N, 128)));
+  const unsigned grid = static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128)));
   nn_mfma_kernel<T, SCALED><<<grid, 256, 0, s>>>(
       a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,
       static_cast<const T*>(a.work), kp, xs, static_cast<float*>(a.C), a.ldc);
@@ -544,7 +562,7 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
     pack_t<T>(static_cast<const float*>(a.Y), a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
     Yt = static_cast<const T*>(a.work);
   }
-  const dim3 grid(static_cast<unsigned>(cdiv(a.p, 128)), static_cast<unsigned>(cdiv(a.r, 128)),
+  const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),
                   static_cast<unsigned>(S));
   tn_mfma_kernel<T, SCALED, PACKED><<<grid, 256, 0, s>>>(
       a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,
