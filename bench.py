@@ -237,7 +237,7 @@ def main():
     per_launch = bx if dom == "ax" else by
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     sha = source_sha(kern_src)
-    kernel_key = f"{'csr_spmm' if w.kind == 'csr' else 'dense_product'}_{dom}_{args.workload}"
+    kernel_key = f"{'csr_product' if w.kind == 'csr' else 'dense_product'}_{dom}_{args.workload}"
     traffic = read_traffic(kernel_key, sha)
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
