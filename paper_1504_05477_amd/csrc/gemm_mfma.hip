@@ -589,6 +589,10 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
   }
   const int S = tn_mfma_splits(a.L, a.p, a.r);
   const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
+  // FP32 operands are transposed through LDS on the fly; with fewer than two
+  // workgroups per CU nothing hides those stores and barriers, and the
+  // vector kernel is faster (e.g. a 220 x 220 Gram over 130000 rows: 4 tiles).
+  if (!packed && cdiv(a.p, 128) * cdiv(a.r, 128) * S < 512) return;
   switch (a.x_type) {
     case BK_F32:
       tn_run<float, false, false>(a, S, Ls, s);

@@ -1,8 +1,10 @@
 // Top-k eigenpairs of the symmetric Rayleigh-Ritz matrix M (Algorithm 2,
 // step 5) for moderate m, in three kernels:
-//   1. Householder reduction M = H T H^T to tridiagonal T (one workgroup;
-//      each step forms a reflector, the symmetric product p = beta M' v and
-//      the rank-2 update M' -= v w^T + w v^T, Golub & Van Loan Sect. 8.3.1);
+//   1. Householder reduction M = H T H^T to tridiagonal T: each step forms
+//      a reflector, the symmetric product p = beta M' v and the rank-2
+//      update M' -= v w^T + w v^T (Golub & Van Loan Sect. 8.3.1); blocked
+//      panels while the trailing block exceeds LDS, then one workgroup with
+//      the block in LDS (for m <= 512; a grid per step beyond);
 //   2. the k largest eigenvalues of T by multisection on Sturm counts, then
 //      their eigenvectors by inverse iteration with a pivoted tridiagonal LU
 //      (vectors of eigenvalues closer than a tiny tolerance are
@@ -16,8 +18,12 @@ namespace bk {
 namespace {
 
 constexpr int TRI_THREADS = 1024;
-constexpr int TRI_LDS_BLOCK = 120;  // trailing blocks up to this order live in LDS
 constexpr int TRI_SMALL = 512;      // one-workgroup reduction up to this order
+constexpr int TRI_NB = 16;          // reflectors per panel of the blocked reduction
+constexpr int TRI_SY = 32;          // tile order of the trailing rank-2 nb update
+// dynamic LDS of the one-workgroup kernels (the static part[] and red[]
+// arrays take the rest of the 160 KB)
+constexpr int TRI_LDS_BYTES = 150 * 1024;
 
 __device__ double block_sum_1024(double v, double* red) {
   const int t = threadIdx.x;
@@ -31,49 +37,185 @@ __device__ double block_sum_1024(double v, double* red) {
   return s;
 }
 
-// A (m x m, ld m, a symmetric copy of M, m <= TRI_THREADS) is reduced in
-// place.  Outputs: reflector j (rows j+1..m-1) in column j of Vh
-// (column-major, ld m), beta[j], diagonal dg[0..m), off-diagonal eo[0..m-1).
-// The symmetric product and the rank-2 update run with threads owning
-// columns of the trailing block (coalesced rows) and RG groups of rows whose
-// partial sums are added in group order.
+// Sum over the workgroup of one value per thread: wave sums by shuffles, then
+// the 16 wave totals in wave order (the same on every thread, so every thread
+// may take decisions on it).  One barrier; `red` must not be written again
+// before a later barrier.
+__device__ double wg_sum_1024(double v, double* red) {
+  const int t = threadIdx.x;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < TRI_THREADS / 64; ++w) s += red[w];
+  return s;
+}
+
+// Steps j_start .. m-3 with the trailing block of order sb0 = m - j_start in
+// LDS (the earlier steps were taken by the panel kernels, which leave A's
+// trailing block at j_start fully updated).  Outputs: reflector j (rows
+// j+1..m-1) in column j of Vh (column-major, ld m), beta[j], diagonal
+// dg[0..m), off-diagonal eo[0..m-1).
+// The rank-2 update of step j-1 is applied lazily: to row j before it forms
+// reflector j, and to the rest of the block in the same pass that forms
+// p = beta M' v_j, so each element is read and written once per step.
+// Threads own columns of the trailing block (RG groups of rows, partial sums
+// added in group order); the reflector's scalars are formed by every thread
+// from the same workgroup sum.
 __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
-    double* __restrict__ A, int64_t m, double* __restrict__ Vh,
+    const double* __restrict__ A, int64_t m, int64_t j_start, double* __restrict__ Vh,
     double* __restrict__ beta, double* __restrict__ dg, double* __restrict__ eo) {
-  extern __shared__ double sm[];  // v, p, w: 3 m doubles; then the LDS block
+  extern __shared__ double sm[];  // v, pv, pw: 3 m doubles; then the block
+  __shared__ double redA[TRI_THREADS / 64], redB[TRI_THREADS / 64];
+  __shared__ double part[TRI_THREADS];
+  const int t = threadIdx.x;
+  const int sb0 = static_cast<int>(m - j_start);
+  double* v = sm;
+  double* pv = sm + m;      // pending update (v, w) of the previous step,
+  double* pw = sm + 2 * m;  // index 0 = the current step's row j
+  double* blk = sm + 3 * m;  // element (i, l) of the trailing square at
+                             // blk[(i - j_start) sb0 + l - j_start]
+  for (int idx = t; idx < sb0 * sb0; idx += TRI_THREADS) {
+    const int r = idx / sb0, c = idx - r * sb0;
+    blk[idx] = A[(j_start + r) * m + j_start + c];
+  }
+  for (int i = t; i < sb0; i += TRI_THREADS) {
+    pv[i] = 0.0;
+    pw[i] = 0.0;
+  }
+  __syncthreads();
+  for (int64_t j = j_start; j + 2 < m; ++j) {
+    const int64_t j1 = j + 1;
+    const int s = static_cast<int>(m - j1);
+    const int o = static_cast<int>(j - j_start);  // block row / column of j
+    double* rowj = blk + o * sb0 + o;
+    // row j with the pending update, columns j .. m-1
+    const double pv0 = pv[0], pw0 = pw[0];
+    double nrm2 = 0.0;
+    for (int l = t; l <= s; l += TRI_THREADS) {
+      const double x = rowj[l] - (pv0 * pw[l] + pw0 * pv[l]);
+      if (l == 0) {
+        dg[j] = x;
+      } else {
+        v[l - 1] = x;
+        nrm2 += x * x;
+      }
+    }
+    nrm2 = wg_sum_1024(nrm2, redA);
+    // reflector scalars on every thread; v[0] stays x0 in LDS, v0 is used
+    // for index 0 from registers
+    const double x0 = v[0];
+    const double nx = sqrt(nrm2);
+    double b = 0.0, alpha = x0, v0 = x0;
+    if (nx > 0.0 && nrm2 - x0 * x0 > 0.0) {
+      alpha = x0 >= 0.0 ? -nx : nx;
+      v0 = x0 - alpha;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+      b = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    }
+    if (t == 0) {
+      eo[j] = alpha;
+      beta[j] = b;
+    }
+    for (int i = t; i < s; i += TRI_THREADS) Vh[j * m + j1 + i] = i == 0 ? v0 : v[i];
+    // fused pass over rows / columns j1 .. m-1: apply the pending update
+    // (pv, pw indexed from row j) and accumulate M' v
+    const int CW = ((s + 63) / 64) * 64;
+    const int RG = TRI_THREADS / CW;
+    const int grp = t / CW, tc = t - grp * CW;
+    const int rlen = (s + RG - 1) / RG;
+    const int r0 = grp * rlen;
+    const int r1 = (r0 + rlen < s) ? r0 + rlen : s;
+    double acc = 0.0;
+    if (grp < RG && tc < s) {
+      const double pvl = pv[1 + tc], pwl = pw[1 + tc];
+      double* col = rowj + sb0 + 1 + tc + r0 * sb0;  // (j1 + r0, j1 + tc)
+#pragma unroll 4
+      for (int i = r0; i < r1; ++i, col += sb0) {
+        const double a = *col - (pv[1 + i] * pwl + pw[1 + i] * pvl);
+        *col = a;
+        acc += a * (i == 0 ? v0 : v[i]);
+      }
+    }
+    part[t] = acc;
+    __syncthreads();
+    double pl = 0.0, vl = 0.0;
+    if (t < s) {
+      double sum = 0.0;
+      for (int g = 0; g < RG; ++g) sum += part[g * CW + t];
+      pl = b * sum;
+      vl = t == 0 ? v0 : v[t];
+    }
+    const double vp = wg_sum_1024(vl * pl, redB);
+    const double K = 0.5 * b * vp;
+    // the pending update of the next step, indexed from row j1
+    if (t < s) {
+      pv[t] = vl;
+      pw[t] = pl - K * vl;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    // last 2 x 2 block with the pending update of step m-3 applied
+    if (m >= 2) {
+      const int o = sb0 - 2;
+      const double* b2 = blk + o * sb0 + o;
+      dg[m - 2] = b2[0] - 2.0 * pv[0] * pw[0];
+      dg[m - 1] = b2[sb0 + 1] - 2.0 * pv[1] * pw[1];
+      eo[m - 2] = b2[sb0] - (pv[1] * pw[0] + pw[1] * pv[0]);
+    } else {
+      dg[0] = A[0];
+    }
+  }
+}
+
+// ------------------------------------------ blocked steps (m <= TRI_SMALL) --
+// While the trailing block is too large for LDS, reflectors are formed in
+// panels of up to TRI_NB steps (the blocked reduction of Golub & Van Loan
+// Sect. 8.3.1, as in LAPACK's sytrd): inside a panel the trailing block keeps
+// its value A0 from the panel's start and the current matrix is
+// A0 - V W^T - W V^T, V and W holding the panel's reflectors v_q and their
+// vectors w_q = p_q - K_q v_q (zero above row j_q + 1).  A step reads A0 once
+// for A0 v and corrects the product with V (W^T v) + W (V^T v); the
+// rank-2 nb update of A0 runs once per panel over the whole chip.
+
+// One workgroup, steps j0 .. j0 + nst - 1.  V and W live in LDS column by
+// column (ld mr = m - j0, row x is row j0 + x); on exit their rows from
+// j0 + nst on go to Vg, Wg (column q at q m, ld m, absolute rows).
+__global__ __launch_bounds__(TRI_THREADS) void tri_panel_kernel(
+    const double* __restrict__ A, int64_t m, int64_t j0, int nst, double* __restrict__ Vg,
+    double* __restrict__ Wg, double* __restrict__ Vh, double* __restrict__ beta,
+    double* __restrict__ dg, double* __restrict__ eo) {
+  extern __shared__ double sm[];  // v[m], p[m], c[2 TRI_NB], V, W [TRI_NB x mr]
   __shared__ double red[TRI_THREADS / 64];
   __shared__ double part[TRI_THREADS];
   __shared__ double s_beta;
+  const int64_t mr = m - j0;
   double* v = sm;
-  double* p = sm + m;
-  double* w = sm + 2 * m;
-  double* blk = sm + 3 * m;  // TRI_LDS_BLOCK^2 doubles
+  double* p = v + m;
+  double* c = p + m;
+  double* V = c + 2 * TRI_NB;
+  double* W = V + TRI_NB * mr;
   const int t = threadIdx.x;
-  // Element (i, l) of the trailing matrix lives at base[(i - off) ld + l - off]:
-  // in A (global, off 0) until it fits in LDS, then in blk.
-  double* base = A;
-  int64_t ld = m, off = 0;
-  for (int64_t j = 0; j + 2 < m; ++j) {
-    const int64_t j1 = j + 1;
+  for (int64_t idx = t; idx < 2 * TRI_NB * mr; idx += TRI_THREADS) V[idx] = 0.0;
+  __syncthreads();
+  for (int jj = 0; jj < nst; ++jj) {
+    const int64_t j = j0 + jj, j1 = j + 1;
     const int s = static_cast<int>(m - j1);
-    if (base == A && m - j <= TRI_LDS_BLOCK) {
-      const int64_t sb = m - j;
-      for (int64_t idx = t; idx < sb * sb; idx += TRI_THREADS) {
-        const int64_t r = idx / sb, c = idx - r * sb;
-        blk[idx] = A[(j + r) * m + j + c];
-      }
-      __syncthreads();
-      base = blk;
-      ld = sb;
-      off = j;
-    }
-    double* rowj = base + (j - off) * ld + (j1 - off);
-    // x = column j below the diagonal = row j right of it (symmetric)
+    // row j of the current matrix, columns j .. m-1 (x = panel row)
     double nrm2 = 0.0;
-    for (int i = t; i < s; i += TRI_THREADS) {
-      const double x = rowj[i];
-      v[i] = x;
-      nrm2 += x * x;
+    for (int l = t; l <= s; l += TRI_THREADS) {
+      const int64_t xl = jj + l;
+      double x = A[j * m + j + l];
+      for (int q = 0; q < jj; ++q)
+        x -= V[q * mr + jj] * W[q * mr + xl] + W[q * mr + jj] * V[q * mr + xl];
+      if (l == 0) {
+        dg[j] = x;
+      } else {
+        v[l - 1] = x;
+        nrm2 += x * x;
+      }
     }
     nrm2 = block_sum_1024(nrm2, red);
     if (t == 0) {
@@ -88,14 +230,13 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
         v[0] = v0;
       }
       s_beta = b;
-      dg[j] = base[(j - off) * ld + (j - off)];
       eo[j] = alpha;
       beta[j] = b;
     }
     __syncthreads();
     const double b = s_beta;
     for (int i = t; i < s; i += TRI_THREADS) Vh[j * m + j1 + i] = v[i];
-    if (b == 0.0) {  // column already reduced (uniform branch)
+    if (b == 0.0) {  // column already reduced: V, W columns jj stay zero
       __syncthreads();
       continue;
     }
@@ -105,26 +246,38 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
     const int rlen = (s + RG - 1) / RG;
     const int r0 = grp * rlen;
     const int r1 = (r0 + rlen < s) ? r0 + rlen : s;
-    // p = b M' v, p_l = sum_i M'[i][l] v_i
+    // A0' v over rows / columns j1 .. m-1
     double acc = 0.0;
     if (tc < s) {
-      const double* col = base + (j1 + r0 - off) * ld + (j1 - off) + tc;
+      const double* col = A + (j1 + r0) * m + j1 + tc;
       int i = r0;
-      // eight independent loads in flight per thread
-      for (; i + 8 <= r1; i += 8, col += 8 * ld) {
+      for (; i + 8 <= r1; i += 8, col += 8 * m) {
         double a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[u * ld];
+        for (int u = 0; u < 8; ++u) a[u] = col[u * m];
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc += a[u] * v[i + u];
       }
-      for (; i < r1; ++i, col += ld) acc += *col * v[i];
+      for (; i < r1; ++i, col += m) acc += *col * v[i];
     }
     part[t] = acc;
+    // c[q] = W'^T v, c[jj + q] = V'^T v over the panel rows of j1 .. m-1
+    {
+      const int wv = t >> 6, ln = t & 63;
+      for (int qq = wv; qq < 2 * jj; qq += TRI_THREADS / 64) {
+        const double* colq = (qq < jj ? W + qq * mr : V + (qq - jj) * mr) + jj + 1;
+        double sum = 0.0;
+        for (int i = ln; i < s; i += 64) sum += colq[i] * v[i];
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        if (ln == 0) c[qq] = sum;
+      }
+    }
     __syncthreads();
     if (t < s) {
       double sum = 0.0;
       for (int g = 0; g < RG; ++g) sum += part[g * CW + t];
+      const int64_t xl = jj + 1 + t;
+      for (int q = 0; q < jj; ++q) sum -= V[q * mr + xl] * c[q] + W[q * mr + xl] * c[jj + q];
       p[t] = b * sum;
     }
     __syncthreads();
@@ -132,33 +285,55 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
     for (int i = t; i < s; i += TRI_THREADS) vp += v[i] * p[i];
     vp = block_sum_1024(vp, red);
     const double K = 0.5 * b * vp;
-    for (int i = t; i < s; i += TRI_THREADS) w[i] = p[i] - K * v[i];
-    __syncthreads();
-    // M' -= v w^T + w v^T
-    if (tc < s) {
-      const double vl = v[tc], wl = w[tc];
-      double* col = base + (j1 + r0 - off) * ld + (j1 - off) + tc;
-      int i = r0;
-      for (; i + 8 <= r1; i += 8, col += 8 * ld) {
-        double a[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[u * ld];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) col[u * ld] = a[u] - (v[i + u] * wl + w[i + u] * vl);
-      }
-      for (; i < r1; ++i, col += ld) *col -= v[i] * wl + w[i] * vl;
+    for (int i = t; i < s; i += TRI_THREADS) {
+      const int64_t xi = jj + 1 + i;
+      V[jj * mr + xi] = v[i];
+      W[jj * mr + xi] = p[i] - K * v[i];
     }
     __syncthreads();
   }
-  if (t == 0) {
-    auto el = [&](int64_t i, int64_t l) { return base[(i - off) * ld + (l - off)]; };
-    if (m >= 2) {
-      dg[m - 2] = el(m - 2, m - 2);
-      dg[m - 1] = el(m - 1, m - 1);
-      eo[m - 2] = el(m - 1, m - 2);
-    } else {
-      dg[0] = A[0];
-    }
+  const int64_t jn = j0 + nst;
+  for (int64_t idx = t; idx < TRI_NB * (m - jn); idx += TRI_THREADS) {
+    const int64_t q = idx / (m - jn), i = jn + idx - q * (m - jn);
+    Vg[q * m + i] = V[q * mr + (i - j0)];
+    Wg[q * m + i] = W[q * mr + (i - j0)];
+  }
+}
+
+// A0[i][l] -= sum_q V[i][q] W[l][q] + W[i][q] V[l][q] over the trailing
+// square i, l >= jn; TRI_SY x TRI_SY tiles, a thread per column and every
+// eighth row of its tile.
+__global__ __launch_bounds__(256) void tri_syr2k_kernel(double* __restrict__ A, int64_t m,
+                                                        int64_t jn, const double* __restrict__ Vg,
+                                                        const double* __restrict__ Wg, int nst) {
+  __shared__ double vr[TRI_NB][TRI_SY], wr[TRI_NB][TRI_SY];
+  const int t = threadIdx.x;
+  const int64_t i0 = jn + static_cast<int64_t>(blockIdx.y) * TRI_SY;
+  const int64_t l0 = jn + static_cast<int64_t>(blockIdx.x) * TRI_SY;
+  for (int idx = t; idx < TRI_NB * TRI_SY; idx += 256) {
+    const int q = idx / TRI_SY, r = idx - q * TRI_SY;
+    const int64_t i = i0 + r;
+    const bool ok = q < nst && i < m;
+    vr[q][r] = ok ? Vg[q * m + i] : 0.0;
+    wr[q][r] = ok ? Wg[q * m + i] : 0.0;
+  }
+  __syncthreads();
+  const int tx = t & (TRI_SY - 1), ty = t / TRI_SY;
+  const int64_t l = l0 + tx;
+  if (l >= m) return;
+  double vl[TRI_NB], wl[TRI_NB];
+#pragma unroll
+  for (int q = 0; q < TRI_NB; ++q) {
+    vl[q] = q < nst ? Vg[q * m + l] : 0.0;
+    wl[q] = q < nst ? Wg[q * m + l] : 0.0;
+  }
+  for (int r = ty; r < TRI_SY; r += 256 / TRI_SY) {
+    const int64_t i = i0 + r;
+    if (i >= m) break;
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < TRI_NB; ++q) sum += vr[q][r] * wl[q] + wr[q][r] * vl[q];
+    A[i * m + l] -= sum;
   }
 }
 
@@ -257,7 +432,7 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
     const double* __restrict__ dgg, const double* __restrict__ eog, int64_t m, int k,
     double* __restrict__ theta, double* __restrict__ X, double* __restrict__ scratch,
     int* __restrict__ iscratch) {
-  extern __shared__ double sm[];  // dg (m), eo (m), e2 (m), lo (k), hi (k)
+  extern __shared__ double sm[];  // dg (m), eo (m), e2 (m), lo (k), hi (k), best (k ints)
   __shared__ int s_done;
   __shared__ double s_tnorm;
   double* dg = sm;
@@ -265,6 +440,7 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
   double* e2 = sm + 2 * m;
   double* lo = sm + 3 * m;
   double* hi = lo + k;
+  int* best = reinterpret_cast<int*>(hi + k);
   const int t = threadIdx.x;
   for (int64_t i = t; i < m; i += TRI_THREADS) {
     dg[i] = dgg[i];
@@ -291,36 +467,38 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
   const double tnorm = s_tnorm;
   const double pivmin = 1e-290 + 2.2e-16 * 2.2e-16 * tnorm * tnorm * 1e-10;
   // Multisection: P threads per eigenvalue evaluate the count at P interior
-  // points; the bracket [lo, hi] of the c-th largest shrinks P+1 fold.
+  // points x_0 < ... < x_{P-1} of the bracket [lo, hi] of the c-th largest
+  // (count(lo) <= target < count(hi), target its ascending index); the new
+  // bracket is [x_b, x_{b+1}] for b the last point with count <= target
+  // (lo for b = -1, hi for b = P-1), P+1 fold smaller.
   const int P = k >= TRI_THREADS ? 1 : TRI_THREADS / k;
+  auto settled = [&](double l, double h) {
+    return h - l <= 2.2e-16 * fmax(fabs(l), fabs(h)) * 2.0 + 1e-18 * tnorm + 1e-300;
+  };
+  auto point = [&](double l, double h, int pp) {
+    return l + (h - l) * static_cast<double>(pp + 1) / static_cast<double>(P + 1);
+  };
   for (int it = 0; it < 200; ++it) {
     if (t == 0) s_done = 1;
+    for (int c = t; c < k; c += TRI_THREADS) best[c] = -1;
     __syncthreads();
-    double* cnts = scratch;  // k * P ints stored as doubles
     for (int idx = t; idx < k * P; idx += TRI_THREADS) {
-      const int c = idx / P, pp = idx % P;
+      const int c = idx / P, pp = idx - c * P;
       const double l = lo[c], h = hi[c];
-      const double x = l + (h - l) * static_cast<double>(pp + 1) / static_cast<double>(P + 1);
-      cnts[idx] = static_cast<double>(sturm_count(dg, e2, m, x, pivmin));
+      if (settled(l, h)) continue;
+      const int target = static_cast<int>(m) - 1 - c;
+      if (sturm_count(dg, e2, m, point(l, h, pp), pivmin) <= target) atomicMax(&best[c], pp);
     }
     __syncthreads();
     for (int c = t; c < k; c += TRI_THREADS) {
       const double l = lo[c], h = hi[c];
-      if (h - l <= 2.2e-16 * fmax(fabs(l), fabs(h)) * 2.0 + 1e-18 * tnorm + 1e-300) continue;
-      const int target = static_cast<int>(m) - 1 - c;  // ascending index
-      double nl = l, nh = h;
-      for (int pp = 0; pp < P; ++pp) {
-        const double x = l + (h - l) * static_cast<double>(pp + 1) / static_cast<double>(P + 1);
-        if (cnts[c * P + pp] > target) {
-          nh = x;
-          break;
-        }
-        nl = x;
-      }
+      if (settled(l, h)) continue;
+      const int b = best[c];
+      const double nl = b >= 0 ? point(l, h, b) : l;
+      const double nh = b + 1 < P ? point(l, h, b + 1) : h;
       lo[c] = nl;
       hi[c] = nh;
-      if (nh - nl > 2.2e-16 * fmax(fabs(nl), fabs(nh)) * 2.0 + 1e-18 * tnorm + 1e-300)
-        s_done = 0;
+      if (!settled(nl, nh)) s_done = 0;
     }
     __syncthreads();
     if (s_done) break;
@@ -560,11 +738,12 @@ __global__ __launch_bounds__(256) void sym_copy_kernel(const double* __restrict_
 
 int64_t tridiag_scratch_doubles(int64_t m, int k) {
   // A copy + Vh + beta/dg/eo + X + solver scratch (5 m per eigenvalue) +
-  // pivots (k m ints) + (large m) v, vp, wp and the row-group partials
+  // pivots (k m ints) + (large m) v, vp, wp and the row-group partials +
+  // (small m) the panel's V and W
   const int64_t groups = cdiv(m, TBG_ROWS);
   return 2 * m * m + 3 * m + static_cast<int64_t>(k) * m +
          std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024) +
-         (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 64;
+         (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64;
 }
 
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double* scratch,
@@ -583,20 +762,38 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   double* vp = v + m;
   double* wp = vp + m;
   double* part = wp + m;
+  double* Vg = part + cdiv(m, TBG_ROWS) * m;
+  double* Wg = Vg + TRI_NB * m;
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_reduce_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-    hipFuncSetAttribute(reinterpret_cast<const void*>(tridiag_topk_kernel),
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    for (const void* f : {reinterpret_cast<const void*>(tridiag_reduce_kernel),
+                          reinterpret_cast<const void*>(tridiag_topk_kernel),
+                          reinterpret_cast<const void*>(tri_panel_kernel)})
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, TRI_LDS_BYTES);
     attr = true;
   }
   sym_copy_kernel<<<static_cast<unsigned>(cdiv(m * m, 256)), 256, 0, s>>>(M, m, ldm, A);
   launch_fill_f64(Vh, m * m, 0.0, s);
   if (m <= TRI_SMALL) {
-    const int64_t sb = m < TRI_LDS_BLOCK ? m : TRI_LDS_BLOCK;
-    tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + sb * sb) * sizeof(double), s>>>(
-        A, m, Vh, beta, dg, eo);
+    // order of the largest trailing block that fits in LDS beside v, p, w
+    const int64_t room = TRI_LDS_BYTES / static_cast<int64_t>(sizeof(double)) - 3 * m;
+    int64_t sb = static_cast<int64_t>(std::sqrt(static_cast<double>(room)));
+    while (sb * sb > room) --sb;
+    if (sb > m) sb = m;
+    // blocked panels until the trailing block fits (sb >= 3 keeps every
+    // panel step a full reflector step, j + 2 < m)
+    int64_t j = 0;
+    while (m - j > sb) {
+      const int nst = static_cast<int>(std::min<int64_t>(TRI_NB, m - sb - j));
+      const size_t lds = (2 * m + 2 * TRI_NB + 2 * TRI_NB * (m - j)) * sizeof(double);
+      tri_panel_kernel<<<1, TRI_THREADS, lds, s>>>(A, m, j, nst, Vg, Wg, Vh, beta, dg, eo);
+      const int64_t jn = j + nst;
+      const unsigned g = static_cast<unsigned>(cdiv(m - jn, TRI_SY));
+      tri_syr2k_kernel<<<dim3(g, g), 256, 0, s>>>(A, m, jn, Vg, Wg, nst);
+      j = jn;
+    }
+    tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + (m - j) * (m - j)) * sizeof(double), s>>>(
+        A, m, j, Vh, beta, dg, eo);
   } else {
     launch_fill_f64(v, 3 * m, 0.0, s);  // v, vp, wp
     int G = 0;
@@ -612,7 +809,7 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, m - 2, v, vp, wp, part,
                                                                   G, Vh, beta, dg, eo);
   }
-  tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 2 * k) * sizeof(double), s>>>(dg, eo, m, k,
+  tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 3 * k) * sizeof(double), s>>>(dg, eo, m, k,
                                                                              theta, X, sol, piv);
   const unsigned gb = static_cast<unsigned>(cdiv(k, 4));
   if (m <= 1024)

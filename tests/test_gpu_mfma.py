@@ -58,7 +58,9 @@ def _operands(prec, A, X):
 @pytest.mark.parametrize("trans", [False, True])
 def test_mfma_block_products(prec, trans):
     rng = np.random.default_rng(17)
-    n, d, k = (10000, 1024, 52) if trans else (1500, 1024, 52)
+    # A^T X: 16 column tiles x 32 row splits = 512 workgroups, the smallest
+    # FP32 grid that stays on the matrix cores
+    n, d, k = (20000, 2048, 52) if trans else (1500, 1024, 52)
     A = rng.standard_normal((n, d)).astype(np.float32)
     X = rng.standard_normal((n if trans else d, k)).astype(np.float32)
     Aq, sc, Ad, Xd = _operands(prec, A, X)
