@@ -78,9 +78,12 @@ typedef struct bk_options {
   double breakdown_tol;      /* tau: block i >= 1 whose projected residual
                                 has ||.||_F <= tau * (||.||_F before the
                                 projection) ends the iteration (q_eff = i-1);
-                                block 0 with a Cholesky pivot <= tau ||A Pi||_F
-                                gives BK_ERANK.  Default 1e-11 for F64,
-                                1e-5 otherwise.                              */
+                                block 0 with a pivot of the Cholesky factor
+                                of (A Pi)^T (A Pi) <= max(tau, sqrt(11 (n k +
+                                k (k+1)) u)) ||A Pi||_F (u = 2^-53: below
+                                that, the Gram's rounding decides) gives
+                                BK_ERANK.  Default 1e-11 for F64, 1e-5
+                                otherwise.                                   */
   const void* pi;            /* nullable: explicit d x k sketch, row-major,
                                 ld = k, FP64 for BK_F64 else FP32; overrides
                                 the seed                                     */

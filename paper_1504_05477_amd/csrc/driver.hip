@@ -244,7 +244,8 @@ struct EventPool {
   hipEvent_t get() {
     if (used == ev.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      // timing only: no system-scope fence (cache write-back) at each record
+      if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
       ev.push_back(e);
     }
     return ev[used++];
@@ -423,7 +424,8 @@ struct Solver {
   // G (p x r FP64, ld r) = X^T Y, X L x p (ldx), Y L x r (ldy), both the
   // working type.
   void gram(const void* X, int64_t ldx, int64_t p, const void* Y, int64_t ldy,
-            int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0) {
+            int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0,
+            bool sym = false) {
     TNArgs a;
     a.L = Lrows;
     a.p = p;
@@ -440,6 +442,7 @@ struct Solver {
     a.alpha = alpha;
     a.beta = beta;
     a.partial = L->partial;
+    a.sym = sym && X == Y && ldx == ldy && p == r;
     launch_tn(a, s);
   }
   // C (rows x N, ldc) = alpha A (rows x K, lda) Xf (K x N FP64, ldx) + beta C
@@ -635,7 +638,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
 
   // Step 4: M = W^T W = Q^T A A^T Q in FP64.
   tm.begin(BK_PH_M);
-  S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M);
+  S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M, 1.0, 0.0, true);
   tm.end(2);
   BK_TRY_LAUNCH();
 

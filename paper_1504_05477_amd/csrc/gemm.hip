@@ -30,7 +30,9 @@ __global__ __launch_bounds__(256) void nn_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = ACC(0);
 
-  for (int64_t k0 = 0; k0 < K; k0 += NN_BK) {
+  // the next K chunk is loaded into registers while this one is multiplied
+  ACC ar[8], xr[4];
+  auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int e = t + 256 * i;
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(256) void nn_kernel(
         v = static_cast<ACC>(Elem<TA>::load(A, gr * lda + gk));
         if (SCALED) v *= static_cast<ACC>(ascale[(gr >> 7) * ascale_ld + (gk >> 7)]);
       }
-      As[kk][r] = v;
+      ar[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -49,9 +51,23 @@ __global__ __launch_bounds__(256) void nn_kernel(
       const int kk = e >> 5, c = e & 31;
       const int64_t gk = k0 + kk;
       const int gc = col0 + c;
-      Xs[kk][c] = (gk < K && gc < N) ? static_cast<ACC>(X[gk * ldx + gc]) : ACC(0);
+      xr[i] = (gk < K && gc < N) ? static_cast<ACC>(X[gk * ldx + gc]) : ACC(0);
+    }
+  };
+  if (K > 0) load(0);
+  for (int64_t k0 = 0; k0 < K; k0 += NN_BK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      As[e & 31][e >> 5] = ar[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = t + 256 * i;
+      Xs[e >> 5][e & 31] = xr[i];
     }
     __syncthreads();
+    if (k0 + NN_BK < K) load(k0 + NN_BK);
 #pragma unroll 8
     for (int kk = 0; kk < NN_BK; ++kk) {
       const ACC a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
@@ -88,12 +104,13 @@ __global__ __launch_bounds__(256) void tn_kernel(
     int64_t L, int64_t p, int r, const TX* __restrict__ X, int64_t ldx,
     const float* __restrict__ xscale, int64_t xscale_ld,
     const TY* __restrict__ Y, int64_t ldy, double* __restrict__ partial,
-    int64_t Ls) {
+    int64_t Ls, int sym) {
   __shared__ ACC Xs[TN_BL][TN_BP];
   __shared__ ACC Ys[TN_BL][TN_BR];
   const int t = threadIdx.x;
   const int64_t p0 = static_cast<int64_t>(blockIdx.x) * TN_BP;
   const int r0 = blockIdx.y * TN_BR;
+  if (sym && p0 > r0 + TN_BR - 1) return;  // below the diagonal: mirrored
   const int64_t s = blockIdx.z;
   const int64_t lb = s * Ls;
   const int64_t le = (lb + Ls < L) ? lb + Ls : L;
@@ -105,7 +122,9 @@ __global__ __launch_bounds__(256) void tn_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) dacc[i][j] = 0.0;
 
-  for (int64_t l0 = lb; l0 < le; l0 += TN_BL) {
+  // the next chunk is loaded into registers while this one is multiplied
+  ACC xr[8], yr[4];
+  auto load = [&](int64_t l0) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int e = t + 256 * i;
@@ -116,7 +135,7 @@ __global__ __launch_bounds__(256) void tn_kernel(
         v = static_cast<ACC>(Elem<TX>::load(X, gl * ldx + gp));
         if (SCALED) v *= static_cast<ACC>(xscale[(gl >> 7) * xscale_ld + (gp >> 7)]);
       }
-      Xs[ll][pp] = v;
+      xr[i] = v;
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -124,9 +143,23 @@ __global__ __launch_bounds__(256) void tn_kernel(
       const int ll = e >> 5, rr = e & 31;
       const int64_t gl = l0 + ll;
       const int gr = r0 + rr;
-      Ys[ll][rr] = (gl < le && gr < r) ? static_cast<ACC>(Y[gl * ldy + gr]) : ACC(0);
+      yr[i] = (gl < le && gr < r) ? static_cast<ACC>(Y[gl * ldy + gr]) : ACC(0);
+    }
+  };
+  if (lb < le) load(lb);
+  for (int64_t l0 = lb; l0 < le; l0 += TN_BL) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = t + 256 * i;
+      Xs[e >> 6][e & 63] = xr[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int e = t + 256 * i;
+      Ys[e >> 5][e & 31] = yr[i];
     }
     __syncthreads();
+    if (l0 + TN_BL < le) load(l0 + TN_BL);
     ACC acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -161,16 +194,19 @@ __global__ __launch_bounds__(256) void tn_kernel(
   }
 }
 
+// sym: X = Y, only partials on or above the diagonal exist; (gp, gr) below
+// it takes the sums of (gr, gp), so C is exactly symmetric.
 template <typename TC>
 __global__ __launch_bounds__(256) void tn_reduce_kernel(
     int S, int64_t p, int r, const double* __restrict__ partial,
-    TC* __restrict__ C, int64_t ldc, double alpha, double beta) {
+    TC* __restrict__ C, int64_t ldc, double alpha, double beta, int sym) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= p * r) return;
   const int64_t gp = idx / r;
   const int gr = static_cast<int>(idx - gp * r);
+  const int64_t src = (sym && gp > gr) ? static_cast<int64_t>(gr) * r + gp : gp * r + gr;
   double acc = 0.0;
-  for (int i = 0; i < S; ++i) acc += partial[(i * p + gp) * r + gr];
+  for (int i = 0; i < S; ++i) acc += partial[i * p * r + src];
   double v = alpha * acc;
   if (beta != 0.0) v += beta * static_cast<double>(C[gp * ldc + gr]);
   C[gp * ldc + gr] = static_cast<TC>(v);
@@ -181,14 +217,15 @@ __global__ __launch_bounds__(256) void tn_reduce_kernel(
 template <typename TC>
 __global__ __launch_bounds__(256) void tn_reduce_wave_kernel(
     int S, int64_t p, int r, const double* __restrict__ partial,
-    TC* __restrict__ C, int64_t ldc, double alpha, double beta) {
+    TC* __restrict__ C, int64_t ldc, double alpha, double beta, int sym) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (idx >= p * r) return;
   const int lane = threadIdx.x & 63;
   const int64_t gp = idx / r;
   const int gr = static_cast<int>(idx - gp * r);
+  const int64_t src = (sym && gp > gr) ? static_cast<int64_t>(gr) * r + gp : gp * r + gr;
   double acc = 0.0;
-  for (int i = lane; i < S; i += 64) acc += partial[(i * p + gp) * r + gr];
+  for (int i = lane; i < S; i += 64) acc += partial[i * p * r + src];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
   if (lane == 0) {
@@ -237,18 +274,18 @@ void tn_dispatch(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
     const double* Y = static_cast<const double*>(a.Y);
     if (a.xscale)
       tn_kernel<TX, double, ACC, true><<<grid, 256, 0, s>>>(
-          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls);
+          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls, a.sym ? 1 : 0);
     else
       tn_kernel<TX, double, ACC, false><<<grid, 256, 0, s>>>(
-          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls);
+          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls, a.sym ? 1 : 0);
   } else {
     const float* Y = static_cast<const float*>(a.Y);
     if (a.xscale)
       tn_kernel<TX, float, ACC, true><<<grid, 256, 0, s>>>(
-          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls);
+          a.L, a.p, a.r, X, a.ldx, a.xscale, a.xscale_ld, Y, a.ldy, a.partial, Ls, a.sym ? 1 : 0);
     else
       tn_kernel<TX, float, ACC, false><<<grid, 256, 0, s>>>(
-          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls);
+          a.L, a.p, a.r, X, a.ldx, nullptr, 0, Y, a.ldy, a.partial, Ls, a.sym ? 1 : 0);
   }
 }
 
@@ -280,7 +317,7 @@ int launch_nn(const NNArgs& a, hipStream_t s) {
 
 int tn_splits(int64_t L, int64_t p, int r) {
   const int64_t tiles = cdiv(p, TN_BP) * cdiv(r, TN_BR);
-  int64_t S = cdiv(1024, tiles);
+  int64_t S = cdiv(2048, tiles);
   const int64_t smax = cdiv(L, 64);
   if (S > smax) S = smax;
   if (S < 1) S = 1;
@@ -327,28 +364,29 @@ int launch_tn(const TNArgs& a, hipStream_t s) {
   }
   // kernels before the reduction: fill, VALU split kernel, or pack + MFMA
   const int before = mfma ? (a.x_type == BK_F32 ? 1 : 2) : 1;
+  const int sym = (a.sym && a.L > 0) ? 1 : 0;
   const int64_t outs = a.p * a.r;
   if (S >= 16 && outs <= (int64_t(1) << 16)) {
     const unsigned g = static_cast<unsigned>(cdiv(outs, 4));
     if (a.c_f64)
       tn_reduce_wave_kernel<double><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                                       static_cast<double*>(a.C), a.ldc,
-                                                      a.alpha, a.beta);
+                                                      a.alpha, a.beta, sym);
     else
       tn_reduce_wave_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                                      static_cast<float*>(a.C), a.ldc,
-                                                     a.alpha, a.beta);
+                                                     a.alpha, a.beta, sym);
     return before + 1;
   }
   const unsigned g = static_cast<unsigned>(cdiv(outs, 256));
   if (a.c_f64)
     tn_reduce_kernel<double><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                                static_cast<double*>(a.C), a.ldc,
-                                               a.alpha, a.beta);
+                                               a.alpha, a.beta, sym);
   else
     tn_reduce_kernel<float><<<g, 256, 0, s>>>(S, a.p, a.r, a.partial,
                                               static_cast<float*>(a.C), a.ldc,
-                                              a.alpha, a.beta);
+                                              a.alpha, a.beta, sym);
   return before + 1;
 }
 

@@ -331,13 +331,14 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
     int64_t L, int64_t p, int r, const T* __restrict__ X, int64_t ldx,
     const float* __restrict__ xscale, int64_t xscale_ld, const float* __restrict__ Yraw,
     int64_t ldy, const T* __restrict__ Yt, int64_t ldyt, const float* __restrict__ yscale,
-    double* __restrict__ partial, int64_t Ls) {
+    double* __restrict__ partial, int64_t Ls, int sym) {
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
   __shared__ uint32_t As[2][128 * LDS_ROW];
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
   int64_t pb, rbk;
   if (!xcd_tile(blockIdx.x, (p + 127) / 128, (r + 127) / 128, &pb, &rbk)) return;
+  if (sym && pb > rbk) return;  // below the diagonal: mirrored by the reduction
   const int64_t p0 = pb * 128;
   const int64_t r0 = rbk * 128;
   const int64_t sidx = blockIdx.y;
@@ -566,7 +567,7 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
                   static_cast<unsigned>(S));
   tn_mfma_kernel<T, SCALED, PACKED><<<grid, 256, 0, s>>>(
       a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,
-      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls);
+      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls, a.sym ? 1 : 0);
 }
 
 void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {

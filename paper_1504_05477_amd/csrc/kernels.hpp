@@ -62,6 +62,9 @@ struct TNArgs {
   // scratch for the matrix-core path (Y^T packed in X's type), nullable
   void* work = nullptr;
   size_t work_bytes = 0;
+  // X and Y the same matrix (p = r): tiles below the diagonal are skipped and
+  // C mirrored from above it
+  bool sym = false;
 };
 int tn_splits(int64_t L, int64_t p, int r);
 int64_t tn_partial_elems(int64_t L, int64_t p, int r);

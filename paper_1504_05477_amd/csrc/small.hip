@@ -99,10 +99,19 @@ __device__ bool chol_factor(int k, const double* G, double shift, double* S,
   return true;
 }
 
+// Relative size below which a pivot of the unshifted factor of A Pi counts
+// as zero: tau, but at least sqrt(shift_coef), the level of the shift that
+// the first CholeskyQR pass adds anyway.  The Gram of an exactly rank
+// deficient block has pivots of rounding size (~ n u tr) of either sign, so
+// a smaller threshold would decide by the summation order.
+__device__ __forceinline__ double rank_floor(double tau, double shift_coef) {
+  return fmax(tau, sqrt(shift_coef));
+}
+
 // Modes:
-//  CHOL_FIRST_BLOCK0  first pass on A Pi: a Cholesky pivot <= tau ||A Pi||_F
-//                     (unshifted factor) flags CTRL_RANK; then the shifted
-//                     factor (shift = shift_coef * trace(G)).
+//  CHOL_FIRST_BLOCK0  first pass on A Pi: a Cholesky pivot of the unshifted
+//                     factor <= rank_floor ||A Pi||_F flags CTRL_RANK; then
+//                     the shifted factor (shift = shift_coef * trace(G)).
 //  CHOL_FIRST         first pass on a projected block i >= 1: when
 //                     ||B||_F <= tau * ||B_pre||_F (traces of G and Gpre)
 //                     the Krylov space is invariant: q_eff = min(q_eff,
@@ -154,7 +163,7 @@ __global__ __launch_bounds__(256) void chol_kernel(int k, const double* G,
   __syncthreads();
   if (!decision && mode == CHOL_FIRST_BLOCK0) {
     const bool ok = chol_factor(k, G, 0.0, S, &minpiv, &fail);
-    if (t == 0 && (!ok || !(minpiv > tau * sqrt(tr)))) {
+    if (t == 0 && (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr)))) {
       atomicOr(&ctrl->flags, CTRL_RANK);
       decision = 1;
     }
@@ -275,7 +284,7 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
   double minpiv = 0.0;
   if (!zero && mode == CHOL_FIRST_BLOCK0) {
     const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv);
-    if (!ok || !(minpiv > tau * sqrt(tr))) {
+    if (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr))) {
       if (c == 0) atomicOr(&ctrl->flags, CTRL_RANK);
       zero = true;
     }
@@ -522,7 +531,7 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   __syncthreads();
   if (!decision && mode == CHOL_FIRST_BLOCK0) {
     const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail, rkk, pan);
-    if (t == 0 && (!ok || !(minpiv > tau * sqrt(tr)))) {
+    if (t == 0 && (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr)))) {
       atomicOr(&ctrl->flags, CTRL_RANK);
       decision = 1;
     }
@@ -767,7 +776,7 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
   const int use_lds = k <= 96 ? 1 : 0;
   static bool attr_set = false;
   if (!attr_set) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(chol_kernel),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_kernel),
                         hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     attr_set = true;
   }
@@ -789,7 +798,7 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
     static bool battr = false;
     const size_t lds = static_cast<size_t>(CB * CB + CB * kCholBlockedMax) * sizeof(double);
     if (!battr) {
-      hipFuncSetAttribute(reinterpret_cast<const void*>(chol_blocked_kernel),
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_blocked_kernel),
                           hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
       battr = true;
     }

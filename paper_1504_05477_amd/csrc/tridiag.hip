@@ -337,16 +337,45 @@ __global__ __launch_bounds__(256) void tri_syr2k_kernel(double* __restrict__ A, 
   }
 }
 
-// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots).
+// 1 / q from the hardware reciprocal and two Newton steps (each roughly
+// squares the relative error; the last one leaves about one ulp), four
+// dependent operations instead of the division sequence.
+__device__ __forceinline__ double recip_f64(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double e = fma(-q, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-q, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots,
+// q_i = d_i - x - e_{i-1}^2 / q_{i-1}, a pivot smaller than pivmin replaced
+// by -pivmin).  The diagonal and e^2 are read eight at a time ahead of the
+// dependent chain.
 __device__ int sturm_count(const double* dg, const double* e2, int64_t m, double x,
                            double pivmin) {
   int cnt = 0;
   double q = dg[0] - x;
   if (q < 0.0) ++cnt;
-  for (int64_t i = 1; i < m; ++i) {
+  int64_t i = 1;
+  for (; i + 8 <= m; i += 8) {
+    double dd[8], ee[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      dd[u] = dg[i + u] - x;
+      ee[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (fabs(q) < pivmin) q = -pivmin;
+      q = fma(-ee[u], recip_f64(q), dd[u]);
+      cnt += q < 0.0 ? 1 : 0;
+    }
+  }
+  for (; i < m; ++i) {
     if (fabs(q) < pivmin) q = -pivmin;
-    q = dg[i] - x - e2[i - 1] / q;
-    if (q < 0.0) ++cnt;
+    q = fma(-e2[i - 1], recip_f64(q), dg[i] - x);
+    cnt += q < 0.0 ? 1 : 0;
   }
   return cnt;
 }

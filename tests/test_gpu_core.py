@@ -192,7 +192,10 @@ def test_svd_dense_f64_wide_blocks(n, d, k, q):
 
 # ------------------------------------------------------------- solve FP32 --
 @pytest.mark.parametrize("n,d,k,q,spec", [(1500, 700, 16, 5, "inv"), (2048, 1024, 32, 10, "inv"),
-                                          (777, 1999, 10, 7, "exp200")])
+                                          (777, 1999, 10, 7, "exp200"),
+                                          # m = 512: M = W^T W on the matrix cores
+                                          # (16 tiles x 32 splits), upper tiles only
+                                          (2500, 4096, 64, 7, "inv")])
 def test_svd_dense_f32(n, d, k, q, spec):
     sv = workloads.spectrum(spec, min(n, d))
     A = workloads.planted_dense(n, d, sv, 3 + n).astype(np.float32)
