@@ -36,11 +36,9 @@ __device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
                                           const float* __restrict__ v,
                                           const float* __restrict__ X, int64_t ldx,
                                           int32_t b, int32_t e, int32_t step, int KC,
-                                          int base, int c, int col, bool colok) {
+                                          int base, int c, int col, bool colok,
+                                          int32_t nci, float nv) {
   float acc = 0.0f;
-  int32_t j = b + c;
-  int32_t nci = (j < e && c < KC) ? ci[j] : 0;
-  float nv = (j < e && c < KC) ? v[j] : 0.0f;
   for (int32_t j0 = b; j0 < e; j0 += step) {
     const int32_t myci = nci;
     const float myv = nv;
@@ -48,8 +46,23 @@ __device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
     const int32_t jn = j0 + step + c;
     nci = (jn < e) ? ci[jn] : 0;
     nv = (jn < e) ? v[jn] : 0.0f;
+    // gathers in batches of 16 in flight (a round trip each)
     int t = 0;
-    for (; t + 8 <= cnt; t += 8) {
+    for (; t + 16 <= cnt; t += 16) {
+      int32_t cc[16];
+      float vv[16], xx[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        cc[u] = __shfl(myci, base + t + u);
+        vv[u] = __shfl(myv, base + t + u);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc += vv[u] * xx[u];
+    }
+    if (t + 8 <= cnt) {
       int32_t cc[8];
       float vv[8], xx[8];
 #pragma unroll
@@ -62,6 +75,7 @@ __device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
         xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
 #pragma unroll
       for (int u = 0; u < 8; ++u) acc += vv[u] * xx[u];
+      t += 8;
     }
     for (; t < cnt; ++t) {
       const int32_t c1 = __shfl(myci, base + t);
@@ -99,7 +113,9 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(
   for (int c0 = 0; c0 < k; c0 += KC) {
     const int col = c0 + c;
     const bool colok = valid && col < k;
-    float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok);
+    const int32_t j0 = beg + c;
+    float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok,
+                         (j0 < end && c < KC) ? ci[j0] : 0, (j0 < end && c < KC) ? v[j0] : 0.0f);
     if (own && col < k) {
       if (colvec) acc -= rv * static_cast<float>(colvec[col]);
       Y[row * ldy + col] = acc;
@@ -120,11 +136,11 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t x) {
 __global__ __launch_bounds__(256) void csr_plan_count_kernel(const int32_t* __restrict__ rp,
                                                              int64_t rows, int piece,
                                                              int32_t* cnt_s, int32_t* cnt_p,
-                                                             int32_t* cnt_m) {
-  __shared__ int32_t red[3][4];
+                                                             int32_t* cnt_m, int32_t* cnt_q) {
+  __shared__ int32_t red[4][4];
   const int t = threadIdx.x;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * kPlanRows + t * 4;
-  int32_t ns = 0, np = 0, nm = 0;
+  int32_t ns = 0, np = 0, nm = 0, nq = 0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int64_t r = r0 + u;
@@ -132,6 +148,7 @@ __global__ __launch_bounds__(256) void csr_plan_count_kernel(const int32_t* __re
       const int32_t len = rp[r + 1] - rp[r];
       if (len <= kCsrShort) {
         ++ns;
+        nq += len;
       } else {
         np += (len + piece - 1) / piece;
         if (len > piece) ++nm;
@@ -141,16 +158,19 @@ __global__ __launch_bounds__(256) void csr_plan_count_kernel(const int32_t* __re
   ns = wave_sum_i32(ns);
   np = wave_sum_i32(np);
   nm = wave_sum_i32(nm);
+  nq = wave_sum_i32(nq);
   if ((t & 63) == 0) {
     red[0][t >> 6] = ns;
     red[1][t >> 6] = np;
     red[2][t >> 6] = nm;
+    red[3][t >> 6] = nq;
   }
   __syncthreads();
   if (t == 0) {
     cnt_s[blockIdx.x] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     cnt_p[blockIdx.x] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
     cnt_m[blockIdx.x] = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    cnt_q[blockIdx.x] = red[3][0] + red[3][1] + red[3][2] + red[3][3];
   }
 }
 
@@ -218,12 +238,13 @@ __global__ __launch_bounds__(256) void csr_plan_write_kernel(
 }
 
 __global__ void csr_plan_totals_kernel(const int32_t* off_s, const int32_t* off_p,
-                                       const int32_t* off_m, int64_t nchunk,
-                                       int32_t* totals) {
+                                       const int32_t* off_m, const int32_t* off_q,
+                                       int64_t nchunk, int32_t* totals) {
   if (threadIdx.x == 0) {
     totals[0] = off_s[nchunk];
     totals[1] = off_p[nchunk];
     totals[2] = off_m[nchunk];
+    totals[3] = off_q[nchunk];
   }
 }
 
@@ -236,36 +257,62 @@ __global__ void csr_plan_totals_kernel(const int32_t* off_s, const int32_t* off_
 // that profiles tell the two products apart.
 template <int OPERAND>
 __global__ __launch_bounds__(256) void csr_product_kernel(
-    int k, int KC, int piece, int nshort, int npieces, const int32_t* __restrict__ short_rows,
+    int k, int KC, int RPS, int piece, int nshort, int npieces,
+    const int32_t* __restrict__ short_rows,
     const int32_t* __restrict__ piece_row, const int32_t* __restrict__ piece_first,
     float* __restrict__ part, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ ci, const float* __restrict__ v,
     const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
     const float* __restrict__ rowvec, const double* __restrict__ colvec) {
   const int SLOTS = 64 / KC;
-  const int nsw = (nshort + SLOTS - 1) / SLOTS;
+  const int nsw = (nshort + SLOTS * RPS - 1) / (SLOTS * RPS);
   const int w = static_cast<int>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int s = lane / KC, c = lane - s * KC;
   if (w < nsw) {
-    const int idx = w * SLOTS + s;
-    const bool valid = s < SLOTS && idx < nshort;
-    int64_t row = 0;
-    int32_t beg = 0, end = 0;
-    if (valid) {
-      row = short_rows[idx];
-      beg = rp[row];
-      end = rp[row + 1];
+    // slot s takes RPS consecutive entries of the short-row list: lane q of
+    // the slot loads row q's id and bounds, shuffled to the slot row by row
+    const int idx0 = (w * SLOTS + s) * RPS;
+    const bool sok = s < SLOTS;
+    int64_t myrow = 0;
+    int32_t mybeg = 0, myend = 0;
+    if (sok && c < RPS && idx0 + c < nshort) {
+      myrow = short_rows[idx0 + c];
+      mybeg = rp[myrow];
+      myend = rp[myrow + 1];
     }
-    const float rv = (valid && rowvec) ? rowvec[row] : 1.0f;
-    for (int c0 = 0; c0 < k; c0 += KC) {
-      const int col = c0 + c;
-      const bool colok = valid && col < k;
-      float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok);
-      if (colok) {
-        if (colvec) acc -= rv * static_cast<float>(colvec[col]);
-        Y[row * ldy + col] = acc;
+    const int nrows = (sok && idx0 < nshort) ? min(RPS, nshort - idx0) : 0;
+    const int base = s * KC;
+    // first chunk of row 0; inside the loop, row q + 1's is loaded before
+    // row q is multiplied
+    int32_t beg = __shfl(mybeg, sok ? base : 0), end = __shfl(myend, sok ? base : 0);
+    if (nrows <= 0) beg = end = 0;
+    int32_t fci = (c < KC && beg + c < end) ? ci[beg + c] : 0;
+    float fv = (c < KC && beg + c < end) ? v[beg + c] : 0.0f;
+    for (int q = 0; q < RPS; ++q) {
+      const int src = sok ? base + q : 0;
+      const int64_t row = __shfl(myrow, src);
+      const bool valid = q < nrows;
+      const int srcn = sok ? base + (q + 1 < RPS ? q + 1 : q) : 0;
+      int32_t nbeg = __shfl(mybeg, srcn), nend = __shfl(myend, srcn);
+      if (q + 1 >= nrows) nbeg = nend = 0;
+      const int32_t nci = (c < KC && nbeg + c < nend) ? ci[nbeg + c] : 0;
+      const float nv = (c < KC && nbeg + c < nend) ? v[nbeg + c] : 0.0f;
+      const float rv = (valid && rowvec) ? rowvec[row] : 1.0f;
+      for (int c0 = 0; c0 < k; c0 += KC) {
+        const int col = c0 + c;
+        const bool colok = valid && col < k;
+        float acc = slot_run(ci, v, X, ldx, valid ? beg : 0, valid ? end : 0, KC, KC, base, c,
+                             col, colok, fci, fv);
+        if (colok) {
+          if (colvec) acc -= rv * static_cast<float>(colvec[col]);
+          Y[row * ldy + col] = acc;
+        }
       }
+      beg = nbeg;
+      end = nend;
+      fci = nci;
+      fv = nv;
     }
     return;
   }
@@ -282,7 +329,10 @@ __global__ __launch_bounds__(256) void csr_product_kernel(
     const int col = c0 + c;
     const bool colok = s < SLOTS && col < k;
     const int32_t bs = (s < SLOTS) ? b + s * KC : e;
-    const float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok);
+    const int32_t j0 = bs + c;
+    const float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok,
+                               (j0 < e && c < KC) ? ci[j0] : 0,
+                               (j0 < e && c < KC) ? v[j0] : 0.0f);
     float tot = 0.0f;
     for (int q = 0; q < SLOTS; ++q) tot += __shfl(acc, q * KC + c);
     if (s == 0 && col < k) {
@@ -532,6 +582,15 @@ void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
 
 int csr_piece_len(int k) { return (64 / kc_for(k)) * kCsrShort; }
 
+// Short rows per KC-lane slot: up to kCsrSlotRows (at most KC, one lane per
+// row for the bounds) when the short rows average at most KC / 2 nonzeros,
+// i.e. mostly fit one chunk; otherwise one, so no slot serializes long rows.
+int csr_slot_rows(const CsrPlan& pl, int k) {
+  const int KC = kc_for(k);
+  if (pl.nshort <= 0 || 2 * pl.short_nnz > static_cast<int64_t>(pl.nshort) * KC) return 1;
+  return std::min(KC, kCsrSlotRows);
+}
+
 int64_t csr_max_pieces(int64_t nnz, int64_t rows) {
   // a row of len > kCsrShort nonzeros has at most len / kCsrShort + 1
   // pieces, and at most nnz / kCsrShort rows are that long
@@ -547,22 +606,25 @@ void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl, int32_
   int32_t* cnt_s = pl.blk;
   int32_t* cnt_p = pl.blk + (nb + 1);
   int32_t* cnt_m = pl.blk + 2 * (nb + 1);
-  int32_t* off_s = pl.blk + 3 * (nb + 1);
-  int32_t* off_p = pl.blk + 4 * (nb + 1);
-  int32_t* off_m = pl.blk + 5 * (nb + 1);
+  int32_t* cnt_q = pl.blk + 3 * (nb + 1);
+  int32_t* off_s = pl.blk + 4 * (nb + 1);
+  int32_t* off_p = pl.blk + 5 * (nb + 1);
+  int32_t* off_m = pl.blk + 6 * (nb + 1);
+  int32_t* off_q = pl.blk + 7 * (nb + 1);
   pl.rows = rows;
   const int piece = csr_piece_len(k);  // pl.operand is set by the caller
   if (nb > 0)
     csr_plan_count_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(rp, rows, piece, cnt_s,
-                                                                   cnt_p, cnt_m);
+                                                                   cnt_p, cnt_m, cnt_q);
   scan_kernel<<<1, 1024, 0, s>>>(cnt_s, nb, off_s);
   scan_kernel<<<1, 1024, 0, s>>>(cnt_p, nb, off_p);
   scan_kernel<<<1, 1024, 0, s>>>(cnt_m, nb, off_m);
+  scan_kernel<<<1, 1024, 0, s>>>(cnt_q, nb, off_q);
   if (nb > 0)
     csr_plan_write_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(
         rp, rows, piece, off_s, off_p, off_m, pl.short_rows, pl.piece_row, pl.piece_first,
         pl.multi_row, pl.multi_first);
-  csr_plan_totals_kernel<<<1, 64, 0, s>>>(off_s, off_p, off_m, nb, totals);
+  csr_plan_totals_kernel<<<1, 64, 0, s>>>(off_s, off_p, off_m, off_q, nb, totals);
 }
 
 void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
@@ -571,12 +633,13 @@ void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
                         hipStream_t s) {
   if (k <= 0) return;
   const int KC = kc_for(k);
-  const int64_t nsw = cdiv(pl.nshort, 64 / KC);
+  const int rps = csr_slot_rows(pl, k);
+  const int64_t nsw = cdiv(pl.nshort, (64 / KC) * rps);
   const int64_t waves = nsw + pl.npieces;
   if (waves <= 0) return;
   auto kern = pl.operand ? csr_product_kernel<1> : csr_product_kernel<0>;
   kern<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
-      k, KC, csr_piece_len(k), pl.nshort, pl.npieces, pl.short_rows, pl.piece_row,
+      k, KC, rps, csr_piece_len(k), pl.nshort, pl.npieces, pl.short_rows, pl.piece_row,
       pl.piece_first, pl.part, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec);
 }
 

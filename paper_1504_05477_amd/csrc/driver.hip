@@ -223,10 +223,10 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
       pl.piece_first = ar.take<int32_t>(static_cast<size_t>(pmax));
       pl.multi_row = ar.take<int32_t>(static_cast<size_t>(pmax));
       pl.multi_first = ar.take<int32_t>(static_cast<size_t>(pmax));
-      pl.blk = ar.take<int32_t>(static_cast<size_t>(6 * (csr_plan_chunks(prow[i]) + 1)));
+      pl.blk = ar.take<int32_t>(static_cast<size_t>(8 * (csr_plan_chunks(prow[i]) + 1)));
       pl.part = part;
     }
-    L.counters = ar.take<int32_t>(6);
+    L.counters = ar.take<int32_t>(8);
     L.colpart = ar.take<double>(static_cast<size_t>(kColsumBlocks) * k);
     L.mu = ar.take<float>(static_cast<size_t>(n));
     L.colvec = ar.take<double>(static_cast<size_t>(k));
@@ -1078,19 +1078,20 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
     tv = L.tv;
   }
   launch_csr_plan(row_ptr, n, pw, L.plan_a, L.counters, s);
-  launch_csr_plan(trp, d, pw, L.plan_t, L.counters + 3, s);
+  launch_csr_plan(trp, d, pw, L.plan_t, L.counters + 4, s);
   if (o.center) launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
-  int32_t cnt[6] = {0, 0, 0, 0, 0, 0};
+  int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
   BK_TRY(hipStreamSynchronize(s));
   BK_TRY_LAUNCH();
   L.plan_t.operand = 1;
-  L.plan_a.nshort = cnt[0];
-  L.plan_a.npieces = cnt[1];
-  L.plan_a.nmulti = cnt[2];
-  L.plan_t.nshort = cnt[3];
-  L.plan_t.npieces = cnt[4];
-  L.plan_t.nmulti = cnt[5];
+  CsrPlan* plans[2] = {&L.plan_a, &L.plan_t};
+  for (int i = 0; i < 2; ++i) {
+    plans[i]->nshort = cnt[4 * i];
+    plans[i]->npieces = cnt[4 * i + 1];
+    plans[i]->nmulti = cnt[4 * i + 2];
+    plans[i]->short_nnz = cnt[4 * i + 3];
+  }
   prep.end(0);
 
   CsrOp op;

@@ -182,6 +182,7 @@ void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
 // kernel that adds its piece sums in piece order (deterministic).  The plan
 // depends only on the sparsity structure and k.
 constexpr int kCsrShort = 64;
+constexpr int kCsrSlotRows = 8;  // consecutive short rows per KC-lane slot
 int csr_piece_len(int k);
 // upper bound on the number of pieces of any matrix with nnz nonzeros
 int64_t csr_max_pieces(int64_t nnz, int64_t rows);
@@ -191,15 +192,19 @@ struct CsrPlan {
   int32_t* piece_first = nullptr;  // max pieces: first piece of that row
   int32_t* multi_row = nullptr;    // max pieces: rows of several pieces
   int32_t* multi_first = nullptr;  // max pieces: their first piece
-  int32_t* blk = nullptr;          // 6 * (row chunks + 1): counts and offsets
+  int32_t* blk = nullptr;          // 8 * (row chunks + 1): counts and offsets
   float* part = nullptr;           // max pieces * k piece sums
   int64_t rows = 0;
   int nshort = 0, npieces = 0, nmulti = 0;
+  int64_t short_nnz = 0;           // nonzeros in the short rows
   int operand = 0;                 // 0: A, 1: A^T (names the kernel instance)
 };
+// short rows per KC-lane slot of the product kernel (1 .. kCsrSlotRows)
+int csr_slot_rows(const CsrPlan& pl, int k);
 int64_t csr_plan_chunks(int64_t rows);
-// builds the plan on the stream; totals[0..2] = short rows, pieces, rows of
-// several pieces (device, read back by the caller before launch_csr_product)
+// builds the plan on the stream; totals[0..3] = short rows, pieces, rows of
+// several pieces, nonzeros in short rows (device, read back by the caller
+// before launch_csr_product)
 void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl,
                      int32_t* totals, hipStream_t s);
 // Y = A X - rowvec colvec^T (rowvec nullable = ones, colvec nullable = no

@@ -252,10 +252,14 @@ def _termdoc(n, d, seed, median=30.0):
     return (rp, ci, va), M
 
 
+# Short rows go several to a KC-lane slot when they average at most KC / 2
+# nonzeros: k = 3 with short documents (3 rows per 3-lane slot), k = 8 (8
+# per slot), k = 40 (one slot per wavefront); the documents' own rows
+# (median 30) one per slot.
+@pytest.mark.parametrize("k,q,median", [(8, 4, 30.0), (3, 5, 10.0), (40, 2, 30.0)])
 @pytest.mark.parametrize("center", [False, True])
-def test_svd_csr_small(center):
-    (rp, ci, va), M = _termdoc(1200, 20000, 5)
-    k, q = 8, 4
+def test_svd_csr_small(center, k, q, median):
+    (rp, ci, va), M = _termdoc(1200, 20000, 5, median=median)
     ref = bki.block_krylov(M, _pi32(77, 20000, k), k, q, center=center, tau=1e-5)
     res = bk.svd_csr(_cuda(rp), _cuda(ci), _cuda(va), 1200, 20000, k, q, seed=77,
                      center=center)
