@@ -88,7 +88,8 @@ typedef struct bk_options {
                                 ld = k, FP64 for BK_F64 else FP32; overrides
                                 the seed                                     */
   int32_t timing;            /* 1: fill bk_info.ms / launches with per-phase
-                                GPU times from HIP events on `stream`        */
+                                GPU times from HIP events on `stream` (each
+                                timed phase costs two event records)        */
   int32_t save_for_backward; /* 1: keep R factors / projection coefficients
                                 in the workspace for bk_svd_dense_backward   */
   int32_t jacobi_block;      /* column block of the eigen-solve (default by
@@ -104,7 +105,10 @@ typedef struct bk_options {
                                 BK_METHOD_SIMULTANEOUS (1, Algorithm 1: the
                                 block is replaced by orth(A A^T block) q
                                 times, Rayleigh-Ritz on the last one)       */
-  int32_t reserved[3];
+  int32_t timing_phases;     /* with timing = 1: bitmask of the BK_PH_*
+                                phases given events (1 << BK_PH_AX | ...);
+                                0 = all.  Launch counts are kept for all.   */
+  int32_t reserved[2];
 } bk_options;
 
 enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1 };

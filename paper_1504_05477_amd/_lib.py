@@ -29,7 +29,8 @@ class Options(C.Structure):
         ("jacobi_block", C.c_int32),
         ("block_size", C.c_int32),
         ("method", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("timing_phases", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 

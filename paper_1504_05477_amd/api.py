@@ -48,6 +48,8 @@ _METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1}
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
              breakdown_tol=0.0, pi=None, timing=False, save=False,
              jacobi_block=0, block_size=0, method="bki") -> L.Options:
+    """timing: False, True (every phase) or an iterable of phase names from
+    _lib.PHASES (only those get events; launch counts are kept for all)."""
     o = L.Options()
     o.struct_size = C.sizeof(L.Options)
     o.refine = int(refine)
@@ -56,7 +58,16 @@ def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
     o.jacobi_tol = float(jacobi_tol)
     o.breakdown_tol = float(breakdown_tol)
     o.pi = _ptr(pi)
-    o.timing = int(bool(timing))
+    if timing is True or timing is False or timing is None:
+        o.timing = int(bool(timing))
+        o.timing_phases = 0
+    else:
+        names = list(timing)
+        bad = [p for p in names if p not in L.PHASES]
+        if bad:
+            raise ValueError(f"unknown phases {bad}; known: {L.PHASES}")
+        o.timing = 1
+        o.timing_phases = sum(1 << L.PHASES.index(p) for p in set(names))
     o.save_for_backward = int(bool(save))
     o.jacobi_block = int(jacobi_block)
     o.block_size = int(block_size or 0)

@@ -45,6 +45,7 @@ struct Arena {
 
 struct Options {
   int refine = 0, center = 0, max_sweeps = 40, timing = 0, save = 0, jblock = 0;
+  int timing_phases = 0;  // bitmask of timed phases (0: all)
   int p = 0;   // block width (0: k), oversampling of Section 6
   int si = 0;  // 1: simultaneous iteration (Algorithm 1)
   double jtol = 0.0, tau = 0.0;
@@ -53,7 +54,7 @@ struct Options {
 
 Options read_options(const bk_options* o, bool f64) {
   Options r;
-  if (o && o->struct_size >= static_cast<int32_t>(offsetof(bk_options, reserved))) {
+  if (o && o->struct_size >= static_cast<int32_t>(offsetof(bk_options, timing_phases))) {
     r.refine = o->refine;
     r.center = o->center_rows;
     if (o->max_jacobi_sweeps > 0) r.max_sweeps = o->max_jacobi_sweeps;
@@ -65,6 +66,8 @@ Options read_options(const bk_options* o, bool f64) {
     r.jblock = o->jacobi_block;
     r.p = o->block_size;
     r.si = o->method == BK_METHOD_SIMULTANEOUS ? 1 : 0;
+    if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, reserved)))
+      r.timing_phases = o->timing_phases;
   }
   if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
   return r;
@@ -255,6 +258,7 @@ thread_local EventPool g_events;
 
 struct Timer {
   bool on = false;
+  int mask = 0;  // phases given events (0: all)
   hipStream_t s = nullptr;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
   int launches[BK_NPHASE] = {0};
@@ -263,7 +267,8 @@ struct Timer {
   hipEvent_t start{};
   void begin(int ph) {
     cur = ph;
-    if (!on) return;
+    start = nullptr;
+    if (!on || (mask != 0 && !(mask & (1 << ph)))) return;
     if (marks.empty()) pool_mark = g_events.used;
     start = g_events.get();
     if (start) hipEventRecord(start, s);
@@ -576,6 +581,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
           hipStream_t s) {
   Timer tm;
   tm.on = o.timing != 0;
+  tm.mask = o.timing_phases;
   tm.s = s;
   op.tm = &tm;
   op.partial = L.partial;
@@ -1056,6 +1062,7 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
 
   Timer prep;
   prep.on = o.timing != 0;
+  prep.mask = o.timing_phases;
   prep.s = s;
   prep.begin(BK_PH_PREP);
   // Validate the structure before any kernel indexes through it.
