@@ -841,7 +841,11 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 3 * k) * sizeof(double), s>>>(dg, eo, m, k,
                                                                              theta, X, sol, piv);
   const unsigned gb = static_cast<unsigned>(cdiv(k, 4));
-  if (m <= 1024)
+  if (m <= 256)
+    tridiag_back_kernel<4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else if (m <= 512)
+    tridiag_back_kernel<8><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else if (m <= 1024)
     tridiag_back_kernel<16><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
   else if (m <= 2048)
     tridiag_back_kernel<32><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
