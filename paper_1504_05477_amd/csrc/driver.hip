@@ -181,8 +181,9 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.partial = ar.take<double>(static_cast<size_t>(partial_need(n, d, k, q, o.refine != 0, csr)));
   if (!csr && !f64) {
     // X^T of A X in FP32 (the widest type), Y^T of A^T Y in BF16 / FP8
-    L.pack_bytes = static_cast<size_t>(std::max(mfma_pack_bytes(d, k, BK_F32),
-                                                mfma_pack_bytes(n, k, BK_BF16)));
+    int64_t nn = 0;  // A X on the matrix cores: packed X^T (+ split partials)
+    for (int t : {BK_F32, BK_BF16, BK_FP8_E4M3}) nn = std::max(nn, mfma_nn_work_bytes(n, d, k, t));
+    L.pack_bytes = static_cast<size_t>(std::max(nn, mfma_pack_bytes(n, k, BK_BF16)));
     L.pack = ar.take<char>(L.pack_bytes);
   }
   const size_t kk = static_cast<size_t>(k) * k;
@@ -1210,7 +1211,8 @@ size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d, int32_t k
             : 256;
   const size_t pack = (a_type == BK_F64)
                           ? 0
-                          : static_cast<size_t>(mfma_pack_bytes(trans ? n : d, k, a_type));
+                          : static_cast<size_t>(trans ? mfma_pack_bytes(n, k, a_type)
+                                                      : mfma_nn_work_bytes(n, d, k, a_type));
   return part + pack;
 }
 

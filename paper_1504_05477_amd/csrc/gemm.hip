@@ -293,9 +293,9 @@ void tn_dispatch(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
 
 int launch_nn(const NNArgs& a, hipStream_t s) {
   if (a.n <= 0 || a.N <= 0) return 0;  // K = 0 gives C = beta C below
-  bool done = false;
-  launch_nn_mfma_if(a, s, &done);
-  if (done) return 2;
+  int mfma = 0;
+  launch_nn_mfma_if(a, s, &mfma);
+  if (mfma) return mfma;
   switch (a.a_type) {
     case BK_F64:
       nn_dispatch_scaled<double, double, double, double>(a, s);

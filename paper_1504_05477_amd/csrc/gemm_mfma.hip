@@ -119,22 +119,33 @@ template <typename T, bool SCALED>
 __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
     int64_t n, int64_t K, int N, const T* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld, const T* __restrict__ Xt,
-    int64_t ldxt, const float* __restrict__ xscale, float* __restrict__ C, int64_t ldc) {
+    int64_t ldxt, const float* __restrict__ xscale, float* __restrict__ C, int64_t ldc,
+    int64_t cps) {
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
   int64_t rb, cb;
   if (!xcd_tile(blockIdx.x, (n + 127) / 128, (N + 127) / 128, &rb, &cb)) return;
+  // split blockIdx.y takes chunks [c0, c0 + nch) of K; with several splits
+  // C is its n x N (ld N) slice of FP32 partials
+  const int64_t nall = K / KC;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * cps;
+  if (c0 >= nall) return;
+  const int64_t nch = (c0 + cps < nall) ? cps : nall - c0;
+  if (gridDim.y > 1) {
+    C += static_cast<int64_t>(blockIdx.y) * n * N;
+    ldc = N;
+  }
   const int64_t row0 = rb * 128;
   const int64_t col0 = cb * 128;
   const int nt = static_cast<int>((N - col0 + 31) / 32 < 4 ? (N - col0 + 31) / 32 : 4);
   const int64_t row = row0 + 32 * w + r32;
-  const uint4* arow = reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h;
+  const uint4* arow =
+      reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h + c0 * 8;
   const int bc = t >> 1, bh = t & 1;  // staging: packed column bc, half bh
   const bool bload = bc < 32 * nt;
   const uint4* xrow =
-      reinterpret_cast<const uint4*>(Xt + (col0 + (bload ? bc : 0)) * ldxt) + 4 * bh;
-  const int64_t nch = K / KC;
+      reinterpret_cast<const uint4*>(Xt + (col0 + (bload ? bc : 0)) * ldxt) + 4 * bh + c0 * 8;
   f32x16 acc[4];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x16{};
@@ -186,7 +197,7 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
     if (SCALED) {
       // 32-row groups never straddle a 128-row scale tile; chunk c is
       // scale column c
-      const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c] * xscale[c];
+      const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + c] * xscale[c0 + c];
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) acc[tt] += sc * tmp[tt];
     }
@@ -208,6 +219,19 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
       if (gr < n && gc < N) C[gr * ldc + gc] = acc[tt][v];
     }
   }
+}
+
+// C (n x N, ldc) = sum over the S splits of the FP32 partials, in split order.
+__global__ __launch_bounds__(256) void nn_split_reduce_kernel(int S, int64_t n, int64_t N,
+                                                              const float* __restrict__ part,
+                                                              float* __restrict__ C,
+                                                              int64_t ldc) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= n * N) return;
+  float acc = 0.0f;
+  for (int sp = 0; sp < S; ++sp) acc += part[sp * n * N + idx];
+  const int64_t r = idx / N;
+  C[r * ldc + (idx - r * N)] = acc;
 }
 
 // ------------------------------------------------------------------ TN --
@@ -518,18 +542,45 @@ static void pack_t(const float* src, int64_t lds, int64_t rows, int64_t cols, vo
 }
 
 template <typename T, bool SCALED>
-static void nn_run(const NNArgs& a, hipStream_t s) {
+static int nn_run(const NNArgs& a, int type, hipStream_t s) {
   int64_t kp = 0, np = 0;
   float* xs = nullptr;
   pack_t<T>(static_cast<const float*>(a.X), a.ldx, a.K, a.N, a.work, &kp, &np, &xs, s);
-  const unsigned grid = static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128)));
+  const int S = nn_mfma_splits(a.n, a.K, a.N, type);
+  const int64_t nch = a.K / Mf<T>::KC;
+  const int64_t cps = cdiv(nch, S);
+  float* part = S > 1 ? reinterpret_cast<float*>(static_cast<char*>(a.work) +
+                                                 mfma_pack_bytes(a.K, a.N, type))
+                      : static_cast<float*>(a.C);
+  const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128))),
+                  static_cast<unsigned>(S));
   nn_mfma_kernel<T, SCALED><<<grid, 256, 0, s>>>(
       a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,
-      static_cast<const T*>(a.work), kp, xs, static_cast<float*>(a.C), a.ldc);
+      static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps);
+  if (S == 1) return 2;
+  nn_split_reduce_kernel<<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(
+      S, a.n, a.N, part, static_cast<float*>(a.C), a.ldc);
+  return 3;
 }
 
-void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done) {
-  *done = false;
+int nn_mfma_splits(int64_t n, int64_t K, int64_t N, int type) {
+  // target 512 workgroups; every split at least 8 chunks of K, at most 16
+  const int64_t tiles = cdiv(n, 128) * cdiv(N, 128);
+  const int64_t nch = K / chunk_vals(type);
+  int64_t S = cdiv(512, tiles);
+  S = std::min<int64_t>(S, std::min<int64_t>(16, nch / 8));
+  if (S < 2) return 1;
+  return static_cast<int>(cdiv(nch, cdiv(nch, S)));  // no empty split
+}
+
+int64_t mfma_nn_work_bytes(int64_t n, int64_t K, int64_t N, int type) {
+  const int S = nn_mfma_splits(n, K, N, type);
+  return mfma_pack_bytes(K, N, type) +
+         (S > 1 ? static_cast<int64_t>(align_up(static_cast<size_t>(S * n * N) * 4, 256)) : 0);
+}
+
+void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches) {
+  *launches = 0;
   if (!a.work || a.x_f64 || a.c_f64 || a.alpha != 1.0 || a.beta != 0.0) return;
   if (a.a_type != BK_F32 && a.a_type != BK_BF16 && a.a_type != BK_FP8_E4M3) return;
   const int es = esize(a.a_type);
@@ -537,21 +588,20 @@ void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done) {
       (reinterpret_cast<uintptr_t>(a.A) & 15) != 0)
     return;
   if (a.a_type == BK_FP8_E4M3 && !a.ascale) return;
-  if (static_cast<int64_t>(a.work_bytes) < mfma_pack_bytes(a.K, a.N, a.a_type)) return;
+  if (static_cast<int64_t>(a.work_bytes) < mfma_nn_work_bytes(a.n, a.K, a.N, a.a_type)) return;
   // only products large enough to pay for the packing launch
   if (2.0 * static_cast<double>(a.n) * static_cast<double>(a.K) * a.N < 1e8) return;
   switch (a.a_type) {
     case BK_F32:
-      nn_run<float, false>(a, s);
+      *launches = nn_run<float, false>(a, BK_F32, s);
       break;
     case BK_BF16:
-      nn_run<bf16_t, false>(a, s);
+      *launches = nn_run<bf16_t, false>(a, BK_BF16, s);
       break;
     default:
-      nn_run<fp8_t, true>(a, s);
+      *launches = nn_run<fp8_t, true>(a, BK_FP8_E4M3, s);
       break;
   }
-  *done = true;
 }
 
 template <typename T, bool SCALED, bool PACKED>

@@ -74,9 +74,14 @@ int launch_tn(const TNArgs& a, hipStream_t s);  // kernels launched
 // of aligned, large enough products; otherwise the VALU kernels run.
 // Bytes of scratch to pack an lred x cols FP32 operand in `type`.
 int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type);
+// Splits of K of the matrix-core A X (n x K times K x N) and the scratch it
+// needs: the packed X^T plus, with several splits, their FP32 partials.
+int nn_mfma_splits(int64_t n, int64_t K, int64_t N, int type);
+int64_t mfma_nn_work_bytes(int64_t n, int64_t K, int64_t N, int type);
 int tn_mfma_splits(int64_t L, int64_t p, int r);
-// *done: the product ran on matrix cores (2 launches: pack, product)
-void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, bool* done);
+// *launches: kernels launched on the matrix-core path (pack, product and,
+// with split K, the reduction); 0 if the product was not taken
+void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches);
 // *splits = number of FP64 partials written (0: not handled)
 void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits);
 
