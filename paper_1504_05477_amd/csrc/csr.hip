@@ -237,17 +237,6 @@ __global__ __launch_bounds__(256) void csr_plan_write_kernel(
   }
 }
 
-__global__ void csr_plan_totals_kernel(const int32_t* off_s, const int32_t* off_p,
-                                       const int32_t* off_m, const int32_t* off_q,
-                                       int64_t nchunk, int32_t* totals) {
-  if (threadIdx.x == 0) {
-    totals[0] = off_s[nchunk];
-    totals[1] = off_p[nchunk];
-    totals[2] = off_m[nchunk];
-    totals[3] = off_q[nchunk];
-  }
-}
-
 // One product Y = A X (- rowvec c^T, c the centring vector) over a plan.
 // Wavefront w < nsw takes SLOTS short rows (one slot each); wavefront
 // nsw + p takes piece p: its slots walk interleaved chunks of the piece and
@@ -467,10 +456,16 @@ __global__ __launch_bounds__(256) void count_cols_kernel(const int32_t* ci,
 }
 
 // Exclusive scan of cnt[0..n) into out[0..n], one 1024-thread workgroup.
+// Exclusive scan of cnt[0..n) into out[0..n] (out[n] = total), one workgroup;
+// workgroup b scans cnt + b stride into out + b stride and, with totals,
+// also writes its total to totals[b].
 __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* cnt, int64_t n,
-                                                    int32_t* out) {
+                                                    int32_t* out, int64_t stride = 0,
+                                                    int32_t* totals = nullptr) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
+  cnt += blockIdx.x * stride;
+  out += blockIdx.x * stride;
   const int64_t per = (n + 1023) / 1024;
   const int64_t b = t * per;
   const int64_t e = (b + per < n) ? b + per : n;
@@ -489,7 +484,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* cnt, int64_t 
     out[i] = static_cast<int32_t>(run);
     run += cnt[i];
   }
-  if (t == 1023) out[n] = static_cast<int32_t>(part[1023]);
+  if (t == 1023) {
+    out[n] = static_cast<int32_t>(part[1023]);
+    if (totals) totals[blockIdx.x] = static_cast<int32_t>(part[1023]);
+  }
 }
 
 __global__ __launch_bounds__(256) void copy_i32_kernel(const int32_t* a, int32_t* b,
@@ -607,24 +605,20 @@ void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl, int32_
   int32_t* cnt_p = pl.blk + (nb + 1);
   int32_t* cnt_m = pl.blk + 2 * (nb + 1);
   int32_t* cnt_q = pl.blk + 3 * (nb + 1);
-  int32_t* off_s = pl.blk + 4 * (nb + 1);
+  int32_t* off_s = pl.blk + 4 * (nb + 1);  // then off_p, off_m, off_q (short nnz)
   int32_t* off_p = pl.blk + 5 * (nb + 1);
   int32_t* off_m = pl.blk + 6 * (nb + 1);
-  int32_t* off_q = pl.blk + 7 * (nb + 1);
   pl.rows = rows;
   const int piece = csr_piece_len(k);  // pl.operand is set by the caller
   if (nb > 0)
     csr_plan_count_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(rp, rows, piece, cnt_s,
                                                                    cnt_p, cnt_m, cnt_q);
-  scan_kernel<<<1, 1024, 0, s>>>(cnt_s, nb, off_s);
-  scan_kernel<<<1, 1024, 0, s>>>(cnt_p, nb, off_p);
-  scan_kernel<<<1, 1024, 0, s>>>(cnt_m, nb, off_m);
-  scan_kernel<<<1, 1024, 0, s>>>(cnt_q, nb, off_q);
+  // the four counts in one launch (arrays nb + 1 apart), totals[0..3]
+  scan_kernel<<<4, 1024, 0, s>>>(cnt_s, nb, off_s, nb + 1, totals);
   if (nb > 0)
     csr_plan_write_kernel<<<static_cast<unsigned>(nb), 256, 0, s>>>(
         rp, rows, piece, off_s, off_p, off_m, pl.short_rows, pl.piece_row, pl.piece_first,
         pl.multi_row, pl.multi_first);
-  csr_plan_totals_kernel<<<1, 64, 0, s>>>(off_s, off_p, off_m, off_q, nb, totals);
 }
 
 void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,

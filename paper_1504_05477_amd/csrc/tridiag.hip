@@ -557,7 +557,9 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
       }
       const double lam = theta[cc] + (cc - c) * 2.0 * tiny;  // split exact ties
       tri_factor(dg, eo, m, lam, tiny, rD, DU, DU2, DL, piv);
-      for (int iter = 0; iter < 3; ++iter) {
+      // two solves: with lam accurate to a few ulps the first already damps
+      // every other eigenvector by ~ eps |lam| / gap, the second is margin
+      for (int iter = 0; iter < 2; ++iter) {
         tri_solve(m, rD, DU, DU2, DL, piv, x);
         for (int pj = c; pj < cc; ++pj) {
           const double* y = X + static_cast<int64_t>(pj) * m;
