@@ -24,7 +24,7 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 COMMON = [
-    f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall",
+    f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall", "-Werror=return-type",
     "-Wno-unused-function", "-Wno-unused-result", "-Wno-unused-value",
     # packed FP32 instructions stay off (they are generated from scalar code
     # otherwise); the host pass warns that it does not know the feature.

@@ -272,14 +272,14 @@ struct Timer {
     if (!on || (mask != 0 && !(mask & (1 << ph)))) return;
     if (marks.empty()) pool_mark = g_events.used;
     start = g_events.get();
-    if (start) hipEventRecord(start, s);
+    if (start) (void)hipEventRecord(start, s);
   }
   void end(int nlaunch) {
     if (cur >= 0) launches[cur] += nlaunch;
     if (on && start) {
       hipEvent_t stop = g_events.get();
       if (stop) {
-        hipEventRecord(stop, s);
+        (void)hipEventRecord(stop, s);
         marks.push_back({cur, {start, stop}});
       }
     }
@@ -429,9 +429,9 @@ struct Solver {
 
   // G (p x r FP64, ld r) = X^T Y, X L x p (ldx), Y L x r (ldy), both the
   // working type.
-  void gram(const void* X, int64_t ldx, int64_t p, const void* Y, int64_t ldy,
-            int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0,
-            bool sym = false) {
+  int gram(const void* X, int64_t ldx, int64_t p, const void* Y, int64_t ldy,
+           int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0,
+           bool sym = false) {
     TNArgs a;
     a.L = Lrows;
     a.p = p;
@@ -449,11 +449,11 @@ struct Solver {
     a.beta = beta;
     a.partial = L->partial;
     a.sym = sym && X == Y && ldx == ldy && p == r;
-    launch_tn(a, s);
+    return launch_tn(a, s);
   }
   // C (rows x N, ldc) = alpha A (rows x K, lda) Xf (K x N FP64, ldx) + beta C
-  void apply(const void* A, int64_t lda, int64_t rows, int64_t K, const double* Xf,
-             int64_t ldx, int N, void* C, int64_t ldc, double alpha, double beta) {
+  int apply(const void* A, int64_t lda, int64_t rows, int64_t K, const double* Xf,
+            int64_t ldx, int N, void* C, int64_t ldc, double alpha, double beta) {
     NNArgs a;
     a.n = rows;
     a.K = K;
@@ -469,27 +469,29 @@ struct Solver {
     a.c_f64 = f64;
     a.alpha = alpha;
     a.beta = beta;
-    launch_nn(a, s);
+    return launch_nn(a, s);
   }
 
-  // Q slab i = orth(Bs): shifted CholeskyQR3 (Fukaya et al., SIAM J. Sci.
-  // Comput. 2020).  Pass 1 factors G + s I with s = 11 (nk + k(k+1)) u
-  // ||B||_F^2 so the FP64 Cholesky cannot fail on an ill-conditioned block;
-  // passes 2 and 3 are plain CholeskyQR on the already well-conditioned
-  // result.  R_i = R3 R2 R1 (saved for the adjoint).
-  void orth_block(int i, int slab) {
+  // Q slab = orth(B), B (n x k, ld ldb: Bs or the slab itself): shifted
+  // CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput. 2020).  Pass 1 factors
+  // G + s I with s = 11 (nk + k(k+1)) u ||B||_F^2 so the FP64 Cholesky cannot
+  // fail on an ill-conditioned block; passes 2 and 3 are plain CholeskyQR on
+  // the already well-conditioned result.  R_i = R3 R2 R1 (saved for the
+  // adjoint).  `gpre` has trace ||B before projection||_F^2 (CHOL_FIRST).
+  void orth_block(int i, int slab, void* B, int64_t ldb, const double* gpre) {
     tm->begin(BK_PH_CHOLQR);
     const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
-    void* src = L->Bs;
-    void* dst = L->Bs2;
+    // B -> Bs2 -> Bs -> slab (B may be the slab)
+    void* bufs[4] = {B, L->Bs2, L->Bs, qslab(slab)};
+    const int64_t lds[4] = {ldb, k, k, m};
     for (int pass = 0; pass < 3; ++pass) {
-      gram(src, k, k, src, k, k, n, L->G);
+      void* src = bufs[pass];
+      const int64_t ls = lds[pass];
+      gram(src, ls, k, src, ls, k, n, L->G);
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
-      launch_chol(k, L->G, L->Gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
+      launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
                   L->cholwork, L->ctrl, s);
-      void* out = (pass == 2) ? static_cast<void*>(qslab(slab)) : dst;
-      const int64_t ldo = (pass == 2) ? m : k;
-      apply(src, k, n, k, L->Rinv, k, k, out, ldo, 1.0, 0.0);
+      apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0);
       if (o.save) {
         if (pass == 0) {
           launch_copy2d(L->R, true, k, L->Racc, true, k, k, k, s);
@@ -498,7 +500,6 @@ struct Solver {
           launch_copy2d(L->Rtmp, true, k, L->Racc, true, k, k, k, s);
         }
       }
-      std::swap(src, dst);
     }
     if (o.save)
       launch_copy2d(L->Racc, true, k, L->Rsave + static_cast<size_t>(i) * k * k, true, k, k,
@@ -506,16 +507,20 @@ struct Solver {
     tm->end(12 + (o.save ? 6 : 0));
   }
 
-  // Bs <- (I - Q_<i Q_<i^T) Bs, twice.
-  void project(int i) {
+  // B <- (I - Q_<i Q_<i^T) B, twice, for the block B held in Q's slab i (so
+  // [Q_<i, B] are the first (i+1)k columns of Q): the first TN product gives
+  // C = Q_<i^T B and B^T B (whose trace the breakdown test of the first
+  // CholeskyQR pass needs) together.  Returns B^T B (k x k, ld k).
+  const double* project(int i) {
     tm->begin(BK_PH_PROJ);
-    gram(L->Bs, k, k, L->Bs, k, k, n, L->Gpre);
     const int64_t p = static_cast<int64_t>(i) * k;
-    for (int pass = 0; pass < 2; ++pass) {
-      gram(L->Q, m, p, L->Bs, k, k, n, L->C);
-      apply(L->Q, m, n, p, L->C, k, k, L->Bs, k, -1.0, 1.0);
-    }
-    tm->end(7);
+    void* B = qslab(i);
+    int nl = gram(L->Q, m, p + k, B, m, k, n, L->C);  // rows p.. : B^T B
+    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0);
+    nl += gram(L->Q, m, p, B, m, k, n, L->C);           // rows 0 .. p-1 only
+    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0);
+    tm->end(nl);
+    return L->C + p * k;
   }
 
   // Eigen-solve of the FP64 symmetric PSD `Mat` (mm x mm): top `kk`
@@ -620,13 +625,13 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
 
   // Step 2-3: Krylov blocks, orthonormalized as they are formed.
   op.ax(L.Pi, pw, pw, L.Bs, pw, s);
-  S.orth_block(0, 0);
+  S.orth_block(0, 0, L.Bs, pw, L.Gpre);
   if (!o.si) {
     for (int i = 1; i <= q; ++i) {
       op.aty(S.qslab(i - 1), m, pw, S.wslab(i - 1), m, s);
-      op.ax(S.wslab(i - 1), m, pw, L.Bs, pw, s);
-      S.project(i);
-      S.orth_block(i, i);
+      op.ax(S.wslab(i - 1), m, pw, S.qslab(i), m, s);  // the block in its slab
+      const double* gpre = S.project(i);
+      S.orth_block(i, i, S.qslab(i), m, gpre);
     }
     op.aty(S.qslab(q), m, pw, S.wslab(q), m, s);
   } else {
@@ -635,9 +640,9 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
       op.aty(S.qslab(0), m, pw, S.wslab(0), m, s);
       op.ax(S.wslab(0), m, pw, L.Bs, pw, s);
       tm.begin(BK_PH_PROJ);
-      S.gram(L.Bs, pw, pw, L.Bs, pw, pw, n, L.Gpre);  // trace for the breakdown test
-      tm.end(2);
-      S.orth_block(i, 0);
+      const int nl = S.gram(L.Bs, pw, pw, L.Bs, pw, pw, n, L.Gpre);  // trace for the breakdown test
+      tm.end(nl);
+      S.orth_block(i, 0, L.Bs, pw, L.Gpre);
     }
     op.aty(S.qslab(0), m, pw, S.wslab(0), m, s);
   }
@@ -936,7 +941,7 @@ struct DevBuf {
   void* p = nullptr;
   hipStream_t s = nullptr;
   ~DevBuf() {
-    if (p) hipFreeAsync(p, s);
+    if (p) (void)hipFreeAsync(p, s);
   }
 };
 
@@ -1121,7 +1126,7 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   if (info && o.timing) {
     float ms = 0.0f;
     if (!prep.marks.empty())
-      hipEventElapsedTime(&ms, prep.marks[0].second.first, prep.marks[0].second.second);
+      (void)hipEventElapsedTime(&ms, prep.marks[0].second.first, prep.marks[0].second.second);
     info->ms[BK_PH_PREP] += ms;
   }
   return st;
