@@ -86,8 +86,11 @@ int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) 
   const int64_t m = static_cast<int64_t>(q + 1) * k;
   int64_t need = std::max<int64_t>(tn_partial_elems(n, k, k), tn_partial_elems(d, m, static_cast<int>(m)));
   if (!csr) need = std::max(need, tn_partial_elems(n, d, k));
-  for (int i = 1; i <= q; ++i)
+  // projection of block i: [Q_<i, B]^T B (i + 1) k x k, then Q_<i^T B
+  for (int i = 1; i <= q + 1; ++i)
     need = std::max(need, tn_partial_elems(n, static_cast<int64_t>(i) * k, k));
+  // Gram partials of the fused applies (k <= 32): one k x k per row block
+  need = std::max(need, nn_gram_partial_elems(n, k));
   if (refine) {
     need = std::max(need, tn_partial_elems(n, d, k));
     need = std::max(need, tn_partial_elems(d, k, k));
@@ -453,7 +456,8 @@ struct Solver {
   }
   // C (rows x N, ldc) = alpha A (rows x K, lda) Xf (K x N FP64, ldx) + beta C
   int apply(const void* A, int64_t lda, int64_t rows, int64_t K, const double* Xf,
-            int64_t ldx, int N, void* C, int64_t ldc, double alpha, double beta) {
+            int64_t ldx, int N, void* C, int64_t ldc, double alpha, double beta,
+            double* gram_partial = nullptr) {
     NNArgs a;
     a.n = rows;
     a.K = K;
@@ -469,29 +473,41 @@ struct Solver {
     a.c_f64 = f64;
     a.alpha = alpha;
     a.beta = beta;
+    a.gram_partial = gram_partial;
     return launch_nn(a, s);
   }
+  // k <= 32: the applies of the orthonormalization also leave the partial
+  // Grams of the block they write, so no separate Gram product is needed
+  bool fuse_gram() const { return nn_gram_partial_elems(n, k) > 0; }
 
   // Q slab = orth(B), B (n x k, ld ldb: Bs or the slab itself): shifted
   // CholeskyQR3 (Fukaya et al., SIAM J. Sci. Comput. 2020).  Pass 1 factors
   // G + s I with s = 11 (nk + k(k+1)) u ||B||_F^2 so the FP64 Cholesky cannot
   // fail on an ill-conditioned block; passes 2 and 3 are plain CholeskyQR on
   // the already well-conditioned result.  R_i = R3 R2 R1 (saved for the
-  // adjoint).  `gpre` has trace ||B before projection||_F^2 (CHOL_FIRST).
-  void orth_block(int i, int slab, void* B, int64_t ldb, const double* gpre) {
+  // adjoint).  `gpre` has trace ||B before projection||_F^2 (CHOL_FIRST);
+  // with have_gram, L->G already holds B^T B.
+  void orth_block(int i, int slab, void* B, int64_t ldb, const double* gpre,
+                  bool have_gram = false) {
     tm->begin(BK_PH_CHOLQR);
     const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
+    const bool fuse = fuse_gram();
     // B -> Bs2 -> Bs -> slab (B may be the slab)
     void* bufs[4] = {B, L->Bs2, L->Bs, qslab(slab)};
     const int64_t lds[4] = {ldb, k, k, m};
+    int nl = 0;
     for (int pass = 0; pass < 3; ++pass) {
       void* src = bufs[pass];
       const int64_t ls = lds[pass];
-      gram(src, ls, k, src, ls, k, n, L->G);
+      if (pass == 0 ? !have_gram : !fuse) nl += gram(src, ls, k, src, ls, k, n, L->G);
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
       launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
                   L->cholwork, L->ctrl, s);
-      apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0);
+      ++nl;
+      const bool g = fuse && pass < 2;
+      nl += apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0,
+                  g ? L->partial : nullptr);
+      if (g) nl += launch_gram_reduce(n, k, L->partial, L->G, s);
       if (o.save) {
         if (pass == 0) {
           launch_copy2d(L->R, true, k, L->Racc, true, k, k, k, s);
@@ -504,21 +520,25 @@ struct Solver {
     if (o.save)
       launch_copy2d(L->Racc, true, k, L->Rsave + static_cast<size_t>(i) * k * k, true, k, k,
                     k, s);
-    tm->end(12 + (o.save ? 6 : 0));
+    tm->end(nl + (o.save ? 6 : 0));
   }
 
   // B <- (I - Q_<i Q_<i^T) B, twice, for the block B held in Q's slab i (so
   // [Q_<i, B] are the first (i+1)k columns of Q): the first TN product gives
   // C = Q_<i^T B and B^T B (whose trace the breakdown test of the first
-  // CholeskyQR pass needs) together.  Returns B^T B (k x k, ld k).
+  // CholeskyQR pass needs) together.  Returns B^T B (k x k, ld k); with
+  // fuse_gram() the last apply also leaves the Gram of the projected block
+  // in L->G.
   const double* project(int i) {
     tm->begin(BK_PH_PROJ);
     const int64_t p = static_cast<int64_t>(i) * k;
     void* B = qslab(i);
+    const bool fuse = fuse_gram();
     int nl = gram(L->Q, m, p + k, B, m, k, n, L->C);  // rows p.. : B^T B
     nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0);
     nl += gram(L->Q, m, p, B, m, k, n, L->C);           // rows 0 .. p-1 only
-    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0);
+    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0, fuse ? L->partial : nullptr);
+    if (fuse) nl += launch_gram_reduce(n, k, L->partial, L->G, s);
     tm->end(nl);
     return L->C + p * k;
   }
@@ -631,7 +651,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
       op.aty(S.qslab(i - 1), m, pw, S.wslab(i - 1), m, s);
       op.ax(S.wslab(i - 1), m, pw, S.qslab(i), m, s);  // the block in its slab
       const double* gpre = S.project(i);
-      S.orth_block(i, i, S.qslab(i), m, gpre);
+      S.orth_block(i, i, S.qslab(i), m, gpre, S.fuse_gram());
     }
     op.aty(S.qslab(q), m, pw, S.wslab(q), m, s);
   } else {

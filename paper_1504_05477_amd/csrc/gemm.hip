@@ -11,12 +11,15 @@ namespace {
 
 constexpr int NN_BM = 64, NN_BN = 32, NN_BK = 32;
 
+// gpart (nullable, N <= NN_BN): after C is written, the workgroup's partial
+// Gram of the C rows it wrote, (C_rows)^T C_rows in FP64 of the stored
+// values, at gpart[blockIdx.x N N] (the layout of the TN split partials).
 template <typename TA, typename TX, typename TC, typename ACC, bool SCALED>
 __global__ __launch_bounds__(256) void nn_kernel(
     int64_t n, int64_t K, int N, const TA* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld,
     const TX* __restrict__ X, int64_t ldx, TC* __restrict__ C, int64_t ldc,
-    ACC alpha, ACC beta) {
+    ACC alpha, ACC beta, double* __restrict__ gpart) {
   __shared__ ACC As[NN_BK][NN_BM + 1];
   __shared__ ACC Xs[NN_BK][NN_BN];
   const int t = threadIdx.x;
@@ -91,6 +94,30 @@ __global__ __launch_bounds__(256) void nn_kernel(
       ACC v = alpha * acc[i][j];
       if (beta != ACC(0)) v += beta * static_cast<ACC>(C[gr * ldc + gc]);
       C[gr * ldc + gc] = static_cast<TC>(v);
+      acc[i][j] = static_cast<ACC>(static_cast<TC>(v));  // as stored
+    }
+  }
+  if (gpart) {
+    ACC* T = &As[0][0];  // NN_BM x NN_BN tile of the stored rows
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bool rok = row0 + ty * 2 + i < n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = tx * 4 + j;
+        T[(ty * 2 + i) * NN_BN + c] = (rok && col0 + c < N) ? acc[i][j] : ACC(0);
+      }
+    }
+    __syncthreads();
+    double* g = gpart + static_cast<int64_t>(blockIdx.x) * N * N;
+    for (int e = t; e < N * N; e += 256) {
+      const int a = e / N, b = e - a * N;
+      double sum = 0.0;
+#pragma unroll 8
+      for (int r = 0; r < NN_BM; ++r)
+        sum += static_cast<double>(T[r * NN_BN + a]) * static_cast<double>(T[r * NN_BN + b]);
+      g[e] = sum;
     }
   }
 }
@@ -245,11 +272,11 @@ void nn_dispatch_scaled(const NNArgs& a, hipStream_t s) {
   if (a.ascale)
     nn_kernel<TA, TX, TC, ACC, true><<<grid, 256, 0, s>>>(
         a.n, a.K, a.N, A, a.lda, a.ascale, a.ascale_ld, X, a.ldx, C, a.ldc,
-        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta));
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial);
   else
     nn_kernel<TA, TX, TC, ACC, false><<<grid, 256, 0, s>>>(
         a.n, a.K, a.N, A, a.lda, nullptr, 0, X, a.ldx, C, a.ldc,
-        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta));
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial);
 }
 
 template <typename TA>
@@ -291,10 +318,27 @@ void tn_dispatch(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
 
 }  // namespace
 
+int64_t nn_gram_partial_elems(int64_t n, int N) {
+  return N <= NN_BN ? cdiv(n, NN_BM) * N * N : 0;
+}
+
+int launch_gram_reduce(int64_t n, int N, const double* gpart, double* G, hipStream_t s) {
+  const int S = static_cast<int>(cdiv(n, NN_BM));
+  const int64_t outs = static_cast<int64_t>(N) * N;
+  if (S >= 16 && outs <= (int64_t(1) << 16))
+    tn_reduce_wave_kernel<double><<<static_cast<unsigned>(cdiv(outs, 4)), 256, 0, s>>>(
+        S, N, N, gpart, G, N, 1.0, 0.0, 0);
+  else
+    tn_reduce_kernel<double><<<static_cast<unsigned>(cdiv(outs, 256)), 256, 0, s>>>(
+        S, N, N, gpart, G, N, 1.0, 0.0, 0);
+  return 1;
+}
+
 int launch_nn(const NNArgs& a, hipStream_t s) {
   if (a.n <= 0 || a.N <= 0) return 0;  // K = 0 gives C = beta C below
+  if (a.gram_partial && a.N > NN_BN) return 0;
   int mfma = 0;
-  launch_nn_mfma_if(a, s, &mfma);
+  if (!a.gram_partial) launch_nn_mfma_if(a, s, &mfma);
   if (mfma) return mfma;
   switch (a.a_type) {
     case BK_F64:

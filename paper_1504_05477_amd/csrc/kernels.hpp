@@ -35,9 +35,16 @@ struct NNArgs {
   // scratch for the matrix-core path (X^T packed in A's type), nullable
   void* work = nullptr;
   size_t work_bytes = 0;
+  // N <= 32 only: per-row-block partial Grams of the stored C rows (FP64,
+  // nn_gram_partial_elems doubles), added up by launch_gram_reduce; the
+  // vector kernel then runs (no matrix-core path)
+  double* gram_partial = nullptr;
 };
-// returns the number of kernels launched
+// returns the number of kernels launched (0: not launched)
 int launch_nn(const NNArgs& a, hipStream_t s);
+int64_t nn_gram_partial_elems(int64_t n, int N);  // 0 if N > 32
+// G (N x N, ld N) = sum of the partial Grams of an n-row launch_nn
+int launch_gram_reduce(int64_t n, int N, const double* gpart, double* G, hipStream_t s);
 
 // C (p x r, ldc) = alpha * X^T . Y + beta * C with X L x p (ldx), Y L x r
 // (ldy): the reduction over the long L is split into S chunks whose FP64
