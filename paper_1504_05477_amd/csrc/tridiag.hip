@@ -25,10 +25,33 @@ constexpr int TRI_SY = 32;          // tile order of the trailing rank-2 nb upda
 // arrays take the rest of the 160 KB)
 constexpr int TRI_LDS_BYTES = 150 * 1024;
 
+// Sum over the 64 lanes of a wavefront (all lanes active), the same value on
+// every lane: DPP adds within quads (lane pairs, then pairs of pairs) and
+// within 16-lane rows (rotations by 4 and 8), then the four row sums are read
+// from lanes 0, 16, 32, 48 and added in that order.  Fixed order, no LDS.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  return read_lane(v, 0) + read_lane(v, 16) + read_lane(v, 32) + read_lane(v, 48);
+}
+
 __device__ double block_sum_1024(double v, double* red) {
   const int t = threadIdx.x;
   // wave sums, then the 16 wave totals in order
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_sum(v);
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   double s = 0.0;
@@ -43,7 +66,7 @@ __device__ double block_sum_1024(double v, double* red) {
 // before a later barrier.
 __device__ double wg_sum_1024(double v, double* red) {
   const int t = threadIdx.x;
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_sum(v);
   if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
   double s = 0.0;
@@ -268,7 +291,7 @@ __global__ __launch_bounds__(TRI_THREADS) void tri_panel_kernel(
         const double* colq = (qq < jj ? W + qq * mr : V + (qq - jj) * mr) + jj + 1;
         double sum = 0.0;
         for (int i = ln; i < s; i += 64) sum += colq[i] * v[i];
-        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+        sum = wave_sum(sum);
         if (ln == 0) c[qq] = sum;
       }
     }
@@ -620,7 +643,7 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
     double dot = 0.0;
 #pragma unroll
     for (int u = 0; u < VR; ++u) dot += vc[u] * xr[u];
-    for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o);
+    dot = wave_sum(dot);
     const double f = b * dot;
 #pragma unroll
     for (int u = 0; u < VR; ++u) xr[u] -= f * vc[u];
