@@ -89,8 +89,10 @@ int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) 
   // projection of block i: [Q_<i, B]^T B (i + 1) k x k, then Q_<i^T B
   for (int i = 1; i <= q + 1; ++i)
     need = std::max(need, tn_partial_elems(n, static_cast<int64_t>(i) * k, k));
-  // Gram partials of the fused applies (k <= 32): one k x k per row block
+  // Gram partials of the fused applies (k <= 32): one k x k per row block;
+  // the one-launch CholeskyQR passes alternate between two sets
   need = std::max(need, nn_gram_partial_elems(n, k));
+  need = std::max(need, 2 * cqr_pass_partial_elems(k));
   if (refine) {
     need = std::max(need, tn_partial_elems(n, d, k));
     need = std::max(need, tn_partial_elems(d, k, k));
@@ -491,23 +493,50 @@ struct Solver {
                   bool have_gram = false) {
     tm->begin(BK_PH_CHOLQR);
     const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
-    const bool fuse = fuse_gram();
+    const bool fuse = fuse_gram() && k <= kCqrPassMaxK;
     // B -> Bs2 -> Bs -> slab (B may be the slab)
     void* bufs[4] = {B, L->Bs2, L->Bs, qslab(slab)};
     const int64_t lds[4] = {ldb, k, k, m};
     int nl = 0;
+    // k <= 32: each pass is one launch that adds the previous pass's Gram
+    // partials, factors, solves the rows against R (no R^-1) and leaves the
+    // partials of the next Gram (two buffers, alternating)
+    double* part[2] = {L->partial, L->partial + cqr_pass_partial_elems(k)};
+    const double* gin = L->G;
+    int P = 1;
     for (int pass = 0; pass < 3; ++pass) {
       void* src = bufs[pass];
       const int64_t ls = lds[pass];
       if (pass == 0 ? !have_gram : !fuse) nl += gram(src, ls, k, src, ls, k, n, L->G);
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
-      launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv,
-                  L->cholwork, L->ctrl, s);
-      ++nl;
-      const bool g = fuse && pass < 2;
-      nl += apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0,
-                  g ? L->partial : nullptr);
-      if (g) nl += launch_gram_reduce(n, k, L->partial, L->G, s);
+      if (fuse) {
+        CqrPass a;
+        a.n = n;
+        a.k = k;
+        a.Gin = gin;
+        a.P = P;
+        a.Gpre = gpre;
+        a.mode = mode;
+        a.block = i;
+        a.tau = o.tau;
+        a.shift_coef = shift_coef;
+        a.R = L->R;
+        a.ctrl = L->ctrl;
+        a.X = src;
+        a.ldx = ls;
+        a.Y = bufs[pass + 1];
+        a.ldy = lds[pass + 1];
+        a.f64 = f64;
+        a.gout = pass < 2 ? part[pass & 1] : nullptr;
+        nl += launch_cqr_pass(a, s);
+        gin = part[pass & 1];
+        P = cqr_pass_grid(n, nullptr);
+      } else {
+        launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv, L->cholwork,
+                    L->ctrl, s);
+        ++nl;
+        nl += apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0);
+      }
       if (o.save) {
         if (pass == 0) {
           launch_copy2d(L->R, true, k, L->Racc, true, k, k, k, s);

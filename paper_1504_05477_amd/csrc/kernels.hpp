@@ -120,6 +120,34 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode,
 // T = A . B for k x k upper-triangular FP64 matrices (one workgroup).
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,
                        hipStream_t s);
+// One CholeskyQR pass for k <= kCqrPassMaxK in one launch: G = the sum of
+// the P FP64 Gram partials Gin (k x k each), R = chol(G [+ shift]) under
+// the modes of launch_chol (R written, ctrl updated), Y = X R^-1 by
+// forward substitution per row (X, Y n x k in the working type, X may be
+// Y), and the Gram partials of the stored Y in gout (one per workgroup,
+// cqr_pass_grid(n) of them; nullable).  Returns the kernels launched.
+constexpr int kCqrPassMaxK = 32;
+struct CqrPass {
+  int64_t n = 0;
+  int k = 0;
+  const double* Gin = nullptr;
+  int P = 1;
+  const double* Gpre = nullptr;
+  int mode = 0, block = 0;
+  double tau = 0.0, shift_coef = 0.0;
+  double* R = nullptr;
+  Ctrl* ctrl = nullptr;
+  const void* X = nullptr;
+  int64_t ldx = 0;
+  void* Y = nullptr;
+  int64_t ldy = 0;
+  bool f64 = false;
+  int64_t rows_per_wg = 0;  // set by the launcher
+  double* gout = nullptr;
+};
+int cqr_pass_grid(int64_t n, int64_t* rows_per_wg);
+int64_t cqr_pass_partial_elems(int k);
+int launch_cqr_pass(const CqrPass& a, hipStream_t s);
 
 // Helpers of the adjoint.
 // dst (cols x rows) = src (rows x cols)^T, FP64/FP32 either side.

@@ -232,12 +232,19 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
 #pragma unroll
   for (int j = 0; j < K; ++j) {  // no early exit: the loop stays unrolled
     double d = lane_f64(a[j], j);
-    if (!(d > 0.0) || !isfinite(d)) {
+    if (!(d > 0x1p-1000) || !isfinite(d)) {  // (a pivot below 2^-1000 is a breakdown)
       ok = false;
       d = 1.0;
     }
-    const double rd = sqrt(d);
-    const double inv = 1.0 / rd;
+    // 1/sqrt(d): hardware estimate and two Newton steps (quadratic), then
+    // sqrt(d) = d / sqrt(d) with one Newton correction; short dependency
+    // chains for the serial loop
+    double inv = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    inv = fma(inv, fma(-hd * inv, inv, 0.5), inv);
+    inv = fma(inv, fma(-hd * inv, inv, 0.5), inv);
+    const double s0 = d * inv;
+    const double rd = fma(fma(-s0, s0, d), 0.5 * inv, s0);
     if (j < k) minpiv = fmin(minpiv, rd);
     rinv[j] = inv;
     a[j] = (c == j) ? rd : a[j] * inv;  // row j of the factor (lanes c >= j)
@@ -245,6 +252,50 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
     for (int r = j + 1; r < K; ++r) a[r] -= lane_f64(a[j], r) * a[j];
   }
   return ok;
+}
+
+// The mode logic of the CholeskyQR factor for k <= 64 in one wavefront
+// (lane c holds g = column c of G; tr = trace G, pre = trace Gpre): the
+// breakdown and rank tests, then the factor in a / rinv.  Returns true when
+// the block is dropped (zero factor); ctrl is updated when `report`.
+template <int K>
+__device__ bool chol_wave_factor(int k, const double (&g)[K], int bad, double tr, double pre,
+                                 int mode, int block, double tau, double shift_coef,
+                                 bool report, Ctrl* ctrl, double (&a)[K], double (&rinv)[K]) {
+  const int c = threadIdx.x & 63;
+  report = report && c == 0;
+  bool zero = false;
+  if (__any(bad)) {
+    if (report) atomicOr(&ctrl->flags, CTRL_NONFINITE);
+    zero = true;
+  } else if (mode == CHOL_FIRST) {
+    if (!(sqrt(tr) > tau * sqrt(pre))) {
+      if (report) atomicMin(&ctrl->q_eff, block - 1);
+      zero = true;
+    }
+  } else if (!(tr > 0.0)) {
+    if (mode == CHOL_FIRST_BLOCK0 && report) atomicOr(&ctrl->flags, CTRL_RANK);
+    zero = true;
+  }
+  double minpiv = 0.0;
+  if (!zero && mode == CHOL_FIRST_BLOCK0) {
+    const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv);
+    if (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr))) {
+      if (report) atomicOr(&ctrl->flags, CTRL_RANK);
+      zero = true;
+    }
+  }
+  if (!zero) {
+    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
+    if (!chol_regs<K>(k, g, shift, a, rinv, minpiv)) {
+      if (report) {
+        if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+        else atomicMin(&ctrl->q_eff, block - 1);
+      }
+      zero = true;
+    }
+  }
+  return zero;
 }
 
 // CholeskyQR factor for k <= 64 in one wavefront (same modes and outputs as
@@ -267,38 +318,9 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
   }
   const double tr = wave_sum_f64(c < k ? G[c * k + c] : 0.0);
   const double pre = (mode == CHOL_FIRST) ? wave_sum_f64(c < k ? Gpre[c * k + c] : 0.0) : 0.0;
-  bool zero = false;
-  if (__any(bad)) {
-    if (c == 0) atomicOr(&ctrl->flags, CTRL_NONFINITE);
-    zero = true;
-  } else if (mode == CHOL_FIRST) {
-    if (!(sqrt(tr) > tau * sqrt(pre))) {
-      if (c == 0) atomicMin(&ctrl->q_eff, block - 1);
-      zero = true;
-    }
-  } else if (!(tr > 0.0)) {
-    if (mode == CHOL_FIRST_BLOCK0 && c == 0) atomicOr(&ctrl->flags, CTRL_RANK);
-    zero = true;
-  }
   double a[K], rinv[K];
-  double minpiv = 0.0;
-  if (!zero && mode == CHOL_FIRST_BLOCK0) {
-    const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv);
-    if (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr))) {
-      if (c == 0) atomicOr(&ctrl->flags, CTRL_RANK);
-      zero = true;
-    }
-  }
-  if (!zero) {
-    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
-    if (!chol_regs<K>(k, g, shift, a, rinv, minpiv)) {
-      if (c == 0) {
-        if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
-        else atomicMin(&ctrl->q_eff, block - 1);
-      }
-      zero = true;
-    }
-  }
+  const bool zero = chol_wave_factor<K>(k, g, bad, tr, pre, mode, block, tau, shift_coef, true,
+                                        ctrl, a, rinv);
   if (zero) {
     for (int i = c; i < k * k; i += 64) {
       R[i] = 0.0;
@@ -813,6 +835,230 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,
                        hipStream_t s) {
   trmm_upper_kernel<<<1, 256, 0, s>>>(k, A, B, T);
+}
+
+namespace {
+constexpr int CQR_ROWS = 256;   // rows per chunk (one per thread)
+constexpr int CQR_MAX_WG = 64;  // workgroups (and Gram partials) per pass
+
+// One CholeskyQR pass for k <= 32 in one launch.  Every workgroup
+//  1. adds the P Gram partials Gin[p k k] in a fixed order (the same G in
+//     every workgroup);
+//  2. factors G [+ shift] in wavefront 0 with the mode logic of
+//     chol_wave_kernel (workgroup 0 reports to ctrl and writes R);
+//  3. for each chunk of 256 rows of its range: Y R = X by forward
+//     substitution, one thread per row (no R^-1 is formed), the rows stored
+//     in the working type, and their Gram accumulated in FP64 from the
+//     stored values; the workgroup's Gram goes to gout[blockIdx.x k k]
+//     (nullable).
+// A dropped block (zero factor) gives Y = 0.  X may be Y.
+template <typename T, int K>
+__global__ __launch_bounds__(256) void cqr_pass_kernel(
+    int64_t n, int k, const double* __restrict__ Gin, int P, const double* __restrict__ Gpre,
+    int mode, int block, double tau, double shift_coef, double* __restrict__ R, Ctrl* ctrl,
+    const T* X, int64_t ldx, T* Y, int64_t ldy, int64_t rows_per_wg, double* __restrict__ gout) {
+  constexpr int LD = K + 1;
+  constexpr int TPR = (K == 24) ? 32 : K;  // threads per row in the tile copies
+  constexpr int RPI = 256 / TPR;           // rows per copy step
+  constexpr int NC = CQR_ROWS / RPI;       // copy steps per chunk
+  constexpr int NE = (K * K + 255) / 256;  // Gram entries per thread in the sum
+  constexpr int PB = 24;                   // partials loaded per batch
+  constexpr int GB = K / 8;                // Gram block edge per lane (8 x 8 lanes)
+  __shared__ double Gs[K * K];
+  __shared__ double Rs[K * K];
+  __shared__ double rd[K];
+  __shared__ double Ys[CQR_ROWS * LD];
+  const int t = threadIdx.x;
+  const int kk = k * k;
+  const int gc = t % TPR, gr = t / TPR;  // copy layout
+  const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
+  const int64_t hi = lo + rows_per_wg < n ? lo + rows_per_wg : n;
+  // the first chunk's rows are requested before the Gram sum and the factor
+  T xv[NC];
+  {
+    const int rows = static_cast<int>(hi - lo < CQR_ROWS ? hi - lo : CQR_ROWS);
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const int r = gr + q * RPI;
+      xv[q] = (gc < k && r < rows) ? X[(lo + r) * ldx + gc] : static_cast<T>(0);
+    }
+  }
+  const double gpre_d = (mode == CHOL_FIRST && t < k) ? Gpre[t * k + t] : 0.0;
+  // G = sum of the partials in index order, PB independent loads in flight
+  {
+    double sum[NE];
+#pragma unroll
+    for (int u = 0; u < NE; ++u) sum[u] = 0.0;
+    for (int p0 = 0; p0 < P; p0 += PB) {
+      double v[NE][PB];
+#pragma unroll
+      for (int u = 0; u < NE; ++u) {
+        const int e = t + 256 * u;
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+          v[u][j] = (e < kk && p0 + j < P) ? Gin[static_cast<int64_t>(p0 + j) * kk + e] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < NE; ++u)
+#pragma unroll
+        for (int j = 0; j < PB; ++j) sum[u] += v[u][j];
+    }
+#pragma unroll
+    for (int u = 0; u < NE; ++u) {
+      const int e = t + 256 * u;
+      if (e < kk) {
+        const int r = e / k;
+        Gs[r * K + (e - r * k)] = sum[u];
+      }
+    }
+  }
+  __syncthreads();
+  if (t < 64) {
+    const int c = t;
+    double g[K];
+    int bad = 0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const double x = (r < k && c < k) ? Gs[r * K + c] : 0.0;
+      if (!isfinite(x)) bad = 1;
+      g[r] = x;
+    }
+    const double tr = wave_sum_f64(c < k ? Gs[c * K + c] : 0.0);
+    const double pre = (mode == CHOL_FIRST) ? wave_sum_f64(gpre_d) : 0.0;
+    double a[K], rinv[K];
+    const bool zero = chol_wave_factor<K>(k, g, bad, tr, pre, mode, block, tau, shift_coef,
+                                          blockIdx.x == 0, ctrl, a, rinv);
+    if (c < K) {
+      double dinv = 0.0;
+#pragma unroll
+      for (int j = 0; j < K; ++j)
+        if (j == c) dinv = rinv[j];
+      rd[c] = (zero || c >= k) ? 0.0 : dinv;
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+        Rs[r * K + c] = (zero || c >= k || r > c) ? 0.0 : a[r];
+      if (blockIdx.x == 0 && c < k) {
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+          if (r < k) R[r * k + c] = (zero || r > c) ? 0.0 : a[r];
+      }
+    }
+  }
+  // wavefront w sums the Gram of rows [64 w, 64 w + 64) of each chunk; lane
+  // (la, lb) holds the GB x GB block at (GB la, GB lb)
+  const int w = t >> 6, la = (t & 63) >> 3, lb = t & 7;
+  double acc[GB][GB];
+#pragma unroll
+  for (int x = 0; x < GB; ++x)
+#pragma unroll
+    for (int z = 0; z < GB; ++z) acc[x][z] = 0.0;
+  for (int64_t r0 = lo; r0 < hi; r0 += CQR_ROWS) {
+    const int rows = static_cast<int>(hi - r0 < CQR_ROWS ? hi - r0 : CQR_ROWS);
+    if (r0 != lo) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int r = gr + q * RPI;
+        xv[q] = (gc < k && r < rows) ? X[(r0 + r) * ldx + gc] : static_cast<T>(0);
+      }
+    }
+    if (gc < K) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) Ys[(gr + q * RPI) * LD + gc] = static_cast<double>(xv[q]);
+    }
+    __syncthreads();
+    double y[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) y[c] = Ys[t * LD + c];
+    // right-looking: each solved entry updates the later ones at once, in
+    // the same order as the row-by-row sums (short dependency chains)
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      y[j] *= rd[j];
+#pragma unroll
+      for (int c = j + 1; c < K; ++c) y[c] -= y[j] * Rs[j * K + c];
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) Ys[t * LD + c] = static_cast<double>(static_cast<T>(y[c]));
+    __syncthreads();
+    if (gc < k) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int r = gr + q * RPI;
+        if (r < rows) Y[(r0 + r) * ldy + gc] = static_cast<T>(Ys[r * LD + gc]);
+      }
+    }
+    if (gout) {
+#pragma unroll 8
+      for (int r = 64 * w; r < 64 * w + 64; ++r) {
+        double av[GB], bv[GB];
+#pragma unroll
+        for (int x = 0; x < GB; ++x) {
+          av[x] = Ys[r * LD + GB * la + x];
+          bv[x] = Ys[r * LD + GB * lb + x];
+        }
+#pragma unroll
+        for (int x = 0; x < GB; ++x)
+#pragma unroll
+          for (int z = 0; z < GB; ++z) acc[x][z] += av[x] * bv[z];
+      }
+    }
+    __syncthreads();
+  }
+  if (!gout) return;
+  // the four wavefronts' sums, added in wavefront order
+  double* ws = Ys;  // 4 K x K
+#pragma unroll
+  for (int x = 0; x < GB; ++x)
+#pragma unroll
+    for (int z = 0; z < GB; ++z) ws[w * K * K + (GB * la + x) * K + GB * lb + z] = acc[x][z];
+  __syncthreads();
+  double* g = gout + static_cast<int64_t>(blockIdx.x) * kk;
+  for (int e = t; e < kk; e += 256) {
+    const int a = e / k, b = e - a * k;
+    const int o = a * K + b;
+    g[e] = ((ws[o] + ws[K * K + o]) + ws[2 * K * K + o]) + ws[3 * K * K + o];
+  }
+}
+
+template <typename T, int K>
+void cqr_pass_launch(unsigned grid, const CqrPass& a, hipStream_t s) {
+  cqr_pass_kernel<T, K><<<grid, 256, 0, s>>>(
+      a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
+      static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
+}
+}  // namespace
+
+int cqr_pass_grid(int64_t n, int64_t* rows_per_wg) {
+  int64_t chunks = cdiv(n, CQR_ROWS);
+  if (chunks < 1) chunks = 1;
+  const int64_t per = cdiv(chunks, CQR_MAX_WG);
+  const int64_t g = cdiv(chunks, per);
+  if (rows_per_wg) *rows_per_wg = per * CQR_ROWS;
+  return static_cast<int>(g);
+}
+
+int64_t cqr_pass_partial_elems(int k) {
+  return k <= kCqrPassMaxK ? static_cast<int64_t>(CQR_MAX_WG) * k * k : 0;
+}
+
+int launch_cqr_pass(const CqrPass& a, hipStream_t s) {
+  if (a.n <= 0 || a.k <= 0 || a.k > kCqrPassMaxK || a.P < 1) return 0;
+  int64_t per = 0;
+  const unsigned g = static_cast<unsigned>(cqr_pass_grid(a.n, &per));
+  CqrPass b = a;
+  b.rows_per_wg = per;
+#define BK_CQR(KK)                                                  \
+  if (a.k <= KK) {                                                  \
+    if (a.f64) cqr_pass_launch<double, KK>(g, b, s);                \
+    else cqr_pass_launch<float, KK>(g, b, s);                       \
+    return 1;                                                       \
+  }
+  BK_CQR(8)
+  BK_CQR(16)
+  BK_CQR(24)
+  BK_CQR(32)
+#undef BK_CQR
+  return 0;
 }
 
 void launch_transpose(const void* src, bool src_f64, int64_t lds, void* dst, bool dst_f64,
