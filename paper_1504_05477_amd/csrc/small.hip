@@ -215,23 +215,40 @@ __device__ __forceinline__ double wave_sum_f64(double x) {
   return x;
 }
 
+// LDS written by lanes of one wavefront becomes visible to its other lanes
+// (LDS operations of a wavefront complete in order; this keeps the compiler
+// from moving them across).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Upper Cholesky factor of (G + shift I) in registers of one wavefront:
 // lane c holds column c (a[r] = S[r][c], rows r <= c meaningful), the k x k
-// problem padded to K with the identity.  Right-looking: the pivot and the
-// scaled row j are broadcast from their lanes with readlane.  rinv[j] =
-// 1 / S[j][j].  Returns false on a non-positive or non-finite pivot.
+// problem padded to K with the identity.  Right-looking: every lane posts
+// its entry of row j to rb (2 x 64 doubles of LDS), reads the pivot and the
+// row back, forms 1 / sqrt(pivot) itself and applies the rank-1 update with
+// one FMA per entry.  rinv[j] = 1 / S[j][j].  Returns false on a
+// non-positive or non-finite pivot.
 template <int K>
 __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)[K],
-                          double (&rinv)[K], double& minpiv) {
-  const int c = threadIdx.x;
+                          double (&rinv)[K], double& minpiv, double* rb) {
+  const int c = threadIdx.x & 63;
 #pragma unroll
   for (int r = 0; r < K; ++r)
     a[r] = (c < k) ? ((r <= c) ? g[r] + (r == c ? shift : 0.0) : 0.0) : (r == c ? 1.0 : 0.0);
   minpiv = INFINITY;
   bool ok = true;
+  // two row buffers, alternating: row j + 1 is posted as soon as its own
+  // entry of step j's update is done, and the rest of the update overlaps
+  // the post
+  rb[c] = a[0];
+  wave_lds_sync();
 #pragma unroll
   for (int j = 0; j < K; ++j) {  // no early exit: the loop stays unrolled
-    double d = lane_f64(a[j], j);
+    const double* b = rb + (j & 1) * 64;
+    double d = b[j];
     if (!(d > 0x1p-1000) || !isfinite(d)) {  // (a pivot below 2^-1000 is a breakdown)
       ok = false;
       d = 1.0;
@@ -248,8 +265,15 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
     if (j < k) minpiv = fmin(minpiv, rd);
     rinv[j] = inv;
     a[j] = (c == j) ? rd : a[j] * inv;  // row j of the factor (lanes c >= j)
+    // S[j][r] S[j][c] = b[r] (a[j] / sqrt(d)): one FMA per entry
+    const double tj = a[j] * inv;
+    if (j + 1 < K) {
+      a[j + 1] -= b[j + 1] * tj;
+      rb[((j + 1) & 1) * 64 + c] = a[j + 1];  // (every lane: no branch)
+      wave_lds_sync();
+    }
 #pragma unroll
-    for (int r = j + 1; r < K; ++r) a[r] -= lane_f64(a[j], r) * a[j];
+    for (int r = j + 2; r < K; ++r) a[r] -= b[r] * tj;
   }
   return ok;
 }
@@ -261,7 +285,8 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
 template <int K>
 __device__ bool chol_wave_factor(int k, const double (&g)[K], int bad, double tr, double pre,
                                  int mode, int block, double tau, double shift_coef,
-                                 bool report, Ctrl* ctrl, double (&a)[K], double (&rinv)[K]) {
+                                 bool report, Ctrl* ctrl, double (&a)[K], double (&rinv)[K],
+                                 double* rb) {
   const int c = threadIdx.x & 63;
   report = report && c == 0;
   bool zero = false;
@@ -279,7 +304,7 @@ __device__ bool chol_wave_factor(int k, const double (&g)[K], int bad, double tr
   }
   double minpiv = 0.0;
   if (!zero && mode == CHOL_FIRST_BLOCK0) {
-    const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv);
+    const bool ok = chol_regs<K>(k, g, 0.0, a, rinv, minpiv, rb);
     if (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr))) {
       if (report) atomicOr(&ctrl->flags, CTRL_RANK);
       zero = true;
@@ -287,7 +312,7 @@ __device__ bool chol_wave_factor(int k, const double (&g)[K], int bad, double tr
   }
   if (!zero) {
     const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
-    if (!chol_regs<K>(k, g, shift, a, rinv, minpiv)) {
+    if (!chol_regs<K>(k, g, shift, a, rinv, minpiv, rb)) {
       if (report) {
         if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
         else atomicMin(&ctrl->q_eff, block - 1);
@@ -319,8 +344,9 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
   const double tr = wave_sum_f64(c < k ? G[c * k + c] : 0.0);
   const double pre = (mode == CHOL_FIRST) ? wave_sum_f64(c < k ? Gpre[c * k + c] : 0.0) : 0.0;
   double a[K], rinv[K];
+  __shared__ double rb[128];
   const bool zero = chol_wave_factor<K>(k, g, bad, tr, pre, mode, block, tau, shift_coef, true,
-                                        ctrl, a, rinv);
+                                        ctrl, a, rinv, rb);
   if (zero) {
     for (int i = c; i < k * k; i += 64) {
       R[i] = 0.0;
@@ -852,7 +878,20 @@ constexpr int CQR_MAX_WG = 64;  // workgroups (and Gram partials) per pass
 //     stored values; the workgroup's Gram goes to gout[blockIdx.x k k]
 //     (nullable).
 // A dropped block (zero factor) gives Y = 0.  X may be Y.
-template <typename T, int K>
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+};
+
+// VEC: rows are copied with 16-byte accesses (k, ldx, ldy multiples of the
+// vector width and X, Y 16-byte aligned).
+template <typename T, int K, bool VEC>
 __global__ __launch_bounds__(256) void cqr_pass_kernel(
     int64_t n, int k, const double* __restrict__ Gin, int P, const double* __restrict__ Gpre,
     int mode, int block, double tau, double shift_coef, double* __restrict__ R, Ctrl* ctrl,
@@ -861,29 +900,70 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
   constexpr int TPR = (K == 24) ? 32 : K;  // threads per row in the tile copies
   constexpr int RPI = 256 / TPR;           // rows per copy step
   constexpr int NC = CQR_ROWS / RPI;       // copy steps per chunk
+  using V = typename Vec16<T>::type;
+  constexpr int VW = 16 / sizeof(T);       // vector width
+  constexpr int NQ = (K + VW - 1) / VW;    // vectors per row, at most
+  constexpr int NX = VEC ? NQ : NC;        // copy registers per thread
   constexpr int NE = (K * K + 255) / 256;  // Gram entries per thread in the sum
   constexpr int PB = 24;                   // partials loaded per batch
   constexpr int GB = K / 8;                // Gram block edge per lane (8 x 8 lanes)
   __shared__ double Gs[K * K];
   __shared__ double Rs[K * K];
   __shared__ double rd[K];
+  __shared__ double pd[K];
+  __shared__ double rb[128];
   __shared__ double Ys[CQR_ROWS * LD];
   const int t = threadIdx.x;
   const int kk = k * k;
   const int gc = t % TPR, gr = t / TPR;  // copy layout
   const int64_t lo = static_cast<int64_t>(blockIdx.x) * rows_per_wg;
   const int64_t hi = lo + rows_per_wg < n ? lo + rows_per_wg : n;
-  // the first chunk's rows are requested before the Gram sum and the factor
-  T xv[NC];
-  {
-    const int rows = static_cast<int>(hi - lo < CQR_ROWS ? hi - lo : CQR_ROWS);
+  // vector copies: item i = t + 256 q of a chunk is row i / kv, vector
+  // i % kv (the quotient by a multiply-high, exact for i < 2^12, kv <= 16)
+  const int kv = k / VW;
+  const unsigned kvm = VEC ? 0xFFFFFFFFu / static_cast<unsigned>(kv) + 1u : 0u;
+  // a chunk's rows: one T (scalar copies) or one V (vector copies) per item
+  V xv[NX];
+  auto fetch = [&](int64_t c0, int rows) {
 #pragma unroll
-    for (int q = 0; q < NC; ++q) {
-      const int r = gr + q * RPI;
-      xv[q] = (gc < k && r < rows) ? X[(lo + r) * ldx + gc] : static_cast<T>(0);
+    for (int q = 0; q < NX; ++q) {
+      V v;
+      if (VEC) {
+        const unsigned i = static_cast<unsigned>(t + 256 * q);
+        const int r = static_cast<int>(__umulhi(i, kvm));
+        const int cv = static_cast<int>(i) - r * kv;
+        if (q < kv && r < rows)
+          v = *reinterpret_cast<const V*>(X + (c0 + r) * ldx + cv * VW);
+        else
+          v = V{};
+      } else {
+        const int r = gr + q * RPI;
+        v = V{};
+        v.x = (gc < k && r < rows) ? X[(c0 + r) * ldx + gc] : static_cast<T>(0);
+      }
+      xv[q] = v;
     }
-  }
-  const double gpre_d = (mode == CHOL_FIRST && t < k) ? Gpre[t * k + t] : 0.0;
+  };
+  auto stage = [&]() {  // the fetched rows into Ys (FP64)
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      if (VEC) {
+        const unsigned i = static_cast<unsigned>(t + 256 * q);
+        const int r = static_cast<int>(__umulhi(i, kvm));
+        const int cv = static_cast<int>(i) - r * kv;
+        if (q < kv) {
+          const T* e = reinterpret_cast<const T*>(&xv[q]);
+#pragma unroll
+          for (int w = 0; w < VW; ++w) Ys[r * LD + cv * VW + w] = static_cast<double>(e[w]);
+        }
+      } else if (gc < K) {
+        Ys[(gr + q * RPI) * LD + gc] = static_cast<double>(xv[q].x);
+      }
+    }
+  };
+  // the first chunk's rows are requested before the Gram sum and the factor
+  fetch(lo, static_cast<int>(hi - lo < CQR_ROWS ? hi - lo : CQR_ROWS));
+  if (t < K) pd[t] = (mode == CHOL_FIRST && t < k) ? Gpre[t * k + t] : 0.0;
   // G = sum of the partials in index order, PB independent loads in flight
   {
     double sum[NE];
@@ -923,11 +1003,16 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
       if (!isfinite(x)) bad = 1;
       g[r] = x;
     }
-    const double tr = wave_sum_f64(c < k ? Gs[c * K + c] : 0.0);
-    const double pre = (mode == CHOL_FIRST) ? wave_sum_f64(gpre_d) : 0.0;
+    // the traces, summed in index order by every lane
+    double tr = 0.0, pre = 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      tr += r < k ? Gs[r * K + r] : 0.0;  // (entries beyond k are unset)
+      pre += pd[r];
+    }
     double a[K], rinv[K];
     const bool zero = chol_wave_factor<K>(k, g, bad, tr, pre, mode, block, tau, shift_coef,
-                                          blockIdx.x == 0, ctrl, a, rinv);
+                                          blockIdx.x == 0, ctrl, a, rinv, rb);
     if (c < K) {
       double dinv = 0.0;
 #pragma unroll
@@ -954,37 +1039,52 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
     for (int z = 0; z < GB; ++z) acc[x][z] = 0.0;
   for (int64_t r0 = lo; r0 < hi; r0 += CQR_ROWS) {
     const int rows = static_cast<int>(hi - r0 < CQR_ROWS ? hi - r0 : CQR_ROWS);
-    if (r0 != lo) {
-#pragma unroll
-      for (int q = 0; q < NC; ++q) {
-        const int r = gr + q * RPI;
-        xv[q] = (gc < k && r < rows) ? X[(r0 + r) * ldx + gc] : static_cast<T>(0);
-      }
-    }
-    if (gc < K) {
-#pragma unroll
-      for (int q = 0; q < NC; ++q) Ys[(gr + q * RPI) * LD + gc] = static_cast<double>(xv[q]);
-    }
+    if (r0 != lo) fetch(r0, rows);
+    stage();
     __syncthreads();
     double y[K];
 #pragma unroll
-    for (int c = 0; c < K; ++c) y[c] = Ys[t * LD + c];
+    for (int c = 0; c < K; ++c) y[c] = c < k ? Ys[t * LD + c] : 0.0;  // (unset beyond k)
     // right-looking: each solved entry updates the later ones at once, in
-    // the same order as the row-by-row sums (short dependency chains)
+    // the same order as the row-by-row sums (short dependency chains); row
+    // j + 1 of R is read from LDS while row j is applied
+    double rn[K];
+#pragma unroll
+    for (int c = 1; c < K; ++c) rn[c] = Rs[c];
+    rn[0] = rd[0];
 #pragma unroll
     for (int j = 0; j < K; ++j) {
-      y[j] *= rd[j];
+      double rc[K];
 #pragma unroll
-      for (int c = j + 1; c < K; ++c) y[c] -= y[j] * Rs[j * K + c];
+      for (int c = j; c < K; ++c) rc[c] = rn[c];
+      if (j + 1 < K) {
+        rn[j + 1] = rd[j + 1];
+#pragma unroll
+        for (int c = j + 2; c < K; ++c) rn[c] = Rs[(j + 1) * K + c];
+      }
+      y[j] *= rc[j];
+#pragma unroll
+      for (int c = j + 1; c < K; ++c) y[c] -= y[j] * rc[c];
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) Ys[t * LD + c] = static_cast<double>(static_cast<T>(y[c]));
     __syncthreads();
-    if (gc < k) {
 #pragma unroll
-      for (int q = 0; q < NC; ++q) {
+    for (int q = 0; q < NX; ++q) {
+      if (VEC) {
+        const unsigned i = static_cast<unsigned>(t + 256 * q);
+        const int r = static_cast<int>(__umulhi(i, kvm));
+        const int cv = static_cast<int>(i) - r * kv;
+        if (q < kv && r < rows) {
+          V v;
+          T* e = reinterpret_cast<T*>(&v);
+#pragma unroll
+          for (int w = 0; w < VW; ++w) e[w] = static_cast<T>(Ys[r * LD + cv * VW + w]);
+          *reinterpret_cast<V*>(Y + (r0 + r) * ldy + cv * VW) = v;
+        }
+      } else {
         const int r = gr + q * RPI;
-        if (r < rows) Y[(r0 + r) * ldy + gc] = static_cast<T>(Ys[r * LD + gc]);
+        if (gc < k && r < rows) Y[(r0 + r) * ldy + gc] = static_cast<T>(Ys[r * LD + gc]);
       }
     }
     if (gout) {
@@ -1022,9 +1122,18 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
 
 template <typename T, int K>
 void cqr_pass_launch(unsigned grid, const CqrPass& a, hipStream_t s) {
-  cqr_pass_kernel<T, K><<<grid, 256, 0, s>>>(
-      a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
-      static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
+  constexpr int VW = 16 / sizeof(T);
+  const bool vec = a.k % VW == 0 && a.ldx % VW == 0 && a.ldy % VW == 0 &&
+                   reinterpret_cast<uintptr_t>(a.X) % 16 == 0 &&
+                   reinterpret_cast<uintptr_t>(a.Y) % 16 == 0;
+  if (vec)
+    cqr_pass_kernel<T, K, true><<<grid, 256, 0, s>>>(
+        a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
+        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
+  else
+    cqr_pass_kernel<T, K, false><<<grid, 256, 0, s>>>(
+        a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
+        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
 }
 }  // namespace
 
