@@ -93,6 +93,8 @@ int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) 
   // the one-launch CholeskyQR passes alternate between two sets
   need = std::max(need, nn_gram_partial_elems(n, k));
   need = std::max(need, 2 * cqr_pass_partial_elems(k));
+  // M = W^T W on the matrix cores (FP32 W, m <= kGramSymMaxM)
+  need = std::max(need, gram_sym_partial_elems(d, static_cast<int>(m)));
   if (refine) {
     need = std::max(need, tn_partial_elems(n, d, k));
     need = std::max(need, tn_partial_elems(d, k, k));
@@ -320,6 +322,12 @@ struct Op {
   virtual void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) = 0;
   // Y (d x k, ldy) = A^T X, X n x k (ldx)
   virtual void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) = 0;
+  // ax for an X that aty produced (the Krylov recurrence): operators that
+  // are exact on such inputs without a correction term may skip it
+  virtual void ax_of_aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
+                         hipStream_t s) {
+    ax(X, ldx, k, Y, ldy, s);
+  }
 };
 
 struct DenseOp : Op {
@@ -386,27 +394,38 @@ struct CsrOp : Op {
   //   Abar X   = A X   - mu (1^T X)    and   Abar^T Y = A^T Y - 1 (mu^T Y),
   // the k-vector (1^T X or mu^T Y) first, then the product with the rank-1
   // correction in its epilogue.
+  //
+  // X = Abar^T Y has 1^T X = (Abar 1)^T Y = 0 (Abar 1 = A 1 - d mu = 0, mu
+  // being the row means), so for such an X the correction of Abar X is zero
+  // in exact arithmetic (computed, it is rounding far below the product's
+  // own) and is skipped (`exact`).
   void product(const int32_t* r_, const int32_t* c_, const float* v_, const CsrPlan& pl,
                int phase, const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
-               const float* rowvec, const float* colw, int64_t Lc, hipStream_t s) {
-    if (mu) {
+               const float* rowvec, const float* colw, int64_t Lc, hipStream_t s,
+               bool exact = false) {
+    if (exact) rowvec = nullptr;
+    if (mu && !exact) {
       tm->begin(BK_PH_CENTER);
       launch_colsum(static_cast<const float*>(X), ldx, Lc, k, colw, colpart, colvec, s);
       tm->end(2);
     }
     tm->begin(phase);
     launch_csr_product(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
-                       static_cast<float*>(Y), ldy, rowvec, mu ? colvec : nullptr, s);
+                       static_cast<float*>(Y), ldy, rowvec, (mu && !exact) ? colvec : nullptr, s);
     tm->end(1);
     if (pl.nmulti > 0) {
       tm->begin(BK_PH_LONG);
-      launch_csr_combine(pl, r_, k, static_cast<float*>(Y), ldy, rowvec, mu ? colvec : nullptr,
-                         s);
+      launch_csr_combine(pl, r_, k, static_cast<float*>(Y), ldy, rowvec,
+                         (mu && !exact) ? colvec : nullptr, s);
       tm->end(1);
     }
   }
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s);
+  }
+  void ax_of_aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
+                 hipStream_t s) override {
+    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s, true);
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s);
@@ -678,7 +697,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   if (!o.si) {
     for (int i = 1; i <= q; ++i) {
       op.aty(S.qslab(i - 1), m, pw, S.wslab(i - 1), m, s);
-      op.ax(S.wslab(i - 1), m, pw, S.qslab(i), m, s);  // the block in its slab
+      op.ax_of_aty(S.wslab(i - 1), m, pw, S.qslab(i), m, s);  // the block in its slab
       const double* gpre = S.project(i);
       S.orth_block(i, i, S.qslab(i), m, gpre, S.fuse_gram());
     }
@@ -687,7 +706,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     // Algorithm 1: the single block is replaced by orth(A A^T block)
     for (int i = 1; i <= q; ++i) {
       op.aty(S.qslab(0), m, pw, S.wslab(0), m, s);
-      op.ax(S.wslab(0), m, pw, L.Bs, pw, s);
+      op.ax_of_aty(S.wslab(0), m, pw, L.Bs, pw, s);
       tm.begin(BK_PH_PROJ);
       const int nl = S.gram(L.Bs, pw, pw, L.Bs, pw, pw, n, L.Gpre);  // trace for the breakdown test
       tm.end(nl);
@@ -699,8 +718,12 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
 
   // Step 4: M = W^T W = Q^T A A^T Q in FP64.
   tm.begin(BK_PH_M);
-  S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M, 1.0, 0.0, true);
-  tm.end(2);
+  // narrow FP32 W: matrix-core tiles of the upper triangle
+  int mlaunch = f64 ? 0
+                    : launch_gram_sym_mfma(d, static_cast<int>(m), static_cast<const float*>(L.W),
+                                           m, L.M, m, L.partial, s);
+  if (!mlaunch) mlaunch = S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M, 1.0, 0.0, true);
+  tm.end(mlaunch);
   BK_TRY_LAUNCH();
 
   // Step 5: top-k eigenpairs of M.

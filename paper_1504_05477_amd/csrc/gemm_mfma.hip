@@ -508,6 +508,171 @@ __global__ __launch_bounds__(256) void pack_t_kernel(const float* __restrict__ s
 int esize(int type) { return type == BK_F32 ? 4 : (type == BK_BF16 ? 2 : 1); }
 int chunk_vals(int type) { return 128 / esize(type); }
 
+// ------------------------------------------------------------ M = W^T W --
+// Symmetric Gram of a narrow FP32 block (m <= 384 columns, long L): the
+// upper triangle in 32 x 32 tiles; a workgroup of 8 wavefronts takes a tile
+// group (up to 32 tiles, 4 per wavefront) over one of S contiguous row
+// splits.  Rows arrive in 32-row chunks (contiguous 16-byte loads when m,
+// ldw and W allow) into two LDS buffers: while chunk c is multiplied,
+// chunk c + 1 goes from registers into the other buffer and chunk c + 2 is
+// requested; a chunk's tile is summed in FP32 by 16 MFMA
+// steps of two rows and added to the wavefront's FP64 running sums.  The G
+// groups of one split run on one XCD (adjacent slots of that XCD), so
+// their re-reads of the rows hit its L2.  Output: part[(split T + tile)
+// 1024 + v 64 + lane], accumulator register v of lane `lane` (see out_row).
+constexpr int GS_CH = 32;    // rows per chunk
+constexpr int GS_TPW = 4;    // tiles per wavefront
+constexpr int GS_WAVES = 8;  // wavefronts per workgroup
+constexpr int GS_TPG = GS_TPW * GS_WAVES;
+
+__device__ __forceinline__ void gs_tile(int ti, int MT, int* bi, int* bj) {
+  int b = 0, rem = ti;
+  while (rem >= MT - b) {
+    rem -= MT - b;
+    ++b;
+  }
+  *bi = b;
+  *bj = b + rem;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(512) void gram_sym_mfma_kernel(int64_t L, int m,
+                                                            const float* __restrict__ W,
+                                                            int64_t ldw, int S, int G,
+                                                            int64_t per, double* __restrict__ part) {
+  extern __shared__ float Wsm[];
+  const int MT = (m + 31) >> 5;
+  const int T = MT * (MT + 1) / 2;
+  const int LDW = MT * 32 + 4;  // (rows 4 banks apart)
+  const int BUF = GS_CH * LDW;
+  const int id = blockIdx.x, xcd = id & 7, slot = id >> 3;
+  const int split = (slot / G) * 8 + xcd, g = slot % G;
+  if (split >= S) return;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int bi[GS_TPW], bj[GS_TPW];
+  int nt = 0;
+#pragma unroll
+  for (int u = 0; u < GS_TPW; ++u) {
+    const int ti = g * GS_TPG + u * GS_WAVES + w;
+    bi[u] = bj[u] = 0;
+    if (ti < T) {
+      gs_tile(ti, MT, &bi[u], &bj[u]);
+      nt = u + 1;
+    }
+  }
+  const int64_t r_lo = static_cast<int64_t>(split) * per;
+  const int64_t r_hi = r_lo + per < L ? r_lo + per : L;
+  const int64_t nch = (r_hi - r_lo + GS_CH - 1) / GS_CH;
+  // chunk copy: VEC: MT * 8 float4 per padded row, NQ = MT / 2 rounded up per
+  // thread; else MT * 32 floats per row, 2 MT per thread
+  const int RW = VEC ? MT * 8 : MT * 32;
+  const int NQ = (GS_CH * RW + 511) / 512;
+  constexpr int NQM = VEC ? 6 : 8;  // (MT <= 12; scalar copies: MT <= 4)
+  using X = typename std::conditional<VEC, float4, float>::type;
+  X xr[NQM];
+  auto fetch = [&](int64_t ch, X (&xr)[NQM]) {
+    const int64_t c0 = r_lo + ch * GS_CH;
+    const int rows = static_cast<int>(r_hi - c0 < GS_CH ? r_hi - c0 : GS_CH);
+#pragma unroll
+    for (int q = 0; q < NQM; ++q) {
+      if (q < NQ) {
+        const int e = t + 512 * q;
+        const int r = e / RW, c = e - r * RW;
+        if constexpr (VEC)
+          xr[q] = (r < rows && 4 * c < m)
+                      ? *reinterpret_cast<const float4*>(W + (c0 + r) * ldw + 4 * c)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        else
+          xr[q] = (r < rows && c < m) ? W[(c0 + r) * ldw + c] : 0.f;
+      }
+    }
+  };
+  auto stage = [&](int64_t ch, const X (&xr)[NQM]) {
+    float* buf = Wsm + (ch & 1) * BUF;
+#pragma unroll
+    for (int q = 0; q < NQM; ++q) {
+      if (q < NQ) {
+        const int e = t + 512 * q;
+        const int r = e / RW, c = e - r * RW;
+        if (r < GS_CH) {
+          if constexpr (VEC)
+            *reinterpret_cast<float4*>(buf + r * LDW + 4 * c) = xr[q];
+          else
+            buf[r * LDW + c] = xr[q];
+        }
+      }
+    }
+  };
+  double acc[GS_TPW][16];
+#pragma unroll
+  for (int u = 0; u < GS_TPW; ++u)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[u][v] = 0.0;
+  const int rh = lane >> 5, cl = lane & 31;
+  // prologue: chunk 0 staged, chunk 1 in registers
+  fetch(0, xr);
+  stage(0, xr);
+  if (nch > 1) fetch(1, xr);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    // chunk ch + 1 (registers) into its buffer, then chunk ch + 2 requested
+    // into the same registers (that buffer was last read in step ch - 1,
+    // which ended with a barrier)
+    if (ch + 1 < nch) stage(ch + 1, xr);
+    if (ch + 2 < nch) fetch(ch + 2, xr);
+    const float* B = Wsm + (ch & 1) * BUF;
+#pragma unroll
+    for (int u = 0; u < GS_TPW; ++u) {
+      if (u < nt) {
+        f32x16 c32;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) c32[v] = 0.f;
+        const float* pa = B + rh * LDW + 32 * bi[u] + cl;
+        const float* pb = B + rh * LDW + 32 * bj[u] + cl;
+#pragma unroll
+        for (int st = 0; st < GS_CH / 2; ++st)
+          c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[2 * st * LDW], pb[2 * st * LDW], c32,
+                                                     0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[u][v] += static_cast<double>(c32[v]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < GS_TPW; ++u) {
+    if (u < nt) {
+      const int ti = g * GS_TPG + u * GS_WAVES + w;
+      double* o = part + (static_cast<int64_t>(split) * T + ti) * 1024;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) o[v * 64 + lane] = acc[u][v];
+    }
+  }
+}
+
+// M (m x m FP64, ld ldm, both triangles) = sum over the S splits, in split
+// order, of the upper tiles; a diagonal tile supplies its upper half.
+__global__ __launch_bounds__(256) void gram_sym_reduce_kernel(int m, int S,
+                                                              const double* __restrict__ part,
+                                                              double* __restrict__ M,
+                                                              int64_t ldm) {
+  const int MT = (m + 31) >> 5;
+  const int T = MT * (MT + 1) / 2;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= static_cast<int64_t>(T) * 1024) return;
+  const int ti = static_cast<int>(e >> 10), rest = static_cast<int>(e & 1023);
+  const int v = rest >> 6, lane = rest & 63;
+  int bi, bj;
+  gs_tile(ti, MT, &bi, &bj);
+  const int i = 32 * bi + out_row(lane, v), j = 32 * bj + (lane & 31);
+  if (i >= m || j >= m || (bi == bj && i > j)) return;
+  double sum = 0.0;
+#pragma unroll 8
+  for (int sp = 0; sp < S; ++sp) sum += part[(static_cast<int64_t>(sp) * T + ti) * 1024 + rest];
+  M[static_cast<int64_t>(i) * ldm + j] = sum;
+  M[static_cast<int64_t>(j) * ldm + i] = sum;
+}
+
 }  // namespace
 
 int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type) {
@@ -656,6 +821,60 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
       break;
   }
   *splits = S;
+}
+
+// Splits and tile groups of the symmetric Gram: up to 32 tiles per group,
+// enough splits for ~256 workgroups (one per CU), at least 128 rows per
+// split.
+static void gram_sym_plan(int64_t L, int m, int* S, int* G, int64_t* per) {
+  const int MT = static_cast<int>(cdiv(m, 32));
+  const int T = MT * (MT + 1) / 2;
+  *G = static_cast<int>(cdiv(T, GS_TPG));
+  int64_t s_ = cdiv(256, *G);
+  const int64_t smax = cdiv(L, 128);
+  if (s_ > smax) s_ = smax;
+  if (s_ < 1) s_ = 1;
+  *per = cdiv(cdiv(L, s_), GS_CH) * GS_CH;
+  *S = static_cast<int>(cdiv(L, *per));  // (no empty split)
+}
+
+int64_t gram_sym_partial_elems(int64_t L, int m) {
+  if (m <= 0 || m > kGramSymMaxM || L < kGramSymMinL) return 0;
+  int S, G;
+  int64_t per;
+  gram_sym_plan(L, m, &S, &G, &per);
+  const int64_t MT = cdiv(m, 32);
+  return static_cast<int64_t>(S) * (MT * (MT + 1) / 2) * 1024;
+}
+
+int launch_gram_sym_mfma(int64_t L, int m, const float* W, int64_t ldw, double* M, int64_t ldm,
+                         double* part, hipStream_t s) {
+  if (m <= 0 || m > kGramSymMaxM || L < kGramSymMinL) return 0;
+  int S, G;
+  int64_t per;
+  gram_sym_plan(L, m, &S, &G, &per);
+  const int MT = static_cast<int>(cdiv(m, 32));
+  const int T = MT * (MT + 1) / 2;
+  const size_t lds = static_cast<size_t>(2) * GS_CH * (MT * 32 + 4) * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gram_sym_mfma_kernel<true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(gram_sym_mfma_kernel<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr = true;
+  }
+  const unsigned grid = static_cast<unsigned>(cdiv(S, 8) * 8 * G);
+  const bool vec = m % 4 == 0 && ldw % 4 == 0 && reinterpret_cast<uintptr_t>(W) % 16 == 0;
+  if (!vec && m > 128) return 0;  // (scalar copies hold at most 4 tile columns)
+  if (vec)
+    gram_sym_mfma_kernel<true><<<grid, 512, lds, s>>>(L, m, W, ldw, S, G, per, part);
+  else
+    gram_sym_mfma_kernel<false><<<grid, 512, lds, s>>>(L, m, W, ldw, S, G, per, part);
+  const int64_t outs = static_cast<int64_t>(T) * 1024;
+  gram_sym_reduce_kernel<<<static_cast<unsigned>(cdiv(outs, 256)), 256, 0, s>>>(m, S, part, M,
+                                                                               ldm);
+  return 2;
 }
 
 }  // namespace bk

@@ -91,6 +91,16 @@ int tn_mfma_splits(int64_t L, int64_t p, int r);
 void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches);
 // *splits = number of FP64 partials written (0: not handled)
 void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits);
+// M (m x m FP64, ld ldm, both triangles) = W^T W for an FP32 W (L x m, ld
+// ldw; m <= kGramSymMaxM, L >= kGramSymMinL: shorter blocks are faster on
+// the vector path) on the matrix cores: FP32 sums of 32-row chunks added in
+// FP64; part: gram_sym_partial_elems(L, m) doubles.  Returns the kernels
+// launched (0: not applicable).
+constexpr int kGramSymMaxM = 384;
+constexpr int64_t kGramSymMinL = 32768;
+int64_t gram_sym_partial_elems(int64_t L, int m);
+int launch_gram_sym_mfma(int64_t L, int m, const float* W, int64_t ldw, double* M, int64_t ldm,
+                         double* part, hipStream_t s);
 
 // ---------------------------------------------------------------- small --
 // Fill / convert helpers.

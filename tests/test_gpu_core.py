@@ -266,6 +266,18 @@ def test_svd_csr_small(center, k, q, median):
     compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-5, 1e-4)
 
 
+# d >= 32768 puts M = W^T W on the matrix-core symmetric Gram: m = 18
+# (scalar row copies), 40 (16-byte copies), 384 (the widest, 78 tiles in
+# three groups); the row splits end in a ragged chunk.
+@pytest.mark.parametrize("k,q", [(3, 5), (8, 4), (32, 11)])
+def test_svd_csr_long_block(k, q):
+    (rp, ci, va), M = _termdoc(1200, 40000, 9, median=30.0)
+    ref = bki.block_krylov(M, _pi32(81, 40000, k), k, q, center=True, tau=1e-5)
+    res = bk.svd_csr(_cuda(rp), _cuda(ci), _cuda(va), 1200, 40000, k, q, seed=81,
+                     center=True)
+    compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-5, 1e-4)
+
+
 def test_svd_csr_config2_full_size():
     """The term-document workload at full size (11000 x 130000, ~1.5M
     nonzeros, k = 20, q = 10, row centring), in the launch configuration the
