@@ -122,6 +122,129 @@ __global__ __launch_bounds__(256) void nn_kernel(
   }
 }
 
+// NN for a short reduction (K <= NS_KMAX) and N <= 32 with FP32 A, FP64 X
+// and FP32 C (the applies of the orthonormalization): a workgroup's whole
+// 64 x K block of A and X (as FP32) are requested at once (clamped, in
+// bounds addresses; one round of memory latency instead of one per
+// 32-wide chunk), staged in LDS, then multiplied; the epilogue is
+// nn_kernel's (alpha, beta, optional Gram partial of the stored rows).
+constexpr int NS_KMAX = 256;
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void nn_smallk_kernel(
+    int64_t n, int K, int N, const float* __restrict__ A, int64_t lda,
+    const double* __restrict__ X, int64_t ldx, float* __restrict__ C, int64_t ldc,
+    float alpha, float beta, double* __restrict__ gpart) {
+  __shared__ float As[NS_KMAX][NN_BM + 1];
+  __shared__ float Xs[NS_KMAX][NN_BN];
+  const int t = threadIdx.x;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * NN_BM;
+  const int64_t rlast = n - 1;
+  {
+    // A: VEC: 64 x K / 4 float4 (at most 16 per thread); else 64 x K
+    // floats (at most 64 per thread)
+    constexpr int QA = VEC ? 16 : 64;
+    const int RW = VEC ? K / 4 : K;
+    const int na = NN_BM * RW;
+    using VA = typename std::conditional<VEC, float4, float>::type;
+    VA av[QA];
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = min(t + 256 * q, na - 1);
+      const int r = e / RW, c = e - r * RW;
+      const int64_t gr = min(row0 + r, rlast);
+      if constexpr (VEC)
+        av[q] = *reinterpret_cast<const float4*>(A + gr * lda + 4 * c);
+      else
+        av[q] = A[gr * lda + c];
+    }
+    // X: K x 32 (columns past N are zero), at most 32 per thread
+    double xv[32];
+    const int nx = K * NN_BN;
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int e = min(t + 256 * q, nx - 1);
+      const int kk = e >> 5, c = e & 31;
+      xv[q] = X[static_cast<int64_t>(kk) * ldx + min(c, N - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      const int e = t + 256 * q;
+      if (e < na) {
+        const int r = e / RW, c = e - r * RW;
+        const bool ok = row0 + r < n;
+        if constexpr (VEC) {
+          As[4 * c + 0][r] = ok ? av[q].x : 0.f;
+          As[4 * c + 1][r] = ok ? av[q].y : 0.f;
+          As[4 * c + 2][r] = ok ? av[q].z : 0.f;
+          As[4 * c + 3][r] = ok ? av[q].w : 0.f;
+        } else {
+          As[c][r] = ok ? av[q] : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int e = t + 256 * q;
+      if (e < nx) Xs[e >> 5][e & 31] = (e & 31) < N ? static_cast<float>(xv[q]) : 0.f;
+    }
+  }
+  __syncthreads();
+  const int tx = t & 7, ty = t >> 3;
+  float acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+#pragma unroll 8
+  for (int kk = 0; kk < K; ++kk) {
+    const float a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float xv = Xs[kk][tx * 4 + j];
+      acc[0][j] += a0 * xv;
+      acc[1][j] += a1 * xv;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int64_t gr = row0 + ty * 2 + i;
+    if (gr >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int gc = tx * 4 + j;
+      if (gc >= N) continue;
+      float v = alpha * acc[i][j];
+      if (beta != 0.f) v += beta * C[gr * ldc + gc];
+      C[gr * ldc + gc] = v;
+      acc[i][j] = v;
+    }
+  }
+  if (gpart) {
+    float* T = &As[0][0];  // NN_BM x NN_BN tile of the stored rows
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const bool rok = row0 + ty * 2 + i < n;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = tx * 4 + j;
+        T[(ty * 2 + i) * NN_BN + c] = (rok && c < N) ? acc[i][j] : 0.f;
+      }
+    }
+    __syncthreads();
+    double* g = gpart + static_cast<int64_t>(blockIdx.x) * N * N;
+    for (int e = t; e < N * N; e += 256) {
+      const int a = e / N, b = e - a * N;
+      double sum = 0.0;
+#pragma unroll 8
+      for (int r = 0; r < NN_BM; ++r)
+        sum += static_cast<double>(T[r * NN_BN + a]) * static_cast<double>(T[r * NN_BN + b]);
+      g[e] = sum;
+    }
+  }
+}
+
 constexpr int TN_BP = 64, TN_BR = 32, TN_BL = 32;
 
 // Partial sums over the rows [s*Ls, (s+1)*Ls) of split s = blockIdx.z:
@@ -340,6 +463,24 @@ int launch_nn(const NNArgs& a, hipStream_t s) {
   int mfma = 0;
   if (!a.gram_partial) launch_nn_mfma_if(a, s, &mfma);
   if (mfma) return mfma;
+  if (a.a_type == BK_F32 && !a.ascale && a.x_f64 && !a.c_f64 && a.N <= NN_BN && a.K > 0 &&
+      a.K <= NS_KMAX) {
+    const bool vec = a.K % 4 == 0 && a.lda % 4 == 0 &&
+                     reinterpret_cast<uintptr_t>(a.A) % 16 == 0;
+    const unsigned g = static_cast<unsigned>(cdiv(a.n, NN_BM));
+    const int K = static_cast<int>(a.K);
+    const float* A = static_cast<const float*>(a.A);
+    const double* X = static_cast<const double*>(a.X);
+    float* C = static_cast<float*>(a.C);
+    const float al = static_cast<float>(a.alpha), be = static_cast<float>(a.beta);
+    if (vec)
+      nn_smallk_kernel<true><<<g, 256, 0, s>>>(a.n, K, a.N, A, a.lda, X, a.ldx, C, a.ldc, al,
+                                               be, a.gram_partial);
+    else
+      nn_smallk_kernel<false><<<g, 256, 0, s>>>(a.n, K, a.N, A, a.lda, X, a.ldx, C, a.ldc, al,
+                                                be, a.gram_partial);
+    return 1;
+  }
   switch (a.a_type) {
     case BK_F64:
       nn_dispatch_scaled<double, double, double, double>(a, s);
