@@ -419,8 +419,9 @@ __device__ void tri_factor(const double* __restrict__ dg, const double* __restri
     const double DUn = (i + 2 < m) ? eo[i + 1] : 0.0;  // DU[i+1] before
     if (fabs(Dc) >= fabs(sub)) {
       if (Dc == 0.0) Dc = tiny;
-      const double f = sub / Dc;
-      rD[i] = 1.0 / Dc;
+      const double r = recip_f64(Dc);
+      const double f = sub * r;
+      rD[i] = r;
       DU[i] = DUc;
       DU2[i] = 0.0;
       DL[i] = f;
@@ -428,8 +429,9 @@ __device__ void tri_factor(const double* __restrict__ dg, const double* __restri
       Dc = Dn - f * DUc;
       DUc = DUn;
     } else {
-      const double f = Dc / sub;
-      rD[i] = 1.0 / sub;
+      const double r = recip_f64(sub);
+      const double f = Dc * r;
+      rD[i] = r;
       DU[i] = Dn;
       DU2[i] = DUn;
       DL[i] = f;
@@ -439,7 +441,7 @@ __device__ void tri_factor(const double* __restrict__ dg, const double* __restri
     }
   }
   if (Dc == 0.0) Dc = tiny;
-  rD[m - 1] = 1.0 / Dc;
+  rD[m - 1] = recip_f64(Dc);
 }
 
 // Solve with the factors of tri_factor, b -> x in place.
@@ -478,124 +480,178 @@ __device__ void tri_solve(int64_t m, const double* __restrict__ rD,
   }
 }
 
-// k largest eigenvalues (descending) and the eigenvectors of T (X, m x k,
-// column-major: column c at X + c m).  scratch: k * 5 m doubles + k * m ints.
-__global__ __launch_bounds__(TRI_THREADS) void tridiag_topk_kernel(
-    const double* __restrict__ dgg, const double* __restrict__ eog, int64_t m, int k,
-    double* __restrict__ theta, double* __restrict__ X, double* __restrict__ scratch,
-    int* __restrict__ iscratch) {
-  extern __shared__ double sm[];  // dg (m), eo (m), e2 (m), lo (k), hi (k), best (k ints)
-  __shared__ int s_done;
-  __shared__ double s_tnorm;
-  double* dg = sm;
-  double* eo = sm + m;
-  double* e2 = sm + 2 * m;
-  double* lo = sm + 3 * m;
-  double* hi = lo + k;
-  int* best = reinterpret_cast<int*>(hi + k);
+// Gershgorin bounds of T (diagonal dgg, off-diagonal eog, m) and its
+// infinity norm, by one workgroup of `nt` threads (order-free min / max).
+__device__ void tri_gershgorin(const double* __restrict__ dgg, const double* __restrict__ eog,
+                               int64_t m, int nt, double* red, double* gl, double* gu,
+                               double* tn) {
   const int t = threadIdx.x;
-  for (int64_t i = t; i < m; i += TRI_THREADS) {
+  double l = INFINITY, u = -INFINITY, n = 0.0;
+  for (int64_t i = t; i < m; i += nt) {
+    const double r = (i > 0 ? fabs(eog[i - 1]) : 0.0) + (i + 1 < m ? fabs(eog[i]) : 0.0);
+    l = fmin(l, dgg[i] - r);
+    u = fmax(u, dgg[i] + r);
+    n = fmax(n, fabs(dgg[i]) + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_xor(l, o));
+    u = fmax(u, __shfl_xor(u, o));
+    n = fmax(n, __shfl_xor(n, o));
+  }
+  const int nw = nt >> 6, w = t >> 6;
+  if ((t & 63) == 0) {
+    red[w] = l;
+    red[nw + w] = u;
+    red[2 * nw + w] = n;
+  }
+  __syncthreads();
+  l = red[0];
+  u = red[nw];
+  n = red[2 * nw];
+  for (int q = 1; q < nw; ++q) {
+    l = fmin(l, red[q]);
+    u = fmax(u, red[nw + q]);
+    n = fmax(n, red[2 * nw + q]);
+  }
+  *gl = l;
+  *gu = u;
+  *tn = n;
+}
+
+// The c-th largest eigenvalue of T (c = blockIdx.x) by multisection: the
+// BS_THREADS threads evaluate the Sturm count at P = BS_THREADS interior
+// points x_0 < ... < x_{P-1} of the bracket [lo, hi] (count(lo) <= target <
+// count(hi), target = m - 1 - c its ascending index); the new bracket is
+// [x_b, x_{b+1}] for b the last point with count <= target (lo for b = -1,
+// hi for b = P-1), P + 1 fold smaller.  One workgroup per eigenvalue: no
+// synchronization between them.
+constexpr int BS_THREADS = 256;
+
+__global__ __launch_bounds__(BS_THREADS) void tridiag_bisect_kernel(
+    const double* __restrict__ dgg, const double* __restrict__ eog, int64_t m, int k,
+    double* __restrict__ theta) {
+  extern __shared__ double sm[];  // dg (m), e2 (m)
+  __shared__ double red[3 * BS_THREADS / 64];
+  __shared__ double s_lo, s_hi;
+  __shared__ int s_best;
+  double* dg = sm;
+  double* e2 = sm + m;
+  const int t = threadIdx.x, c = blockIdx.x;
+  for (int64_t i = t; i < m; i += BS_THREADS) {
     dg[i] = dgg[i];
-    eo[i] = (i + 1 < m) ? eog[i] : 0.0;
-    e2[i] = eo[i] * eo[i];
+    const double e = (i + 1 < m) ? eog[i] : 0.0;
+    e2[i] = e * e;
   }
-  __syncthreads();
-  if (t == 0) {
-    double gl = INFINITY, gu = -INFINITY, tn = 0.0;
-    for (int64_t i = 0; i < m; ++i) {
-      const double r = (i > 0 ? fabs(eo[i - 1]) : 0.0) + (i + 1 < m ? fabs(eo[i]) : 0.0);
-      gl = fmin(gl, dg[i] - r);
-      gu = fmax(gu, dg[i] + r);
-      tn = fmax(tn, fabs(dg[i]) + r);
-    }
-    const double pad = 2.2e-16 * tn * 4.0 + 1e-300;
-    s_tnorm = tn;
-    for (int c = 0; c < k; ++c) {
-      lo[c] = gl - pad;
-      hi[c] = gu + pad;
-    }
-  }
-  __syncthreads();
-  const double tnorm = s_tnorm;
+  double gl, gu, tnorm;
+  tri_gershgorin(dgg, eog, m, BS_THREADS, red, &gl, &gu, &tnorm);
+  const double pad = 2.2e-16 * tnorm * 4.0 + 1e-300;
   const double pivmin = 1e-290 + 2.2e-16 * 2.2e-16 * tnorm * tnorm * 1e-10;
-  // Multisection: P threads per eigenvalue evaluate the count at P interior
-  // points x_0 < ... < x_{P-1} of the bracket [lo, hi] of the c-th largest
-  // (count(lo) <= target < count(hi), target its ascending index); the new
-  // bracket is [x_b, x_{b+1}] for b the last point with count <= target
-  // (lo for b = -1, hi for b = P-1), P+1 fold smaller.
-  const int P = k >= TRI_THREADS ? 1 : TRI_THREADS / k;
+  const int P = BS_THREADS;
   auto settled = [&](double l, double h) {
     return h - l <= 2.2e-16 * fmax(fabs(l), fabs(h)) * 2.0 + 1e-18 * tnorm + 1e-300;
   };
   auto point = [&](double l, double h, int pp) {
     return l + (h - l) * static_cast<double>(pp + 1) / static_cast<double>(P + 1);
   };
-  for (int it = 0; it < 200; ++it) {
-    if (t == 0) s_done = 1;
-    for (int c = t; c < k; c += TRI_THREADS) best[c] = -1;
-    __syncthreads();
-    for (int idx = t; idx < k * P; idx += TRI_THREADS) {
-      const int c = idx / P, pp = idx - c * P;
-      const double l = lo[c], h = hi[c];
-      if (settled(l, h)) continue;
-      const int target = static_cast<int>(m) - 1 - c;
-      if (sturm_count(dg, e2, m, point(l, h, pp), pivmin) <= target) atomicMax(&best[c], pp);
-    }
-    __syncthreads();
-    for (int c = t; c < k; c += TRI_THREADS) {
-      const double l = lo[c], h = hi[c];
-      if (settled(l, h)) continue;
-      const int b = best[c];
-      const double nl = b >= 0 ? point(l, h, b) : l;
-      const double nh = b + 1 < P ? point(l, h, b + 1) : h;
-      lo[c] = nl;
-      hi[c] = nh;
-      if (!settled(nl, nh)) s_done = 0;
-    }
-    __syncthreads();
-    if (s_done) break;
+  if (t == 0) {
+    s_lo = gl - pad;
+    s_hi = gu + pad;
+    s_best = -1;
   }
-  for (int c = t; c < k; c += TRI_THREADS) theta[c] = 0.5 * (lo[c] + hi[c]);
   __syncthreads();
-  // Inverse iteration; eigenvalues closer than ctol form a cluster handled
-  // by one thread in order (modified Gram-Schmidt against earlier members).
+  const int target = static_cast<int>(m) - 1 - c;
+  for (int it = 0; it < 200; ++it) {
+    const double l = s_lo, h = s_hi;
+    if (settled(l, h)) break;  // (uniform)
+    if (sturm_count(dg, e2, m, point(l, h, t), pivmin) <= target) atomicMax(&s_best, t);
+    __syncthreads();
+    if (t == 0) {
+      const int b = s_best;
+      s_lo = b >= 0 ? point(l, h, b) : l;
+      s_hi = b + 1 < P ? point(l, h, b + 1) : h;
+      s_best = -1;
+    }
+    __syncthreads();
+  }
+  if (t == 0) theta[c] = 0.5 * (s_lo + s_hi);
+}
+
+// Inverse iteration for the eigenvalues theta (descending) of T, into X
+// (m x k, column-major: column c at X + c m).  Eigenvalues closer than ctol
+// form a cluster handled by one workgroup (the one of its first member) in
+// order, modified Gram-Schmidt against the earlier members.  A workgroup is
+// one wavefront: lane 0 runs the factorization and the two triangular
+// sweeps, the wavefront the start vector, dot products and scalings.
+// use_lds: the factors and the working vector in LDS, else in scratch
+// (5 m doubles per eigenvalue) and iscratch (m ints).
+__global__ __launch_bounds__(64) void tridiag_invit_kernel(
+    const double* __restrict__ dgg, const double* __restrict__ eog, int64_t m, int k,
+    const double* __restrict__ theta, double* __restrict__ X, double* __restrict__ scratch,
+    int* __restrict__ iscratch, int use_lds) {
+  extern __shared__ double sm[];  // dg (m), eo (m) [, rD DU DU2 DL x (5 m), piv (m ints)]
+  __shared__ double red[3];
+  const int t = threadIdx.x, c = blockIdx.x;
+  double* dg = sm;
+  double* eo = sm + m;
+  for (int64_t i = t; i < m; i += 64) {
+    dg[i] = dgg[i];
+    eo[i] = (i + 1 < m) ? eog[i] : 0.0;
+  }
+  double gl, gu, tnorm;
+  tri_gershgorin(dgg, eog, m, 64, red, &gl, &gu, &tnorm);
   const double ctol = 1e-10 * tnorm + 1e-300;
   const double tiny = 2.2e-16 * tnorm + 1e-300;
-  for (int c = t; c < k; c += TRI_THREADS) {
-    const bool starts = (c == 0) || (theta[c - 1] - theta[c] > ctol);
-    if (!starts) continue;
-    int ce = c + 1;
-    while (ce < k && theta[ce - 1] - theta[ce] <= ctol) ++ce;
-    double* rD = scratch + static_cast<int64_t>(c) * 5 * m;
-    double* DU = rD + m;
-    double* DU2 = DU + m;
-    double* DL = DU2 + m;
-    int* piv = iscratch + static_cast<int64_t>(c) * m;
-    for (int cc = c; cc < ce; ++cc) {
-      double* x = X + static_cast<int64_t>(cc) * m;
-      // start vector: deterministic, not orthogonal to any eigenvector in general
-      for (int64_t i = 0; i < m; ++i) {
-        const uint32_t h = static_cast<uint32_t>(i) * 2654435761u + static_cast<uint32_t>(cc) * 40503u;
-        x[i] = 0.5 + static_cast<double>(h >> 8) * (1.0 / 16777216.0);
-      }
-      const double lam = theta[cc] + (cc - c) * 2.0 * tiny;  // split exact ties
-      tri_factor(dg, eo, m, lam, tiny, rD, DU, DU2, DL, piv);
-      // two solves: with lam accurate to a few ulps the first already damps
-      // every other eigenvector by ~ eps |lam| / gap, the second is margin
-      for (int iter = 0; iter < 2; ++iter) {
-        tri_solve(m, rD, DU, DU2, DL, piv, x);
-        for (int pj = c; pj < cc; ++pj) {
-          const double* y = X + static_cast<int64_t>(pj) * m;
-          double dot = 0.0;
-          for (int64_t i = 0; i < m; ++i) dot += y[i] * x[i];
-          for (int64_t i = 0; i < m; ++i) x[i] -= dot * y[i];
-        }
-        double nn = 0.0;
-        for (int64_t i = 0; i < m; ++i) nn += x[i] * x[i];
-        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-        for (int64_t i = 0; i < m; ++i) x[i] *= inv;
-      }
+  if (c > 0 && theta[c - 1] - theta[c] <= ctol) return;  // (uniform) not a first member
+  int ce = c + 1;
+  while (ce < k && theta[ce - 1] - theta[ce] <= ctol) ++ce;
+  double* rD;
+  double* xw = nullptr;
+  int* piv;
+  if (use_lds) {
+    rD = sm + 2 * m;
+    xw = rD + 4 * m;
+    piv = reinterpret_cast<int*>(rD + 5 * m);
+  } else {
+    rD = scratch + static_cast<int64_t>(c) * 5 * m;
+    piv = iscratch + static_cast<int64_t>(c) * m;
+  }
+  double* DU = rD + m;
+  double* DU2 = DU + m;
+  double* DL = DU2 + m;
+  for (int cc = c; cc < ce; ++cc) {
+    double* xg = X + static_cast<int64_t>(cc) * m;
+    double* x = use_lds ? xw : xg;
+    // start vector: deterministic, not orthogonal to any eigenvector in general
+    for (int64_t i = t; i < m; i += 64) {
+      const uint32_t h = static_cast<uint32_t>(i) * 2654435761u + static_cast<uint32_t>(cc) * 40503u;
+      x[i] = 0.5 + static_cast<double>(h >> 8) * (1.0 / 16777216.0);
     }
+    const double lam = theta[cc] + (cc - c) * 2.0 * tiny;  // split exact ties
+    if (t == 0) tri_factor(dg, eo, m, lam, tiny, rD, DU, DU2, DL, piv);
+    __syncthreads();
+    // two solves: with lam accurate to a few ulps the first already damps
+    // every other eigenvector by ~ eps |lam| / gap, the second is margin
+    for (int iter = 0; iter < 2; ++iter) {
+      if (t == 0) tri_solve(m, rD, DU, DU2, DL, piv, x);
+      __syncthreads();
+      for (int pj = c; pj < cc; ++pj) {
+        const double* y = X + static_cast<int64_t>(pj) * m;  // (written by this workgroup)
+        double dot = 0.0;
+        for (int64_t i = t; i < m; i += 64) dot += y[i] * x[i];
+        dot = wave_sum(dot);
+        for (int64_t i = t; i < m; i += 64) x[i] -= dot * y[i];
+        __syncthreads();
+      }
+      double nn = 0.0;
+      for (int64_t i = t; i < m; i += 64) nn += x[i] * x[i];
+      nn = wave_sum(nn);
+      const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int64_t i = t; i < m; i += 64) x[i] *= inv;
+      __syncthreads();
+    }
+    if (use_lds)
+      for (int64_t i = t; i < m; i += 64) xg[i] = x[i];
+    __syncthreads();
   }
 }
 
@@ -821,7 +877,8 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   static bool attr = false;
   if (!attr) {
     for (const void* f : {reinterpret_cast<const void*>(tridiag_reduce_kernel),
-                          reinterpret_cast<const void*>(tridiag_topk_kernel),
+                          reinterpret_cast<const void*>(tridiag_bisect_kernel),
+                          reinterpret_cast<const void*>(tridiag_invit_kernel),
                           reinterpret_cast<const void*>(tri_panel_kernel)})
       (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, TRI_LDS_BYTES);
     attr = true;
@@ -863,8 +920,14 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, m - 2, v, vp, wp, part,
                                                                   G, Vh, beta, dg, eo);
   }
-  tridiag_topk_kernel<<<1, TRI_THREADS, (3 * m + 3 * k) * sizeof(double), s>>>(dg, eo, m, k,
-                                                                             theta, X, sol, piv);
+  // eigenvalues: a workgroup each; eigenvectors: a workgroup per cluster,
+  // its factors in LDS when they fit beside the tridiagonal
+  tridiag_bisect_kernel<<<static_cast<unsigned>(k), BS_THREADS, 2 * m * sizeof(double), s>>>(
+      dg, eo, m, k, theta);
+  const size_t inv_lds = (7 * m + (m + 1) / 2) * sizeof(double);
+  const int use_lds = inv_lds <= static_cast<size_t>(TRI_LDS_BYTES) ? 1 : 0;
+  tridiag_invit_kernel<<<static_cast<unsigned>(k), 64, use_lds ? inv_lds : 2 * m * sizeof(double),
+                         s>>>(dg, eo, m, k, theta, X, sol, piv, use_lds);
   const unsigned gb = static_cast<unsigned>(cdiv(k, 4));
   if (m <= 256)
     tridiag_back_kernel<4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
