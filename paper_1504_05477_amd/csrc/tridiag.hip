@@ -671,38 +671,43 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
   const int lane = threadIdx.x & 63;
   if (ritz && lane == 0) ritz[c] = sqrt(fmax(theta[c], 0.0));
   const double* x = X + static_cast<int64_t>(c) * m;
-  // column in registers (row lane + 64 u); next reflector prefetched
-  double xr[VR], vc[VR], vn[VR];
+  // column in registers (row lane + 64 u); the next AH reflectors in flight
+  // (a ring of register sets, rotated by the unrolled loop)
+  constexpr int AH = VR <= 8 ? 4 : (VR <= 16 ? 2 : 1);
+  double xr[VR], vq[AH][VR], bq[AH];
 #pragma unroll
   for (int u = 0; u < VR; ++u) {
     const int64_t i = lane + 64 * u;
     xr[u] = i < m ? x[i] : 0.0;
   }
-  int64_t j = m - 3;
+  auto fetch = [&](int64_t jj, double (&vv)[VR], double& bb) {
+    bb = jj >= 0 ? beta[jj] : 0.0;
 #pragma unroll
-  for (int u = 0; u < VR; ++u) {
-    const int64_t i = lane + 64 * u;
-    vn[u] = (j >= 0 && i > j && i < m) ? Vh[j * m + i] : 0.0;
-  }
-  for (; j >= 0; --j) {
-#pragma unroll
-    for (int u = 0; u < VR; ++u) vc[u] = vn[u];
-    const double b = beta[j];
-    if (j > 0) {
-#pragma unroll
-      for (int u = 0; u < VR; ++u) {
-        const int64_t i = lane + 64 * u;
-        vn[u] = (i > j - 1 && i < m) ? Vh[(j - 1) * m + i] : 0.0;
-      }
+    for (int u = 0; u < VR; ++u) {
+      const int64_t i = lane + 64 * u;
+      vv[u] = (jj >= 0 && i > jj && i < m) ? Vh[jj * m + i] : 0.0;
     }
-    if (b == 0.0) continue;
+  };
+  auto apply = [&](const double (&vv)[VR], double bb) {
+    if (bb == 0.0) return;
     double dot = 0.0;
 #pragma unroll
-    for (int u = 0; u < VR; ++u) dot += vc[u] * xr[u];
+    for (int u = 0; u < VR; ++u) dot += vv[u] * xr[u];
     dot = wave_sum(dot);
-    const double f = b * dot;
+    const double f = bb * dot;
 #pragma unroll
-    for (int u = 0; u < VR; ++u) xr[u] -= f * vc[u];
+    for (int u = 0; u < VR; ++u) xr[u] -= f * vv[u];
+  };
+  // reflectors j = m - 3 down to 0; slot q holds j = m - 3 - (step mod AH)
+#pragma unroll
+  for (int q = 0; q < AH; ++q) fetch(m - 3 - q, vq[q], bq[q]);
+  for (int64_t j0 = m - 3; j0 >= 0; j0 -= AH) {
+#pragma unroll
+    for (int q = 0; q < AH; ++q) {
+      const int64_t j = j0 - q;
+      if (j >= 0) apply(vq[q], bq[q]);
+      fetch(j - AH, vq[q], bq[q]);
+    }
   }
 #pragma unroll
   for (int u = 0; u < VR; ++u) {
