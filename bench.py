@@ -204,17 +204,19 @@ def main():
     torch.cuda.synchronize()
     log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s ({args.workload})")
 
-    # The timed steps record events only around the product phases (for the
-    # roofline kernel); every phase boundary with events costs idle time.
+    # The last n_ev timed steps record events around the product phases (the
+    # roofline kernel's launch durations); an event between two kernels
+    # stalls the queue (~4 us), so the other timed steps run without them.
     # The per-phase breakdown comes from extra steps after the timed region.
     timed_phases = ("ax", "aty")
+    n_ev = min(2, args.steps)
     for _ in range(args.warmup):
-        step(timed_phases)
+        step(False)
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = step(timed_phases)
+    for i in range(args.steps):
+        r = step(timed_phases if i >= args.steps - n_ev else False)
         infos.append(r.info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -226,11 +228,11 @@ def main():
     torch.cuda.synchronize()
 
     def tot(key, what="ms"):
-        return sum(float(i[what][key]) for i in infos)
+        return sum(float(i[what][key]) for i in infos[-n_ev:])
     ph = {p: sum(float(i["ms"][p]) for i in full) / nbd for p in full[0]["ms"]}
     if args.breakdown:
         log("phase ms/step: " + ", ".join(f"{p}={v:.3f}" for p, v in ph.items()))
-        log(f"launches/step: {infos[0]['launches']}")
+        log(f"launches/step: {full[0]['launches']}")
     dom = "ax" if tot("ax") >= tot("aty") else "aty"
     if w.kind == "csr":
         # one product kernel per launch in these phases (the combine and
@@ -239,7 +241,7 @@ def main():
     else:
         # a dense product is a short sequence of kernels (operand packing,
         # the MFMA or vector product, the split reduction): rate per product
-        nl = args.steps * (infos[-1]["q_eff"] + 1)
+        nl = n_ev * (infos[-1]["q_eff"] + 1)
     avg_ms = tot(dom) / max(nl, 1)
     per_launch = bx if dom == "ax" else by
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
@@ -249,7 +251,7 @@ def main():
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "kernel": kern_names[dom],
-            "avg_launch_ms": round(avg_ms, 5),
+            "avg_launch_ms": round(avg_ms, 5), "event_steps": n_ev,
             "algorithmic_bytes_per_launch": int(per_launch), "source_sha": sha}
     if w.kind == "dense" and args.precision == "plain":
         flops = 2.0 * w.n * w.d * k
