@@ -513,9 +513,12 @@ struct Solver {
     tm->begin(BK_PH_CHOLQR);
     const double shift_coef = 11.0 * (static_cast<double>(n) * k + static_cast<double>(k) * (k + 1)) * kUnit64;
     const bool fuse = fuse_gram() && k <= kCqrPassMaxK;
-    // B -> Bs2 -> Bs -> slab (B may be the slab)
-    void* bufs[4] = {B, L->Bs2, L->Bs, qslab(slab)};
-    const int64_t lds[4] = {ldb, k, k, m};
+    // B -> Bs2 -> Bs -> slab (B may be the slab); fused: B -> Bs2 -> slab,
+    // and the third pass in place, skipped on the device when the second
+    // already left the block orthonormal to working precision
+    void* bufs[4] = {B, L->Bs2, fuse ? qslab(slab) : L->Bs, qslab(slab)};
+    const int64_t lds[4] = {ldb, k, fuse ? m : k, m};
+    const double unit = f64 ? 0x1p-53 : 0x1p-24;
     int nl = 0;
     // k <= 32: each pass is one launch that adds the previous pass's Gram
     // partials, factors, solves the rows against R (no R^-1) and leaves the
@@ -547,6 +550,7 @@ struct Solver {
         a.ldy = lds[pass + 1];
         a.f64 = f64;
         a.gout = pass < 2 ? part[pass & 1] : nullptr;
+        a.skip_tol = pass == 2 ? 64.0 * unit : 0.0;
         nl += launch_cqr_pass(a, s);
         gin = part[pass & 1];
         P = cqr_pass_grid(n, nullptr);

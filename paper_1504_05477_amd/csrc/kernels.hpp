@@ -154,6 +154,9 @@ struct CqrPass {
   bool f64 = false;
   int64_t rows_per_wg = 0;  // set by the launcher
   double* gout = nullptr;
+  // > 0: when max |G - I| <= skip_tol the pass leaves X as it is (R = I);
+  // then X must be Y (in place)
+  double skip_tol = 0.0;
 };
 int cqr_pass_grid(int64_t n, int64_t* rows_per_wg);
 int64_t cqr_pass_partial_elems(int k);

@@ -895,7 +895,8 @@ template <typename T, int K, bool VEC>
 __global__ __launch_bounds__(256) void cqr_pass_kernel(
     int64_t n, int k, const double* __restrict__ Gin, int P, const double* __restrict__ Gpre,
     int mode, int block, double tau, double shift_coef, double* __restrict__ R, Ctrl* ctrl,
-    const T* X, int64_t ldx, T* Y, int64_t ldy, int64_t rows_per_wg, double* __restrict__ gout) {
+    const T* X, int64_t ldx, T* Y, int64_t ldy, int64_t rows_per_wg, double* __restrict__ gout,
+    double skip_tol) {
   constexpr int LD = K + 1;
   constexpr int TPR = (K == 24) ? 32 : K;  // threads per row in the tile copies
   constexpr int RPI = 256 / TPR;           // rows per copy step
@@ -963,7 +964,7 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
   };
   // the first chunk's rows are requested before the Gram sum and the factor
   fetch(lo, static_cast<int>(hi - lo < CQR_ROWS ? hi - lo : CQR_ROWS));
-  if (t < K) pd[t] = (mode == CHOL_FIRST && t < k) ? Gpre[t * k + t] : 0.0;
+  const double gpre_d = (mode == CHOL_FIRST && t < k) ? Gpre[t * k + t] : 0.0;
   // G = sum of the partials in index order, PB independent loads in flight
   {
     double sum[NE];
@@ -992,6 +993,27 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
       }
     }
   }
+  __syncthreads();
+  if (skip_tol > 0.0) {
+    // X already orthonormal to working precision (max |G - I| <= skip_tol,
+    // the same decision in every workgroup): R = I, Y = X (in place)
+    double dev = 0.0;
+    for (int e = t; e < kk; e += 256) {
+      const int r = e / k, cc = e - r * k;
+      dev = fmax(dev, fabs(Gs[r * K + cc] - (r == cc ? 1.0 : 0.0)));
+    }
+    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o));
+    if ((t & 63) == 0) pd[t >> 6] = dev;  // (pd is rewritten after the next barrier)
+    __syncthreads();
+    dev = fmax(fmax(pd[0], pd[1]), fmax(pd[2], pd[3]));
+    if (!(dev > skip_tol)) {
+      if (blockIdx.x == 0)
+        for (int e = t; e < kk; e += 256) R[e] = (e / k == e % k) ? 1.0 : 0.0;
+      return;
+    }
+    __syncthreads();
+  }
+  if (t < K) pd[t] = gpre_d;
   __syncthreads();
   if (t < 64) {
     const int c = t;
@@ -1129,11 +1151,13 @@ void cqr_pass_launch(unsigned grid, const CqrPass& a, hipStream_t s) {
   if (vec)
     cqr_pass_kernel<T, K, true><<<grid, 256, 0, s>>>(
         a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
-        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
+        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout,
+        a.skip_tol);
   else
     cqr_pass_kernel<T, K, false><<<grid, 256, 0, s>>>(
         a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
-        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout);
+        static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout,
+        a.skip_tol);
 }
 }  // namespace
 
