@@ -144,6 +144,7 @@ struct Layout {
   void* Bs = nullptr;
   void* Bs2 = nullptr;
   double* partial = nullptr;
+  int64_t partial_elems = 0;
   void* pack = nullptr;  // matrix-core operand packing of the dense products
   size_t pack_bytes = 0;
   double *G = nullptr, *Gpre = nullptr, *R = nullptr, *Rinv = nullptr,
@@ -185,7 +186,8 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   L.W = ar.take<char>(static_cast<size_t>(d * m) * es);
   L.Bs = ar.take<char>(static_cast<size_t>(n * k) * es);
   L.Bs2 = ar.take<char>(static_cast<size_t>(n * k) * es);
-  L.partial = ar.take<double>(static_cast<size_t>(partial_need(n, d, k, q, o.refine != 0, csr)));
+  L.partial_elems = partial_need(n, d, k, q, o.refine != 0, csr);
+  L.partial = ar.take<double>(static_cast<size_t>(L.partial_elems));
   if (!csr && !f64) {
     // X^T of A X in FP32 (the widest type), Y^T of A^T Y in BF16 / FP8
     int64_t nn = 0;  // A X on the matrix cores: packed X^T (+ split partials)
@@ -316,6 +318,7 @@ struct Op {
   int64_t n = 0, d = 0;
   bool f64 = false;
   double* partial = nullptr;
+  int64_t partial_elems = 0;  // (free during ax: split-K scratch)
   Timer* tm = nullptr;
   virtual ~Op() = default;
   // Y (n x k, ldy) = A X, X d x k (ldx)
@@ -356,6 +359,8 @@ struct DenseOp : Op {
     a.c_f64 = f64;
     a.work = pack;
     a.work_bytes = pack_bytes;
+    a.split_work = partial;
+    a.split_work_elems = partial_elems;
     tm->end(launch_nn(a, s));
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
@@ -663,6 +668,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
   tm.s = s;
   op.tm = &tm;
   op.partial = L.partial;
+  op.partial_elems = L.partial_elems;
   if (DenseOp* dop = dynamic_cast<DenseOp*>(&op)) {
     dop->pack = L.pack;
     dop->pack_bytes = L.pack_bytes;

@@ -19,7 +19,10 @@ __global__ __launch_bounds__(256) void nn_kernel(
     int64_t n, int64_t K, int N, const TA* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld,
     const TX* __restrict__ X, int64_t ldx, TC* __restrict__ C, int64_t ldc,
-    ACC alpha, ACC beta, double* __restrict__ gpart) {
+    ACC alpha, ACC beta, double* __restrict__ gpart, int64_t kchunk,
+    double* __restrict__ split_out) {
+  // split s = blockIdx.z takes K range [s kchunk, (s + 1) kchunk); with
+  // split_out its raw sums go to split_out[(s n + row) N + col] (no epilogue)
   __shared__ ACC As[NN_BK][NN_BM + 1];
   __shared__ ACC Xs[NN_BK][NN_BN];
   const int t = threadIdx.x;
@@ -33,6 +36,8 @@ __global__ __launch_bounds__(256) void nn_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = ACC(0);
 
+  const int64_t kb = static_cast<int64_t>(blockIdx.z) * kchunk;
+  const int64_t ke = kb + kchunk < K ? kb + kchunk : K;
   // the next K chunk is loaded into registers while this one is multiplied
   ACC ar[8], xr[4];
   auto load = [&](int64_t k0) {
@@ -42,7 +47,7 @@ __global__ __launch_bounds__(256) void nn_kernel(
       const int r = e >> 5, kk = e & 31;
       const int64_t gr = row0 + r, gk = k0 + kk;
       ACC v = ACC(0);
-      if (gr < n && gk < K) {
+      if (gr < n && gk < ke) {
         v = static_cast<ACC>(Elem<TA>::load(A, gr * lda + gk));
         if (SCALED) v *= static_cast<ACC>(ascale[(gr >> 7) * ascale_ld + (gk >> 7)]);
       }
@@ -54,11 +59,11 @@ __global__ __launch_bounds__(256) void nn_kernel(
       const int kk = e >> 5, c = e & 31;
       const int64_t gk = k0 + kk;
       const int gc = col0 + c;
-      xr[i] = (gk < K && gc < N) ? static_cast<ACC>(X[gk * ldx + gc]) : ACC(0);
+      xr[i] = (gk < ke && gc < N) ? static_cast<ACC>(X[gk * ldx + gc]) : ACC(0);
     }
   };
-  if (K > 0) load(0);
-  for (int64_t k0 = 0; k0 < K; k0 += NN_BK) {
+  if (kb < ke) load(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += NN_BK) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int e = t + 256 * i;
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(256) void nn_kernel(
       Xs[e >> 5][e & 31] = xr[i];
     }
     __syncthreads();
-    if (k0 + NN_BK < K) load(k0 + NN_BK);
+    if (k0 + NN_BK < ke) load(k0 + NN_BK);
 #pragma unroll 8
     for (int kk = 0; kk < NN_BK; ++kk) {
       const ACC a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
@@ -82,6 +87,21 @@ __global__ __launch_bounds__(256) void nn_kernel(
       }
     }
     __syncthreads();
+  }
+  if (split_out) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int64_t gr = row0 + ty * 2 + i;
+      if (gr >= n) continue;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int gc = col0 + tx * 4 + j;
+        if (gc < N)
+          split_out[(static_cast<int64_t>(blockIdx.z) * n + gr) * N + gc] =
+              static_cast<double>(acc[i][j]);
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -120,6 +140,24 @@ __global__ __launch_bounds__(256) void nn_kernel(
       g[e] = sum;
     }
   }
+}
+
+// C = alpha (sum over the S splits, in split order) + beta C, one thread
+// per element.
+template <typename TC>
+__global__ __launch_bounds__(256) void nn_vsplit_reduce_kernel(int64_t n, int N, int S,
+                                                               const double* __restrict__ sp,
+                                                               TC* __restrict__ C, int64_t ldc,
+                                                               double alpha, double beta) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= n * N) return;
+  const int64_t r = e / N;
+  const int c = static_cast<int>(e - r * N);
+  double sum = 0.0;
+  for (int z = 0; z < S; ++z) sum += sp[static_cast<int64_t>(z) * n * N + e];
+  double v = alpha * sum;
+  if (beta != 0.0) v += beta * static_cast<double>(C[r * ldc + c]);
+  C[r * ldc + c] = static_cast<TC>(v);
 }
 
 // NN for a short reduction (K <= NS_KMAX) and N <= 32 with FP32 A, FP64 X
@@ -385,33 +423,55 @@ __global__ __launch_bounds__(256) void tn_reduce_wave_kernel(
   }
 }
 
+// Splits of K for the vector NN when its tiles leave most of the chip idle
+// (~256 workgroups, at least four 32-wide chunks per split).
+int nn_vec_splits(int64_t n, int64_t K, int N) {
+  const int64_t tiles = cdiv(n, NN_BM) * cdiv(N, NN_BN);
+  if (tiles >= 128 || K < 8 * NN_BK) return 1;
+  int64_t S = cdiv(256, tiles);
+  const int64_t smax = cdiv(K, 4 * NN_BK);
+  if (S > smax) S = smax;
+  return static_cast<int>(S < 1 ? 1 : S);
+}
+
 template <typename TA, typename TX, typename TC, typename ACC>
-void nn_dispatch_scaled(const NNArgs& a, hipStream_t s) {
+int nn_dispatch_scaled(const NNArgs& a, hipStream_t s) {
+  const int64_t tiles = cdiv(a.n, NN_BM) * cdiv(a.N, NN_BN);
+  const int S = a.gram_partial ? 1 : nn_vec_splits(a.n, a.K, a.N);
+  const bool split = S > 1 && a.split_work &&
+                     static_cast<int64_t>(S) * a.n * a.N <= a.split_work_elems;
+  const int64_t kchunk = split ? cdiv(cdiv(a.K, S), NN_BK) * NN_BK : (a.K > 0 ? a.K : 1);
+  const int Sx = split ? static_cast<int>(cdiv(a.K, kchunk)) : 1;
   const dim3 grid(static_cast<unsigned>(cdiv(a.n, NN_BM)),
-                  static_cast<unsigned>(cdiv(a.N, NN_BN)));
+                  static_cast<unsigned>(cdiv(a.N, NN_BN)), static_cast<unsigned>(Sx));
+  (void)tiles;
   const TA* A = static_cast<const TA*>(a.A);
   const TX* X = static_cast<const TX*>(a.X);
   TC* C = static_cast<TC*>(a.C);
+  double* so = split ? a.split_work : nullptr;
   if (a.ascale)
     nn_kernel<TA, TX, TC, ACC, true><<<grid, 256, 0, s>>>(
         a.n, a.K, a.N, A, a.lda, a.ascale, a.ascale_ld, X, a.ldx, C, a.ldc,
-        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial);
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial, kchunk, so);
   else
     nn_kernel<TA, TX, TC, ACC, false><<<grid, 256, 0, s>>>(
         a.n, a.K, a.N, A, a.lda, nullptr, 0, X, a.ldx, C, a.ldc,
-        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial);
+        static_cast<ACC>(a.alpha), static_cast<ACC>(a.beta), a.gram_partial, kchunk, so);
+  if (!split) return 1;
+  nn_vsplit_reduce_kernel<TC><<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(
+      a.n, a.N, Sx, so, C, a.ldc, a.alpha, a.beta);
+  return 2;
 }
 
 template <typename TA>
-void nn_dispatch_lowp(const NNArgs& a, hipStream_t s) {
+int nn_dispatch_lowp(const NNArgs& a, hipStream_t s) {
   // FP32-accumulating paths: X FP64 or FP32, C FP32 (or FP64)
   if (a.x_f64) {
-    if (a.c_f64) nn_dispatch_scaled<TA, double, double, float>(a, s);
-    else nn_dispatch_scaled<TA, double, float, float>(a, s);
-  } else {
-    if (a.c_f64) nn_dispatch_scaled<TA, float, double, float>(a, s);
-    else nn_dispatch_scaled<TA, float, float, float>(a, s);
+    if (a.c_f64) return nn_dispatch_scaled<TA, double, double, float>(a, s);
+    return nn_dispatch_scaled<TA, double, float, float>(a, s);
   }
+  if (a.c_f64) return nn_dispatch_scaled<TA, float, double, float>(a, s);
+  return nn_dispatch_scaled<TA, float, float, float>(a, s);
 }
 
 template <typename TX, typename ACC>
@@ -483,21 +543,16 @@ int launch_nn(const NNArgs& a, hipStream_t s) {
   }
   switch (a.a_type) {
     case BK_F64:
-      nn_dispatch_scaled<double, double, double, double>(a, s);
-      break;
+      return nn_dispatch_scaled<double, double, double, double>(a, s);
     case BK_F32:
-      nn_dispatch_lowp<float>(a, s);
-      break;
+      return nn_dispatch_lowp<float>(a, s);
     case BK_BF16:
-      nn_dispatch_lowp<bf16_t>(a, s);
-      break;
+      return nn_dispatch_lowp<bf16_t>(a, s);
     case BK_FP8_E4M3:
-      nn_dispatch_lowp<fp8_t>(a, s);
-      break;
+      return nn_dispatch_lowp<fp8_t>(a, s);
     default:
       return 0;
   }
-  return 1;
 }
 
 int tn_splits(int64_t L, int64_t p, int r) {

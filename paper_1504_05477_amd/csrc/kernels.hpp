@@ -39,6 +39,10 @@ struct NNArgs {
   // nn_gram_partial_elems doubles), added up by launch_gram_reduce; the
   // vector kernel then runs (no matrix-core path)
   double* gram_partial = nullptr;
+  // FP64 scratch (nullable) for splitting K when few row tiles leave the
+  // chip idle (vector path, no gram_partial): S n N doubles
+  double* split_work = nullptr;
+  int64_t split_work_elems = 0;
 };
 // returns the number of kernels launched (0: not launched)
 int launch_nn(const NNArgs& a, hipStream_t s);
