@@ -521,6 +521,8 @@ __device__ __forceinline__ void chol_blocked_inverse(int k, const double* __rest
       for (int e = t; e < CB * bj; e += CB_THREADS) {
         const int r = e / bj, c = e - (e / bj) * bj;
         double sum = 0.0;
+        // (unrolled: the global loads of a batch are in flight together)
+#pragma unroll 16
         for (int l = oi + CB; l < oj + bj; ++l) sum += S[(oi + r) * k + l] * Rinv[l * k + oj + c];
         T[r * CB + c] = sum;
       }
@@ -528,6 +530,7 @@ __device__ __forceinline__ void chol_blocked_inverse(int k, const double* __rest
       for (int e = t; e < CB * bj; e += CB_THREADS) {
         const int r = e / bj, c = e - (e / bj) * bj;
         double sum = 0.0;
+#pragma unroll 16
         for (int l = r; l < CB; ++l) sum += Rinv[(oi + r) * k + oi + l] * T[l * CB + c];
         Rinv[(oi + r) * k + oj + c] = -sum;
       }
