@@ -389,7 +389,7 @@ constexpr int CB_THREADS = 256;
 __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restrict__ G, double shift,
                                     double* __restrict__ S, double* __restrict__ Rinv,
                                     double* minpiv, int* fail, double* __restrict__ rkk,
-                                    double* __restrict__ pan) {
+                                    double* __restrict__ pan, int pld) {
   const int t = threadIdx.x;
   for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
     const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
@@ -474,7 +474,7 @@ __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restr
           double sum = 0.0;
 #pragma unroll
           for (int l = 0; l < CB; ++l) sum += rkk[l * CB + r] * col[l];
-          pan[r * kCholBlockedMax + jj] = sum;
+          pan[r * pld + jj] = sum;
           if (r < bs) S[(o + r) * k + j] = sum;
         }
       }
@@ -498,7 +498,7 @@ __device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restr
         const int i = o + bs + ii, j = o + bs + jj;
         double sum = 0.0;
 #pragma unroll 8
-        for (int r = 0; r < CB; ++r) sum += pan[r * kCholBlockedMax + ii] * pan[r * kCholBlockedMax + jj];
+        for (int r = 0; r < CB; ++r) sum += pan[r * pld + ii] * pan[r * pld + jj];
         S[i * k + j] -= sum;
       }
       __syncthreads();
@@ -542,17 +542,19 @@ __device__ __forceinline__ void chol_blocked_inverse(int k, const double* __rest
 __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
     int k, const double* __restrict__ G, const double* __restrict__ Gpre, int mode, int block,
     double tau, double shift_coef, double* __restrict__ R, double* __restrict__ Rinv,
-    double* __restrict__ work, Ctrl* ctrl) {
+    double* __restrict__ work, Ctrl* ctrl, int s_lds) {
   __shared__ double red[CB_THREADS];
   __shared__ double minpiv;
   __shared__ int fail;
   __shared__ int decision;
-  extern __shared__ double cb_dyn[];  // R_kk^-1 (CB x CB), panel (CB x kCholBlockedMax)
+  // R_kk^-1 (CB x CB; the inverse's T after the factor), panel (CB x k),
+  // with s_lds S (k x k) too, else S in work
+  extern __shared__ double cb_dyn[];
   double* rkk = cb_dyn;
   double* pan = cb_dyn + CB * CB;
   const int t = threadIdx.x;
-  double* S = work;
-  double* T = work + static_cast<int64_t>(k) * k;
+  double* S = s_lds ? pan + CB * k : work;
+  double* T = rkk;
   double trp = 0.0, prp = 0.0;
   int bad = 0;
   for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS)
@@ -581,7 +583,7 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   }
   __syncthreads();
   if (!decision && mode == CHOL_FIRST_BLOCK0) {
-    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail, rkk, pan);
+    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail, rkk, pan, k);
     if (t == 0 && (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr)))) {
       atomicOr(&ctrl->flags, CTRL_RANK);
       decision = 1;
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   }
   if (!decision) {
     const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
-    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail, rkk, pan);
+    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail, rkk, pan, k);
     if (t == 0 && !ok) {
       if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
       else atomicMin(&ctrl->q_eff, block - 1);
@@ -847,14 +849,18 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
 #undef BK_CHOL_WAVE
   if (k <= kCholBlockedMax) {
     static bool battr = false;
-    const size_t lds = static_cast<size_t>(CB * CB + CB * kCholBlockedMax) * sizeof(double);
+    constexpr size_t kMaxLds = 150 * 1024;
     if (!battr) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_blocked_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kMaxLds));
       battr = true;
     }
-    chol_blocked_kernel<<<1, CB_THREADS, lds, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,
-                                                   Rinv, work, ctrl);
+    // the working matrix in LDS beside the panel when it fits (k <= ~118)
+    const size_t base = static_cast<size_t>(CB * CB + CB * k) * sizeof(double);
+    const size_t with_s = base + static_cast<size_t>(k) * k * sizeof(double);
+    const int s_lds = with_s <= kMaxLds ? 1 : 0;
+    chol_blocked_kernel<<<1, CB_THREADS, s_lds ? with_s : base, s>>>(
+        k, G, Gpre, mode, block, tau, shift_coef, R, Rinv, work, ctrl, s_lds);
     return;
   }
   chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,

@@ -179,7 +179,9 @@ def test_svd_dense_f64_ragged(n, d, k, q):
     compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, k, 1e-10, 1e-8)
 
 
-@pytest.mark.parametrize("n,d,k,q", [(2400, 1200, 150, 2), (3000, 1600, 256, 1)])
+# k = 100: the blocked Cholesky's working matrix in LDS; 150, 256 in memory
+@pytest.mark.parametrize("n,d,k,q", [(2000, 1000, 100, 2), (2400, 1200, 150, 2),
+                                     (3000, 1600, 256, 1)])
 def test_svd_dense_f64_wide_blocks(n, d, k, q):
     """Blocks wider than one wavefront: the blocked Cholesky of CholeskyQR
     (32-column blocks, a ragged last block for k = 150)."""
