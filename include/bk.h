@@ -196,6 +196,70 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx,
                bk_info* info, void* workspace, size_t workspace_bytes,
                void* stream);
 
+/* Error measures of a rank-k basis Z (Section 3 and Section 7):
+ * Abar is A, or A - mu 1^T with mu the row means (center_rows, CSR only).
+ * eq. (1) uses ||Abar - Z Z^T Abar||_F, obtained from the matrix Pythagorean
+ * theorem of Section 3.2 as sqrt(||Abar||_F^2 - ||Z^T Abar||_F^2); eq. (2)
+ * uses ||Abar - Z Z^T Abar||_2, estimated as the top Ritz value of a block
+ * Krylov solve (Algorithm 2, block width k, depth q_spec, sketch seed `seed`)
+ * on the residual operator (I - Z Z^T) Abar, a lower bound that converges
+ * to it as q_spec grows (Theorem 1); eq. (3) compares each
+ * z_i^T Abar Abar^T z_i with sigma_i^2.  All products run on the GPU. */
+typedef struct bk_metrics { /* HOST struct                                  */
+  double fro2;          /* ||Abar||_F^2 (FP64 sums of the FP32/FP64 values) */
+  double captured_fro2; /* ||Z^T Abar||_F^2 = sum of captured[i]           */
+  double resid_fro;     /* ||Abar - Z Z^T Abar||_F                         */
+  double resid_spec;    /* ||Abar - Z Z^T Abar||_2 estimate (NaN: residual
+                           of rank below k, status BK_ERANK)               */
+  double fro_ratio;     /* eq. (1): resid_fro / ||Abar - Abar_k||_F        */
+  double spec_ratio;    /* eq. (2): resid_spec / sigma_{k+1}               */
+  double per_vector;    /* eq. (3) as reported in Section 7:
+                           max_i |sigma_i^2 - captured[i]| / sigma_{k+1}^2
+                           (the three ratios are NaN without sigma_true)   */
+} bk_metrics;
+
+/* Bytes of workspace bk_error_metrics_dense needs (0 on invalid arguments:
+ * a_type other than BK_F64 / BK_F32, or (q_spec+1) k > min(n, d)). */
+size_t bk_error_metrics_dense_workspace(int64_t n, int64_t d, int32_t k,
+                                        int32_t q_spec, int32_t a_type);
+
+/* Error measures of Z against a dense A (device, n x d row-major, ld lda,
+ * BK_F64 or BK_F32; Z device n x k, ld ldz >= k, the same type, orthonormal
+ * columns, e.g. the output of bk_svd_dense).
+ * sigma_true  nullable HOST array of n_sigma >= k+1 FP64 singular values of
+ *             A, descending; with n_sigma >= min(n, d) the tail
+ *             ||A - A_k||_F^2 is summed from them, otherwise taken as
+ *             ||A||_F^2 - sum_{i<=k} sigma_i^2.
+ * captured    nullable HOST array of k FP64: z_i^T A A^T z_i.
+ * out         nullable HOST struct.
+ * workspace   device scratch of bk_error_metrics_dense_workspace(...) bytes
+ *             or NULL (allocated and freed inside, stream-ordered).
+ * Synchronizes `stream`.  Returns BK_ERANK when the residual has rank below
+ * k (every other field is still written). */
+int bk_error_metrics_dense(const void* A, int64_t lda, int32_t a_type,
+                           int64_t n, int64_t d, const void* Z, int64_t ldz,
+                           int32_t k, int32_t q_spec, uint64_t seed,
+                           const double* sigma_true, int64_t n_sigma,
+                           double* captured, bk_metrics* out, void* workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* Bytes of workspace bk_error_metrics_csr needs (0 on invalid arguments). */
+size_t bk_error_metrics_csr_workspace(int64_t n, int64_t d, int64_t nnz,
+                                      int32_t k, int32_t q_spec);
+
+/* As bk_error_metrics_dense for a CSR A (arrays as bk_svd_csr, validated on
+ * the GPU first: BK_EINVAL when malformed), Z FP32 n x k; center_rows != 0
+ * measures against the row-centred A - mu 1^T (footnote on PCA, Section 1),
+ * never formed. */
+int bk_error_metrics_csr(const int32_t* row_ptr, const int32_t* col_idx,
+                         const float* vals, const int32_t* t_row_ptr,
+                         const int32_t* t_col_idx, const float* t_vals,
+                         int64_t n, int64_t d, int64_t nnz, int32_t center_rows,
+                         const float* Z, int64_t ldz, int32_t k, int32_t q_spec,
+                         uint64_t seed, const double* sigma_true,
+                         int64_t n_sigma, double* captured, bk_metrics* out,
+                         void* workspace, size_t workspace_bytes, void* stream);
+
 /* Reverse-mode adjoint of bk_svd_dense for the FP32 and FP64 plain paths.
  * Inputs: the same A / n / d / k / q / a_type as the forward, the forward's
  * workspace (opt->save_for_backward = 1 in the forward, unmodified since),

@@ -10,6 +10,9 @@ leg may import this.
 * Per-vector error, eq. (3), reported as in Section 7 (largest deviation over
   the top k, relative to sigma_{k+1}^2):
   max_i |sigma_i^2 - z_i^T A A^T z_i| / sigma_{k+1}^2.
+* The raw quantities behind them: ||A||_F^2, the captured energies
+  z_i^T A A^T z_i, and the two norms of the residual A - Z Z^T A from their
+  definitions (dense, small inputs).
 * Largest principal angle between two k-dimensional subspaces.
 """
 from __future__ import annotations
@@ -17,7 +20,8 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["frobenius_ratio", "spectral_ratio", "per_vector_error",
-           "principal_angle", "principal_angle_sin"]
+           "principal_angle", "principal_angle_sin", "frobenius_sq", "captured",
+           "residual_norms"]
 
 
 def _op(A):
@@ -25,9 +29,9 @@ def _op(A):
     return A if isinstance(A, LinearOperator) else LinearOperator(A)
 
 
-def frobenius_ratio(A, Z, sigma_true, k: int) -> float:
+def frobenius_sq(A) -> float:
+    """||A||_F^2, or ||A - mu 1^T||_F^2 for a centred operator."""
     op = _op(A)
-    ZtA = op.tmul(Z).T
     if hasattr(op.A, "multiply"):
         fro2 = float(op.A.multiply(op.A).sum())
     else:
@@ -35,8 +39,33 @@ def frobenius_ratio(A, Z, sigma_true, k: int) -> float:
     if op.center:
         # ||A - mu 1^T||_F^2 = ||A||_F^2 - d ||mu||^2
         fro2 -= op.d * float(op.mu @ op.mu)
+    return fro2
+
+
+def captured(A, Z) -> np.ndarray:
+    """z_i^T A A^T z_i = ||A^T z_i||^2 for each column of Z."""
+    W = _op(A).tmul(np.asarray(Z, dtype=np.float64))
+    return np.sum(W ** 2, axis=0)
+
+
+def residual_norms(A, Z) -> tuple[float, float]:
+    """(||R||_F, ||R||_2) of R = A - Z Z^T A from the definition; A dense, or
+    a (small) operator that is materialised, centring included."""
+    op = _op(A)
+    D = op.A.toarray() if hasattr(op.A, "toarray") else np.asarray(op.A, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    if op.center:
+        D = D - op.mu[:, None]
+    Z = np.asarray(Z, dtype=np.float64)
+    R = D - Z @ (Z.T @ D)
+    return float(np.linalg.norm(R, "fro")), float(np.linalg.norm(R, 2))
+
+
+def frobenius_ratio(A, Z, sigma_true, k: int) -> float:
+    ZtA_sq = float(np.sum(captured(A, Z)))
+    fro2 = frobenius_sq(A)
     tail = float(np.sum(np.asarray(sigma_true[k:], dtype=np.float64) ** 2))
-    return float(np.sqrt(max(fro2 - np.sum(ZtA ** 2), 0.0) / tail))
+    return float(np.sqrt(max(fro2 - ZtA_sq, 0.0) / tail))
 
 
 def spectral_ratio(A, Z, sigma_true, k: int) -> float:
@@ -47,11 +76,9 @@ def spectral_ratio(A, Z, sigma_true, k: int) -> float:
 
 
 def per_vector_error(A, Z, sigma_true, k: int) -> float:
-    op = _op(A)
-    W = op.tmul(Z)                       # A^T z_i in column i
-    captured = np.sum(W ** 2, axis=0)    # z_i^T A A^T z_i
+    cap = captured(A, Z)                 # z_i^T A A^T z_i
     s2 = np.asarray(sigma_true[:k], dtype=np.float64) ** 2
-    return float(np.max(np.abs(s2 - captured)) / sigma_true[k] ** 2)
+    return float(np.max(np.abs(s2 - cap)) / sigma_true[k] ** 2)
 
 
 def principal_angle_sin(Z1, Z2) -> float:

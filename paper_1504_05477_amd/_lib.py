@@ -55,6 +55,15 @@ class Info(C.Structure):
         }
 
 
+class Metrics(C.Structure):
+    _fields_ = [(f, C.c_double) for f in (
+        "fro2", "captured_fro2", "resid_fro", "resid_spec", "fro_ratio", "spec_ratio",
+        "per_vector")]
+
+    def as_dict(self) -> dict:
+        return {f: float(getattr(self, f)) for f, _ in self._fields_}
+
+
 class BKError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -79,6 +88,13 @@ _SIGS = [
     ("bk_svd_csr_workspace", _SZ, [_I64, _I64, _I64, _I32, _I32, _P]),
     ("bk_svd_csr", C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _U64,
                              _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    ("bk_error_metrics_dense_workspace", _SZ, [_I64, _I64, _I32, _I32, _I32]),
+    ("bk_error_metrics_dense", C.c_int, [_P, _I64, _I32, _I64, _I64, _P, _I64, _I32, _I32,
+                                         _U64, _P, _I64, _P, _P, _P, _SZ, _P]),
+    ("bk_error_metrics_csr_workspace", _SZ, [_I64, _I64, _I64, _I32, _I32]),
+    ("bk_error_metrics_csr", C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _P,
+                                       _I64, _I32, _I32, _U64, _P, _I64, _P, _P, _P, _SZ,
+                                       _P]),
     ("bk_svd_dense_backward_workspace", _SZ, [_I64, _I64, _I32, _I32, _I32]),
     ("bk_svd_dense_backward", C.c_int, [_P, _I64, _I32, _I64, _I64, _I32, _I32, _P, _I64, _P,
                                         _P, _P, _P, _I64, _P, _SZ, _P, _SZ, _P]),

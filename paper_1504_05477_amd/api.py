@@ -217,6 +217,86 @@ def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 
     return SVDResult(Z, sig, info.as_dict())
 
 
+@dataclass
+class Metrics:
+    """Error measures of a basis Z (Section 3): the raw norms and, with the
+    true singular values, the ratios of eqs. (1)-(3)."""
+    values: dict
+    captured: torch.Tensor  # k FP64 (CPU): z_i^T Abar Abar^T z_i
+    status: int
+
+
+def _sigma_host(sigma_true):
+    if sigma_true is None:
+        return None, 0, None
+    s = torch.as_tensor(sigma_true, dtype=torch.float64).detach().cpu().contiguous()
+    return s, s.numel(), C.cast(s.data_ptr(), C.c_void_p)
+
+
+def _finish_metrics(st, what, m, cap) -> Metrics:
+    if st not in (L.OK, L.ERANK):
+        L.check(st, what)
+    return Metrics(m.as_dict(), cap, st)
+
+
+def error_metrics_dense(A: torch.Tensor, Z: torch.Tensor, sigma_true=None, q_spec: int = 4,
+                        seed: int = 0, stream=None) -> Metrics:
+    """Error measures of Z (n x k, orthonormal columns, A's dtype) against a
+    dense FP32 / FP64 A on the GPU; ``sigma_true`` (k+1 or more values,
+    descending) enables the ratios."""
+    lib = L.load()
+    _need_cuda(A, Z)
+    if A.dim() != 2 or A.stride(1) != 1 or Z.dim() != 2 or Z.stride(1) != 1:
+        raise ValueError("A and Z must be row-major 2-D tensors")
+    if Z.dtype != A.dtype:
+        raise TypeError("Z must have A's dtype")
+    n, d = A.shape
+    k = Z.shape[1]
+    code = _dtype_code(A)
+    nbytes = lib.bk_error_metrics_dense_workspace(n, d, k, q_spec, code)
+    if nbytes == 0:
+        raise ValueError(f"invalid shape/type: n={n} d={d} k={k} q_spec={q_spec} {A.dtype}")
+    ws = _ws(nbytes, A.device)
+    sig, ns, sp = _sigma_host(sigma_true)
+    cap = torch.empty(k, dtype=torch.float64)
+    m = L.Metrics()
+    st = lib.bk_error_metrics_dense(_ptr(A), A.stride(0), code, n, d, _ptr(Z), Z.stride(0), k,
+                                    q_spec, int(seed) & (2**64 - 1), sp, ns,
+                                    C.cast(cap.data_ptr(), C.c_void_p), C.byref(m), _ptr(ws),
+                                    nbytes, _stream(stream))
+    return _finish_metrics(st, "bk_error_metrics_dense", m, cap)
+
+
+def error_metrics_csr(row_ptr, col_idx, vals, n: int, d: int, Z: torch.Tensor,
+                      sigma_true=None, q_spec: int = 4, seed: int = 0, *, center=False,
+                      transpose=None, stream=None) -> Metrics:
+    """Error measures of an FP32 Z (n x k) against a CSR A (or its row-centred
+    form with ``center``) on the GPU."""
+    lib = L.load()
+    _need_cuda(row_ptr, col_idx, vals, Z)
+    for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (vals, torch.float32)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise ValueError("CSR arrays must be contiguous int32/int32/float32")
+    if Z.dtype != torch.float32 or Z.dim() != 2 or Z.stride(1) != 1:
+        raise ValueError("Z must be a row-major float32 n x k tensor")
+    nnz = col_idx.numel()
+    k = Z.shape[1]
+    tr = transpose or (None, None, None)
+    nbytes = lib.bk_error_metrics_csr_workspace(n, d, nnz, k, q_spec)
+    if nbytes == 0:
+        raise ValueError(f"invalid shape: n={n} d={d} k={k} q_spec={q_spec}")
+    ws = _ws(nbytes, row_ptr.device)
+    sig, ns, sp = _sigma_host(sigma_true)
+    cap = torch.empty(k, dtype=torch.float64)
+    m = L.Metrics()
+    st = lib.bk_error_metrics_csr(_ptr(row_ptr), _ptr(col_idx), _ptr(vals), _ptr(tr[0]),
+                                  _ptr(tr[1]), _ptr(tr[2]), n, d, nnz, 1 if center else 0,
+                                  _ptr(Z), Z.stride(0), k, q_spec, int(seed) & (2**64 - 1), sp,
+                                  ns, C.cast(cap.data_ptr(), C.c_void_p), C.byref(m), _ptr(ws),
+                                  nbytes, _stream(stream))
+    return _finish_metrics(st, "bk_error_metrics_csr", m, cap)
+
+
 def gaussian(seed: int, rows: int, cols: int, dtype=torch.float32, device="cuda",
              stream=None) -> torch.Tensor:
     """The Philox4x32-10 / Box-Muller sketch (see bk_gaussian)."""

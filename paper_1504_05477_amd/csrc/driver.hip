@@ -18,8 +18,10 @@
 // zero-padded basis equals the one over the blocks built so far: no host
 // round trip is needed inside the loop.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "kernels.hpp"
@@ -434,6 +436,82 @@ struct CsrOp : Op {
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s);
+  }
+};
+
+// The residual R = (I - Z Z^T) Abar of a rank-k projection (Section 3.2),
+// whose norms eqs. (1) and (2) measure, as an operator over a base one:
+//   R X   = Abar X - Z (Z^T Abar X),    R^T Y = Abar^T (Y - Z (Z^T Y)).
+// Its largest singular value, ||Abar - Z Z^T Abar||_2, is then the top Ritz
+// value of a block Krylov solve on R.  R^T Y lies in the range of Abar^T, so
+// the base operator's ax_of_aty shortcut stays valid.
+struct ProjOp : Op {
+  Op* base = nullptr;
+  const void* Z = nullptr;  // n x kz, working type
+  int64_t ldz = 0;
+  int kz = 0;
+  void* tmp = nullptr;      // n x (block width), ld = block width
+  double* C = nullptr;      // kz x (block width) FP64
+  void forward_state() {
+    base->tm = tm;
+    base->partial = partial;
+    base->partial_elems = partial_elems;
+  }
+  // Y (n x k, ldy) -= Z (Z^T Y)
+  int project(void* Y, int64_t ldy, int k, hipStream_t s) {
+    const int zt = f64 ? BK_F64 : BK_F32;
+    TNArgs g;
+    g.L = n;
+    g.p = kz;
+    g.r = k;
+    g.X = Z;
+    g.ldx = ldz;
+    g.x_type = zt;
+    g.Y = Y;
+    g.ldy = ldy;
+    g.y_f64 = f64;
+    g.C = C;
+    g.ldc = k;
+    g.c_f64 = true;
+    g.partial = partial;
+    int nl = launch_tn(g, s);
+    NNArgs a;
+    a.n = n;
+    a.K = kz;
+    a.N = k;
+    a.A = Z;
+    a.lda = ldz;
+    a.a_type = zt;
+    a.X = C;
+    a.ldx = k;
+    a.x_f64 = true;
+    a.C = Y;
+    a.ldc = ldy;
+    a.c_f64 = f64;
+    a.alpha = -1.0;
+    a.beta = 1.0;
+    nl += launch_nn(a, s);
+    return nl;
+  }
+  void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    forward_state();
+    base->ax(X, ldx, k, Y, ldy, s);
+    tm->begin(BK_PH_PROJ);
+    tm->end(project(Y, ldy, k, s));
+  }
+  void ax_of_aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
+                 hipStream_t s) override {
+    forward_state();
+    base->ax_of_aty(X, ldx, k, Y, ldy, s);
+    tm->begin(BK_PH_PROJ);
+    tm->end(project(Y, ldy, k, s));
+  }
+  void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    forward_state();
+    tm->begin(BK_PH_PROJ);
+    launch_copy2d(X, f64, ldx, tmp, f64, k, n, k, s);
+    tm->end(1 + project(tmp, k, k, s));
+    base->aty(tmp, k, k, Y, ldy, s);
   }
 };
 
@@ -1027,6 +1105,235 @@ struct DevBuf {
   }
 };
 
+// The CSR solve's preparation: the structure check (before any kernel
+// indexes through it), the CSR of A^T unless given, the work plans of both
+// products for block width pw, the row means (centring); then
+// run(op, L, extra): extra is `extra_bytes` of the workspace after the
+// layout.
+template <typename Run>
+int csr_prepare_and_run(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                        const int32_t* t_row_ptr, const int32_t* t_col_idx, const float* t_vals,
+                        int64_t n, int64_t d, int64_t nnz, int32_t pw, int32_t q,
+                        const Options& o, void* workspace, size_t workspace_bytes,
+                        size_t extra_bytes, bk_info* info, hipStream_t s, Run run) {
+  const bool given_t = t_row_ptr && t_col_idx && t_vals;
+  const size_t lay =
+      align_up(make_layout(nullptr, n, d, nnz, pw, q, false, o, true, !given_t).bytes, 256);
+  const size_t need = lay + extra_bytes;
+  DevBuf own;
+  char* base = static_cast<char*>(workspace);
+  if (!base) {
+    own.s = s;
+    if (hipMallocAsync(&own.p, need, s) != hipSuccess) return BK_ENOMEM;
+    base = static_cast<char*>(own.p);
+  } else if (workspace_bytes < need) {
+    return BK_ENOMEM;
+  }
+  Layout L = make_layout(base, n, d, nnz, pw, q, false, o, true, !given_t);
+
+  Timer prep;
+  prep.on = o.timing != 0;
+  prep.mask = o.timing_phases;
+  prep.s = s;
+  prep.begin(BK_PH_PREP);
+  // Validate the structure before any kernel indexes through it.
+  launch_ctrl_init(L.ctrl, q, s);
+  launch_csr_validate(row_ptr, col_idx, n, d, nnz, L.ctrl, s);
+  if (given_t) launch_csr_validate(t_row_ptr, t_col_idx, d, n, nnz, L.ctrl, s);
+  Ctrl h;
+  BK_TRY(hipMemcpyAsync(&h, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  if (h.csr_bad) return BK_EINVAL;
+  const int32_t* trp = t_row_ptr;
+  const int32_t* tci = t_col_idx;
+  const float* tv = t_vals;
+  if (!given_t) {
+    launch_csr_transpose(row_ptr, col_idx, vals, n, d, nnz, L.trp, L.tci, L.tv, L.cursor,
+                         L.keys, s);
+    trp = L.trp;
+    tci = L.tci;
+    tv = L.tv;
+  }
+  launch_csr_plan(row_ptr, n, pw, L.plan_a, L.counters, s);
+  launch_csr_plan(trp, d, pw, L.plan_t, L.counters + 4, s);
+  if (o.center) launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
+  int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+  L.plan_t.operand = 1;
+  CsrPlan* plans[2] = {&L.plan_a, &L.plan_t};
+  for (int i = 0; i < 2; ++i) {
+    plans[i]->nshort = cnt[4 * i];
+    plans[i]->npieces = cnt[4 * i + 1];
+    plans[i]->nmulti = cnt[4 * i + 2];
+    plans[i]->short_nnz = cnt[4 * i + 3];
+  }
+  prep.end(0);
+
+  CsrOp op;
+  op.n = n;
+  op.d = d;
+  op.f64 = false;
+  op.rp = row_ptr;
+  op.ci = col_idx;
+  op.v = vals;
+  op.trp = trp;
+  op.tci = tci;
+  op.tv = tv;
+  op.pa = &L.plan_a;
+  op.pt = &L.plan_t;
+  op.mu = o.center ? L.mu : nullptr;
+  op.colpart = L.colpart;
+  op.colvec = L.colvec;
+  const int st = run(op, L, base + lay);
+  if (info && o.timing) {
+    float ms = 0.0f;
+    if (!prep.marks.empty())
+      (void)hipEventElapsedTime(&ms, prep.marks[0].second.first, prep.marks[0].second.second);
+    info->ms[BK_PH_PREP] += ms;
+  }
+  return st;
+}
+
+size_t csr_workspace_bytes(int64_t n, int64_t d, int64_t nnz, int32_t pw, int32_t q,
+                           const Options& o, bool own_transpose, size_t extra_bytes) {
+  return align_up(make_layout(nullptr, n, d, nnz, pw, q, false, o, true, own_transpose).bytes,
+                  256) +
+         extra_bytes;
+}
+
+// ------------------------------------------------------ error measures --
+struct MetricsWs {
+  void* tmp = nullptr;   // n x k working type: R^T's projected operand
+  double* C = nullptr;   // k x k FP64: Z^T Y of the projection
+  void* W = nullptr;     // d x k working type: Abar^T Z
+  double* G = nullptr;   // k x k FP64: W^T W
+  double* part = nullptr;
+  double* fro2 = nullptr;
+  void* zs = nullptr;    // n working type: top left singular vector of R
+  double* rs = nullptr;  // its singular value
+  size_t bytes = 0;
+};
+
+MetricsWs make_metrics_ws(char* base, int64_t n, int64_t d, int k, bool f64) {
+  Arena ar;
+  ar.base = base;
+  MetricsWs w;
+  const size_t es = f64 ? 8 : 4;
+  const size_t kk = static_cast<size_t>(k) * k;
+  w.tmp = ar.take<char>(static_cast<size_t>(n) * k * es);
+  w.C = ar.take<double>(kk);
+  w.W = ar.take<char>(static_cast<size_t>(d) * k * es);
+  w.G = ar.take<double>(kk);
+  w.part = ar.take<double>(
+      static_cast<size_t>(std::max(fro2_partial_elems(), tn_partial_elems(d, k, k))));
+  w.fro2 = ar.take<double>(1);
+  w.zs = ar.take<char>(static_cast<size_t>(n) * es);
+  w.rs = ar.take<double>(1);
+  w.bytes = align_up(ar.off, 256);
+  return w;
+}
+
+// The error measures of Z (n x k, orthonormal columns) against Abar:
+//   ||Abar||_F^2 (the `fro2` launcher), captured_i = ||Abar^T z_i||^2 =
+//   z_i^T Abar Abar^T z_i (the diagonal of W^T W, W = Abar^T Z), the
+//   Frobenius residual by the Pythagorean identity of Section 3.2, and the
+//   spectral residual as the top Ritz value of a depth-q_spec block Krylov
+//   solve (block width k) on R = (I - Z Z^T) Abar.  The ratios of eqs.
+//   (1)-(3) follow from sigma (host, n_sigma >= k + 1 values) when given.
+// L is a solve layout for block width k and depth q_spec over `op`.
+template <typename Fro2>
+int metrics_run(Op& op, Layout& L, const MetricsWs& w, const void* Z, int64_t ldz, int k,
+                int q_spec, uint64_t seed, const double* sigma, int64_t n_sigma,
+                double* captured, bk_metrics* out, hipStream_t s, Fro2 fro2) {
+  const bool f64 = op.f64;
+  Timer off;
+  op.tm = &off;
+  op.partial = L.partial;
+  op.partial_elems = L.partial_elems;
+  fro2(w.part, w.fro2);
+  op.aty(Z, ldz, k, w.W, k, s);
+  TNArgs g;
+  g.L = op.d;
+  g.p = k;
+  g.r = k;
+  g.X = w.W;
+  g.ldx = k;
+  g.x_type = f64 ? BK_F64 : BK_F32;
+  g.Y = w.W;
+  g.ldy = k;
+  g.y_f64 = f64;
+  g.C = w.G;
+  g.ldc = k;
+  g.c_f64 = true;
+  g.partial = w.part;
+  g.sym = true;
+  launch_tn(g, s);
+  std::vector<double> G(static_cast<size_t>(k) * k);
+  double f2 = 0.0;
+  BK_TRY(hipMemcpyAsync(G.data(), w.G, G.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipMemcpyAsync(&f2, w.fro2, sizeof(double), hipMemcpyDeviceToHost, s));
+  BK_TRY(hipStreamSynchronize(s));
+  BK_TRY_LAUNCH();
+
+  ProjOp pop;
+  pop.n = op.n;
+  pop.d = op.d;
+  pop.f64 = f64;
+  pop.base = &op;
+  pop.Z = Z;
+  pop.ldz = ldz;
+  pop.kz = k;
+  pop.tmp = w.tmp;
+  pop.C = w.C;
+  Options so;
+  so.p = k;
+  so.tau = f64 ? 1e-11 : 1e-5;
+  const int st = solve(pop, L, so, 1, q_spec, seed, nullptr, w.zs, 1, w.rs, nullptr, s);
+  if (st != BK_OK && st != BK_ERANK) return st;
+  // BK_ERANK: R Pi is rank deficient (R of rank below k); the spectral
+  // residual is then left unestimated (NaN)
+  double rs = std::numeric_limits<double>::quiet_NaN();
+  if (st == BK_OK) {
+    BK_TRY(hipMemcpyAsync(&rs, w.rs, sizeof(double), hipMemcpyDeviceToHost, s));
+    BK_TRY(hipStreamSynchronize(s));
+  }
+
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  double csum = 0.0;
+  for (int i = 0; i < k; ++i) {
+    const double c = G[static_cast<size_t>(i) * k + i];
+    csum += c;
+    if (captured) captured[i] = c;
+  }
+  bk_metrics m;
+  m.fro2 = f2;
+  m.captured_fro2 = csum;
+  m.resid_fro = std::sqrt(std::max(f2 - csum, 0.0));
+  m.resid_spec = rs;
+  m.fro_ratio = m.spec_ratio = m.per_vector = nan;
+  if (sigma && n_sigma >= k + 1) {
+    double head = 0.0, tail = 0.0, pv = 0.0;
+    for (int i = 0; i < k; ++i) head += sigma[i] * sigma[i];
+    if (n_sigma >= std::min(op.n, op.d))
+      for (int64_t i = k; i < n_sigma; ++i) tail += sigma[i] * sigma[i];
+    else
+      tail = f2 - head;  // ||Abar - Abar_k||_F^2 = ||Abar||_F^2 - sum_{i<=k} sigma_i^2
+    const double sk1 = sigma[k];
+    for (int i = 0; i < k; ++i)
+      pv = std::max(pv, std::fabs(sigma[i] * sigma[i] - G[static_cast<size_t>(i) * k + i]));
+    if (tail > 0.0) m.fro_ratio = m.resid_fro / std::sqrt(tail);
+    if (sk1 > 0.0) {
+      m.spec_ratio = rs / sk1;
+      m.per_vector = pv / (sk1 * sk1);
+    }
+  }
+  if (out) *out = m;
+  return st;
+}
+
 }  // namespace
 }  // namespace bk
 
@@ -1117,7 +1424,7 @@ size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k, int32_
   o.save = 0;
   const int32_t pw = block_width(n, d, k, q, o);
   if (!pw) return 0;
-  return make_layout(nullptr, n, d, nnz, pw, q, false, o, true, true).bytes;
+  return csr_workspace_bytes(n, d, nnz, pw, q, o, true, 0);
 }
 
 int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
@@ -1136,7 +1443,38 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   const int32_t pw = block_width(n, d, k, q, o);
   if (!pw) return BK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t need = make_layout(nullptr, n, d, nnz, pw, q, false, o, true, !given_t).bytes;
+  return csr_prepare_and_run(
+      row_ptr, col_idx, vals, t_row_ptr, t_col_idx, t_vals, n, d, nnz, pw, q, o, workspace,
+      workspace_bytes, 0, info, s, [&](CsrOp& op, Layout& L, char*) {
+        return solve(op, L, o, k, q, seed, nullptr, Z, ldz, ritz, info, s);
+      });
+}
+
+size_t bk_error_metrics_dense_workspace(int64_t n, int64_t d, int32_t k, int32_t q_spec,
+                                        int32_t a_type) {
+  if (a_type != BK_F64 && a_type != BK_F32) return 0;
+  const bool f64 = a_type == BK_F64;
+  Options o;
+  if (!block_width(n, d, k, q_spec, o)) return 0;
+  return align_up(make_layout(nullptr, n, d, 0, k, q_spec, f64, o, false, false).bytes, 256) +
+         make_metrics_ws(nullptr, n, d, k, f64).bytes;
+}
+
+int bk_error_metrics_dense(const void* A, int64_t lda, int32_t a_type, int64_t n, int64_t d,
+                           const void* Z, int64_t ldz, int32_t k, int32_t q_spec,
+                           uint64_t seed, const double* sigma_true, int64_t n_sigma,
+                           double* captured, bk_metrics* out, void* workspace,
+                           size_t workspace_bytes, void* stream) {
+  if (!A || !Z || lda < d || ldz < k) return BK_EINVAL;
+  if (a_type != BK_F64 && a_type != BK_F32) return BK_EINVAL;
+  const bool f64 = a_type == BK_F64;
+  Options o;
+  o.tau = f64 ? 1e-11 : 1e-5;
+  if (!block_width(n, d, k, q_spec, o)) return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t lay =
+      align_up(make_layout(nullptr, n, d, 0, k, q_spec, f64, o, false, false).bytes, 256);
+  const size_t need = lay + make_metrics_ws(nullptr, n, d, k, f64).bytes;
   DevBuf own;
   char* base = static_cast<char*>(workspace);
   if (!base) {
@@ -1146,72 +1484,58 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   } else if (workspace_bytes < need) {
     return BK_ENOMEM;
   }
-  Layout L = make_layout(base, n, d, nnz, pw, q, false, o, true, !given_t);
-
-  Timer prep;
-  prep.on = o.timing != 0;
-  prep.mask = o.timing_phases;
-  prep.s = s;
-  prep.begin(BK_PH_PREP);
-  // Validate the structure before any kernel indexes through it.
-  launch_ctrl_init(L.ctrl, q, s);
-  launch_csr_validate(row_ptr, col_idx, n, d, nnz, L.ctrl, s);
-  if (given_t) launch_csr_validate(t_row_ptr, t_col_idx, d, n, nnz, L.ctrl, s);
-  Ctrl h;
-  BK_TRY(hipMemcpyAsync(&h, L.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  BK_TRY(hipStreamSynchronize(s));
-  BK_TRY_LAUNCH();
-  if (h.csr_bad) return BK_EINVAL;
-  const int32_t* trp = t_row_ptr;
-  const int32_t* tci = t_col_idx;
-  const float* tv = t_vals;
-  if (!given_t) {
-    launch_csr_transpose(row_ptr, col_idx, vals, n, d, nnz, L.trp, L.tci, L.tv, L.cursor,
-                         L.keys, s);
-    trp = L.trp;
-    tci = L.tci;
-    tv = L.tv;
-  }
-  launch_csr_plan(row_ptr, n, pw, L.plan_a, L.counters, s);
-  launch_csr_plan(trp, d, pw, L.plan_t, L.counters + 4, s);
-  if (o.center) launch_csr_row_means(row_ptr, vals, n, d, L.mu, s);
-  int32_t cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BK_TRY(hipMemcpyAsync(cnt, L.counters, sizeof(cnt), hipMemcpyDeviceToHost, s));
-  BK_TRY(hipStreamSynchronize(s));
-  BK_TRY_LAUNCH();
-  L.plan_t.operand = 1;
-  CsrPlan* plans[2] = {&L.plan_a, &L.plan_t};
-  for (int i = 0; i < 2; ++i) {
-    plans[i]->nshort = cnt[4 * i];
-    plans[i]->npieces = cnt[4 * i + 1];
-    plans[i]->nmulti = cnt[4 * i + 2];
-    plans[i]->short_nnz = cnt[4 * i + 3];
-  }
-  prep.end(0);
-
-  CsrOp op;
+  Layout L = make_layout(base, n, d, 0, k, q_spec, f64, o, false, false);
+  const MetricsWs w = make_metrics_ws(base + lay, n, d, k, f64);
+  DenseOp op;
   op.n = n;
   op.d = d;
-  op.f64 = false;
-  op.rp = row_ptr;
-  op.ci = col_idx;
-  op.v = vals;
-  op.trp = trp;
-  op.tci = tci;
-  op.tv = tv;
-  op.pa = &L.plan_a;
-  op.pt = &L.plan_t;
-  op.mu = o.center ? L.mu : nullptr;
-  op.colpart = L.colpart;
-  op.colvec = L.colvec;
-  const int st = solve(op, L, o, k, q, seed, nullptr, Z, ldz, ritz, info, s);
-  if (info && o.timing) {
-    float ms = 0.0f;
-    if (!prep.marks.empty())
-      (void)hipEventElapsedTime(&ms, prep.marks[0].second.first, prep.marks[0].second.second);
-    info->ms[BK_PH_PREP] += ms;
-  }
-  return st;
+  op.f64 = f64;
+  op.A = A;
+  op.lda = lda;
+  op.a_type = a_type;
+  op.pack = L.pack;
+  op.pack_bytes = L.pack_bytes;
+  return metrics_run(op, L, w, Z, ldz, k, q_spec, seed, sigma_true, n_sigma, captured, out, s,
+                     [&](double* part, double* res) {
+                       launch_dense_fro2(A, f64, n, d, lda, part, res, s);
+                     });
+}
+
+size_t bk_error_metrics_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k,
+                                      int32_t q_spec) {
+  if (nnz < 0 || nnz >= (int64_t(1) << 31)) return 0;
+  Options o;
+  if (!block_width(n, d, k, q_spec, o)) return 0;
+  return csr_workspace_bytes(n, d, nnz, k, q_spec, o, true,
+                             make_metrics_ws(nullptr, n, d, k, false).bytes);
+}
+
+int bk_error_metrics_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals,
+                         const int32_t* t_row_ptr, const int32_t* t_col_idx,
+                         const float* t_vals, int64_t n, int64_t d, int64_t nnz,
+                         int32_t center_rows, const float* Z, int64_t ldz, int32_t k,
+                         int32_t q_spec, uint64_t seed, const double* sigma_true,
+                         int64_t n_sigma, double* captured, bk_metrics* out, void* workspace,
+                         size_t workspace_bytes, void* stream) {
+  if (nnz < 0 || nnz >= (int64_t(1) << 31) || !row_ptr || !Z || ldz < k) return BK_EINVAL;
+  if (nnz > 0 && (!col_idx || !vals)) return BK_EINVAL;
+  const bool given_t = t_row_ptr && t_col_idx && t_vals;
+  if ((t_row_ptr || t_col_idx || t_vals) && !given_t) return BK_EINVAL;
+  Options o;
+  o.tau = 1e-5;
+  o.center = center_rows ? 1 : 0;
+  if (!block_width(n, d, k, q_spec, o)) return BK_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t wbytes = make_metrics_ws(nullptr, n, d, k, false).bytes;
+  return csr_prepare_and_run(
+      row_ptr, col_idx, vals, t_row_ptr, t_col_idx, t_vals, n, d, nnz, k, q_spec, o,
+      workspace, workspace_bytes, wbytes, nullptr, s, [&](CsrOp& op, Layout& L, char* extra) {
+        const MetricsWs w = make_metrics_ws(extra, n, d, k, false);
+        return metrics_run(op, L, w, Z, ldz, k, q_spec, seed, sigma_true, n_sigma, captured,
+                           out, s, [&](double* part, double* res) {
+                             launch_csr_fro2(row_ptr, vals, n, d, o.center != 0, part, res, s);
+                           });
+      });
 }
 
 size_t bk_svd_dense_backward_workspace(int64_t n, int64_t d, int32_t k, int32_t q,

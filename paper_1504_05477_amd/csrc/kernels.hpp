@@ -126,6 +126,16 @@ void launch_ctrl_reset_off(Ctrl* c, hipStream_t s);
 // by 32 in one workgroup for k <= kCholBlockedMax (work: k k + 4096
 // doubles), else one workgroup step by step.
 constexpr int kCholBlockedMax = 512;
+
+// Squared Frobenius norms for the error measures (metrics.hip): *out (FP64,
+// device) = ||A||_F^2 of a dense n x d A (ld lda, FP64 or FP32), or of a CSR
+// A (- mu 1^T with centre, mu the row means); part: fro2_partial_elems()
+// doubles of scratch.
+int64_t fro2_partial_elems();
+void launch_dense_fro2(const void* A, bool f64, int64_t n, int64_t d, int64_t lda,
+                       double* part, double* out, hipStream_t s);
+void launch_csr_fro2(const int32_t* rp, const float* v, int64_t n, int64_t d, bool center,
+                     double* part, double* out, hipStream_t s);
 inline int64_t chol_work_doubles(int k) { return static_cast<int64_t>(k) * k + 4096; }
 enum CholMode { CHOL_FIRST_BLOCK0 = 0, CHOL_FIRST = 1, CHOL_REPEAT = 2 };
 void launch_chol(int k, const double* G, const double* Gpre, int mode,

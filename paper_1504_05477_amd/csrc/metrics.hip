@@ -1,0 +1,98 @@
+// Reductions behind the error measures of Section 3 (eqs. (1)-(3)): the
+// squared Frobenius norm of A, or of the row-centred A - mu 1^T (the PCA
+// footnote of Section 1), which the matrix Pythagorean theorem of Section
+// 3.2 turns into ||A - Z Z^T A||_F^2 = ||A||_F^2 - ||Z^T A||_F^2.  FP64 sums
+// in a fixed order (per-block partials, then the blocks in order).
+#include "kernels.hpp"
+
+namespace bk {
+namespace {
+
+constexpr int FRO_BLOCKS = 256;
+
+__device__ double block_sum256(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  return ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+// Block b sums a[r][c]^2 over rows [b per, (b + 1) per) of a rows x cols
+// row-major array (ld).
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ a, int64_t rows,
+                                                    int64_t cols, int64_t ld, int64_t per,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  double s = 0.0;
+  for (int64_t r = r0; r < r1; ++r)
+    for (int64_t c = threadIdx.x; c < cols; c += 256) {
+      const double x = static_cast<double>(a[r * ld + c]);
+      s += x * x;
+    }
+  const double tot = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// CSR rows: sum of v^2 over the row, minus (sum of v)^2 / d with centring
+// (||a_r - mean(a_r) 1||^2 = ||a_r||^2 - (1^T a_r)^2 / d), a thread per row.
+__global__ __launch_bounds__(256) void csr_sumsq_kernel(const int32_t* __restrict__ rp,
+                                                        const float* __restrict__ v,
+                                                        int64_t rows, int64_t d, int center,
+                                                        int64_t per, double* __restrict__ part) {
+  __shared__ double red[4];
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
+  double s = 0.0;
+  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+    double s2 = 0.0, s1 = 0.0;
+    for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+      const double x = static_cast<double>(v[j]);
+      s2 += x * x;
+      s1 += x;
+    }
+    s += center ? s2 - s1 * s1 / static_cast<double>(d) : s2;
+  }
+  const double tot = block_sum256(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ void sum_parts_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b];
+    *out = s;
+  }
+}
+
+int fro_blocks(int64_t rows) {
+  return static_cast<int>(rows < FRO_BLOCKS ? (rows > 0 ? rows : 1) : FRO_BLOCKS);
+}
+
+}  // namespace
+
+int64_t fro2_partial_elems() { return FRO_BLOCKS; }
+
+void launch_dense_fro2(const void* A, bool f64, int64_t n, int64_t d, int64_t lda,
+                       double* part, double* out, hipStream_t s) {
+  const int nb = fro_blocks(n);
+  const int64_t per = cdiv(n, nb);
+  if (f64)
+    sumsq_kernel<double><<<nb, 256, 0, s>>>(static_cast<const double*>(A), n, d, lda, per, part);
+  else
+    sumsq_kernel<float><<<nb, 256, 0, s>>>(static_cast<const float*>(A), n, d, lda, per, part);
+  sum_parts_kernel<<<1, 64, 0, s>>>(part, nb, out);
+}
+
+void launch_csr_fro2(const int32_t* rp, const float* v, int64_t n, int64_t d, bool center,
+                     double* part, double* out, hipStream_t s) {
+  const int nb = fro_blocks(cdiv(n, 256));
+  const int64_t per = cdiv(n, nb);
+  csr_sumsq_kernel<<<nb, 256, 0, s>>>(rp, v, n, d, center ? 1 : 0, per, part);
+  sum_parts_kernel<<<1, 64, 0, s>>>(part, nb, out);
+}
+
+}  // namespace bk

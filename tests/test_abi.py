@@ -46,6 +46,7 @@ def test_status_strings(lib):
 def test_struct_layouts():
     assert C.sizeof(L.Options) == 72
     assert L.Info.workspace_bytes.offset == 112
+    assert C.sizeof(L.Metrics) == 56
 
 
 def _opt():
@@ -135,6 +136,32 @@ def test_csr_and_helpers_reject_bad_arguments(lib):
     assert lib.bk_eigh_psd(None, 4, 4, None, None, 4, 0, 0.0, None, None, 0, None) == L.EINVAL
     assert lib.bk_dense_product(0, C.c_void_p(16), 3, L.F32, None, 4, 4, C.c_void_p(16), 2, 2,
                                 C.c_void_p(16), 2, None, 0, None) == L.EINVAL
+
+
+def test_error_metrics_argument_rules(lib):
+    """The error-measure calls validate shapes and types before any GPU work."""
+    assert lib.bk_error_metrics_dense_workspace(600, 400, 8, 4, L.F64) > 600 * 8 * 8
+    assert lib.bk_error_metrics_dense_workspace(600, 400, 8, 4, L.BF16) == 0
+    assert lib.bk_error_metrics_dense_workspace(600, 400, 8, 60, L.F32) == 0  # (q+1) k > d
+    assert lib.bk_error_metrics_csr_workspace(11000, 130000, 1_500_000, 20, 4) > 0
+    assert lib.bk_error_metrics_csr_workspace(10, 10, 2**31, 2, 1) == 0
+    P = C.c_void_p(16)
+    # unsupported A type, ldz < k, lda < d, null Z
+    assert lib.bk_error_metrics_dense(P, 400, L.BF16, 600, 400, P, 8, 8, 4, 0, None, 0, None,
+                                      None, None, 0, None) == L.EINVAL
+    assert lib.bk_error_metrics_dense(P, 400, L.F32, 600, 400, P, 7, 8, 4, 0, None, 0, None,
+                                      None, None, 0, None) == L.EINVAL
+    assert lib.bk_error_metrics_dense(P, 399, L.F32, 600, 400, P, 8, 8, 4, 0, None, 0, None,
+                                      None, None, 0, None) == L.EINVAL
+    assert lib.bk_error_metrics_dense(P, 400, L.F32, 600, 400, None, 8, 8, 4, 0, None, 0, None,
+                                      None, None, 0, None) == L.EINVAL
+    # CSR: null row_ptr, half a transpose, q_spec too deep
+    assert lib.bk_error_metrics_csr(None, P, P, None, None, None, 10, 10, 5, 0, P, 2, 2, 1, 0,
+                                    None, 0, None, None, None, 0, None) == L.EINVAL
+    assert lib.bk_error_metrics_csr(P, P, P, P, None, None, 10, 10, 5, 0, P, 2, 2, 1, 0, None,
+                                    0, None, None, None, 0, None) == L.EINVAL
+    assert lib.bk_error_metrics_csr(P, P, P, None, None, None, 10, 10, 5, 0, P, 2, 2, 5, 0,
+                                    None, 0, None, None, None, 0, None) == L.EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):

@@ -168,6 +168,41 @@ def test_metrics_on_exact_singular_vectors():
     assert abs(metrics.frobenius_ratio(A, Uk, sv, 6) - 1.0) < 1e-12
 
 
+def test_residual_norms_and_captured_closed_forms():
+    # Eckart-Young (Section 2): with Z the exact top-k left singular vectors
+    # the residual is A - A_k, whose norms are sqrt(sum_{i>k} sigma_i^2) and
+    # sigma_{k+1}; the captured energies are sigma_i^2; ||A||_F^2 is the sum
+    # of all sigma_i^2.
+    sv = workloads.spectrum("inv", 40)
+    A = workloads.planted_dense(70, 40, sv, seed=16)
+    U = np.linalg.svd(A)[0]
+    fro, spec = metrics.residual_norms(A, U[:, :5])
+    assert abs(fro - np.sqrt(np.sum(sv[5:] ** 2))) < 1e-12 * fro
+    assert abs(spec - sv[5]) < 1e-12 * spec
+    assert np.allclose(metrics.captured(A, U[:, :5]), sv[:5] ** 2, rtol=1e-12)
+    assert abs(metrics.frobenius_sq(A) - np.sum(sv ** 2)) < 1e-12 * np.sum(sv ** 2)
+    # a generic orthonormal Z: Pythagoras ties the three together, and the
+    # spectral residual is at least sigma_{k+1} (optimality of A_k)
+    Z = np.linalg.qr(np.random.default_rng(17).standard_normal((70, 5)))[0]
+    fro, spec = metrics.residual_norms(A, Z)
+    assert abs(fro ** 2 + np.sum(metrics.captured(A, Z)) - metrics.frobenius_sq(A)) < 1e-12
+    assert spec >= sv[5] * (1 - 1e-12)
+    # centring: the operator's materialised form is A with each row's mean
+    # taken out (the row means computed here independently)
+    rp, ci, va = workloads.term_document_csr(120, 500, seed=18, median_len=15)
+    M = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(120, 500))
+    Ac = M.toarray() - M.toarray().mean(axis=1, keepdims=True)
+    op = bki.LinearOperator(M, center=True)
+    Zc = np.linalg.qr(np.random.default_rng(19).standard_normal((120, 4)))[0]
+    assert abs(metrics.frobenius_sq(op) - np.sum(Ac ** 2)) < 1e-10 * np.sum(Ac ** 2)
+    Rc = Ac - Zc @ (Zc.T @ Ac)
+    fro_c, spec_c = metrics.residual_norms(op, Zc)
+    assert abs(fro_c - np.sqrt(np.sum(Rc ** 2))) < 1e-10 * fro_c
+    assert abs(spec_c - np.linalg.svd(Rc, compute_uv=False)[0]) < 1e-10 * spec_c
+    assert np.allclose(metrics.captured(op, Zc), np.sum((Ac.T @ Zc) ** 2, axis=0),
+                       rtol=1e-10)
+
+
 def test_frobenius_pythagoras_matches_direct():
     sv = workloads.spectrum("inv", 50)
     A = workloads.planted_dense(70, 50, sv, seed=10)
