@@ -45,7 +45,8 @@ import numpy as np
 __all__ = [
     "RankError", "BKIResult", "LinearOperator", "validate",
     "block_krylov", "block_krylov_route_b", "rayleigh_ritz_svd",
-    "rayleigh_ritz", "simultaneous_iteration", "sign_normalize",
+    "rayleigh_ritz", "simultaneous_iteration", "sign_normalize", "block_lanczos",
+    "block_tridiagonal",
 ]
 
 
@@ -219,3 +220,78 @@ def simultaneous_iteration(A, Pi, k: int, q: int, *, center: bool = False) -> BK
         X = _qr_pos(op.mul(op.tmul(X)))[0]
     Z, sigma, theta, U = rayleigh_ritz(op, X, k)
     return BKIResult(Z, sigma, theta, X, U, q)
+
+
+def block_tridiagonal(diag, sub) -> np.ndarray:
+    """The symmetric block-tridiagonal matrix with diagonal blocks diag[i]
+    and blocks sub[i] = T_{i+1,i} below the diagonal (sub[i]^T above)."""
+    p = diag[0].shape[0]
+    m = p * len(diag)
+    T = np.zeros((m, m))
+    for i, D in enumerate(diag):
+        T[i * p:(i + 1) * p, i * p:(i + 1) * p] = 0.5 * (D + D.T)
+    for i, B in enumerate(sub):
+        T[(i + 1) * p:(i + 2) * p, i * p:(i + 1) * p] = B
+        T[i * p:(i + 1) * p, (i + 1) * p:(i + 2) * p] = B.T
+    return T
+
+
+def block_lanczos(A, Pi, k: int, q: int, *, center: bool = False,
+                  tau: float = 1e-12):
+    """Route D (Section 4.2, the block Lanczos alternative): the same Krylov
+    space built by the three-term recurrence of block Lanczos on A A^T,
+
+        Q_0 B_0 = A Pi,
+        Q_i B_i = A A^T Q_{i-1} - Q_{i-1} D_{i-1} - Q_{i-2} B_{i-1}^T,
+        D_i = Q_i^T A A^T Q_i,
+
+    so that T = Q^T A A^T Q is block tridiagonal (diagonal blocks D_i, B_i
+    below the diagonal).  The recurrence alone loses orthogonality (the
+    instability Section 4.2 warns of), so each new block is also projected
+    against all earlier ones, twice, before its QR.  Rayleigh-Ritz then takes
+    the eigenpairs of T instead of forming W^T W.  Breakdown and ordering
+    rules as route A.  Returns (BKIResult, T)."""
+    op = A if isinstance(A, LinearOperator) else LinearOperator(A, center)
+    n, d = op.n, op.d
+    Pi = np.asarray(Pi, dtype=np.float64)
+    if Pi.ndim != 2 or Pi.shape[0] != d:
+        raise ValueError(f"Pi must be {d} x p")
+    validate(n, d, k, q, Pi.shape[1])
+    B = op.mul(Pi)
+    if not np.all(np.isfinite(B)):
+        raise ValueError("non-finite entries")
+    sv = np.linalg.svd(B, compute_uv=False)
+    if sv[-1] <= tau * max(np.linalg.norm(B), np.finfo(float).tiny):
+        raise RankError("A Pi is numerically rank deficient")
+    blocks = [_qr_pos(B)[0]]
+    diag, sub = [], []
+    q_eff = q
+    for i in range(1, q + 1):
+        X = op.mul(op.tmul(blocks[-1]))          # A A^T Q_{i-1}
+        before = np.linalg.norm(X)
+        D = blocks[-1].T @ X
+        diag.append(D)
+        X = X - blocks[-1] @ D
+        if len(sub):
+            X = X - blocks[-2] @ sub[-1].T
+        P = np.hstack(blocks)
+        for _ in range(2):
+            X = X - P @ (P.T @ X)
+        if np.linalg.norm(X) <= tau * before:
+            q_eff = i - 1
+            break
+        Qi, Bi = _qr_pos(X)
+        blocks.append(Qi)
+        sub.append(Bi)
+    if len(diag) < len(blocks):               # the last block's D_q
+        W = op.tmul(blocks[-1])
+        diag.append(W.T @ W)
+    T = block_tridiagonal(diag, sub)
+    Q = np.hstack(blocks)
+    theta, U = np.linalg.eigh(T)
+    order = np.argsort(-theta, kind="stable")
+    theta = theta[order]
+    U = U[:, order]
+    Z = sign_normalize(Q @ U[:, :k])
+    sigma = np.sqrt(np.maximum(theta[:k], 0.0))
+    return BKIResult(Z, sigma, theta, Q, U, q_eff), T

@@ -281,6 +281,48 @@ def test_centered_operator_matches_explicit_centering():
     assert abs(metrics.frobenius_ratio(op, r1.Z, sv, 5) - fr_direct) < 1e-10
 
 
+def test_block_lanczos_tridiagonal_and_exact():
+    # the recurrence's T is Q^T A A^T Q itself (block tridiagonal: the
+    # entries outside the band vanish), and Q is orthonormal
+    sv = workloads.spectrum("inv", 60)
+    A = workloads.planted_dense(90, 60, sv, seed=24)
+    Pi = philox.gaussian(25, 60, 4)
+    r, T = bki.block_lanczos(A, Pi, 4, 5)
+    M = r.Q.T @ (A @ (A.T @ r.Q))
+    assert np.max(np.abs(M - T)) < 1e-13
+    assert np.max(np.abs(r.Q.T @ r.Q - np.eye(24))) < 1e-13
+    band = np.abs(np.subtract.outer(np.arange(24) // 4, np.arange(24) // 4)) > 1
+    assert np.all(T[band] == 0.0) and np.max(np.abs(M[band])) < 1e-13
+    # its span is the literal Krylov space of Algorithm 2 (route B's K)
+    Kq = bki.block_krylov_route_b(A, Pi, 4, 2).Q
+    r2, _ = bki.block_lanczos(A, Pi, 4, 2)
+    assert metrics.principal_angle(Kq, r2.Q) < 1e-9
+    # brute force: a rank-12 A with (q+1) k = 12 recovers the exact top k
+    sig = np.linspace(3.0, 1.0, 12)
+    B = workloads.planted_dense(50, 40, sig, seed=26)
+    rb, _ = bki.block_lanczos(B, philox.gaussian(27, 40, 4), 4, 2)
+    assert np.allclose(rb.sigma, sig[:4], rtol=1e-12)
+    U = np.linalg.svd(B)[0][:, :4]
+    assert metrics.principal_angle(rb.Z, U) < 1e-10
+
+
+def test_block_lanczos_breakdown_and_centring():
+    k = 4
+    sig = np.linspace(4.0, 1.0, 2 * k)
+    A = workloads.planted_dense(60, 45, sig, seed=28)
+    r, T = bki.block_lanczos(A, philox.gaussian(29, 45, k), k, 4)
+    assert r.q_eff == 1 and T.shape == (2 * k, 2 * k)
+    assert np.allclose(r.sigma, sig[:k], rtol=1e-12)
+    rp, ci, va = workloads.term_document_csr(200, 900, seed=30, median_len=15)
+    M = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(200, 900))
+    Ac = M.toarray() - M.toarray().mean(axis=1, keepdims=True)
+    Pi = philox.gaussian(31, 900, 5)
+    r1, _ = bki.block_lanczos(M, Pi, 5, 3, center=True)
+    r2, _ = bki.block_lanczos(Ac, Pi, 5, 3)
+    assert np.allclose(r1.sigma, r2.sigma, rtol=1e-11)
+    assert metrics.principal_angle(r1.Z, r2.Z) < 1e-8
+
+
 def test_sign_normalization():
     Z = np.array([[0.6, -0.8], [-0.8, 0.6]])
     out = bki.sign_normalize(Z)
