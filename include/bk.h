@@ -101,17 +101,27 @@ typedef struct bk_options {
                                 (BK_METHOD_BLOCK_KRYLOV) or p (simultaneous
                                 iteration); needs save_for_backward = 0 when
                                 p != k                                      */
-  int32_t method;            /* BK_METHOD_BLOCK_KRYLOV (0, Algorithm 2) or
+  int32_t method;            /* BK_METHOD_BLOCK_KRYLOV (0, Algorithm 2),
                                 BK_METHOD_SIMULTANEOUS (1, Algorithm 1: the
                                 block is replaced by orth(A A^T block) q
-                                times, Rayleigh-Ritz on the last one)       */
+                                times, Rayleigh-Ritz on the last one) or
+                                BK_METHOD_BLOCK_LANCZOS (2, Section 4.2:
+                                the Krylov basis of Algorithm 2, with
+                                Q^T A A^T Q taken as the block-tridiagonal
+                                matrix of the block Lanczos recurrence --
+                                diagonal blocks from the projection
+                                coefficients, sub-diagonal blocks from the
+                                R factors -- instead of the product W^T W;
+                                every block is still reorthogonalized
+                                against all earlier ones; not with
+                                save_for_backward)                          */
   int32_t timing_phases;     /* with timing = 1: bitmask of the BK_PH_*
                                 phases given events (1 << BK_PH_AX | ...);
                                 0 = all.  Launch counts are kept for all.   */
   int32_t reserved[2];
 } bk_options;
 
-enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1 };
+enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1, BK_METHOD_BLOCK_LANCZOS = 2 };
 
 /* Phases of bk_info.ms[] / launches[]. */
 enum {

@@ -42,7 +42,8 @@ def _dtype_code(t: torch.Tensor) -> int:
     raise TypeError(f"unsupported matrix dtype {t.dtype}")
 
 
-_METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1}
+_METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1, "lanczos": 2,
+            "block_lanczos": 2}
 
 
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,

@@ -50,6 +50,7 @@ struct Options {
   int timing_phases = 0;  // bitmask of timed phases (0: all)
   int p = 0;   // block width (0: k), oversampling of Section 6
   int si = 0;  // 1: simultaneous iteration (Algorithm 1)
+  int bl = 0;  // 1: block-tridiagonal Rayleigh-Ritz matrix (block Lanczos)
   double jtol = 0.0, tau = 0.0;
   const void* pi = nullptr;
 };
@@ -68,6 +69,7 @@ Options read_options(const bk_options* o, bool f64) {
     r.jblock = o->jacobi_block;
     r.p = o->block_size;
     r.si = o->method == BK_METHOD_SIMULTANEOUS ? 1 : 0;
+    r.bl = o->method == BK_METHOD_BLOCK_LANCZOS ? 1 : 0;
     if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, reserved)))
       r.timing_phases = o->timing_phases;
   }
@@ -87,6 +89,7 @@ int jacobi_block_for(int64_t m, int user) {
 int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) {
   const int64_t m = static_cast<int64_t>(q + 1) * k;
   int64_t need = std::max<int64_t>(tn_partial_elems(n, k, k), tn_partial_elems(d, m, static_cast<int>(m)));
+  need = std::max(need, tn_partial_elems(d, k, k));  // the last block's Gram (block Lanczos)
   if (!csr) need = std::max(need, tn_partial_elems(n, d, k));
   // projection of block i: [Q_<i, B]^T B (i + 1) k x k, then Q_<i^T B
   for (int i = 1; i <= q + 1; ++i)
@@ -159,6 +162,9 @@ struct Layout {
   double* sign = nullptr;
   double* Rsave = nullptr;  // (q+1) x k x k, R_i of B_i = Q_i R_i (saved)
   double* ritz_dev = nullptr;
+  // block Lanczos: per-block projection coefficients (two passes, stride
+  // m k) and CholeskyQR factors (three passes), scratch, the last block
+  double *Cband = nullptr, *Rband = nullptr, *Pband = nullptr, *Tqq = nullptr;
   // refinement
   float* Wk = nullptr;
   double* Gk = nullptr;
@@ -212,6 +218,12 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
   if (use_tridiag(m, o)) L.tri = ar.take<double>(static_cast<size_t>(tridiag_scratch_doubles(m, k)));
   L.sign = ar.take<double>(static_cast<size_t>(k));
   L.ritz_dev = ar.take<double>(static_cast<size_t>(k));
+  if (o.bl && !o.si) {
+    L.Cband = ar.take<double>(2 * static_cast<size_t>(q + 1) * static_cast<size_t>(m * k));
+    L.Rband = ar.take<double>(3 * static_cast<size_t>(q + 1) * kk);
+    L.Pband = ar.take<double>(static_cast<size_t>(q + 1) * kk);
+    L.Tqq = ar.take<double>(kk);
+  }
   if (o.save) L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
   if (o.refine) {
     L.Wk = ar.take<float>(static_cast<size_t>(d * k));
@@ -612,6 +624,8 @@ struct Solver {
     for (int pass = 0; pass < 3; ++pass) {
       void* src = bufs[pass];
       const int64_t ls = lds[pass];
+      // block Lanczos keeps every pass's factor (the sub-diagonal blocks)
+      double* R = L->Rband ? L->Rband + (3 * static_cast<size_t>(i) + pass) * k * k : L->R;
       if (pass == 0 ? !have_gram : !fuse) nl += gram(src, ls, k, src, ls, k, n, L->G);
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
       if (fuse) {
@@ -625,7 +639,7 @@ struct Solver {
         a.block = i;
         a.tau = o.tau;
         a.shift_coef = shift_coef;
-        a.R = L->R;
+        a.R = R;
         a.ctrl = L->ctrl;
         a.X = src;
         a.ldx = ls;
@@ -638,16 +652,16 @@ struct Solver {
         gin = part[pass & 1];
         P = cqr_pass_grid(n, nullptr);
       } else {
-        launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, L->R, L->Rinv, L->cholwork,
+        launch_chol(k, L->G, gpre, mode, i, o.tau, shift_coef, R, L->Rinv, L->cholwork,
                     L->ctrl, s);
         ++nl;
         nl += apply(src, ls, n, k, L->Rinv, k, k, bufs[pass + 1], lds[pass + 1], 1.0, 0.0);
       }
       if (o.save) {
         if (pass == 0) {
-          launch_copy2d(L->R, true, k, L->Racc, true, k, k, k, s);
+          launch_copy2d(R, true, k, L->Racc, true, k, k, k, s);
         } else {
-          launch_trmm_upper(k, L->R, L->Racc, L->Rtmp, s);
+          launch_trmm_upper(k, R, L->Racc, L->Rtmp, s);
           launch_copy2d(L->Rtmp, true, k, L->Racc, true, k, k, k, s);
         }
       }
@@ -669,13 +683,16 @@ struct Solver {
     const int64_t p = static_cast<int64_t>(i) * k;
     void* B = qslab(i);
     const bool fuse = fuse_gram();
-    int nl = gram(L->Q, m, p + k, B, m, k, n, L->C);  // rows p.. : B^T B
-    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0);
-    nl += gram(L->Q, m, p, B, m, k, n, L->C);           // rows 0 .. p-1 only
-    nl += apply(L->Q, m, n, p, L->C, k, k, B, m, -1.0, 1.0, fuse ? L->partial : nullptr);
+    // block Lanczos keeps both passes' coefficients of every block
+    double* C1 = L->Cband ? L->Cband + 2 * static_cast<size_t>(i) * m * k : L->C;
+    double* C2 = L->Cband ? C1 + static_cast<size_t>(m) * k : L->C;
+    int nl = gram(L->Q, m, p + k, B, m, k, n, C1);  // rows p.. : B^T B
+    nl += apply(L->Q, m, n, p, C1, k, k, B, m, -1.0, 1.0);
+    nl += gram(L->Q, m, p, B, m, k, n, C2);         // rows 0 .. p-1 only
+    nl += apply(L->Q, m, n, p, C2, k, k, B, m, -1.0, 1.0, fuse ? L->partial : nullptr);
     if (fuse) nl += launch_gram_reduce(n, k, L->partial, L->G, s);
     tm->end(nl);
-    return L->C + p * k;
+    return C1 + p * k;
   }
 
   // Eigen-solve of the FP64 symmetric PSD `Mat` (mm x mm): top `kk`
@@ -806,11 +823,21 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
 
   // Step 4: M = W^T W = Q^T A A^T Q in FP64.
   tm.begin(BK_PH_M);
-  // narrow FP32 W: matrix-core tiles of the upper triangle
-  int mlaunch = f64 ? 0
-                    : launch_gram_sym_mfma(d, static_cast<int>(m), static_cast<const float*>(L.W),
-                                           m, L.M, m, L.partial, s);
-  if (!mlaunch) mlaunch = S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M, 1.0, 0.0, true);
+  int mlaunch = 0;
+  if (L.Cband) {
+    // block Lanczos: the block-tridiagonal T from the recurrence's own
+    // coefficients; only the last diagonal block needs a product
+    mlaunch = S.gram(S.wslab(q), m, pw, S.wslab(q), m, pw, d, L.Tqq, 1.0, 0.0, true);
+    mlaunch += launch_block_tridiag(m, pw, q, L.Cband, m * pw, L.Rband, L.Pband, L.Tqq, L.M, m,
+                                    s);
+  } else {
+    // narrow FP32 W: matrix-core tiles of the upper triangle
+    mlaunch = f64 ? 0
+                  : launch_gram_sym_mfma(d, static_cast<int>(m), static_cast<const float*>(L.W),
+                                         m, L.M, m, L.partial, s);
+    if (!mlaunch)
+      mlaunch = S.gram(L.W, m, m, L.W, m, static_cast<int>(m), d, L.M, 1.0, 0.0, true);
+  }
   tm.end(mlaunch);
   BK_TRY_LAUNCH();
 
@@ -1093,7 +1120,7 @@ int32_t block_width(int64_t n, int64_t d, int32_t k, int32_t q, const Options& o
   const int32_t p = o.p > 0 ? o.p : k;
   if (p < k || p > std::min(n, d)) return 0;
   if (!o.si && static_cast<int64_t>(q + 1) * p > std::min(n, d)) return 0;
-  if (o.save && (p != k || o.si)) return 0;
+  if (o.save && (p != k || o.si || o.bl)) return 0;
   return p;
 }
 

@@ -144,6 +144,15 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode,
 // T = A . B for k x k upper-triangular FP64 matrices (one workgroup).
 void launch_trmm_upper(int k, const double* A, const double* B, double* T,
                        hipStream_t s);
+// The block-tridiagonal Q^T A A^T Q of block Lanczos into M (m x m, ld
+// ldm), m = (q+1) k: diagonal blocks from the two projection passes' FP64
+// coefficients (block i's pass-j coefficients at Cband + (2 i + j) cstride,
+// ld k) and Tqq (the last block), sub-diagonal blocks R3 R2 R1 from the
+// CholeskyQR factors (block i's pass j at Rband + (3 i + j) k^2); P holds
+// (q+1) k^2 doubles of scratch.  Returns the kernels launched.
+int launch_block_tridiag(int64_t m, int k, int q, const double* Cband, int64_t cstride,
+                         const double* Rband, double* P, const double* Tqq, double* M,
+                         int64_t ldm, hipStream_t s);
 // One CholeskyQR pass for k <= kCqrPassMaxK in one launch: G = the sum of
 // the P FP64 Gram partials Gin (k x k each), R = chol(G [+ shift]) under
 // the modes of launch_chol (R written, ctrl updated), Y = X R^-1 by

@@ -85,6 +85,12 @@ def test_block_size_and_method_rules(lib):
     o.save_for_backward = 1                               # no adjoint for Algorithm 1
     assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) == 0
     o = _opt()
+    o.method = 2                                          # block Lanczos: T's blocks kept
+    bl = lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o))
+    assert bl > base
+    o.save_for_backward = 1                               # no adjoint for it either
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) == 0
+    o = _opt()
     o.block_size = 30
     assert lib.bk_svd_csr_workspace(11000, 130000, 1_500_000, 20, 10, C.byref(o)) > \
         lib.bk_svd_csr_workspace(11000, 130000, 1_500_000, 20, 10, C.byref(_opt()))
