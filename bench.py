@@ -1,7 +1,8 @@
 """Benchmark of the Block Krylov hot path on one MI355X.
 
 A step is one whole solve (sketch, Krylov products, projection,
-CholeskyQR, M = W^T W, Jacobi eigen-solve, Z = Q U_k) on one synthetic input
+CholeskyQR, M = W^T W -- or the block-tridiagonal T of block Lanczos with
+--method lanczos --, the eigen-solve, Z = Q U_k) on one synthetic input
 already resident in HBM.  Default workload: the term-document CSR matrix
 (11000 x 130000, ~1.47M nonzeros, log-normal row lengths, Zipf(1.1) terms,
 log(1+tf)*idf values), k = 20, q = 10, implicit row centring, FP32.
@@ -109,6 +110,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
+    ap.add_argument("--method", default="bki", choices=["bki", "lanczos"],
+                    help="Rayleigh-Ritz matrix: W^T W (Algorithm 2) or the block-tridiagonal "
+                         "T of the block Lanczos recurrence (Section 4.2)")
+    ap.add_argument("--metrics-q", type=int, default=4, metavar="Q",
+                    help="depth of the GPU spectral-residual estimate of the error measures "
+                         "taken after the timed steps (-1: skip them)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the reference "
                          "kernel that scales the HBM byte counters) and exit")
@@ -156,7 +163,12 @@ def main():
 
         def step(timing):
             return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
-                              center=w.center, transpose=tr, timing=timing)
+                              center=w.center, transpose=tr, timing=timing,
+                              method=args.method)
+
+        def error_measures(Z, qs):
+            return bk.error_metrics_csr(g_rp, g_ci, g_va, w.n, w.d, Z, q_spec=qs,
+                                        seed=w.seed_sketch + 1, center=w.center, transpose=tr)
         kern_src = ["csr.hip"]
         kern_names = {"ax": "csr_product_kernel (A.X, CSR of A)",
                       "aty": "csr_product_kernel (A^T.Y, CSR of A^T)"}
@@ -196,7 +208,12 @@ def main():
         bx, by = dense_product_bytes(w.n, w.d, k, a_bytes, x_bytes)
 
         def step(timing):
-            return bk.svd_dense(A_in, k, q, seed=w.seed_sketch, timing=timing, **kw)
+            return bk.svd_dense(A_in, k, q, seed=w.seed_sketch, timing=timing,
+                                method=args.method, **kw)
+
+        def error_measures(Z, qs):
+            return bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), q_spec=qs,
+                                          seed=w.seed_sketch + 1)
         kern_src = ["gemm.hip", "gemm_mfma.hip"]
         kern_names = {"ax": "A.X product (operand pack + product kernel)",
                       "aty": "A^T.Y product (operand pack + product kernel + split reduction)"}
@@ -276,7 +293,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}",
                    "n": w.n, "d": w.d, "k": k, "q": q,
-                   "precision": args.precision,
+                   "precision": args.precision, "method": args.method,
                    "product_bytes_per_solve": int(bytes_per_solve)},
         "roofline": roof,
         "phases_ms_per_step": {p: round(v, 4) for p, v in ph.items()},
@@ -286,10 +303,31 @@ def main():
         "jacobi_sweeps": infos[-1]["jacobi_sweeps"],
     }
 
+    if args.metrics_q >= 0:
+        out["error_measures"] = gpu_error_measures(error_measures, r.Z, args.metrics_q)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(args, w, host_inputs, r,
                                                           bytes_per_solve)
     print(json.dumps(out), flush=True)
+
+
+def gpu_error_measures(fn, Z, qs):
+    """eqs. (1)-(3) quantities of the last solve's Z on the GPU (Section 3):
+    ||Abar||_F^2, the Frobenius residual (Pythagoras), the spectral residual
+    (block Krylov on (I - Z Z^T) Abar, depth qs); no true spectrum at this
+    size, so the ratios are not formed.  Wall time of one call (it
+    synchronizes), after a warm-up call."""
+    import torch
+    fn(Z, qs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = fn(Z, qs)
+    ms = (time.perf_counter() - t0) * 1e3
+    v = m.values
+    return {"fro2": v["fro2"], "resid_fro": v["resid_fro"], "resid_spec": v["resid_spec"],
+            "captured_fro2": v["captured_fro2"], "q_spec": qs, "ms": round(ms, 3),
+            "status": m.status}
 
 
 def products_all_kernels(ph, q_eff, bx, by):
