@@ -146,3 +146,43 @@ def test_metrics_exact_basis_reaches_optimum():
     assert abs(v["fro_ratio"] - 1.0) < 1e-10
     assert abs(v["spec_ratio"] - 1.0) < 1e-6
     assert v["per_vector"] < 1e-10
+
+
+def test_metrics_csr_term_document_full_size():
+    """The 11000 x 130000 term-document workload (k = 20, q = 10, centred):
+    ||Abar||_F^2, the captured energies and the Frobenius residual against the
+    oracle's sparse definitions; the spectral residual against ARPACK's top
+    singular value of the implicit residual operator (a library routine on
+    the oracle's products), as a lower bound that q_spec = 10 brings within
+    1e-3."""
+    from scipy.sparse.linalg import LinearOperator as SpOp, svds
+    from oracle import bki
+    w = workloads.WORKLOADS["csr2"]
+    (rp, ci, va), M = _termdoc(w.n, w.d, w.seed_matrix, median=90.0)
+    op = bki.LinearOperator(M, center=True)
+    g = (_cuda(rp), _cuda(ci), _cuda(va))
+    Z = bk.svd_csr(*g, w.n, w.d, w.k, w.q, seed=w.seed_sketch, center=True).Z
+    res = bk.error_metrics_csr(*g, w.n, w.d, Z, q_spec=10, seed=5, center=True)
+    assert res.status == 0
+    v = res.values
+    Zh = Z.cpu().numpy().astype(np.float64)
+    fro2 = metrics.frobenius_sq(op)
+    cap = metrics.captured(op, Zh)
+    assert abs(v["fro2"] - fro2) <= 1e-12 * fro2
+    np.testing.assert_allclose(res.captured.numpy(), cap, rtol=1e-5, atol=0)
+    assert abs(v["resid_fro"] ** 2 - (fro2 - cap.sum())) <= 1e-5 * fro2
+
+    def rmul(x):
+        y = op.mul(x.reshape(w.d, -1))
+        return y - Zh @ (Zh.T @ y)
+
+    def rtmul(y):
+        y = y.reshape(w.n, -1)
+        return op.tmul(y - Zh @ (Zh.T @ y))
+
+    R = SpOp((w.n, w.d), matvec=rmul, rmatvec=rtmul, matmat=rmul, rmatmat=rtmul,
+             dtype=np.float64)
+    spec = svds(R, k=1, tol=1e-12, return_singular_vectors=False,
+                random_state=np.random.default_rng(3))[0]
+    assert v["resid_spec"] <= spec * (1 + 1e-6)
+    assert v["resid_spec"] >= spec * (1 - 1e-3)
