@@ -178,6 +178,16 @@ __global__ __launch_bounds__(256) void nn_smallk_kernel(
   const int t = threadIdx.x;
   const int64_t row0 = static_cast<int64_t>(blockIdx.x) * NN_BM;
   const int64_t rlast = n - 1;
+  const int tx = t & 7, ty = t >> 3;
+  // this thread's outputs C[row0 + 2 ty + i][4 tx + j] for the beta term,
+  // requested with the operands (clamped, in-bounds addresses, loaded
+  // unconditionally; the values are used only when beta != 0)
+  float cpre[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      cpre[i][j] = C[min(row0 + ty * 2 + i, rlast) * ldc + min(tx * 4 + j, N - 1)];
   {
     // A: VEC: 64 x K / 4 float4 (at most 16 per thread); else 64 x K
     // floats (at most 64 per thread)
@@ -228,7 +238,6 @@ __global__ __launch_bounds__(256) void nn_smallk_kernel(
     }
   }
   __syncthreads();
-  const int tx = t & 7, ty = t >> 3;
   float acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(256) void nn_smallk_kernel(
       const int gc = tx * 4 + j;
       if (gc >= N) continue;
       float v = alpha * acc[i][j];
-      if (beta != 0.f) v += beta * C[gr * ldc + gc];
+      if (beta != 0.f) v += beta * cpre[i][j];
       C[gr * ldc + gc] = v;
       acc[i][j] = v;
     }
