@@ -657,6 +657,11 @@ void launch_colsum(const float* X, int64_t ldx, int64_t L, int k, const float* w
   colsum_final_kernel<<<1, 256, 0, s>>>(colpart, nb, k, kc_for(k), colvec);
 }
 
+void launch_colsum_final(const double* colpart, int nb, int k, double* colvec, hipStream_t s) {
+  if (k <= 0) return;
+  colsum_final_kernel<<<1, 256, 0, s>>>(colpart, nb, k, kc_for(k), colvec);
+}
+
 void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s) {
   scan_kernel<<<1, 1024, 0, s>>>(cnt, n, out);
 }

@@ -345,6 +345,11 @@ struct Op {
                          hipStream_t s) {
     ax(X, ldx, k, Y, ldy, s);
   }
+  // Row weights whose weighted column sums w^T X the next aty needs (null:
+  // none), and the block partials of them for the X of that next aty, when
+  // the orthonormalization that wrote X formed them (nb x k, consumed once).
+  virtual const float* aty_row_weights() const { return nullptr; }
+  virtual void set_aty_partials(const double*, int) {}
 };
 
 struct DenseOp : Op {
@@ -421,12 +426,17 @@ struct CsrOp : Op {
   void product(const int32_t* r_, const int32_t* c_, const float* v_, const CsrPlan& pl,
                int phase, const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
                const float* rowvec, const float* colw, int64_t Lc, hipStream_t s,
-               bool exact = false) {
+               bool exact = false, const double* part = nullptr, int nb = 0) {
     if (exact) rowvec = nullptr;
     if (mu && !exact) {
       tm->begin(BK_PH_CENTER);
-      launch_colsum(static_cast<const float*>(X), ldx, Lc, k, colw, colpart, colvec, s);
-      tm->end(2);
+      if (part) {  // the partials came with X
+        launch_colsum_final(part, nb, k, colvec, s);
+        tm->end(1);
+      } else {
+        launch_colsum(static_cast<const float*>(X), ldx, Lc, k, colw, colpart, colvec, s);
+        tm->end(2);
+      }
     }
     tm->begin(phase);
     launch_csr_product(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
@@ -439,6 +449,13 @@ struct CsrOp : Op {
       tm->end(1);
     }
   }
+  const double* pre_part = nullptr;  // block partials of mu^T X for the next aty
+  int pre_nb = 0;
+  const float* aty_row_weights() const override { return mu; }
+  void set_aty_partials(const double* part, int nb) override {
+    pre_part = part;
+    pre_nb = nb;
+  }
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s);
   }
@@ -447,7 +464,9 @@ struct CsrOp : Op {
     product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s, true);
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
-    product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s);
+    product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s, false,
+            pre_part, pre_nb);
+    pre_part = nullptr;
   }
 };
 
@@ -614,6 +633,7 @@ struct Solver {
     void* bufs[4] = {B, L->Bs2, fuse ? qslab(slab) : L->Bs, qslab(slab)};
     const int64_t lds[4] = {ldb, k, fuse ? m : k, m};
     const double unit = f64 ? 0x1p-53 : 0x1p-24;
+    const float* muw = (fuse && !f64) ? op->aty_row_weights() : nullptr;
     int nl = 0;
     // k <= 32: each pass is one launch that adds the previous pass's Gram
     // partials, factors, solves the rows against R (no R^-1) and leaves the
@@ -648,6 +668,12 @@ struct Solver {
         a.f64 = f64;
         a.gout = pass < 2 ? part[pass & 1] : nullptr;
         a.skip_tol = pass == 2 ? 64.0 * unit : 0.0;
+        // the last two passes write the final block (the third may skip
+        // itself): both leave the partials of mu^T Q_i for the next aty
+        if (pass >= 1 && muw) {
+          a.mu = muw;
+          a.mupart = L->colpart;
+        }
         nl += launch_cqr_pass(a, s);
         gin = part[pass & 1];
         P = cqr_pass_grid(n, nullptr);
@@ -669,6 +695,7 @@ struct Solver {
     if (o.save)
       launch_copy2d(L->Racc, true, k, L->Rsave + static_cast<size_t>(i) * k * k, true, k, k,
                     k, s);
+    if (muw) op->set_aty_partials(L->colpart, cqr_pass_grid(n, nullptr));
     tm->end(nl + (o.save ? 6 : 0));
   }
 

@@ -180,6 +180,11 @@ struct CqrPass {
   // > 0: when max |G - I| <= skip_tol the pass leaves X as it is (R = I);
   // then X must be Y (in place)
   double skip_tol = 0.0;
+  // nullable: mupart[b k + c] = sum over workgroup b's rows r of
+  // mu[r] Y[r][c] (FP64, the stored values): the block partials of mu^T Y
+  // that launch_colsum_final adds up (a skipped pass writes none)
+  const float* mu = nullptr;
+  double* mupart = nullptr;
 };
 int cqr_pass_grid(int64_t n, int64_t* rows_per_wg);
 int64_t cqr_pass_partial_elems(int k);
@@ -299,6 +304,8 @@ constexpr int kColsumBlocks = 256;
 int colsum_blocks(int64_t L);
 void launch_colsum(const float* X, int64_t ldx, int64_t L, int k, const float* w,
                    double* colpart, double* colvec, hipStream_t s);
+// colvec = the sum of nb block partials (nb x k), in block order
+void launch_colsum_final(const double* colpart, int nb, int k, double* colvec, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (one workgroup)
 void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s);
 void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,

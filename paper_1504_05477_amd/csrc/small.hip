@@ -905,7 +905,7 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
     int64_t n, int k, const double* __restrict__ Gin, int P, const double* __restrict__ Gpre,
     int mode, int block, double tau, double shift_coef, double* __restrict__ R, Ctrl* ctrl,
     const T* X, int64_t ldx, T* Y, int64_t ldy, int64_t rows_per_wg, double* __restrict__ gout,
-    double skip_tol) {
+    double skip_tol, const float* __restrict__ mu, double* __restrict__ mupart) {
   constexpr int LD = K + 1;
   constexpr int TPR = (K == 24) ? 32 : K;  // threads per row in the tile copies
   constexpr int RPI = 256 / TPR;           // rows per copy step
@@ -923,6 +923,7 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
   __shared__ double pd[K];
   __shared__ double rb[128];
   __shared__ double Ys[CQR_ROWS * LD];
+  __shared__ double mus[CQR_ROWS];
   const int t = threadIdx.x;
   const int kk = k * k;
   const int gc = t % TPR, gr = t / TPR;  // copy layout
@@ -1068,9 +1069,13 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
   for (int x = 0; x < GB; ++x)
 #pragma unroll
     for (int z = 0; z < GB; ++z) acc[x][z] = 0.0;
+  // mu^T Y: lane c of wavefront w sums column c over rows [64 w, 64 w + 64)
+  double musum = 0.0;
+  const int mc = t & 63;
   for (int64_t r0 = lo; r0 < hi; r0 += CQR_ROWS) {
     const int rows = static_cast<int>(hi - r0 < CQR_ROWS ? hi - r0 : CQR_ROWS);
     if (r0 != lo) fetch(r0, rows);
+    if (mupart) mus[t] = t < rows ? static_cast<double>(mu[r0 + t]) : 0.0;
     stage();
     __syncthreads();
     double y[K];
@@ -1118,6 +1123,11 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
         if (gc < k && r < rows) Y[(r0 + r) * ldy + gc] = static_cast<T>(Ys[r * LD + gc]);
       }
     }
+    if (mupart && mc < k) {
+      // rows past the chunk have mus = 0 (Ys holds whatever was staged)
+#pragma unroll 8
+      for (int r = 64 * w; r < 64 * w + 64; ++r) musum += mus[r] * Ys[r * LD + mc];
+    }
     if (gout) {
 #pragma unroll 8
       for (int r = 64 * w; r < 64 * w + 64; ++r) {
@@ -1134,6 +1144,15 @@ __global__ __launch_bounds__(256) void cqr_pass_kernel(
       }
     }
     __syncthreads();
+  }
+  if (mupart) {
+    // the four wavefronts' sums in wavefront order (rb is free after the
+    // factor: 4 x 32 doubles)
+    if (mc < k) rb[w * 32 + mc] = musum;
+    __syncthreads();
+    if (t < k)
+      mupart[static_cast<int64_t>(blockIdx.x) * k + t] =
+          ((rb[t] + rb[32 + t]) + rb[64 + t]) + rb[96 + t];
   }
   if (!gout) return;
   // the four wavefronts' sums, added in wavefront order
@@ -1161,12 +1180,12 @@ void cqr_pass_launch(unsigned grid, const CqrPass& a, hipStream_t s) {
     cqr_pass_kernel<T, K, true><<<grid, 256, 0, s>>>(
         a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
         static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout,
-        a.skip_tol);
+        a.skip_tol, a.mu, a.mupart);
   else
     cqr_pass_kernel<T, K, false><<<grid, 256, 0, s>>>(
         a.n, a.k, a.Gin, a.P, a.Gpre, a.mode, a.block, a.tau, a.shift_coef, a.R, a.ctrl,
         static_cast<const T*>(a.X), a.ldx, static_cast<T*>(a.Y), a.ldy, a.rows_per_wg, a.gout,
-        a.skip_tol);
+        a.skip_tol, a.mu, a.mupart);
 }
 }  // namespace
 
