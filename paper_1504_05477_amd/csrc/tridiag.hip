@@ -371,15 +371,23 @@ __device__ __forceinline__ double recip_f64(double q) {
   return fma(r, e, r);
 }
 
-// Number of eigenvalues of T below x (Sturm sequence of the LDL^T pivots,
-// q_i = d_i - x - e_{i-1}^2 / q_{i-1}, a pivot smaller than pivmin replaced
-// by -pivmin).  The diagonal and e^2 are read eight at a time ahead of the
-// dependent chain.
+// Number of eigenvalues of T below x, from the signs of the leading
+// principal minors a_i of T - x I: a_i = (d_i - x) a_{i-1} - e_{i-1}^2 a_{i-2}
+// (a_{-1} = 1), whose ratios a_i / a_{i-1} are the LDL^T pivots, so a pivot
+// is negative exactly where consecutive minors change sign.  A pivot of
+// magnitude below pivmin is replaced by -pivmin (a_i = -pivmin a_{i-1}) and
+// so counted.  No division: one fma, a compare and a select per step on the
+// dependency chain (e^2 a_{i-2} is formed a step ahead).  The minors are
+// rescaled by a power of two every eight steps (exact); T must be scaled so
+// that its entries are at most about 1, so that eight steps cannot overflow.
+// The diagonal and e^2 are read eight at a time ahead of the chain.
 __device__ int sturm_count(const double* dg, const double* e2, int64_t m, double x,
                            double pivmin) {
-  int cnt = 0;
-  double q = dg[0] - x;
-  if (q < 0.0) ++cnt;
+  double ap = 1.0;
+  double a = dg[0] - x;
+  if (fabs(a) < pivmin) a = -pivmin;
+  bool sg = a < 0.0;
+  int cnt = sg ? 1 : 0;
   int64_t i = 1;
   for (; i + 8 <= m; i += 8) {
     double dd[8], ee[8];
@@ -390,15 +398,27 @@ __device__ int sturm_count(const double* dg, const double* e2, int64_t m, double
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (fabs(q) < pivmin) q = -pivmin;
-      q = fma(-ee[u], recip_f64(q), dd[u]);
-      cnt += q < 0.0 ? 1 : 0;
+      double an = fma(dd[u], a, -ee[u] * ap);
+      if (fabs(an) < pivmin * fabs(a)) an = -pivmin * a;
+      ap = a;
+      a = an;
+      const bool sn = a < 0.0;
+      cnt += (sn != sg) ? 1 : 0;
+      sg = sn;
     }
+    int ex;
+    (void)frexp(a, &ex);
+    a = ldexp(a, -ex);
+    ap = ldexp(ap, -ex);
   }
   for (; i < m; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = fma(-e2[i - 1], recip_f64(q), dg[i] - x);
-    cnt += q < 0.0 ? 1 : 0;
+    double an = fma(dg[i] - x, a, -e2[i - 1] * ap);
+    if (fabs(an) < pivmin * fabs(a)) an = -pivmin * a;
+    ap = a;
+    a = an;
+    const bool sn = a < 0.0;
+    cnt += (sn != sg) ? 1 : 0;
+    sg = sn;
   }
   return cnt;
 }
@@ -537,15 +557,21 @@ __global__ __launch_bounds__(BS_THREADS) void tridiag_bisect_kernel(
   double* dg = sm;
   double* e2 = sm + m;
   const int t = threadIdx.x, c = blockIdx.x;
-  for (int64_t i = t; i < m; i += BS_THREADS) {
-    dg[i] = dgg[i];
-    const double e = (i + 1 < m) ? eog[i] : 0.0;
-    e2[i] = e * e;
-  }
   double gl, gu, tnorm;
   tri_gershgorin(dgg, eog, m, BS_THREADS, red, &gl, &gu, &tnorm);
+  // the Sturm counts run on T sc, sc a power of two with |T sc| <= 1 (exact
+  // scaling: the counts are those of T at the unscaled points)
+  int tex = 0;
+  (void)frexp(tnorm > 0.0 ? tnorm : 1.0, &tex);
+  const double sc = ldexp(1.0, -tex);
+  for (int64_t i = t; i < m; i += BS_THREADS) {
+    dg[i] = dgg[i] * sc;
+    const double e = (i + 1 < m) ? eog[i] * sc : 0.0;
+    e2[i] = e * e;
+  }
+  __syncthreads();
   const double pad = 2.2e-16 * tnorm * 4.0 + 1e-300;
-  const double pivmin = 1e-290 + 2.2e-16 * 2.2e-16 * tnorm * tnorm * 1e-10;
+  const double pivmin = (1e-290 + 2.2e-16 * 2.2e-16 * tnorm * tnorm * 1e-10) * sc;
   const int P = BS_THREADS;
   auto settled = [&](double l, double h) {
     return h - l <= 2.2e-16 * fmax(fabs(l), fabs(h)) * 2.0 + 1e-18 * tnorm + 1e-300;
@@ -563,7 +589,7 @@ __global__ __launch_bounds__(BS_THREADS) void tridiag_bisect_kernel(
   for (int it = 0; it < 200; ++it) {
     const double l = s_lo, h = s_hi;
     if (settled(l, h)) break;  // (uniform)
-    if (sturm_count(dg, e2, m, point(l, h, t), pivmin) <= target) atomicMax(&s_best, t);
+    if (sturm_count(dg, e2, m, point(l, h, t) * sc, pivmin) <= target) atomicMax(&s_best, t);
     __syncthreads();
     if (t == 0) {
       const int b = s_best;
