@@ -167,6 +167,7 @@ __global__ __launch_bounds__(256) void nn_vsplit_reduce_kernel(int64_t n, int N,
 // 32-wide chunk), staged in LDS, then multiplied; the epilogue is
 // nn_kernel's (alpha, beta, optional Gram partial of the stored rows).
 constexpr int NS_KMAX = 256;
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
 template <bool VEC>
 __global__ __launch_bounds__(256) void nn_smallk_kernel(
@@ -175,19 +176,23 @@ __global__ __launch_bounds__(256) void nn_smallk_kernel(
     float alpha, float beta, double* __restrict__ gpart) {
   __shared__ float As[NS_KMAX][NN_BM + 1];
   __shared__ float Xs[NS_KMAX][NN_BN];
+  __shared__ float Cs[2][16 * 64];
   const int t = threadIdx.x;
   const int64_t row0 = static_cast<int64_t>(blockIdx.x) * NN_BM;
   const int64_t rlast = n - 1;
-  const int tx = t & 7, ty = t >> 3;
-  // this thread's outputs C[row0 + 2 ty + i][4 tx + j] for the beta term,
+  // the beta term of this lane's outputs (see the epilogue: rows
+  // 32 (w & 1) + 8 (v >> 2) + 4 (lane >> 5) + (v & 3), column lane & 31),
   // requested with the operands (clamped, in-bounds addresses, loaded
   // unconditionally; the values are used only when beta != 0)
-  float cpre[2][4];
+  float cpre[16];
+  {
+    const int wv = t >> 6, ln = t & 63;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      cpre[i][j] = C[min(row0 + ty * 2 + i, rlast) * ldc + min(tx * 4 + j, N - 1)];
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gr = row0 + 32 * (wv & 1) + 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
+      cpre[v] = C[min(gr, rlast) * ldc + min(ln & 31, N - 1)];
+    }
+  }
   {
     // A: VEC: 64 x K / 4 float4 (at most 16 per thread); else 64 x K
     // floats (at most 64 per thread)
@@ -237,46 +242,58 @@ __global__ __launch_bounds__(256) void nn_smallk_kernel(
       if (e < nx) Xs[e >> 5][e & 31] = (e & 31) < N ? static_cast<float>(xv[q]) : 0.f;
     }
   }
+  // the reduction padded with zero rows to KP, a multiple of 16 (<= NS_KMAX),
+  // so that each wavefront's share is a whole number of 4-step groups
+  const int KP = (K + 15) & ~15;
+  for (int i = t; i < (KP - K) * (NN_BM + 1); i += 256) As[K + i / (NN_BM + 1)][i % (NN_BM + 1)] = 0.f;
+  for (int i = t; i < (KP - K) * NN_BN; i += 256) Xs[K + i / NN_BN][i % NN_BN] = 0.f;
   __syncthreads();
-  float acc[2][4];
+  // matrix cores: wavefront w takes the 32-row half w & 1 of the block and
+  // the half w >> 1 of the reduction pairs; 32 x 32 x 2 FP32 steps, lane
+  // (rh, cl) supplying A[32 rt + cl][kk] and X[kk][cl], kk = 2 pair + rh
+  const int w = t >> 6, lane = t & 63, rh = lane >> 5, cl = lane & 31;
+  const int rt = w & 1, kh = w >> 1;
+  const int hp = KP >> 2;  // pairs per wavefront (a multiple of 4)
+  const int p_lo = kh * hp, p_hi = p_lo + hp;
+  f32x16_t c32;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int v = 0; v < 16; ++v) c32[v] = 0.f;
+  const float* pa = &As[0][0] + 32 * rt + cl;
+  const float* pb = &Xs[0][0] + cl;
+  for (int pp = p_lo; pp < p_hi; pp += 4) {
+    float a[4], b[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
-#pragma unroll 8
-  for (int kk = 0; kk < K; ++kk) {
-    const float a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const float xv = Xs[kk][tx * 4 + j];
-      acc[0][j] += a0 * xv;
-      acc[1][j] += a1 * xv;
+    for (int u = 0; u < 4; ++u) {
+      const int kk = 2 * (pp + u) + rh;
+      a[u] = pa[kk * (NN_BM + 1)];
+      b[u] = pb[kk * NN_BN];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c32 = __builtin_amdgcn_mfma_f32_32x32x2f32(a[u], b[u], c32, 0, 0, 0);
   }
+  // the second reduction half added to the first, in that order
+  if (kh == 1)
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int64_t gr = row0 + ty * 2 + i;
-    if (gr >= n) continue;
+    for (int v = 0; v < 16; ++v) Cs[rt][v * 64 + lane] = c32[v];
+  __syncthreads();
+  if (kh == 0) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gc = tx * 4 + j;
-      if (gc >= N) continue;
-      float v = alpha * acc[i][j];
-      if (beta != 0.f) v += beta * cpre[i][j];
-      C[gr * ldc + gc] = v;
-      acc[i][j] = v;
+    for (int v = 0; v < 16; ++v) {
+      c32[v] += Cs[rt][v * 64 + lane];
+      const int64_t gr = row0 + 32 * rt + 8 * (v >> 2) + 4 * rh + (v & 3);
+      float val = alpha * c32[v];
+      if (beta != 0.f) val += beta * cpre[v];
+      if (gr < n && cl < N) C[gr * ldc + cl] = val;
+      c32[v] = val;  // as stored
     }
   }
   if (gpart) {
     float* T = &As[0][0];  // NN_BM x NN_BN tile of the stored rows
-    __syncthreads();
+    if (kh == 0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const bool rok = row0 + ty * 2 + i < n;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int c = tx * 4 + j;
-        T[(ty * 2 + i) * NN_BN + c] = (rok && c < N) ? acc[i][j] : 0.f;
+      for (int v = 0; v < 16; ++v) {
+        const int row = 32 * rt + 8 * (v >> 2) + 4 * rh + (v & 3);
+        T[row * NN_BN + cl] = (row0 + row < n && cl < N) ? c32[v] : 0.f;
       }
     }
     __syncthreads();
