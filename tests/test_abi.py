@@ -173,3 +173,18 @@ def test_error_metrics_argument_rules(lib):
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(ImportError):
         L.load(str(tmp_path / "libbk.so"))
+
+
+def test_binding_rejects_host_tensors_and_type_mismatch():
+    """The Python binding checks placement and types before any library call."""
+    torch = pytest.importorskip("torch")
+    import paper_1504_05477_amd as bk
+    A = torch.zeros(8, 6, dtype=torch.float64)
+    Z = torch.zeros(8, 2, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        bk.error_metrics_dense(A, Z)                       # host tensors
+    with pytest.raises(ValueError):
+        bk.svd_dense(A, 2, 1)
+    rp = torch.zeros(9, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        bk.error_metrics_csr(rp, rp[:0], torch.zeros(0), 8, 6, Z.float())
