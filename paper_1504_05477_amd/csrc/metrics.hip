@@ -38,26 +38,34 @@ __global__ __launch_bounds__(256) void sumsq_kernel(const T* __restrict__ a, int
 }
 
 // CSR rows: sum of v^2 over the row, minus (sum of v)^2 / d with centring
-// (||a_r - mean(a_r) 1||^2 = ||a_r||^2 - (1^T a_r)^2 / d), a thread per row.
+// (||a_r - mean(a_r) 1||^2 = ||a_r||^2 - (1^T a_r)^2 / d).  A wavefront per
+// row (coalesced reads of the values), rows dealt to the grid's wavefronts
+// in turn; each wavefront adds its rows in order, the block its four
+// wavefronts in order.
 __global__ __launch_bounds__(256) void csr_sumsq_kernel(const int32_t* __restrict__ rp,
                                                         const float* __restrict__ v,
                                                         int64_t rows, int64_t d, int center,
-                                                        int64_t per, double* __restrict__ part) {
+                                                        double* __restrict__ part) {
   __shared__ double red[4];
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
-  const int64_t r1 = r0 + per < rows ? r0 + per : rows;
-  double s = 0.0;
-  for (int64_t r = r0 + threadIdx.x; r < r1; r += 256) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t nw = static_cast<int64_t>(gridDim.x) * 4;
+  double acc = 0.0;  // (lane 0's is the wavefront's)
+  for (int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + w; r < rows; r += nw) {
     double s2 = 0.0, s1 = 0.0;
-    for (int32_t j = rp[r]; j < rp[r + 1]; ++j) {
+    for (int32_t j = rp[r] + lane; j < rp[r + 1]; j += 64) {
       const double x = static_cast<double>(v[j]);
       s2 += x * x;
       s1 += x;
     }
-    s += center ? s2 - s1 * s1 / static_cast<double>(d) : s2;
+    for (int o = 32; o > 0; o >>= 1) {
+      s2 += __shfl_xor(s2, o);
+      s1 += __shfl_xor(s1, o);
+    }
+    acc += center ? s2 - s1 * s1 / static_cast<double>(d) : s2;
   }
-  const double tot = block_sum256(s, red);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  if (lane == 0) red[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
 __global__ void sum_parts_kernel(const double* __restrict__ part, int nb, double* __restrict__ out) {
@@ -89,9 +97,8 @@ void launch_dense_fro2(const void* A, bool f64, int64_t n, int64_t d, int64_t ld
 
 void launch_csr_fro2(const int32_t* rp, const float* v, int64_t n, int64_t d, bool center,
                      double* part, double* out, hipStream_t s) {
-  const int nb = fro_blocks(cdiv(n, 256));
-  const int64_t per = cdiv(n, nb);
-  csr_sumsq_kernel<<<nb, 256, 0, s>>>(rp, v, n, d, center ? 1 : 0, per, part);
+  const int nb = fro_blocks(cdiv(n, 4));
+  csr_sumsq_kernel<<<nb, 256, 0, s>>>(rp, v, n, d, center ? 1 : 0, part);
   sum_parts_kernel<<<1, 64, 0, s>>>(part, nb, out);
 }
 
