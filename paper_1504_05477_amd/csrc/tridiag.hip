@@ -205,12 +205,16 @@ __global__ __launch_bounds__(TRI_THREADS) void tridiag_reduce_kernel(
 
 // One workgroup, steps j0 .. j0 + nst - 1.  V and W live in LDS column by
 // column (ld mr = m - j0, row x is row j0 + x); on exit their rows from
-// j0 + nst on go to Vg, Wg (column q at q m, ld m, absolute rows).
+// j0 + nst on go to Vg, Wg (column q at q m, ld m, absolute rows).  The
+// first R rows of the panel-start block (rows j0 .. j0 + R - 1, columns
+// j0 .. m - 1) are staged in LDS once; each step's A0 v pass reads them
+// there and the rest from memory, the rows dealt to the row groups in turn
+// so that every group gets its share of both.
 __global__ __launch_bounds__(TRI_THREADS) void tri_panel_kernel(
-    const double* __restrict__ A, int64_t m, int64_t j0, int nst, double* __restrict__ Vg,
-    double* __restrict__ Wg, double* __restrict__ Vh, double* __restrict__ beta,
-    double* __restrict__ dg, double* __restrict__ eo) {
-  extern __shared__ double sm[];  // v[m], p[m], c[2 TRI_NB], V, W [TRI_NB x mr]
+    const double* __restrict__ A, int64_t m, int64_t j0, int nst, int R,
+    double* __restrict__ Vg, double* __restrict__ Wg, double* __restrict__ Vh,
+    double* __restrict__ beta, double* __restrict__ dg, double* __restrict__ eo) {
+  extern __shared__ double sm[];  // v[m], p[m], c[2 TRI_NB], V, W [TRI_NB x mr], A0s [R x mr]
   __shared__ double red[TRI_THREADS / 64];
   __shared__ double part[TRI_THREADS];
   __shared__ double s_beta;
@@ -220,8 +224,13 @@ __global__ __launch_bounds__(TRI_THREADS) void tri_panel_kernel(
   double* c = p + m;
   double* V = c + 2 * TRI_NB;
   double* W = V + TRI_NB * mr;
+  double* A0s = W + TRI_NB * mr;
   const int t = threadIdx.x;
   for (int64_t idx = t; idx < 2 * TRI_NB * mr; idx += TRI_THREADS) V[idx] = 0.0;
+  for (int64_t idx = t; idx < static_cast<int64_t>(R) * mr; idx += TRI_THREADS) {
+    const int64_t r = idx / mr, cc = idx - r * mr;
+    A0s[idx] = A[(j0 + r) * m + j0 + cc];
+  }
   __syncthreads();
   for (int jj = 0; jj < nst; ++jj) {
     const int64_t j = j0 + jj, j1 = j + 1;
@@ -266,22 +275,26 @@ __global__ __launch_bounds__(TRI_THREADS) void tri_panel_kernel(
     const int RG = (s <= TRI_THREADS / 4) ? 4 : ((s <= TRI_THREADS / 2) ? 2 : 1);
     const int CW = TRI_THREADS / RG;
     const int grp = t / CW, tc = t - grp * CW;
-    const int rlen = (s + RG - 1) / RG;
-    const int r0 = grp * rlen;
-    const int r1 = (r0 + rlen < s) ? r0 + rlen : s;
-    // A0' v over rows / columns j1 .. m-1
+    // A0' v over rows / columns j1 .. m-1; group grp takes rows grp,
+    // grp + RG, ...: those of the staged rows (i < iL) from LDS first
     double acc = 0.0;
     if (tc < s) {
-      const double* col = A + (j1 + r0) * m + j1 + tc;
-      int i = r0;
-      for (; i + 8 <= r1; i += 8, col += 8 * m) {
+      const int64_t iL64 = j0 + R - j1;
+      const int iL = static_cast<int>(iL64 < s ? iL64 : s);
+      const int64_t off = j1 - j0;
+      const double* lcol = A0s + off * mr + off + tc;
+      int i = grp;
+      for (; i < iL; i += RG) acc += lcol[static_cast<int64_t>(i) * mr] * v[i];
+      const double* col = A + (j1 + i) * m + j1 + tc;
+      const int64_t step = static_cast<int64_t>(RG) * m;
+      for (; i + 7 * RG < s; i += 8 * RG, col += 8 * step) {
         double a[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) a[u] = col[u * m];
+        for (int u = 0; u < 8; ++u) a[u] = col[u * step];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc += a[u] * v[i + u];
+        for (int u = 0; u < 8; ++u) acc += a[u] * v[i + u * RG];
       }
-      for (; i < r1; ++i, col += m) acc += *col * v[i];
+      for (; i < s; i += RG, col += step) acc += *col * v[i];
     }
     part[t] = acc;
     // c[q] = W'^T v, c[jj + q] = V'^T v over the panel rows of j1 .. m-1
@@ -927,8 +940,13 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     int64_t j = 0;
     while (m - j > sb) {
       const int nst = static_cast<int>(std::min<int64_t>(TRI_NB, m - sb - j));
-      const size_t lds = (2 * m + 2 * TRI_NB + 2 * TRI_NB * (m - j)) * sizeof(double);
-      tri_panel_kernel<<<1, TRI_THREADS, lds, s>>>(A, m, j, nst, Vg, Wg, Vh, beta, dg, eo);
+      const int64_t mr = m - j;
+      const int64_t base = 2 * m + 2 * TRI_NB + 2 * TRI_NB * mr;  // doubles
+      // rows of the panel-start block staged in the LDS left over
+      const int64_t free_d = TRI_LDS_BYTES / static_cast<int64_t>(sizeof(double)) - base;
+      const int R = static_cast<int>(std::max<int64_t>(0, std::min<int64_t>(mr, free_d / mr)));
+      const size_t lds = static_cast<size_t>(base + static_cast<int64_t>(R) * mr) * sizeof(double);
+      tri_panel_kernel<<<1, TRI_THREADS, lds, s>>>(A, m, j, nst, R, Vg, Wg, Vh, beta, dg, eo);
       const int64_t jn = j + nst;
       const unsigned g = static_cast<unsigned>(cdiv(m - jn, TRI_SY));
       tri_syr2k_kernel<<<dim3(g, g), 256, 0, s>>>(A, m, jn, Vg, Wg, nst);
