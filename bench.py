@@ -15,6 +15,7 @@ on the solve's stream inside the timed steps) against the 8 TB/s HBM peak.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        [--workload csr2|dense1|dense3|dense4|dense5] [--precision plain|bf16|fp8]
+       [--method bki|lanczos] [--time-to-eps] [--metrics-q Q]
 """
 from __future__ import annotations
 
@@ -113,6 +114,10 @@ def main():
     ap.add_argument("--method", default="bki", choices=["bki", "lanczos"],
                     help="Rayleigh-Ritz matrix: W^T W (Algorithm 2) or the block-tridiagonal "
                          "T of the block Lanczos recurrence (Section 4.2)")
+    ap.add_argument("--time-to-eps", action="store_true",
+                    help="dense workloads: for each eps in 1e-1, 1e-2, 1e-3 the smallest q whose "
+                         "per-vector error (eq. 3, planted spectrum, measured on the GPU) is at "
+                         "most eps, and the time of one solve at that q")
     ap.add_argument("--metrics-q", type=int, default=4, metavar="Q",
                     help="depth of the GPU spectral-residual estimate of the error measures "
                          "taken after the timed steps (-1: skip them)")
@@ -214,6 +219,14 @@ def main():
         def error_measures(Z, qs):
             return bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), q_spec=qs,
                                           seed=w.seed_sketch + 1)
+
+        def solve_q(qq):
+            return bk.svd_dense(A_in, k, qq, seed=w.seed_sketch, **kw)
+
+        def per_vector(Z):
+            m = bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(),
+                                       sigma_true=sv[:k + 1], q_spec=0, seed=w.seed_sketch + 1)
+            return m.values["per_vector"]
         kern_src = ["gemm.hip", "gemm_mfma.hip"]
         kern_names = {"ax": "A.X product (operand pack + product kernel)",
                       "aty": "A^T.Y product (operand pack + product kernel + split reduction)"}
@@ -305,6 +318,11 @@ def main():
 
     if args.metrics_q >= 0:
         out["error_measures"] = gpu_error_measures(error_measures, r.Z, args.metrics_q)
+    if args.time_to_eps:
+        if w.kind == "dense":
+            out["time_to_eps"] = time_to_eps(solve_q, per_vector, q)
+        else:
+            out["time_to_eps"] = {"skipped": "needs the true spectrum (planted dense inputs)"}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["parity"] = cpu_baseline(args, w, host_inputs, r,
@@ -328,6 +346,31 @@ def gpu_error_measures(fn, Z, qs):
     return {"fro2": v["fro2"], "resid_fro": v["resid_fro"], "resid_spec": v["resid_spec"],
             "captured_fro2": v["captured_fro2"], "q_spec": qs, "ms": round(ms, 3),
             "status": m.status}
+
+
+def time_to_eps(solve_q, per_vector, q_max, eps_list=(1e-1, 1e-2, 1e-3), reps=3):
+    """Time-to-eps (the paper's per-vector error, eq. 3, against the planted
+    spectrum, Section 7): for q = 0 .. q_max the per-vector error of one
+    solve's Z (error measures on the GPU) and the median wall time of `reps`
+    solves after one warm-up; for each eps the smallest q reaching it."""
+    import torch
+    rows = []
+    for qq in range(0, q_max + 1):
+        solve_q(qq)
+        torch.cuda.synchronize()
+        ts = []
+        res = None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            res = solve_q(qq)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        rows.append({"q": qq, "per_vector": per_vector(res.Z), "ms": round(sorted(ts)[reps // 2], 4)})
+    out = {"sweep": rows}
+    for eps in eps_list:
+        hit = next((r for r in rows if r["per_vector"] <= eps), None)
+        out[f"{eps:g}"] = ({"q": hit["q"], "ms": hit["ms"]} if hit else "not reached")
+    return out
 
 
 def products_all_kernels(ph, q_eff, bx, by):
