@@ -186,3 +186,21 @@ def test_metrics_csr_term_document_full_size():
                 random_state=np.random.default_rng(3))[0]
     assert v["resid_spec"] <= spec * (1 + 1e-6)
     assert v["resid_spec"] >= spec * (1 - 1e-3)
+
+
+def test_metrics_csr_given_transpose_matches():
+    """A caller-supplied CSR of A^T (column ids sorted, as the library builds
+    it) gives the same measures bit for bit."""
+    n, d, k = 800, 5000, 6
+    (rp, ci, va), M = _termdoc(n, d, 13)
+    T = M.T.tocsr()
+    T.sort_indices()
+    g = (_cuda(rp), _cuda(ci), _cuda(va))
+    tr = (_cuda(T.indptr.astype(np.int32)), _cuda(T.indices.astype(np.int32)),
+          _cuda(T.data.astype(np.float32)))
+    Z = bk.svd_csr(*g, n, d, k, 3, seed=8, center=True).Z
+    a = bk.error_metrics_csr(*g, n, d, Z, q_spec=5, seed=2, center=True)
+    b = bk.error_metrics_csr(*g, n, d, Z, q_spec=5, seed=2, center=True, transpose=tr)
+    assert a.values["fro2"] == b.values["fro2"]
+    assert a.values["resid_spec"] == b.values["resid_spec"]
+    assert torch.equal(a.captured, b.captured)
