@@ -732,11 +732,22 @@ __global__ __launch_bounds__(256) void col_sign_kernel(const T* Z, int64_t n,
   const int t = threadIdx.x;
   double best = -1.0;
   int64_t bidx = n;
-  for (int64_t r = t; r < n; r += 256) {
-    const double a = fabs(static_cast<double>(Z[r * ldz + c]));
-    if (a > best) {  // rows visited in increasing order: first max kept
-      best = a;
-      bidx = r;
+  // eight rows per thread in flight (clamped, unconditional loads), then
+  // compared in increasing row order: the first maximum is kept
+  for (int64_t r0 = t; r0 < n; r0 += 256 * 8) {
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t r = r0 + 256 * u;
+      const double x = fabs(static_cast<double>(Z[(r < n ? r : n - 1) * ldz + c]));
+      a[u] = r < n ? x : -1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (a[u] > best) {
+        best = a[u];
+        bidx = r0 + 256 * u;
+      }
     }
   }
   bv[t] = best;
