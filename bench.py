@@ -111,9 +111,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
-    ap.add_argument("--method", default="bki", choices=["bki", "lanczos"],
+    ap.add_argument("--method", default="bki", choices=["bki", "lanczos", "si"],
                     help="Rayleigh-Ritz matrix: W^T W (Algorithm 2) or the block-tridiagonal "
-                         "T of the block Lanczos recurrence (Section 4.2)")
+                         "T of the block Lanczos recurrence (Section 4.2); or simultaneous "
+                         "iteration (Algorithm 1)")
+    ap.add_argument("--block-size", type=int, default=0, metavar="P",
+                    help="block width p >= k (oversampling, Section 6); 0: p = k")
     ap.add_argument("--time-to-eps", action="store_true",
                     help="dense workloads: for each eps in 1e-1, 1e-2, 1e-3 the smallest q whose "
                          "per-vector error (eq. 3, planted spectrum, measured on the GPU) is at "
@@ -154,7 +157,7 @@ def main():
         g_ci = torch.from_numpy(ci).to(dev)
         g_va = torch.from_numpy(va).to(dev)
         nnz = int(ci.size)
-        bx, by = csr_product_bytes(w.n, w.d, nnz, k)
+        bx, by = csr_product_bytes(w.n, w.d, nnz, args.block_size or k)
         dtype = "f32"
         # CSR of A^T: an input layout built once on the GPU (as a caller
         # solving repeatedly would), timed on its own, outside the steps
@@ -169,7 +172,7 @@ def main():
         def step(timing):
             return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
                               center=w.center, transpose=tr, timing=timing,
-                              method=args.method)
+                              method=args.method, block_size=args.block_size)
 
         def error_measures(Z, qs):
             return bk.error_metrics_csr(g_rp, g_ci, g_va, w.n, w.d, Z, q_spec=qs,
@@ -210,11 +213,11 @@ def main():
         else:
             A_in = A
         x_bytes = 8 if A.dtype == torch.float64 else 4
-        bx, by = dense_product_bytes(w.n, w.d, k, a_bytes, x_bytes)
+        bx, by = dense_product_bytes(w.n, w.d, args.block_size or k, a_bytes, x_bytes)
 
         def step(timing):
             return bk.svd_dense(A_in, k, q, seed=w.seed_sketch, timing=timing,
-                                method=args.method, **kw)
+                                method=args.method, block_size=args.block_size, **kw)
 
         def error_measures(Z, qs):
             return bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), q_spec=qs,
@@ -283,7 +286,7 @@ def main():
             "avg_launch_ms": round(avg_ms, 5), "event_steps": n_ev,
             "algorithmic_bytes_per_launch": int(per_launch), "source_sha": sha}
     if w.kind == "dense" and args.precision == "plain":
-        flops = 2.0 * w.n * w.d * k
+        flops = 2.0 * w.n * w.d * (args.block_size or k)
         tf = flops / (avg_ms * 1e-3) / 1e12
         if flops / per_launch > FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9):
             roof.update({"bound": "mfma", "achieved": round(tf, 3),
@@ -307,6 +310,7 @@ def main():
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}",
                    "n": w.n, "d": w.d, "k": k, "q": q,
                    "precision": args.precision, "method": args.method,
+                   "block_size": args.block_size or k,
                    "product_bytes_per_solve": int(bytes_per_solve)},
         "roofline": roof,
         "phases_ms_per_step": {p: round(v, 4) for p, v in ph.items()},
@@ -409,7 +413,8 @@ def cpu_baseline(args, w, host, res, bytes_per_solve):
     from oracle import bki, metrics, philox
 
     k, q = w.k, w.q
-    Pi = philox.gaussian(w.seed_sketch, w.d, k)
+    pw = args.block_size or k
+    Pi = philox.gaussian(w.seed_sketch, w.d, pw)
     if w.kind == "csr":
         A = sp.csr_matrix((host["va"].astype(np.float64), host["ci"], host["rp"]),
                           shape=(w.n, w.d))
@@ -428,7 +433,13 @@ def cpu_baseline(args, w, host, res, bytes_per_solve):
     t_end = time.perf_counter() + args.cpu_seconds
     while time.perf_counter() < t_end or not times:
         t0 = time.perf_counter()
-        ref = bki.block_krylov(A, Pi, k, q, center=w.center, tau=tau)
+        # the oracle route of the method timed on the GPU
+        if args.method == "si":
+            ref = bki.simultaneous_iteration(A, Pi, k, q, center=w.center)
+        elif args.method == "lanczos":
+            ref = bki.block_lanczos(A, Pi, k, q, center=w.center, tau=tau)[0]
+        else:
+            ref = bki.block_krylov(A, Pi, k, q, center=w.center, tau=tau)
         times.append(time.perf_counter() - t0)
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     per = float(np.median(times))
@@ -442,7 +453,7 @@ def cpu_baseline(args, w, host, res, bytes_per_solve):
     sg = res.sigma.cpu().numpy()
     rel = float(np.max(np.abs(sg - ref.sigma) / ref.sigma))
     j = 0   # widest leading subspace with relative Ritz gap >= 1e-2
-    for jj in range(1, k + 1):
+    for jj in range(1, min(k, len(ref.theta) - 1) + 1):
         if (ref.theta[jj - 1] - ref.theta[jj]) / ref.theta[0] >= 1e-2:
             j = jj
     ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j]) if j else None
