@@ -14,15 +14,16 @@ span routes; Ritz-value interlacing and nestedness in q; Lemma 1; the matrix
 Pythagorean identity; planted spectra with known sigma.
 """
 from .philox import gaussian, philox4x32_10, philox_words
-from .bki import (BKIResult, LinearOperator, RankError, block_krylov,
-                  block_krylov_route_b, rayleigh_ritz, rayleigh_ritz_svd,
-                  sign_normalize, simultaneous_iteration, validate)
+from .bki import (BKIResult, LinearOperator, RankError, StreamedDense,
+                  block_krylov, block_krylov_planted, block_krylov_route_b,
+                  rayleigh_ritz, rayleigh_ritz_svd, sign_normalize,
+                  simultaneous_iteration, validate)
 from .metrics import (frobenius_ratio, per_vector_error, principal_angle,
                       principal_angle_sin, spectral_ratio)
 
 __all__ = [
     "gaussian", "philox4x32_10", "philox_words", "BKIResult", "LinearOperator",
-    "RankError", "block_krylov", "block_krylov_route_b", "rayleigh_ritz",
+    "RankError", "StreamedDense", "block_krylov", "block_krylov_planted", "block_krylov_route_b", "rayleigh_ritz",
     "rayleigh_ritz_svd", "sign_normalize", "simultaneous_iteration", "validate",
     "frobenius_ratio", "per_vector_error", "principal_angle",
     "principal_angle_sin", "spectral_ratio",

@@ -46,7 +46,7 @@ __all__ = [
     "RankError", "BKIResult", "LinearOperator", "validate",
     "block_krylov", "block_krylov_route_b", "rayleigh_ritz_svd",
     "rayleigh_ritz", "simultaneous_iteration", "sign_normalize", "block_lanczos",
-    "block_tridiagonal",
+    "block_tridiagonal", "StreamedDense", "block_krylov_planted",
 ]
 
 
@@ -90,6 +90,44 @@ class LinearOperator:
         out = np.asarray(self.A.T @ Y, dtype=np.float64)
         if self.center:
             out = out - np.outer(np.ones(self.d), self.mu @ Y)
+        return out
+
+
+class StreamedDense(LinearOperator):
+    """A dense FP32 matrix (the stored master copy of A) used in float64
+    without an n x d float64 copy: every product upcasts ``rows`` rows at a
+    time (exactly: every float32 is a float64) and multiplies them in
+    float64; A^T Y adds the row blocks' float64 partial products in order.
+    The same products as LinearOperator(A.astype(float64)) up to the order
+    of the float64 sums; only the memory use differs.  No centring."""
+
+    def __init__(self, A32, rows: int = 8192):
+        A32 = np.asarray(A32)
+        if A32.ndim != 2:
+            raise ValueError("need a 2-D matrix")
+        self.A = A32
+        self.n, self.d = A32.shape
+        self.center = False
+        self.mu = None
+        self.rows = int(rows)
+
+    def _blocks(self):
+        for r0 in range(0, self.n, self.rows):
+            r1 = min(self.n, r0 + self.rows)
+            yield r0, r1, np.asarray(self.A[r0:r1], dtype=np.float64)
+
+    def mul(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        out = np.empty((self.n, X.shape[1]))
+        for r0, r1, blk in self._blocks():
+            out[r0:r1] = blk @ X
+        return out
+
+    def tmul(self, Y):
+        Y = np.asarray(Y, dtype=np.float64)
+        out = np.zeros((self.d, Y.shape[1]))
+        for r0, r1, blk in self._blocks():
+            out += blk.T @ Y[r0:r1]
         return out
 
 
@@ -295,3 +333,32 @@ def block_lanczos(A, Pi, k: int, q: int, *, center: bool = False,
     Z = sign_normalize(Q @ U[:, :k])
     sigma = np.sqrt(np.maximum(theta[:k], 0.0))
     return BKIResult(Z, sigma, theta, Q, U, q_eff), T
+
+
+def block_krylov_planted(U, sigma, V, Pi, k: int, q: int, *,
+                         tau: float = 1e-12) -> BKIResult:
+    """Algorithm 2 on A = U diag(sigma) V^T (U n x r, V d x r, orthonormal
+    columns), worked in the coordinates of the factors.
+
+    A Pi = U (S V^T Pi) and A A^T = U S^2 U^T, so every Krylov block of A
+    with sketch Pi is U times the matching block of the r x r diagonal
+    matrix S = diag(sigma) with sketch V^T Pi.  Q = U Q_S is then an
+    orthonormal basis of span(K), Q^T A A^T Q = Q_S^T S^2 Q_S, and
+    Rayleigh-Ritz gives the same theta, Z = U Z_S (Lemma 1).  The breakdown
+    tests see the same norms and singular values (U has orthonormal
+    columns), so q_eff agrees as well.  route A (block_krylov) runs on S as
+    it stands; only the n x r and d x r factor products are outside it."""
+    import scipy.sparse as sp
+
+    U = np.asarray(U, dtype=np.float64)
+    V = np.asarray(V, dtype=np.float64)
+    sigma = np.asarray(sigma, dtype=np.float64)
+    r = sigma.shape[0]
+    if U.shape[1] != r or V.shape[1] != r:
+        raise ValueError("U and V need one column per singular value")
+    S = sp.diags(sigma, format="csr")
+    Ps = V.T @ np.asarray(Pi, dtype=np.float64)
+    validate(U.shape[0], V.shape[0], k, q, Ps.shape[1])
+    res = block_krylov(S, Ps, k, q, tau=tau)
+    Z = sign_normalize(U @ res.Z)
+    return BKIResult(Z, res.sigma, res.theta, U @ res.Q, res.Ubar, res.q_eff)

@@ -329,3 +329,117 @@ def test_sign_normalization():
     assert np.allclose(out, [[-0.6, 0.8], [0.8, -0.6]])
     tie = bki.sign_normalize(np.array([[-0.5], [0.5]]))
     assert tie[0, 0] > 0                      # tie -> the lower row decides
+
+
+# ------------------------------------------- Algorithm 1 in closed form --
+def _planted_factors(n, d, sig, seed):
+    """U (n x r), V (d x r) with orthonormal columns and A = U diag(sig) V^T,
+    built here (not by the oracle) from Householder QR of Gaussians."""
+    rng = np.random.default_rng(seed)
+    r = len(sig)
+    U = np.linalg.qr(rng.standard_normal((n, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((d, r)))[0]
+    return U, V, (U * sig) @ V.T
+
+
+def _rr_closed_form(A, B):
+    """Rayleigh-Ritz on span(B) by Lemma 1's route: Q from the SVD of B,
+    then the singular values and left vectors of Q^T A (no eigen-solve)."""
+    Q = np.linalg.svd(B, full_matrices=False)[0]
+    Ub, s, _ = np.linalg.svd(Q.T @ A, full_matrices=False)
+    return s, Q @ Ub
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_simultaneous_iteration_closed_form(q):
+    # A = U S V^T:  (A A^T)^q A Pi = U S^(2q+1) (V^T Pi), so after q steps
+    # Algorithm 1's block spans U diag(sigma^(2q+1)) V^T Pi exactly; the
+    # Rayleigh-Ritz pairs of that span are fixed without iterating.
+    sig = np.linspace(1.0, 0.3, 80)
+    U, V, A = _planted_factors(120, 80, sig, 51)
+    k = 4
+    Pi = philox.gaussian(52, 80, 6)                    # p = 6 >= k
+    res = bki.simultaneous_iteration(A, Pi, k, q)
+    Vp = V.T @ Pi
+    want_s, want_Z = _rr_closed_form(A, U @ (sig[:, None] ** (2 * q + 1) * Vp))
+    assert np.allclose(res.sigma, want_s[:k], rtol=1e-10, atol=0)
+    assert metrics.principal_angle(res.Z, want_Z[:, :k]) < 1e-8
+    # the test tells q from q - 1 and q + 1: an off-by-one in the iteration
+    # count moves the Ritz values far beyond the tolerance above
+    for qq in (q - 1, q + 1):
+        s_other = _rr_closed_form(A, U @ (sig[:, None] ** (2 * qq + 1) * Vp))[0][:k]
+        assert np.max(np.abs(s_other - res.sigma) / res.sigma) > 1e-6
+
+
+def test_simultaneous_iteration_exact_when_sketch_spans_column_space():
+    # rank(A) = p: span(A Pi) = col(A) already, so every q returns the exact
+    # top k (brute force: numpy SVD)
+    sig = np.array([3.0, 2.5, 2.0, 1.2, 0.7, 0.4])
+    U, V, A = _planted_factors(70, 50, sig, 53)
+    for q in (0, 1, 3):
+        res = bki.simultaneous_iteration(A, philox.gaussian(54, 50, 6), 3, q)
+        assert np.allclose(res.sigma, sig[:3], rtol=1e-12)
+        assert _proj_dist(res.Z, U[:, :3]) < 1e-10
+
+
+def test_block_krylov_closed_form_span():
+    # Algorithm 2's space is span{U S^(2i+1) V^T Pi, i = 0..q}; its
+    # Rayleigh-Ritz pairs from the closed form, at q = 1..3
+    sig = np.linspace(1.0, 0.3, 80)
+    U, V, A = _planted_factors(120, 80, sig, 55)
+    Pi = philox.gaussian(56, 80, 4)
+    Vp = V.T @ Pi
+    for q in (1, 2, 3):
+        res = bki.block_krylov(A, Pi, 4, q)
+        K = np.hstack([U @ (sig[:, None] ** (2 * i + 1) * Vp) for i in range(q + 1)])
+        want_s, want_Z = _rr_closed_form(A, K)
+        assert np.allclose(res.sigma, want_s[:4], rtol=1e-9)
+        assert metrics.principal_angle(res.Z, want_Z[:, :4]) < 1e-7
+
+
+# ------------------------------------- streamed FP32 operator, factor route --
+def test_streamed_dense_matches_dense_operator():
+    rng = np.random.default_rng(57)
+    A32 = rng.standard_normal((1000, 300)).astype(np.float32)
+    A64 = A32.astype(np.float64)
+    op = bki.StreamedDense(A32, rows=128)             # 7 full blocks + a ragged one
+    X = rng.standard_normal((300, 7))
+    Y = rng.standard_normal((1000, 7))
+    assert np.allclose(op.mul(X), A64 @ X, rtol=0, atol=1e-12)
+    assert np.allclose(op.tmul(Y), A64.T @ Y, rtol=0, atol=1e-11)
+    sv = workloads.spectrum("inv", 300)
+    B32 = workloads.planted_dense(1000, 300, sv, 58).astype(np.float32)
+    Pi = philox.gaussian(59, 300, 5)
+    r1 = bki.block_krylov(bki.StreamedDense(B32, rows=100), Pi, 5, 4, tau=1e-5)
+    r2 = bki.block_krylov(B32.astype(np.float64), Pi, 5, 4, tau=1e-5)
+    assert np.allclose(r1.sigma, r2.sigma, rtol=1e-12)
+    assert metrics.principal_angle(r1.Z, r2.Z) < 1e-9
+    assert r1.q_eff == r2.q_eff
+
+
+@pytest.mark.parametrize("n,d,r,q", [(150, 100, 100, 3), (90, 140, 90, 2), (200, 120, 40, 4)])
+def test_planted_factor_route_matches_route_a(n, d, r, q):
+    # Algorithm 2 is equivariant under A -> U A V^T with orthonormal factors:
+    # the route that runs it on diag(sigma) with sketch V^T Pi and maps Z
+    # back by U must equal route A on the assembled matrix
+    sig = workloads.spectrum("pow08", r)
+    U, V, A = _planted_factors(n, d, sig, 60 + n)
+    k = 5
+    Pi = philox.gaussian(61, d, k)
+    a = bki.block_krylov(A, Pi, k, q)
+    b = bki.block_krylov_planted(U, sig, V, Pi, k, q)
+    assert a.q_eff == b.q_eff
+    assert np.allclose(a.sigma, b.sigma, rtol=1e-11)
+    assert metrics.principal_angle(a.Z, b.Z) < 1e-9
+    assert np.allclose(b.Z.T @ b.Z, np.eye(k), atol=1e-13)
+    # the columns agree one by one (sign rule applied after mapping back)
+    assert np.max(np.abs(a.Z - b.Z)) < 1e-8
+
+
+def test_planted_factor_route_exact_top_k():
+    # (q+1) k >= rank: exact singular values and vectors, as route A
+    sig = np.linspace(2.0, 0.5, 12)
+    U, V, A = _planted_factors(60, 45, sig, 62)
+    res = bki.block_krylov_planted(U, sig, V, philox.gaussian(63, 45, 3), 3, 3)
+    assert np.allclose(res.sigma, sig[:3], rtol=1e-12)
+    assert _proj_dist(res.Z, U[:, :3]) < 1e-10

@@ -139,32 +139,48 @@ _BIG = 1 << 31
 _ROWBLK = 8192
 
 
-def _orth_blocked(rows, cols, g, device):
-    """Q factor (positive diagonal of R) of a seeded N(0,1) rows x cols
-    matrix drawn in row blocks, by CholeskyQR2 in FP64: with G = X^T X =
-    R^T R (Cholesky), Q = X R^-1, repeated once on Q.  In exact arithmetic
-    this is the Householder Q made unique by diag(R) > 0; a Gaussian matrix
-    with rows >= 2 cols is well conditioned, so two passes reach FP64
-    orthogonality.  Every library call sees at most _ROWBLK x cols entries."""
+def _gaussian_rows(rows, cols, g, device, rowblk=None):
+    """rows x cols N(0,1) FP64 drawn from generator g in row blocks."""
     import torch
 
-    q = torch.empty(rows, cols, dtype=torch.float64, device=device)
-    for r0 in range(0, rows, _ROWBLK):
-        r1 = min(rows, r0 + _ROWBLK)
-        q[r0:r1] = torch.randn(r1 - r0, cols, generator=g, device=device,
+    rb = rowblk or _ROWBLK
+    x = torch.empty(rows, cols, dtype=torch.float64, device=device)
+    for r0 in range(0, rows, rb):
+        r1 = min(rows, r0 + rb)
+        x[r0:r1] = torch.randn(r1 - r0, cols, generator=g, device=device,
                                dtype=torch.float64)
+    return x
+
+
+def _cholqr2_rows(x, rowblk=None):
+    """In place: x <- its Q factor (positive diagonal of R) by CholeskyQR2 in
+    FP64: with G = X^T X = R^T R (Cholesky), Q = X R^-1, repeated once on
+    Q.  In exact arithmetic this is the Householder Q made unique by
+    diag(R) > 0; a Gaussian matrix with rows >= 2 cols is well conditioned,
+    so two passes reach FP64 orthogonality.  Every library call sees at most
+    rowblk x cols entries (Grams accumulated over row blocks)."""
+    import torch
+
+    rb = rowblk or _ROWBLK
+    rows, cols = x.shape
     for _ in range(2):
-        gram = torch.zeros(cols, cols, dtype=torch.float64, device=device)
-        for r0 in range(0, rows, _ROWBLK):
-            blk = q[r0:min(rows, r0 + _ROWBLK)]
+        gram = torch.zeros(cols, cols, dtype=torch.float64, device=x.device)
+        for r0 in range(0, rows, rb):
+            blk = x[r0:min(rows, r0 + rb)]
             gram += blk.t() @ blk
         rfac = torch.linalg.cholesky(gram, upper=True)
         del gram
-        for r0 in range(0, rows, _ROWBLK):
-            r1 = min(rows, r0 + _ROWBLK)
-            q[r0:r1] = torch.linalg.solve_triangular(rfac, q[r0:r1], upper=True, left=False)
+        for r0 in range(0, rows, rb):
+            r1 = min(rows, r0 + rb)
+            x[r0:r1] = torch.linalg.solve_triangular(rfac, x[r0:r1], upper=True, left=False)
         del rfac
-    return q
+    return x
+
+
+def _orth_blocked(rows, cols, g, device):
+    """Q factor of a seeded N(0,1) rows x cols matrix for factors too large
+    for one library QR: drawn in row blocks, orthonormalized by CholeskyQR2."""
+    return _cholqr2_rows(_gaussian_rows(rows, cols, g, device))
 
 
 def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
