@@ -171,16 +171,23 @@ class BKSVD(torch.autograd.Function):
     def forward(ctx, A, k: int, q: int, seed: int = 0):
         A = A.contiguous()
         res = svd_dense(A, k, q, seed, save_for_backward=True)
-        ctx.save_for_backward(A)
-        ctx.fwd = res
+        # The outputs go through save_for_backward (version-checked: an
+        # in-place change to Z or sigma before backward raises), and ctx
+        # holds only the forward workspace, not the outputs, so there is no
+        # output -> grad_fn -> ctx -> output cycle keeping the workspace alive.
+        ctx.save_for_backward(A, res.Z, res.sigma)
+        ctx.workspace = res.workspace
+        ctx.info = res.info
         ctx.kq = (k, q)
         return res.Z, res.sigma
 
     @staticmethod
     def backward(ctx, Z_bar, sigma_bar):
-        (A,) = ctx.saved_tensors
+        A, Z, sigma = ctx.saved_tensors
         k, q = ctx.kq
-        A_bar = svd_dense_backward(A, k, q, ctx.fwd, Z_bar, sigma_bar)
+        fwd = SVDResult(Z, sigma, ctx.info, ctx.workspace)
+        A_bar = svd_dense_backward(A, k, q, fwd, Z_bar, sigma_bar)
+        ctx.workspace = None
         return A_bar, None, None, None
 
 

@@ -16,10 +16,27 @@ def gap_index(theta: np.ndarray, k: int, rel_gap: float = 1e-2) -> int:
     return best
 
 
+def angle_bound_at_k(theta: np.ndarray, k: int, ritz_rtol: float, angle_tol: float):
+    """Tolerance on the largest principal angle of the whole k-dimensional
+    Ritz subspace, or None when theta_k = theta_{k+1} (the subspace is not
+    unique).  Davis-Kahan: a perturbation E of M moves span(U_k) by at most
+    ||E|| / (theta_k - theta_{k+1}); a Ritz-value tolerance of ritz_rtol
+    (relative on sigma) admits ||E|| up to ~2 ritz_rtol theta_1, taken with a
+    factor 5 of slack."""
+    if len(theta) <= k:
+        return angle_tol               # the whole space: no gap to resolve
+    gap = (theta[k - 1] - theta[k]) / theta[0]
+    if not gap > 0:
+        return None
+    return float(min(np.pi / 2, max(angle_tol, 10.0 * ritz_rtol / gap)))
+
+
 def compare(Zg, sg, ref, k: int, ritz_rtol: float, angle_tol: float, rel_gap=1e-2,
-            orth_tol=None):
+            orth_tol=None, angle_k=True):
     """Ritz values elementwise; the largest principal angle on the widest
-    gap-separated leading subspace; orthonormality of Z."""
+    gap-separated leading subspace (which must exist) and, whenever theta_k >
+    theta_{k+1}, on the whole k-subspace against its Davis-Kahan bound;
+    orthonormality of Z."""
     Zg = np.asarray(Zg, dtype=np.float64)
     sg = np.asarray(sg, dtype=np.float64)
     rel = np.abs(sg - ref.sigma) / ref.sigma    # per Ritz value
@@ -28,6 +45,14 @@ def compare(Zg, sg, ref, k: int, ritz_rtol: float, angle_tol: float, rel_gap=1e-
     otol = orth_tol if orth_tol is not None else max(1e3 * ritz_rtol, 1e-12)
     assert np.abs(Zg.T @ Zg - np.eye(k)).max() <= otol
     j = gap_index(ref.theta, k, rel_gap)
-    ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j]) if j else 0.0
+    assert j >= 1, "no leading subspace with a relative Ritz gap >= rel_gap"
+    ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j])
     assert ang <= angle_tol, (j, ang)
-    return {"ritz_rel_max": float(rel.max()), "angle": ang, "j": j}
+    out = {"ritz_rel_max": float(rel.max()), "angle": ang, "j": j}
+    if angle_k:
+        tol_k = angle_bound_at_k(ref.theta, k, ritz_rtol, angle_tol)
+        if tol_k is not None:
+            ang_k = metrics.principal_angle(ref.Z, Zg)
+            assert ang_k <= tol_k, (k, ang_k, tol_k)
+            out.update({"angle_k": ang_k, "angle_k_tol": tol_k})
+    return out

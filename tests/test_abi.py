@@ -188,3 +188,43 @@ def test_binding_rejects_host_tensors_and_type_mismatch():
     rp = torch.zeros(9, dtype=torch.int32)
     with pytest.raises(ValueError):
         bk.error_metrics_csr(rp, rp[:0], torch.zeros(0), 8, 6, Z.float())
+
+
+def test_too_small_workspace_gives_enomem(lib):
+    """A caller-given workspace one byte short of the queried size is
+    rejected with BK_ENOMEM before anything is enqueued (no GPU needed: the
+    pointers are never dereferenced)."""
+    P = C.c_void_p(4096)
+    o = _opt()
+    for code in (L.F64, L.F32):
+        need = lib.bk_svd_dense_workspace(600, 400, 8, 4, code, C.byref(o))
+        assert need > 0
+        st = lib.bk_svd_dense(P, 400, code, None, None, 0, 600, 400, 8, 4, 0, C.byref(o), P, 8,
+                              P, None, P, need - 1, None)
+        assert st == L.ENOMEM
+    # the backward, given a forward workspace of the right size
+    o.save_for_backward = 1
+    fwd = lib.bk_svd_dense_workspace(600, 400, 8, 4, L.F32, C.byref(o))
+    need = lib.bk_svd_dense_backward_workspace(600, 400, 8, 4, L.F32)
+    assert need > 0
+    st = lib.bk_svd_dense_backward(P, 400, L.F32, 600, 400, 8, 4, P, 8, P, P, P, P, 400, P,
+                                   fwd, P, need - 1, None)
+    assert st == L.ENOMEM
+    # CSR (transpose built inside, and given)
+    o = _opt()
+    need = lib.bk_svd_csr_workspace(500, 3000, 9000, 6, 3, C.byref(o))
+    assert need > 0
+    st = lib.bk_svd_csr(P, P, P, None, None, None, 500, 3000, 9000, 6, 3, 0, C.byref(o), P, 6,
+                        P, None, P, need - 1, None)
+    assert st == L.ENOMEM
+    st = lib.bk_svd_csr(P, P, P, P, P, P, 500, 3000, 9000, 6, 3, 0, C.byref(o), P, 6, P, None,
+                        P, 4096, None)
+    assert st == L.ENOMEM
+    # error measures and the block product
+    need = lib.bk_error_metrics_dense_workspace(600, 400, 8, 4, L.F32)
+    assert lib.bk_error_metrics_dense(P, 400, L.F32, 600, 400, P, 8, 8, 4, 0, None, 0, None,
+                                      None, P, need - 1, None) == L.ENOMEM
+    need = lib.bk_dense_product_workspace(1, 600, 400, 8, L.F32)
+    if need > 0:
+        assert lib.bk_dense_product(1, P, 400, L.F32, None, 600, 400, P, 8, 8, P, 8, P,
+                                    need - 1, None) == L.ENOMEM
