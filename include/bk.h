@@ -184,6 +184,31 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type,
                  double* ritz, bk_info* info, void* workspace,
                  size_t workspace_bytes, void* stream);
 
+/* Allocation-free form of bk_svd_dense, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments and results as bk_svd_dense, with
+ * no workspace argument: the solve's scratch is a static device array of
+ * BK_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends (its address is looked up once per device, on the
+ * first call there).  The call itself allocates nothing.
+ * - Returns BK_ENOMEM, before touching the device, when
+ *   bk_svd_dense_workspace(n, d, k, q, a_type, opt) exceeds
+ *   BK_NOALLOC_SCRATCH_BYTES; BK_EINVAL as bk_svd_dense, and also for
+ *   opt->save_for_backward != 0 (the next call would overwrite the saved
+ *   state).  opt->timing is ignored (no per-phase times; launch counts are
+ *   still written to info).
+ * - Every call on one GPU uses that GPU's one array, which keeps the last
+ *   call's contents (the solve initializes what it reads): calls that
+ *   overlap on one GPU (different streams, or host threads) race and must
+ *   be serialized by the caller, e.g. by issuing them on one stream. */
+#define BK_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int bk_svd_dense_noalloc(const void* A, int64_t lda, int32_t a_type,
+                         const float* a_scales, const float* A_master,
+                         int64_t ld_master, int64_t n, int64_t d, int32_t k,
+                         int32_t q, uint64_t seed, const bk_options* opt,
+                         void* Z, int64_t ldz, double* ritz, bk_info* info,
+                         void* stream);
+
 /* Bytes of workspace bk_svd_csr needs (0 on invalid arguments). */
 size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k,
                             int32_t q, const bk_options* opt);

@@ -85,6 +85,8 @@ _SIGS = [
     ("bk_svd_dense_workspace", _SZ, [_I64, _I64, _I32, _I32, _I32, _P]),
     ("bk_svd_dense", C.c_int, [_P, _I64, _I32, _P, _P, _I64, _I64, _I64, _I32, _I32, _U64,
                                _P, _P, _I64, _P, _P, _P, _SZ, _P]),
+    ("bk_svd_dense_noalloc", C.c_int, [_P, _I64, _I32, _P, _P, _I64, _I64, _I64, _I32, _I32,
+                                       _U64, _P, _P, _I64, _P, _P, _P]),
     ("bk_svd_csr_workspace", _SZ, [_I64, _I64, _I64, _I32, _I32, _P]),
     ("bk_svd_csr", C.c_int, [_P, _P, _P, _P, _P, _P, _I64, _I64, _I64, _I32, _I32, _U64,
                              _P, _P, _I64, _P, _P, _P, _SZ, _P]),

@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <vector>
 
 #include "kernels.hpp"
@@ -1393,6 +1394,51 @@ int metrics_run(Op& op, Layout& L, const MetricsWs& w, const void* Z, int64_t ld
 
 using namespace bk;
 
+// ------------------------------------------------ allocation-free solve --
+// The scratch of bk_svd_dense_noalloc: one static array per GPU the library
+// runs on (the code object's global, allocated when the module is loaded on
+// that device).  In host code `scratch` names a host-side stand-in, not a
+// device address, so it is never passed to a kernel or a copy: the device
+// address comes from hipGetSymbolAddress, looked up once per device with
+// that device current, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[BK_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxScratchDevices];
+
+// Device address of `scratch` on the device of stream s (nullptr on error).
+void* scratch_address(hipStream_t s) {
+  int dev = 0;
+  if (s) {
+    if (hipStreamGetDevice(s, &dev) != hipSuccess) return nullptr;
+  } else if (hipGetDevice(&dev) != hipSuccess) {
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+  ScratchSlot& slot = g_scratch[dev];
+  std::call_once(slot.once, [&] {
+    int cur = 0;
+    slot.err = hipGetDevice(&cur);
+    if (slot.err != hipSuccess) return;
+    if (cur != dev && (slot.err = hipSetDevice(dev)) != hipSuccess) return;
+    void* p = nullptr;
+    slot.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (slot.err == hipSuccess) slot.ptr = p;
+    if (cur != dev) (void)hipSetDevice(cur);
+  });
+  return slot.err == hipSuccess ? slot.ptr : nullptr;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* bk_status_string(int status) {
@@ -1468,6 +1514,31 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
     mp = &master;
   }
   return solve(op, L, o, k, q, seed, mp, Z, ldz, ritz, info, s);
+}
+
+int bk_svd_dense_noalloc(const void* A, int64_t lda, int32_t a_type, const float* a_scales,
+                         const float* A_master, int64_t ld_master, int64_t n, int64_t d,
+                         int32_t k, int32_t q, uint64_t seed, const bk_options* opt, void* Z,
+                         int64_t ldz, double* ritz, bk_info* info, void* stream) {
+  if (!A || !Z || !ritz || lda < d || ldz < k) return BK_EINVAL;
+  // a struct too short to hold the fields read_options takes counts as
+  // "all defaults", as in bk_svd_dense
+  const bool has_opt =
+      opt && opt->struct_size >= static_cast<int32_t>(offsetof(bk_options, timing_phases));
+  if (has_opt && opt->save_for_backward)
+    return BK_EINVAL;  // the next call would overwrite the saved state
+  const size_t need = bk_svd_dense_workspace(n, d, k, q, a_type, opt);
+  if (need == 0) return BK_EINVAL;
+  if (need > BK_NOALLOC_SCRATCH_BYTES) return BK_ENOMEM;
+  bk_options o{};
+  if (has_opt)
+    std::memcpy(&o, opt, std::min(sizeof(o), static_cast<size_t>(opt->struct_size)));
+  o.struct_size = static_cast<int32_t>(sizeof(o));
+  o.timing = 0;  // timing would create events; launch counts are kept
+  void* ws = scratch_address(static_cast<hipStream_t>(stream));
+  if (!ws) return BK_EHIP;
+  return bk_svd_dense(A, lda, a_type, a_scales, A_master, ld_master, n, d, k, q, seed, &o, Z,
+                      ldz, ritz, info, ws, BK_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k, int32_t q,

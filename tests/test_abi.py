@@ -228,3 +228,25 @@ def test_too_small_workspace_gives_enomem(lib):
     if need > 0:
         assert lib.bk_dense_product(1, P, 400, L.F32, None, 600, 400, P, 8, 8, P, 8, P,
                                     need - 1, None) == L.ENOMEM
+
+
+def test_noalloc_size_limit_and_rules(lib):
+    """The allocation-free solve rejects a problem whose workspace exceeds
+    its static scratch (BK_ENOMEM) and a save_for_backward request
+    (BK_EINVAL) before touching the device (no GPU needed)."""
+    P = C.c_void_p(4096)
+    limit = 64 << 20
+    o = _opt()
+    assert lib.bk_svd_dense_workspace(2000, 1000, 10, 8, L.F64, C.byref(o)) <= limit
+    big = lib.bk_svd_dense_workspace(8192, 4096, 32, 10, L.F32, C.byref(o))
+    assert big > limit
+    assert lib.bk_svd_dense_noalloc(P, 4096, L.F32, None, None, 0, 8192, 4096, 32, 10, 0,
+                                    C.byref(o), P, 32, P, None, None) == L.ENOMEM
+    o.save_for_backward = 1
+    assert lib.bk_svd_dense_noalloc(P, 1000, L.F64, None, None, 0, 2000, 1000, 10, 8, 0,
+                                    C.byref(o), P, 10, P, None, None) == L.EINVAL
+    o = _opt()
+    assert lib.bk_svd_dense_noalloc(None, 1000, L.F64, None, None, 0, 2000, 1000, 10, 8, 0,
+                                    C.byref(o), P, 10, P, None, None) == L.EINVAL
+    assert lib.bk_svd_dense_noalloc(P, 1000, L.F64, None, None, 0, 2000, 1000, 0, 8, 0,
+                                    C.byref(o), P, 10, P, None, None) == L.EINVAL
