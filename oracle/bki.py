@@ -336,7 +336,7 @@ def block_lanczos(A, Pi, k: int, q: int, *, center: bool = False,
 
 
 def block_krylov_planted(U, sigma, V, Pi, k: int, q: int, *,
-                         tau: float = 1e-12) -> BKIResult:
+                         tau: float = 1e-12, basis: bool = True) -> BKIResult:
     """Algorithm 2 on A = U diag(sigma) V^T (U n x r, V d x r, orthonormal
     columns), worked in the coordinates of the factors.
 
@@ -347,10 +347,15 @@ def block_krylov_planted(U, sigma, V, Pi, k: int, q: int, *,
     Rayleigh-Ritz gives the same theta, Z = U Z_S (Lemma 1).  The breakdown
     tests see the same norms and singular values (U has orthonormal
     columns), so q_eff agrees as well.  route A (block_krylov) runs on S as
-    it stands; only the n x r and d x r factor products are outside it."""
+    it stands; only the n x r and d x r factor products are outside it.
+
+    U may be any n x r object with ``shape`` and ``@`` (e.g. one that reads
+    a large factor in row blocks).  basis=False leaves Q as None (mapping
+    the n x m basis back costs an n x r x m product; Z needs n x r x k)."""
     import scipy.sparse as sp
 
-    U = np.asarray(U, dtype=np.float64)
+    if isinstance(U, np.ndarray) or not hasattr(U, "__matmul__"):
+        U = np.asarray(U, dtype=np.float64)
     V = np.asarray(V, dtype=np.float64)
     sigma = np.asarray(sigma, dtype=np.float64)
     r = sigma.shape[0]
@@ -360,5 +365,6 @@ def block_krylov_planted(U, sigma, V, Pi, k: int, q: int, *,
     Ps = V.T @ np.asarray(Pi, dtype=np.float64)
     validate(U.shape[0], V.shape[0], k, q, Ps.shape[1])
     res = block_krylov(S, Ps, k, q, tau=tau)
-    Z = sign_normalize(U @ res.Z)
-    return BKIResult(Z, res.sigma, res.theta, U @ res.Q, res.Ubar, res.q_eff)
+    Z = sign_normalize(np.asarray(U @ res.Z, dtype=np.float64))
+    Q = np.asarray(U @ res.Q, dtype=np.float64) if basis else None
+    return BKIResult(Z, res.sigma, res.theta, Q, res.Ubar, res.q_eff)

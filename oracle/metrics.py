@@ -14,6 +14,10 @@ leg may import this.
   z_i^T A A^T z_i, and the two norms of the residual A - Z Z^T A from their
   definitions (dense, small inputs).
 * Largest principal angle between two k-dimensional subspaces.
+* Residual norms of Ritz pairs, ||A A^T z_i - sigma_i^2 z_i||: for a unit z_i
+  and the symmetric A A^T, some eigenvalue of A A^T lies within that norm of
+  sigma_i^2 (Bauer-Fike), the certificate of the Rayleigh-Ritz values of
+  Lemma 1.
 """
 from __future__ import annotations
 
@@ -21,7 +25,7 @@ import numpy as np
 
 __all__ = ["frobenius_ratio", "spectral_ratio", "per_vector_error",
            "principal_angle", "principal_angle_sin", "frobenius_sq", "captured",
-           "residual_norms"]
+           "residual_norms", "ritz_residuals"]
 
 
 def _op(A):
@@ -46,6 +50,16 @@ def captured(A, Z) -> np.ndarray:
     """z_i^T A A^T z_i = ||A^T z_i||^2 for each column of Z."""
     W = _op(A).tmul(np.asarray(Z, dtype=np.float64))
     return np.sum(W ** 2, axis=0)
+
+
+def ritz_residuals(A, Z, sigma) -> np.ndarray:
+    """||A A^T z_i - sigma_i^2 z_i||_2 for each column z_i of Z (centring of a
+    centred operator included)."""
+    op = _op(A)
+    Z = np.asarray(Z, dtype=np.float64)
+    s2 = np.asarray(sigma, dtype=np.float64) ** 2
+    R = op.mul(op.tmul(Z)) - Z * s2[None, :]
+    return np.sqrt(np.sum(R ** 2, axis=0))
 
 
 def residual_norms(A, Z) -> tuple[float, float]:

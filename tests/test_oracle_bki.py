@@ -443,3 +443,59 @@ def test_planted_factor_route_exact_top_k():
     res = bki.block_krylov_planted(U, sig, V, philox.gaussian(63, 45, 3), 3, 3)
     assert np.allclose(res.sigma, sig[:3], rtol=1e-12)
     assert _proj_dist(res.Z, U[:, :3]) < 1e-10
+
+
+class _RowBlocks:
+    """An n x r factor read in row blocks through ``@`` (as a caller holding
+    a factor too large to copy at once would supply it)."""
+
+    def __init__(self, U, rows):
+        self.U, self.rows, self.shape = U, rows, U.shape
+
+    def __matmul__(self, X):
+        return np.vstack([self.U[r0:r0 + self.rows] @ X
+                          for r0 in range(0, self.shape[0], self.rows)])
+
+
+def test_planted_factor_route_streamed_factor_without_basis():
+    sig = workloads.spectrum("pow08", 100)
+    U, V, A = _planted_factors(150, 100, sig, 64)
+    Pi = philox.gaussian(65, 100, 5)
+    a = bki.block_krylov_planted(U, sig, V, Pi, 5, 3)
+    b = bki.block_krylov_planted(_RowBlocks(U, 37), sig, V, Pi, 5, 3, basis=False)
+    assert b.Q is None
+    assert np.array_equal(a.sigma, b.sigma)
+    assert np.max(np.abs(a.Z - b.Z)) < 1e-13
+
+
+# ------------------------------------------- residual norms of Ritz pairs --
+def test_ritz_residuals_closed_forms():
+    s = np.array([3.0, 2.0, 1.5, 0.5, 0.25])
+    U, V, A = _planted_factors(40, 30, s, 70)
+    # exact singular pairs: zero residual
+    r0 = metrics.ritz_residuals(A, U[:, :3], s[:3])
+    assert np.all(r0 < 1e-13)
+    # z = (u1 + u2)/sqrt(2), sigma^2 = (s1^2 + s2^2)/2: A A^T z - sigma^2 z =
+    # (s1^2 - s2^2)/2 (u1 - u2)/sqrt(2), of norm |s1^2 - s2^2|/2
+    z = (U[:, :1] + U[:, 1:2]) / np.sqrt(2.0)
+    sig = np.sqrt((s[0] ** 2 + s[1] ** 2) / 2.0)
+    r = metrics.ritz_residuals(A, z, [sig])
+    assert r[0] == pytest.approx((s[0] ** 2 - s[1] ** 2) / 2.0, rel=1e-13)
+    # a wrong sigma on an exact vector: |s_j^2 - sigma^2|
+    r = metrics.ritz_residuals(A, U[:, 2:3], [1.0])
+    assert r[0] == pytest.approx(abs(s[2] ** 2 - 1.0), rel=1e-13)
+
+
+def test_ritz_residuals_bauer_fike_and_centring():
+    rng = np.random.default_rng(71)
+    A = rng.standard_normal((60, 25))
+    lam = np.linalg.eigvalsh(A @ A.T)           # includes the 35 zeros
+    Z = np.linalg.qr(rng.standard_normal((60, 6)))[0]
+    sig = rng.uniform(0.5, 8.0, 6)
+    r = metrics.ritz_residuals(A, Z, sig)
+    for i in range(6):
+        assert np.min(np.abs(lam - sig[i] ** 2)) <= r[i] * (1 + 1e-12)
+    # centred operator = the explicitly centred dense matrix
+    Ac = A - A.mean(axis=1, keepdims=True)
+    rc = metrics.ritz_residuals(bki.LinearOperator(A, center=True), Z, sig)
+    assert np.allclose(rc, metrics.ritz_residuals(Ac, Z, sig), rtol=1e-12)
