@@ -3,19 +3,26 @@
 A step is one whole solve (sketch, Krylov products, projection,
 CholeskyQR, M = W^T W -- or the block-tridiagonal T of block Lanczos with
 --method lanczos --, the eigen-solve, Z = Q U_k) on one synthetic input
-already resident in HBM.  Default workload: the term-document CSR matrix
-(11000 x 130000, ~1.47M nonzeros, log-normal row lengths, Zipf(1.1) terms,
-log(1+tf)*idf values), k = 20, q = 10, implicit row centring, FP32.
+already resident in HBM.
 
-Metric: GB/s of the Krylov block products A.X / A^T.Y, i.e. the algorithmic
-bytes those products must move in one solve divided by the time of the whole
-solve.  The roofline object reports the dominant product kernel alone:
-algorithmic bytes per launch / its average launch time (HIP events recorded
-on the solve's stream inside the timed steps) against the 8 TB/s HBM peak.
+Default workload: the large dense matrix, 131072 x 32768 with planted
+singular values sigma_i = i^-0.8, k = 256, q = 8.  The plain FP32 path is
+the timed line; the FP8 e4m3 copy (128 x 128 tile scales, one FP32
+correction pass on the FP32 master) is timed in the same run on the same
+matrix and reported beside it with its speedup.  Both results are compared
+with the float64 oracle (Algorithm 2 run in the coordinates of the planted
+factors) and the oracle's block products are timed on the host cores.
+
+Metric: throughput of the Krylov block products A.X / A^T.Y over whole
+solves -- TFLOP/s when the product is bound by the matrix cores (FP32 with
+arithmetic intensity above the FP32 ridge), GB/s of algorithmic bytes
+otherwise.  The roofline object reports the dominant product alone (HIP
+events recorded on the solve's stream inside the timed steps).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-       [--workload csr2|dense1|dense3|dense4|dense5] [--precision plain|bf16|fp8]
-       [--method bki|lanczos] [--time-to-eps] [--metrics-q Q]
+       [--workload dense5|dense3|dense4|dense1|csr2] [--precision plain|bf16|fp8]
+       [--compare auto|none|bf16|fp8] [--method bki|lanczos|si] [--time-to-eps]
+       [--metrics-q Q] [--no-parity] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -36,7 +43,7 @@ import workloads  # noqa: E402
 METRIC = ("Krylov A·X/Aᵀ·Y GB/s or TFLOP/s & time-to-ε "
           "(BF16/FP8 vs FP32), 1 GPU")
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFS = 157.3
+PEAK_TFS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
 DESCR = {
     "csr2": "term-document CSR 11000x130000 (~1.47M nnz, log-normal rows, Zipf(1.1) "
             "terms, log(1+tf)*idf), k=20, q=10, implicit row centring",
@@ -45,6 +52,8 @@ DESCR = {
     "dense4": "dense planted sigma_i=1/i 8192x4096, k=32, q=10",
     "dense5": "dense planted sigma_i=i^-0.8 131072x32768, k=256, q=8",
 }
+# low-precision form timed beside the plain FP32 path (--compare auto)
+AUTO_COMPARE = {"dense5": "fp8", "dense3": "bf16"}
 
 
 def log(msg):
@@ -100,16 +109,83 @@ def read_traffic(kernel_key, sha):
         return None
 
 
+def value_unit(kind, dtype, n, d, pw, a_bytes):
+    """TFLOP/s for FP32 / FP64 dense products above the ridge of their
+    matrix-core peak (flops per byte), GB/s otherwise."""
+    if kind != "dense" or dtype not in ("f32", "f64"):
+        return "GB/s"
+    ai = 2.0 * n * d * pw / (n * d * a_bytes)
+    ridge = PEAK_TFS[dtype] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    return "TFLOP/s" if ai > ridge else "GB/s"
+
+
+def rate(unit, bytes_, flops, ms):
+    if unit == "TFLOP/s":
+        return flops / (ms * 1e-3) / 1e12
+    return bytes_ / (ms * 1e-3) / 1e9
+
+
+# --------------------------------------------------------------- legs --
+def timed_leg(step, steps, warmup):
+    """`warmup` untimed solves, `steps` timed ones (the last two record HIP
+    events around the product phases only: an event between two kernels
+    stalls the queue for ~4 us), then two solves with events on every phase
+    for the breakdown."""
+    import torch
+    timed_phases = ("ax", "aty")
+    n_ev = min(2, steps)
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    r = None
+    for i in range(steps):
+        r = step(timed_phases if i >= steps - n_ev else False)
+        infos.append(r.info)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    full = [step(True).info for _ in range(2)]
+    torch.cuda.synchronize()
+    ph = {p: sum(float(i["ms"][p]) for i in full) / len(full) for p in full[0]["ms"]}
+    return {"ms": ms, "infos": infos, "n_ev": n_ev, "phases": ph, "launches": full[0]["launches"],
+            "last": r}
+
+
+def dominant_product(leg, kind):
+    """(phase, average ms per launch) of the larger product phase over the
+    event-timed steps."""
+    infos, n_ev = leg["infos"], leg["n_ev"]
+
+    def tot(key, what="ms"):
+        return sum(float(i[what][key]) for i in infos[-n_ev:])
+    dom = "ax" if tot("ax") >= tot("aty") else "aty"
+    if kind == "csr":
+        # one product kernel per launch in these phases (the combine and
+        # centring kernels are timed in phases of their own)
+        nl = tot(dom, "launches")
+    else:
+        # a dense product is a short sequence of kernels (operand packing,
+        # the MFMA or vector product, the split reduction): rate per product
+        nl = n_ev * (infos[-1]["q_eff"] + 1)
+    return dom, tot(dom) / max(nl, 1)
+
+
 # ---------------------------------------------------------------- main --
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="csr2", choices=sorted(workloads.WORKLOADS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="dense5", choices=sorted(workloads.WORKLOADS))
     ap.add_argument("--precision", default="plain", choices=["plain", "bf16", "fp8"])
+    ap.add_argument("--compare", default="auto", choices=["auto", "none", "bf16", "fp8"],
+                    help="low-precision copy timed beside the plain path on the same matrix "
+                         "(auto: FP8 for dense5, BF16 for dense3, none otherwise)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true",
+                    help="skip the comparison with the float64 oracle")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
     ap.add_argument("--method", default="bki", choices=["bki", "lanczos", "si"],
                     help="Rayleigh-Ritz matrix: W^T W (Algorithm 2) or the block-tridiagonal "
@@ -120,7 +196,7 @@ def main():
     ap.add_argument("--time-to-eps", action="store_true",
                     help="dense workloads: for each eps in 1e-1, 1e-2, 1e-3 the smallest q whose "
                          "per-vector error (eq. 3, planted spectrum, measured on the GPU) is at "
-                         "most eps, and the time of one solve at that q")
+                         "most eps, and the time of one solve at that q (each timed form)")
     ap.add_argument("--metrics-q", type=int, default=4, metavar="Q",
                     help="depth of the GPU spectral-residual estimate of the error measures "
                          "taken after the timed steps (-1: skip them)")
@@ -144,202 +220,434 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     bk.load()
-    dev = torch.device("cuda:0")
     w = workloads.WORKLOADS[args.workload]
-    k, q = w.k, w.q
-    t_gen = time.perf_counter()
-    host_inputs = {}
-    prep_ms = {}
     if w.kind == "csr":
-        rp, ci, va = make_csr(w)
-        host_inputs = {"rp": rp, "ci": ci, "va": va}
-        g_rp = torch.from_numpy(rp).to(dev)
-        g_ci = torch.from_numpy(ci).to(dev)
-        g_va = torch.from_numpy(va).to(dev)
-        nnz = int(ci.size)
-        bx, by = csr_product_bytes(w.n, w.d, nnz, args.block_size or k)
-        dtype = "f32"
-        # CSR of A^T: an input layout built once on the GPU (as a caller
-        # solving repeatedly would), timed on its own, outside the steps
-        tr = bk.csr_transpose(g_rp, g_ci, g_va, w.d)
-        torch.cuda.synchronize()
-        t0p = time.perf_counter()
-        for _ in range(3):
-            tr = bk.csr_transpose(g_rp, g_ci, g_va, w.d)
-        torch.cuda.synchronize()
-        prep_ms["csr_transpose"] = round((time.perf_counter() - t0p) * 1e3 / 3, 4)
-
-        def step(timing):
-            return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
-                              center=w.center, transpose=tr, timing=timing,
-                              method=args.method, block_size=args.block_size)
-
-        def error_measures(Z, qs):
-            return bk.error_metrics_csr(g_rp, g_ci, g_va, w.n, w.d, Z, q_spec=qs,
-                                        seed=w.seed_sketch + 1, center=w.center, transpose=tr)
-        kern_src = ["csr.hip"]
-        kern_names = {"ax": "csr_product_kernel (A.X, CSR of A)",
-                      "aty": "csr_product_kernel (A^T.Y, CSR of A^T)"}
+        out = run_csr(args, w, bk, torch)
     else:
-        sv = workloads.spectrum(w.spectrum, min(w.n, w.d))
-        if w.n * w.d <= 4_000_000:
-            A64 = workloads.planted_dense(w.n, w.d, sv, w.seed_matrix)
-            host_inputs = {"A": A64}
-            A = torch.from_numpy(A64).to(dev)
-            if w.dtype != "f64":
-                A = A.float()
-        else:
-            A = workloads.planted_dense_torch(w.n, w.d, sv, w.seed_matrix, device=dev,
-                                              noise=w.noise, noise_seed=w.seed_noise)
-        if w.dtype == "f64":
-            A = A.double()
-        kw = {}
-        a_bytes = A.element_size()
-        dtype = "f64" if A.dtype == torch.float64 else "f32"
-        if args.precision in ("bf16", "fp8"):
-            # the low-precision copy is made once, outside the timed steps
-            torch.cuda.synchronize()
-            t0p = time.perf_counter()
-            if args.precision == "bf16":
-                A_in = bk.quantize(A, "bf16")
-                kw = {"A_master": A}
-                a_bytes, dtype = 2, "bf16"
-            else:
-                A_in, sc = bk.quantize(A, "fp8")
-                kw = {"A_master": A, "a_scales": sc}
-                a_bytes, dtype = 1, "fp8"
-            torch.cuda.synchronize()
-            prep_ms["quantize"] = round((time.perf_counter() - t0p) * 1e3, 4)
-        else:
-            A_in = A
-        x_bytes = 8 if A.dtype == torch.float64 else 4
-        bx, by = dense_product_bytes(w.n, w.d, args.block_size or k, a_bytes, x_bytes)
+        out = run_dense(args, w, bk, torch)
+    print(json.dumps(out), flush=True)
 
-        def step(timing):
-            return bk.svd_dense(A_in, k, q, seed=w.seed_sketch, timing=timing,
-                                method=args.method, block_size=args.block_size, **kw)
 
-        def error_measures(Z, qs):
-            return bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), q_spec=qs,
-                                          seed=w.seed_sketch + 1)
-
-        def solve_q(qq):
-            return bk.svd_dense(A_in, k, qq, seed=w.seed_sketch, **kw)
-
-        def per_vector(Z):
-            m = bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(),
-                                       sigma_true=sv[:k + 1], q_spec=0, seed=w.seed_sketch + 1)
-            return m.values["per_vector"]
-        kern_src = ["gemm.hip", "gemm_mfma.hip"]
-        kern_names = {"ax": "A.X product (operand pack + product kernel)",
-                      "aty": "A^T.Y product (operand pack + product kernel + split reduction)"}
-    torch.cuda.synchronize()
-    log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s ({args.workload})")
-
-    # The last n_ev timed steps record events around the product phases (the
-    # roofline kernel's launch durations); an event between two kernels
-    # stalls the queue (~4 us), so the other timed steps run without them.
-    # The per-phase breakdown comes from extra steps after the timed region.
-    timed_phases = ("ax", "aty")
-    n_ev = min(2, args.steps)
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    infos = []
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r = step(timed_phases if i >= args.steps - n_ev else False)
-        infos.append(r.info)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    bytes_per_solve = (q + 1) * (bx + by)
-    value = bytes_per_solve / (ms_step * 1e-3) / 1e9
-    nbd = 2
-    full = [step(True).info for _ in range(nbd)]
-    torch.cuda.synchronize()
-
-    def tot(key, what="ms"):
-        return sum(float(i[what][key]) for i in infos[-n_ev:])
-    ph = {p: sum(float(i["ms"][p]) for i in full) / nbd for p in full[0]["ms"]}
-    if args.breakdown:
-        log("phase ms/step: " + ", ".join(f"{p}={v:.3f}" for p, v in ph.items()))
-        log(f"launches/step: {full[0]['launches']}")
-    dom = "ax" if tot("ax") >= tot("aty") else "aty"
-    if w.kind == "csr":
-        # one product kernel per launch in these phases (the combine and
-        # centring kernels are timed in phases of their own)
-        nl = tot(dom, "launches")
-    else:
-        # a dense product is a short sequence of kernels (operand packing,
-        # the MFMA or vector product, the split reduction): rate per product
-        nl = n_ev * (infos[-1]["q_eff"] + 1)
-    avg_ms = tot(dom) / max(nl, 1)
-    per_launch = bx if dom == "ax" else by
-    achieved = per_launch / (avg_ms * 1e-3) / 1e9
-    sha = source_sha(kern_src)
-    kernel_key = f"{'csr_product' if w.kind == 'csr' else 'dense_product'}_{dom}_{args.workload}"
-    traffic = read_traffic(kernel_key, sha)
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "kernel": kern_names[dom],
-            "avg_launch_ms": round(avg_ms, 5), "event_steps": n_ev,
-            "algorithmic_bytes_per_launch": int(per_launch), "source_sha": sha}
-    if w.kind == "dense" and args.precision == "plain":
-        flops = 2.0 * w.n * w.d * (args.block_size or k)
-        tf = flops / (avg_ms * 1e-3) / 1e12
-        if flops / per_launch > FP32_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9):
-            roof.update({"bound": "mfma", "achieved": round(tf, 3),
-                         "peak": FP32_PEAK_TFS if dtype == "f32" else 78.6,
-                         "unit": "TFLOP/s", "frac": round(tf / (FP32_PEAK_TFS if dtype == "f32" else 78.6), 4)})
-        roof["avg_ms_is"] = "per product"
-
-    out = {
+def base_record(args, w, value, unit, ms, dtype, extra_config):
+    cfg = {"workload": f"{args.workload}: {DESCR[args.workload]}",
+           "n": w.n, "d": w.d, "k": w.k, "q": w.q, "precision": args.precision,
+           "method": args.method, "block_size": args.block_size or w.k}
+    cfg.update(extra_config)
+    return {
         "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GB/s",
+        "value": round(value, 4),
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {DESCR[args.workload]}",
-                   "n": w.n, "d": w.d, "k": k, "q": q,
-                   "precision": args.precision, "method": args.method,
-                   "block_size": args.block_size or k,
-                   "product_bytes_per_solve": int(bytes_per_solve)},
-        "roofline": roof,
-        "phases_ms_per_step": {p: round(v, 4) for p, v in ph.items()},
-        "products_all_kernels": products_all_kernels(ph, infos[-1]["q_eff"], bx, by),
-        "input_prep_ms_untimed": prep_ms,
-        "q_eff": infos[-1]["q_eff"],
-        "jacobi_sweeps": infos[-1]["jacobi_sweeps"],
+        "config": cfg,
     }
 
-    if args.metrics_q >= 0:
-        out["error_measures"] = gpu_error_measures(error_measures, r.Z, args.metrics_q)
-    if args.time_to_eps:
-        if w.kind == "dense":
-            out["time_to_eps"] = time_to_eps(solve_q, per_vector, q)
-        else:
-            out["time_to_eps"] = {"skipped": "needs the true spectrum (planted dense inputs)"}
 
+# ---------------------------------------------------------------- CSR --
+def run_csr(args, w, bk, torch):
+    dev = torch.device("cuda:0")
+    k, q = w.k, w.q
+    pw = args.block_size or k
+    t_gen = time.perf_counter()
+    rp, ci, va = make_csr(w)
+    g_rp = torch.from_numpy(rp).to(dev)
+    g_ci = torch.from_numpy(ci).to(dev)
+    g_va = torch.from_numpy(va).to(dev)
+    nnz = int(ci.size)
+    bx, by = csr_product_bytes(w.n, w.d, nnz, pw)
+    # CSR of A^T: an input layout built once on the GPU (as a caller solving
+    # repeatedly would), timed on its own, outside the steps
+    tr = bk.csr_transpose(g_rp, g_ci, g_va, w.d)
+    torch.cuda.synchronize()
+    t0p = time.perf_counter()
+    for _ in range(3):
+        tr = bk.csr_transpose(g_rp, g_ci, g_va, w.d)
+    torch.cuda.synchronize()
+    prep_ms = {"csr_transpose": round((time.perf_counter() - t0p) * 1e3 / 3, 4)}
+    log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s ({args.workload})")
+
+    def step(timing):
+        return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
+                          center=w.center, transpose=tr, timing=timing,
+                          method=args.method, block_size=args.block_size)
+
+    leg = timed_leg(step, args.steps, args.warmup)
+    if args.breakdown:
+        log("phase ms/step: " + ", ".join(f"{p}={v:.3f}" for p, v in leg["phases"].items()))
+    q_eff = leg["last"].info["q_eff"]
+    bytes_per_solve = (q + 1) * (bx + by)
+    value = bytes_per_solve / (leg["ms"] * 1e-3) / 1e9
+    dom, avg_ms = dominant_product(leg, "csr")
+    per_launch = bx if dom == "ax" else by
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    sha = source_sha(["csr.hip"])
+    kernel_key = f"csr_product_{dom}_{args.workload}"
+    names = {"ax": "csr_product_kernel (A.X, CSR of A)",
+             "aty": "csr_product_kernel (A^T.Y, CSR of A^T)"}
+    out = base_record(args, w, value, "GB/s", leg["ms"], "f32",
+                      {"product_bytes_per_solve": int(bytes_per_solve)})
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                       "traffic": read_traffic(kernel_key, sha), "kernel": names[dom],
+                       "avg_launch_ms": round(avg_ms, 5), "event_steps": leg["n_ev"],
+                       "algorithmic_bytes_per_launch": int(per_launch), "source_sha": sha}
+    out["phases_ms_per_step"] = {p: round(v, 4) for p, v in leg["phases"].items()}
+    out["products_all_kernels"] = products_all_kernels(leg["phases"], q_eff, bx, by)
+    out["input_prep_ms_untimed"] = prep_ms
+    out["q_eff"] = q_eff
+    if args.metrics_q >= 0:
+        out["error_measures"] = gpu_error_measures(
+            lambda Z, qs: bk.error_metrics_csr(g_rp, g_ci, g_va, w.n, w.d, Z, q_spec=qs,
+                                               seed=w.seed_sketch + 1, center=w.center,
+                                               transpose=tr),
+            leg["last"].Z, args.metrics_q)
+    if args.time_to_eps:
+        out["time_to_eps"] = {"skipped": "needs the true spectrum (planted dense inputs)"}
+    if not (args.no_cpu_baseline and args.no_parity):
+        import scipy.sparse as sp
+        A = sp.csr_matrix((va.astype(np.float64), ci, rp), shape=(w.n, w.d))
+        ref, base = oracle_solves(args, w, A, tau=1e-5, f32=True,
+                                  seconds=0.0 if args.no_cpu_baseline else args.cpu_seconds)
+        if not args.no_cpu_baseline:
+            per = base.pop("sec_per_solve")
+            base.update({"value": round(bytes_per_solve / per / 1e9, 4), "unit": "GB/s"})
+            out["cpu_baseline"] = base
+        if not args.no_parity:
+            out["parity"] = parity_record(ref, leg["last"], k)
+    return out
+
+
+# -------------------------------------------------------------- dense --
+def run_dense(args, w, bk, torch):
+    dev = torch.device("cuda:0")
+    k, q = w.k, w.q
+    pw = args.block_size or k
+    compare = args.compare
+    if compare == "auto":
+        compare = AUTO_COMPARE.get(args.workload, "none") if args.precision == "plain" else "none"
+    if args.precision != "plain" or w.dtype == "f64":
+        compare = "none"
+    t_gen = time.perf_counter()
+    sv = workloads.spectrum(w.spectrum, min(w.n, w.d))
+    factors = None
+    gen_stats = {}
+    if w.n * w.d <= 4_000_000:
+        A64 = workloads.planted_dense(w.n, w.d, sv, w.seed_matrix, noise=w.noise,
+                                      noise_seed=w.seed_noise)
+        A = torch.from_numpy(A64).to(dev)
+        if w.dtype != "f64":
+            A = A.float()
+    else:
+        # noise-free planted matrices keep their factors for the oracle
+        want_f = not args.no_parity and w.noise == 0.0
+        res = workloads.planted_dense_torch(w.n, w.d, sv, w.seed_matrix, device=dev,
+                                            noise=w.noise, noise_seed=w.seed_noise,
+                                            return_factors=want_f, stats=gen_stats)
+        A, factors = res if want_f else (res, None)
+    if w.dtype == "f64":
+        A = A.double()
+    prep_ms = {}
+
+    def lowp(prec):
+        torch.cuda.synchronize()
+        t0p = time.perf_counter()
+        if prec == "bf16":
+            A_in, kw, a_bytes = bk.quantize(A, "bf16"), {"A_master": A}, 2
+        else:
+            A_in, sc = bk.quantize(A, "fp8")
+            kw, a_bytes = {"A_master": A, "a_scales": sc}, 1
+        torch.cuda.synchronize()
+        prep_ms[f"quantize_{prec}"] = round((time.perf_counter() - t0p) * 1e3, 4)
+        return A_in, kw, a_bytes
+
+    x_bytes = 8 if A.dtype == torch.float64 else 4
+    main_dtype = "f64" if A.dtype == torch.float64 else "f32"
+    if args.precision == "plain":
+        A_in, kw, a_bytes = A, {}, A.element_size()
+    else:
+        A_in, kw, a_bytes = lowp(args.precision)
+        main_dtype = args.precision
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.perf_counter() - t_gen:.1f}s ({args.workload})")
+
+    def stepper(Ai, kwi):
+        def step(timing):
+            return bk.svd_dense(Ai, k, q, seed=w.seed_sketch, timing=timing,
+                                method=args.method, block_size=args.block_size, **kwi)
+        return step
+
+    flops_per_product = 2.0 * w.n * w.d * pw
+    unit = value_unit("dense", main_dtype, w.n, w.d, pw, a_bytes)
+
+    def leg_summary(leg, dtype, a_b):
+        bx, by = dense_product_bytes(w.n, w.d, pw, a_b, x_bytes)
+        nprod = 2 * (leg["last"].info["q_eff"] + 1)
+        per_solve_bytes = (bx + by) / 2 * nprod
+        per_solve_flops = flops_per_product * nprod
+        u = value_unit("dense", dtype, w.n, w.d, pw, a_b)
+        return {"unit": u, "value": rate(u, per_solve_bytes, per_solve_flops, leg["ms"]),
+                "bytes_per_product": (bx + by) / 2, "products_per_solve": nprod,
+                "GBps": per_solve_bytes / (leg["ms"] * 1e-3) / 1e9,
+                "TFLOPs": per_solve_flops / (leg["ms"] * 1e-3) / 1e12}
+
+    leg = timed_leg(stepper(A_in, kw), args.steps, args.warmup)
+    log(f"{main_dtype} leg: {leg['ms']:.2f} ms/solve")
+    if args.breakdown:
+        log("phase ms/step: " + ", ".join(f"{p}={v:.3f}" for p, v in leg["phases"].items()))
+    summ = leg_summary(leg, main_dtype, a_bytes)
+    out = base_record(args, w, summ["value"], unit, leg["ms"], main_dtype,
+                      {"product_bytes_per_solve": int(summ["bytes_per_product"]
+                                                      * summ["products_per_solve"]),
+                       "product_flops_per_solve": flops_per_product * summ["products_per_solve"]})
+    out["roofline"] = dense_roofline(leg, args, w, main_dtype, a_bytes, x_bytes, pw)
+    out["phases_ms_per_step"] = {p: round(v, 4) for p, v in leg["phases"].items()}
+    out["q_eff"] = leg["last"].info["q_eff"]
+    out["jacobi_sweeps"] = leg["last"].info["jacobi_sweeps"]
+
+    legs = {main_dtype: leg}
+    if compare != "none":
+        Alp, kwlp, ablp = lowp(compare)
+        lp = timed_leg(stepper(Alp, kwlp), args.steps, args.warmup)
+        log(f"{compare} leg: {lp['ms']:.2f} ms/solve")
+        s2 = leg_summary(lp, compare, ablp)
+        out["low_precision"] = {
+            "precision": compare, "refine": True, "ms_per_step": round(lp["ms"], 4),
+            "speedup_vs_plain": round(leg["ms"] / lp["ms"], 3),
+            "products_GBps": round(s2["GBps"], 2), "products_TFLOPs": round(s2["TFLOPs"], 2),
+            "roofline": dense_roofline(lp, args, w, compare, ablp, x_bytes, pw),
+            "phases_ms_per_step": {p: round(v, 4) for p, v in lp["phases"].items()},
+            "q_eff": lp["last"].info["q_eff"]}
+        legs[compare] = lp
+    out["input_prep_ms_untimed"] = prep_ms
+    if gen_stats:
+        out["input_storage_rounding_fro"] = gen_stats.get("storage_rounding_fro")
+
+    if args.metrics_q >= 0:
+        out["error_measures"] = gpu_error_measures(
+            lambda Z, qs: bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), q_spec=qs,
+                                                 seed=w.seed_sketch + 1),
+            leg["last"].Z, args.metrics_q)
+    if args.time_to_eps:
+        tte = {}
+        for name, (Ai, kwi) in {main_dtype: (A_in, kw)}.items():
+            tte[name] = time_to_eps(lambda qq: bk.svd_dense(Ai, k, qq, seed=w.seed_sketch, **kwi),
+                                    lambda Z: per_vector_gpu(bk, A, Z, sv, k, w), q)
+        if compare != "none":
+            tte[compare] = time_to_eps(
+                lambda qq: bk.svd_dense(Alp, k, qq, seed=w.seed_sketch, **kwlp),
+                lambda Z: per_vector_gpu(bk, A, Z, sv, k, w), q)
+        out["time_to_eps"] = tte
+
+    # the host side: the oracle (float64) for parity, its products for the
+    # CPU baseline
+    results = {name: lg["last"] for name, lg in legs.items()}
+    for lg in legs.values():
+        lg["last"] = None
+    if compare != "none":
+        del Alp, kwlp
+    A_host = None
+    if not (args.no_parity and args.no_cpu_baseline):
+        t_h = time.perf_counter()
+        A_host = A.cpu().numpy() if w.n * w.d > 4_000_000 else None
+        log(f"A copied to the host in {time.perf_counter() - t_h:.1f}s")
+    if not args.no_parity:
+        out["parity"] = dense_parity(args, w, k, q, pw, A, A_host, factors, results, torch)
+    del factors
     if not args.no_cpu_baseline:
-        out["cpu_baseline"], out["parity"] = cpu_baseline(args, w, host_inputs, r,
-                                                          bytes_per_solve)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = dense_cpu_baseline(args, w, pw, A, A_host, unit, a_bytes,
+                                                 x_bytes, flops_per_product)
+    return out
+
+
+def per_vector_gpu(bk, A, Z, sv, k, w):
+    m = bk.error_metrics_dense(A, Z.to(A.dtype).contiguous(), sigma_true=sv[:k + 1], q_spec=0,
+                               seed=w.seed_sketch + 1)
+    return m.values["per_vector"]
+
+
+def dense_roofline(leg, args, w, dtype, a_bytes, x_bytes, pw):
+    dom, avg_ms = dominant_product(leg, "dense")
+    bx, by = dense_product_bytes(w.n, w.d, pw, a_bytes, x_bytes)
+    per_launch = bx if dom == "ax" else by
+    sha = source_sha(["gemm.hip", "gemm_mfma.hip"])
+    kernel_key = f"dense_product_{dom}_{args.workload}_{dtype}"
+    names = {"ax": "A.X product (operand pack + product kernel)",
+             "aty": "A^T.Y product (operand pack + product kernel + split reduction)"}
+    roof = {"bound": "hbm", "achieved": round(per_launch / (avg_ms * 1e-3) / 1e9, 2),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(per_launch / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": read_traffic(kernel_key, sha), "kernel": names[dom],
+            "avg_launch_ms": round(avg_ms, 5), "avg_ms_is": "per product",
+            "event_steps": leg["n_ev"], "algorithmic_bytes_per_launch": int(per_launch),
+            "source_sha": sha}
+    flops = 2.0 * w.n * w.d * pw
+    peak = PEAK_TFS[dtype]
+    if flops / per_launch > peak * 1e12 / (HBM_PEAK_GBS * 1e9):
+        tf = flops / (avg_ms * 1e-3) / 1e12
+        roof.update({"bound": "mfma", "achieved": round(tf, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(tf / peak, 4),
+                     "algorithmic_flops_per_launch": flops})
+    return roof
+
+
+class _DeviceRows:
+    """An n x r FP64 device factor read through ``@`` in row blocks copied
+    to the host (the product itself runs on the host in float64)."""
+
+    def __init__(self, U, rows=8192):
+        self.U, self.rows, self.shape = U, rows, tuple(U.shape)
+
+    def __matmul__(self, X):
+        X = np.asarray(X, dtype=np.float64)
+        out = np.empty((self.shape[0], X.shape[1]))
+        for r0 in range(0, self.shape[0], self.rows):
+            r1 = min(self.shape[0], r0 + self.rows)
+            out[r0:r1] = self.U[r0:r1].cpu().numpy() @ X
+        return out
+
+
+def dense_parity(args, w, k, q, pw, A, A_host, factors, results, torch):
+    """The float64 oracle of the same matrix and the same rounded sketch:
+    Algorithm 2 in the coordinates of the planted factors (noise-free
+    planted inputs: exact for U diag(sigma) V^T, the FP32 storage of A
+    perturbing it by input_storage_rounding_fro), else route A on the
+    stored matrix (streamed float64 upcast of the FP32 master)."""
+    from oracle import bki, philox
+
+    f64 = w.dtype == "f64"
+    tau = 1e-11 if f64 else 1e-5
+    Pi = philox.gaussian(w.seed_sketch, w.d, pw)
+    if not f64:
+        Pi = Pi.astype(np.float32).astype(np.float64)
+    if args.method != "bki":
+        return {"skipped": "the oracle legs here cover Algorithm 2 with W^T W"}
+    t0 = time.perf_counter()
+    if factors is not None:
+        U, sig, V = factors
+        ref = bki.block_krylov_planted(_DeviceRows(U), sig.cpu().numpy(), V.cpu().numpy(), Pi,
+                                       k, q, tau=tau, basis=False)
+        route = "planted factors (Algorithm 2 on diag(sigma), sketch V^T Pi, Z mapped by U)"
+    elif A_host is not None:
+        ref = bki.block_krylov(bki.StreamedDense(A_host), Pi, k, q, tau=tau)
+        route = "route A on the stored FP32 matrix (float64, streamed row blocks)"
+    else:
+        Ah = A.cpu().numpy().astype(np.float64)
+        ref = bki.block_krylov(Ah, Pi, k, q, tau=tau)
+        route = "route A on the stored matrix (float64)"
+    out = {"oracle_route": route, "oracle_s": round(time.perf_counter() - t0, 2),
+           "oracle_q_eff": int(ref.q_eff)}
+    for name, r in results.items():
+        out[name] = parity_record(ref, r, k)
+    return out
+
+
+def parity_record(ref, r, k):
+    from oracle import metrics
+    Zg = r.Z.double().cpu().numpy()
+    sg = r.sigma.cpu().numpy()
+    rel = float(np.max(np.abs(sg - ref.sigma) / ref.sigma))
+    j = 0   # widest leading subspace with relative Ritz gap >= 1e-2
+    for jj in range(1, min(k, len(ref.theta) - 1) + 1):
+        if (ref.theta[jj - 1] - ref.theta[jj]) / ref.theta[0] >= 1e-2:
+            j = jj
+    ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j]) if j else None
+    rel_i = np.abs(sg - ref.sigma) / ref.sigma
+    return {"ritz_rel_max": rel, "ritz_rel_median": float(np.median(rel_i)),
+            "principal_angle_rad": ang, "gap_separated_j": j,
+            "angle_at_k_rad": metrics.principal_angle(ref.Z, Zg),
+            "q_eff": int(r.info["q_eff"])}
+
+
+def oracle_threads():
+    from threadpoolctl import threadpool_info
+    return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [1]))
+
+
+def oracle_solves(args, w, A, tau, f32, seconds):
+    """Whole oracle solves of the same input (route of --method), repeated
+    for about `seconds` (at least one): the last result and the timing."""
+    from oracle import bki, philox
+    k, q = w.k, w.q
+    pw = args.block_size or k
+    Pi = philox.gaussian(w.seed_sketch, w.d, pw)
+    if f32:
+        Pi = Pi.astype(np.float32).astype(np.float64)
+    times = []
+    ref = None
+    t_end = time.perf_counter() + seconds
+    while time.perf_counter() < t_end or not times:
+        t0 = time.perf_counter()
+        if args.method == "si":
+            ref = bki.simultaneous_iteration(A, Pi, k, q, center=w.center)
+        elif args.method == "lanczos":
+            ref = bki.block_lanczos(A, Pi, k, q, center=w.center, tau=tau)[0]
+        else:
+            ref = bki.block_krylov(A, Pi, k, q, center=w.center, tau=tau)
+        times.append(time.perf_counter() - t0)
+    threads = oracle_threads()
+    per = float(np.median(times))
+    base = {"cores": threads, "kind": "oracle",
+            "sample": f"{len(times)} whole solves of the same input "
+                      f"(median {per * 1e3:.1f} ms/solve, NumPy/SciPy float64; sparse "
+                      f"products single-threaded, dense BLAS on {threads} threads)",
+            "ms_per_solve": round(per * 1e3, 2), "sec_per_solve": per}
+    return ref, base
+
+
+def dense_cpu_baseline(args, w, pw, A, A_host, unit, a_bytes, x_bytes, flops):
+    """The oracle's block products (its float64 operator on the stored
+    matrix, as it stands) on the host cores for about --cpu-seconds,
+    alternating A.X and A^T.Y, in the unit of the GPU value.  Small inputs
+    run whole oracle solves instead."""
+    from oracle import bki, philox
+    if A_host is None:
+        Ah = A.cpu().numpy().astype(np.float64)
+        _, base = oracle_solves(args, w, Ah, 1e-11 if w.dtype == "f64" else 1e-5,
+                                w.dtype != "f64", args.cpu_seconds)
+        per = base.pop("sec_per_solve")
+        bx, by = dense_product_bytes(w.n, w.d, pw, a_bytes, x_bytes)
+        nprod = 2 * (w.q + 1)
+        base.update({"value": round(rate(unit, (bx + by) / 2 * nprod, flops * nprod,
+                                         per * 1e3), 6), "unit": unit})
+        return base
+    op = bki.StreamedDense(A_host)
+    X = philox.gaussian(w.seed_sketch, w.d, pw)
+    Y = philox.gaussian(w.seed_sketch + 7, w.n, pw)
+    times = []
+    t_end = time.perf_counter() + args.cpu_seconds
+    while time.perf_counter() < t_end or len(times) < 2:
+        t0 = time.perf_counter()
+        if len(times) % 2 == 0:
+            op.mul(X)
+        else:
+            op.tmul(Y)
+        times.append(time.perf_counter() - t0)
+    per = float(np.mean(times))
+    bx, by = dense_product_bytes(w.n, w.d, pw, a_bytes, x_bytes)
+    threads = oracle_threads()
+    return {"value": round(rate(unit, (bx + by) / 2, flops, per * 1e3), 6), "unit": unit,
+            "cores": threads, "kind": "oracle",
+            "sample": f"{len(times)} block products of the full matrix, A.X and A^T.Y "
+                      f"alternately, with the oracle's float64 operator on the stored FP32 "
+                      f"matrix (StreamedDense, 8192-row blocks upcast, BLAS on {threads} "
+                      f"threads); {per * 1e3:.0f} ms per product, a whole oracle solve makes "
+                      f"{2 * (w.q + 1)} of them",
+            "ms_per_product": round(per * 1e3, 2)}
 
 
 def gpu_error_measures(fn, Z, qs):
     """eqs. (1)-(3) quantities of the last solve's Z on the GPU (Section 3):
     ||Abar||_F^2, the Frobenius residual (Pythagoras), the spectral residual
-    (block Krylov on (I - Z Z^T) Abar, depth qs); no true spectrum at this
-    size, so the ratios are not formed.  Wall time of one call (it
-    synchronizes), after a warm-up call."""
+    (block Krylov on (I - Z Z^T) Abar, depth qs); no true spectrum here, so
+    the ratios are not formed.  Wall time of one call (it synchronizes),
+    after a warm-up call."""
     import torch
     fn(Z, qs)
     torch.cuda.synchronize()
@@ -402,64 +710,6 @@ def copy_calibration(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read_per_launch": n * 4,
                       "copy_bytes_written_per_launch": n * 4, "launches": 5}), flush=True)
-
-
-def cpu_baseline(args, w, host, res, bytes_per_solve):
-    """The oracle, as it stands, on the host cores: whole solves of the same
-    input repeated for about --cpu-seconds (the sample), in the same unit."""
-    import scipy.sparse as sp
-    from threadpoolctl import threadpool_info
-
-    from oracle import bki, metrics, philox
-
-    k, q = w.k, w.q
-    pw = args.block_size or k
-    Pi = philox.gaussian(w.seed_sketch, w.d, pw)
-    if w.kind == "csr":
-        A = sp.csr_matrix((host["va"].astype(np.float64), host["ci"], host["rp"]),
-                          shape=(w.n, w.d))
-        Pi = Pi.astype(np.float32).astype(np.float64)
-        tau = 1e-5
-    elif "A" in host:
-        A = host["A"] if w.dtype == "f64" else host["A"].astype(np.float32).astype(np.float64)
-        if w.dtype != "f64":
-            Pi = Pi.astype(np.float32).astype(np.float64)
-        tau = 1e-11 if w.dtype == "f64" else 1e-5
-    else:
-        return ({"value": None, "unit": "GB/s", "cores": 0, "kind": "oracle",
-                 "sample": "skipped: matrix generated on the GPU only"}, None)
-    times = []
-    ref = None
-    t_end = time.perf_counter() + args.cpu_seconds
-    while time.perf_counter() < t_end or not times:
-        t0 = time.perf_counter()
-        # the oracle route of the method timed on the GPU
-        if args.method == "si":
-            ref = bki.simultaneous_iteration(A, Pi, k, q, center=w.center)
-        elif args.method == "lanczos":
-            ref = bki.block_lanczos(A, Pi, k, q, center=w.center, tau=tau)[0]
-        else:
-            ref = bki.block_krylov(A, Pi, k, q, center=w.center, tau=tau)
-        times.append(time.perf_counter() - t0)
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    per = float(np.median(times))
-    base = {"value": round(bytes_per_solve / per / 1e9, 4), "unit": "GB/s",
-            "cores": int(threads), "kind": "oracle",
-            "sample": f"{len(times)} whole solves of the same input "
-                      f"(median {per * 1e3:.1f} ms/solve, NumPy/SciPy float64; sparse "
-                      f"products single-threaded, dense BLAS on {threads} threads)",
-            "ms_per_solve": round(per * 1e3, 2)}
-    Zg = res.Z.double().cpu().numpy()
-    sg = res.sigma.cpu().numpy()
-    rel = float(np.max(np.abs(sg - ref.sigma) / ref.sigma))
-    j = 0   # widest leading subspace with relative Ritz gap >= 1e-2
-    for jj in range(1, min(k, len(ref.theta) - 1) + 1):
-        if (ref.theta[jj - 1] - ref.theta[jj]) / ref.theta[0] >= 1e-2:
-            j = jj
-    ang = metrics.principal_angle(ref.Z[:, :j], Zg[:, :j]) if j else None
-    parity = {"ritz_rel_max": rel, "principal_angle_rad": ang, "gap_separated_j": j,
-              "angle_at_k_rad": metrics.principal_angle(ref.Z, Zg)}
-    return base, parity
 
 
 if __name__ == "__main__":

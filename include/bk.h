@@ -119,6 +119,19 @@ typedef struct bk_options {
                                 phases given events (1 << BK_PH_AX | ...);
                                 0 = all.  Launch counts are kept for all.   */
   int32_t reserved[2];
+  double* residuals;         /* nullable DEVICE array of k FP64: the
+                                residual norms r_i = ||A A^T z_i -
+                                sigma_i^2 z_i||_2 of the returned Ritz
+                                pairs, formed after the solve with two more
+                                k-wide block products (A: the FP32 master
+                                when the correction pass ran, else the
+                                matrix the solve used, centred when
+                                center_rows).  For the unit vector z_i and
+                                the symmetric A A^T, some eigenvalue of
+                                A A^T lies within r_i of sigma_i^2
+                                (Bauer-Fike), so some singular value s of
+                                A has |sigma_i - s| <= r_i / sigma_i.  CSR
+                                path: needs block_size = k.             */
 } bk_options;
 
 enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1, BK_METHOD_BLOCK_LANCZOS = 2 };

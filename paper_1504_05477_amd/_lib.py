@@ -31,6 +31,7 @@ class Options(C.Structure):
         ("method", C.c_int32),
         ("timing_phases", C.c_int32),
         ("reserved", C.c_int32 * 2),
+        ("residuals", C.c_void_p),
     ]
 
 
@@ -117,11 +118,12 @@ EXPORTS = tuple(name for name, _, _ in _SIGS)
 
 
 def load(path: str | None = None):
-    """Load libbk.so; raises when it has not been built (no fallback)."""
+    """Load libbk.so (or the build named by BK_LIBRARY, e.g. the host-
+    sanitized one); raises when it has not been built (no fallback)."""
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    p = path or os.environ.get("BK_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise ImportError(
             f"{p} is missing: build the HIP library first "

@@ -48,7 +48,7 @@ _METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1, "lanczos": 
 
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
              breakdown_tol=0.0, pi=None, timing=False, save=False,
-             jacobi_block=0, block_size=0, method="bki") -> L.Options:
+             jacobi_block=0, block_size=0, method="bki", residuals=None) -> L.Options:
     """timing: False, True (every phase) or an iterable of phase names from
     _lib.PHASES (only those get events; launch counts are kept for all)."""
     o = L.Options()
@@ -75,6 +75,7 @@ def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
     if method not in _METHODS:
         raise ValueError(f"method must be one of {sorted(_METHODS)}")
     o.method = _METHODS[method]
+    o.residuals = _ptr(residuals)
     return o
 
 
@@ -84,20 +85,23 @@ class SVDResult:
     sigma: torch.Tensor      # k Ritz values (FP64), descending
     info: dict
     workspace: torch.Tensor | None = None   # forward state (save_for_backward)
+    residuals: torch.Tensor | None = None   # k FP64 ||A A^T z_i - sigma_i^2 z_i||
 
 
 def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
               A_master=None, refine: int = 0, pi=None, timing=False,
               save_for_backward=False, max_sweeps=0, jacobi_tol=0.0,
               breakdown_tol=0.0, jacobi_block=0, block_size=0, method="bki",
-              stream=None) -> SVDResult:
+              residuals=False, stream=None) -> SVDResult:
     """Block Krylov Iteration on a dense A (n x d row-major on the GPU).
 
     A's dtype selects the path: float64 / float32 (plain), bfloat16, or uint8
     holding OCP e4m3 codes with ``a_scales`` (FP8).  Returns Z (n x k, FP64 for
     the FP64 path, FP32 otherwise) and the Ritz values (FP64).
     ``block_size`` = p >= k oversamples the sketch (0: p = k);
-    ``method`` = "si" runs Simultaneous Iteration instead."""
+    ``method`` = "si" runs Simultaneous Iteration instead.
+    ``residuals`` also returns ||A A^T z_i - sigma_i^2 z_i|| per Ritz pair
+    (A: the FP32 master after the correction pass)."""
     lib = L.load()
     _need_cuda(A, a_scales, A_master, pi)
     if A.dim() != 2 or A.stride(1) != 1:
@@ -111,10 +115,11 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
         pi = pi.to(zdt).contiguous()
     if A_master is not None and (A_master.dtype != torch.float32 or A_master.stride(1) != 1):
         raise ValueError("A_master must be a row-major float32 tensor")
+    res_t = torch.empty(k, dtype=torch.float64, device=A.device) if residuals else None
     opt = _options(refine=refine, pi=pi, timing=timing, save=save_for_backward,
                    max_sweeps=max_sweeps, jacobi_tol=jacobi_tol,
                    breakdown_tol=breakdown_tol, jacobi_block=jacobi_block,
-                   block_size=block_size, method=method)
+                   block_size=block_size, method=method, residuals=res_t)
     nbytes = lib.bk_svd_dense_workspace(n, d, k, q, code, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
@@ -127,7 +132,7 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
                           int(seed) & (2**64 - 1), C.byref(opt), _ptr(Z), Z.stride(0),
                           _ptr(sig), C.byref(info), _ptr(ws), nbytes, _stream(stream))
     L.check(st, "bk_svd_dense")
-    return SVDResult(Z, sig, info.as_dict(), ws if save_for_backward else None)
+    return SVDResult(Z, sig, info.as_dict(), ws if save_for_backward else None, res_t)
 
 
 def svd_dense_backward(A: torch.Tensor, k: int, q: int, fwd: SVDResult, Z_bar=None,
@@ -194,10 +199,11 @@ class BKSVD(torch.autograd.Function):
 def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 0, *,
             transpose=None, center=False, pi=None, timing=False, max_sweeps=0,
             jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, block_size=0,
-            method="bki", stream=None) -> SVDResult:
+            method="bki", residuals=False, stream=None) -> SVDResult:
     """Block Krylov Iteration on a CSR A (int32 row_ptr / col_idx, float32
     values, on the GPU).  ``transpose`` = (t_row_ptr, t_col_idx, t_vals) of A^T
-    is optional; ``center`` applies implicit row centring."""
+    is optional; ``center`` applies implicit row centring; ``residuals`` as
+    svd_dense (of the centred matrix with ``center``; needs block_size k)."""
     lib = L.load()
     _need_cuda(row_ptr, col_idx, vals, pi)
     for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (vals, torch.float32)):
@@ -207,9 +213,12 @@ def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 
     tr = transpose or (None, None, None)
     if pi is not None:
         pi = pi.to(torch.float32).contiguous()
+    res_t = (torch.empty(k, dtype=torch.float64, device=row_ptr.device) if residuals
+             else None)
     opt = _options(center=center, pi=pi, timing=timing, max_sweeps=max_sweeps,
                    jacobi_tol=jacobi_tol, breakdown_tol=breakdown_tol,
-                   jacobi_block=jacobi_block, block_size=block_size, method=method)
+                   jacobi_block=jacobi_block, block_size=block_size, method=method,
+                   residuals=res_t)
     nbytes = lib.bk_svd_csr_workspace(n, d, nnz, k, q, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
@@ -222,7 +231,7 @@ def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 
                         _ptr(Z), Z.stride(0), _ptr(sig), C.byref(info), _ptr(ws), nbytes,
                         _stream(stream))
     L.check(st, "bk_svd_csr")
-    return SVDResult(Z, sig, info.as_dict())
+    return SVDResult(Z, sig, info.as_dict(), None, res_t)
 
 
 @dataclass

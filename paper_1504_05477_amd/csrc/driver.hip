@@ -54,6 +54,7 @@ struct Options {
   int bl = 0;  // 1: block-tridiagonal Rayleigh-Ritz matrix (block Lanczos)
   double jtol = 0.0, tau = 0.0;
   const void* pi = nullptr;
+  double* resid = nullptr;  // device k: residual norms of the Ritz pairs
 };
 
 Options read_options(const bk_options* o, bool f64) {
@@ -73,6 +74,8 @@ Options read_options(const bk_options* o, bool f64) {
     r.bl = o->method == BK_METHOD_BLOCK_LANCZOS ? 1 : 0;
     if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, reserved)))
       r.timing_phases = o->timing_phases;
+    if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, residuals) + sizeof(double*)))
+      r.resid = o->residuals;
   }
   if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
   return r;
@@ -166,6 +169,10 @@ struct Layout {
   // block Lanczos: per-block projection coefficients (two passes, stride
   // m k) and CholeskyQR factors (three passes), scratch, the last block
   double *Cband = nullptr, *Rband = nullptr, *Pband = nullptr, *Tqq = nullptr;
+  // residual norms of the Ritz pairs: A^T Z (d x block width, the working
+  // type) and the norm partials
+  void* Wr = nullptr;
+  double* rpart = nullptr;
   // refinement
   float* Wk = nullptr;
   double* Gk = nullptr;
@@ -226,6 +233,10 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
     L.Tqq = ar.take<double>(kk);
   }
   if (o.save) L.Rsave = ar.take<double>(static_cast<size_t>(q + 1) * kk);
+  if (o.resid) {
+    L.Wr = ar.take<char>(static_cast<size_t>(d * k) * es);
+    L.rpart = ar.take<double>(static_cast<size_t>(ritz_resid_partial_elems(k)));
+  }
   if (o.refine) {
     L.Wk = ar.take<float>(static_cast<size_t>(d * k));
     L.Gk = ar.take<double>(kk);
@@ -610,6 +621,10 @@ struct Solver {
     a.alpha = alpha;
     a.beta = beta;
     a.gram_partial = gram_partial;
+    if (L) {  // wide applies of an FP32 block on the matrix cores
+      a.work = L->pack;
+      a.work_bytes = L->pack_bytes;
+    }
     return launch_nn(a, s);
   }
   // k <= 32: the applies of the orthonormalization also leave the partial
@@ -915,6 +930,38 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     launch_copy2d(L.Bs, false, k, Z, false, ldz, n, k, s);
     launch_sign_normalize(Z, false, n, k, ldz, nullptr, 0, 0, L.sign, s);
     tm.end(4);
+    BK_TRY_LAUNCH();
+  }
+
+  // Residual norms r_i = ||A A^T z_i - sigma_i^2 z_i|| of the returned pairs
+  // (Bauer-Fike certificate of Lemma 1's Ritz values): W_r = A^T Z -- after
+  // the correction pass that is W_k P, already formed with the FP32 master
+  // -- then R = A W_r and the column norms of R - Z diag(sigma^2).
+  if (o.resid) {
+    tm.begin(BK_PH_REFINE);
+    int nl = 0;
+    Op* rop = &op;
+    DenseOp mop;
+    Timer dummy;
+    // the correction pass signed Z after forming W_k: R then carries the
+    // columns before those signs
+    const double* rsign = (o.refine && master) ? L.sign : nullptr;
+    if (o.refine && master) {
+      mop = *master;
+      mop.partial = L.partial;
+      mop.partial_elems = L.partial_elems;
+      mop.pack = L.pack;
+      mop.pack_bytes = L.pack_bytes;
+      mop.tm = &dummy;
+      rop = &mop;
+      nl += S.apply(L.Wk, k, d, k, L.Pk, k, k, L.Wr, k, 1.0, 0.0);
+    } else {
+      rop->aty(Z, ldz, k, L.Wr, k, s);
+      ++nl;
+    }
+    rop->ax_of_aty(L.Wr, k, k, L.Bs, k, s);
+    launch_ritz_resid(L.Bs, k, Z, ldz, f64, n, k, L.ritz_dev, rsign, L.rpart, o.resid, s);
+    tm.end(nl + 3);
     BK_TRY_LAUNCH();
   }
 
@@ -1548,7 +1595,7 @@ size_t bk_svd_csr_workspace(int64_t n, int64_t d, int64_t nnz, int32_t k, int32_
   o.refine = 0;
   o.save = 0;
   const int32_t pw = block_width(n, d, k, q, o);
-  if (!pw) return 0;
+  if (!pw || (o.resid && pw != k)) return 0;
   return csr_workspace_bytes(n, d, nnz, pw, q, o, true, 0);
 }
 
@@ -1567,6 +1614,7 @@ int bk_svd_csr(const int32_t* row_ptr, const int32_t* col_idx, const float* vals
   o.save = 0;
   const int32_t pw = block_width(n, d, k, q, o);
   if (!pw) return BK_EINVAL;
+  if (o.resid && pw != k) return BK_EINVAL;  // the work plans are for width pw
   hipStream_t s = static_cast<hipStream_t>(stream);
   return csr_prepare_and_run(
       row_ptr, col_idx, vals, t_row_ptr, t_col_idx, t_vals, n, d, nnz, pw, q, o, workspace,

@@ -115,12 +115,12 @@ __device__ __forceinline__ int out_row(int lane, int v) {
 // rows of A go straight from memory into the operand registers (the next
 // chunk in flight while the current one is multiplied), the packed X^T
 // chunk (128 columns x 128 bytes) is staged in LDS, double-buffered.
-template <typename T, bool SCALED>
+template <typename T, bool SCALED, int PD>
 __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
     int64_t n, int64_t K, int N, const T* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld, const T* __restrict__ Xt,
     int64_t ldxt, const float* __restrict__ xscale, float* __restrict__ C, int64_t ldc,
-    int64_t cps) {
+    int64_t cps, float alpha, float beta) {
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
@@ -149,89 +149,110 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   f32x16 acc[4];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x16{};
-  uint4 acur[4], anxt[4], bst[4];
+  // A chunks in a ring of R = PD + 1 register sets, PD chunks in flight
+  // ahead of the one multiplied (a chunk of BF16 / FP8 is a few hundred
+  // cycles of matrix-core work, far below one memory latency); the packed
+  // X^T chunk goes through LDS one chunk ahead.
+  constexpr int R = PD + 1;
+  uint4 abuf[R][4], bst[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    acur[i] = arow[i];
-    bst[i] = bload ? xrow[i] : make_uint4(0, 0, 0, 0);
+  for (int u = 0; u < PD; ++u) {
+    if (u < nch) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) abuf[u][i] = arow[u * 8 + i];
+    }
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bst[i] = bload ? xrow[i] : make_uint4(0, 0, 0, 0);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
     *reinterpret_cast<uint4*>(&Bs[0][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
   __syncthreads();
-  for (int64_t c = 0; c < nch; ++c) {
-    const bool more = c + 1 < nch;
-    if (more) {
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += R) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        anxt[i] = arow[(c + 1) * 8 + i];
-        bst[i] = bload ? xrow[(c + 1) * 8 + i] : make_uint4(0, 0, 0, 0);
-      }
-    }
-    uint32_t aw[16];
+    for (int u = 0; u < R; ++u) {
+      const int64_t c = cb0 + u;
+      if (c < nch) {  // (uniform)
+        const bool more = c + 1 < nch;
+        if (c + PD < nch) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      aw[4 * i] = acur[i].x;
-      aw[4 * i + 1] = acur[i].y;
-      aw[4 * i + 2] = acur[i].z;
-      aw[4 * i + 3] = acur[i].w;
-    }
-    const uint32_t* tile = Bs[c & 1];
-    f32x16 tmp[4];
-    if (SCALED) {
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
-    }
-#pragma unroll
-    for (int q = 0; q < STEPS; ++q) {
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) {
-        if (tt < nt) {
-          uint32_t bw[LW];
-          lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
-          if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
-          else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
+          for (int i = 0; i < 4; ++i) abuf[(u + PD) % R][i] = arow[(c + PD) * 8 + i];
         }
+        if (more) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bst[i] = bload ? xrow[(c + 1) * 8 + i] : make_uint4(0, 0, 0, 0);
+        }
+        uint32_t aw[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          aw[4 * i] = abuf[u][i].x;
+          aw[4 * i + 1] = abuf[u][i].y;
+          aw[4 * i + 2] = abuf[u][i].z;
+          aw[4 * i + 3] = abuf[u][i].w;
+        }
+        const uint32_t* tile = Bs[c & 1];
+        f32x16 tmp[4];
+        if (SCALED) {
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
+        }
+#pragma unroll
+        for (int q = 0; q < STEPS; ++q) {
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            if (tt < nt) {
+              uint32_t bw[LW];
+              lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
+              if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
+              else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
+            }
+          }
+        }
+        if (SCALED) {
+          // 32-row groups never straddle a 128-row scale tile; chunk c is
+          // scale column c
+          const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + c] * xscale[c0 + c];
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) acc[tt] += sc * tmp[tt];
+        }
+        if (more) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            *reinterpret_cast<uint4*>(&Bs[(c + 1) & 1][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
+        }
+        __syncthreads();
       }
     }
-    if (SCALED) {
-      // 32-row groups never straddle a 128-row scale tile; chunk c is
-      // scale column c
-      const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + c] * xscale[c0 + c];
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) acc[tt] += sc * tmp[tt];
-    }
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        acur[i] = anxt[i];
-        *reinterpret_cast<uint4*>(&Bs[(c + 1) & 1][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
-      }
-    }
-    __syncthreads();
   }
+  // C = alpha acc + beta C (a split's partial: alpha 1, beta 0)
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
     const int64_t gc = col0 + 32 * tt + r32;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t gr = row0 + 32 * w + out_row(lane, v);
-      if (gr < n && gc < N) C[gr * ldc + gc] = acc[tt][v];
+      if (gr < n && gc < N) {
+        float* c = C + gr * ldc + gc;
+        *c = beta != 0.0f ? alpha * acc[tt][v] + beta * *c : alpha * acc[tt][v];
+      }
     }
   }
 }
 
-// C (n x N, ldc) = sum over the S splits of the FP32 partials, in split order.
+// C (n x N, ldc) = alpha (sum over the S splits of the FP32 partials, in
+// split order) + beta C.
 __global__ __launch_bounds__(256) void nn_split_reduce_kernel(int S, int64_t n, int64_t N,
                                                               const float* __restrict__ part,
                                                               float* __restrict__ C,
-                                                              int64_t ldc) {
+                                                              int64_t ldc, float alpha,
+                                                              float beta) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (idx >= n * N) return;
   float acc = 0.0f;
   for (int sp = 0; sp < S; ++sp) acc += part[sp * n * N + idx];
   const int64_t r = idx / N;
-  C[r * ldc + (idx - r * N)] = acc;
+  float* c = C + r * ldc + (idx - r * N);
+  *c = beta != 0.0f ? alpha * acc + beta * *c : alpha * acc;
 }
 
 // ------------------------------------------------------------------ TN --
@@ -370,12 +391,21 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   const int64_t le = (lb + Ls < L) ? lb + Ls : L;
   const int nt = static_cast<int>((r - r0 + 31) / 32 < 4 ? (r - r0 + 31) / 32 : 4);
   const int64_t nch = (le - lb + KC - 1) / KC;
-  double acc[4][16];
+  // running sums: FP64 for FP32 operands; FP32 for BF16 / FP8, whose
+  // rounding of the operands is ~2^-9 / 2^-4, far above FP32 summation
+  // error, and whose registers go to the chunks in flight instead
+  using ACC = typename std::conditional<sizeof(T) == 4, double, float>::type;
+  ACC acc[4][16];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) acc[tt][v] = 0.0;
-  TLoad<T> xa;
+    for (int v = 0; v < 16; ++v) acc[tt][v] = ACC(0);
+  // chunks of X in a ring of R = PD register sets: while chunk c is read
+  // from LDS, chunks c+1 .. c+PD are in registers or in flight (chunk c+PD
+  // goes into the slot chunk c left); Y (raw or packed) one chunk ahead
+  constexpr int PD = sizeof(T) == 4 ? 1 : 3;
+  constexpr int R = PD;
+  TLoad<T> xr[R];
   TLoad<float> ya;
   PLoad yp;
   const int bc = t >> 1, bh = t & 1;
@@ -383,59 +413,71 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   const uint4* yrow = nullptr;
   if (PACKED_Y)
     yrow = reinterpret_cast<const uint4*>(Yt + (r0 + (bload ? bc : 0)) * ldyt + lb) + 4 * bh;
-  auto load = [&](int64_t c) {
-    xa.load(X, ldx, lb + c * KC, le, p0, p, t);
+  auto yload = [&](int64_t c) {
     if (PACKED_Y) yp.load(yrow, bload, c);
     else ya.load(Yraw, ldy, lb + c * KC, le, r0, r, t);
   };
-  auto store = [&](int buf) {
-    xa.store(As[buf], t);
+  auto ystore = [&](int buf) {
     if (PACKED_Y) yp.store(Bs[buf], bc, bh);
     else ya.store(Bs[buf], t);
   };
+#pragma unroll
+  for (int u = 0; u < PD; ++u)
+    if (u < nch) xr[u].load(X, ldx, lb + u * KC, le, p0, p, t);
   if (nch > 0) {
-    load(0);
-    store(0);
+    yload(0);
+    xr[0].store(As[0], t);
+    ystore(0);
   }
   __syncthreads();
-  for (int64_t c = 0; c < nch; ++c) {
-    const bool more = c + 1 < nch;
-    if (more) load(c + 1);
-    const uint32_t* at = As[c & 1];
-    const uint32_t* bt = Bs[c & 1];
-    double sc = 1.0;
-    if (SCALED) {
-      const int64_t lt = (lb + c * KC) >> 7;  // 128-row scale tile of this chunk
-      sc = static_cast<double>(xscale[lt * xscale_ld + (p0 >> 7)]) *
-           static_cast<double>(yscale[lt]);
-    }
-    // chunk sums two output tiles at a time (fewer live FP32 registers)
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += R) {
 #pragma unroll
-    for (int pr = 0; pr < 2; ++pr) {
-      if (2 * pr < nt) {
-        f32x16 tmp[2] = {f32x16{}, f32x16{}};
+    for (int u = 0; u < R; ++u) {
+      const int64_t c = cb0 + u;
+      if (c < nch) {  // (uniform)
+        const bool more = c + 1 < nch;
+        if (c + PD < nch) xr[u].load(X, ldx, lb + (c + PD) * KC, le, p0, p, t);
+        if (more) yload(c + 1);
+        const uint32_t* at = As[c & 1];
+        const uint32_t* bt = Bs[c & 1];
+        ACC sc = ACC(1);
+        if (SCALED) {
+          const int64_t lt = (lb + c * KC) >> 7;  // 128-row scale tile of this chunk
+          sc = static_cast<ACC>(xscale[lt * xscale_ld + (p0 >> 7)]) *
+               static_cast<ACC>(yscale[lt]);
+        }
+        // chunk sums two output tiles at a time (fewer live FP32 registers)
 #pragma unroll
-        for (int q = 0; q < STEPS; ++q) {
-          uint32_t aw[LW];
-          lds_operand<T>(at, 32 * w + r32, h, q, aw);
+        for (int pr = 0; pr < 2; ++pr) {
+          if (2 * pr < nt) {
+            f32x16 tmp[2] = {f32x16{}, f32x16{}};
 #pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            if (2 * pr + u < nt) {
-              uint32_t bw[LW];
-              lds_operand<T>(bt, 32 * (2 * pr + u) + r32, h, q, bw);
-              tmp[u] = mfma_step<T>(aw, bw, tmp[u]);
+            for (int q = 0; q < STEPS; ++q) {
+              uint32_t aw[LW];
+              lds_operand<T>(at, 32 * w + r32, h, q, aw);
+#pragma unroll
+              for (int uu = 0; uu < 2; ++uu) {
+                if (2 * pr + uu < nt) {
+                  uint32_t bw[LW];
+                  lds_operand<T>(bt, 32 * (2 * pr + uu) + r32, h, q, bw);
+                  tmp[uu] = mfma_step<T>(aw, bw, tmp[uu]);
+                }
+              }
             }
+#pragma unroll
+            for (int uu = 0; uu < 2; ++uu)
+#pragma unroll
+              for (int v = 0; v < 16; ++v)
+                acc[2 * pr + uu][v] += sc * static_cast<ACC>(tmp[uu][v]);
           }
         }
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int v = 0; v < 16; ++v)
-            acc[2 * pr + u][v] += sc * static_cast<double>(tmp[u][v]);
+        if (more) {
+          xr[(u + 1) % R].store(As[(c + 1) & 1], t);
+          ystore((c + 1) & 1);
+        }
+        __syncthreads();
       }
     }
-    if (more) store((c + 1) & 1);
-    __syncthreads();
   }
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
@@ -443,15 +485,16 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t gp = p0 + 32 * w + out_row(lane, v);
-      if (gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = acc[tt][v];
+      if (gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = static_cast<double>(acc[tt][v]);
     }
   }
 }
 
 // ---------------------------------------------------------------- pack --
 // Dst (cols_pad x rows_pad, T, ld rows_pad) = Src^T for Src rows x cols
-// FP32 (ld lds), zero padded; FP8: one scale per 128 source rows,
-// s = amax / 448 over those rows and all columns, values e4m3(x / s).
+// FP32, or FP64 rounded to FP32 (ld lds), zero padded; FP8: one scale per
+// 128 source rows, s = amax / 448 over those rows and all columns, values
+// e4m3(x / s).
 template <typename T>
 __device__ __forceinline__ T to_elem(float x, float inv_unused);
 template <>
@@ -459,8 +502,8 @@ __device__ __forceinline__ float to_elem<float>(float x, float) { return x; }
 template <>
 __device__ __forceinline__ bf16_t to_elem<bf16_t>(float x, float) { return f32_to_bf16(x); }
 
-template <typename T>
-__global__ __launch_bounds__(256) void pack_t_kernel(const float* __restrict__ src, int64_t lds,
+template <typename T, typename TS>
+__global__ __launch_bounds__(256) void pack_t_kernel(const TS* __restrict__ src, int64_t lds,
                                                      int64_t rows, int64_t cols,
                                                      T* __restrict__ dst, int64_t rows_pad,
                                                      int64_t cols_pad, float* __restrict__ scales) {
@@ -473,7 +516,7 @@ __global__ __launch_bounds__(256) void pack_t_kernel(const float* __restrict__ s
     float am = 0.0f;
     for (int64_t i = t; i < 128 * cols; i += 256) {
       const int64_t rr = rb + i / cols, cc = i % cols;
-      if (rr < rows) am = fmaxf(am, fabsf(src[rr * lds + cc]));
+      if (rr < rows) am = fmaxf(am, fabsf(static_cast<float>(src[rr * lds + cc])));
     }
     red[t] = am;
     __syncthreads();
@@ -489,7 +532,7 @@ __global__ __launch_bounds__(256) void pack_t_kernel(const float* __restrict__ s
     for (int i = t; i < 128 * 32; i += 256) {
       const int rr = i >> 5, cc = i & 31;
       const int64_t gr = rb + rr, gc = c0 + cc;
-      tile[rr][cc] = (gr < rows && gc < cols) ? src[gr * lds + gc] : 0.0f;
+      tile[rr][cc] = (gr < rows && gc < cols) ? static_cast<float>(src[gr * lds + gc]) : 0.0f;
     }
     __syncthreads();
     // write 32 destination rows of 128 values (coalesced along rows)
@@ -693,24 +736,31 @@ int tn_mfma_splits(int64_t L, int64_t p, int r) {
   return static_cast<int>(cdiv(L, Ls));
 }
 
-// Packs Y (L x cols FP32) for a TN product or X^T for an NN product.
+// Packs Y (L x cols FP32) for a TN product or X^T for an NN product (X
+// FP32, or FP64 coefficients rounded to FP32 when src_f64).
 template <typename T>
-static void pack_t(const float* src, int64_t lds, int64_t rows, int64_t cols, void* work,
-                   int64_t* rows_pad, int64_t* cols_pad, float** scales, hipStream_t s) {
+static void pack_t(const void* src, bool src_f64, int64_t lds, int64_t rows, int64_t cols,
+                   void* work, int64_t* rows_pad, int64_t* cols_pad, float** scales,
+                   hipStream_t s) {
   *rows_pad = align_up(static_cast<size_t>(rows), 128);
   *cols_pad = align_up(static_cast<size_t>(cols), 32);
   T* dst = static_cast<T*>(work);
   const size_t body = align_up(static_cast<size_t>(*rows_pad * *cols_pad) * sizeof(T), 256);
   *scales = reinterpret_cast<float*>(static_cast<char*>(work) + body);
-  pack_t_kernel<T><<<static_cast<unsigned>(*rows_pad / 128), 256, 0, s>>>(
-      src, lds, rows, cols, dst, *rows_pad, *cols_pad, *scales);
+  const unsigned g = static_cast<unsigned>(*rows_pad / 128);
+  if (src_f64)
+    pack_t_kernel<T, double><<<g, 256, 0, s>>>(static_cast<const double*>(src), lds, rows, cols,
+                                                dst, *rows_pad, *cols_pad, *scales);
+  else
+    pack_t_kernel<T, float><<<g, 256, 0, s>>>(static_cast<const float*>(src), lds, rows, cols,
+                                               dst, *rows_pad, *cols_pad, *scales);
 }
 
 template <typename T, bool SCALED>
 static int nn_run(const NNArgs& a, int type, hipStream_t s) {
   int64_t kp = 0, np = 0;
   float* xs = nullptr;
-  pack_t<T>(static_cast<const float*>(a.X), a.ldx, a.K, a.N, a.work, &kp, &np, &xs, s);
+  pack_t<T>(a.X, a.x_f64, a.ldx, a.K, a.N, a.work, &kp, &np, &xs, s);
   const int S = nn_mfma_splits(a.n, a.K, a.N, type);
   const int64_t nch = a.K / Mf<T>::KC;
   const int64_t cps = cdiv(nch, S);
@@ -719,12 +769,17 @@ static int nn_run(const NNArgs& a, int type, hipStream_t s) {
                       : static_cast<float*>(a.C);
   const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128))),
                   static_cast<unsigned>(S));
-  nn_mfma_kernel<T, SCALED><<<grid, 256, 0, s>>>(
+  const float al = static_cast<float>(a.alpha), be = static_cast<float>(a.beta);
+  // chunks of A in flight: one for FP32 (a chunk is ~4000 cycles of
+  // matrix-core work), three for BF16 / FP8
+  constexpr int PD = sizeof(T) == 4 ? 1 : 3;
+  nn_mfma_kernel<T, SCALED, PD><<<grid, 256, 0, s>>>(
       a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,
-      static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps);
+      static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps,
+      S > 1 ? 1.0f : al, S > 1 ? 0.0f : be);
   if (S == 1) return 2;
   nn_split_reduce_kernel<<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(
-      S, a.n, a.N, part, static_cast<float*>(a.C), a.ldc);
+      S, a.n, a.N, part, static_cast<float*>(a.C), a.ldc, al, be);
   return 3;
 }
 
@@ -746,7 +801,11 @@ int64_t mfma_nn_work_bytes(int64_t n, int64_t K, int64_t N, int type) {
 
 void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches) {
   *launches = 0;
-  if (!a.work || a.x_f64 || a.c_f64 || a.alpha != 1.0 || a.beta != 0.0) return;
+  // FP64 X (coefficients of the orthonormalization and of Z = Q U_k) only
+  // with an FP32 A: X is rounded to FP32 in the packing, the sums are FP32
+  // as on the vector path
+  if (!a.work || a.c_f64 || (a.x_f64 && a.a_type != BK_F32)) return;
+  if (a.x_f64 && a.N <= 32) return;  // the small-K vector apply is faster there
   if (a.a_type != BK_F32 && a.a_type != BK_BF16 && a.a_type != BK_FP8_E4M3) return;
   const int es = esize(a.a_type);
   if (a.K <= 0 || a.K % chunk_vals(a.a_type) != 0 || (a.lda * es) % 16 != 0 ||
@@ -775,7 +834,7 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
   float* ys = nullptr;
   int64_t lp = 0, rp = 0;
   if (PACKED) {
-    pack_t<T>(static_cast<const float*>(a.Y), a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
+    pack_t<T>(a.Y, false, a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
     Yt = static_cast<const T*>(a.work);
   }
   const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),

@@ -123,8 +123,8 @@ void launch_ctrl_reset_off(Ctrl* c, hipStream_t s);
 // One-workgroup Cholesky + triangular inverse of a k x k FP64 Gram matrix
 // (see chol_kernel for the modes).
 // Cholesky of CholeskyQR: registers of one wavefront for k <= 64, blocked
-// by 32 in one workgroup for k <= kCholBlockedMax (work: k k + 4096
-// doubles), else one workgroup step by step.
+// by 32 over a chain of chip-wide kernels for k <= kCholBlockedMax (work:
+// k k + 4096 doubles), else one workgroup step by step.
 constexpr int kCholBlockedMax = 512;
 
 // Squared Frobenius norms for the error measures (metrics.hip): *out (FP64,
@@ -136,6 +136,14 @@ void launch_dense_fro2(const void* A, bool f64, int64_t n, int64_t d, int64_t ld
                        double* part, double* out, hipStream_t s);
 void launch_csr_fro2(const int32_t* rp, const float* v, int64_t n, int64_t d, bool center,
                      double* part, double* out, hipStream_t s);
+// Residual norms of the returned Ritz pairs (metrics.hip): out[c] (FP64,
+// device) = ||g_c R_c - sigma_c^2 Z_c||_2 with R = A A^T Z' (n x k, ld ldr),
+// Z = Z' diag(g) (n x k, ld ldz; g = rsign, or all +1 when null), both FP64
+// or both FP32; part: ritz_resid_partial_elems(k) doubles of scratch.
+int64_t ritz_resid_partial_elems(int k);
+void launch_ritz_resid(const void* R, int64_t ldr, const void* Z, int64_t ldz, bool f64,
+                       int64_t n, int k, const double* sigma, const double* rsign, double* part,
+                       double* out, hipStream_t s);
 inline int64_t chol_work_doubles(int k) { return static_cast<int64_t>(k) * k + 4096; }
 enum CholMode { CHOL_FIRST_BLOCK0 = 0, CHOL_FIRST = 1, CHOL_REPEAT = 2 };
 void launch_chol(int k, const double* G, const double* Gpre, int mode,

@@ -76,6 +76,40 @@ __global__ void sum_parts_kernel(const double* __restrict__ part, int nb, double
   }
 }
 
+// Residual norms of Ritz pairs: block b sums (g_c R[r][c] - theta_c
+// Z[r][c])^2 over rows [b per, (b + 1) per) for every column c (a thread
+// per column, rows in order), theta_c = sigma_c^2, g_c = rsign[c] (+1 when
+// null: a sign applied to Z after R was formed); part is nb x k.
+template <typename T>
+__global__ __launch_bounds__(256) void ritz_resid_part_kernel(
+    const T* __restrict__ R, int64_t ldr, const T* __restrict__ Z, int64_t ldz, int64_t n,
+    int k, const double* __restrict__ sigma, const double* __restrict__ rsign, int64_t per,
+    double* __restrict__ part) {
+  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * per;
+  const int64_t r1 = r0 + per < n ? r0 + per : n;
+  for (int c = threadIdx.x; c < k; c += 256) {
+    const double th = sigma[c] * sigma[c];
+    const double g = rsign ? rsign[c] : 1.0;
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) {
+      const double e = g * static_cast<double>(R[r * ldr + c]) - th * static_cast<double>(Z[r * ldz + c]);
+      s += e * e;
+    }
+    part[static_cast<int64_t>(blockIdx.x) * k + c] = s;
+  }
+}
+
+// out[c] = sqrt(sum over blocks, in block order, of part[b][c])
+__global__ __launch_bounds__(256) void ritz_resid_final_kernel(const double* __restrict__ part,
+                                                               int nb, int k,
+                                                               double* __restrict__ out) {
+  for (int c = blockIdx.x * 256 + threadIdx.x; c < k; c += gridDim.x * 256) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[static_cast<int64_t>(b) * k + c];
+    out[c] = sqrt(s);
+  }
+}
+
 int fro_blocks(int64_t rows) {
   return static_cast<int>(rows < FRO_BLOCKS ? (rows > 0 ? rows : 1) : FRO_BLOCKS);
 }
@@ -93,6 +127,24 @@ void launch_dense_fro2(const void* A, bool f64, int64_t n, int64_t d, int64_t ld
   else
     sumsq_kernel<float><<<nb, 256, 0, s>>>(static_cast<const float*>(A), n, d, lda, per, part);
   sum_parts_kernel<<<1, 64, 0, s>>>(part, nb, out);
+}
+
+int64_t ritz_resid_partial_elems(int k) { return static_cast<int64_t>(FRO_BLOCKS) * k; }
+
+void launch_ritz_resid(const void* R, int64_t ldr, const void* Z, int64_t ldz, bool f64,
+                       int64_t n, int k, const double* sigma, const double* rsign, double* part,
+                       double* out, hipStream_t s) {
+  const int nb = fro_blocks(n);
+  const int64_t per = cdiv(n, nb);
+  if (f64)
+    ritz_resid_part_kernel<double><<<nb, 256, 0, s>>>(static_cast<const double*>(R), ldr,
+                                                      static_cast<const double*>(Z), ldz, n, k,
+                                                      sigma, rsign, per, part);
+  else
+    ritz_resid_part_kernel<float><<<nb, 256, 0, s>>>(static_cast<const float*>(R), ldr,
+                                                     static_cast<const float*>(Z), ldz, n, k,
+                                                     sigma, rsign, per, part);
+  ritz_resid_final_kernel<<<static_cast<int>(cdiv(k, 256)), 256, 0, s>>>(part, nb, k, out);
 }
 
 void launch_csr_fro2(const int32_t* rp, const float* v, int64_t n, int64_t d, bool center,

@@ -374,192 +374,47 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
   }
 }
 
-// CholeskyQR factor for 64 < k <= 512 (same modes and outputs as
-// chol_kernel), blocked by 32 in one workgroup of 256 threads, with S in
-// global scratch (k x k, upper triangle used) and T (32 x 32) beside it:
-// for each diagonal block, one wavefront factors it in registers and
-// inverts it (R_kk, R_kk^-1 into R and Rinv), the panel right of it becomes
-// R_kb,j = R_kk^-T S_kb,j (a thread per column, the column in registers)
-// and the trailing upper triangle takes S_ij -= sum_r R_ri R_rj.  The
-// off-diagonal blocks of R^-1 follow by blocked back substitution,
-// Rinv_IJ = -Rinv_II sum_{L=I+1..J} R_IL Rinv_LJ.
-constexpr int CB = 32;
-constexpr int CB_THREADS = 256;
+// --------------------------------------------- chip-wide blocked Cholesky --
+// For 64 < k <= kCholBlockedMax: the factor of CholeskyQR as a short chain
+// of kernels instead of one workgroup walking a k x k matrix in memory:
+//   begin    the mode logic (non-finite, breakdown and rank tests) and the
+//            working copy S = G [+ shift] (upper triangle; block 0 first
+//            unshifted for its rank test);
+//   panel p  one wavefront factors the 32 x 32 diagonal block R_pp in
+//            registers and inverts it; the panel row R_p,j = R_pp^-T S_p,j
+//            (a thread per column j);
+//   update p S_ij -= sum_r R_ri R_rj on the trailing upper triangle, one
+//            workgroup per 32 x 32 tile;
+//   inverse  Rinv_IJ = -Rinv_II sum_{L=I+1..J} R_IL Rinv_LJ, one workgroup
+//            per block column J (its column of Rinv in LDS);
+//   end      failure reports to ctrl, R = upper(S), zeros below the
+//            diagonals (everything zero after a failure).
+// Every kernel after begin returns at once when the state says the block is
+// dropped or a pivot failed.  All sums run in a fixed order.
+constexpr int CM = 32;
 
-__device__ __forceinline__ bool chol_blocked_factor(int k, const double* __restrict__ G, double shift,
-                                    double* __restrict__ S, double* __restrict__ Rinv,
-                                    double* minpiv, int* fail, double* __restrict__ rkk,
-                                    double* __restrict__ pan, int pld) {
-  const int t = threadIdx.x;
-  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
-    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
-    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
-    Rinv[i] = 0.0;
-  }
-  if (t == 0) {
-    *fail = 0;
-    *minpiv = INFINITY;
-  }
-  __syncthreads();
-  const int nb = (k + CB - 1) / CB;
-  for (int kb = 0; kb < nb; ++kb) {
-    const int o = kb * CB;
-    const int bs = (k - o < CB) ? k - o : CB;
-    if (t < 64) {  // diagonal block in the registers of wavefront 0 (lane c: column c)
-      const int c = t;
-      double a[CB];
-#pragma unroll
-      for (int r = 0; r < CB; ++r)
-        a[r] = (c < bs) ? ((r < bs) ? S[(o + r) * k + o + c] : 0.0) : (r == c ? 1.0 : 0.0);
-      bool ok = true;
-      double mp = INFINITY;
-#pragma unroll
-      for (int j = 0; j < CB; ++j) {  // no early exit: the loop stays unrolled
-        double d = lane_f64(a[j], j);
-        if (!(d > 0.0) || !isfinite(d)) {
-          ok = false;
-          d = 1.0;
-        }
-        const double rd = sqrt(d);
-        if (j < bs) mp = fmin(mp, rd);
-        a[j] = (c == j) ? rd : a[j] * (1.0 / rd);
-#pragma unroll
-        for (int r = j + 1; r < CB; ++r) a[r] -= lane_f64(a[j], r) * a[j];
-      }
-      if (ok) {
-        // x = column c of R_kk^-1 by back substitution
-        double x[CB];
-#pragma unroll
-        for (int i = CB - 1; i >= 0; --i) {
-          double sum = 0.0;
-#pragma unroll
-          for (int l = i + 1; l < CB; ++l) sum += lane_f64(a[i], l) * x[l];
-          x[i] = ((i == c ? 1.0 : 0.0) - sum) / lane_f64(a[i], i);
-        }
-        if (c < bs) {
-#pragma unroll
-          for (int r = 0; r < CB; ++r) {
-            if (r <= c) {
-              S[(o + r) * k + o + c] = a[r];
-              Rinv[(o + r) * k + o + c] = x[r];
-            }
-          }
-        }
-      }
-      if (c == 0) {
-        if (!ok) *fail = 1;
-        else if (mp < *minpiv) *minpiv = mp;
-      }
-    }
-    __syncthreads();
-    if (*fail) return false;
-    const int rest = k - o - bs;
-    if (rest > 0) {
-      // R_kk^-1 of this block into LDS (zero outside the block)
-      for (int e = t; e < CB * CB; e += CB_THREADS) {
-        const int l = e / CB, r = e % CB;
-        rkk[e] = (l < bs && r < bs && l <= r) ? Rinv[(o + l) * k + o + r] : 0.0;
-      }
-      __syncthreads();
-      // panel: R[o + r][j] = sum_{l <= r} Rinv_kk[l][r] S[o + l][j], kept in
-      // LDS (pan[r][jj]) for the trailing update
-      for (int jj = t; jj < rest; jj += CB_THREADS) {
-        const int j = o + bs + jj;
-        double col[CB];
-#pragma unroll
-        for (int l = 0; l < CB; ++l) col[l] = (l < bs) ? S[(o + l) * k + j] : 0.0;
-        // rkk is zero below its diagonal: full-length dot products
-#pragma unroll 1
-        for (int r = 0; r < CB; ++r) {
-          double sum = 0.0;
-#pragma unroll
-          for (int l = 0; l < CB; ++l) sum += rkk[l * CB + r] * col[l];
-          pan[r * pld + jj] = sum;
-          if (r < bs) S[(o + r) * k + j] = sum;
-        }
-      }
-      __syncthreads();
-      // trailing upper triangle: S[i][j] -= sum_r R[o + r][i] R[o + r][j]
-      const int64_t tri = static_cast<int64_t>(rest) * (rest + 1) / 2;
-      for (int64_t e = t; e < tri; e += CB_THREADS) {
-        // e -> (ii, jj), ii <= jj, row-major over the upper triangle; row ii
-        // starts at off(ii) = ii rest - ii (ii - 1) / 2
-        const double b2 = 2.0 * rest + 1.0;
-        int ii = static_cast<int>((b2 - sqrt(b2 * b2 - 8.0 * static_cast<double>(e))) / 2.0);
-        if (ii < 0) ii = 0;
-        if (ii > rest - 1) ii = rest - 1;
-        while (ii > 0 && static_cast<int64_t>(ii) * rest - static_cast<int64_t>(ii) * (ii - 1) / 2 > e)
-          --ii;
-        while (ii + 1 < rest &&
-               static_cast<int64_t>(ii + 1) * rest - static_cast<int64_t>(ii + 1) * ii / 2 <= e)
-          ++ii;
-        const int jj = ii + static_cast<int>(e - (static_cast<int64_t>(ii) * rest -
-                                                  static_cast<int64_t>(ii) * (ii - 1) / 2));
-        const int i = o + bs + ii, j = o + bs + jj;
-        double sum = 0.0;
-#pragma unroll 8
-        for (int r = 0; r < CB; ++r) sum += pan[r * pld + ii] * pan[r * pld + jj];
-        S[i * k + j] -= sum;
-      }
-      __syncthreads();
-    }
-  }
-  return true;
-}
+struct CholMState {
+  int decision;  // 1: dropped before or at the rank test
+  int fail;      // 1: a pivot was not positive and finite
+  int pad0, pad1;
+  double minpiv;
+  double tr;
+};
 
-// Off-diagonal blocks of Rinv = R^-1 (diagonal blocks already in Rinv):
-// for each block column J, I = J-1 .. 0: T = sum_{L=I+1..J} R_IL Rinv_LJ,
-// Rinv_IJ = -Rinv_II T.
-__device__ __forceinline__ void chol_blocked_inverse(int k, const double* __restrict__ S,
-                                     double* __restrict__ Rinv, double* __restrict__ T) {
+__global__ __launch_bounds__(256) void cholm_begin_kernel(int k, const double* __restrict__ G,
+                                                          const double* __restrict__ Gpre,
+                                                          int mode, int block, double tau,
+                                                          double shift_coef, Ctrl* ctrl,
+                                                          CholMState* st, double* __restrict__ S) {
+  __shared__ double red[256];
+  __shared__ int s_dec;
+  __shared__ double s_tr;
   const int t = threadIdx.x;
-  const int nb = (k + CB - 1) / CB;
-  for (int J = 1; J < nb; ++J) {
-    const int oj = J * CB, bj = (k - oj < CB) ? k - oj : CB;
-    for (int I = J - 1; I >= 0; --I) {
-      const int oi = I * CB;  // full block (only the last block is short)
-      for (int e = t; e < CB * bj; e += CB_THREADS) {
-        const int r = e / bj, c = e - (e / bj) * bj;
-        double sum = 0.0;
-        // (unrolled: the global loads of a batch are in flight together)
-#pragma unroll 16
-        for (int l = oi + CB; l < oj + bj; ++l) sum += S[(oi + r) * k + l] * Rinv[l * k + oj + c];
-        T[r * CB + c] = sum;
-      }
-      __syncthreads();
-      for (int e = t; e < CB * bj; e += CB_THREADS) {
-        const int r = e / bj, c = e - (e / bj) * bj;
-        double sum = 0.0;
-#pragma unroll 16
-        for (int l = r; l < CB; ++l) sum += Rinv[(oi + r) * k + oi + l] * T[l * CB + c];
-        Rinv[(oi + r) * k + oj + c] = -sum;
-      }
-      __syncthreads();
-    }
-  }
-}
-
-__global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
-    int k, const double* __restrict__ G, const double* __restrict__ Gpre, int mode, int block,
-    double tau, double shift_coef, double* __restrict__ R, double* __restrict__ Rinv,
-    double* __restrict__ work, Ctrl* ctrl, int s_lds) {
-  __shared__ double red[CB_THREADS];
-  __shared__ double minpiv;
-  __shared__ int fail;
-  __shared__ int decision;
-  // R_kk^-1 (CB x CB; the inverse's T after the factor), panel (CB x k),
-  // with s_lds S (k x k) too, else S in work
-  extern __shared__ double cb_dyn[];
-  double* rkk = cb_dyn;
-  double* pan = cb_dyn + CB * CB;
-  const int t = threadIdx.x;
-  double* S = s_lds ? pan + CB * k : work;
-  double* T = rkk;
   double trp = 0.0, prp = 0.0;
   int bad = 0;
-  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS)
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += 256)
     if (!isfinite(G[i])) bad = 1;
-  for (int i = t; i < k; i += CB_THREADS) {
+  for (int i = t; i < k; i += 256) {
     trp += G[static_cast<int64_t>(i) * k + i];
     if (mode == CHOL_FIRST) prp += Gpre[static_cast<int64_t>(i) * k + i];
   }
@@ -567,51 +422,250 @@ __global__ __launch_bounds__(CB_THREADS) void chol_blocked_kernel(
   const double tr = block_sum(trp, red);
   const double pre = (mode == CHOL_FIRST) ? block_sum(prp, red) : 0.0;
   if (t == 0) {
-    decision = 0;
+    int dec = 0;
     if (anybad) {
       atomicOr(&ctrl->flags, CTRL_NONFINITE);
-      decision = 1;
+      dec = 1;
     } else if (mode == CHOL_FIRST) {
       if (!(sqrt(tr) > tau * sqrt(pre))) {
         atomicMin(&ctrl->q_eff, block - 1);
-        decision = 1;
+        dec = 1;
       }
     } else if (!(tr > 0.0)) {
       if (mode == CHOL_FIRST_BLOCK0) atomicOr(&ctrl->flags, CTRL_RANK);
-      decision = 1;
+      dec = 1;
+    }
+    st->decision = dec;
+    st->fail = 0;
+    st->minpiv = INFINITY;
+    st->tr = tr;
+    s_dec = dec;
+    s_tr = tr;
+  }
+  __syncthreads();
+  if (s_dec) return;
+  // block 0 is factored unshifted first (its rank test)
+  const double shift = (mode == CHOL_FIRST) ? shift_coef * s_tr : 0.0;
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += 256) {
+    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
+  }
+}
+
+// Block 0: the unshifted factor decides the rank; then S = G + shift I.
+__global__ __launch_bounds__(256) void cholm_rank_kernel(int k, const double* __restrict__ G,
+                                                         double tau, double shift_coef, Ctrl* ctrl,
+                                                         CholMState* st, double* __restrict__ S) {
+  __shared__ int s_dec;
+  __shared__ double s_tr;
+  const int t = threadIdx.x;
+  if (t == 0) {
+    int dec = st->decision;
+    if (!dec && (st->fail || !(st->minpiv > rank_floor(tau, shift_coef) * sqrt(st->tr)))) {
+      atomicOr(&ctrl->flags, CTRL_RANK);
+      dec = 1;
+      st->decision = 1;
+    }
+    st->fail = 0;
+    st->minpiv = INFINITY;
+    s_dec = dec;
+    s_tr = st->tr;
+  }
+  __syncthreads();
+  if (s_dec) return;
+  const double shift = shift_coef * s_tr;
+  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += 256) {
+    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void cholm_panel_kernel(int k, int o, double* __restrict__ S,
+                                                          double* __restrict__ Rinv,
+                                                          CholMState* st) {
+  __shared__ double rkk[CM * CM];
+  __shared__ int s_fail;
+  __shared__ double s_mp;
+  if (st->decision || st->fail) return;
+  const int t = threadIdx.x;
+  const int bs = (k - o < CM) ? k - o : CM;
+  if (t < 64) {  // the diagonal block in the registers of wavefront 0 (lane c: column c)
+    const int c = t;
+    double a[CM];
+#pragma unroll
+    for (int r = 0; r < CM; ++r)
+      a[r] = (c < bs) ? ((r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0)
+                      : (r == c ? 1.0 : 0.0);
+    bool ok = true;
+    double mp = INFINITY;
+#pragma unroll
+    for (int j = 0; j < CM; ++j) {  // no early exit: the loop stays unrolled
+      double d = lane_f64(a[j], j);
+      if (!(d > 0.0) || !isfinite(d)) {
+        ok = false;
+        d = 1.0;
+      }
+      const double rd = sqrt(d);
+      if (j < bs) mp = fmin(mp, rd);
+      a[j] = (c == j) ? rd : a[j] * (1.0 / rd);
+#pragma unroll
+      for (int r = j + 1; r < CM; ++r) a[r] -= lane_f64(a[j], r) * a[j];
+    }
+    // x = column c of R_pp^-1 by back substitution
+    double x[CM];
+#pragma unroll
+    for (int i = CM - 1; i >= 0; --i) {
+      double sum = 0.0;
+#pragma unroll
+      for (int l = i + 1; l < CM; ++l) sum += lane_f64(a[i], l) * x[l];
+      x[i] = ((i == c ? 1.0 : 0.0) - sum) / lane_f64(a[i], i);
+    }
+    if (ok && c < bs) {
+#pragma unroll
+      for (int r = 0; r < CM; ++r) {
+        if (r <= c) {
+          S[static_cast<int64_t>(o + r) * k + o + c] = a[r];
+          Rinv[static_cast<int64_t>(o + r) * k + o + c] = x[r];
+        }
+      }
+    }
+    // R_pp^-1 (zero outside the block and below its diagonal) for the panel
+    if (c < CM) {
+#pragma unroll
+      for (int r = 0; r < CM; ++r) rkk[r * CM + c] = (ok && c < bs && r <= c) ? x[r] : 0.0;
+    }
+    if (c == 0) {
+      s_fail = ok ? 0 : 1;
+      s_mp = mp;
     }
   }
   __syncthreads();
-  if (!decision && mode == CHOL_FIRST_BLOCK0) {
-    const bool ok = chol_blocked_factor(k, G, 0.0, S, Rinv, &minpiv, &fail, rkk, pan, k);
-    if (t == 0 && (!ok || !(minpiv > rank_floor(tau, shift_coef) * sqrt(tr)))) {
-      atomicOr(&ctrl->flags, CTRL_RANK);
-      decision = 1;
-    }
-    __syncthreads();
-  }
-  if (!decision) {
-    const double shift = (mode == CHOL_REPEAT) ? 0.0 : shift_coef * tr;
-    const bool ok = chol_blocked_factor(k, G, shift, S, Rinv, &minpiv, &fail, rkk, pan, k);
-    if (t == 0 && !ok) {
-      if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
-      else atomicMin(&ctrl->q_eff, block - 1);
-      decision = 1;
-    }
-    __syncthreads();
-  }
-  if (decision) {
-    for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
-      R[i] = 0.0;
-      Rinv[i] = 0.0;
-    }
+  if (s_fail) {
+    if (t == 0) st->fail = 1;
     return;
   }
-  chol_blocked_inverse(k, S, Rinv, T);
-  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += CB_THREADS) {
-    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
-    R[i] = (c >= r) ? S[i] : 0.0;
+  if (t == 0 && s_mp < st->minpiv) st->minpiv = s_mp;
+  const int rest = k - o - bs;
+  // panel row: R[o + r][j] = sum_{l <= r} Rinv_pp[l][r] S[o + l][j]
+  for (int jj = t; jj < rest; jj += 256) {
+    const int64_t j = o + bs + jj;
+    double col[CM];
+#pragma unroll
+    for (int l = 0; l < CM; ++l) col[l] = (l < bs) ? S[static_cast<int64_t>(o + l) * k + j] : 0.0;
+#pragma unroll 4
+    for (int r = 0; r < CM; ++r) {
+      double sum = 0.0;
+#pragma unroll
+      for (int l = 0; l < CM; ++l) sum += rkk[l * CM + r] * col[l];
+      if (r < bs) S[static_cast<int64_t>(o + r) * k + j] = sum;
+    }
   }
+}
+
+__global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
+                                                           double* __restrict__ S,
+                                                           const CholMState* st) {
+  __shared__ double Pi[CM][CM + 1], Pj[CM][CM + 1];
+  if (st->decision || st->fail) return;
+  const int t = threadIdx.x;
+  const int base = o + bs, rest = k - base;
+  const int nt = (rest + CM - 1) / CM;
+  // blockIdx.x -> tile (ti, tj), ti <= tj, row-major over the upper triangle
+  int e = static_cast<int>(blockIdx.x), ti = 0;
+  while (e >= nt - ti) {
+    e -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + e;
+  for (int idx = t; idx < CM * CM; idx += 256) {
+    const int r = idx / CM, c = idx % CM;
+    const int gi = base + CM * ti + c, gj = base + CM * tj + c;
+    const int64_t row = static_cast<int64_t>(o + r) * k;
+    Pi[r][c] = (r < bs && gi < k) ? S[row + gi] : 0.0;
+    Pj[r][c] = (r < bs && gj < k) ? S[row + gj] : 0.0;
+  }
+  __syncthreads();
+  const int tx = t & 31, ty = t >> 5;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int ii = ty + 8 * u;
+    const int i = base + CM * ti + ii, j = base + CM * tj + tx;
+    if (i < k && j < k && i <= j) {
+      double sum = 0.0;
+#pragma unroll 8
+      for (int r = 0; r < CM; ++r) sum += Pi[r][ii] * Pj[r][tx];
+      S[static_cast<int64_t>(i) * k + j] -= sum;
+    }
+  }
+}
+
+// Block column J of R^-1 above its diagonal block (workgroup J); X holds
+// rows 0 .. oj + bj - 1 of the column (the diagonal block from the panels).
+__global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double* __restrict__ S,
+                                                            double* __restrict__ Rinv,
+                                                            const CholMState* st) {
+  extern __shared__ double cm_dyn[];
+  __shared__ double T[CM][CM + 1];
+  if (st->decision || st->fail) return;
+  const int J = blockIdx.x;
+  if (J == 0) return;
+  const int t = threadIdx.x;
+  const int oj = J * CM, bj = (k - oj < CM) ? k - oj : CM;
+  double* X = cm_dyn;  // (oj + bj) x (CM + 1)
+  for (int idx = t; idx < CM * CM; idx += 256) {
+    const int r = idx / CM, c = idx % CM;
+    X[(oj + r) * (CM + 1) + c] =
+        (r < bj && c < bj && r <= c) ? Rinv[static_cast<int64_t>(oj + r) * k + oj + c] : 0.0;
+  }
+  __syncthreads();
+  const int c = t & 31, r0 = t >> 5;
+  for (int I = J - 1; I >= 0; --I) {
+    const int oi = I * CM;
+    // T = sum_{L = I+1 .. J} R_IL X_L  (rows oi .. oi+31 of R, columns oi+32 ..)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 8 * u;
+      const double* srow = S + static_cast<int64_t>(oi + r) * k;
+      double sum = 0.0;
+#pragma unroll 8
+      for (int l = oi + CM; l < oj + bj; ++l) sum += srow[l] * X[l * (CM + 1) + c];
+      T[r][c] = sum;
+    }
+    __syncthreads();
+    // X_I = -Rinv_II T (Rinv_II upper triangular, from the panels)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 8 * u;
+      const double* rrow = Rinv + static_cast<int64_t>(oi + r) * k + oi;
+      double sum = 0.0;
+#pragma unroll 8
+      for (int l = r; l < CM; ++l) sum += rrow[l] * T[l][c];
+      X[(oi + r) * (CM + 1) + c] = -sum;
+    }
+    __syncthreads();
+  }
+  for (int idx = t; idx < oj * CM; idx += 256) {
+    const int r = idx / CM, cc = idx % CM;
+    if (cc < bj) Rinv[static_cast<int64_t>(r) * k + oj + cc] = X[r * (CM + 1) + cc];
+  }
+}
+
+__global__ __launch_bounds__(256) void cholm_end_kernel(int k, const double* __restrict__ S,
+                                                        double* __restrict__ R,
+                                                        double* __restrict__ Rinv, int block,
+                                                        Ctrl* ctrl, const CholMState* st) {
+  const int dec = st->decision, fail = st->fail;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !dec && fail) {
+    if (block == 0) atomicOr(&ctrl->flags, CTRL_RANK);
+    else atomicMin(&ctrl->q_eff, block - 1);
+  }
+  const bool zero = dec || fail;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= static_cast<int64_t>(k) * k) return;
+  const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+  const bool up = c >= r;
+  R[i] = (zero || !up) ? 0.0 : S[i];
+  if (zero || !up) Rinv[i] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void trmm_upper_kernel(int k, const double* A,
@@ -859,19 +913,37 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
   BK_CHOL_WAVE(64)
 #undef BK_CHOL_WAVE
   if (k <= kCholBlockedMax) {
-    static bool battr = false;
-    constexpr size_t kMaxLds = 150 * 1024;
-    if (!battr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(chol_blocked_kernel),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kMaxLds));
-      battr = true;
+    static bool mattr = false;
+    if (!mattr) {
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(cholm_inverse_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                static_cast<int>(kCholBlockedMax * (CM + 1) * sizeof(double)));
+      mattr = true;
     }
-    // the working matrix in LDS beside the panel when it fits (k <= ~118)
-    const size_t base = static_cast<size_t>(CB * CB + CB * k) * sizeof(double);
-    const size_t with_s = base + static_cast<size_t>(k) * k * sizeof(double);
-    const int s_lds = with_s <= kMaxLds ? 1 : 0;
-    chol_blocked_kernel<<<1, CB_THREADS, s_lds ? with_s : base, s>>>(
-        k, G, Gpre, mode, block, tau, shift_coef, R, Rinv, work, ctrl, s_lds);
+    double* S = work;
+    CholMState* st = reinterpret_cast<CholMState*>(work + static_cast<int64_t>(k) * k);
+    const int nb = (k + CM - 1) / CM;
+    cholm_begin_kernel<<<1, 256, 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, ctrl, st, S);
+    auto factor = [&]() {
+      for (int p = 0; p < nb; ++p) {
+        const int o = p * CM, bs = std::min(CM, k - o);
+        cholm_panel_kernel<<<1, 256, 0, s>>>(k, o, S, Rinv, st);
+        const int rest = k - o - bs;
+        if (rest > 0) {
+          const int nt = (rest + CM - 1) / CM;
+          cholm_update_kernel<<<nt * (nt + 1) / 2, 256, 0, s>>>(k, o, bs, S, st);
+        }
+      }
+    };
+    factor();
+    if (mode == CHOL_FIRST_BLOCK0) {
+      cholm_rank_kernel<<<1, 256, 0, s>>>(k, G, tau, shift_coef, ctrl, st, S);
+      factor();
+    }
+    cholm_inverse_kernel<<<nb, 256, static_cast<size_t>(nb * CM) * (CM + 1) * sizeof(double), s>>>(
+        k, S, Rinv, st);
+    cholm_end_kernel<<<static_cast<unsigned>(cdiv(static_cast<int64_t>(k) * k, 256)), 256, 0, s>>>(
+        k, S, R, Rinv, block, ctrl, st);
     return;
   }
   chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,

@@ -880,6 +880,51 @@ __global__ __launch_bounds__(TBG_COLS) void tribig_update_kernel(
   part[blockIdx.y * m + l] = acc;
 }
 
+// Reorthogonalization of the inverse-iteration vectors (columns of X,
+// column-major, ld m).  Inverse iteration only orthogonalizes within groups
+// of eigenvalues closer than 1e-10 ||T||; a pair separated by a gap g keeps
+// an overlap of ~ eps ||T|| / g.  One CholeskyQR pass over all k columns in
+// eigenvalue order (X <- X R^-1, R^T R = X^T X), i.e. Gram-Schmidt with the
+// larger eigenvalue's vector kept, removes those overlaps; for well
+// separated pairs the corrections are rounding-sized.
+// G = X^T X: a 16 x 16 tile per workgroup, rows in 64-row chunks through
+// LDS; G_ij and G_ji get the same products in the same order (symmetric).
+__global__ __launch_bounds__(256) void xgram_kernel(const double* __restrict__ X, int64_t m,
+                                                    int k, double* __restrict__ G) {
+  __shared__ double xi[64][17], xj[64][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  double acc = 0.0;
+  for (int64_t r0 = 0; r0 < m; r0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int c = e >> 6, r = e & 63;
+      const int64_t row = r0 + r;
+      xi[r][c] = (i0 + c < k && row < m) ? X[static_cast<int64_t>(i0 + c) * m + row] : 0.0;
+      xj[r][c] = (j0 + c < k && row < m) ? X[static_cast<int64_t>(j0 + c) * m + row] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 16
+    for (int r = 0; r < 64; ++r) acc += xi[r][ty] * xj[r][tx];
+    __syncthreads();
+  }
+  const int i = i0 + ty, j = j0 + tx;
+  if (i < k && j < k) G[static_cast<int64_t>(i) * k + j] = acc;
+}
+
+// Xn[:, c] = sum_{l <= c} X[:, l] Rinv[l][c] (a thread per entry, rows
+// consecutive across threads).
+__global__ __launch_bounds__(256) void xapply_kernel(const double* __restrict__ X, int64_t m,
+                                                     int k, const double* __restrict__ Rinv,
+                                                     double* __restrict__ Xn) {
+  const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (idx >= m * k) return;
+  const int c = static_cast<int>(idx / m);
+  const int64_t i = idx - static_cast<int64_t>(c) * m;
+  double sum = 0.0;
+  for (int l = 0; l <= c; ++l) sum += X[static_cast<int64_t>(l) * m + i] * Rinv[static_cast<int64_t>(l) * k + c];
+  Xn[idx] = sum;
+}
+
 __global__ __launch_bounds__(256) void sym_copy_kernel(const double* __restrict__ M, int64_t m,
                                                        int64_t ldm, double* __restrict__ A) {
   const int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
@@ -894,10 +939,14 @@ int64_t tridiag_scratch_doubles(int64_t m, int k) {
   // A copy + Vh + beta/dg/eo + X + solver scratch (5 m per eigenvalue) +
   // pivots (k m ints) + (large m) v, vp, wp and the row-group partials +
   // (small m) the panel's V and W
+  // + the reorthogonalization: the new X, G, R, R^-1, the Cholesky's work
+  // and a status word it may write
   const int64_t groups = cdiv(m, TBG_ROWS);
+  const int64_t kk = static_cast<int64_t>(k) * k;
   return 2 * m * m + 3 * m + static_cast<int64_t>(k) * m +
          std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024) +
-         (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64;
+         (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64 +
+         static_cast<int64_t>(k) * m + 3 * kk + chol_work_doubles(k) + 8;
 }
 
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double* scratch,
@@ -918,6 +967,13 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   double* part = wp + m;
   double* Vg = part + cdiv(m, TBG_ROWS) * m;
   double* Wg = Vg + TRI_NB * m;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  double* Xn = Wg + TRI_NB * m + 64;
+  double* Gx = Xn + static_cast<int64_t>(k) * m;
+  double* Rx = Gx + kk;
+  double* Rix = Rx + kk;
+  double* cwork = Rix + kk;
+  Ctrl* cdummy = reinterpret_cast<Ctrl*>(cwork + chol_work_doubles(k));
   static bool attr = false;
   if (!attr) {
     for (const void* f : {reinterpret_cast<const void*>(tridiag_reduce_kernel),
@@ -977,6 +1033,15 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   const int use_lds = inv_lds <= static_cast<size_t>(TRI_LDS_BYTES) ? 1 : 0;
   tridiag_invit_kernel<<<static_cast<unsigned>(k), 64, use_lds ? inv_lds : 2 * m * sizeof(double),
                          s>>>(dg, eo, m, k, theta, X, sol, piv, use_lds);
+  // Gram-Schmidt over all k vectors in eigenvalue order (CholeskyQR; the
+  // Cholesky's failure reports go to a status word nobody reads: a Gram of
+  // unit vectors this close to I has no failing pivot)
+  const unsigned gt = static_cast<unsigned>(cdiv(k, 16));
+  xgram_kernel<<<dim3(gt, gt), 256, 0, s>>>(X, m, k, Gx);
+  launch_ctrl_init(cdummy, 0, s);
+  launch_chol(k, Gx, nullptr, CHOL_REPEAT, 1 << 30, 0.0, 0.0, Rx, Rix, cwork, cdummy, s);
+  xapply_kernel<<<static_cast<unsigned>(cdiv(m * k, 256)), 256, 0, s>>>(X, m, k, Rix, Xn);
+  X = Xn;
   const unsigned gb = static_cast<unsigned>(cdiv(k, 4));
   if (m <= 256)
     tridiag_back_kernel<4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);

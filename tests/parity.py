@@ -16,6 +16,16 @@ def gap_index(theta: np.ndarray, k: int, rel_gap: float = 1e-2) -> int:
     return best
 
 
+def gap_tolerance(theta: np.ndarray, j: int, ritz_rtol: float, floor: float) -> float:
+    """Davis-Kahan tolerance on the largest principal angle of the leading
+    j-subspace: a Ritz-value tolerance of ritz_rtol admits a perturbation of
+    M of ~2 ritz_rtol theta_1, which moves that subspace by at most its size
+    over the relative gap (theta_j - theta_{j+1}) / theta_1 (factor 5 of
+    slack); never below `floor`."""
+    gap = (theta[j - 1] - theta[j]) / theta[0]
+    return float(min(np.pi / 2, max(floor, 10.0 * ritz_rtol / gap)))
+
+
 def angle_bound_at_k(theta: np.ndarray, k: int, ritz_rtol: float, angle_tol: float):
     """Tolerance on the largest principal angle of the whole k-dimensional
     Ritz subspace, or None when theta_k = theta_{k+1} (the subspace is not

@@ -44,7 +44,8 @@ def test_status_strings(lib):
 
 
 def test_struct_layouts():
-    assert C.sizeof(L.Options) == 72
+    assert C.sizeof(L.Options) == 80
+    assert L.Options.residuals.offset == 72
     assert L.Info.workspace_bytes.offset == 112
     assert C.sizeof(L.Metrics) == 56
 

@@ -42,3 +42,17 @@ def test_traffic_reader_requires_matching_source(tmp_path, monkeypatch):
     assert bench.read_traffic("k", "def") is None
     assert bench.read_traffic("missing", "abc") is None
     assert os.path.exists(prof / "k_traffic.txt")
+
+
+def test_value_unit_follows_the_ridge():
+    # FP32 dense products above the FP32 matrix-core ridge (157.3 TFLOP/s
+    # over 8 TB/s: 19.7 flop/B) report TFLOP/s; below it, or in BF16 / FP8,
+    # or on CSR, GB/s
+    assert bench.value_unit("dense", "f32", 131072, 32768, 256, 4) == "TFLOP/s"   # AI 128
+    assert bench.value_unit("dense", "f32", 65536, 16384, 100, 4) == "TFLOP/s"    # AI 50
+    assert bench.value_unit("dense", "f32", 8192, 4096, 32, 4) == "GB/s"          # AI 16
+    assert bench.value_unit("dense", "f64", 2000, 1000, 10, 8) == "GB/s"          # AI 2.5
+    assert bench.value_unit("dense", "fp8", 131072, 32768, 256, 1) == "GB/s"
+    assert bench.value_unit("csr", "f32", 11000, 130000, 20, 4) == "GB/s"
+    assert bench.rate("TFLOP/s", 1e9, 2e12, 1000.0) == pytest.approx(2.0)
+    assert bench.rate("GB/s", 4e9, 1.0, 500.0) == pytest.approx(8.0)

@@ -46,3 +46,18 @@ def test_planted_dense_torch_cpu_factors():
     s = np.linalg.svd(A.numpy(), compute_uv=False)
     assert np.allclose(s, sv, rtol=1e-12)
     assert torch.max(torch.abs((U * sig) @ V.t() - A)).item() < 1e-14
+
+
+def test_planted_dense_torch_storage_rounding():
+    # the reported rounding norm is ||A_FP32 - A_FP64||_F of the same
+    # product, and Weyl bounds the singular values of the stored matrix by it
+    sv = workloads.spectrum("pow08", 120)
+    st = {}
+    A32 = workloads.planted_dense_torch(300, 120, sv, 5, device="cpu", stats=st)
+    A64 = workloads.planted_dense_torch(300, 120, sv, 5, device="cpu",
+                                        out_dtype=torch.float64)
+    want = float(torch.linalg.norm(A32.double() - A64))
+    assert st["storage_rounding_fro"] == pytest.approx(want, rel=1e-12)
+    assert 0 < want < 2 ** -23 * float(torch.linalg.norm(A64))
+    s = np.linalg.svd(A32.double().numpy(), compute_uv=False)
+    assert np.max(np.abs(s - sv)) <= want

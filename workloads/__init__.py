@@ -185,13 +185,18 @@ def _orth_blocked(rows, cols, g, device):
 
 def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
                         out_dtype=None, noise: float = 0.0,
-                        noise_seed: int | None = None, return_factors=False):
+                        noise_seed: int | None = None, return_factors=False,
+                        stats: dict | None = None):
     """A = U diag(sigma) V^T built with torch on ``device`` (for large shapes).
 
     U and V are Q factors of seeded N(0,1) matrices (FP64 QR, made unique by a
     positive diagonal of R); the product is formed in FP64 row block by row
     block and stored as ``out_dtype`` (default float32).  Returns A, and also
-    (U, sigma, V) in FP64 when ``return_factors``."""
+    (U, sigma, V) in FP64 when ``return_factors``.  ``stats``, when given,
+    receives "storage_rounding_fro": ||A_stored - A_FP64||_F, the Frobenius
+    norm of what storing the FP64 product (noise included) in ``out_dtype``
+    changed (a bound on how far the stored matrix's singular values are from
+    the planted ones, Weyl)."""
     import torch
 
     out_dtype = torch.float32 if out_dtype is None else out_dtype
@@ -221,6 +226,7 @@ def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
         gn = torch.Generator(device=device)
         gn.manual_seed(noise_seed if noise_seed is not None else seed + 200)
     rb = 8192
+    rnd2 = 0.0
     for r0 in range(0, n, rb):
         r1 = min(n, r0 + rb)
         blk = (u[r0:r1] * sig) @ vt
@@ -228,7 +234,11 @@ def planted_dense_torch(n: int, d: int, sigma, seed: int, device="cuda",
             blk += noise * torch.randn(r1 - r0, d, generator=gn, device=device,
                                        dtype=torch.float64)
         a[r0:r1] = blk.to(out_dtype)
+        if stats is not None:
+            rnd2 += float(((a[r0:r1].to(torch.float64) - blk) ** 2).sum())
         del blk
+    if stats is not None:
+        stats["storage_rounding_fro"] = math.sqrt(rnd2)
     if return_factors:
         return a, (u, sig, v)
     del u, v, vt
