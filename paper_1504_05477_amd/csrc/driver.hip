@@ -178,6 +178,7 @@ struct Layout {
   double* Gk = nullptr;
   double* Pk = nullptr;
   JacobiWs jk;
+  double* trik = nullptr;  // its tridiagonal eigen-solve scratch
   // CSR
   int32_t *trp = nullptr, *tci = nullptr, *cursor = nullptr, *counters = nullptr;
   CsrPlan plan_a, plan_t;       // work plans of A and A^T (shared part)
@@ -242,6 +243,9 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
     L.Gk = ar.take<double>(kk);
     L.Pk = ar.take<double>(kk);
     L.jk = take_jacobi(ar, k, 0, true);
+    // the k x k Rayleigh-Ritz of the correction pass: tridiagonal path
+    if (k >= 3 && k <= kTridiagMax)
+      L.trik = ar.take<double>(static_cast<size_t>(tridiag_scratch_doubles(k, k)));
   }
   if (csr) {
     if (own_transpose) {
@@ -923,7 +927,7 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     g.partial = L.partial;
     launch_tn(g, s);
     tm.end(4);
-    st = S.eig(L.Gk, k, L.jk, k, L.Pk, k, L.ritz_dev);
+    st = S.eig(L.Gk, k, L.jk, k, L.Pk, k, L.ritz_dev, L.trik);
     if (st != BK_OK) return st;
     tm.begin(BK_PH_REFINE);
     S.apply(Z, ldz, n, k, L.Pk, k, k, L.Bs, k, 1.0, 0.0);

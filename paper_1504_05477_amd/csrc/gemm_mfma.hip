@@ -6,7 +6,8 @@
 // Element types and instructions (lane layouts checked on gfx950):
 //   FP32  v_mfma_f32_32x32x2_f32        1 value per lane and step
 //   BF16  v_mfma_f32_32x32x16_bf16      8 values per lane and step
-//   FP8   v_mfma_f32_32x32x16_fp8_fp8   8 values (OCP e4m3) per lane and step
+//   FP8   v_mfma_scale_f32_32x32x64_f8f6f4  32 values (OCP e4m3) per lane and
+//         step, block scales at 1
 // The reduction dimension is walked in chunks of 128 bytes per row (32 FP32,
 // 64 BF16 or 128 FP8 values; for FP8 one chunk is one 128-wide scale tile).
 // Inside a chunk, lanes 0-31 supply bytes 0-63 and lanes 32-63 bytes
@@ -22,6 +23,7 @@ namespace {
 
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 constexpr int LDS_ROW = 36;  // 32-bit words per staged row: 128 bytes + 16 pad
 
@@ -42,8 +44,8 @@ struct Mf<bf16_t> {
 template <>
 struct Mf<fp8_t> {
   static constexpr int KC = 128;
-  static constexpr int STEPS = 8;
-  static constexpr int LW = 2;
+  static constexpr int STEPS = 2;
+  static constexpr int LW = 8;
 };
 
 template <typename T>
@@ -65,9 +67,16 @@ __device__ __forceinline__ f32x16 mfma_step<bf16_t>(const uint32_t* a, const uin
 template <>
 __device__ __forceinline__ f32x16 mfma_step<fp8_t>(const uint32_t* a, const uint32_t* b,
                                                    f32x16 c) {
-  const long la = static_cast<long>(static_cast<uint64_t>(a[0]) | (static_cast<uint64_t>(a[1]) << 32));
-  const long lb = static_cast<long>(static_cast<uint64_t>(b[0]) | (static_cast<uint64_t>(b[1]) << 32));
-  return __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(la, lb, c, 0, 0, 0);
+  // gfx950's 32 x 32 x 64 FP8 step (both operands OCP e4m3, format 0), with
+  // the block scales at 2^0 (E8M0 127): the FP32 tile scales are applied
+  // to the chunk sums instead
+  i32x8 va, vb;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    va[i] = static_cast<int>(a[i]);
+    vb[i] = static_cast<int>(b[i]);
+  }
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(va, vb, c, 0, 0, 0, 127, 0, 127);
 }
 
 // LDS words of the lane's operand for step q: row `row` of a staged tile.
@@ -75,7 +84,18 @@ template <typename T>
 __device__ __forceinline__ void lds_operand(const uint32_t* tile, int row, int h, int q,
                                             uint32_t* out) {
   const uint32_t* p = tile + row * LDS_ROW + 16 * h + q * Mf<T>::LW;
-  if constexpr (Mf<T>::LW == 4) {
+  if constexpr (Mf<T>::LW == 8) {
+    const uint4 v0 = *reinterpret_cast<const uint4*>(p);
+    const uint4 v1 = *reinterpret_cast<const uint4*>(p + 4);
+    out[0] = v0.x;
+    out[1] = v0.y;
+    out[2] = v0.z;
+    out[3] = v0.w;
+    out[4] = v1.x;
+    out[5] = v1.y;
+    out[6] = v1.z;
+    out[7] = v1.w;
+  } else if constexpr (Mf<T>::LW == 4) {
     const uint4 v = *reinterpret_cast<const uint4*>(p);
     out[0] = v.x;
     out[1] = v.y;
@@ -115,7 +135,7 @@ __device__ __forceinline__ int out_row(int lane, int v) {
 // rows of A go straight from memory into the operand registers (the next
 // chunk in flight while the current one is multiplied), the packed X^T
 // chunk (128 columns x 128 bytes) is staged in LDS, double-buffered.
-template <typename T, bool SCALED, int PD>
+template <typename T, bool SCALED, int PD, int NT>
 __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
     int64_t n, int64_t K, int N, const T* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld, const T* __restrict__ Xt,
@@ -138,7 +158,10 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   }
   const int64_t row0 = rb * 128;
   const int64_t col0 = cb * 128;
-  const int nt = static_cast<int>((N - col0 + 31) / 32 < 4 ? (N - col0 + 31) / 32 : 4);
+  // NT output tiles of 32 columns (compile time: no branch between the
+  // matrix-core steps); tiles past the valid columns multiply the zeros
+  // staged for them and are not stored
+  const int nt = static_cast<int>((N - col0 + 31) / 32 < NT ? (N - col0 + 31) / 32 : NT);
   const int64_t row = row0 + 32 * w + r32;
   const uint4* arow =
       reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h + c0 * 8;
@@ -199,13 +222,11 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
 #pragma unroll
         for (int q = 0; q < STEPS; ++q) {
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt) {
-            if (tt < nt) {
-              uint32_t bw[LW];
-              lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
-              if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
-              else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
-            }
+          for (int tt = 0; tt < NT; ++tt) {
+            uint32_t bw[LW];
+            lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
+            if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
+            else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
           }
         }
         if (SCALED) {
@@ -213,7 +234,7 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
           // scale column c
           const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + c] * xscale[c0 + c];
 #pragma unroll
-          for (int tt = 0; tt < 4; ++tt) acc[tt] += sc * tmp[tt];
+          for (int tt = 0; tt < NT; ++tt) acc[tt] += sc * tmp[tt];
         }
         if (more) {
 #pragma unroll
@@ -371,7 +392,7 @@ struct PLoad {
 // rows [s Ls, (s+1) Ls) of split s = blockIdx.z.  Y is either raw FP32
 // (row-major L x r, transposing load; T = float only) or packed
 // (r_pad x L_pad in T, zero padded, with FP8 scales per 128 rows).
-template <typename T, bool SCALED, bool PACKED_Y>
+template <typename T, bool SCALED, bool PACKED_Y, int NT>
 __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
     int64_t L, int64_t p, int r, const T* __restrict__ X, int64_t ldx,
     const float* __restrict__ xscale, int64_t xscale_ld, const float* __restrict__ Yraw,
@@ -389,7 +410,10 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   const int64_t sidx = blockIdx.y;
   const int64_t lb = sidx * Ls;
   const int64_t le = (lb + Ls < L) ? lb + Ls : L;
-  const int nt = static_cast<int>((r - r0 + 31) / 32 < 4 ? (r - r0 + 31) / 32 : 4);
+  // NT output tiles of 32 columns at compile time (tiles past the valid
+  // columns multiply the zeros staged for them and are not stored)
+  const int ntmax = NT > 0 ? NT : 4;
+  const int nt = static_cast<int>((r - r0 + 31) / 32 < ntmax ? (r - r0 + 31) / 32 : ntmax);
   const int64_t nch = (le - lb + KC - 1) / KC;
   // running sums: FP64 for FP32 operands; FP32 for BF16 / FP8, whose
   // rounding of the operands is ~2^-9 / 2^-4, far above FP32 summation
@@ -403,7 +427,7 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   // chunks of X in a ring of R = PD register sets: while chunk c is read
   // from LDS, chunks c+1 .. c+PD are in registers or in flight (chunk c+PD
   // goes into the slot chunk c left); Y (raw or packed) one chunk ahead
-  constexpr int PD = sizeof(T) == 4 ? 1 : 3;
+  constexpr int PD = sizeof(T) == 2 ? 2 : 1;
   constexpr int R = PD;
   TLoad<T> xr[R];
   TLoad<float> ya;
@@ -447,28 +471,36 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
                static_cast<ACC>(yscale[lt]);
         }
         // chunk sums two output tiles at a time (fewer live FP32 registers)
+        // two output tiles per pass (fewer live FP32 registers); NT = 0:
+        // the tile count is the runtime nt (FP32, whose long matrix-core
+        // steps hide the branches and whose FP64 sums leave no registers
+        // for a fully unrolled pass)
+        constexpr int NTT = NT > 0 ? NT : 4;
+        constexpr int NU = NTT < 2 ? NTT : 2;
 #pragma unroll
-        for (int pr = 0; pr < 2; ++pr) {
-          if (2 * pr < nt) {
-            f32x16 tmp[2] = {f32x16{}, f32x16{}};
+        for (int pr = 0; pr < (NTT + 1) / 2; ++pr) {
+          if (NT > 0 || NU * pr < nt) {
+            f32x16 tmp[NU];
+#pragma unroll
+            for (int uu = 0; uu < NU; ++uu) tmp[uu] = f32x16{};
 #pragma unroll
             for (int q = 0; q < STEPS; ++q) {
               uint32_t aw[LW];
               lds_operand<T>(at, 32 * w + r32, h, q, aw);
 #pragma unroll
-              for (int uu = 0; uu < 2; ++uu) {
-                if (2 * pr + uu < nt) {
+              for (int uu = 0; uu < NU; ++uu) {
+                if (NT > 0 || NU * pr + uu < nt) {
                   uint32_t bw[LW];
-                  lds_operand<T>(bt, 32 * (2 * pr + uu) + r32, h, q, bw);
+                  lds_operand<T>(bt, 32 * (NU * pr + uu) + r32, h, q, bw);
                   tmp[uu] = mfma_step<T>(aw, bw, tmp[uu]);
                 }
               }
             }
 #pragma unroll
-            for (int uu = 0; uu < 2; ++uu)
+            for (int uu = 0; uu < NU; ++uu)
 #pragma unroll
               for (int v = 0; v < 16; ++v)
-                acc[2 * pr + uu][v] += sc * static_cast<ACC>(tmp[uu][v]);
+                acc[NU * pr + uu][v] += sc * static_cast<ACC>(tmp[uu][v]);
           }
         }
         if (more) {
@@ -771,12 +803,18 @@ static int nn_run(const NNArgs& a, int type, hipStream_t s) {
                   static_cast<unsigned>(S));
   const float al = static_cast<float>(a.alpha), be = static_cast<float>(a.beta);
   // chunks of A in flight: one for FP32 (a chunk is ~4000 cycles of
-  // matrix-core work), three for BF16 / FP8
-  constexpr int PD = sizeof(T) == 4 ? 1 : 3;
-  nn_mfma_kernel<T, SCALED, PD><<<grid, 256, 0, s>>>(
-      a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,
-      static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps,
-      S > 1 ? 1.0f : al, S > 1 ? 0.0f : be);
+  // matrix-core work), three for BF16, two for FP8 (whose scaled partial
+  // sums take the registers of the third)
+  constexpr int PD = sizeof(T) == 4 ? 1 : (sizeof(T) == 2 ? 3 : 2);
+#define BK_NN_LAUNCH(NTV)                                                                  \
+  nn_mfma_kernel<T, SCALED, PD, NTV><<<grid, 256, 0, s>>>(                                 \
+      a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,             \
+      static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps,               \
+      S > 1 ? 1.0f : al, S > 1 ? 0.0f : be)
+  if (a.N <= 32) BK_NN_LAUNCH(1);
+  else if (a.N <= 64) BK_NN_LAUNCH(2);
+  else BK_NN_LAUNCH(4);
+#undef BK_NN_LAUNCH
   if (S == 1) return 2;
   nn_split_reduce_kernel<<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(
       S, a.n, a.N, part, static_cast<float*>(a.C), a.ldc, al, be);
@@ -839,9 +877,18 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
   }
   const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),
                   static_cast<unsigned>(S));
-  tn_mfma_kernel<T, SCALED, PACKED><<<grid, 256, 0, s>>>(
-      a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,
-      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls, a.sym ? 1 : 0);
+#define BK_TN_LAUNCH(NTV)                                                                 \
+  tn_mfma_kernel<T, SCALED, PACKED, NTV><<<grid, 256, 0, s>>>(                            \
+      a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,            \
+      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls, a.sym ? 1 : 0)
+  if constexpr (sizeof(T) == 4) {
+    BK_TN_LAUNCH(0);
+  } else {
+    if (a.r <= 32) BK_TN_LAUNCH(1);
+    else if (a.r <= 64) BK_TN_LAUNCH(2);
+    else BK_TN_LAUNCH(4);
+  }
+#undef BK_TN_LAUNCH
 }
 
 void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {

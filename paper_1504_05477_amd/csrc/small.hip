@@ -377,9 +377,11 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
 // --------------------------------------------- chip-wide blocked Cholesky --
 // For 64 < k <= kCholBlockedMax: the factor of CholeskyQR as a short chain
 // of kernels instead of one workgroup walking a k x k matrix in memory:
-//   begin    the mode logic (non-finite, breakdown and rank tests) and the
-//            working copy S = G [+ shift] (upper triangle; block 0 first
-//            unshifted for its rank test);
+//   scan     the working copy S = upper(G) over the chip, with a check of
+//            every entry for finiteness and the traces;
+//   decide   the mode logic (non-finite, breakdown and rank tests) and the
+//            shift on the diagonal (block 0 first unshifted, for its rank
+//            test);
 //   panel p  one wavefront factors the 32 x 32 diagonal block R_pp in
 //            registers and inverts it; the panel row R_p,j = R_pp^-T S_p,j
 //            (a thread per column j);
@@ -389,39 +391,70 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
 //            per block column J (its column of Rinv in LDS);
 //   end      failure reports to ctrl, R = upper(S), zeros below the
 //            diagonals (everything zero after a failure).
-// Every kernel after begin returns at once when the state says the block is
+// Every kernel after decide returns at once when the state says the block is
 // dropped or a pivot failed.  All sums run in a fixed order.
 constexpr int CM = 32;
+
+constexpr int CM_SCAN_WG = 64;  // workgroups of the copy / finiteness scan
+constexpr int CM_WC = 64;       // columns of R rows per LDS chunk (inverse)
 
 struct CholMState {
   int decision;  // 1: dropped before or at the rank test
   int fail;      // 1: a pivot was not positive and finite
   int pad0, pad1;
   double minpiv;
-  double tr;
+  double tr;                 // trace of G
+  double pre;                // trace of Gpre (CHOL_FIRST)
+  int bad[CM_SCAN_WG];       // per scan workgroup: a non-finite entry of G
 };
 
-__global__ __launch_bounds__(256) void cholm_begin_kernel(int k, const double* __restrict__ G,
-                                                          const double* __restrict__ Gpre,
-                                                          int mode, int block, double tau,
-                                                          double shift_coef, Ctrl* ctrl,
-                                                          CholMState* st, double* __restrict__ S) {
+// S = upper triangle of G (zeros below), every entry checked for
+// finiteness (a flag per workgroup); workgroup 0 also sums the traces.
+__global__ __launch_bounds__(256) void cholm_scan_kernel(int k, const double* __restrict__ G,
+                                                         const double* __restrict__ Gpre,
+                                                         int mode, CholMState* st,
+                                                         double* __restrict__ S) {
   __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int64_t kk = static_cast<int64_t>(k) * k;
+  int bad = 0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + t; i < kk; i += CM_SCAN_WG * 256) {
+    const double g = G[i];
+    if (!isfinite(g)) bad = 1;
+    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
+    S[i] = (c >= r) ? g : 0.0;
+  }
+  const int anybad = __syncthreads_or(bad);
+  if (t == 0) st->bad[blockIdx.x] = anybad;
+  if (blockIdx.x == 0) {
+    double trp = 0.0, prp = 0.0;
+    for (int i = t; i < k; i += 256) {
+      trp += G[static_cast<int64_t>(i) * k + i];
+      if (mode == CHOL_FIRST) prp += Gpre[static_cast<int64_t>(i) * k + i];
+    }
+    const double tr = block_sum(trp, red);
+    const double pre = (mode == CHOL_FIRST) ? block_sum(prp, red) : 0.0;
+    if (t == 0) {
+      st->tr = tr;
+      st->pre = pre;
+    }
+  }
+}
+
+// The mode logic (non-finite, breakdown, rank tests) and the shift of the
+// first pass on the diagonal of S (block 0 is factored unshifted first,
+// for its rank test).
+__global__ __launch_bounds__(256) void cholm_decide_kernel(int k, int mode, int block, double tau,
+                                                           double shift_coef, Ctrl* ctrl,
+                                                           CholMState* st,
+                                                           double* __restrict__ S) {
   __shared__ int s_dec;
   __shared__ double s_tr;
   const int t = threadIdx.x;
-  double trp = 0.0, prp = 0.0;
-  int bad = 0;
-  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += 256)
-    if (!isfinite(G[i])) bad = 1;
-  for (int i = t; i < k; i += 256) {
-    trp += G[static_cast<int64_t>(i) * k + i];
-    if (mode == CHOL_FIRST) prp += Gpre[static_cast<int64_t>(i) * k + i];
-  }
-  const int anybad = __syncthreads_or(bad);
-  const double tr = block_sum(trp, red);
-  const double pre = (mode == CHOL_FIRST) ? block_sum(prp, red) : 0.0;
+  const int b = t < CM_SCAN_WG ? st->bad[t] : 0;
+  const int anybad = __syncthreads_or(b);
   if (t == 0) {
+    const double tr = st->tr, pre = st->pre;
     int dec = 0;
     if (anybad) {
       atomicOr(&ctrl->flags, CTRL_NONFINITE);
@@ -438,18 +471,13 @@ __global__ __launch_bounds__(256) void cholm_begin_kernel(int k, const double* _
     st->decision = dec;
     st->fail = 0;
     st->minpiv = INFINITY;
-    st->tr = tr;
     s_dec = dec;
     s_tr = tr;
   }
   __syncthreads();
-  if (s_dec) return;
-  // block 0 is factored unshifted first (its rank test)
-  const double shift = (mode == CHOL_FIRST) ? shift_coef * s_tr : 0.0;
-  for (int64_t i = t; i < static_cast<int64_t>(k) * k; i += 256) {
-    const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
-    S[i] = (c >= r) ? G[i] + (r == c ? shift : 0.0) : 0.0;
-  }
+  if (s_dec || mode != CHOL_FIRST) return;
+  const double shift = shift_coef * s_tr;
+  for (int i = t; i < k; i += 256) S[static_cast<int64_t>(i) * k + i] += shift;
 }
 
 // Block 0: the unshifted factor decides the rank; then S = G + shift I.
@@ -480,92 +508,88 @@ __global__ __launch_bounds__(256) void cholm_rank_kernel(int k, const double* __
   }
 }
 
-__global__ __launch_bounds__(256) void cholm_panel_kernel(int k, int o, double* __restrict__ S,
-                                                          double* __restrict__ Rinv,
-                                                          CholMState* st) {
-  __shared__ double rkk[CM * CM];
-  __shared__ int s_fail;
-  __shared__ double s_mp;
+// Diagonal block p: one wavefront factors S_pp (32 x 32, trailing updates
+// applied) and inverts it: R_pp into R, R_pp^-1 into Rinv.  Lane c holds
+// column c in registers; each step broadcasts row j through LDS (one write
+// per lane, reads of the same address by every lane), and the inverse runs
+// by back substitution, a column per lane, over R_pp staged in LDS.
+__global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const double* __restrict__ S,
+                                                        double* __restrict__ R,
+                                                        double* __restrict__ Rinv,
+                                                        CholMState* st) {
+  __shared__ double row[CM];
+  __shared__ double Rs[CM][CM + 1];
+  __shared__ double rdiag[CM];
   if (st->decision || st->fail) return;
-  const int t = threadIdx.x;
+  const int c = threadIdx.x;  // lanes 0..31: columns; 32..63 idle but in step
   const int bs = (k - o < CM) ? k - o : CM;
-  if (t < 64) {  // the diagonal block in the registers of wavefront 0 (lane c: column c)
-    const int c = t;
-    double a[CM];
+  const bool col = c < CM;
+  double a[CM];
 #pragma unroll
-    for (int r = 0; r < CM; ++r)
-      a[r] = (c < bs) ? ((r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0)
-                      : (r == c ? 1.0 : 0.0);
-    bool ok = true;
-    double mp = INFINITY;
+  for (int r = 0; r < CM; ++r)
+    a[r] = (c < bs) ? ((r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0)
+                    : (r == c ? 1.0 : 0.0);
+  bool ok = true;
+  double mp = INFINITY;
 #pragma unroll
-    for (int j = 0; j < CM; ++j) {  // no early exit: the loop stays unrolled
-      double d = lane_f64(a[j], j);
-      if (!(d > 0.0) || !isfinite(d)) {
-        ok = false;
-        d = 1.0;
-      }
-      const double rd = sqrt(d);
-      if (j < bs) mp = fmin(mp, rd);
-      a[j] = (c == j) ? rd : a[j] * (1.0 / rd);
-#pragma unroll
-      for (int r = j + 1; r < CM; ++r) a[r] -= lane_f64(a[j], r) * a[j];
+  for (int j = 0; j < CM; ++j) {
+    if (col) row[c] = a[j];
+    __syncthreads();
+    double d = row[j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      ok = false;
+      d = 1.0;
     }
-    // x = column c of R_pp^-1 by back substitution
-    double x[CM];
+    const double rd = sqrt(d);
+    const double inv = 1.0 / rd;
+    if (j < bs) mp = fmin(mp, rd);
+    const double rjc = (c == j) ? rd : a[j] * inv;  // R[j][c]
+    a[j] = rjc;
 #pragma unroll
-    for (int i = CM - 1; i >= 0; --i) {
-      double sum = 0.0;
+    for (int r = j + 1; r < CM; ++r) a[r] -= (row[r] * inv) * rjc;
+    __syncthreads();
+  }
+  if (col) {
 #pragma unroll
-      for (int l = i + 1; l < CM; ++l) sum += lane_f64(a[i], l) * x[l];
-      x[i] = ((i == c ? 1.0 : 0.0) - sum) / lane_f64(a[i], i);
-    }
-    if (ok && c < bs) {
-#pragma unroll
-      for (int r = 0; r < CM; ++r) {
-        if (r <= c) {
-          S[static_cast<int64_t>(o + r) * k + o + c] = a[r];
-          Rinv[static_cast<int64_t>(o + r) * k + o + c] = x[r];
-        }
-      }
-    }
-    // R_pp^-1 (zero outside the block and below its diagonal) for the panel
-    if (c < CM) {
-#pragma unroll
-      for (int r = 0; r < CM; ++r) rkk[r * CM + c] = (ok && c < bs && r <= c) ? x[r] : 0.0;
-    }
-    if (c == 0) {
-      s_fail = ok ? 0 : 1;
-      s_mp = mp;
-    }
+    for (int r = 0; r < CM; ++r) Rs[r][c] = a[r];
+    rdiag[c] = 1.0 / a[c];
   }
   __syncthreads();
-  if (s_fail) {
-    if (t == 0) st->fail = 1;
-    return;
+  // x = column c of R_pp^-1: x_i = (delta_ic - sum_{l > i} R_il x_l) / R_ii
+  double x[CM];
+#pragma unroll
+  for (int i = CM - 1; i >= 0; --i) {
+    double sum = 0.0;
+#pragma unroll
+    for (int l = i + 1; l < CM; ++l) sum += Rs[i][l] * x[l];
+    x[i] = ((i == c ? 1.0 : 0.0) - sum) * rdiag[i];
   }
-  if (t == 0 && s_mp < st->minpiv) st->minpiv = s_mp;
-  const int rest = k - o - bs;
-  // panel row: R[o + r][j] = sum_{l <= r} Rinv_pp[l][r] S[o + l][j]
-  for (int jj = t; jj < rest; jj += 256) {
-    const int64_t j = o + bs + jj;
-    double col[CM];
+  if (ok && c < bs) {
 #pragma unroll
-    for (int l = 0; l < CM; ++l) col[l] = (l < bs) ? S[static_cast<int64_t>(o + l) * k + j] : 0.0;
-#pragma unroll 4
     for (int r = 0; r < CM; ++r) {
-      double sum = 0.0;
-#pragma unroll
-      for (int l = 0; l < CM; ++l) sum += rkk[l * CM + r] * col[l];
-      if (r < bs) S[static_cast<int64_t>(o + r) * k + j] = sum;
+      if (r <= c) {
+        R[static_cast<int64_t>(o + r) * k + o + c] = a[r];
+        Rinv[static_cast<int64_t>(o + r) * k + o + c] = x[r];
+      }
     }
+  }
+  if (c == 0) {
+    if (!ok) st->fail = 1;
+    else if (mp < st->minpiv) st->minpiv = mp;
   }
 }
 
+// Trailing update after diagonal block p, a workgroup per 32 x 32 tile
+// (ti, tj), ti <= tj, of the trailing upper triangle: the two panel-row
+// blocks R_p,ti = R_pp^-T S_p,ti and R_p,tj (32 x 32 x 32 each, from the
+// raw rows of S, which stay untouched), then S_ti,tj -= R_p,ti^T R_p,tj.
+// The diagonal tiles store their panel-row block into R.
 __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
                                                            double* __restrict__ S,
+                                                           double* __restrict__ R,
+                                                           const double* __restrict__ Rinv,
                                                            const CholMState* st) {
-  __shared__ double Pi[CM][CM + 1], Pj[CM][CM + 1];
+  __shared__ double Ri[CM][CM + 1], Pi[CM][CM + 1], Pj[CM][CM + 1];
   if (st->decision || st->fail) return;
   const int t = threadIdx.x;
   const int base = o + bs, rest = k - base;
@@ -581,11 +605,42 @@ __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
     const int r = idx / CM, c = idx % CM;
     const int gi = base + CM * ti + c, gj = base + CM * tj + c;
     const int64_t row = static_cast<int64_t>(o + r) * k;
+    Ri[r][c] = (r < bs && c < bs && r <= c) ? Rinv[row + o + c] : 0.0;  // R_pp^-1 (upper)
     Pi[r][c] = (r < bs && gi < k) ? S[row + gi] : 0.0;
     Pj[r][c] = (r < bs && gj < k) ? S[row + gj] : 0.0;
   }
   __syncthreads();
+  // panel rows: X[r][c] = sum_{l <= r} Rinv_pp[l][r] P[l][c], four per thread
   const int tx = t & 31, ty = t >> 5;
+  double xi[4], xj[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = ty + 8 * u;
+    double si = 0.0, sj = 0.0;
+#pragma unroll 8
+    for (int l = 0; l < CM; ++l) {
+      const double w = Ri[l][r];
+      si += w * Pi[l][tx];
+      sj += w * Pj[l][tx];
+    }
+    xi[u] = si;
+    xj[u] = sj;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    Pi[ty + 8 * u][tx] = xi[u];
+    Pj[ty + 8 * u][tx] = xj[u];
+  }
+  __syncthreads();
+  if (ti == tj) {
+    const int gc = base + CM * ti + tx;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int r = ty + 8 * u;
+      if (r < bs && gc < k) R[static_cast<int64_t>(o + r) * k + gc] = Pi[r][tx];
+    }
+  }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int ii = ty + 8 * u;
@@ -600,8 +655,9 @@ __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
 }
 
 // Block column J of R^-1 above its diagonal block (workgroup J); X holds
-// rows 0 .. oj + bj - 1 of the column (the diagonal block from the panels).
-__global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double* __restrict__ S,
+// rows 0 .. oj + bj - 1 of the column (the diagonal block from the panels),
+// the rows of R of the current block row go through LDS.
+__global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double* __restrict__ R,
                                                             double* __restrict__ Rinv,
                                                             const CholMState* st) {
   extern __shared__ double cm_dyn[];
@@ -611,7 +667,9 @@ __global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double*
   if (J == 0) return;
   const int t = threadIdx.x;
   const int oj = J * CM, bj = (k - oj < CM) ? k - oj : CM;
-  double* X = cm_dyn;  // (oj + bj) x (CM + 1)
+  const int span = oj + bj;        // rows of X, columns of the R rows used
+  double* X = cm_dyn;              // span x (CM + 1)
+  double* Rb = cm_dyn + static_cast<int64_t>(span) * (CM + 1);  // CM x CM_WC
   for (int idx = t; idx < CM * CM; idx += 256) {
     const int r = idx / CM, c = idx % CM;
     X[(oj + r) * (CM + 1) + c] =
@@ -621,16 +679,27 @@ __global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double*
   const int c = t & 31, r0 = t >> 5;
   for (int I = J - 1; I >= 0; --I) {
     const int oi = I * CM;
-    // T = sum_{L = I+1 .. J} R_IL X_L  (rows oi .. oi+31 of R, columns oi+32 ..)
+    const int w = span - (oi + CM);  // columns oi+32 .. span-1 of rows oi .. oi+31
+    // T = sum_{L = I+1 .. J} R_IL X_L, the rows of R in chunks of CM_WC columns
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int l0 = 0; l0 < w; l0 += CM_WC) {
+      const int wc = (w - l0 < CM_WC) ? w - l0 : CM_WC;
+      for (int idx = t; idx < CM * wc; idx += 256) {
+        const int r = idx / wc, l = idx - (idx / wc) * wc;
+        Rb[r * CM_WC + l] = R[static_cast<int64_t>(oi + r) * k + oi + CM + l0 + l];
+      }
+      __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = r0 + 8 * u;
-      const double* srow = S + static_cast<int64_t>(oi + r) * k;
-      double sum = 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const int r = r0 + 8 * u;
 #pragma unroll 8
-      for (int l = oi + CM; l < oj + bj; ++l) sum += srow[l] * X[l * (CM + 1) + c];
-      T[r][c] = sum;
+        for (int l = 0; l < wc; ++l)
+          acc[u] += Rb[r * CM_WC + l] * X[(oi + CM + l0 + l) * (CM + 1) + c];
+      }
+      __syncthreads();
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) T[r0 + 8 * u][c] = acc[u];
     __syncthreads();
     // X_I = -Rinv_II T (Rinv_II upper triangular, from the panels)
 #pragma unroll
@@ -650,8 +719,7 @@ __global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double*
   }
 }
 
-__global__ __launch_bounds__(256) void cholm_end_kernel(int k, const double* __restrict__ S,
-                                                        double* __restrict__ R,
+__global__ __launch_bounds__(256) void cholm_end_kernel(int k, double* __restrict__ R,
                                                         double* __restrict__ Rinv, int block,
                                                         Ctrl* ctrl, const CholMState* st) {
   const int dec = st->decision, fail = st->fail;
@@ -663,9 +731,10 @@ __global__ __launch_bounds__(256) void cholm_end_kernel(int k, const double* __r
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= static_cast<int64_t>(k) * k) return;
   const int r = static_cast<int>(i / k), c = static_cast<int>(i - static_cast<int64_t>(r) * k);
-  const bool up = c >= r;
-  R[i] = (zero || !up) ? 0.0 : S[i];
-  if (zero || !up) Rinv[i] = 0.0;
+  if (zero || c < r) {
+    R[i] = 0.0;
+    Rinv[i] = 0.0;
+  }
 }
 
 __global__ __launch_bounds__(256) void trmm_upper_kernel(int k, const double* A,
@@ -917,21 +986,23 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
     if (!mattr) {
       (void)hipFuncSetAttribute(reinterpret_cast<const void*>(cholm_inverse_kernel),
                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>(kCholBlockedMax * (CM + 1) * sizeof(double)));
+                                static_cast<int>((kCholBlockedMax * (CM + 1) + CM * CM_WC) *
+                                                 sizeof(double)));
       mattr = true;
     }
     double* S = work;
     CholMState* st = reinterpret_cast<CholMState*>(work + static_cast<int64_t>(k) * k);
     const int nb = (k + CM - 1) / CM;
-    cholm_begin_kernel<<<1, 256, 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, ctrl, st, S);
+    cholm_scan_kernel<<<CM_SCAN_WG, 256, 0, s>>>(k, G, Gpre, mode, st, S);
+    cholm_decide_kernel<<<1, 256, 0, s>>>(k, mode, block, tau, shift_coef, ctrl, st, S);
     auto factor = [&]() {
       for (int p = 0; p < nb; ++p) {
         const int o = p * CM, bs = std::min(CM, k - o);
-        cholm_panel_kernel<<<1, 256, 0, s>>>(k, o, S, Rinv, st);
+        cholm_diag_kernel<<<1, 64, 0, s>>>(k, o, S, R, Rinv, st);
         const int rest = k - o - bs;
         if (rest > 0) {
           const int nt = (rest + CM - 1) / CM;
-          cholm_update_kernel<<<nt * (nt + 1) / 2, 256, 0, s>>>(k, o, bs, S, st);
+          cholm_update_kernel<<<nt * (nt + 1) / 2, 256, 0, s>>>(k, o, bs, S, R, Rinv, st);
         }
       }
     };
@@ -940,10 +1011,13 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
       cholm_rank_kernel<<<1, 256, 0, s>>>(k, G, tau, shift_coef, ctrl, st, S);
       factor();
     }
-    cholm_inverse_kernel<<<nb, 256, static_cast<size_t>(nb * CM) * (CM + 1) * sizeof(double), s>>>(
-        k, S, Rinv, st);
+    // X (k x 33) and a chunk of the rows of R of one block row (32 x 64):
+    // at most 160000 bytes (k = 512, with the static T)
+    const size_t inv_lds =
+        (static_cast<size_t>(nb * CM) * (CM + 1) + static_cast<size_t>(CM) * CM_WC) * sizeof(double);
+    cholm_inverse_kernel<<<nb, 256, inv_lds, s>>>(k, R, Rinv, st);
     cholm_end_kernel<<<static_cast<unsigned>(cdiv(static_cast<int64_t>(k) * k, 256)), 256, 0, s>>>(
-        k, S, R, Rinv, block, ctrl, st);
+        k, R, Rinv, block, ctrl, st);
     return;
   }
   chol_kernel<<<1, 256, use_lds ? need : 0, s>>>(k, G, Gpre, mode, block, tau, shift_coef, R,

@@ -757,11 +757,13 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
 
 // ------------------------------------------------- large m (> TRI_SMALL) --
 // The same reduction with the trailing block in global memory and the work
-// of a step spread over the chip, in two launches per step:
-//   tribig_step_kernel (one workgroup): finishes step j-1 (p = beta A' v
-//     from the column partial sums, w = p - (beta v^T p / 2) v, which become
-//     the pending update) and forms reflector j from column j with that
-//     update applied (row j of the symmetric square, read contiguously);
+// of a step spread over the chip, in three launches per step:
+//   tribig_reduce_kernel (grid): p = beta A' v of step j-1 from the row-group
+//     partial sums, and partials of v^T p;
+//   tribig_step_kernel (one workgroup): finishes step j-1 (w = p - (beta
+//     v^T p / 2) v, which with v becomes the pending update) and forms
+//     reflector j from column j with that update applied (row j of the
+//     symmetric square, read contiguously);
 //   tribig_update_kernel (grid): applies the pending update to the trailing
 //     square (both triangles, a thread per column, 64-row groups) and
 //     writes the partial sums of A' v_j per row group, added in group order
@@ -769,32 +771,60 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
 constexpr int TBG_ROWS = 64;
 constexpr int TBG_COLS = 256;
 
+// Finish of step j-1 over the chip: p_l = beta_{j-1} (sum over the row
+// groups, in group order, of the partials of A' v_{j-1}) for l >= j, and
+// the workgroup's partial of v_{j-1}^T p (its 256 entries in order).
+__global__ __launch_bounds__(256) void tribig_reduce_kernel(int64_t m, int64_t j,
+                                                            const double* __restrict__ v,
+                                                            const double* __restrict__ part,
+                                                            int G, const double* __restrict__ beta,
+                                                            double* __restrict__ pbuf,
+                                                            double* __restrict__ dotpart) {
+  __shared__ double red[4];
+  const int t = threadIdx.x;
+  const int64_t l = j + static_cast<int64_t>(blockIdx.x) * 256 + t;
+  double vp = 0.0;
+  if (l < m) {
+    double sum = 0.0;
+    int g = 0;
+    for (; g + 8 <= G; g += 8) {
+      double q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) q[u] = part[static_cast<int64_t>(g + u) * m + l];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += q[u];
+    }
+    for (; g < G; ++g) sum += part[static_cast<int64_t>(g) * m + l];
+    const double pl = beta[j - 1] * sum;
+    pbuf[l] = pl;
+    vp = v[l] * pl;
+  }
+  // fixed order: lanes by butterfly, then the four wavefronts in order
+  for (int o = 32; o > 0; o >>= 1) vp += __shfl_xor(vp, o);
+  if ((t & 63) == 0) red[t >> 6] = vp;
+  __syncthreads();
+  if (t == 0) dotpart[blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
 __global__ __launch_bounds__(1024) void tribig_step_kernel(
     double* __restrict__ A, int64_t m, int64_t j, double* __restrict__ v,
-    double* __restrict__ vp, double* __restrict__ wp, const double* __restrict__ part, int G,
-    double* __restrict__ Vh, double* __restrict__ beta, double* __restrict__ dg,
-    double* __restrict__ eo) {
-  extern __shared__ double p_s[];  // m
+    double* __restrict__ vp, double* __restrict__ wp, const double* __restrict__ pbuf,
+    const double* __restrict__ dotpart, int ND, double* __restrict__ Vh,
+    double* __restrict__ beta, double* __restrict__ dg, double* __restrict__ eo) {
   __shared__ double red[TRI_THREADS / 64];
   __shared__ double s_diag;
   const int t = threadIdx.x;
   if (j >= 1) {
-    // finish step j-1 over rows / columns j .. m-1
+    // finish step j-1 over rows / columns j .. m-1: p and the partials of
+    // v^T p came from the reduction kernel (added here in order)
     const double bprev = beta[j - 1];
     double vtp = 0.0;
-    for (int64_t l = j + t; l < m; l += TRI_THREADS) {
-      double sum = 0.0;
-      for (int g = 0; g < G; ++g) sum += part[g * m + l];
-      const double pl = bprev * sum;
-      p_s[l] = pl;
-      vtp += v[l] * pl;
-    }
-    vtp = block_sum_1024(vtp, red);
+    for (int b = 0; b < ND; ++b) vtp += dotpart[b];
     const double K = 0.5 * bprev * vtp;
     for (int64_t l = j + t; l < m; l += TRI_THREADS) {
       const double vl = v[l];
       vp[l] = vl;
-      wp[l] = p_s[l] - K * vl;
+      wp[l] = pbuf[l] - K * vl;
     }
     __syncthreads();
   }
@@ -946,7 +976,8 @@ int64_t tridiag_scratch_doubles(int64_t m, int k) {
   return 2 * m * m + 3 * m + static_cast<int64_t>(k) * m +
          std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024) +
          (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64 +
-         static_cast<int64_t>(k) * m + 3 * kk + chol_work_doubles(k) + 8;
+         static_cast<int64_t>(k) * m + 3 * kk + chol_work_doubles(k) + 8 +
+         m + cdiv(m, 256) + 64;  // p and the v^T p partials of the large-m steps
 }
 
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double* scratch,
@@ -968,7 +999,9 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   double* Vg = part + cdiv(m, TBG_ROWS) * m;
   double* Wg = Vg + TRI_NB * m;
   const int64_t kk = static_cast<int64_t>(k) * k;
-  double* Xn = Wg + TRI_NB * m + 64;
+  double* pbuf = Wg + TRI_NB * m + 64;
+  double* dotpart = pbuf + m;
+  double* Xn = dotpart + cdiv(m, 256) + 64;
   double* Gx = Xn + static_cast<int64_t>(k) * m;
   double* Rx = Gx + kk;
   double* Rix = Rx + kk;
@@ -1012,18 +1045,26 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
         A, m, j, Vh, beta, dg, eo);
   } else {
     launch_fill_f64(v, 3 * m, 0.0, s);  // v, vp, wp
-    int G = 0;
+    int G = 0, ND = 0;
+    // reduce (grid) -> step (one workgroup) -> update (grid) per step
+    auto finish = [&](int64_t j) {
+      if (j >= 1) {
+        ND = static_cast<int>(cdiv(m - j, 256));
+        tribig_reduce_kernel<<<static_cast<unsigned>(ND), 256, 0, s>>>(m, j, v, part, G, beta,
+                                                                       pbuf, dotpart);
+      }
+      tribig_step_kernel<<<1, TRI_THREADS, 0, s>>>(A, m, j, v, vp, wp, pbuf, dotpart, ND, Vh,
+                                                   beta, dg, eo);
+    };
     for (int64_t j = 0; j + 2 < m; ++j) {
-      tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, j, v, vp, wp, part, G,
-                                                                    Vh, beta, dg, eo);
+      finish(j);
       const int64_t sj = m - j - 1;
       G = static_cast<int>(cdiv(sj, TBG_ROWS));
       tribig_update_kernel<<<dim3(static_cast<unsigned>(cdiv(sj, TBG_COLS)),
                                   static_cast<unsigned>(G)),
                              TBG_COLS, 0, s>>>(A, m, j, v, vp, wp, part);
     }
-    tribig_step_kernel<<<1, TRI_THREADS, m * sizeof(double), s>>>(A, m, m - 2, v, vp, wp, part,
-                                                                  G, Vh, beta, dg, eo);
+    finish(m - 2);
   }
   // eigenvalues: a workgroup each; eigenvectors: a workgroup per cluster,
   // its factors in LDS when they fit beside the tridiagonal
