@@ -187,6 +187,10 @@ def main():
     ap.add_argument("--no-parity", action="store_true",
                     help="skip the comparison with the float64 oracle")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
+    ap.add_argument("--input", default="planted", choices=["planted", "gaussian"],
+                    help="dense workloads: the planted matrix of the workload, or a seeded "
+                         "N(0, 1/d) matrix of the same shape built without factorizations "
+                         "(for profiler counter runs; no parity or CPU baseline)")
     ap.add_argument("--method", default="bki", choices=["bki", "lanczos", "si"],
                     help="Rayleigh-Ritz matrix: W^T W (Algorithm 2) or the block-tridiagonal "
                          "T of the block Lanczos recurrence (Section 4.2); or simultaneous "
@@ -338,7 +342,16 @@ def run_dense(args, w, bk, torch):
     sv = workloads.spectrum(w.spectrum, min(w.n, w.d))
     factors = None
     gen_stats = {}
-    if w.n * w.d <= 4_000_000:
+    if args.input == "gaussian":
+        args.no_parity = args.no_cpu_baseline = True
+        args.time_to_eps = False
+        g = torch.Generator(device=dev)
+        g.manual_seed(w.seed_matrix)
+        A = torch.empty(w.n, w.d, dtype=torch.float32, device=dev)
+        for r0 in range(0, w.n, 8192):
+            r1 = min(w.n, r0 + 8192)
+            A[r0:r1] = torch.randn(r1 - r0, w.d, generator=g, device=dev) / float(np.sqrt(w.d))
+    elif w.n * w.d <= 4_000_000:
         A64 = workloads.planted_dense(w.n, w.d, sv, w.seed_matrix, noise=w.noise,
                                       noise_seed=w.seed_noise)
         A = torch.from_numpy(A64).to(dev)
@@ -405,7 +418,8 @@ def run_dense(args, w, bk, torch):
     out = base_record(args, w, summ["value"], unit, leg["ms"], main_dtype,
                       {"product_bytes_per_solve": int(summ["bytes_per_product"]
                                                       * summ["products_per_solve"]),
-                       "product_flops_per_solve": flops_per_product * summ["products_per_solve"]})
+                       "product_flops_per_solve": flops_per_product * summ["products_per_solve"],
+                       "input": args.input})
     out["roofline"] = dense_roofline(leg, args, w, main_dtype, a_bytes, x_bytes, pw)
     out["phases_ms_per_step"] = {p: round(v, 4) for p, v in leg["phases"].items()}
     out["q_eff"] = leg["last"].info["q_eff"]

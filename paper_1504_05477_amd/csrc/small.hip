@@ -387,8 +387,8 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
 //            (a thread per column j);
 //   update p S_ij -= sum_r R_ri R_rj on the trailing upper triangle, one
 //            workgroup per 32 x 32 tile;
-//   inverse  Rinv_IJ = -Rinv_II sum_{L=I+1..J} R_IL Rinv_LJ, one workgroup
-//            per block column J (its column of Rinv in LDS);
+//   inverse  R^-1 by doubling: neighbouring diagonal blocks joined level by
+//            level, X12 = -X11 R12 X22, a workgroup per 32 x 32 tile;
 //   end      failure reports to ctrl, R = upper(S), zeros below the
 //            diagonals (everything zero after a failure).
 // Every kernel after decide returns at once when the state says the block is
@@ -396,7 +396,6 @@ __global__ __launch_bounds__(64) void chol_wave_kernel(int k, const double* __re
 constexpr int CM = 32;
 
 constexpr int CM_SCAN_WG = 64;  // workgroups of the copy / finiteness scan
-constexpr int CM_WC = 64;       // columns of R rows per LDS chunk (inverse)
 
 struct CholMState {
   int decision;  // 1: dropped before or at the rank test
@@ -654,70 +653,71 @@ __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
   }
 }
 
-// Block column J of R^-1 above its diagonal block (workgroup J); X holds
-// rows 0 .. oj + bj - 1 of the column (the diagonal block from the panels),
-// the rows of R of the current block row go through LDS.
-__global__ __launch_bounds__(256) void cholm_inverse_kernel(int k, const double* __restrict__ R,
-                                                            double* __restrict__ Rinv,
-                                                            const CholMState* st) {
-  extern __shared__ double cm_dyn[];
-  __shared__ double T[CM][CM + 1];
+// R^-1 by doubling (after the diagonal blocks' inverses): at level L the
+// pairs of neighbouring diagonal blocks of 2^(L-1) 32-blocks become one,
+// with X12 = -X11 (R12 X22): phase 0 forms T = R12 X22 into the scratch S
+// (no longer needed once R is complete), phase 1 writes -X11 T into R^-1.
+// A workgroup per 32 x 32 output tile; the lower triangles of the diagonal
+// blocks of R^-1 (not written by the diagonal kernel) read as zero.
+template <int PHASE>
+__global__ __launch_bounds__(256) void cholm_invlevel_kernel(int k, int nbb,
+                                                             const double* __restrict__ R,
+                                                             double* __restrict__ Rinv,
+                                                             double* __restrict__ T,
+                                                             const CholMState* st) {
+  __shared__ double Ab[CM][CM + 1], Bb[CM][CM + 1];
   if (st->decision || st->fail) return;
-  const int J = blockIdx.x;
-  if (J == 0) return;
-  const int t = threadIdx.x;
-  const int oj = J * CM, bj = (k - oj < CM) ? k - oj : CM;
-  const int span = oj + bj;        // rows of X, columns of the R rows used
-  double* X = cm_dyn;              // span x (CM + 1)
-  double* Rb = cm_dyn + static_cast<int64_t>(span) * (CM + 1);  // CM x CM_WC
-  for (int idx = t; idx < CM * CM; idx += 256) {
-    const int r = idx / CM, c = idx % CM;
-    X[(oj + r) * (CM + 1) + c] =
-        (r < bj && c < bj && r <= c) ? Rinv[static_cast<int64_t>(oj + r) * k + oj + c] : 0.0;
-  }
-  __syncthreads();
-  const int c = t & 31, r0 = t >> 5;
-  for (int I = J - 1; I >= 0; --I) {
-    const int oi = I * CM;
-    const int w = span - (oi + CM);  // columns oi+32 .. span-1 of rows oi .. oi+31
-    // T = sum_{L = I+1 .. J} R_IL X_L, the rows of R in chunks of CM_WC columns
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int l0 = 0; l0 < w; l0 += CM_WC) {
-      const int wc = (w - l0 < CM_WC) ? w - l0 : CM_WC;
-      for (int idx = t; idx < CM * wc; idx += 256) {
-        const int r = idx / wc, l = idx - (idx / wc) * wc;
-        Rb[r * CM_WC + l] = R[static_cast<int64_t>(oi + r) * k + oi + CM + l0 + l];
+  const int nb = (k + CM - 1) / CM;
+  const int per = nbb * nbb;
+  const int pair = blockIdx.x / per, rem = blockIdx.x - pair * per;
+  const int ti = rem / nbb, tj = rem - (rem / nbb) * nbb;
+  const int b1 = pair * 2 * nbb, b2 = b1 + nbb;  // first block of each half
+  const int I = b1 + ti, J = b2 + tj;
+  if (J >= nb) return;  // (uniform) past the last block
+  const int t = threadIdx.x, tx = t & 31, ty = t >> 5;
+  // PHASE 0: sum over L in [b2, J] of R[I][L] Rinv[L][J]
+  // PHASE 1: sum over L in [I, b2) of Rinv[I][L] T[L][J]
+  const int l0 = PHASE == 0 ? b2 : I;
+  const int l1 = PHASE == 0 ? J : b2 - 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int L = l0; L <= l1; ++L) {
+    for (int e = t; e < CM * CM; e += 256) {
+      const int r = e / CM, c = e - (e / CM) * CM;
+      const int ga = I * CM + r, gl = L * CM + c;   // left block (I, L)
+      const int gb = L * CM + r, gj = J * CM + c;   // right block (L, J)
+      double av = 0.0, bv = 0.0;
+      if (ga < k && gl < k) {
+        if (PHASE == 0) av = R[static_cast<int64_t>(ga) * k + gl];
+        else if (L != I || r <= c) av = Rinv[static_cast<int64_t>(ga) * k + gl];
       }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int r = r0 + 8 * u;
-#pragma unroll 8
-        for (int l = 0; l < wc; ++l)
-          acc[u] += Rb[r * CM_WC + l] * X[(oi + CM + l0 + l) * (CM + 1) + c];
+      if (gb < k && gj < k) {
+        if (PHASE == 0) bv = (L != J || r <= c) ? Rinv[static_cast<int64_t>(gb) * k + gj] : 0.0;
+        else bv = T[static_cast<int64_t>(gb) * k + gj];
       }
-      __syncthreads();
+      Ab[r][c] = av;
+      Bb[r][c] = bv;
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) T[r0 + 8 * u][c] = acc[u];
     __syncthreads();
-    // X_I = -Rinv_II T (Rinv_II upper triangular, from the panels)
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int r = r0 + 8 * u;
-      const double* rrow = Rinv + static_cast<int64_t>(oi + r) * k + oi;
+      const int r = ty + 8 * u;
       double sum = 0.0;
 #pragma unroll 8
-      for (int l = r; l < CM; ++l) sum += rrow[l] * T[l][c];
-      X[(oi + r) * (CM + 1) + c] = -sum;
+      for (int l = 0; l < CM; ++l) sum += Ab[r][l] * Bb[l][tx];
+      acc[u] += sum;
     }
     __syncthreads();
   }
-  for (int idx = t; idx < oj * CM; idx += 256) {
-    const int r = idx / CM, cc = idx % CM;
-    if (cc < bj) Rinv[static_cast<int64_t>(r) * k + oj + cc] = X[r * (CM + 1) + cc];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int gr = I * CM + ty + 8 * u, gc = J * CM + tx;
+    if (gr < k && gc < k) {
+      if (PHASE == 0) T[static_cast<int64_t>(gr) * k + gc] = acc[u];
+      else Rinv[static_cast<int64_t>(gr) * k + gc] = -acc[u];
+    }
   }
 }
+
 
 __global__ __launch_bounds__(256) void cholm_end_kernel(int k, double* __restrict__ R,
                                                         double* __restrict__ Rinv, int block,
@@ -982,14 +982,6 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
   BK_CHOL_WAVE(64)
 #undef BK_CHOL_WAVE
   if (k <= kCholBlockedMax) {
-    static bool mattr = false;
-    if (!mattr) {
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(cholm_inverse_kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                static_cast<int>((kCholBlockedMax * (CM + 1) + CM * CM_WC) *
-                                                 sizeof(double)));
-      mattr = true;
-    }
     double* S = work;
     CholMState* st = reinterpret_cast<CholMState*>(work + static_cast<int64_t>(k) * k);
     const int nb = (k + CM - 1) / CM;
@@ -1011,11 +1003,14 @@ void launch_chol(int k, const double* G, const double* Gpre, int mode, int block
       cholm_rank_kernel<<<1, 256, 0, s>>>(k, G, tau, shift_coef, ctrl, st, S);
       factor();
     }
-    // X (k x 33) and a chunk of the rows of R of one block row (32 x 64):
-    // at most 160000 bytes (k = 512, with the static T)
-    const size_t inv_lds =
-        (static_cast<size_t>(nb * CM) * (CM + 1) + static_cast<size_t>(CM) * CM_WC) * sizeof(double);
-    cholm_inverse_kernel<<<nb, 256, inv_lds, s>>>(k, R, Rinv, st);
+    // R^-1 above the diagonal blocks by doubling: log2(nb) levels of two
+    // launches
+    for (int nbb = 1; nbb < nb; nbb *= 2) {
+      const int pairs = (nb + 2 * nbb - 1) / (2 * nbb);
+      const unsigned g = static_cast<unsigned>(pairs * nbb * nbb);
+      cholm_invlevel_kernel<0><<<g, 256, 0, s>>>(k, nbb, R, Rinv, S, st);
+      cholm_invlevel_kernel<1><<<g, 256, 0, s>>>(k, nbb, R, Rinv, S, st);
+    }
     cholm_end_kernel<<<static_cast<unsigned>(cdiv(static_cast<int64_t>(k) * k, 256)), 256, 0, s>>>(
         k, R, Rinv, block, ctrl, st);
     return;
