@@ -30,6 +30,7 @@ struct Ctrl {
 enum : int32_t {
   CTRL_RANK = 1,       // block 0 rank deficient
   CTRL_NONFINITE = 2,  // NaN / Inf in a Gram matrix
+  CTRL_STALL = 4,      // a grid barrier gave up waiting (the device stalled)
 };
 
 #define BK_TRY(expr)                          \

@@ -747,7 +747,7 @@ struct Solver {
   int eig(const double* Mat, int64_t mm, JacobiWs& jw, int kk, double* Uk, int64_t ldu,
           double* ritz, double* tri = nullptr) {
     if (tri) {  // tridiagonal reduction path: top-k only
-      launch_tridiag_topk(Mat, mm, mm, kk, tri, jw.theta, Uk, ldu, ritz, s);
+      launch_tridiag_topk(Mat, mm, mm, kk, tri, jw.theta, Uk, ldu, ritz, L->ctrl, s);
       BK_TRY_LAUNCH();
       return BK_OK;
     }
@@ -794,6 +794,7 @@ void normalize_refine(Options& o, int a_type, bool has_master) {
 }
 
 int finish_status(const Ctrl& h, bool noconv) {
+  if (h.flags & CTRL_STALL) return BK_EHIP;
   if (h.flags & CTRL_NONFINITE) return BK_ENONFINITE;
   if (h.flags & CTRL_RANK) return BK_ERANK;
   if (noconv) return BK_ENOCONV;

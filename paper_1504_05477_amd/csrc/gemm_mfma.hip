@@ -175,74 +175,84 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   // A chunks in a ring of R = PD + 1 register sets, PD chunks in flight
   // ahead of the one multiplied (a chunk of BF16 / FP8 is a few hundred
   // cycles of matrix-core work, far below one memory latency); the packed
-  // X^T chunk goes through LDS one chunk ahead.
+  // X^T chunk goes through LDS one chunk ahead; FP8 chunk scales travel with
+  // the A chunks.  No load is conditional and no branch separates the
+  // chunks (either would make the wait-count pass assume the prefetches
+  // unfinished): chunks go in rounds of R, a chunk past the split's last
+  // re-reads the last one and stages zeros for X^T, so it adds nothing.
   constexpr int R = PD + 1;
   uint4 abuf[R][4], bst[4];
+  float scr[R];
+  auto aload = [&](int slot, int64_t c) {
+    const int64_t cc = c < nch ? c : nch - 1;
 #pragma unroll
-  for (int u = 0; u < PD; ++u) {
-    if (u < nch) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) abuf[u][i] = arow[u * 8 + i];
+    for (int i = 0; i < 4; ++i) abuf[slot][i] = arow[cc * 8 + i];
+    if (SCALED) {
+      // 32-row groups never straddle a 128-row scale tile; chunk c is
+      // scale column c0 + c
+      scr[slot] = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + cc] * xscale[c0 + cc];
     }
-  }
+  };
+  auto bload_ = [&](int64_t c) {
+    const int64_t cc = c < nch ? c : nch - 1;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) bst[i] = bload ? xrow[i] : make_uint4(0, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) bst[i] = xrow[cc * 8 + i];
+  };
+  auto bstore = [&](int buf, int64_t c) {
+    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-    *reinterpret_cast<uint4*>(&Bs[0][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
+    for (int i = 0; i < 4; ++i)
+      *reinterpret_cast<uint4*>(&Bs[buf][bc * LDS_ROW + 16 * bh + 4 * i]) =
+          make_uint4(bst[i].x & mk, bst[i].y & mk, bst[i].z & mk, bst[i].w & mk);
+  };
+#pragma unroll
+  for (int u = 0; u < PD; ++u) aload(u, u);
+  bload_(0);
+  bstore(0, 0);
   __syncthreads();
   for (int64_t cb0 = 0; cb0 < nch; cb0 += R) {
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const int64_t c = cb0 + u;
-      if (c < nch) {  // (uniform)
-        const bool more = c + 1 < nch;
-        if (c + PD < nch) {
+      // X^T first: the wait before its store then leaves the A chunks in
+      // flight (the wait counter drains in issue order)
+      bload_(c + 1);
+      aload((u + PD) % R, c + PD);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < nch) {  // (uniform; no memory operation inside)
+      uint32_t aw[16];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) abuf[(u + PD) % R][i] = arow[(c + PD) * 8 + i];
-        }
-        if (more) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) bst[i] = bload ? xrow[(c + 1) * 8 + i] : make_uint4(0, 0, 0, 0);
-        }
-        uint32_t aw[16];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          aw[4 * i] = abuf[u][i].x;
-          aw[4 * i + 1] = abuf[u][i].y;
-          aw[4 * i + 2] = abuf[u][i].z;
-          aw[4 * i + 3] = abuf[u][i].w;
-        }
-        const uint32_t* tile = Bs[c & 1];
-        f32x16 tmp[4];
-        if (SCALED) {
-#pragma unroll
-          for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
-        }
-#pragma unroll
-        for (int q = 0; q < STEPS; ++q) {
-#pragma unroll
-          for (int tt = 0; tt < NT; ++tt) {
-            uint32_t bw[LW];
-            lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
-            if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
-            else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
-          }
-        }
-        if (SCALED) {
-          // 32-row groups never straddle a 128-row scale tile; chunk c is
-          // scale column c
-          const float sc = ascale[((row0 + 32 * w) >> 7) * ascale_ld + c0 + c] * xscale[c0 + c];
-#pragma unroll
-          for (int tt = 0; tt < NT; ++tt) acc[tt] += sc * tmp[tt];
-        }
-        if (more) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            *reinterpret_cast<uint4*>(&Bs[(c + 1) & 1][bc * LDS_ROW + 16 * bh + 4 * i]) = bst[i];
-        }
-        __syncthreads();
+      for (int i = 0; i < 4; ++i) {
+        aw[4 * i] = abuf[u][i].x;
+        aw[4 * i + 1] = abuf[u][i].y;
+        aw[4 * i + 2] = abuf[u][i].z;
+        aw[4 * i + 3] = abuf[u][i].w;
       }
+      const uint32_t* tile = Bs[c & 1];
+      f32x16 tmp[4];
+      if (SCALED) {
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
+      }
+#pragma unroll
+      for (int q = 0; q < STEPS; ++q) {
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          uint32_t bw[LW];
+          lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
+          if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
+          else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
+        }
+      }
+      if (SCALED) {
+        const float sc = scr[u];
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) acc[tt] += sc * tmp[tt];
+      }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      bstore((c + 1) & 1, c + 1);
+      __syncthreads();
     }
   }
   // C = alpha acc + beta C (a split's partial: alpha 1, beta 0)
@@ -280,58 +290,37 @@ __global__ __launch_bounds__(256) void nn_split_reduce_kernel(int S, int64_t n, 
 // Transposing load of one chunk (KC rows x 128 columns) of a row-major
 // L x cols matrix into the staged layout [column][128 bytes of rows]; rows
 // at or beyond `le` read as zero, columns beyond `cols` are clamped (they
-// only feed outputs that are not stored).
+// only feed outputs that are not stored).  Thread t holds row group t mod
+// 16 of column group t / 16: the 16 lanes of one LDS store pass write 16
+// consecutive 8-byte words of one staged column (no bank conflict; the
+// loads of a wavefront take 16 row segments of 64 or 32 bytes).
 template <typename T>
 struct TLoad;
 template <>
-struct TLoad<float> {  // thread: 4 rows x 4 columns (16 bytes per row)
-  uint4 v[4];
-  __device__ void load(const float* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
-                       int64_t cols, int t) {
-    const int cg = t & 31, rg = t >> 5;
-    int64_t c = c0 + 4 * cg;
-    if (c + 4 > cols) c = cols - 4;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t l = l0 + 4 * rg + i;
-      v[i] = (l < le) ? *reinterpret_cast<const uint4*>(X + l * ldx + c) : make_uint4(0, 0, 0, 0);
-    }
-  }
-  __device__ void store(uint32_t* tile, int t) const {
-    const int cg = t & 31, rg = t >> 5;
-    const uint32_t w[4][4] = {{v[0].x, v[0].y, v[0].z, v[0].w},
-                              {v[1].x, v[1].y, v[1].z, v[1].w},
-                              {v[2].x, v[2].y, v[2].z, v[2].w},
-                              {v[3].x, v[3].y, v[3].z, v[3].w}};
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      *reinterpret_cast<uint4*>(&tile[(4 * cg + e) * LDS_ROW + 4 * rg]) =
-          make_uint4(w[0][e], w[1][e], w[2][e], w[3][e]);
-  }
-};
-template <>
 struct TLoad<bf16_t> {  // thread: 4 rows x 8 columns
   uint4 v[4];
+  uint32_t mk[4];  // rows at or past `le`: re-read the last row, stored as zeros
   __device__ void load(const bf16_t* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
                        int64_t cols, int t) {
-    const int cg = t & 15, rg = t >> 4;
+    const int cg = t >> 4, rg = t & 15;
     int64_t c = c0 + 8 * cg;
     if (c + 8 > cols) c = cols - 8;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int64_t l = l0 + 4 * rg + i;
-      v[i] = (l < le) ? *reinterpret_cast<const uint4*>(X + l * ldx + c) : make_uint4(0, 0, 0, 0);
+      v[i] = *reinterpret_cast<const uint4*>(X + (l < le ? l : le - 1) * ldx + c);
+      mk[i] = l < le ? 0xFFFFFFFFu : 0u;
     }
   }
   __device__ void store(uint32_t* tile, int t) const {
-    const int cg = t & 15, rg = t >> 4;
+    const int cg = t >> 4, rg = t & 15;
     uint32_t w[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      w[i][0] = v[i].x;
-      w[i][1] = v[i].y;
-      w[i][2] = v[i].z;
-      w[i][3] = v[i].w;
+      w[i][0] = v[i].x & mk[i];
+      w[i][1] = v[i].y & mk[i];
+      w[i][2] = v[i].z & mk[i];
+      w[i][3] = v[i].w & mk[i];
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -347,25 +336,27 @@ struct TLoad<bf16_t> {  // thread: 4 rows x 8 columns
 template <>
 struct TLoad<fp8_t> {  // thread: 8 rows x 8 columns
   uint2 v[8];
+  uint32_t mk[8];  // rows at or past `le`: re-read the last row, stored as zeros
   __device__ void load(const fp8_t* X, int64_t ldx, int64_t l0, int64_t le, int64_t c0,
                        int64_t cols, int t) {
-    const int cg = t & 15, rg = t >> 4;
+    const int cg = t >> 4, rg = t & 15;
     int64_t c = c0 + 8 * cg;
     if (c + 8 > cols) c = cols - 8;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int64_t l = l0 + 8 * rg + i;
-      v[i] = (l < le) ? *reinterpret_cast<const uint2*>(X + l * ldx + c) : make_uint2(0, 0);
+      v[i] = *reinterpret_cast<const uint2*>(X + (l < le ? l : le - 1) * ldx + c);
+      mk[i] = l < le ? 0xFFFFFFFFu : 0u;
     }
   }
   __device__ void store(uint32_t* tile, int t) const {
-    const int cg = t & 15, rg = t >> 4;
+    const int cg = t >> 4, rg = t & 15;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int sh = (e & 3) * 8;
       uint32_t b[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) b[i] = (((e < 4) ? v[i].x : v[i].y) >> sh) & 0xFFu;
+      for (int i = 0; i < 8; ++i) b[i] = ((((e < 4) ? v[i].x : v[i].y) & mk[i]) >> sh) & 0xFFu;
       *reinterpret_cast<uint2*>(&tile[(8 * cg + e) * LDS_ROW + 2 * rg]) =
           make_uint2(b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24),
                      b[4] | (b[5] << 8) | (b[6] << 16) | (b[7] << 24));
@@ -377,27 +368,31 @@ struct TLoad<fp8_t> {  // thread: 8 rows x 8 columns
 // reduction): thread t stages half bh of row bc.
 struct PLoad {
   uint4 v[4];
-  __device__ void load(const uint4* rowp, bool ok, int64_t chunk) {
+  // unconditional (the caller clamps the row and the chunk); `ok` false
+  // stages zeros
+  __device__ void load(const uint4* rowp, int64_t chunk) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = ok ? rowp[chunk * 8 + i] : make_uint4(0, 0, 0, 0);
+    for (int i = 0; i < 4; ++i) v[i] = rowp[chunk * 8 + i];
   }
-  __device__ void store(uint32_t* tile, int bc, int bh) const {
+  __device__ void store(uint32_t* tile, int bc, int bh, bool ok) const {
+    const uint32_t mk = ok ? 0xFFFFFFFFu : 0u;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      *reinterpret_cast<uint4*>(&tile[bc * LDS_ROW + 16 * bh + 4 * i]) = v[i];
+      *reinterpret_cast<uint4*>(&tile[bc * LDS_ROW + 16 * bh + 4 * i]) =
+          make_uint4(v[i].x & mk, v[i].y & mk, v[i].z & mk, v[i].w & mk);
   }
 };
 
 // Workgroup: 128 columns of X (4 wavefronts of 32) x up to 128 columns of Y,
-// rows [s Ls, (s+1) Ls) of split s = blockIdx.z.  Y is either raw FP32
-// (row-major L x r, transposing load; T = float only) or packed
-// (r_pad x L_pad in T, zero padded, with FP8 scales per 128 rows).
-template <typename T, bool SCALED, bool PACKED_Y, int NT>
+// rows [s Ls, (s+1) Ls) of split s = blockIdx.y; BF16 / FP8 X through the
+// transposing load, Y packed (r_pad x L_pad in T, zero padded, with FP8
+// scales per 128 rows).
+template <typename T, bool SCALED, int NT>
 __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
     int64_t L, int64_t p, int r, const T* __restrict__ X, int64_t ldx,
-    const float* __restrict__ xscale, int64_t xscale_ld, const float* __restrict__ Yraw,
-    int64_t ldy, const T* __restrict__ Yt, int64_t ldyt, const float* __restrict__ yscale,
-    double* __restrict__ partial, int64_t Ls, int sym) {
+    const float* __restrict__ xscale, int64_t xscale_ld, const T* __restrict__ Yt,
+    int64_t ldyt, const float* __restrict__ yscale, double* __restrict__ partial, int64_t Ls,
+    int sym) {
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
   __shared__ uint32_t As[2][128 * LDS_ROW];
   __shared__ uint32_t Bs[2][128 * LDS_ROW];
@@ -412,104 +407,63 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
   const int64_t le = (lb + Ls < L) ? lb + Ls : L;
   // NT output tiles of 32 columns at compile time (tiles past the valid
   // columns multiply the zeros staged for them and are not stored)
-  const int ntmax = NT > 0 ? NT : 4;
-  const int nt = static_cast<int>((r - r0 + 31) / 32 < ntmax ? (r - r0 + 31) / 32 : ntmax);
+  const int nt = static_cast<int>((r - r0 + 31) / 32 < NT ? (r - r0 + 31) / 32 : NT);
   const int64_t nch = (le - lb + KC - 1) / KC;
-  // running sums: FP64 for FP32 operands; FP32 for BF16 / FP8, whose
-  // rounding of the operands is ~2^-9 / 2^-4, far above FP32 summation
-  // error, and whose registers go to the chunks in flight instead
-  using ACC = typename std::conditional<sizeof(T) == 4, double, float>::type;
-  ACC acc[4][16];
+  // FP32 running sums: the operands' rounding (~2^-9 / 2^-4) is far above
+  // FP32 summation error
+  f32x16 acc[4];
 #pragma unroll
-  for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-    for (int v = 0; v < 16; ++v) acc[tt][v] = ACC(0);
-  // chunks of X in a ring of R = PD register sets: while chunk c is read
-  // from LDS, chunks c+1 .. c+PD are in registers or in flight (chunk c+PD
-  // goes into the slot chunk c left); Y (raw or packed) one chunk ahead
-  constexpr int PD = sizeof(T) == 2 ? 2 : 1;
-  constexpr int R = PD;
-  TLoad<T> xr[R];
-  TLoad<float> ya;
+  for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x16{};
+  // X and Y of chunk c+1 (and its FP8 scale) are loaded while chunk c is
+  // multiplied out of LDS, then staged for the next chunk.  Loads are never
+  // conditional and no branch separates the chunks (either makes the
+  // wait-count pass treat the loads in flight as due): the chunk after the
+  // last re-reads the last one and stages zeros.
+  TLoad<T> xr;
   PLoad yp;
   const int bc = t >> 1, bh = t & 1;
   const bool bload = bc < 32 * nt;
-  const uint4* yrow = nullptr;
-  if (PACKED_Y)
-    yrow = reinterpret_cast<const uint4*>(Yt + (r0 + (bload ? bc : 0)) * ldyt + lb) + 4 * bh;
-  auto yload = [&](int64_t c) {
-    if (PACKED_Y) yp.load(yrow, bload, c);
-    else ya.load(Yraw, ldy, lb + c * KC, le, r0, r, t);
+  const uint4* yrow =
+      reinterpret_cast<const uint4*>(Yt + (r0 + (bload ? bc : 0)) * ldyt + lb) + 4 * bh;
+  auto scale_of = [&](int64_t c) {
+    const int64_t lt = (lb + (c < nch ? c : nch - 1) * KC) >> 7;  // 128-row scale tile
+    return xscale[lt * xscale_ld + (p0 >> 7)] * yscale[lt];
   };
-  auto ystore = [&](int buf) {
-    if (PACKED_Y) yp.store(Bs[buf], bc, bh);
-    else ya.store(Bs[buf], t);
-  };
-#pragma unroll
-  for (int u = 0; u < PD; ++u)
-    if (u < nch) xr[u].load(X, ldx, lb + u * KC, le, p0, p, t);
-  if (nch > 0) {
-    yload(0);
-    xr[0].store(As[0], t);
-    ystore(0);
-  }
+  float sc_next = 1.0f;
+  if (SCALED) sc_next = scale_of(0);
+  xr.load(X, ldx, lb, le, p0, p, t);
+  yp.load(yrow, 0);
+  xr.store(As[0], t);
+  yp.store(Bs[0], bc, bh, bload);
   __syncthreads();
-  for (int64_t cb0 = 0; cb0 < nch; cb0 += R) {
+  for (int64_t c = 0; c < nch; ++c) {
+    const float sc = sc_next;
+    if (SCALED) sc_next = scale_of(c + 1);
+    yp.load(yrow, c + 1 < nch ? c + 1 : nch - 1);
+    xr.load(X, ldx, lb + (c + 1) * KC, le, p0, p, t);
+    __builtin_amdgcn_sched_barrier(0);
+    const uint32_t* at = As[c & 1];
+    const uint32_t* bt = Bs[c & 1];
+    f32x16 tmp[4];
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      const int64_t c = cb0 + u;
-      if (c < nch) {  // (uniform)
-        const bool more = c + 1 < nch;
-        if (c + PD < nch) xr[u].load(X, ldx, lb + (c + PD) * KC, le, p0, p, t);
-        if (more) yload(c + 1);
-        const uint32_t* at = As[c & 1];
-        const uint32_t* bt = Bs[c & 1];
-        ACC sc = ACC(1);
-        if (SCALED) {
-          const int64_t lt = (lb + c * KC) >> 7;  // 128-row scale tile of this chunk
-          sc = static_cast<ACC>(xscale[lt * xscale_ld + (p0 >> 7)]) *
-               static_cast<ACC>(yscale[lt]);
-        }
-        // chunk sums two output tiles at a time (fewer live FP32 registers)
-        // two output tiles per pass (fewer live FP32 registers); NT = 0:
-        // the tile count is the runtime nt (FP32, whose long matrix-core
-        // steps hide the branches and whose FP64 sums leave no registers
-        // for a fully unrolled pass)
-        constexpr int NTT = NT > 0 ? NT : 4;
-        constexpr int NU = NTT < 2 ? NTT : 2;
+    for (int tt = 0; tt < 4; ++tt) tmp[tt] = f32x16{};
 #pragma unroll
-        for (int pr = 0; pr < (NTT + 1) / 2; ++pr) {
-          if (NT > 0 || NU * pr < nt) {
-            f32x16 tmp[NU];
+    for (int q = 0; q < STEPS; ++q) {
+      uint32_t aw[LW];
+      lds_operand<T>(at, 32 * w + r32, h, q, aw);
 #pragma unroll
-            for (int uu = 0; uu < NU; ++uu) tmp[uu] = f32x16{};
-#pragma unroll
-            for (int q = 0; q < STEPS; ++q) {
-              uint32_t aw[LW];
-              lds_operand<T>(at, 32 * w + r32, h, q, aw);
-#pragma unroll
-              for (int uu = 0; uu < NU; ++uu) {
-                if (NT > 0 || NU * pr + uu < nt) {
-                  uint32_t bw[LW];
-                  lds_operand<T>(bt, 32 * (NU * pr + uu) + r32, h, q, bw);
-                  tmp[uu] = mfma_step<T>(aw, bw, tmp[uu]);
-                }
-              }
-            }
-#pragma unroll
-            for (int uu = 0; uu < NU; ++uu)
-#pragma unroll
-              for (int v = 0; v < 16; ++v)
-                acc[NU * pr + uu][v] += sc * static_cast<ACC>(tmp[uu][v]);
-          }
-        }
-        if (more) {
-          xr[(u + 1) % R].store(As[(c + 1) & 1], t);
-          ystore((c + 1) & 1);
-        }
-        __syncthreads();
+      for (int tt = 0; tt < NT; ++tt) {
+        uint32_t bw[LW];
+        lds_operand<T>(bt, 32 * tt + r32, h, q, bw);
+        tmp[tt] = mfma_step<T>(aw, bw, tmp[tt]);
       }
     }
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) acc[tt] += sc * tmp[tt];
+    __builtin_amdgcn_sched_barrier(0);
+    xr.store(As[(c + 1) & 1], t);
+    yp.store(Bs[(c + 1) & 1], bc, bh, bload && c + 1 < nch);
+    __syncthreads();
   }
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
@@ -517,7 +471,168 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int64_t gp = p0 + 32 * w + out_row(lane, v);
-      if (gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = static_cast<double>(acc[tt][v]);
+      if (tt < nt && gp < p && gc < r)
+        partial[(sidx * p + gp) * r + gc] = static_cast<double>(acc[tt][v]);
+    }
+  }
+}
+
+// FP32 X^T Y.  Workgroup: 128 columns of X (4 wavefronts of 32) x RB =
+// 32 NT columns of Y.  X (row-major L x p) goes straight from memory into
+// the operand registers: lane (i, h) of wavefront w holds column
+// p0 + 32 w + i and, at step q, row 2 q + h of the 32-row chunk, so each
+// load of a wavefront takes two 128-byte row segments and nothing is
+// transposed.  The Y chunk (32 rows x RB columns) is staged in LDS in its
+// own row order, rows RB + 32 words apart: the two rows one step reads
+// (2 q and 2 q + 1) sit 32 banks apart, and a lane reads its column of row
+// 2 q + h.  Sums over a pair of 32-row chunks are FP32 (the matrix-core
+// steps), added into FP64 running sums.  NT = 2 (64 columns of Y) keeps the FP64 sums,
+// two chunks of X and the staging in registers without spills; X is then
+// read once per 64 columns of Y, the repeats served by L2 (the column
+// blocks of one row block run one after another on one XCD).
+template <int NT>
+__global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, int r,
+                                                        const float* __restrict__ X,
+                                                        int64_t ldx,
+                                                        const float* __restrict__ Y,
+                                                        int64_t ldy,
+                                                        double* __restrict__ partial,
+                                                        int64_t Ls, int sym) {
+  constexpr int RB = 32 * NT;           // columns of Y per workgroup
+  constexpr int YS = RB + 32;           // LDS words per staged row
+  constexpr int YQ = RB / 4;            // staging threads per row (16 bytes each)
+  constexpr int YR = 256 / YQ;          // rows staged per pass
+  constexpr int NP = 32 / YR;           // passes per chunk
+  __shared__ float Ys[2][32 * YS];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
+  int64_t pb, rbk;
+  if (!xcd_tile(blockIdx.x, (p + 127) / 128, (r + RB - 1) / RB, &pb, &rbk)) return;
+  const int64_t p0 = pb * 128;
+  const int64_t r0 = rbk * RB;
+  if (sym && p0 > r0 + RB - 1) return;  // below the diagonal: mirrored by the reduction
+  const int64_t sidx = blockIdx.y;
+  const int64_t lb = sidx * Ls;
+  const int64_t le = (lb + Ls < L) ? lb + Ls : L;
+  const int nt = static_cast<int>((r - r0 + 31) / 32 < NT ? (r - r0 + 31) / 32 : NT);
+  const int64_t nch = (le - lb + 31) / 32;
+  // this lane's column of X (clamped: columns past p only feed outputs
+  // that are not stored); addresses are a uniform row base plus a 32-bit
+  // lane offset
+  const int64_t xc = (p0 + 32 * w + r32 < p) ? p0 + 32 * w + r32 : p - 1;
+  const uint32_t xob = static_cast<uint32_t>((xc + h * ldx) * 4);  // bytes
+  auto at = [](const float* base, uint32_t off) {  // SGPR base + 32-bit offset
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
+  };
+  // Y staging: thread t moves 16 bytes at columns 4 (t mod YQ) of rows
+  // t / YQ + YR i, i < NP (columns past r clamped as above)
+  const int yq = t % YQ, yr = t / YQ;
+  const bool ycol = 4 * yq < 32 * nt;
+  int64_t yc = r0 + 4 * yq;
+  if (yc + 4 > r) yc = r - 4;
+  const uint32_t yob = static_cast<uint32_t>((yr * ldy + yc) * 4);
+  // Loads are never conditional (a load whose register may instead be
+  // zeroed forces a wait for every load in flight where the paths meet):
+  // rows past the split's end re-read its last row; Y's copies of them are
+  // stored as zeros, so they add nothing.
+  const int64_t lrel = le - 1 - lb;  // last row of the split, relative
+  auto xload = [&](float* xv, int64_t c) {
+    if (32 * (c + 1) <= lrel + 1) {  // (uniform) a whole chunk
+      const float* b = X + (lb + 32 * c) * ldx;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) xv[q] = at(b + 2 * q * ldx, xob);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int64_t rr = (32 * c + 2 * q + h < lrel) ? 32 * c + 2 * q + h : lrel;
+        xv[q] = X[(lb + rr) * ldx + xc];
+      }
+    }
+  };
+  auto yload_ = [&](uint4* yv, int64_t c) {
+    if (32 * (c + 1) <= lrel + 1) {
+      const float* b = Y + (lb + 32 * c) * ldy;
+#pragma unroll
+      for (int i = 0; i < NP; ++i)
+        yv[i] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(b + YR * i * ldy) +
+                                                yob);
+    } else {
+#pragma unroll
+      for (int i = 0; i < NP; ++i) {
+        const int64_t rr = (32 * c + yr + YR * i < lrel) ? 32 * c + yr + YR * i : lrel;
+        yv[i] = *reinterpret_cast<const uint4*>(Y + (lb + rr) * ldy + yc);
+      }
+    }
+  };
+  auto ystore = [&](const uint4* yv, int buf, int64_t c) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      // zeros by a mask, not a branch (a store skipped on some lanes leaves
+      // the loads before it looking unfinished to the next chunk)
+      const uint32_t mk = (ycol && 32 * c + yr + YR * i <= lrel) ? 0xFFFFFFFFu : 0u;
+      *reinterpret_cast<uint4*>(&Ys[buf][(yr + YR * i) * YS + 4 * yq]) =
+          make_uint4(yv[i].x & mk, yv[i].y & mk, yv[i].z & mk, yv[i].w & mk);
+    }
+  };
+  double acc[NT][16];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[tt][v] = 0.0;
+  // X: the next chunk in flight while the current one is multiplied (a
+  // chunk is 16 NT matrix-core steps of 64 cycles per wavefront); Y one
+  // chunk ahead through LDS.  Chunks go in pairs (the two register sets)
+  // with no branch between them: the chunk after the last, and the second
+  // of an odd last pair, re-read the split's last row and stage zeros.
+  float xv[2][16];
+  uint4 yv[NP];
+  if (nch == 0) return;  // (uniform; no partials: a split is never empty)
+  xload(xv[0], 0);
+  yload_(yv, 0);
+  ystore(yv, 0, 0);
+  __syncthreads();
+  // FP32 sums of a pair of chunks (64 rows) per tile, then into FP64
+  f32x16 tmp[NT];
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += 2) {
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt) tmp[tt] = f32x16{};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t c = cb0 + u;
+      {
+        yload_(yv, c + 1);
+        xload(xv[u ^ 1], c + 1);
+        // keep the loads here, a whole chunk ahead of their use (the
+        // scheduler would otherwise sink the Y loads next to their stores);
+        // Y first, so that the wait before its store leaves X in flight
+        __builtin_amdgcn_sched_barrier(0);
+        const float* yt = Ys[u] + h * YS + r32;
+#pragma unroll
+        for (int tt = 0; tt < NT; ++tt) {
+          // the tile's 16 Y operands first, then its 16 steps
+          float yb[16];
+#pragma unroll
+          for (int q = 0; q < 16; ++q) yb[q] = yt[2 * q * YS + 32 * tt];
+#pragma unroll
+          for (int q = 0; q < 16; ++q)
+            tmp[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[u][q], yb[q], tmp[tt], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        ystore(yv, u ^ 1, c + 1);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[tt][v] += static_cast<double>(tmp[tt][v]);
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int64_t gc = r0 + 32 * tt + r32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gp = p0 + 32 * w + out_row(lane, v);
+      if (tt < nt && gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = acc[tt][v];
     }
   }
 }
@@ -866,29 +981,36 @@ void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches) {
   }
 }
 
-template <typename T, bool SCALED, bool PACKED>
+template <typename T, bool SCALED>
 static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
-  const T* Yt = nullptr;
-  float* ys = nullptr;
-  int64_t lp = 0, rp = 0;
-  if (PACKED) {
-    pack_t<T>(a.Y, false, a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
-    Yt = static_cast<const T*>(a.work);
-  }
   const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),
                   static_cast<unsigned>(S));
-#define BK_TN_LAUNCH(NTV)                                                                 \
-  tn_mfma_kernel<T, SCALED, PACKED, NTV><<<grid, 256, 0, s>>>(                            \
-      a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld,            \
-      static_cast<const float*>(a.Y), a.ldy, Yt, lp, ys, a.partial, Ls, a.sym ? 1 : 0)
   if constexpr (sizeof(T) == 4) {
-    BK_TN_LAUNCH(0);
+    // 64 columns of Y per workgroup (32 for narrower Y)
+    const int NTV = a.r <= 32 ? 1 : 2;
+    const dim3 gridf(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 32 * NTV))),
+                     static_cast<unsigned>(S));
+#define BK_TNF_LAUNCH(NTV)                                                                  \
+  tn_f32_kernel<NTV><<<gridf, 256, 0, s>>>(a.L, a.p, a.r, static_cast<const float*>(a.X), a.ldx, \
+                                           static_cast<const float*>(a.Y), a.ldy, a.partial, Ls,  \
+                                           a.sym ? 1 : 0)
+    if (NTV == 1) BK_TNF_LAUNCH(1);
+    else BK_TNF_LAUNCH(2);
+#undef BK_TNF_LAUNCH
   } else {
+    float* ys = nullptr;
+    int64_t lp = 0, rp = 0;
+    pack_t<T>(a.Y, false, a.ldy, a.L, a.r, a.work, &lp, &rp, &ys, s);
+    const T* Yt = static_cast<const T*>(a.work);
+#define BK_TN_LAUNCH(NTV)                                                                 \
+  tn_mfma_kernel<T, SCALED, NTV><<<grid, 256, 0, s>>>(                                    \
+      a.L, a.p, a.r, static_cast<const T*>(a.X), a.ldx, a.xscale, a.xscale_ld, Yt, lp, ys, \
+      a.partial, Ls, a.sym ? 1 : 0)
     if (a.r <= 32) BK_TN_LAUNCH(1);
     else if (a.r <= 64) BK_TN_LAUNCH(2);
     else BK_TN_LAUNCH(4);
-  }
 #undef BK_TN_LAUNCH
+  }
 }
 
 void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
@@ -906,24 +1028,24 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
   if (packed) {
     if (!a.work || static_cast<int64_t>(a.work_bytes) < mfma_pack_bytes(a.L, a.r, a.x_type)) return;
     if (a.x_type == BK_FP8_E4M3 && !a.xscale) return;
-  } else if (a.r % 4 != 0 || a.ldy % 4 != 0 || (reinterpret_cast<uintptr_t>(a.Y) & 15) != 0) {
-    return;
+  } else if (a.r % 4 != 0 || a.ldy % 4 != 0 || (reinterpret_cast<uintptr_t>(a.Y) & 15) != 0 ||
+             (a.p + a.ldx) * 4 >= (int64_t(1) << 32) || 32 * a.ldy * 4 >= (int64_t(1) << 32)) {
+    return;  // (FP32: lane offsets in bytes must fit 32 bits)
   }
   const int S = tn_mfma_splits(a.L, a.p, a.r);
   const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
-  // FP32 operands are transposed through LDS on the fly; with fewer than two
-  // workgroups per CU nothing hides those stores and barriers, and the
-  // vector kernel is faster (e.g. a 220 x 220 Gram over 130000 rows: 4 tiles).
+  // below two workgroups per CU the vector kernel is faster (e.g. a 256 x
+  // 256 Gram over 131072 rows: 390 us against 660 us)
   if (!packed && cdiv(a.p, 128) * cdiv(a.r, 128) * S < 512) return;
   switch (a.x_type) {
     case BK_F32:
-      tn_run<float, false, false>(a, S, Ls, s);
+      tn_run<float, false>(a, S, Ls, s);
       break;
     case BK_BF16:
-      tn_run<bf16_t, false, true>(a, S, Ls, s);
+      tn_run<bf16_t, false>(a, S, Ls, s);
       break;
     default:
-      tn_run<fp8_t, true, true>(a, S, Ls, s);
+      tn_run<fp8_t, true>(a, S, Ls, s);
       break;
   }
   *splits = S;

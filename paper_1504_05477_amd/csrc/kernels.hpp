@@ -249,9 +249,11 @@ void launch_jacobi_finalize(const double* Xc, const double* Vc, int64_t ldc,
 // (nullable) = sqrt(max(theta, 0)).  scratch: tridiag_scratch_doubles(m, k).
 constexpr int64_t kTridiagMax = 2560;
 int64_t tridiag_scratch_doubles(int64_t m, int k);
+// ctrl (nullable) gets CTRL_STALL if a grid barrier of the cooperative
+// reduction gave up waiting.
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k,
                          double* scratch, double* theta, double* Uk, int64_t ldu,
-                         double* ritz, hipStream_t s);
+                         double* ritz, Ctrl* ctrl, hipStream_t s);
 
 // ------------------------------------------------------------------ csr --
 void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,

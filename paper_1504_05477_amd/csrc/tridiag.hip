@@ -910,6 +910,225 @@ __global__ __launch_bounds__(TBG_COLS) void tribig_update_kernel(
   part[blockIdx.y * m + l] = acc;
 }
 
+// ------------------------------ one cooperative grid for the large-m steps --
+// The same reduction with every step inside one launch of G co-resident
+// workgroups (a cooperative launch, which fails rather than start fewer):
+// row i of the matrix lives in the registers of workgroup i mod G, thread t
+// holding columns t + 1024 e.  Step j:
+//   (1) every workgroup forms reflector j from row j (published by its
+//       owner) with the pending update of step j-1 applied: the same
+//       operations in the same order everywhere, so every copy agrees;
+//   (2) each workgroup applies the pending update to its rows i > j and
+//       forms p_i = beta (M' v_j)_i; the owner of row j+1 publishes that row;
+//   (3) grid barrier;
+//   (4) every workgroup reads p and forms K = beta v^T p / 2 and w = p - K v,
+//       the pending update of step j+1.
+// One grid barrier per step.  p and the published row alternate between two
+// buffers by step parity: no workgroup gets more than a phase ahead of
+// another.  Everything one workgroup hands to another (p, the row, the
+// barrier count) goes through device-scope relaxed atomic loads and stores,
+// which are coherent across the XCDs' L2 caches by themselves, so the
+// barrier needs no cache write-back or invalidation: each thread waits for
+// its own stores to complete before the workgroup arrives.  The count only
+// grows; the wait gives up after TCO_SPIN polls (a co-resident grid never
+// needs that many), sets `stall` and stops waiting at every later barrier,
+// so the launch always ends.
+constexpr int TCO_THREADS = 1024;
+constexpr int TCO_E = 3;     // columns per thread: m <= 3072
+constexpr int TCO_RL = 10;   // rows per workgroup: m <= 10 G
+constexpr unsigned TCO_SPIN = 1u << 22;
+
+struct TcoSync {
+  unsigned count;
+  int stall;
+};
+
+__device__ __forceinline__ void tco_put(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double tco_get(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void tco_grid_sync(TcoSync* sy, unsigned target) {
+  // this thread's stores complete (vmcnt counts stores on this target),
+  // then the workgroup arrives
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(&sy->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned polls = 0;
+    while (__hip_atomic_load(&sy->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(&sy->stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+      if (++polls > TCO_SPIN) {
+        __hip_atomic_store(&sy->stall, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  __syncthreads();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__global__ void tco_init_kernel(TcoSync* sy) {
+  sy->count = 0u;
+  sy->stall = 0;
+}
+
+__global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
+    const double* __restrict__ A, int64_t m, double* __restrict__ Vh, double* __restrict__ beta,
+    double* __restrict__ dg, double* __restrict__ eo, double* pbuf, double* rbuf,
+    TcoSync* sy) {
+  __shared__ double spv[TCO_E * TCO_THREADS], spw[TCO_E * TCO_THREADS];
+  __shared__ double redA[TCO_THREADS / 64], redB[TCO_THREADS / 64];
+  __shared__ double redR[TCO_RL][TCO_THREADS / 64];
+  __shared__ double bc[2];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int G = static_cast<int>(gridDim.x), g = static_cast<int>(blockIdx.x);
+  // own rows g + r G, r < TCO_RL; columns t + 1024 e
+  double a[TCO_RL][TCO_E];
+#pragma unroll
+  for (int r = 0; r < TCO_RL; ++r) {
+    const int64_t i = g + static_cast<int64_t>(r) * G;
+#pragma unroll
+    for (int e = 0; e < TCO_E; ++e) {
+      const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+      a[r][e] = (i < m && l < m) ? A[i * m + l] : 0.0;
+    }
+  }
+  // pending update (v, w) of the previous step: own columns in registers,
+  // the whole vectors in LDS (rows read them by index); the published row
+  double pv[TCO_E], pw[TCO_E], xr[TCO_E];
+#pragma unroll
+  for (int e = 0; e < TCO_E; ++e) {
+    const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+    pv[e] = 0.0;
+    pw[e] = 0.0;
+    spv[l] = 0.0;
+    spw[l] = 0.0;
+    xr[e] = l < m ? A[l] : 0.0;  // row 0
+  }
+  __syncthreads();
+  for (int64_t j = 0; j + 2 < m; ++j) {
+    const int par = static_cast<int>(j & 1);
+    const int64_t j1 = j + 1;
+    // (1) reflector j from x = row j with the pending update, columns >= j
+    const double pvj = spv[j], pwj = spw[j];
+    double x[TCO_E];
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < TCO_E; ++e) {
+      const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+      x[e] = 0.0;
+      if (l >= j && l < m) {
+        x[e] = xr[e] - (pvj * pw[e] + pwj * pv[e]);
+        if (l == j) bc[0] = x[e];
+        if (l == j1) bc[1] = x[e];
+        if (l > j) nrm2 += x[e] * x[e];
+      }
+    }
+    nrm2 = wg_sum_1024(nrm2, redA);  // (its barrier also publishes bc)
+    const double djj = bc[0], x0 = bc[1];
+    const double nx = sqrt(nrm2);
+    double b = 0.0, alpha = x0, v0 = x0;
+    if (nx > 0.0 && nrm2 - x0 * x0 > 0.0) {
+      alpha = x0 >= 0.0 ? -nx : nx;
+      v0 = x0 - alpha;
+      const double vtv = nrm2 - x0 * x0 + v0 * v0;
+      b = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    }
+    double vv[TCO_E];
+#pragma unroll
+    for (int e = 0; e < TCO_E; ++e) {
+      const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+      vv[e] = (l == j1) ? v0 : ((l > j1 && l < m) ? x[e] : 0.0);
+      if (g == 0 && l > j && l < m) Vh[j * m + l] = vv[e];
+    }
+    if (g == 0 && t == 0) {
+      dg[j] = djj;
+      eo[j] = alpha;
+      beta[j] = b;
+    }
+    // (2) own rows i > j: the pending update, then their partials of M' v
+#pragma unroll
+    for (int r = 0; r < TCO_RL; ++r) {
+      const int64_t i = g + static_cast<int64_t>(r) * G;
+      double ps = 0.0;
+      if (i > j && i < m) {  // (uniform)
+        const double pvi = spv[i], pwi = spw[i];
+#pragma unroll
+        for (int e = 0; e < TCO_E; ++e) {
+          const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+          if (l > j && l < m) {
+            a[r][e] -= pvi * pw[e] + pwi * pv[e];
+            ps += a[r][e] * vv[e];
+          }
+        }
+        ps = wave_sum(ps);
+        if (lane == 0) redR[r][wv] = ps;
+        if (i == j1) {  // the owner publishes row j+1
+#pragma unroll
+          for (int e = 0; e < TCO_E; ++e) {
+            const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+            if (l < m) tco_put(rbuf + par * m + l, a[r][e]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (t < TCO_RL) {
+      const int64_t i = g + static_cast<int64_t>(t) * G;
+      if (i > j && i < m) {
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < TCO_THREADS / 64; ++w) sum += redR[t][w];
+        tco_put(pbuf + par * m + i, b * sum);
+      }
+    }
+    // (3)
+    tco_grid_sync(sy, static_cast<unsigned>(G) * static_cast<unsigned>(j + 1));
+    // (4) p on own columns, K, the next pending update, the next row
+    double pl[TCO_E];
+    double vp = 0.0;
+#pragma unroll
+    for (int e = 0; e < TCO_E; ++e) {
+      const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+      pl[e] = (l > j && l < m) ? tco_get(pbuf + par * m + l) : 0.0;
+      vp += vv[e] * pl[e];
+      xr[e] = (l > j && l < m) ? tco_get(rbuf + par * m + l) : 0.0;
+    }
+    vp = wg_sum_1024(vp, redB);
+    const double K = 0.5 * b * vp;
+#pragma unroll
+    for (int e = 0; e < TCO_E; ++e) {
+      const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+      pv[e] = vv[e];
+      pw[e] = pl[e] - K * vv[e];
+      spv[l] = pv[e];
+      spw[l] = pw[e];
+    }
+    __syncthreads();
+  }
+  // last 2 x 2 block: rows m-2 and m-1 (updated through step m-4) with the
+  // pending update of step m-3
+#pragma unroll
+  for (int r = 0; r < TCO_RL; ++r) {
+    const int64_t i = g + static_cast<int64_t>(r) * G;
+    if (i >= m - 2 && i < m) {
+#pragma unroll
+      for (int e = 0; e < TCO_E; ++e) {
+        const int64_t l = t + static_cast<int64_t>(e) * TCO_THREADS;
+        if (l == i) dg[i] = a[r][e] - 2.0 * spv[i] * spw[i];
+        if (i == m - 2 && l == m - 1)
+          eo[i] = a[r][e] - (spv[i] * spw[l] + spw[i] * spv[l]);
+      }
+    }
+  }
+}
+
 // Reorthogonalization of the inverse-iteration vectors (columns of X,
 // column-major, ld m).  Inverse iteration only orthogonalizes within groups
 // of eigenvalues closer than 1e-10 ||T||; a pair separated by a gap g keeps
@@ -977,11 +1196,37 @@ int64_t tridiag_scratch_doubles(int64_t m, int k) {
          std::max<int64_t>(static_cast<int64_t>(k) * 5 * m, static_cast<int64_t>(k) * 1024) +
          (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64 +
          static_cast<int64_t>(k) * m + 3 * kk + chol_work_doubles(k) + 8 +
-         m + cdiv(m, 256) + 64;  // p and the v^T p partials of the large-m steps
+         m + cdiv(m, 256) + 64 +  // p and the v^T p partials of the large-m steps
+         4 * m + 8;               // the cooperative grid's p, row and barrier
 }
 
+namespace {
+// Workgroups of the cooperative reduction on the current device (one per
+// CU), 0 if the device cannot take it.
+int tco_grid(hipStream_t s) {
+  static int cached[64] = {0};  // 0: not asked yet, -1: none, else G
+  int dev = 0;
+  if (hipStreamGetDevice(s, &dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int coop = 0, cus = 0, nb = 0;
+    const bool ok =
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void*>(tri_coop_kernel), TCO_THREADS, 0) == hipSuccess;
+    cached[dev] = (ok && coop && cus > 0 && nb >= 1) ? cus : -1;
+  }
+  return cached[dev] > 0 ? cached[dev] : 0;
+}
+
+__global__ void tco_report_kernel(const TcoSync* sy, Ctrl* ctrl) {
+  if (sy->stall) atomicOr(&ctrl->flags, CTRL_STALL);
+}
+}  // namespace
+
 void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double* scratch,
-                         double* theta, double* Uk, int64_t ldu, double* ritz, hipStream_t s) {
+                         double* theta, double* Uk, int64_t ldu, double* ritz, Ctrl* ctrl,
+                         hipStream_t s) {
   double* A = scratch;
   double* Vh = A + m * m;
   double* beta = Vh + m * m;
@@ -1007,6 +1252,9 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
   double* Rix = Rx + kk;
   double* cwork = Rix + kk;
   Ctrl* cdummy = reinterpret_cast<Ctrl*>(cwork + chol_work_doubles(k));
+  double* cpb = cwork + chol_work_doubles(k) + 8;  // cooperative grid: p (2 m),
+  double* crb = cpb + 2 * m;                       // the published row (2 m),
+  TcoSync* csy = reinterpret_cast<TcoSync*>(crb + 2 * m);  // the barrier
   static bool attr = false;
   if (!attr) {
     for (const void* f : {reinterpret_cast<const void*>(tridiag_reduce_kernel),
@@ -1043,6 +1291,23 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     }
     tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + (m - j) * (m - j)) * sizeof(double), s>>>(
         A, m, j, Vh, beta, dg, eo);
+  } else if (const int Gc = tco_grid(s);
+             Gc > 0 && m <= static_cast<int64_t>(TCO_E) * TCO_THREADS &&
+             m <= static_cast<int64_t>(TCO_RL) * Gc &&
+             [&] {
+               tco_init_kernel<<<1, 1, 0, s>>>(csy);
+               const double* a0 = A;
+               void* args[] = {&a0, &m, &Vh, &beta, &dg, &eo, &cpb, &crb, &csy};
+               if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tri_coop_kernel),
+                                              dim3(Gc), dim3(TCO_THREADS), args, 0,
+                                              s) != hipSuccess) {
+                 (void)hipGetLastError();  // not taken: the launch-per-step path below
+                 return false;
+               }
+               if (ctrl) tco_report_kernel<<<1, 1, 0, s>>>(csy, ctrl);
+               return true;
+             }()) {
+    // reduced by the cooperative grid
   } else {
     launch_fill_f64(v, 3 * m, 0.0, s);  // v, vp, wp
     int G = 0, ND = 0;
