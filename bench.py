@@ -44,6 +44,16 @@ METRIC = ("Krylov A·X/Aᵀ·Y GB/s or TFLOP/s & time-to-ε "
           "(BF16/FP8 vs FP32), 1 GPU")
 HBM_PEAK_GBS = 8000.0
 PEAK_TFS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "fp8": 5000.0}
+# FP32 products as three BF16 limbs: six BF16 matrix-core products per FP32
+# product, so the FP32-equivalent peak is the dense BF16 peak over six
+LIMB_PEAK_TFS = PEAK_TFS["bf16"] / 6.0
+
+
+def f32_peak(args):
+    """(peak TFLOP/s, basis) of the FP32 products in this run."""
+    if getattr(args, "fp32_products", "limbs") == "limbs":
+        return LIMB_PEAK_TFS, "dense BF16 2.5 PFLOP/s / 6 limb products"
+    return PEAK_TFS["f32"], "FP32 matrix cores 157.3 TFLOP/s"
 DESCR = {
     "csr2": "term-document CSR 11000x130000 (~1.47M nnz, log-normal rows, Zipf(1.1) "
             "terms, log(1+tf)*idf), k=20, q=10, implicit row centring",
@@ -109,13 +119,13 @@ def read_traffic(kernel_key, sha):
         return None
 
 
-def value_unit(kind, dtype, n, d, pw, a_bytes):
+def value_unit(kind, dtype, n, d, pw, a_bytes, peak=None):
     """TFLOP/s for FP32 / FP64 dense products above the ridge of their
     matrix-core peak (flops per byte), GB/s otherwise."""
     if kind != "dense" or dtype not in ("f32", "f64"):
         return "GB/s"
     ai = 2.0 * n * d * pw / (n * d * a_bytes)
-    ridge = PEAK_TFS[dtype] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    ridge = (peak or PEAK_TFS[dtype]) * 1e12 / (HBM_PEAK_GBS * 1e9)
     return "TFLOP/s" if ai > ridge else "GB/s"
 
 
@@ -187,6 +197,12 @@ def main():
     ap.add_argument("--no-parity", action="store_true",
                     help="skip the comparison with the float64 oracle")
     ap.add_argument("--breakdown", action="store_true", help="phase times to stderr")
+    ap.add_argument("--fp32-products", default="limbs", choices=["limbs", "cores"],
+                    help="FP32 block products as three BF16 limbs on the BF16 matrix cores "
+                         "(limbs) or on the FP32 matrix cores (cores)")
+    ap.add_argument("--lowp-layout", default="both", choices=["both", "rows"],
+                    help="low-precision leg: also hold the copy transposed, so that the "
+                         "A^T Y products read it row by row (both), or A only (rows)")
     ap.add_argument("--input", default="planted", choices=["planted", "gaussian"],
                     help="dense workloads: the planted matrix of the workload, or a seeded "
                          "N(0, 1/d) matrix of the same shape built without factorizations "
@@ -235,7 +251,8 @@ def main():
 def base_record(args, w, value, unit, ms, dtype, extra_config):
     cfg = {"workload": f"{args.workload}: {DESCR[args.workload]}",
            "n": w.n, "d": w.d, "k": w.k, "q": w.q, "precision": args.precision,
-           "method": args.method, "block_size": args.block_size or w.k}
+           "method": args.method, "block_size": args.block_size or w.k,
+           "fp32_products": getattr(args, "fp32_products", "limbs")}
     cfg.update(extra_config)
     return {
         "metric": METRIC,
@@ -373,9 +390,13 @@ def run_dense(args, w, bk, torch):
         t0p = time.perf_counter()
         if prec == "bf16":
             A_in, kw, a_bytes = bk.quantize(A, "bf16"), {"A_master": A}, 2
+            if args.lowp_layout == "both":
+                kw["A_t"] = bk.quantize(A, "bf16", transposed=True)
         else:
             A_in, sc = bk.quantize(A, "fp8")
             kw, a_bytes = {"A_master": A, "a_scales": sc}, 1
+            if args.lowp_layout == "both":
+                kw["A_t"], kw["at_scales"] = bk.quantize(A, "fp8", transposed=True)
         torch.cuda.synchronize()
         prep_ms[f"quantize_{prec}"] = round((time.perf_counter() - t0p) * 1e3, 4)
         return A_in, kw, a_bytes
@@ -393,7 +414,8 @@ def run_dense(args, w, bk, torch):
     def stepper(Ai, kwi):
         def step(timing):
             return bk.svd_dense(Ai, k, q, seed=w.seed_sketch, timing=timing,
-                                method=args.method, block_size=args.block_size, **kwi)
+                                method=args.method, block_size=args.block_size,
+                                fp32_products=args.fp32_products, **kwi)
         return step
 
     flops_per_product = 2.0 * w.n * w.d * pw
@@ -432,7 +454,8 @@ def run_dense(args, w, bk, torch):
         log(f"{compare} leg: {lp['ms']:.2f} ms/solve")
         s2 = leg_summary(lp, compare, ablp)
         out["low_precision"] = {
-            "precision": compare, "refine": True, "ms_per_step": round(lp["ms"], 4),
+            "precision": compare, "refine": True, "layout": args.lowp_layout,
+            "ms_per_step": round(lp["ms"], 4),
             "speedup_vs_plain": round(leg["ms"] / lp["ms"], 3),
             "products_GBps": round(s2["GBps"], 2), "products_TFLOPs": round(s2["TFLOPs"], 2),
             "roofline": dense_roofline(lp, args, w, compare, ablp, x_bytes, pw),
@@ -502,12 +525,14 @@ def dense_roofline(leg, args, w, dtype, a_bytes, x_bytes, pw):
             "event_steps": leg["n_ev"], "algorithmic_bytes_per_launch": int(per_launch),
             "source_sha": sha}
     flops = 2.0 * w.n * w.d * pw
-    peak = PEAK_TFS[dtype]
+    peak, basis = f32_peak(args) if dtype == "f32" else (PEAK_TFS[dtype], None)
     if flops / per_launch > peak * 1e12 / (HBM_PEAK_GBS * 1e9):
         tf = flops / (avg_ms * 1e-3) / 1e12
-        roof.update({"bound": "mfma", "achieved": round(tf, 3), "peak": peak,
+        roof.update({"bound": "mfma", "achieved": round(tf, 3), "peak": round(peak, 2),
                      "unit": "TFLOP/s", "frac": round(tf / peak, 4),
                      "algorithmic_flops_per_launch": flops})
+        if basis:
+            roof["peak_basis"] = basis
     return roof
 
 

@@ -132,6 +132,28 @@ typedef struct bk_options {
                                 (Bauer-Fike), so some singular value s of
                                 A has |sigma_i - s| <= r_i / sigma_i.  CSR
                                 path: needs block_size = k.             */
+  const void* a_transposed;  /* nullable DEVICE matrix: A^T (d x n, ld
+                                ld_at) in a_type, BK_BF16 or BK_FP8_E4M3
+                                only (bk_quantize_dense_transposed makes
+                                it), with at_scales (FP8: the transpose of
+                                a_scales, ceil(d/128) x ceil(n/128)).  When
+                                given, the A^T Y products (Algorithm 2,
+                                step 3) read it row by row, as the A X
+                                products read A, instead of A column-wise:
+                                the same products, 2 n d bytes of HBM held
+                                instead of n d.  Ignored for BK_F32 /
+                                BK_F64 and the CSR path.                  */
+  int64_t ld_at;             /* leading dimension of a_transposed (>= n)  */
+  const float* at_scales;    /* FP8 tile scales of a_transposed (DEVICE)  */
+  int32_t fp32_products;     /* FP32 block products on the matrix cores:
+                                0 (default): each FP32 operand as three
+                                BF16 limbs (a = a1 + a2 + a3 exactly), the
+                                six leading limb products on the BF16
+                                matrix cores, FP32 sums (error within
+                                2^-23 |a b| per product beyond FP32
+                                summation); 1: on the FP32 matrix cores
+                                (32 x 32 x 2 steps).                     */
+  int32_t reserved2;
 } bk_options;
 
 enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1, BK_METHOD_BLOCK_LANCZOS = 2 };
@@ -350,6 +372,14 @@ int bk_philox4x32_10(const uint32_t* in, int64_t count, uint32_t* out,
  * in OCP e4m3, tile_scales[ceil(n/128) x ceil(d/128)] = s. */
 int bk_quantize_dense(const float* A, int64_t n, int64_t d, int64_t lda,
                       int32_t to, void* out, float* tile_scales, void* stream);
+
+/* The same copy stored transposed: out_t (d x n, ld = n) holds at (c, r) the
+ * code bk_quantize_dense gives A[r][c]; FP8 tile_scales_t[ceil(d/128) x
+ * ceil(n/128)] is the transpose of its tile scales.  For
+ * bk_options.a_transposed. */
+int bk_quantize_dense_transposed(const float* A, int64_t n, int64_t d, int64_t lda,
+                                 int32_t to, void* out_t, float* tile_scales_t,
+                                 void* stream);
 
 /* The block products on their own (the Krylov loop's A.X and A^T.Y,
  * Algorithm 2, steps 2-3):

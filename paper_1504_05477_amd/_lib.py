@@ -32,6 +32,11 @@ class Options(C.Structure):
         ("timing_phases", C.c_int32),
         ("reserved", C.c_int32 * 2),
         ("residuals", C.c_void_p),
+        ("a_transposed", C.c_void_p),
+        ("ld_at", C.c_int64),
+        ("at_scales", C.c_void_p),
+        ("fp32_products", C.c_int32),
+        ("reserved2", C.c_int32),
     ]
 
 
@@ -104,6 +109,7 @@ _SIGS = [
     ("bk_gaussian", C.c_int, [_U64, _I64, _I64, _I64, _I32, _P, _P]),
     ("bk_philox4x32_10", C.c_int, [_P, _I64, _P, _P]),
     ("bk_quantize_dense", C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P, _P]),
+    ("bk_quantize_dense_transposed", C.c_int, [_P, _I64, _I64, _I64, _I32, _P, _P, _P]),
     ("bk_dense_product_workspace", _SZ, [_I32, _I64, _I64, _I32, _I32]),
     ("bk_dense_product", C.c_int, [_I32, _P, _I64, _I32, _P, _I64, _I64, _P, _I64, _I32, _P,
                                    _I64, _P, _SZ, _P]),

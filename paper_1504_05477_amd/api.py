@@ -48,7 +48,8 @@ _METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1, "lanczos": 
 
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
              breakdown_tol=0.0, pi=None, timing=False, save=False,
-             jacobi_block=0, block_size=0, method="bki", residuals=None) -> L.Options:
+             jacobi_block=0, block_size=0, method="bki", residuals=None,
+             A_t=None, at_scales=None, fp32_products="limbs") -> L.Options:
     """timing: False, True (every phase) or an iterable of phase names from
     _lib.PHASES (only those get events; launch counts are kept for all)."""
     o = L.Options()
@@ -76,6 +77,12 @@ def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
         raise ValueError(f"method must be one of {sorted(_METHODS)}")
     o.method = _METHODS[method]
     o.residuals = _ptr(residuals)
+    o.a_transposed = _ptr(A_t)
+    o.ld_at = 0 if A_t is None else A_t.stride(0)
+    o.at_scales = _ptr(at_scales)
+    if fp32_products not in ("limbs", "cores"):
+        raise ValueError("fp32_products must be 'limbs' or 'cores'")
+    o.fp32_products = 1 if fp32_products == "cores" else 0
     return o
 
 
@@ -92,7 +99,8 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
               A_master=None, refine: int = 0, pi=None, timing=False,
               save_for_backward=False, max_sweeps=0, jacobi_tol=0.0,
               breakdown_tol=0.0, jacobi_block=0, block_size=0, method="bki",
-              residuals=False, stream=None) -> SVDResult:
+              residuals=False, A_t=None, at_scales=None, fp32_products="limbs",
+              stream=None) -> SVDResult:
     """Block Krylov Iteration on a dense A (n x d row-major on the GPU).
 
     A's dtype selects the path: float64 / float32 (plain), bfloat16, or uint8
@@ -101,13 +109,22 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
     ``block_size`` = p >= k oversamples the sketch (0: p = k);
     ``method`` = "si" runs Simultaneous Iteration instead.
     ``residuals`` also returns ||A A^T z_i - sigma_i^2 z_i|| per Ritz pair
-    (A: the FP32 master after the correction pass)."""
+    (A: the FP32 master after the correction pass).
+    ``A_t`` (with ``at_scales`` for FP8): the BF16 / FP8 copy stored
+    transposed (``quantize(..., transposed=True)``); the A^T Y products then
+    read it row by row.  ``fp32_products``: "limbs" (FP32 operands as three
+    BF16 limbs on the BF16 matrix cores) or "cores" (the FP32 matrix
+    cores)."""
     lib = L.load()
-    _need_cuda(A, a_scales, A_master, pi)
+    _need_cuda(A, a_scales, A_master, pi, A_t, at_scales)
     if A.dim() != 2 or A.stride(1) != 1:
         raise ValueError("A must be a 2-D row-major tensor")
     n, d = A.shape
     code = _dtype_code(A)
+    if A_t is not None:
+        if (tuple(A_t.shape) != (d, n) or A_t.stride(1) != 1
+                or A_t.element_size() != A.element_size()):
+            raise ValueError("A_t must be the row-major d x n transposed copy in A's dtype")
     if code == L.FP8_E4M3 and A.dtype != torch.uint8:
         A = A.view(torch.uint8)
     zdt = torch.float64 if code == L.F64 else torch.float32
@@ -119,7 +136,8 @@ def svd_dense(A: torch.Tensor, k: int, q: int, seed: int = 0, *, a_scales=None,
     opt = _options(refine=refine, pi=pi, timing=timing, save=save_for_backward,
                    max_sweeps=max_sweeps, jacobi_tol=jacobi_tol,
                    breakdown_tol=breakdown_tol, jacobi_block=jacobi_block,
-                   block_size=block_size, method=method, residuals=res_t)
+                   block_size=block_size, method=method, residuals=res_t,
+                   A_t=A_t, at_scales=at_scales, fp32_products=fp32_products)
     nbytes = lib.bk_svd_dense_workspace(n, d, k, q, code, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")
@@ -336,25 +354,29 @@ def philox(ctr_key: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
-def quantize(A: torch.Tensor, to: str, stream=None):
+def quantize(A: torch.Tensor, to: str, stream=None, transposed: bool = False):
     """A float32 (n x d) -> ("bf16": bfloat16 copy) or ("fp8": (uint8 e4m3
-    codes, float32 tile scales ceil(n/128) x ceil(d/128)))."""
+    codes, float32 tile scales ceil(n/128) x ceil(d/128))).  ``transposed``
+    returns the same codes stored as A^T (d x n; FP8 scales ceil(d/128) x
+    ceil(n/128)), for ``svd_dense(..., A_t=...)``."""
     lib = L.load()
     _need_cuda(A)
     if A.dtype != torch.float32 or A.stride(1) != 1:
         raise ValueError("A must be a row-major float32 tensor")
     n, d = A.shape
+    fn = lib.bk_quantize_dense_transposed if transposed else lib.bk_quantize_dense
+    name = "bk_quantize_dense_transposed" if transposed else "bk_quantize_dense"
+    rows, cols = (d, n) if transposed else (n, d)
     if to == "bf16":
-        out = torch.empty(n, d, dtype=torch.bfloat16, device=A.device)
-        L.check(lib.bk_quantize_dense(_ptr(A), n, d, A.stride(0), L.BF16, _ptr(out), None,
-                                      _stream(stream)), "bk_quantize_dense")
+        out = torch.empty(rows, cols, dtype=torch.bfloat16, device=A.device)
+        L.check(fn(_ptr(A), n, d, A.stride(0), L.BF16, _ptr(out), None, _stream(stream)), name)
         return out
     if to == "fp8":
-        out = torch.empty(n, d, dtype=torch.uint8, device=A.device)
-        sc = torch.empty((n + 127) // 128, (d + 127) // 128, dtype=torch.float32,
+        out = torch.empty(rows, cols, dtype=torch.uint8, device=A.device)
+        sc = torch.empty((rows + 127) // 128, (cols + 127) // 128, dtype=torch.float32,
                          device=A.device)
-        L.check(lib.bk_quantize_dense(_ptr(A), n, d, A.stride(0), L.FP8_E4M3, _ptr(out),
-                                      _ptr(sc), _stream(stream)), "bk_quantize_dense")
+        L.check(fn(_ptr(A), n, d, A.stride(0), L.FP8_E4M3, _ptr(out), _ptr(sc),
+                   _stream(stream)), name)
         return out, sc
     raise ValueError("to must be 'bf16' or 'fp8'")
 

@@ -55,6 +55,10 @@ struct Options {
   double jtol = 0.0, tau = 0.0;
   const void* pi = nullptr;
   double* resid = nullptr;  // device k: residual norms of the Ritz pairs
+  const void* at = nullptr;  // transposed low-precision copy of A (nullable)
+  int64_t ld_at = 0;
+  const float* at_scales = nullptr;
+  bool fp32_cores = false;   // FP32 products on the FP32 matrix cores
 };
 
 Options read_options(const bk_options* o, bool f64) {
@@ -76,6 +80,13 @@ Options read_options(const bk_options* o, bool f64) {
       r.timing_phases = o->timing_phases;
     if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, residuals) + sizeof(double*)))
       r.resid = o->residuals;
+    if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, at_scales) + sizeof(float*))) {
+      r.at = o->a_transposed;
+      r.ld_at = o->ld_at;
+      r.at_scales = o->at_scales;
+    }
+    if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, fp32_products) + sizeof(int32_t)))
+      r.fp32_cores = o->fp32_products == 1;
   }
   if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
   return r;
@@ -209,6 +220,11 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
     // X^T of A X in FP32 (the widest type), Y^T of A^T Y in BF16 / FP8
     int64_t nn = 0;  // A X on the matrix cores: packed X^T (+ split partials)
     for (int t : {BK_F32, BK_BF16, BK_FP8_E4M3}) nn = std::max(nn, mfma_nn_work_bytes(n, d, k, t));
+    // A^T Y on a transposed BF16 / FP8 copy: packed Y^T (+ split partials)
+    for (int t : {BK_BF16, BK_FP8_E4M3}) nn = std::max(nn, mfma_nn_work_bytes(d, n, k, t));
+    // FP32 X^T Y through BF16 limbs: Y's limb planes (A^T Y: n rows; the
+    // Grams: n or d rows)
+    nn = std::max(nn, x3_pack_bytes(std::max(n, d), k));
     L.pack_bytes = static_cast<size_t>(std::max(nn, mfma_pack_bytes(n, k, BK_BF16)));
     L.pack = ar.take<char>(L.pack_bytes);
   }
@@ -347,6 +363,7 @@ struct Timer {
 struct Op {
   int64_t n = 0, d = 0;
   bool f64 = false;
+  bool fp32_cores = false;  // FP32 products on the FP32 matrix cores
   double* partial = nullptr;
   int64_t partial_elems = 0;  // (free during ax: split-K scratch)
   Timer* tm = nullptr;
@@ -373,6 +390,9 @@ struct DenseOp : Op {
   int64_t lda = 0;
   int a_type = BK_F32;
   const float* ascale = nullptr;
+  const void* At = nullptr;  // A^T (d x n) in a_type, for the A^T Y products
+  int64_t ld_at = 0;
+  const float* atscale = nullptr;
   void* pack = nullptr;  // matrix-core operand packing (nullable)
   size_t pack_bytes = 0;
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
@@ -396,10 +416,34 @@ struct DenseOp : Op {
     a.work_bytes = pack_bytes;
     a.split_work = partial;
     a.split_work_elems = partial_elems;
+    a.fp32_cores = fp32_cores;
     tm->end(launch_nn(a, s));
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
     tm->begin(BK_PH_ATY);
+    if (At) {  // A^T Y as an A X-form product on the transposed copy
+      NNArgs a;
+      a.n = d;
+      a.K = n;
+      a.N = k;
+      a.A = At;
+      a.lda = ld_at;
+      a.a_type = a_type;
+      a.ascale = atscale;
+      a.ascale_ld = cdiv(n, 128);
+      a.X = X;
+      a.ldx = ldx;
+      a.x_f64 = f64;
+      a.C = Y;
+      a.ldc = ldy;
+      a.c_f64 = f64;
+      a.work = pack;
+      a.work_bytes = pack_bytes;
+      a.split_work = partial;
+      a.split_work_elems = partial_elems;
+      tm->end(launch_nn(a, s));
+      return;
+    }
     TNArgs a;
     a.L = n;
     a.p = d;
@@ -418,6 +462,7 @@ struct DenseOp : Op {
     a.partial = partial;
     a.work = pack;
     a.work_bytes = pack_bytes;
+    a.fp32_cores = fp32_cores;
     tm->end(launch_tn(a, s));
   }
 };
@@ -603,6 +648,9 @@ struct Solver {
     a.beta = beta;
     a.partial = L->partial;
     a.sym = sym && X == Y && ldx == ldy && p == r;
+    a.work = L->pack;
+    a.work_bytes = L->pack_bytes;
+    a.fp32_cores = o.fp32_cores;
     return launch_tn(a, s);
   }
   // C (rows x N, ldc) = alpha A (rows x K, lda) Xf (K x N FP64, ldx) + beta C
@@ -629,6 +677,7 @@ struct Solver {
       a.work = L->pack;
       a.work_bytes = L->pack_bytes;
     }
+    a.fp32_cores = o.fp32_cores;
     return launch_nn(a, s);
   }
   // k <= 32: the applies of the orthonormalization also leave the partial
@@ -926,6 +975,9 @@ int solve(Op& op, Layout& L, const Options& o, int k, int q, uint64_t seed,
     g.ldc = k;
     g.c_f64 = true;
     g.partial = L.partial;
+    g.work = L.pack;
+    g.work_bytes = L.pack_bytes;
+    g.fp32_cores = o.fp32_cores;
     launch_tn(g, s);
     tm.end(4);
     st = S.eig(L.Gk, k, L.jk, k, L.Pk, k, L.ritz_dev, L.trik);
@@ -1534,6 +1586,9 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
   normalize_refine(o, a_type, A_master != nullptr);
   if (o.refine && (!A_master || ld_master < d)) return BK_EINVAL;
   if (o.center) return BK_EINVAL;  // dense centring is not offered
+  if (o.at && (a_type == BK_BF16 || a_type == BK_FP8_E4M3) &&
+      (o.ld_at < n || (a_type == BK_FP8_E4M3 && !o.at_scales)))
+    return BK_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t need = make_layout(nullptr, n, d, 0, pw, q, f64, o, false, false).bytes;
   DevBuf own;
@@ -1554,6 +1609,12 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
   op.lda = lda;
   op.a_type = a_type;
   op.ascale = a_type == BK_FP8_E4M3 ? a_scales : nullptr;
+  op.fp32_cores = o.fp32_cores;
+  if (o.at && (a_type == BK_BF16 || a_type == BK_FP8_E4M3)) {
+    op.At = o.at;
+    op.ld_at = o.ld_at;
+    op.atscale = a_type == BK_FP8_E4M3 ? o.at_scales : nullptr;
+  }
   DenseOp master;
   const DenseOp* mp = nullptr;
   if (o.refine) {
@@ -1563,6 +1624,7 @@ int bk_svd_dense(const void* A, int64_t lda, int32_t a_type, const float* a_scal
     master.A = A_master;
     master.lda = ld_master;
     master.a_type = BK_F32;
+    master.fp32_cores = o.fp32_cores;
     mp = &master;
   }
   return solve(op, L, o, k, q, seed, mp, Z, ldz, ritz, info, s);
@@ -1791,6 +1853,16 @@ int bk_quantize_dense(const float* A, int64_t n, int64_t d, int64_t lda, int32_t
   return BK_OK;
 }
 
+int bk_quantize_dense_transposed(const float* A, int64_t n, int64_t d, int64_t lda, int32_t to,
+                                 void* out_t, float* tile_scales_t, void* stream) {
+  if (n < 0 || d < 0 || lda < d || !A || !out_t) return BK_EINVAL;
+  if (to != BK_BF16 && to != BK_FP8_E4M3) return BK_EINVAL;
+  if (to == BK_FP8_E4M3 && !tile_scales_t) return BK_EINVAL;
+  launch_quant_t(A, n, d, lda, to, out_t, tile_scales_t, static_cast<hipStream_t>(stream));
+  BK_TRY_LAUNCH();
+  return BK_OK;
+}
+
 size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d, int32_t k,
                                   int32_t a_type) {
   if (n <= 0 || d <= 0 || k <= 0) return 0;
@@ -1798,10 +1870,13 @@ size_t bk_dense_product_workspace(int32_t trans, int64_t n, int64_t d, int32_t k
   const size_t part =
       trans ? align_up(static_cast<size_t>(tn_partial_elems(n, d, k)) * sizeof(double), 256)
             : 256;
-  const size_t pack = (a_type == BK_F64)
-                          ? 0
-                          : static_cast<size_t>(trans ? mfma_pack_bytes(n, k, a_type)
-                                                      : mfma_nn_work_bytes(n, d, k, a_type));
+  // (FP32 A^T X: Y's three BF16 limb planes)
+  const size_t pack =
+      (a_type == BK_F64)
+          ? 0
+          : static_cast<size_t>(trans ? (a_type == BK_F32 ? x3_pack_bytes(n, k)
+                                                          : mfma_pack_bytes(n, k, a_type))
+                                      : mfma_nn_work_bytes(n, d, k, a_type));
   return part + pack;
 }
 

@@ -26,6 +26,8 @@ typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) int i32x8;
 
 constexpr int LDS_ROW = 36;  // 32-bit words per staged row: 128 bytes + 16 pad
+// Buffer descriptor word 3 of a raw (unswizzled, 32-bit data format) buffer.
+constexpr int kBufferFlags = 0x00020000;
 
 template <typename T>
 struct Mf;
@@ -270,6 +272,200 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   }
 }
 
+// ---------------------------------------------------- FP32 as BF16 limbs --
+// An FP32 value a splits exactly into three BF16 limbs a = a1 + a2 + a3
+// (a1 = RNE_bf16(a), a2 = RNE_bf16(a - a1), a3 = a - a1 - a2: each
+// difference is exact in FP32 and the last one has at most 8 significant
+// bits).  A product a b is then the sum of nine limb products; the six with
+// limb orders adding up to at most 4 are kept (a1 b1, a1 b2, a2 b1, a1 b3,
+// a2 b2, a3 b1), the dropped three are below 2^-23 |a b| together, and the
+// BF16 matrix-core step multiplies limbs exactly and sums in FP32.  Six
+// 32 x 32 x 16 BF16 steps (32 cycles each) replace eight 32 x 32 x 2 FP32
+// steps (64 cycles each) for 16 values of the reduction.  Finite inputs
+// below the BF16 overflow threshold (about 3.39e38) only.
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+// two FP32 values rounded to BF16 (RNE) in one register, low half first
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
+}
+// Limbs of 8 values, two at a time in packed registers (no element moves):
+// the BF16 halves widen back to FP32 by a shift or a mask.
+__device__ __forceinline__ void split3(const float* x, bf16x8& l1, bf16x8& l2, bf16x8& l3) {
+  uint32_t w1[4], w2[4], w3[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const float a = x[2 * q], b = x[2 * q + 1];
+    const uint32_t p1 = bf16_pair(a, b);
+    const float ra = a - __uint_as_float(p1 << 16), rb = b - __uint_as_float(p1 & 0xFFFF0000u);
+    const uint32_t p2 = bf16_pair(ra, rb);
+    const float sa = ra - __uint_as_float(p2 << 16), sb = rb - __uint_as_float(p2 & 0xFFFF0000u);
+    w1[q] = p1;
+    w2[q] = p2;
+    w3[q] = bf16_pair(sa, sb);
+  }
+  l1 = __builtin_bit_cast(bf16x8, make_uint4(w1[0], w1[1], w1[2], w1[3]));
+  l2 = __builtin_bit_cast(bf16x8, make_uint4(w2[0], w2[1], w2[2], w2[3]));
+  l3 = __builtin_bit_cast(bf16x8, make_uint4(w3[0], w3[1], w3[2], w3[3]));
+}
+
+// acc += a b over one 16-value step from limbs (smallest products first)
+__device__ __forceinline__ f32x16 mfma_x3(const bf16x8* a, const bf16x8* b, f32x16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc, 0, 0, 0);
+}
+
+// Words per staged column of one limb: 32 BF16 (one 32-value chunk) + 16
+// bytes of padding, so that the 8 lanes of a 16-byte LDS read pass hit
+// distinct banks.
+constexpr int X3_COL = 20;
+// Rows per split of the limb X^T Y kernel, whose sums over a split are FP32
+// (the A X kernel sums 32768 values in FP32 likewise).
+constexpr int64_t kX3SplitRows = 16384;
+
+// FP32 A X (A n x K row-major, X^T packed as three BF16 limb planes, see
+// pack_t_x3): workgroup 128 rows x 128 columns of C as in nn_mfma_kernel;
+// the rows of A go from memory into registers (the next chunk in flight)
+// and are split into limbs there, the X^T limbs of a chunk go through LDS.
+// Chunks of 32 values: two steps of 16.
+template <int NT, int WN>
+__global__ __launch_bounds__(256 * WN) void nn_x3_kernel(
+    int64_t n, int64_t K, int N, const float* __restrict__ A, int64_t lda,
+    const bf16_t* __restrict__ Xt, int64_t ldxt, int64_t plane, float* __restrict__ C,
+    int64_t ldc, int64_t cps, float alpha, float beta) {
+  constexpr int CB = 128 * WN;  // columns of C per workgroup
+  __shared__ uint32_t Bs[2][3][CB * X3_COL];
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, r32 = lane & 31;
+  // wavefront (w, cw): rows 32 w .. 32 w + 31 x columns 128 cw .. 128 cw +
+  // 127 of the block; the WN wavefronts of one row group load the same rows
+  // of A at the same time (served once from memory)
+  const int w = (t >> 6) & 3, cw = t >> 8;
+  int64_t rb, cb;
+  if (!xcd_tile(blockIdx.x, (n + 127) / 128, (N + CB - 1) / CB, &rb, &cb)) return;
+  const int64_t nall = K / 32;
+  const int64_t c0 = static_cast<int64_t>(blockIdx.y) * cps;
+  if (c0 >= nall) return;
+  const int64_t nch = (c0 + cps < nall) ? cps : nall - c0;
+  if (gridDim.y > 1) {
+    C += static_cast<int64_t>(blockIdx.y) * n * N;
+    ldc = N;
+  }
+  const int64_t row0 = rb * 128;
+  const int64_t colb = cb * CB;              // the block's first column
+  const int64_t col0 = colb + 128 * cw;      // the wavefront's first column
+  const int ntb = static_cast<int>((N - colb + 31) / 32 < NT * WN ? (N - colb + 31) / 32
+                                                                   : NT * WN);
+  const int64_t row = row0 + 32 * w + r32;
+  // lane (i, h) holds values 8 h .. 8 h + 7 of each 16-value step
+  const uint4* arow =
+      reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 2 * h + c0 * 8;
+  const int bc = t >> 1, bh = t & 1;  // staging: packed column bc, half bh
+  const bool bload = bc < 32 * ntb;
+  const uint4* xrow =
+      reinterpret_cast<const uint4*>(Xt + (colb + (bload ? bc : 0)) * ldxt) + 2 * bh + c0 * 4;
+  const int64_t pl4 = plane / 8;  // limb plane stride in uint4
+  f32x16 acc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) acc[tt] = f32x16{};
+  // A: chunks c+1 and c+2 in flight while chunk c is multiplied (slots mod
+  // 3); X^T limbs of chunk c+1 staged after it.  Unconditional loads (a
+  // chunk past the split's last re-reads the last one; its X^T is staged as
+  // zeros and its steps are skipped).
+  uint4 abuf[3][4], bst[2][3][2];
+  auto aload = [&](int slot, int64_t c) {
+    const int64_t cc = c < nch ? c : nch - 1;
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      abuf[slot][2 * s2] = arow[cc * 8 + 4 * s2];
+      abuf[slot][2 * s2 + 1] = arow[cc * 8 + 4 * s2 + 1];
+    }
+  };
+  auto bload_ = [&](int slot, int64_t c) {
+    const int64_t cc = c < nch ? c : nch - 1;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      bst[slot][l][0] = xrow[l * pl4 + cc * 4];
+      bst[slot][l][1] = xrow[l * pl4 + cc * 4 + 1];
+    }
+  };
+  auto bstore = [&](int slot, int buf, int64_t c) {
+    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        *reinterpret_cast<uint4*>(&Bs[buf][l][bc * X3_COL + 8 * bh + 4 * i]) =
+            make_uint4(bst[slot][l][i].x & mk, bst[slot][l][i].y & mk, bst[slot][l][i].z & mk,
+                       bst[slot][l][i].w & mk);
+  };
+  aload(0, 0);
+  aload(1, 1);
+  bload_(0, 0);
+  bload_(1, 1);
+  bstore(0, 0, 0);
+  __syncthreads();
+  // rounds of 6 chunks: A in slots mod 3, X^T limbs in slots mod 2
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += 6) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int64_t c = cb0 + u;
+      // X^T of chunk c+2 into the slot that chunk c's limbs left (staged at
+      // the end of the previous chunk); then A of chunk c+2
+      bload_(u & 1, c + 2);
+      aload((u + 2) % 3, c + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < nch) {  // (uniform; no memory operation but LDS reads inside)
+        const uint32_t* tile = &Bs[c & 1][0][0];
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) {
+          float av[8];
+          const uint4 a0 = abuf[u % 3][2 * s2], a1v = abuf[u % 3][2 * s2 + 1];
+          av[0] = __uint_as_float(a0.x);
+          av[1] = __uint_as_float(a0.y);
+          av[2] = __uint_as_float(a0.z);
+          av[3] = __uint_as_float(a0.w);
+          av[4] = __uint_as_float(a1v.x);
+          av[5] = __uint_as_float(a1v.y);
+          av[6] = __uint_as_float(a1v.z);
+          av[7] = __uint_as_float(a1v.w);
+          bf16x8 al[3];
+          split3(av, al[0], al[1], al[2]);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) {
+            bf16x8 bl[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+              bl[l] = __builtin_bit_cast(
+                  bf16x8, *reinterpret_cast<const uint4*>(
+                              tile + l * CB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
+                              8 * s2 + 4 * h));
+            acc[tt] = mfma_x3(al, bl, acc[tt]);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      bstore((u + 1) & 1, (c + 1) & 1, c + 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int64_t gc = col0 + 32 * tt + r32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gr = row0 + 32 * w + out_row(lane, v);
+      if (gr < n && gc < N) {
+        float* cp = C + gr * ldc + gc;
+        *cp = beta != 0.0f ? alpha * acc[tt][v] + beta * *cp : alpha * acc[tt][v];
+      }
+    }
+  }
+}
+
 // C (n x N, ldc) = alpha (sum over the S splits of the FP32 partials, in
 // split order) + beta C.
 __global__ __launch_bounds__(256) void nn_split_reduce_kernel(int S, int64_t n, int64_t N,
@@ -485,7 +681,7 @@ __global__ __launch_bounds__(256, 2) void tn_mfma_kernel(
 // transposed.  The Y chunk (32 rows x RB columns) is staged in LDS in its
 // own row order, rows RB + 32 words apart: the two rows one step reads
 // (2 q and 2 q + 1) sit 32 banks apart, and a lane reads its column of row
-// 2 q + h.  Sums over a pair of 32-row chunks are FP32 (the matrix-core
+// 2 q + h.  Sums over three 32-row chunks are FP32 (the matrix-core
 // steps), added into FP64 running sums.  NT = 2 (64 columns of Y) keeps the FP64 sums,
 // two chunks of X and the staging in registers without spills; X is then
 // read once per 64 columns of Y, the repeats served by L2 (the column
@@ -520,9 +716,7 @@ __global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, in
   // lane offset
   const int64_t xc = (p0 + 32 * w + r32 < p) ? p0 + 32 * w + r32 : p - 1;
   const uint32_t xob = static_cast<uint32_t>((xc + h * ldx) * 4);  // bytes
-  auto at = [](const float* base, uint32_t off) {  // SGPR base + 32-bit offset
-    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + off);
-  };
+
   // Y staging: thread t moves 16 bytes at columns 4 (t mod YQ) of rows
   // t / YQ + YR i, i < NP (columns past r clamped as above)
   const int yq = t % YQ, yr = t / YQ;
@@ -535,31 +729,48 @@ __global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, in
   // rows past the split's end re-read its last row; Y's copies of them are
   // stored as zeros, so they add nothing.
   const int64_t lrel = le - 1 - lb;  // last row of the split, relative
+  // whole chunks through buffer loads: the chunk's base in a descriptor
+  // (scalar registers), the row in the scalar offset, the lane's column in
+  // one vector register (no per-load address arithmetic)
   auto xload = [&](float* xv, int64_t c) {
     if (32 * (c + 1) <= lrel + 1) {  // (uniform) a whole chunk
-      const float* b = X + (lb + 32 * c) * ldx;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(X + (lb + 32 * c) * ldx), 0, -1, kBufferFlags);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) xv[q] = at(b + 2 * q * ldx, xob);
-    } else {
+      for (int q = 0; q < 16; ++q)
+        xv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rs, xob, static_cast<int>(2 * q * ldx * 4), 0));
+    } else {  // rows clamped to the split's last (base: the chunk's first
+              // row, or the last row for a chunk past the end)
+      const int64_t cbase = 32 * c < lrel ? 32 * c : lrel;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(X + (lb + cbase) * ldx), 0, -1, kBufferFlags);
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int64_t rr = (32 * c + 2 * q + h < lrel) ? 32 * c + 2 * q + h : lrel;
-        xv[q] = X[(lb + rr) * ldx + xc];
+        xv[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            rs, static_cast<uint32_t>(xc * 4 + (rr - cbase) * ldx * 4), 0, 0));
       }
     }
   };
   auto yload_ = [&](uint4* yv, int64_t c) {
     if (32 * (c + 1) <= lrel + 1) {
-      const float* b = Y + (lb + 32 * c) * ldy;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(Y + (lb + 32 * c) * ldy), 0, -1, kBufferFlags);
 #pragma unroll
       for (int i = 0; i < NP; ++i)
-        yv[i] = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(b + YR * i * ldy) +
-                                                yob);
+        yv[i] = __builtin_bit_cast(
+            uint4, __builtin_amdgcn_raw_buffer_load_b128(rs, yob, static_cast<int>(YR * i * ldy * 4), 0));
     } else {
+      const int64_t cbase = 32 * c < lrel ? 32 * c : lrel;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(Y + (lb + cbase) * ldy), 0, -1, kBufferFlags);
 #pragma unroll
       for (int i = 0; i < NP; ++i) {
         const int64_t rr = (32 * c + yr + YR * i < lrel) ? 32 * c + yr + YR * i : lrel;
-        yv[i] = *reinterpret_cast<const uint4*>(Y + (lb + rr) * ldy + yc);
+        yv[i] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(
+                                              rs, static_cast<uint32_t>(yc * 4 + (rr - cbase) * ldy * 4),
+                                              0, 0));
       }
     }
   };
@@ -578,34 +789,40 @@ __global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, in
   for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[tt][v] = 0.0;
-  // X: the next chunk in flight while the current one is multiplied (a
-  // chunk is 16 NT matrix-core steps of 64 cycles per wavefront); Y one
-  // chunk ahead through LDS.  Chunks go in pairs (the two register sets)
-  // with no branch between them: the chunk after the last, and the second
-  // of an odd last pair, re-read the split's last row and stage zeros.
-  float xv[2][16];
-  uint4 yv[NP];
+  // Two chunks in flight ahead of the one multiplied (a chunk is 16 NT
+  // matrix-core steps of 64 cycles per wavefront, two wavefronts per SIMD:
+  // about one memory latency): X and Y of chunk c+2 are loaded into register
+  // slot (c+2) mod 3 while chunk c is multiplied, and Y of chunk c+1 (loaded
+  // a chunk earlier) is staged in LDS after it.  Chunks go in rounds of
+  // three with no branch around a memory operation: chunks past the last
+  // re-read the split's last row and stage zeros (their steps are skipped).
+  float xv[3][16];
+  uint4 yv[3][NP];
   if (nch == 0) return;  // (uniform; no partials: a split is never empty)
+  yload_(yv[0], 0);
   xload(xv[0], 0);
-  yload_(yv, 0);
-  ystore(yv, 0, 0);
+  yload_(yv[1], 1);
+  xload(xv[1], 1);
+  ystore(yv[0], 0, 0);
   __syncthreads();
-  // FP32 sums of a pair of chunks (64 rows) per tile, then into FP64
+  // FP32 sums of a round of chunks (96 rows) per tile, then into FP64
   f32x16 tmp[NT];
-  for (int64_t cb0 = 0; cb0 < nch; cb0 += 2) {
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += 3) {
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt) tmp[tt] = f32x16{};
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < 3; ++u) {
       const int64_t c = cb0 + u;
-      {
-        yload_(yv, c + 1);
-        xload(xv[u ^ 1], c + 1);
-        // keep the loads here, a whole chunk ahead of their use (the
-        // scheduler would otherwise sink the Y loads next to their stores);
-        // Y first, so that the wait before its store leaves X in flight
-        __builtin_amdgcn_sched_barrier(0);
-        const float* yt = Ys[u] + h * YS + r32;
+      const int s2 = (u + 2) % 3, s1 = (u + 1) % 3;
+      // Y first: the wait before the store of Y(c+1) then leaves chunk
+      // c+2 in flight (the wait counter drains in issue order)
+      yload_(yv[s2], c + 2);
+      xload(xv[s2], c + 2);
+      // keep the loads here (the scheduler would otherwise sink them
+      // next to their uses)
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < nch) {  // (uniform; no memory operation but LDS reads inside)
+        const float* yt = Ys[c & 1] + h * YS + r32;
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) {
           // the tile's 16 Y operands first, then its 16 steps
@@ -616,10 +833,10 @@ __global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, in
           for (int q = 0; q < 16; ++q)
             tmp[tt] = __builtin_amdgcn_mfma_f32_32x32x2f32(xv[u][q], yb[q], tmp[tt], 0, 0, 0);
         }
-        __builtin_amdgcn_sched_barrier(0);
-        ystore(yv, u ^ 1, c + 1);
-        __syncthreads();
       }
+      __builtin_amdgcn_sched_barrier(0);
+      ystore(yv[s1], (c + 1) & 1, c + 1);
+      __syncthreads();
     }
 #pragma unroll
     for (int tt = 0; tt < NT; ++tt)
@@ -633,6 +850,154 @@ __global__ __launch_bounds__(256, 2) void tn_f32_kernel(int64_t L, int64_t p, in
     for (int v = 0; v < 16; ++v) {
       const int64_t gp = p0 + 32 * w + out_row(lane, v);
       if (tt < nt && gp < p && gc < r) partial[(sidx * p + gp) * r + gc] = acc[tt][v];
+    }
+  }
+}
+
+// FP32 X^T Y through BF16 limbs: X as in tn_f32_kernel (columns straight
+// from memory into registers, here split into limbs there), Y^T packed as
+// three limb planes (pack_t_x3) and staged in LDS as in nn_x3_kernel.
+// Lane (i, h) of wavefront w holds column p0 + 32 w + i and, at step s of a
+// 32-row chunk, rows 16 s + 8 h .. 16 s + 8 h + 7.  Workgroup: 128 columns
+// of X x 128 of Y.  FP32 sums over the split (at most kX3SplitRows rows, as
+// long as the FP32 sums of the A X products), whose partials the reduction
+// adds in FP64.
+template <int WN>
+__global__ __launch_bounds__(256 * WN) void tn_x3_kernel(int64_t L, int64_t p, int r,
+                                                         const float* __restrict__ X,
+                                                         int64_t ldx,
+                                                         const bf16_t* __restrict__ Yt,
+                                                         int64_t ldyt, int64_t plane,
+                                                         double* __restrict__ partial,
+                                                         int64_t Ls, int sym) {
+  constexpr int NT = 4, RB = 128 * WN;  // columns of Y per workgroup
+  __shared__ uint32_t Bs[2][3][RB * X3_COL];
+  const int t = threadIdx.x, lane = t & 63, h = lane >> 5, r32 = lane & 31;
+  // wavefront (w, cw): columns 32 w .. of X x columns 128 cw .. of Y; the
+  // WN wavefronts of one X column group load the same rows at the same time
+  const int w = (t >> 6) & 3, cw = t >> 8;
+  int64_t pb, rbk;
+  if (!xcd_tile(blockIdx.x, (p + 127) / 128, (r + RB - 1) / RB, &pb, &rbk)) return;
+  const int64_t p0 = pb * 128;
+  const int64_t rblk = rbk * RB;          // the block's first column of Y
+  const int64_t r0 = rblk + 128 * cw;     // the wavefront's
+  if (sym && p0 > rblk + RB - 1) return;  // below the diagonal: mirrored by the reduction
+  const int64_t sidx = blockIdx.y;
+  const int64_t lb = sidx * Ls;
+  const int64_t le = (lb + Ls < L) ? lb + Ls : L;
+  const int nt = static_cast<int>((r - r0 + 31) / 32 < NT ? (r - r0 + 31) / 32 : NT);
+  const int ntb = static_cast<int>((r - rblk + 31) / 32 < NT * WN ? (r - rblk + 31) / 32
+                                                                   : NT * WN);
+  const int64_t nch = (le - lb + 31) / 32;
+  if (nch == 0) return;  // (uniform; a split is never empty)
+  const int64_t xc = (p0 + 32 * w + r32 < p) ? p0 + 32 * w + r32 : p - 1;
+  const uint32_t xob = static_cast<uint32_t>((xc + 8 * h * ldx) * 4);
+  const int64_t lrel = le - 1 - lb;  // last row of the split, relative
+  // X rows of chunk c: whole chunks by buffer loads (row in the scalar
+  // offset); a chunk reaching past the split clamps its rows to the last
+  // one (their Y limbs are staged as zeros)
+  auto xload = [&](float* xv, int64_t c) {
+    if (32 * (c + 1) <= lrel + 1) {
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(X + (lb + 32 * c) * ldx), 0, -1, kBufferFlags);
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          xv[8 * s2 + j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              rs, xob, static_cast<int>((16 * s2 + j) * ldx * 4), 0));
+    } else {
+      const int64_t cbase = 32 * c < lrel ? 32 * c : lrel;
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(X + (lb + cbase) * ldx), 0, -1, kBufferFlags);
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t rr0 = 32 * c + 16 * s2 + 8 * h + j;
+          const int64_t rr = rr0 < lrel ? rr0 : lrel;
+          xv[8 * s2 + j] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+              rs, static_cast<uint32_t>(xc * 4 + (rr - cbase) * ldx * 4), 0, 0));
+        }
+    }
+  };
+  // Y^T limb staging: thread t moves 32 bytes (16 values) of packed column
+  // t / 2, half t mod 2 of the chunk, for each limb
+  const int bc = t >> 1, bh = t & 1;
+  const bool bload = bc < 32 * ntb;
+  const uint4* yrow =
+      reinterpret_cast<const uint4*>(Yt + (rblk + (bload ? bc : 0)) * ldyt + lb) + 2 * bh;
+  const int64_t pl4 = plane / 8;
+  auto yload_ = [&](uint4 (*yv)[2], int64_t c) {
+    const int64_t cc = c < nch ? c : nch - 1;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      yv[l][0] = yrow[l * pl4 + cc * 4];
+      yv[l][1] = yrow[l * pl4 + cc * 4 + 1];
+    }
+  };
+  auto ystore = [&](const uint4 (*yv)[2], int buf, int64_t c) {
+    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        *reinterpret_cast<uint4*>(&Bs[buf][l][bc * X3_COL + 8 * bh + 4 * i]) =
+            make_uint4(yv[l][i].x & mk, yv[l][i].y & mk, yv[l][i].z & mk, yv[l][i].w & mk);
+  };
+  f32x16 acc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) acc[tt] = f32x16{};
+  // X and the Y limbs: two chunks in flight ahead of the one multiplied (X
+  // in slots mod 3, Y in slots mod 2); chunk c+1's Y limbs are staged after
+  // chunk c.  Rounds of six chunks.
+  float xv[3][16];
+  uint4 yv[2][3][2];
+  yload_(yv[0], 0);
+  yload_(yv[1], 1);
+  xload(xv[0], 0);
+  xload(xv[1], 1);
+  ystore(yv[0], 0, 0);
+  __syncthreads();
+  for (int64_t cb0 = 0; cb0 < nch; cb0 += 6) {
+#pragma unroll
+    for (int u = 0; u < 6; ++u) {
+      const int64_t c = cb0 + u;
+      yload_(yv[u & 1], c + 2);
+      xload(xv[(u + 2) % 3], c + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      if (c < nch) {  // (uniform; no memory operation but LDS reads inside)
+        const uint32_t* tile = &Bs[c & 1][0][0];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+          bf16x8 al[3];
+          split3(&xv[u % 3][8 * st], al[0], al[1], al[2]);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) {
+            bf16x8 bl[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+              bl[l] = __builtin_bit_cast(
+                  bf16x8, *reinterpret_cast<const uint4*>(
+                              tile + l * RB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
+                              8 * st + 4 * h));
+            acc[tt] = mfma_x3(al, bl, acc[tt]);
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      ystore(yv[(u + 1) & 1], (c + 1) & 1, c + 1);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int64_t gc = r0 + 32 * tt + r32;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t gp = p0 + 32 * w + out_row(lane, v);
+      if (tt < nt && gp < p && gc < r)
+        partial[(sidx * p + gp) * r + gc] = static_cast<double>(acc[tt][v]);
     }
   }
 }
@@ -690,6 +1055,41 @@ __global__ __launch_bounds__(256) void pack_t_kernel(const TS* __restrict__ src,
       if constexpr (sizeof(T) == 1) y = f32_to_e4m3(__fdiv_rn(x, sc));
       else y = to_elem<T>(x, 0.0f);
       dst[(c0 + cc) * rows_pad + rb + rr] = y;
+    }
+    __syncthreads();
+  }
+}
+
+// Dst (three planes of cols_pad x rows_pad BF16, plane stride `plane`,
+// zero padded) = the limbs of Src^T (Src rows x cols FP32, or FP64 rounded
+// to FP32 first), for the split FP32 products.
+template <typename TS>
+__global__ __launch_bounds__(256) void pack_t_x3_kernel(const TS* __restrict__ src, int64_t lds,
+                                                        int64_t rows, int64_t cols,
+                                                        bf16_t* __restrict__ dst,
+                                                        int64_t rows_pad, int64_t cols_pad,
+                                                        int64_t plane) {
+  __shared__ float tile[128][33];
+  const int t = threadIdx.x;
+  const int64_t rb = static_cast<int64_t>(blockIdx.x) * 128;
+  for (int64_t c0 = 0; c0 < cols_pad; c0 += 32) {
+    for (int i = t; i < 128 * 32; i += 256) {
+      const int rr = i >> 5, cc = i & 31;
+      const int64_t gr = rb + rr, gc = c0 + cc;
+      tile[rr][cc] = (gr < rows && gc < cols) ? static_cast<float>(src[gr * lds + gc]) : 0.0f;
+    }
+    __syncthreads();
+    for (int i = t; i < 128 * 32; i += 256) {
+      const int cc = i >> 7, rr = i & 127;
+      const float x = tile[rr][cc];
+      const __bf16 h1 = static_cast<__bf16>(x);
+      const float r1 = x - static_cast<float>(h1);
+      const __bf16 h2 = static_cast<__bf16>(r1);
+      const __bf16 h3 = static_cast<__bf16>(r1 - static_cast<float>(h2));
+      const int64_t o = (c0 + cc) * rows_pad + rb + rr;
+      dst[o] = __builtin_bit_cast(bf16_t, h1);
+      dst[plane + o] = __builtin_bit_cast(bf16_t, h2);
+      dst[2 * plane + o] = __builtin_bit_cast(bf16_t, h3);
     }
     __syncthreads();
   }
@@ -875,6 +1275,8 @@ int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type) {
 int tn_mfma_splits(int64_t L, int64_t p, int r) {
   const int64_t tiles = cdiv(p, 128) * cdiv(r, 128);
   int64_t S = cdiv(512, tiles);
+  // FP32 sums of the limb kernel over at most kX3SplitRows rows
+  S = std::max<int64_t>(S, cdiv(L, kX3SplitRows));
   const int64_t smax = std::max<int64_t>(1, cdiv(L, 128));
   if (S > smax) S = smax;
   if (S > 64) S = 64;
@@ -901,6 +1303,54 @@ static void pack_t(const void* src, bool src_f64, int64_t lds, int64_t rows, int
   else
     pack_t_kernel<T, float><<<g, 256, 0, s>>>(static_cast<const float*>(src), lds, rows, cols,
                                                dst, *rows_pad, *cols_pad, *scales);
+}
+
+// Bytes of the three BF16 limb planes of an lred x cols FP32 operand.
+int64_t x3_pack_bytes(int64_t lred, int64_t cols) {
+  const int64_t lp = align_up(static_cast<size_t>(lred), 128);
+  const int64_t cp = align_up(static_cast<size_t>(cols), 32);
+  return static_cast<int64_t>(align_up(static_cast<size_t>(3 * cp * lp * 2), 256)) + 256;
+}
+
+// FP32 A X on the BF16 matrix cores through limbs (nn_x3_kernel).
+static int nn_run_x3(const NNArgs& a, hipStream_t s) {
+  const int64_t kp = align_up(static_cast<size_t>(a.K), 128);
+  const int64_t np = align_up(static_cast<size_t>(a.N), 32);
+  const int64_t plane = kp * np;
+  bf16_t* xt = static_cast<bf16_t*>(a.work);
+  const unsigned g = static_cast<unsigned>(kp / 128);
+  if (a.x_f64)
+    pack_t_x3_kernel<double><<<g, 256, 0, s>>>(static_cast<const double*>(a.X), a.ldx, a.K, a.N,
+                                               xt, kp, np, plane);
+  else
+    pack_t_x3_kernel<float><<<g, 256, 0, s>>>(static_cast<const float*>(a.X), a.ldx, a.K, a.N,
+                                              xt, kp, np, plane);
+  const int S = nn_mfma_splits(a.n, a.K, a.N, BK_F32);
+  const int64_t nch = a.K / 32;
+  const int64_t cps = cdiv(nch, S);
+  float* part = S > 1 ? reinterpret_cast<float*>(static_cast<char*>(a.work) +
+                                                 x3_pack_bytes(a.K, a.N))
+                      : static_cast<float*>(a.C);
+  // N > 128: one workgroup of 512 takes 256 columns, so every row of A is
+  // read from memory once (two 128-column workgroups drift apart and read
+  // it twice)
+  const int WN = a.N > 128 ? 2 : 1;
+  const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128 * WN))),
+                  static_cast<unsigned>(S));
+  const float al = static_cast<float>(a.alpha), be = static_cast<float>(a.beta);
+#define BK_NNX_LAUNCH(NTV, WNV)                                                             \
+  nn_x3_kernel<NTV, WNV><<<grid, 256 * WNV, 0, s>>>(                                        \
+      a.n, a.K, a.N, static_cast<const float*>(a.A), a.lda, xt, kp, plane, part,             \
+      S > 1 ? a.N : a.ldc, cps, S > 1 ? 1.0f : al, S > 1 ? 0.0f : be)
+  if (WN == 2) BK_NNX_LAUNCH(4, 2);
+  else if (a.N <= 32) BK_NNX_LAUNCH(1, 1);
+  else if (a.N <= 64) BK_NNX_LAUNCH(2, 1);
+  else BK_NNX_LAUNCH(4, 1);
+#undef BK_NNX_LAUNCH
+  if (S == 1) return 2;
+  nn_split_reduce_kernel<<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(
+      S, a.n, a.N, part, static_cast<float*>(a.C), a.ldc, al, be);
+  return 3;
 }
 
 template <typename T, bool SCALED>
@@ -948,7 +1398,10 @@ int nn_mfma_splits(int64_t n, int64_t K, int64_t N, int type) {
 
 int64_t mfma_nn_work_bytes(int64_t n, int64_t K, int64_t N, int type) {
   const int S = nn_mfma_splits(n, K, N, type);
-  return mfma_pack_bytes(K, N, type) +
+  // FP32: the larger of the FP32 packing and the three BF16 limb planes
+  const int64_t pk = type == BK_F32 ? std::max(mfma_pack_bytes(K, N, type), x3_pack_bytes(K, N))
+                                    : mfma_pack_bytes(K, N, type);
+  return pk +
          (S > 1 ? static_cast<int64_t>(align_up(static_cast<size_t>(S * n * N) * 4, 256)) : 0);
 }
 
@@ -970,7 +1423,7 @@ void launch_nn_mfma_if(const NNArgs& a, hipStream_t s, int* launches) {
   if (2.0 * static_cast<double>(a.n) * static_cast<double>(a.K) * a.N < 1e8) return;
   switch (a.a_type) {
     case BK_F32:
-      *launches = nn_run<float, false>(a, BK_F32, s);
+      *launches = a.fp32_cores ? nn_run<float, false>(a, BK_F32, s) : nn_run_x3(a, s);
       break;
     case BK_BF16:
       *launches = nn_run<bf16_t, false>(a, BK_BF16, s);
@@ -986,6 +1439,32 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),
                   static_cast<unsigned>(S));
   if constexpr (sizeof(T) == 4) {
+    if (!a.fp32_cores && a.work &&
+        static_cast<int64_t>(a.work_bytes) >= x3_pack_bytes(a.L, a.r)) {
+      // BF16 limbs: Y^T packed in three planes, 64 columns of Y per workgroup
+      const int64_t lp = align_up(static_cast<size_t>(a.L), 128);
+      const int64_t rp = align_up(static_cast<size_t>(a.r), 32);
+      const int64_t plane = lp * rp;
+      bf16_t* yt = static_cast<bf16_t*>(a.work);
+      pack_t_x3_kernel<float><<<static_cast<unsigned>(lp / 128), 256, 0, s>>>(
+          static_cast<const float*>(a.Y), a.ldy, a.L, a.r, yt, lp, rp, plane);
+      // r > 128: a workgroup of 512 takes 256 columns of Y, so that X is
+      // read from memory once
+      if (a.r > 128) {
+        const dim3 gridx(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 256))),
+                         static_cast<unsigned>(S));
+        tn_x3_kernel<2><<<gridx, 512, 0, s>>>(a.L, a.p, a.r, static_cast<const float*>(a.X),
+                                              a.ldx, yt, lp, plane, a.partial, Ls,
+                                              a.sym ? 1 : 0);
+      } else {
+        const dim3 gridx(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 128))),
+                         static_cast<unsigned>(S));
+        tn_x3_kernel<1><<<gridx, 256, 0, s>>>(a.L, a.p, a.r, static_cast<const float*>(a.X),
+                                              a.ldx, yt, lp, plane, a.partial, Ls,
+                                              a.sym ? 1 : 0);
+      }
+      return;
+    }
     // 64 columns of Y per workgroup (32 for narrower Y)
     const int NTV = a.r <= 32 ? 1 : 2;
     const dim3 gridf(static_cast<unsigned>(xcd_grid(cdiv(a.p, 128), cdiv(a.r, 32 * NTV))),
@@ -1034,9 +1513,13 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
   }
   const int S = tn_mfma_splits(a.L, a.p, a.r);
   const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
-  // below two workgroups per CU the vector kernel is faster (e.g. a 256 x
-  // 256 Gram over 131072 rows: 390 us against 660 us)
-  if (!packed && cdiv(a.p, 128) * cdiv(a.r, 128) * S < 512) return;
+  // FP32 on the FP32 matrix cores: below two workgroups per CU the vector
+  // kernel is faster (e.g. a 256 x 256 Gram over 131072 rows: 390 us
+  // against 660 us); as BF16 limbs from half a workgroup per CU on
+  const bool limbs = !packed && !a.fp32_cores && a.work &&
+                     static_cast<int64_t>(a.work_bytes) >= x3_pack_bytes(a.L, a.r);
+  const int64_t wgs = cdiv(a.p, 128) * cdiv(a.r, 128) * S;
+  if (!packed && wgs < (limbs ? 128 : 512)) return;
   switch (a.x_type) {
     case BK_F32:
       tn_run<float, false>(a, S, Ls, s);

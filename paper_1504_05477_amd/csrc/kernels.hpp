@@ -43,6 +43,9 @@ struct NNArgs {
   // chip idle (vector path, no gram_partial): S n N doubles
   double* split_work = nullptr;
   int64_t split_work_elems = 0;
+  // FP32 A on the FP32 matrix cores (32 x 32 x 2 steps) instead of as three
+  // BF16 limbs on the BF16 matrix cores
+  bool fp32_cores = false;
 };
 // returns the number of kernels launched (0: not launched)
 int launch_nn(const NNArgs& a, hipStream_t s);
@@ -76,6 +79,9 @@ struct TNArgs {
   // X and Y the same matrix (p = r): tiles below the diagonal are skipped and
   // C mirrored from above it
   bool sym = false;
+  // FP32 X on the FP32 matrix cores instead of as three BF16 limbs (the
+  // limbs need `work` for Y's limb planes; without it the FP32 cores run)
+  bool fp32_cores = false;
 };
 int tn_splits(int64_t L, int64_t p, int r);
 int64_t tn_partial_elems(int64_t L, int64_t p, int r);
@@ -85,6 +91,9 @@ int launch_tn(const TNArgs& a, hipStream_t s);  // kernels launched
 // of aligned, large enough products; otherwise the VALU kernels run.
 // Bytes of scratch to pack an lred x cols FP32 operand in `type`.
 int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type);
+// Bytes of the three BF16 limb planes of an lred x cols FP32 operand (FP32
+// products on the BF16 matrix cores).
+int64_t x3_pack_bytes(int64_t lred, int64_t cols);
 // Splits of K of the matrix-core A X (n x K times K x N) and the scratch it
 // needs: the packed X^T plus, with several splits, their FP32 partials.
 int nn_mfma_splits(int64_t n, int64_t K, int64_t N, int type);
@@ -328,6 +337,10 @@ void launch_csr_transpose(const int32_t* rp, const int32_t* ci,
                           hipStream_t s);
 
 // ---------------------------------------------------------------- quant --
+// Transposed copy (d x n, ld n) with the codes of the copies below; FP8
+// scales_t [ceil(d/128)][ceil(n/128)] (the transpose of their tile scales).
+void launch_quant_t(const float* A, int64_t n, int64_t d, int64_t lda, int to, void* out,
+                    float* scales_t, hipStream_t s);
 void launch_quant_bf16(const float* A, int64_t n, int64_t d, int64_t lda,
                        bf16_t* out, hipStream_t s);
 void launch_quant_fp8(const float* A, int64_t n, int64_t d, int64_t lda,

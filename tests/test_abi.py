@@ -44,10 +44,40 @@ def test_status_strings(lib):
 
 
 def test_struct_layouts():
-    assert C.sizeof(L.Options) == 80
+    assert C.sizeof(L.Options) == 112
     assert L.Options.residuals.offset == 72
+    assert L.Options.at_scales.offset == 96
     assert L.Info.workspace_bytes.offset == 112
     assert C.sizeof(L.Metrics) == 56
+
+
+def test_struct_layouts_match_the_c_header(tmp_path):
+    # every field of the ctypes mirrors sits where a C compiler puts it
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bk.h"', "int main(void) {"]
+    for cname, py in (("bk_options", L.Options), ("bk_info", L.Info), ("bk_metrics", L.Metrics)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "lay.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "lay"
+    subprocess.run([cc, f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {}
+    for line in out.splitlines():
+        cname, f, v = line.split()
+        got[(cname, f)] = int(v)
+    for cname, py in (("bk_options", L.Options), ("bk_info", L.Info), ("bk_metrics", L.Metrics)):
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
 
 
 def _opt():

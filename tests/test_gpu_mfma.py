@@ -72,7 +72,7 @@ def test_mfma_block_products(prec, trans):
     assert err.max() < 1e-5 if trans else err.max() < 2e-5
 
 
-@pytest.mark.parametrize("prec", ["plain", "bf16", "fp8"])
+@pytest.mark.parametrize("prec", ["plain", "plain_fp32_cores", "bf16", "fp8"])
 def test_svd_dense_on_matrix_cores(prec):
     # both block products above the thresholds (2 n d k >= 1e9)
     n, d, k, q = 8192, 2048, 32, 4
@@ -82,8 +82,10 @@ def test_svd_dense_on_matrix_cores(prec):
                            philox.gaussian(33, d, k).astype(np.float32).astype(np.float64),
                            k, q, tau=1e-5)
     Ag = _cuda(A)
-    if prec == "plain":
-        res = bk.svd_dense(Ag, k, q, seed=33)
+    if prec.startswith("plain"):
+        # FP32 products as BF16 limbs (default) or on the FP32 matrix cores
+        res = bk.svd_dense(Ag, k, q, seed=33,
+                           fp32_products="cores" if prec.endswith("cores") else "limbs")
         tol = 1e-5
     elif prec == "bf16":
         res = bk.svd_dense(bk.quantize(Ag, "bf16"), k, q, seed=33, A_master=Ag)
@@ -98,3 +100,57 @@ def test_svd_dense_on_matrix_cores(prec):
     print(f"{prec}: max Ritz rel err {rel.max():.2e}, |Z^T Z - I| {orth:.1e}")
     assert rel.max() <= tol, rel.max()
     assert orth < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_transposed_copy_is_the_transpose(prec):
+    # ragged in both dimensions: partial 128 x 128 tiles on both edges
+    rng = np.random.default_rng(19)
+    A = (rng.standard_normal((1000, 700)) * np.exp(rng.uniform(-3, 3, (1000, 1)))).astype(
+        np.float32)
+    Ag = _cuda(A)
+    if prec == "bf16":
+        Aq, At = bk.quantize(Ag, "bf16"), bk.quantize(Ag, "bf16", transposed=True)
+        assert tuple(At.shape) == (700, 1000)
+        assert torch.equal(At.view(torch.int16), Aq.t().contiguous().view(torch.int16))
+    else:
+        (Aq, sc), (At, sct) = bk.quantize(Ag, "fp8"), bk.quantize(Ag, "fp8", transposed=True)
+        assert tuple(At.shape) == (700, 1000) and tuple(sct.shape) == (6, 8)
+        assert torch.equal(At, Aq.t().contiguous())
+        assert torch.equal(sct, sc.t().contiguous())
+        # and A^T X read row by row from the copy equals the dequantised A^T X
+        X = rng.standard_normal((1000, 40)).astype(np.float32)
+        Y = bk.dense_product(At, _cuda(X), a_scales=sct).cpu().numpy()
+        Ad = quant.dequantize_fp8_tiles(Aq.cpu().numpy().view(np.uint8), sc.cpu().numpy())
+        ref = Ad.T @ X.astype(np.float64)
+        err = np.abs(Y - ref) / (np.abs(Ad).T @ np.abs(X.astype(np.float64)))
+        assert err.max() < 1e-5, err.max()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("n", [8192, 8000])
+def test_svd_dense_with_transposed_copy(prec, n):
+    # A^T Y on the transposed copy: the A X-form matrix-core kernel (n a
+    # multiple of its 128-value chunks) or the vector kernel (n = 8000)
+    d, k, q = 2048, 32, 4
+    A = workloads.planted_dense(n, d, workloads.spectrum("inv", d), 23).astype(np.float32)
+    ref = bki.block_krylov(A.astype(np.float64),
+                           philox.gaussian(33, d, k).astype(np.float32).astype(np.float64),
+                           k, q, tau=1e-5)
+    Ag = _cuda(A)
+    if prec == "bf16":
+        Aq, At = bk.quantize(Ag, "bf16"), bk.quantize(Ag, "bf16", transposed=True)
+        res = bk.svd_dense(Aq, k, q, seed=33, A_master=Ag, A_t=At)
+        res0 = bk.svd_dense(Aq, k, q, seed=33, A_master=Ag)
+    else:
+        (Aq, sc), (At, sct) = bk.quantize(Ag, "fp8"), bk.quantize(Ag, "fp8", transposed=True)
+        res = bk.svd_dense(Aq, k, q, seed=33, a_scales=sc, A_master=Ag, A_t=At, at_scales=sct)
+        res0 = bk.svd_dense(Aq, k, q, seed=33, a_scales=sc, A_master=Ag)
+    s, s0 = res.sigma.cpu().numpy(), res0.sigma.cpu().numpy()
+    rel = np.abs(s - ref.sigma) / ref.sigma
+    print(f"{prec} n={n}: Ritz rel err {rel.max():.2e} (without the copy "
+          f"{(np.abs(s0 - ref.sigma) / ref.sigma).max():.2e}), q_eff {res.info['q_eff']}")
+    assert rel.max() <= 1e-3
+    assert res.info["q_eff"] == res0.info["q_eff"]
+    Z = res.Z.cpu().numpy()
+    assert np.abs(Z.T @ Z - np.eye(k)).max() < 1e-4
