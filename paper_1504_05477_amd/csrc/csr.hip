@@ -3,6 +3,8 @@
 // of the PCA footnote in Section 1 (A - mu 1^T applied as a rank-1
 // correction, never densified) and a deterministic GPU transpose that gives
 // A^T X the same row-split kernel.
+#include <rocprim/device/device_radix_sort.hpp>
+
 #include "kernels.hpp"
 
 namespace bk {
@@ -490,70 +492,42 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int32_t* cnt, int64_t 
   }
 }
 
-__global__ __launch_bounds__(256) void copy_i32_kernel(const int32_t* a, int32_t* b,
-                                                       int64_t n) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
-  if (i < n) b[i] = a[i];
-}
 
-// Each nonzero (r, c, v) of A goes to the row c of A^T; its slot in that row
-// is taken with an atomic, so the key (r << 32 | bits(v)) is stored and the
-// rows are sorted afterwards: the result does not depend on the atomics.
-__global__ __launch_bounds__(256) void scatter_kernel(const int32_t* rp,
-                                                      const int32_t* ci,
-                                                      const float* v, int64_t rows,
-                                                      int32_t* cursor,
-                                                      unsigned long long* keys) {
+// Row id and position of every nonzero (the payload of the sort below), a
+// wavefront per row.
+__global__ __launch_bounds__(256) void expand_rows_kernel(const int32_t* rp, int64_t rows,
+                                                          int32_t* rowid, int32_t* pos) {
   const int64_t row = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
   const int lane = threadIdx.x & 63;
   for (int32_t j = rp[row] + lane; j < rp[row + 1]; j += 64) {
-    const int32_t pos = atomicAdd(&cursor[ci[j]], 1);
-    keys[pos] = (static_cast<unsigned long long>(static_cast<uint32_t>(row)) << 32) |
-                static_cast<unsigned long long>(__float_as_uint(v[j]));
+    rowid[j] = static_cast<int32_t>(row);
+    pos[j] = j;
   }
 }
 
-// Bitonic sort of one row of keys (ascending) per workgroup; rows of up to
-// 4096 keys in LDS, longer rows in the global scratch area `big`
-// (length rounded up to a power of two, padded with all-ones keys).
-__global__ __launch_bounds__(256) void sort_rows_kernel(const int32_t* trp,
-                                                        int64_t nrows,
-                                                        unsigned long long* keys,
-                                                        unsigned long long* big,
-                                                        int32_t* tci, float* tv) {
-  __shared__ unsigned long long sk[4096];
-  const int64_t row = blockIdx.x;
-  if (row >= nrows) return;
-  const int t = threadIdx.x;
-  const int32_t beg = trp[row], end = trp[row + 1];
-  const int32_t len = end - beg;
-  if (len <= 0) return;
-  int32_t P = 1;
-  while (P < len) P <<= 1;
-  unsigned long long* K = (P <= 4096) ? sk : big + 2 * static_cast<int64_t>(beg);
-  for (int32_t i = t; i < P; i += 256) K[i] = (i < len) ? keys[beg + i] : ~0ull;
-  __syncthreads();
-  for (int32_t size = 2; size <= P; size <<= 1) {
-    for (int32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int32_t i = t; i < P / 2; i += 256) {
-        const int32_t lo = 2 * stride * (i / stride) + (i % stride);
-        const int32_t hi = lo + stride;
-        const bool asc = (lo & size) == 0;
-        const unsigned long long a = K[lo], b = K[hi];
-        if ((a > b) == asc) {
-          K[lo] = b;
-          K[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int32_t i = t; i < len; i += 256) {
-    const unsigned long long key = K[i];
-    tci[beg + i] = static_cast<int32_t>(key >> 32);
-    tv[beg + i] = __uint_as_float(static_cast<uint32_t>(key & 0xFFFFFFFFull));
-  }
+__global__ __launch_bounds__(256) void copy_keys_kernel(const int32_t* ci, int64_t nnz,
+                                                        int32_t* keys) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i < nnz) keys[i] = ci[i];
+}
+
+// Entry p of A^T (column-major order of A) from the sorted positions.
+__global__ __launch_bounds__(256) void gather_t_kernel(const int32_t* src, int64_t nnz,
+                                                       const int32_t* rowid,
+                                                       const float* v, int32_t* tci,
+                                                       float* tv) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= nnz) return;
+  const int32_t j = src[p];
+  tci[p] = rowid[j];
+  tv[p] = v[j];
+}
+
+unsigned key_bits(int64_t cols) {
+  unsigned b = 1;
+  while ((int64_t(1) << b) < cols) ++b;
+  return b;
 }
 
 int kc_for(int k) { return k < 64 ? k : 64; }
@@ -673,25 +647,53 @@ void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,
         rp, v, rows, cols, mu);
 }
 
-void launch_csr_transpose(const int32_t* rp, const int32_t* ci, const float* v,
-                          int64_t rows, int64_t cols, int64_t nnz, int32_t* trp,
-                          int32_t* tci, float* tv, int32_t* cursor,
-                          unsigned long long* keys, hipStream_t s) {
-  // cursor: cols ints; keys: 3 * nnz (nnz sort keys + 2 * nnz scratch)
+size_t csr_transpose_scratch_bytes(int64_t nnz, int64_t cols) {
+  // keys and positions in two buffers each (the sort's double buffers) and
+  // the row ids: 20 bytes per nonzero, plus the sort's own storage
+  size_t tb = 0;
+  rocprim::double_buffer<int32_t> kb(nullptr, nullptr);
+  rocprim::double_buffer<int32_t> vb(nullptr, nullptr);
+  if (rocprim::radix_sort_pairs(nullptr, tb, kb, vb, static_cast<unsigned>(nnz > 0 ? nnz : 1), 0,
+                                key_bits(cols)) != hipSuccess)
+    tb = 0;
+  return 5 * align_up(static_cast<size_t>(nnz > 0 ? nnz : 1) * 4, 256) + align_up(tb, 256) + 256;
+}
+
+int launch_csr_transpose(const int32_t* rp, const int32_t* ci, const float* v, int64_t rows,
+                         int64_t cols, int64_t nnz, int32_t* trp, int32_t* tci, float* tv,
+                         int32_t* cursor, void* scratch, size_t scratch_bytes, hipStream_t s) {
+  // row pointers of A^T: column counts (order-free) and their scan
   launch_fill_i32(cursor, cols, 0, s);
   if (nnz > 0)
-    count_cols_kernel<<<static_cast<unsigned>(cdiv(nnz, 256)), 256, 0, s>>>(ci, nnz,
-                                                                           cursor);
+    count_cols_kernel<<<static_cast<unsigned>(cdiv(nnz, 256)), 256, 0, s>>>(ci, nnz, cursor);
   scan_kernel<<<1, 1024, 0, s>>>(cursor, cols, trp);
-  if (cols > 0)
-    copy_i32_kernel<<<static_cast<unsigned>(cdiv(cols, 256)), 256, 0, s>>>(trp, cursor,
-                                                                          cols);
-  if (rows > 0)
-    scatter_kernel<<<static_cast<unsigned>(cdiv(rows, 4)), 256, 0, s>>>(rp, ci, v, rows,
-                                                                       cursor, keys);
-  if (cols > 0)
-    sort_rows_kernel<<<static_cast<unsigned>(cols), 256, 0, s>>>(trp, cols, keys,
-                                                                keys + nnz, tci, tv);
+  if (nnz <= 0) return 0;
+  // entries: a stable radix sort of the column ids (A's entries come in row
+  // order, so each column's entries stay in row order), positions as payload
+  const size_t seg = align_up(static_cast<size_t>(nnz) * 4, 256);
+  char* b = static_cast<char*>(scratch);
+  int32_t* k0 = reinterpret_cast<int32_t*>(b);
+  int32_t* k1 = reinterpret_cast<int32_t*>(b + seg);
+  int32_t* v0 = reinterpret_cast<int32_t*>(b + 2 * seg);
+  int32_t* v1 = reinterpret_cast<int32_t*>(b + 3 * seg);
+  int32_t* rowid = reinterpret_cast<int32_t*>(b + 4 * seg);
+  void* tmp = b + 5 * seg;
+  size_t tb = scratch_bytes > 5 * seg ? scratch_bytes - 5 * seg : 0;
+  copy_keys_kernel<<<static_cast<unsigned>(cdiv(nnz, 256)), 256, 0, s>>>(ci, nnz, k0);
+  expand_rows_kernel<<<static_cast<unsigned>(cdiv(rows, 4)), 256, 0, s>>>(rp, rows, rowid, v0);
+  rocprim::double_buffer<int32_t> kb(k0, k1);
+  rocprim::double_buffer<int32_t> vb(v0, v1);
+  size_t need = 0;
+  if (rocprim::radix_sort_pairs(nullptr, need, kb, vb, static_cast<unsigned>(nnz), 0,
+                                key_bits(cols), s) != hipSuccess ||
+      need > tb)
+    return -1;
+  if (rocprim::radix_sort_pairs(tmp, need, kb, vb, static_cast<unsigned>(nnz), 0, key_bits(cols),
+                                s) != hipSuccess)
+    return -1;
+  gather_t_kernel<<<static_cast<unsigned>(cdiv(nnz, 256)), 256, 0, s>>>(vb.current(), nnz,
+                                                                       rowid, v, tci, tv);
+  return 0;
 }
 
 }  // namespace bk

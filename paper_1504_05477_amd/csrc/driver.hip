@@ -195,7 +195,8 @@ struct Layout {
   CsrPlan plan_a, plan_t;       // work plans of A and A^T (shared part)
   double* colpart = nullptr;    // kColsumBlocks x k block sums of the centring
   float* tv = nullptr;
-  unsigned long long* keys = nullptr;
+  char* tscratch = nullptr;  // CSR transpose: sort buffers
+  size_t tscratch_bytes = 0;
   float* mu = nullptr;
   double* colvec = nullptr;
   size_t bytes = 0;
@@ -269,7 +270,8 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
       L.tci = ar.take<int32_t>(static_cast<size_t>(nnz));
       L.tv = ar.take<float>(static_cast<size_t>(nnz));
       L.cursor = ar.take<int32_t>(static_cast<size_t>(d));
-      L.keys = ar.take<unsigned long long>(static_cast<size_t>(3 * nnz));
+      L.tscratch_bytes = csr_transpose_scratch_bytes(nnz, d);
+      L.tscratch = ar.take<char>(L.tscratch_bytes);
     }
     const int64_t pmax = csr_max_pieces(nnz, std::max(n, d));
     float* part = ar.take<float>(static_cast<size_t>(pmax) * static_cast<size_t>(k));
@@ -1308,8 +1310,9 @@ int csr_prepare_and_run(const int32_t* row_ptr, const int32_t* col_idx, const fl
   const int32_t* tci = t_col_idx;
   const float* tv = t_vals;
   if (!given_t) {
-    launch_csr_transpose(row_ptr, col_idx, vals, n, d, nnz, L.trp, L.tci, L.tv, L.cursor,
-                         L.keys, s);
+    if (launch_csr_transpose(row_ptr, col_idx, vals, n, d, nnz, L.trp, L.tci, L.tv, L.cursor,
+                             L.tscratch, L.tscratch_bytes, s) != 0)
+      return BK_EHIP;
     trp = L.trp;
     tci = L.tci;
     tv = L.tv;
@@ -1939,7 +1942,7 @@ int bk_csr_product(const int32_t* row_ptr, const int32_t* col_idx, const float* 
 size_t bk_csr_transpose_workspace(int64_t rows, int64_t cols, int64_t nnz) {
   (void)rows;
   if (cols < 0 || nnz < 0) return 0;
-  return align_up(static_cast<size_t>(cols) * 4, 256) + static_cast<size_t>(3 * nnz) * 8 +
+  return align_up(static_cast<size_t>(cols) * 4, 256) + csr_transpose_scratch_bytes(nnz, cols) +
          align_up(sizeof(Ctrl), 256) + 256;
 }
 
@@ -1962,8 +1965,9 @@ int bk_csr_transpose(const int32_t* row_ptr, const int32_t* col_idx, const float
   }
   int32_t* cursor = reinterpret_cast<int32_t*>(base);
   const size_t koff = align_up(static_cast<size_t>(cols) * 4, 256);
-  unsigned long long* keys = reinterpret_cast<unsigned long long*>(base + koff);
-  Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + koff + static_cast<size_t>(3 * nnz) * 8);
+  const size_t sb = csr_transpose_scratch_bytes(nnz, cols);
+  char* scratch = base + koff;
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(base + koff + sb);
   // the structure is checked before the transpose indexes through it
   launch_ctrl_init(ctrl, 0, s);
   launch_csr_validate(row_ptr, col_idx, rows, cols, nnz, ctrl, s);
@@ -1971,8 +1975,9 @@ int bk_csr_transpose(const int32_t* row_ptr, const int32_t* col_idx, const float
   BK_TRY(hipMemcpyAsync(&h, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   BK_TRY(hipStreamSynchronize(s));
   if (h.csr_bad) return BK_EINVAL;
-  launch_csr_transpose(row_ptr, col_idx, vals, rows, cols, nnz, t_row_ptr, t_col_idx, t_vals,
-                       cursor, keys, s);
+  if (launch_csr_transpose(row_ptr, col_idx, vals, rows, cols, nnz, t_row_ptr, t_col_idx,
+                           t_vals, cursor, scratch, sb, s) != 0)
+    return BK_EHIP;
   BK_TRY_LAUNCH();
   return BK_OK;
 }

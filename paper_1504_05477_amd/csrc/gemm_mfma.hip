@@ -1513,13 +1513,11 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
   }
   const int S = tn_mfma_splits(a.L, a.p, a.r);
   const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
-  // FP32 on the FP32 matrix cores: below two workgroups per CU the vector
-  // kernel is faster (e.g. a 256 x 256 Gram over 131072 rows: 390 us
-  // against 660 us); as BF16 limbs from half a workgroup per CU on
-  const bool limbs = !packed && !a.fp32_cores && a.work &&
-                     static_cast<int64_t>(a.work_bytes) >= x3_pack_bytes(a.L, a.r);
-  const int64_t wgs = cdiv(a.p, 128) * cdiv(a.r, 128) * S;
-  if (!packed && wgs < (limbs ? 128 : 512)) return;
+  // FP32: below two workgroups per CU the vector kernel is faster (a 256 x
+  // 256 Gram over 131072 rows: 390 us against 660 us on the FP32 matrix
+  // cores and 486 us as BF16 limbs, whose limb packing of Y alone writes
+  // 200 MB there)
+  if (!packed && cdiv(a.p, 128) * cdiv(a.r, 128) * S < 512) return;
   switch (a.x_type) {
     case BK_F32:
       tn_run<float, false>(a, S, Ls, s);

@@ -329,12 +329,14 @@ void launch_colsum_final(const double* colpart, int nb, int k, double* colvec, h
 void launch_scan_i32(const int32_t* cnt, int64_t n, int32_t* out, hipStream_t s);
 void launch_csr_row_means(const int32_t* rp, const float* v, int64_t rows,
                           int64_t cols, float* mu, hipStream_t s);
-// CSR transpose: counts -> scan -> atomic scatter -> per-row sort.
-void launch_csr_transpose(const int32_t* rp, const int32_t* ci,
-                          const float* v, int64_t rows, int64_t cols,
-                          int64_t nnz, int32_t* trp, int32_t* tci, float* tv,
-                          int32_t* cursor, unsigned long long* keys,
-                          hipStream_t s);
+// CSR transpose: column counts -> scan -> stable radix sort of the column ids
+// (positions as payload) -> gather.  cursor: cols ints; scratch:
+// csr_transpose_scratch_bytes(nnz, cols).  Returns 0, or -1 when the sort
+// could not run (scratch too small / a HIP error).
+size_t csr_transpose_scratch_bytes(int64_t nnz, int64_t cols);
+int launch_csr_transpose(const int32_t* rp, const int32_t* ci, const float* v, int64_t rows,
+                         int64_t cols, int64_t nnz, int32_t* trp, int32_t* tci, float* tv,
+                         int32_t* cursor, void* scratch, size_t scratch_bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- quant --
 // Transposed copy (d x n, ld n) with the codes of the copies below; FP8

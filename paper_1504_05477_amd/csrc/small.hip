@@ -508,50 +508,32 @@ __global__ __launch_bounds__(256) void cholm_rank_kernel(int k, const double* __
 }
 
 // Diagonal block p: one wavefront factors S_pp (32 x 32, trailing updates
-// applied) and inverts it: R_pp into R, R_pp^-1 into Rinv.  Lane c holds
-// column c in registers; each step broadcasts row j through LDS (one write
-// per lane, reads of the same address by every lane), and the inverse runs
+// applied) in registers (chol_regs: lane c holds column c, rows posted to
+// LDS one step ahead, 1 / sqrt(pivot) from the hardware estimate and two
+// Newton steps) and inverts it: R_pp into R, R_pp^-1 into Rinv, the inverse
 // by back substitution, a column per lane, over R_pp staged in LDS.
 __global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const double* __restrict__ S,
                                                         double* __restrict__ R,
                                                         double* __restrict__ Rinv,
                                                         CholMState* st) {
-  __shared__ double row[CM];
+  __shared__ double rb[2 * 64];
   __shared__ double Rs[CM][CM + 1];
   __shared__ double rdiag[CM];
   if (st->decision || st->fail) return;
   const int c = threadIdx.x;  // lanes 0..31: columns; 32..63 idle but in step
   const int bs = (k - o < CM) ? k - o : CM;
-  const bool col = c < CM;
-  double a[CM];
+  double g[CM];
 #pragma unroll
   for (int r = 0; r < CM; ++r)
-    a[r] = (c < bs) ? ((r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0)
-                    : (r == c ? 1.0 : 0.0);
-  bool ok = true;
-  double mp = INFINITY;
+    g[r] = (c < bs && r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0;
+  double a[CM], rinv[CM], mp;
+  const bool ok = chol_regs<CM>(bs, g, 0.0, a, rinv, mp, rb);
+  if (c < CM) {
 #pragma unroll
-  for (int j = 0; j < CM; ++j) {
-    if (col) row[c] = a[j];
-    __syncthreads();
-    double d = row[j];
-    if (!(d > 0.0) || !isfinite(d)) {
-      ok = false;
-      d = 1.0;
+    for (int r = 0; r < CM; ++r) {
+      Rs[r][c] = a[r];
+      if (r == c) rdiag[c] = rinv[r];  // (static register index)
     }
-    const double rd = sqrt(d);
-    const double inv = 1.0 / rd;
-    if (j < bs) mp = fmin(mp, rd);
-    const double rjc = (c == j) ? rd : a[j] * inv;  // R[j][c]
-    a[j] = rjc;
-#pragma unroll
-    for (int r = j + 1; r < CM; ++r) a[r] -= (row[r] * inv) * rjc;
-    __syncthreads();
-  }
-  if (col) {
-#pragma unroll
-    for (int r = 0; r < CM; ++r) Rs[r][c] = a[r];
-    rdiag[c] = 1.0 / a[c];
   }
   __syncthreads();
   // x = column c of R_pp^-1: x_i = (delta_ic - sum_{l > i} R_il x_l) / R_ii

@@ -755,6 +755,85 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
   }
 }
 
+// The same back-transformation for large m with the rows of a column spread
+// over a workgroup of 256 threads (row t + 256 u in lane t, u < VR) and CPW
+// columns per workgroup sharing each reflector's loads: short per-lane rows
+// leave registers for AH reflectors in flight (one reflector's loads cost a
+// memory latency, the per-reflector work a few hundred cycles).  The dot
+// products: wave sums, then the four wavefronts' partials through LDS (two
+// alternating slots, one barrier per reflector).
+template <int VR, int CPW>
+__global__ __launch_bounds__(256) void tridiag_back_wg_kernel(
+    const double* __restrict__ Vh, const double* __restrict__ beta, int64_t m, int k,
+    const double* __restrict__ X, double* __restrict__ Uk, int64_t ldu,
+    const double* __restrict__ theta, double* __restrict__ ritz) {
+  constexpr int AH = 4;
+  __shared__ double part[2][4][CPW];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int c0 = blockIdx.x * CPW;
+  if (ritz && t < CPW && c0 + t < k) ritz[c0 + t] = sqrt(fmax(theta[c0 + t], 0.0));
+  double xr[CPW][VR];
+#pragma unroll
+  for (int cc = 0; cc < CPW; ++cc)
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int64_t i = t + 256 * u;
+      xr[cc][u] = (c0 + cc < k && i < m) ? X[static_cast<int64_t>(c0 + cc) * m + i] : 0.0;
+    }
+  double vq[AH][VR], bq[AH];
+  auto fetch = [&](int64_t jj, double (&vv)[VR], double& bb) {
+    bb = jj >= 0 ? beta[jj] : 0.0;
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int64_t i = t + 256 * u;
+      vv[u] = (jj >= 0 && i > jj && i < m) ? Vh[jj * m + i] : 0.0;
+    }
+  };
+  int slot = 0;
+  auto apply = [&](const double (&vv)[VR], double bb) {
+    double dot[CPW];
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc) {
+      double d = 0.0;
+#pragma unroll
+      for (int u = 0; u < VR; ++u) d += vv[u] * xr[cc][u];
+      d = wave_sum(d);
+      dot[cc] = d;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int cc = 0; cc < CPW; ++cc) part[slot][wv][cc] = dot[cc];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < CPW; ++cc) {
+      const double f =
+          bb * (((part[slot][0][cc] + part[slot][1][cc]) + part[slot][2][cc]) + part[slot][3][cc]);
+#pragma unroll
+      for (int u = 0; u < VR; ++u) xr[cc][u] -= f * vv[u];
+    }
+    slot ^= 1;  // the next reflector writes the other slot (no second barrier)
+  };
+  // reflectors j = m - 3 down to 0; slot q holds j = m - 3 - (step mod AH)
+#pragma unroll
+  for (int q = 0; q < AH; ++q) fetch(m - 3 - q, vq[q], bq[q]);
+  for (int64_t j0 = m - 3; j0 >= 0; j0 -= AH) {
+#pragma unroll
+    for (int q = 0; q < AH; ++q) {
+      const int64_t j = j0 - q;
+      if (j >= 0) apply(vq[q], bq[q]);  // (uniform)
+      fetch(j - AH, vq[q], bq[q]);
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < CPW; ++cc)
+#pragma unroll
+    for (int u = 0; u < VR; ++u) {
+      const int64_t i = t + 256 * u;
+      if (c0 + cc < k && i < m) Uk[i * ldu + c0 + cc] = xr[cc][u];
+    }
+}
+
 // ------------------------------------------------- large m (> TRI_SMALL) --
 // The same reduction with the trailing block in global memory and the work
 // of a step spread over the chip, in three launches per step:
@@ -926,21 +1005,23 @@ __global__ __launch_bounds__(TBG_COLS) void tribig_update_kernel(
 // One grid barrier per step.  p and the published row alternate between two
 // buffers by step parity: no workgroup gets more than a phase ahead of
 // another.  Everything one workgroup hands to another (p, the row, the
-// barrier count) goes through device-scope relaxed atomic loads and stores,
+// barrier flags) goes through device-scope relaxed atomic loads and stores,
 // which are coherent across the XCDs' L2 caches by themselves, so the
 // barrier needs no cache write-back or invalidation: each thread waits for
-// its own stores to complete before the workgroup arrives.  The count only
-// grows; the wait gives up after TCO_SPIN polls (a co-resident grid never
-// needs that many), sets `stall` and stops waiting at every later barrier,
-// so the launch always ends.
+// its own stores to complete before its workgroup posts its flag.  Each
+// workgroup has a flag of its own (no contended atomic); a wait gives up
+// after TCO_SPIN polls (a co-resident grid never needs that many), sets
+// `stall` and stops waiting at every later barrier, so the launch always
+// ends.
 constexpr int TCO_THREADS = 1024;
 constexpr int TCO_E = 3;     // columns per thread: m <= 3072
 constexpr int TCO_RL = 10;   // rows per workgroup: m <= 10 G
 constexpr unsigned TCO_SPIN = 1u << 22;
 
 struct TcoSync {
-  unsigned count;
   int stall;
+  int pad;
+  unsigned flag[256];  // per workgroup: the last step it finished (G <= 256)
 };
 
 __device__ __forceinline__ void tco_put(double* p, double v) {
@@ -950,17 +1031,21 @@ __device__ __forceinline__ double tco_get(const double* p) {
   return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void tco_grid_sync(TcoSync* sy, unsigned target) {
-  // this thread's stores complete (vmcnt counts stores on this target),
-  // then the workgroup arrives
+// Grid barrier of step `step` (>= 1): every thread's stores complete (vmcnt
+// counts stores on this target), then the workgroup posts its own flag; one
+// thread per workgroup polls each flag (flags only grow, so nothing is
+// reset, and no two workgroups write one address).
+__device__ __forceinline__ void tco_grid_sync(TcoSync* sy, unsigned step) {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0xF70);  // vmcnt(0)
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(&sy->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&sy->flag[blockIdx.x], step, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < gridDim.x) {
     unsigned polls = 0;
-    while (__hip_atomic_load(&sy->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(&sy->flag[threadIdx.x], __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT) < step) {
       if (__hip_atomic_load(&sy->stall, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
       if (++polls > TCO_SPIN) {
         __hip_atomic_store(&sy->stall, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -974,8 +1059,11 @@ __device__ __forceinline__ void tco_grid_sync(TcoSync* sy, unsigned target) {
 }
 
 __global__ void tco_init_kernel(TcoSync* sy) {
-  sy->count = 0u;
-  sy->stall = 0;
+  if (threadIdx.x == 0) {
+    sy->stall = 0;
+    sy->pad = 0;
+  }
+  sy->flag[threadIdx.x] = 0u;
 }
 
 __global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
@@ -1089,7 +1177,7 @@ __global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
       }
     }
     // (3)
-    tco_grid_sync(sy, static_cast<unsigned>(G) * static_cast<unsigned>(j + 1));
+    tco_grid_sync(sy, static_cast<unsigned>(j + 1));
     // (4) p on own columns, K, the next pending update, the next row
     double pl[TCO_E];
     double vp = 0.0;
@@ -1197,7 +1285,7 @@ int64_t tridiag_scratch_doubles(int64_t m, int k) {
          (static_cast<int64_t>(k) * m + 1) / 2 + 3 * m + groups * m + 2 * TRI_NB * m + 64 +
          static_cast<int64_t>(k) * m + 3 * kk + chol_work_doubles(k) + 8 +
          m + cdiv(m, 256) + 64 +  // p and the v^T p partials of the large-m steps
-         4 * m + 8;               // the cooperative grid's p, row and barrier
+         4 * m + 136;             // the cooperative grid's p, row and barrier flags
 }
 
 namespace {
@@ -1291,11 +1379,11 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     }
     tridiag_reduce_kernel<<<1, TRI_THREADS, (3 * m + (m - j) * (m - j)) * sizeof(double), s>>>(
         A, m, j, Vh, beta, dg, eo);
-  } else if (const int Gc = tco_grid(s);
+  } else if (const int Gc = std::min(tco_grid(s), 256);
              Gc > 0 && m <= static_cast<int64_t>(TCO_E) * TCO_THREADS &&
              m <= static_cast<int64_t>(TCO_RL) * Gc &&
              [&] {
-               tco_init_kernel<<<1, 1, 0, s>>>(csy);
+               tco_init_kernel<<<1, 256, 0, s>>>(csy);
                const double* a0 = A;
                void* args[] = {&a0, &m, &Vh, &beta, &dg, &eo, &cpb, &crb, &csy};
                if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(tri_coop_kernel),
@@ -1353,12 +1441,12 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     tridiag_back_kernel<4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
   else if (m <= 512)
     tridiag_back_kernel<8><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
-  else if (m <= 1024)
-    tridiag_back_kernel<16><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else if (m <= 1024)  // a workgroup per 4 columns, rows spread over it
+    tridiag_back_wg_kernel<4, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
   else if (m <= 2048)
-    tridiag_back_kernel<32><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
-  else  // m <= kTridiagMax = 64 * 40
-    tridiag_back_kernel<40><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+    tridiag_back_wg_kernel<8, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else  // m <= kTridiagMax = 256 * 10
+    tridiag_back_wg_kernel<10, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
 }
 
 }  // namespace bk
