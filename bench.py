@@ -200,6 +200,9 @@ def main():
     ap.add_argument("--fp32-products", default="limbs", choices=["limbs", "cores"],
                     help="FP32 block products as three BF16 limbs on the BF16 matrix cores "
                          "(limbs) or on the FP32 matrix cores (cores)")
+    ap.add_argument("--csr-gather", default="default", choices=["default", "inplace", "staged"],
+                    help="CSR workloads: gather the right-hand block's rows from the Krylov "
+                         "block (inplace) or from a copy with 128-byte-aligned rows (staged)")
     ap.add_argument("--lowp-layout", default="both", choices=["both", "rows"],
                     help="low-precision leg: also hold the copy transposed, so that the "
                          "A^T Y products read it row by row (both), or A only (rows)")
@@ -297,7 +300,8 @@ def run_csr(args, w, bk, torch):
     def step(timing):
         return bk.svd_csr(g_rp, g_ci, g_va, w.n, w.d, k, q, seed=w.seed_sketch,
                           center=w.center, transpose=tr, timing=timing,
-                          method=args.method, block_size=args.block_size)
+                          method=args.method, block_size=args.block_size,
+                          csr_gather=args.csr_gather)
 
     leg = timed_leg(step, args.steps, args.warmup)
     if args.breakdown:
@@ -309,11 +313,12 @@ def run_csr(args, w, bk, torch):
     per_launch = bx if dom == "ax" else by
     achieved = per_launch / (avg_ms * 1e-3) / 1e9
     sha = source_sha(["csr.hip"])
-    kernel_key = f"csr_product_{dom}_{args.workload}"
+    gather = "staged" if args.csr_gather == "staged" else "inplace"
+    kernel_key = f"csr_product_{dom}_{args.workload}" + ("_staged" if gather == "staged" else "")
     names = {"ax": "csr_product_kernel (A.X, CSR of A)",
              "aty": "csr_product_kernel (A^T.Y, CSR of A^T)"}
     out = base_record(args, w, value, "GB/s", leg["ms"], "f32",
-                      {"product_bytes_per_solve": int(bytes_per_solve)})
+                      {"product_bytes_per_solve": int(bytes_per_solve), "csr_gather": gather})
     out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                        "traffic": read_traffic(kernel_key, sha), "kernel": names[dom],

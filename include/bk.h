@@ -153,10 +153,21 @@ typedef struct bk_options {
                                 2^-23 |a b| per product beyond FP32
                                 summation); 1: on the FP32 matrix cores
                                 (32 x 32 x 2 steps).                     */
-  int32_t reserved2;
+  int32_t csr_gather;        /* CSR path: where the sparse products
+                                (Theorem 6's nnz(A) k term) gather the rows
+                                of their right-hand block from.
+                                BK_CSR_GATHER_INPLACE (1): from the
+                                Krylov block itself (rows (q+1) p
+                                floats apart); BK_CSR_GATHER_STAGED (2):
+                                from a copy whose rows start on their own
+                                128-byte lines (p rounded up to 32 floats;
+                                + (n + d) that many floats of workspace);
+                                0: the library's choice (in place).  Same
+                                sums in the same order either way.        */
 } bk_options;
 
 enum { BK_METHOD_BLOCK_KRYLOV = 0, BK_METHOD_SIMULTANEOUS = 1, BK_METHOD_BLOCK_LANCZOS = 2 };
+enum { BK_CSR_GATHER_DEFAULT = 0, BK_CSR_GATHER_INPLACE = 1, BK_CSR_GATHER_STAGED = 2 };
 
 /* Phases of bk_info.ms[] / launches[]. */
 enum {
@@ -170,7 +181,8 @@ enum {
   BK_PH_Z = 7,       /* Z = Q U_k, sign normalisation                  */
   BK_PH_REFINE = 8,  /* FP32 correction pass                           */
   BK_PH_PREP = 9,    /* CSR validation / transpose / work plans        */
-  BK_PH_CENTER = 10, /* centring vectors 1^T X and mu^T Y (CSR)        */
+  BK_PH_CENTER = 10, /* CSR operands: centring vectors 1^T X and mu^T Y,
+                        staged gather copies (csr_gather)              */
   BK_PH_LONG = 11,   /* CSR: combine of rows cut into several pieces  */
   BK_NPHASE = 12
 };

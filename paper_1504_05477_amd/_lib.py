@@ -36,7 +36,7 @@ class Options(C.Structure):
         ("ld_at", C.c_int64),
         ("at_scales", C.c_void_p),
         ("fp32_products", C.c_int32),
-        ("reserved2", C.c_int32),
+        ("csr_gather", C.c_int32),
     ]
 
 

@@ -49,7 +49,8 @@ _METHODS = {"bki": 0, "block_krylov": 0, "si": 1, "simultaneous": 1, "lanczos": 
 def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
              breakdown_tol=0.0, pi=None, timing=False, save=False,
              jacobi_block=0, block_size=0, method="bki", residuals=None,
-             A_t=None, at_scales=None, fp32_products="limbs") -> L.Options:
+             A_t=None, at_scales=None, fp32_products="limbs",
+             csr_gather="default") -> L.Options:
     """timing: False, True (every phase) or an iterable of phase names from
     _lib.PHASES (only those get events; launch counts are kept for all)."""
     o = L.Options()
@@ -83,6 +84,10 @@ def _options(*, refine=0, center=False, max_sweeps=0, jacobi_tol=0.0,
     if fp32_products not in ("limbs", "cores"):
         raise ValueError("fp32_products must be 'limbs' or 'cores'")
     o.fp32_products = 1 if fp32_products == "cores" else 0
+    gathers = {"default": 0, "inplace": 1, "staged": 2}
+    if csr_gather not in gathers:
+        raise ValueError(f"csr_gather must be one of {sorted(gathers)}")
+    o.csr_gather = gathers[csr_gather]
     return o
 
 
@@ -217,11 +222,14 @@ class BKSVD(torch.autograd.Function):
 def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 0, *,
             transpose=None, center=False, pi=None, timing=False, max_sweeps=0,
             jacobi_tol=0.0, breakdown_tol=0.0, jacobi_block=0, block_size=0,
-            method="bki", residuals=False, stream=None) -> SVDResult:
+            method="bki", residuals=False, csr_gather="default",
+            stream=None) -> SVDResult:
     """Block Krylov Iteration on a CSR A (int32 row_ptr / col_idx, float32
     values, on the GPU).  ``transpose`` = (t_row_ptr, t_col_idx, t_vals) of A^T
     is optional; ``center`` applies implicit row centring; ``residuals`` as
-    svd_dense (of the centred matrix with ``center``; needs block_size k)."""
+    svd_dense (of the centred matrix with ``center``; needs block_size k);
+    ``csr_gather``: "inplace" (gathers from the Krylov block), "staged" (from
+    a copy with 128-byte-aligned rows) or "default"."""
     lib = L.load()
     _need_cuda(row_ptr, col_idx, vals, pi)
     for t, dt in ((row_ptr, torch.int32), (col_idx, torch.int32), (vals, torch.float32)):
@@ -236,7 +244,7 @@ def svd_csr(row_ptr, col_idx, vals, n: int, d: int, k: int, q: int, seed: int = 
     opt = _options(center=center, pi=pi, timing=timing, max_sweeps=max_sweeps,
                    jacobi_tol=jacobi_tol, breakdown_tol=breakdown_tol,
                    jacobi_block=jacobi_block, block_size=block_size, method=method,
-                   residuals=res_t)
+                   residuals=res_t, csr_gather=csr_gather)
     nbytes = lib.bk_svd_csr_workspace(n, d, nnz, k, q, C.byref(opt))
     if nbytes == 0:
         raise ValueError(f"invalid shape/rank: n={n} d={d} k={k} q={q}")

@@ -32,58 +32,128 @@ __global__ __launch_bounds__(256) void csr_validate_kernel(const int32_t* rp,
 // SLOTS = 64 / KC slots of KC lanes (KC = min(k, 64)); lane c of a slot owns
 // output column c0 + c.  A slot walks a run of nonzeros in chunks of KC: the
 // chunk's (column id, value) pairs are loaded with one coalesced access (one
-// per lane, next chunk prefetched), then broadcast inside the slot with
-// shuffles while eight independent X-row gathers are in flight.
+// per lane, next chunk prefetched).  BATCH (products whose short rows
+// average 16 or more nonzeros, so that most chunks fill a batch):
+// the pairs are posted to the wavefront's LDS area (slot s at s * KCP, KCP =
+// KC rounded up to 4), every lane of the slot reads them back four at a
+// time, and the X-row gathers go out 32 at a time with no branch between
+// them: entries past the chunk gather nothing (XBUF: an out-of-range buffer
+// offset, which reads zero without a memory access; otherwise row 0,
+// selected away) and add exact zeros, so the products are added in index
+// order as by a plain loop -- one round trip to the cache per 32
+// nonzeros.  Otherwise (short runs) the gathers are issued 16, 8, then one
+// at a time: more round trips, but the number of gather instructions, which
+// bounds these kernels through the texture address unit, stays at the run
+// length.  Both add the same products in the same order.
+constexpr int kSlotLds = 288;  // LDS entries per wavefront (>= (SLOTS - 1) KCP + 32)
+
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool XBUF, bool BATCH>
 __device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
                                           const float* __restrict__ v,
                                           const float* __restrict__ X, int64_t ldx,
-                                          int32_t b, int32_t e, int32_t step, int KC,
-                                          int base, int c, int col, bool colok,
-                                          int32_t nci, float nv) {
+                                          uint32_t xbytes, int32_t b, int32_t e, int32_t step,
+                                          int KC, int base, int lbase, int c, int col,
+                                          bool colok, int32_t nci, float nv, int32_t* lci,
+                                          float* lv) {
   float acc = 0.0f;
+  if constexpr (!BATCH) {
+    // runs that mostly stop short of 32: the chunk's pairs broadcast by
+    // shuffles, gathers in batches of 16, then 8, then one at a time (a
+    // round trip each, but no gather instruction past the run)
+    for (int32_t j0 = b; j0 < e; j0 += step) {
+      const int32_t myci = nci;
+      const float myv = nv;
+      const int cnt = (e - j0 < KC) ? (e - j0) : KC;
+      const int32_t jn = j0 + step + c;
+      nci = (jn < e) ? ci[jn] : 0;
+      nv = (jn < e) ? v[jn] : 0.0f;
+      int t = 0;
+      for (; t + 16 <= cnt; t += 16) {
+        int32_t cc[16];
+        float vv[16], xx[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          cc[u] = __shfl(myci, base + t + u);
+          vv[u] = __shfl(myv, base + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc += vv[u] * xx[u];
+      }
+      if (t + 8 <= cnt) {
+        int32_t cc[8];
+        float vv[8], xx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          cc[u] = __shfl(myci, base + t + u);
+          vv[u] = __shfl(myv, base + t + u);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += vv[u] * xx[u];
+        t += 8;
+      }
+      for (; t < cnt; ++t) {
+        const int32_t c1 = __shfl(myci, base + t);
+        const float v1 = __shfl(myv, base + t);
+        const float x1 = colok ? X[static_cast<int64_t>(c1) * ldx + col] : 0.0f;
+        acc += v1 * x1;
+      }
+    }
+    return acc;
+  }
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(X), 0, static_cast<int>(xbytes),
+                                        0x00020000);
+  const uint32_t cofs = static_cast<uint32_t>(colok ? col : 0) * 4u;
   for (int32_t j0 = b; j0 < e; j0 += step) {
-    const int32_t myci = nci;
-    const float myv = nv;
     const int cnt = (e - j0 < KC) ? (e - j0) : KC;
+    wave_lds_order();  // (the previous chunk's reads come first)
+    lci[lbase + c] = nci;
+    lv[lbase + c] = nv;
+    wave_lds_order();
     const int32_t jn = j0 + step + c;
     nci = (jn < e) ? ci[jn] : 0;
     nv = (jn < e) ? v[jn] : 0.0f;
-    // gathers in batches of 16 in flight (a round trip each)
-    int t = 0;
-    for (; t + 16 <= cnt; t += 16) {
-      int32_t cc[16];
-      float vv[16], xx[16];
+    for (int t = 0; t < cnt; t += 32) {
+      int4 c4[8];
+      float4 v4[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        cc[u] = __shfl(myci, base + t + u);
-        vv[u] = __shfl(myv, base + t + u);
+      for (int q = 0; q < 8; ++q) {
+        c4[q] = *reinterpret_cast<const int4*>(lci + lbase + t + 4 * q);
+        v4[q] = *reinterpret_cast<const float4*>(lv + lbase + t + 4 * q);
       }
+      float xx[32], vv[32];
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc += vv[u] * xx[u];
-    }
-    if (t + 8 <= cnt) {
-      int32_t cc[8];
-      float vv[8], xx[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        cc[u] = __shfl(myci, base + t + u);
-        vv[u] = __shfl(myv, base + t + u);
+      for (int u = 0; u < 32; ++u) {
+        const int q = u >> 2, w = u & 3;
+        const int32_t cu = w == 0 ? c4[q].x : w == 1 ? c4[q].y : w == 2 ? c4[q].z : c4[q].w;
+        const float vu = w == 0 ? v4[q].x : w == 1 ? v4[q].y : w == 2 ? v4[q].z : v4[q].w;
+        const bool in = t + u < cnt && colok;
+        vv[u] = in ? vu : 0.0f;
+        if constexpr (XBUF) {
+          const uint32_t off = in ? static_cast<uint32_t>(cu) * static_cast<uint32_t>(ldx) * 4u + cofs
+                                  : 0xFFFFFFF0u;
+          xx[u] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+        } else {
+          const int64_t row = in ? cu : 0;
+          xx[u] = X[row * ldx + (colok ? col : 0)];
+          xx[u] = in ? xx[u] : 0.0f;
+        }
       }
+      __builtin_amdgcn_sched_barrier(0);  // (all 32 gathers out before the first sum)
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        xx[u] = colok ? X[static_cast<int64_t>(cc[u]) * ldx + col] : 0.0f;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc += vv[u] * xx[u];
-      t += 8;
-    }
-    for (; t < cnt; ++t) {
-      const int32_t c1 = __shfl(myci, base + t);
-      const float v1 = __shfl(myv, base + t);
-      const float x1 = colok ? X[static_cast<int64_t>(c1) * ldx + col] : 0.0f;
-      acc += v1 * x1;
+      for (int u = 0; u < 32; ++u) acc += vv[u] * xx[u];
     }
   }
   return acc;
@@ -91,14 +161,19 @@ __device__ __forceinline__ float slot_run(const int32_t* __restrict__ ci,
 
 // Rows of at most short_thr nonzeros: one slot per row (SLOTS rows per
 // wavefront).  Longer rows are left to the piece kernels.
+template <bool XBUF, bool BATCH>
 __global__ __launch_bounds__(256) void csr_spmm_kernel(
     int64_t rows, int k, int KC, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ ci, const float* __restrict__ v,
-    const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
+    const float* __restrict__ X, int64_t ldx, uint32_t xbytes, float* __restrict__ Y, int64_t ldy,
     const float* __restrict__ rowvec, const double* __restrict__ colvec,
     int short_thr) {
-  const int SLOTS = 64 / KC;
+  __shared__ __align__(16) int32_t s_ci[4 * kSlotLds];
+  __shared__ __align__(16) float s_v[4 * kSlotLds];
+  const int SLOTS = 64 / KC, KCP = (KC + 3) & ~3;
   const int64_t wave = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  int32_t* lci = s_ci + (threadIdx.x >> 6) * kSlotLds;
+  float* lv = s_v + (threadIdx.x >> 6) * kSlotLds;
   const int lane = threadIdx.x & 63;
   const int s = lane / KC, c = lane - s * KC;
   const int64_t row = wave * SLOTS + s;
@@ -116,8 +191,9 @@ __global__ __launch_bounds__(256) void csr_spmm_kernel(
     const int col = c0 + c;
     const bool colok = valid && col < k;
     const int32_t j0 = beg + c;
-    float acc = slot_run(ci, v, X, ldx, beg, end, KC, KC, s * KC, c, col, colok,
-                         (j0 < end && c < KC) ? ci[j0] : 0, (j0 < end && c < KC) ? v[j0] : 0.0f);
+    float acc = slot_run<XBUF, BATCH>(ci, v, X, ldx, xbytes, beg, end, KC, KC, s * KC, s * KCP, c,
+                                      col, colok, (j0 < end && c < KC) ? ci[j0] : 0,
+                                      (j0 < end && c < KC) ? v[j0] : 0.0f, lci, lv);
     if (own && col < k) {
       if (colvec) acc -= rv * static_cast<float>(colvec[col]);
       Y[row * ldy + col] = acc;
@@ -244,20 +320,26 @@ __global__ __launch_bounds__(256) void csr_plan_write_kernel(
 // nsw + p takes piece p: its slots walk interleaved chunks of the piece and
 // are added in slot order.  A single-piece row is written at once; the sums
 // of a row cut into several pieces go to part[p] and are added by
-// csr_combine_kernel.  OPERAND (0: A, 1: A^T) only names the instance, so
+// csr_combine_kernel.  Y2 (nullable, ld ldy2) receives a second copy of
+// every finished row.  OPERAND (0: A, 1: A^T) only names the instance, so
 // that profiles tell the two products apart.
-template <int OPERAND>
+template <int OPERAND, bool XBUF, bool BATCH>
 __global__ __launch_bounds__(256) void csr_product_kernel(
     int k, int KC, int RPS, int piece, int nshort, int npieces,
     const int32_t* __restrict__ short_rows,
     const int32_t* __restrict__ piece_row, const int32_t* __restrict__ piece_first,
     float* __restrict__ part, const int32_t* __restrict__ rp,
     const int32_t* __restrict__ ci, const float* __restrict__ v,
-    const float* __restrict__ X, int64_t ldx, float* __restrict__ Y, int64_t ldy,
-    const float* __restrict__ rowvec, const double* __restrict__ colvec) {
-  const int SLOTS = 64 / KC;
+    const float* __restrict__ X, int64_t ldx, uint32_t xbytes, float* __restrict__ Y,
+    int64_t ldy, float* __restrict__ Y2, int64_t ldy2, const float* __restrict__ rowvec,
+    const double* __restrict__ colvec) {
+  __shared__ __align__(16) int32_t s_ci[4 * kSlotLds];
+  __shared__ __align__(16) float s_v[4 * kSlotLds];
+  const int SLOTS = 64 / KC, KCP = (KC + 3) & ~3;
   const int nsw = (nshort + SLOTS * RPS - 1) / (SLOTS * RPS);
   const int w = static_cast<int>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  int32_t* lci = s_ci + (threadIdx.x >> 6) * kSlotLds;
+  float* lv = s_v + (threadIdx.x >> 6) * kSlotLds;
   const int lane = threadIdx.x & 63;
   const int s = lane / KC, c = lane - s * KC;
   if (w < nsw) {
@@ -293,11 +375,13 @@ __global__ __launch_bounds__(256) void csr_product_kernel(
       for (int c0 = 0; c0 < k; c0 += KC) {
         const int col = c0 + c;
         const bool colok = valid && col < k;
-        float acc = slot_run(ci, v, X, ldx, valid ? beg : 0, valid ? end : 0, KC, KC, base, c,
-                             col, colok, fci, fv);
+        float acc = slot_run<XBUF, BATCH>(ci, v, X, ldx, xbytes, valid ? beg : 0,
+                                                valid ? end : 0, KC, KC, base, s * KCP, c, col,
+                                                colok, fci, fv, lci, lv);
         if (colok) {
           if (colvec) acc -= rv * static_cast<float>(colvec[col]);
           Y[row * ldy + col] = acc;
+          if (Y2) Y2[row * ldy2 + col] = acc;
         }
       }
       beg = nbeg;
@@ -321,15 +405,16 @@ __global__ __launch_bounds__(256) void csr_product_kernel(
     const bool colok = s < SLOTS && col < k;
     const int32_t bs = (s < SLOTS) ? b + s * KC : e;
     const int32_t j0 = bs + c;
-    const float acc = slot_run(ci, v, X, ldx, bs, e, SLOTS * KC, KC, s * KC, c, col, colok,
-                               (j0 < e && c < KC) ? ci[j0] : 0,
-                               (j0 < e && c < KC) ? v[j0] : 0.0f);
+    const float acc = slot_run<XBUF, BATCH>(ci, v, X, ldx, xbytes, bs, e, SLOTS * KC, KC, s * KC,
+                                           s * KCP, c, col, colok, (j0 < e && c < KC) ? ci[j0] : 0,
+                                           (j0 < e && c < KC) ? v[j0] : 0.0f, lci, lv);
     float tot = 0.0f;
     for (int q = 0; q < SLOTS; ++q) tot += __shfl(acc, q * KC + c);
     if (s == 0 && col < k) {
       if (single) {
         if (colvec) tot -= rv * static_cast<float>(colvec[col]);
         Y[row * ldy + col] = tot;
+        if (Y2) Y2[row * ldy2 + col] = tot;
       } else {
         part[static_cast<int64_t>(p) * k + col] = tot;
       }
@@ -343,7 +428,8 @@ __global__ __launch_bounds__(256) void csr_combine_kernel(
     int nmulti, int k, int piece, const int32_t* __restrict__ multi_row,
     const int32_t* __restrict__ multi_first, const int32_t* __restrict__ rp,
     const float* __restrict__ part, float* __restrict__ Y, int64_t ldy,
-    const float* __restrict__ rowvec, const double* __restrict__ colvec) {
+    float* __restrict__ Y2, int64_t ldy2, const float* __restrict__ rowvec,
+    const double* __restrict__ colvec) {
   const int i = static_cast<int>(blockIdx.x) * 4 + (threadIdx.x >> 6);
   if (i >= nmulti) return;
   const int lane = threadIdx.x & 63;
@@ -365,7 +451,28 @@ __global__ __launch_bounds__(256) void csr_combine_kernel(
     for (; j < npc; ++j) acc += pp[static_cast<int64_t>(j) * k];
     if (colvec) acc -= rv * static_cast<float>(colvec[col]);
     Y[row * ldy + col] = acc;
+    if (Y2) Y2[row * ldy2 + col] = acc;
   }
+}
+
+// Gather copy: xs (rows x kp, kp a multiple of 32 floats, so that every row
+// starts on a 128-byte line) = X (rows x k, ld ldx); the padding columns are
+// written as zeros.  A thread per four output floats.
+__global__ __launch_bounds__(256) void csr_stage_kernel(const float* __restrict__ X,
+                                                        int64_t ldx, int64_t rows, int k,
+                                                        float* __restrict__ xs, int kp) {
+  const int q4 = kp >> 2;
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= rows * q4) return;
+  const int64_t r = e / q4;
+  const int c = 4 * static_cast<int>(e - r * q4);
+  const float* x = X + r * ldx;
+  float4 o;
+  o.x = c < k ? x[c] : 0.0f;
+  o.y = c + 1 < k ? x[c + 1] : 0.0f;
+  o.z = c + 2 < k ? x[c + 2] : 0.0f;
+  o.w = c + 3 < k ? x[c + 3] : 0.0f;
+  *reinterpret_cast<float4*>(xs + r * kp + c) = o;
 }
 
 // Block partials of the weighted column sums w^T X (FP64): block b sums
@@ -541,15 +648,25 @@ void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
       rp, ci, rows, cols, nnz, ctrl);
 }
 
+// X through a buffer descriptor (range-checked gathers) when its rows span
+// less than 2 GB: 32-bit byte offsets, and 0xFFFFFFF0 is out of range.
+static uint32_t gather_bytes(int64_t xrows, int64_t ldx) {
+  const int64_t b = xrows * ldx * 4;
+  return (b > 0 && b <= 0x7FFFFFFF) ? static_cast<uint32_t>(b) : 0u;
+}
+
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
-                     int64_t rows, int k, const float* X, int64_t ldx, float* Y,
-                     int64_t ldy, const float* rowvec, const double* colvec,
+                     int64_t rows, int k, const float* X, int64_t xrows, int64_t ldx, float* Y,
+                     int64_t ldy, const float* rowvec, const double* colvec, bool batch,
                      hipStream_t s) {
   if (rows <= 0 || k <= 0) return;
   const int KC = kc_for(k);
   const int64_t waves = cdiv(rows, 64 / KC);
-  csr_spmm_kernel<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
-      rows, k, KC, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec, 0x7FFFFFFF);
+  const uint32_t xb = gather_bytes(xrows, ldx);
+  auto kern = xb ? (batch ? csr_spmm_kernel<true, true> : csr_spmm_kernel<true, false>)
+                 : (batch ? csr_spmm_kernel<false, true> : csr_spmm_kernel<false, false>);
+  kern<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
+      rows, k, KC, rp, ci, v, X, ldx, xb, Y, ldy, rowvec, colvec, 0x7FFFFFFF);
 }
 
 int csr_piece_len(int k) { return (64 / kc_for(k)) * kCsrShort; }
@@ -596,27 +713,52 @@ void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl, int32_
 }
 
 void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
-                        const float* v, int k, const float* X, int64_t ldx, float* Y,
-                        int64_t ldy, const float* rowvec, const double* colvec,
-                        hipStream_t s) {
+                        const float* v, int k, const float* X, int64_t xrows, int64_t ldx,
+                        float* Y, int64_t ldy, float* Y2, int64_t ldy2, const float* rowvec,
+                        const double* colvec, hipStream_t s) {
   if (k <= 0) return;
   const int KC = kc_for(k);
   const int rps = csr_slot_rows(pl, k);
   const int64_t nsw = cdiv(pl.nshort, (64 / KC) * rps);
   const int64_t waves = nsw + pl.npieces;
   if (waves <= 0) return;
-  auto kern = pl.operand ? csr_product_kernel<1> : csr_product_kernel<0>;
+  const uint32_t xb = gather_bytes(xrows, ldx);
+  // gathers 32 at a time when the short rows average 16 or more nonzeros
+  // (A X at the term-document workload, document rows: 30.0 -> 25.9 us);
+  // else 16 / 8 / 1 at a time (its A^T Y, term rows of ~11 nonzeros: 39.3
+  // us, against 45.3 us in batches of 32, whose extra gather instructions
+  // load the texture address unit)
+  const bool sb = pl.short_nnz >= 16 * static_cast<int64_t>(pl.nshort);
+  using K = decltype(&csr_product_kernel<0, true, true>);
+  static const K kerns[2][2][2] = {
+      {{csr_product_kernel<0, false, false>, csr_product_kernel<0, false, true>},
+       {csr_product_kernel<0, true, false>, csr_product_kernel<0, true, true>}},
+      {{csr_product_kernel<1, false, false>, csr_product_kernel<1, false, true>},
+       {csr_product_kernel<1, true, false>, csr_product_kernel<1, true, true>}}};
+  const K kern = kerns[pl.operand ? 1 : 0][xb ? 1 : 0][sb ? 1 : 0];
   kern<<<static_cast<unsigned>(cdiv(waves, 4)), 256, 0, s>>>(
       k, KC, rps, csr_piece_len(k), pl.nshort, pl.npieces, pl.short_rows, pl.piece_row,
-      pl.piece_first, pl.part, rp, ci, v, X, ldx, Y, ldy, rowvec, colvec);
+      pl.piece_first, pl.part, rp, ci, v, X, ldx, xb, Y, ldy, Y2, ldy2, rowvec, colvec);
 }
 
 void launch_csr_combine(const CsrPlan& pl, const int32_t* rp, int k, float* Y, int64_t ldy,
-                        const float* rowvec, const double* colvec, hipStream_t s) {
+                        float* Y2, int64_t ldy2, const float* rowvec, const double* colvec,
+                        hipStream_t s) {
   if (pl.nmulti > 0 && k > 0)
     csr_combine_kernel<<<static_cast<unsigned>(cdiv(pl.nmulti, 4)), 256, 0, s>>>(
         pl.nmulti, k, csr_piece_len(k), pl.multi_row, pl.multi_first, rp, pl.part, Y, ldy,
-        rowvec, colvec);
+        Y2, ldy2, rowvec, colvec);
+}
+
+int csr_stage_ld(int k) { return static_cast<int>(align_up(static_cast<size_t>(k), 32)); }
+
+void launch_csr_stage(const float* X, int64_t ldx, int64_t rows, int k, float* xs,
+                      hipStream_t s) {
+  const int kp = csr_stage_ld(k);
+  const int64_t total = rows * (kp / 4);
+  if (total > 0)
+    csr_stage_kernel<<<static_cast<unsigned>(cdiv(total, 256)), 256, 0, s>>>(X, ldx, rows, k,
+                                                                            xs, kp);
 }
 
 int colsum_blocks(int64_t L) {

@@ -59,6 +59,7 @@ struct Options {
   int64_t ld_at = 0;
   const float* at_scales = nullptr;
   bool fp32_cores = false;   // FP32 products on the FP32 matrix cores
+  bool csr_staged = false;   // CSR products gather from padded copies
 };
 
 Options read_options(const bk_options* o, bool f64) {
@@ -87,6 +88,8 @@ Options read_options(const bk_options* o, bool f64) {
     }
     if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, fp32_products) + sizeof(int32_t)))
       r.fp32_cores = o->fp32_products == 1;
+    if (o->struct_size >= static_cast<int32_t>(offsetof(bk_options, csr_gather) + sizeof(int32_t)))
+      r.csr_staged = o->csr_gather == BK_CSR_GATHER_STAGED;
   }
   if (!(r.tau > 0.0)) r.tau = f64 ? 1e-11 : 1e-5;
   return r;
@@ -113,8 +116,10 @@ int64_t partial_need(int64_t n, int64_t d, int k, int q, bool refine, bool csr) 
   // the one-launch CholeskyQR passes alternate between two sets
   need = std::max(need, nn_gram_partial_elems(n, k));
   need = std::max(need, 2 * cqr_pass_partial_elems(k));
-  // M = W^T W on the matrix cores (FP32 W, m <= kGramSymMaxM)
+  // M = W^T W on the matrix cores (FP32 W, m <= kGramSymMaxM), and the
+  // CholeskyQR Grams of the blocks the same way
   need = std::max(need, gram_sym_partial_elems(d, static_cast<int>(m)));
+  need = std::max(need, gram_sym_partial_elems(n, k));
   if (refine) {
     need = std::max(need, tn_partial_elems(n, d, k));
     need = std::max(need, tn_partial_elems(d, k, k));
@@ -199,6 +204,8 @@ struct Layout {
   size_t tscratch_bytes = 0;
   float* mu = nullptr;
   double* colvec = nullptr;
+  float* xs = nullptr;  // staged CSR gathers: d x csr_stage_ld(k), n x ...
+  float* ys = nullptr;
   size_t bytes = 0;
 };
 
@@ -291,6 +298,10 @@ Layout make_layout(char* base, int64_t n, int64_t d, int64_t nnz, int k, int q,
     L.colpart = ar.take<double>(static_cast<size_t>(kColsumBlocks) * k);
     L.mu = ar.take<float>(static_cast<size_t>(n));
     L.colvec = ar.take<double>(static_cast<size_t>(k));
+    if (o.csr_staged) {
+      L.xs = ar.take<float>(static_cast<size_t>(d) * csr_stage_ld(k));
+      L.ys = ar.take<float>(static_cast<size_t>(n) * csr_stage_ld(k));
+    }
   }
   L.bytes = align_up(ar.off, 256);
   return L;
@@ -477,6 +488,18 @@ struct CsrOp : Op {
   const float* mu = nullptr;    // row means (centring) or null
   double* colpart = nullptr;    // kColsumBlocks x k
   double* colvec = nullptr;     // k
+  // Staged gathers (nullable): the right-hand block of every product is
+  // gathered from a copy whose rows start on their own 128-byte lines (one
+  // line per gathered row instead of two or three at the Krylov slab's
+  // stride, and a smaller footprint in each XCD's L2): xs for A X (d rows),
+  // ys for A^T Y (n rows).  The product A^T Y leaves its result in xs too,
+  // so that the A X of that result that follows it (ax_of_aty) needs no
+  // copy; any other A X copies its block first.
+  float* xs = nullptr;
+  float* ys = nullptr;
+  const void* mirror = nullptr;  // the block whose copy xs holds, or null
+  int64_t mirror_ld = 0;
+  int mirror_k = 0;
   // Centred products (footnote on PCA, Section 1): with Abar = A - mu 1^T,
   //   Abar X   = A X   - mu (1^T X)    and   Abar^T Y = A^T Y - 1 (mu^T Y),
   // the k-vector (1^T X or mu^T Y) first, then the product with the rank-1
@@ -489,7 +512,8 @@ struct CsrOp : Op {
   void product(const int32_t* r_, const int32_t* c_, const float* v_, const CsrPlan& pl,
                int phase, const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
                const float* rowvec, const float* colw, int64_t Lc, hipStream_t s,
-               bool exact = false, const double* part = nullptr, int nb = 0) {
+               bool exact = false, const double* part = nullptr, int nb = 0,
+               const float* Xg = nullptr, float* Y2 = nullptr) {
     if (exact) rowvec = nullptr;
     if (mu && !exact) {
       tm->begin(BK_PH_CENTER);
@@ -502,15 +526,30 @@ struct CsrOp : Op {
       }
     }
     tm->begin(phase);
-    launch_csr_product(pl, r_, c_, v_, k, static_cast<const float*>(X), ldx,
-                       static_cast<float*>(Y), ldy, rowvec, (mu && !exact) ? colvec : nullptr, s);
+    const int kp = csr_stage_ld(k);
+    launch_csr_product(pl, r_, c_, v_, k, Xg ? Xg : static_cast<const float*>(X), Lc,
+                       Xg ? kp : ldx, static_cast<float*>(Y), ldy, Y2, kp, rowvec,
+                       (mu && !exact) ? colvec : nullptr, s);
     tm->end(1);
     if (pl.nmulti > 0) {
       tm->begin(BK_PH_LONG);
-      launch_csr_combine(pl, r_, k, static_cast<float*>(Y), ldy, rowvec,
+      launch_csr_combine(pl, r_, k, static_cast<float*>(Y), ldy, Y2, kp, rowvec,
                          (mu && !exact) ? colvec : nullptr, s);
       tm->end(1);
     }
+  }
+  // the gather copy of an A X operand (d rows): xs, copied unless it is
+  // the result of the A^T Y just before (a_of_aty)
+  const float* stage_x(const void* X, int64_t ldx, int k, bool of_aty, hipStream_t s) {
+    const bool hit = of_aty && X == mirror && ldx == mirror_ld && k == mirror_k;
+    mirror = nullptr;
+    if (!xs) return nullptr;
+    if (!hit) {
+      tm->begin(BK_PH_CENTER);
+      launch_csr_stage(static_cast<const float*>(X), ldx, d, k, xs, s);
+      tm->end(1);
+    }
+    return xs;
   }
   const double* pre_part = nullptr;  // block partials of mu^T X for the next aty
   int pre_nb = 0;
@@ -520,16 +559,31 @@ struct CsrOp : Op {
     pre_nb = nb;
   }
   void ax(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
-    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s);
+    const float* xg = stage_x(X, ldx, k, false, s);
+    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s, false, nullptr, 0,
+            xg);
   }
   void ax_of_aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy,
                  hipStream_t s) override {
-    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s, true);
+    const float* xg = stage_x(X, ldx, k, true, s);
+    product(rp, ci, v, *pa, BK_PH_AX, X, ldx, k, Y, ldy, mu, nullptr, d, s, true, nullptr, 0,
+            xg);
   }
   void aty(const void* X, int64_t ldx, int k, void* Y, int64_t ldy, hipStream_t s) override {
+    mirror = nullptr;
+    if (ys) {
+      tm->begin(BK_PH_CENTER);
+      launch_csr_stage(static_cast<const float*>(X), ldx, n, k, ys, s);
+      tm->end(1);
+    }
     product(trp, tci, tv, *pt, BK_PH_ATY, X, ldx, k, Y, ldy, nullptr, mu, n, s, false,
-            pre_part, pre_nb);
+            pre_part, pre_nb, ys, xs);
     pre_part = nullptr;
+    if (xs) {
+      mirror = Y;
+      mirror_ld = ldy;
+      mirror_k = k;
+    }
   }
 };
 
@@ -633,6 +687,16 @@ struct Solver {
   int gram(const void* X, int64_t ldx, int64_t p, const void* Y, int64_t ldy,
            int r, int64_t Lrows, double* G, double alpha = 1.0, double beta = 0.0,
            bool sym = false) {
+    // a plain symmetric Gram of a long narrow FP32 block (the CholeskyQR
+    // Grams): upper 32 x 32 tiles on the matrix cores, FP64 sums of FP32
+    // chunk sums, when its partials fit
+    if (!f64 && sym && X == Y && ldx == ldy && p == r && alpha == 1.0 && beta == 0.0 &&
+        gram_sym_partial_elems(Lrows, r) > 0 &&
+        gram_sym_partial_elems(Lrows, r) <= L->partial_elems) {
+      const int nl = launch_gram_sym_mfma(Lrows, r, static_cast<const float*>(X), ldx, G, r,
+                                          L->partial, s);
+      if (nl) return nl;
+    }
     TNArgs a;
     a.L = Lrows;
     a.p = p;
@@ -717,7 +781,8 @@ struct Solver {
       const int64_t ls = lds[pass];
       // block Lanczos keeps every pass's factor (the sub-diagonal blocks)
       double* R = L->Rband ? L->Rband + (3 * static_cast<size_t>(i) + pass) * k * k : L->R;
-      if (pass == 0 ? !have_gram : !fuse) nl += gram(src, ls, k, src, ls, k, n, L->G);
+      if (pass == 0 ? !have_gram : !fuse)
+        nl += gram(src, ls, k, src, ls, k, n, L->G, 1.0, 0.0, true);
       const int mode = pass ? CHOL_REPEAT : (i == 0 ? CHOL_FIRST_BLOCK0 : CHOL_FIRST);
       if (fuse) {
         CqrPass a;
@@ -1349,6 +1414,8 @@ int csr_prepare_and_run(const int32_t* row_ptr, const int32_t* col_idx, const fl
   op.mu = o.center ? L.mu : nullptr;
   op.colpart = L.colpart;
   op.colvec = L.colvec;
+  op.xs = L.xs;
+  op.ys = L.ys;
   const int st = run(op, L, base + lay);
   if (info && o.timing) {
     float ms = 0.0f;
@@ -1931,10 +1998,9 @@ int bk_csr_product(const int32_t* row_ptr, const int32_t* col_idx, const float* 
                    int32_t k, float* Y, int64_t ldy, void* stream) {
   if (rows < 0 || cols < 0 || nnz < 0 || k <= 0 || !row_ptr || !X || !Y || ldx < k || ldy < k)
     return BK_EINVAL;
-  (void)cols;
   // every row by the row kernel (no long-row plan for a one-off product)
-  launch_csr_spmm(row_ptr, col_idx, vals, rows, k, X, ldx, Y, ldy, nullptr, nullptr,
-                  static_cast<hipStream_t>(stream));
+  launch_csr_spmm(row_ptr, col_idx, vals, rows, k, X, cols, ldx, Y, ldy, nullptr, nullptr,
+                  nnz >= 16 * rows, static_cast<hipStream_t>(stream));
   BK_TRY_LAUNCH();
   return BK_OK;
 }

@@ -1072,7 +1072,10 @@ __global__ __launch_bounds__(256) void pack_t_x3_kernel(const TS* __restrict__ s
   __shared__ float tile[128][33];
   const int t = threadIdx.x;
   const int64_t rb = static_cast<int64_t>(blockIdx.x) * 128;
-  for (int64_t c0 = 0; c0 < cols_pad; c0 += 32) {
+  // blockIdx.y: the first of this workgroup's 32-column chunks (gridDim.y
+  // chunks apart)
+  for (int64_t c0 = 32 * static_cast<int64_t>(blockIdx.y); c0 < cols_pad;
+       c0 += 32 * static_cast<int64_t>(gridDim.y)) {
     for (int i = t; i < 128 * 32; i += 256) {
       const int rr = i >> 5, cc = i & 31;
       const int64_t gr = rb + rr, gc = c0 + cc;
@@ -1318,7 +1321,7 @@ static int nn_run_x3(const NNArgs& a, hipStream_t s) {
   const int64_t np = align_up(static_cast<size_t>(a.N), 32);
   const int64_t plane = kp * np;
   bf16_t* xt = static_cast<bf16_t*>(a.work);
-  const unsigned g = static_cast<unsigned>(kp / 128);
+  const dim3 g(static_cast<unsigned>(kp / 128), static_cast<unsigned>(np / 32));
   if (a.x_f64)
     pack_t_x3_kernel<double><<<g, 256, 0, s>>>(static_cast<const double*>(a.X), a.ldx, a.K, a.N,
                                                xt, kp, np, plane);
@@ -1446,8 +1449,10 @@ static void tn_run(const TNArgs& a, int S, int64_t Ls, hipStream_t s) {
       const int64_t rp = align_up(static_cast<size_t>(a.r), 32);
       const int64_t plane = lp * rp;
       bf16_t* yt = static_cast<bf16_t*>(a.work);
-      pack_t_x3_kernel<float><<<static_cast<unsigned>(lp / 128), 256, 0, s>>>(
-          static_cast<const float*>(a.Y), a.ldy, a.L, a.r, yt, lp, rp, plane);
+      pack_t_x3_kernel<float><<<dim3(static_cast<unsigned>(lp / 128),
+                                     static_cast<unsigned>(rp / 32)),
+                                256, 0, s>>>(static_cast<const float*>(a.Y), a.ldy, a.L, a.r,
+                                             yt, lp, rp, plane);
       // r > 128: a workgroup of 512 takes 256 columns of Y, so that X is
       // read from memory once
       if (a.r > 128) {

@@ -271,9 +271,9 @@ void launch_csr_validate(const int32_t* rp, const int32_t* ci, int64_t rows,
 // colvec nullable = no correction), every row by one slot of KC lanes
 // (no work plan: the one-off product of the public helper).
 void launch_csr_spmm(const int32_t* rp, const int32_t* ci, const float* v,
-                     int64_t rows, int k, const float* X, int64_t ldx,
+                     int64_t rows, int k, const float* X, int64_t xrows, int64_t ldx,
                      float* Y, int64_t ldy, const float* rowvec,
-                     const double* colvec, hipStream_t s);
+                     const double* colvec, bool batch, hipStream_t s);
 
 // Work plan of one CSR operand for the Krylov products.  Rows of at most
 // kCsrShort nonzeros are listed in row order and taken SLOTS = 64 / KC to a
@@ -308,14 +308,21 @@ int64_t csr_plan_chunks(int64_t rows);
 void launch_csr_plan(const int32_t* rp, int64_t rows, int k, CsrPlan& pl,
                      int32_t* totals, hipStream_t s);
 // Y = A X - rowvec colvec^T (rowvec nullable = ones, colvec nullable = no
-// centring term).
+// centring term); Y2 (nullable, ld ldy2) receives a second copy of Y.
 void launch_csr_product(const CsrPlan& pl, const int32_t* rp, const int32_t* ci,
-                        const float* v, int k, const float* X, int64_t ldx,
-                        float* Y, int64_t ldy, const float* rowvec,
-                        const double* colvec, hipStream_t s);
+                        const float* v, int k, const float* X, int64_t xrows, int64_t ldx,
+                        float* Y, int64_t ldy, float* Y2, int64_t ldy2,
+                        const float* rowvec, const double* colvec, hipStream_t s);
 // finishes the rows of several pieces (after launch_csr_product)
 void launch_csr_combine(const CsrPlan& pl, const int32_t* rp, int k, float* Y, int64_t ldy,
-                        const float* rowvec, const double* colvec, hipStream_t s);
+                        float* Y2, int64_t ldy2, const float* rowvec, const double* colvec,
+                        hipStream_t s);
+// Gather copies of the product's right-hand block: row stride
+// csr_stage_ld(k) floats (k rounded up to 32: every row on its own 128-byte
+// lines), padding zeroed.
+int csr_stage_ld(int k);
+void launch_csr_stage(const float* X, int64_t ldx, int64_t rows, int k, float* xs,
+                      hipStream_t s);
 // colvec[c] = sum_r w[r] X[r][c] (FP64) over L rows (w nullable = ones):
 // colsum_blocks(L) blocks sum contiguous row ranges into colpart (blocks x k)
 // and a one-block kernel adds those in block order (fixed order throughout).

@@ -248,7 +248,12 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
 #pragma unroll
   for (int j = 0; j < K; ++j) {  // no early exit: the loop stays unrolled
     const double* b = rb + (j & 1) * 64;
-    double d = b[j];
+    // the whole row j (entries j .. K-1) requested at once, before the
+    // pivot's dependent chain: one LDS round trip per step
+    double bv[K];
+#pragma unroll
+    for (int r = j; r < K; ++r) bv[r] = b[r];
+    double d = bv[j];
     if (!(d > 0x1p-1000) || !isfinite(d)) {  // (a pivot below 2^-1000 is a breakdown)
       ok = false;
       d = 1.0;
@@ -268,12 +273,12 @@ __device__ bool chol_regs(int k, const double (&g)[K], double shift, double (&a)
     // S[j][r] S[j][c] = b[r] (a[j] / sqrt(d)): one FMA per entry
     const double tj = a[j] * inv;
     if (j + 1 < K) {
-      a[j + 1] -= b[j + 1] * tj;
+      a[j + 1] -= bv[j + 1] * tj;
       rb[((j + 1) & 1) * 64 + c] = a[j + 1];  // (every lane: no branch)
       wave_lds_sync();
     }
 #pragma unroll
-    for (int r = j + 2; r < K; ++r) a[r] -= b[r] * tj;
+    for (int r = j + 2; r < K; ++r) a[r] -= bv[r] * tj;
   }
   return ok;
 }
@@ -508,49 +513,92 @@ __global__ __launch_bounds__(256) void cholm_rank_kernel(int k, const double* __
 }
 
 // Diagonal block p: one wavefront factors S_pp (32 x 32, trailing updates
-// applied) in registers (chol_regs: lane c holds column c, rows posted to
-// LDS one step ahead, 1 / sqrt(pivot) from the hardware estimate and two
-// Newton steps) and inverts it: R_pp into R, R_pp^-1 into Rinv, the inverse
-// by back substitution, a column per lane, over R_pp staged in LDS.
+// applied) and inverts it: R_pp into R, R_pp^-1 into Rinv.  Lane c holds
+// column c; both loops are rolled (a kernel this short and serial is bound
+// by instruction fetch when unrolled: ~50 KB of straight-line code took
+// ~26 us) and keep their register indices static by shifting: at step j
+// the lane's array holds rows j, j+1, ... of its column (zeros past the
+// block), so the pivot row is always entry 0.  Step j posts its row of the
+// current matrix to LDS, reads it back whole (one round trip), forms
+// 1 / sqrt(pivot) from the hardware estimate and two Newton steps, keeps
+// row j of R in LDS and applies the rank-1 update while shifting.  The
+// inverse follows by back substitution over the rows of R in LDS, a column
+// of R_pp^-1 per lane, x_i = (delta_ic - sum_{l > i} R_il x_l) / R_ii with
+// the sum in increasing l, the same operations as an unrolled solve.
 __global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const double* __restrict__ S,
                                                         double* __restrict__ R,
                                                         double* __restrict__ Rinv,
                                                         CholMState* st) {
-  __shared__ double rb[2 * 64];
-  __shared__ double Rs[CM][CM + 1];
+  __shared__ __align__(16) double rb[64];            // row j of the current matrix
+  __shared__ __align__(16) double Rs[CM][2 * CM];   // rows of R_pp, zero past column CM
   __shared__ double rdiag[CM];
   if (st->decision || st->fail) return;
-  const int c = threadIdx.x;  // lanes 0..31: columns; 32..63 idle but in step
+  const int c = threadIdx.x;  // lanes 0..31: columns; 32..63 hold zeros
   const int bs = (k - o < CM) ? k - o : CM;
-  double g[CM];
+  double a[CM];
 #pragma unroll
-  for (int r = 0; r < CM; ++r)
-    g[r] = (c < bs && r < bs) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0;
-  double a[CM], rinv[CM], mp;
-  const bool ok = chol_regs<CM>(bs, g, 0.0, a, rinv, mp, rb);
-  if (c < CM) {
-#pragma unroll
-    for (int r = 0; r < CM; ++r) {
-      Rs[r][c] = a[r];
-      if (r == c) rdiag[c] = rinv[r];  // (static register index)
-    }
+  for (int r = 0; r < CM; ++r) {
+    // upper triangle of the block, padded with the identity to CM
+    double g = 0.0;
+    if (c < bs && r < bs) g = (r <= c) ? S[static_cast<int64_t>(o + r) * k + o + c] : 0.0;
+    else if (c < CM && r == c) g = 1.0;
+    a[r] = g;
   }
-  __syncthreads();
-  // x = column c of R_pp^-1: x_i = (delta_ic - sum_{l > i} R_il x_l) / R_ii
-  double x[CM];
+  bool ok = true;
+  double mp = INFINITY;
+#pragma unroll 1
+  for (int j = 0; j < CM; ++j) {
+    rb[c] = a[0];
+    wave_lds_sync();
+    double bv[CM];
 #pragma unroll
+    for (int r = 0; r < CM; ++r) bv[r] = rb[j + r];
+    double d = bv[0];
+    if (!(d > 0x1p-1000) || !isfinite(d)) {  // (a pivot below 2^-1000 is a breakdown)
+      ok = false;
+      d = 1.0;
+    }
+    double inv = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    inv = fma(inv, fma(-hd * inv, inv, 0.5), inv);
+    inv = fma(inv, fma(-hd * inv, inv, 0.5), inv);
+    const double s0 = d * inv;
+    const double rd = fma(fma(-s0, s0, d), 0.5 * inv, s0);
+    if (j < bs) mp = fmin(mp, rd);
+    const double rjc = (c == j) ? rd : a[0] * inv;  // R[j][c] (zero for c < j)
+    Rs[j][c] = (c >= j && c < CM) ? rjc : 0.0;
+    if (c == 0) rdiag[j] = inv;
+    const double tj = a[0] * inv * inv;  // S[j][c] / pivot
+#pragma unroll
+    for (int r = 0; r + 1 < CM; ++r) a[r] = a[r + 1] - bv[r + 1] * tj;
+    a[CM - 1] = 0.0;
+    wave_lds_sync();  // (row j's reads come before the next post)
+  }
+  wave_lds_sync();
+  // back substitution: xs[m] = x_{i+1+m} while row i is solved
+  double xs[CM];
+#pragma unroll
+  for (int m = 0; m < CM; ++m) xs[m] = 0.0;
+#pragma unroll 1
   for (int i = CM - 1; i >= 0; --i) {
+    double rr[CM];
+#pragma unroll
+    for (int m = 0; m < CM; ++m) rr[m] = Rs[i][i + 1 + m];
+    const double ri = rdiag[i];
     double sum = 0.0;
 #pragma unroll
-    for (int l = i + 1; l < CM; ++l) sum += Rs[i][l] * x[l];
-    x[i] = ((i == c ? 1.0 : 0.0) - sum) * rdiag[i];
+    for (int m = 0; m < CM; ++m) sum += rr[m] * xs[m];
+    const double xi = ((i == c ? 1.0 : 0.0) - sum) * ri;
+#pragma unroll
+    for (int m = CM - 1; m > 0; --m) xs[m] = xs[m - 1];
+    xs[0] = xi;
   }
   if (ok && c < bs) {
 #pragma unroll
     for (int r = 0; r < CM; ++r) {
       if (r <= c) {
-        R[static_cast<int64_t>(o + r) * k + o + c] = a[r];
-        Rinv[static_cast<int64_t>(o + r) * k + o + c] = x[r];
+        R[static_cast<int64_t>(o + r) * k + o + c] = Rs[r][c];
+        Rinv[static_cast<int64_t>(o + r) * k + o + c] = xs[r];
       }
     }
   }

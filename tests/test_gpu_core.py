@@ -283,15 +283,38 @@ def test_svd_csr_long_block(k, q):
 def test_svd_csr_config2_full_size():
     """The term-document workload at full size (11000 x 130000, ~1.5M
     nonzeros, k = 20, q = 10, row centring), in the launch configuration the
-    benchmark times."""
+    benchmark times, with both gather layouts."""
     w = workloads.WORKLOADS["csr2"]
     (rp, ci, va), M = _termdoc(w.n, w.d, w.seed_matrix, median=90.0)
     ref = bki.block_krylov(M, _pi32(w.seed_sketch, w.d, w.k), w.k, w.q, center=True,
                            tau=1e-5)
-    res = bk.svd_csr(_cuda(rp), _cuda(ci), _cuda(va), w.n, w.d, w.k, w.q,
-                     seed=w.seed_sketch, center=True)
+    args = (_cuda(rp), _cuda(ci), _cuda(va), w.n, w.d, w.k, w.q)
+    res = bk.svd_csr(*args, seed=w.seed_sketch, center=True)
     assert res.info["q_eff"] == w.q
     compare(res.Z.cpu().numpy(), res.sigma.cpu().numpy(), ref, w.k, 1e-5, 1e-4)
+    # the gathers from padded copies: bit-identical
+    for gather in ("inplace", "staged"):
+        r2 = bk.svd_csr(*args, seed=w.seed_sketch, center=True, csr_gather=gather)
+        assert torch.equal(res.Z, r2.Z) and torch.equal(res.sigma, r2.sigma), gather
+
+
+# Gathers from the padded copies (csr_gather="staged") feed the products the
+# same values in the same order, so every result is bit-identical to the
+# in-place gathers: short rows several to a slot (k = 3), the documents' own
+# rows (k = 20, one 128-byte line per copied row), k = 40 (two lines); with
+# centring and the residual certificate (an A^T Z followed by the A X of its
+# result, which reads the copy the A^T Z left).
+@pytest.mark.parametrize("k,q,center", [(3, 5, True), (20, 4, False), (40, 2, True)])
+def test_svd_csr_staged_gathers_bit_identical(k, q, center):
+    (rp, ci, va), M = _termdoc(1500, 24000, 12, median=30.0)
+    args = (_cuda(rp), _cuda(ci), _cuda(va), 1500, 24000, k, q)
+    r1 = bk.svd_csr(*args, seed=5, center=center, residuals=True, csr_gather="inplace")
+    r2 = bk.svd_csr(*args, seed=5, center=center, residuals=True, csr_gather="staged")
+    assert torch.equal(r1.Z, r2.Z)
+    assert torch.equal(r1.sigma, r2.sigma)
+    assert torch.equal(r1.residuals, r2.residuals)
+    ref = bki.block_krylov(M, _pi32(5, 24000, k), k, q, center=center, tau=1e-5)
+    compare(r2.Z.cpu().numpy(), r2.sigma.cpu().numpy(), ref, k, 1e-5, 1e-4)
 
 
 def test_svd_csr_given_transpose_matches():
