@@ -392,15 +392,18 @@ __global__ __launch_bounds__(256 * WN) void nn_x3_kernel(
       bst[slot][l][1] = xrow[l * pl4 + cc * 4 + 1];
     }
   };
+  // (no masking: a chunk past the end is never multiplied, and a column
+  // past the valid ones, which holds column 0's limbs, only feeds output
+  // columns that are not stored; the K tail is zero in the packed limbs)
   auto bstore = [&](int slot, int buf, int64_t c) {
-    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
+    (void)c;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         *reinterpret_cast<uint4*>(&Bs[buf][l][bc * X3_COL + 8 * bh + 4 * i]) =
-            make_uint4(bst[slot][l][i].x & mk, bst[slot][l][i].y & mk, bst[slot][l][i].z & mk,
-                       bst[slot][l][i].w & mk);
+            make_uint4(bst[slot][l][i].x, bst[slot][l][i].y, bst[slot][l][i].z,
+                       bst[slot][l][i].w);
   };
   aload(0, 0);
   aload(1, 1);
@@ -434,16 +437,35 @@ __global__ __launch_bounds__(256 * WN) void nn_x3_kernel(
           av[7] = __uint_as_float(a1v.w);
           bf16x8 al[3];
           split3(av, al[0], al[1], al[2]);
+          // limb-major, as in tn_x3_kernel
+          auto bfrag = [&](int l, int tt) {
+            return __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const uint4*>(
+                            tile + l * CB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
+                            8 * s2 + 4 * h));
+          };
+          bf16x8 b3[NT], b2[NT], b1[NT];
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b3[tt] = bfrag(2, tt);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b2[tt] = bfrag(1, tt);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b3[tt], acc[tt], 0, 0, 0);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b1[tt] = bfrag(0, tt);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int tt = 0; tt < NT; ++tt) {
-            bf16x8 bl[3];
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1], b2[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b2[tt], acc[tt], 0, 0, 0);
+          }
 #pragma unroll
-            for (int l = 0; l < 3; ++l)
-              bl[l] = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const uint4*>(
-                              tile + l * CB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
-                              8 * s2 + 4 * h));
-            acc[tt] = mfma_x3(al, bl, acc[tt]);
+          for (int tt = 0; tt < NT; ++tt) {
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[2], b1[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1], b1[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b1[tt], acc[tt], 0, 0, 0);
           }
         }
       }
@@ -936,14 +958,17 @@ __global__ __launch_bounds__(256 * WN) void tn_x3_kernel(int64_t L, int64_t p, i
       yv[l][1] = yrow[l * pl4 + cc * 4 + 1];
     }
   };
+  // (no masking: a chunk past the end is never multiplied, a column past
+  // the valid ones, which holds column 0's limbs, only feeds output columns
+  // that are not stored, and rows past the split are zero in the packing)
   auto ystore = [&](const uint4 (*yv)[2], int buf, int64_t c) {
-    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
+    (void)c;
 #pragma unroll
     for (int l = 0; l < 3; ++l)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         *reinterpret_cast<uint4*>(&Bs[buf][l][bc * X3_COL + 8 * bh + 4 * i]) =
-            make_uint4(yv[l][i].x & mk, yv[l][i].y & mk, yv[l][i].z & mk, yv[l][i].w & mk);
+            make_uint4(yv[l][i].x, yv[l][i].y, yv[l][i].z, yv[l][i].w);
   };
   f32x16 acc[NT];
 #pragma unroll
@@ -968,20 +993,41 @@ __global__ __launch_bounds__(256 * WN) void tn_x3_kernel(int64_t L, int64_t p, i
       __builtin_amdgcn_sched_barrier(0);
       if (c < nch) {  // (uniform; no memory operation but LDS reads inside)
         const uint32_t* tile = &Bs[c & 1][0][0];
+        // limb-major: the NT tiles' fragments of one B limb requested
+        // together, the next limb's while these are used (the products of a
+        // tile in the order a1 b3, a2 b2, a1 b2, a3 b1, a2 b1, a1 b1)
+        auto bfrag = [&](int l, int st, int tt) {
+          return __builtin_bit_cast(
+              bf16x8, *reinterpret_cast<const uint4*>(
+                          tile + l * RB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
+                          8 * st + 4 * h));
+        };
 #pragma unroll
         for (int st = 0; st < 2; ++st) {
           bf16x8 al[3];
           split3(&xv[u % 3][8 * st], al[0], al[1], al[2]);
+          bf16x8 b3[NT], b2[NT], b1[NT];
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b3[tt] = bfrag(2, st, tt);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b2[tt] = bfrag(1, st, tt);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b3[tt], acc[tt], 0, 0, 0);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt) b1[tt] = bfrag(0, st, tt);
+          __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int tt = 0; tt < NT; ++tt) {
-            bf16x8 bl[3];
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1], b2[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b2[tt], acc[tt], 0, 0, 0);
+          }
 #pragma unroll
-            for (int l = 0; l < 3; ++l)
-              bl[l] = __builtin_bit_cast(
-                  bf16x8, *reinterpret_cast<const uint4*>(
-                              tile + l * RB * X3_COL + (128 * cw + 32 * tt + r32) * X3_COL +
-                              8 * st + 4 * h));
-            acc[tt] = mfma_x3(al, bl, acc[tt]);
+          for (int tt = 0; tt < NT; ++tt) {
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[2], b1[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[1], b1[tt], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[0], b1[tt], acc[tt], 0, 0, 0);
           }
         }
       }

@@ -757,25 +757,18 @@ __global__ __launch_bounds__(256) void tridiag_back_kernel(const double* __restr
 
 // The same back-transformation for large m with the rows of a column spread
 // over a workgroup of 256 threads (row t + 256 u in lane t, u < VR) and CPW
-// columns per workgroup sharing each reflector's loads, the reflectors
-// taken NB at a time with one barrier per group.  For the group applied in
-// the order H_1, ..., H_NB (descending j) to a column u,
-//   d_i = v_i^T u - sum_{l < i} beta_l d_l (v_i^T v_l),
-//   u  <- u - sum_i beta_i d_i v_i        (added in i order),
-// the compact form of the product of the group (as in blocked Householder
-// application): the NB CPW dots v_i^T u and the NB (NB - 1) / 2 couplings
-// v_i^T v_l are summed in one pass (wave sums, then the four wavefronts'
-// partials through LDS, two alternating slots), the small triangular
-// recurrence runs in every thread alike.  The next group's vectors are
-// loaded while the current group is applied.
+// columns per workgroup sharing each reflector's loads: short per-lane rows
+// leave registers for AH reflectors in flight (one reflector's loads cost a
+// memory latency, the per-reflector work a few hundred cycles).  The dot
+// products: wave sums, then the four wavefronts' partials through LDS (two
+// alternating slots, one barrier per reflector).
 template <int VR, int CPW>
 __global__ __launch_bounds__(256) void tridiag_back_wg_kernel(
     const double* __restrict__ Vh, const double* __restrict__ beta, int64_t m, int k,
     const double* __restrict__ X, double* __restrict__ Uk, int64_t ldu,
     const double* __restrict__ theta, double* __restrict__ ritz) {
-  constexpr int NB = 4;
-  constexpr int NR = NB * CPW + NB * (NB - 1) / 2;  // dots, then couplings
-  __shared__ double part[2][4][NR];
+  constexpr int AH = 4;
+  __shared__ double part[2][4][CPW];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int c0 = blockIdx.x * CPW;
   if (ritz && t < CPW && c0 + t < k) ritz[c0 + t] = sqrt(fmax(theta[c0 + t], 0.0));
@@ -787,77 +780,50 @@ __global__ __launch_bounds__(256) void tridiag_back_wg_kernel(
       const int64_t i = t + 256 * u;
       xr[cc][u] = (c0 + cc < k && i < m) ? X[static_cast<int64_t>(c0 + cc) * m + i] : 0.0;
     }
-  // group starting at reflector j (then j - 1, ..., j - NB + 1); reflectors
-  // below 0 are zero vectors with beta 0
-  auto fetch = [&](int64_t j, double (&vv)[NB][VR], double (&bb)[NB]) {
+  double vq[AH][VR], bq[AH];
+  auto fetch = [&](int64_t jj, double (&vv)[VR], double& bb) {
+    bb = jj >= 0 ? beta[jj] : 0.0;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int64_t jj = j - q;
-      bb[q] = jj >= 0 ? beta[jj] : 0.0;
-#pragma unroll
-      for (int u = 0; u < VR; ++u) {
-        const int64_t i = t + 256 * u;
-        vv[q][u] = (jj >= 0 && i > jj && i < m) ? Vh[jj * m + i] : 0.0;
-      }
+    for (int u = 0; u < VR; ++u) {
+      const int64_t i = t + 256 * u;
+      vv[u] = (jj >= 0 && i > jj && i < m) ? Vh[jj * m + i] : 0.0;
     }
   };
   int slot = 0;
-  auto apply = [&](const double (&vv)[NB][VR], const double (&bb)[NB]) {
-    double acc[NR];
+  auto apply = [&](const double (&vv)[VR], double bb) {
+    double dot[CPW];
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
+    for (int cc = 0; cc < CPW; ++cc) {
+      double d = 0.0;
 #pragma unroll
-      for (int cc = 0; cc < CPW; ++cc) {
-        double d = 0.0;
-#pragma unroll
-        for (int u = 0; u < VR; ++u) d += vv[i][u] * xr[cc][u];
-        acc[i * CPW + cc] = d;
-      }
-#pragma unroll
-    for (int i = 1; i < NB; ++i)
-#pragma unroll
-      for (int l = 0; l < i; ++l) {
-        double d = 0.0;
-#pragma unroll
-        for (int u = 0; u < VR; ++u) d += vv[i][u] * vv[l][u];
-        acc[NB * CPW + i * (i - 1) / 2 + l] = d;
-      }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = wave_sum(acc[q]);
+      for (int u = 0; u < VR; ++u) d += vv[u] * xr[cc][u];
+      d = wave_sum(d);
+      dot[cc] = d;
+    }
     if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < NR; ++q) part[slot][wv][q] = acc[q];
+      for (int cc = 0; cc < CPW; ++cc) part[slot][wv][cc] = dot[cc];
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NR; ++q)
-      acc[q] = ((part[slot][0][q] + part[slot][1][q]) + part[slot][2][q]) + part[slot][3][q];
-    double f[NB][CPW];  // beta_i d_i
+    for (int cc = 0; cc < CPW; ++cc) {
+      const double f =
+          bb * (((part[slot][0][cc] + part[slot][1][cc]) + part[slot][2][cc]) + part[slot][3][cc]);
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int cc = 0; cc < CPW; ++cc) {
-        double d = acc[i * CPW + cc];
-#pragma unroll
-        for (int l = 0; l < i; ++l) d -= f[l][cc] * acc[NB * CPW + i * (i - 1) / 2 + l];
-        f[i][cc] = bb[i] * d;
-      }
-#pragma unroll
-    for (int i = 0; i < NB; ++i)
-#pragma unroll
-      for (int cc = 0; cc < CPW; ++cc)
-#pragma unroll
-        for (int u = 0; u < VR; ++u) xr[cc][u] -= f[i][cc] * vv[i][u];
-    slot ^= 1;  // the next group writes the other slot (no second barrier)
+      for (int u = 0; u < VR; ++u) xr[cc][u] -= f * vv[u];
+    }
+    slot ^= 1;  // the next reflector writes the other slot (no second barrier)
   };
-  // groups from reflector m - 3 down to 0, two register sets alternating
-  double va[NB][VR], vb[NB][VR], ba[NB], bb2[NB];
-  fetch(m - 3, va, ba);
-  for (int64_t j0 = m - 3; j0 >= 0; j0 -= 2 * NB) {
-    fetch(j0 - NB, vb, bb2);
-    apply(va, ba);
-    fetch(j0 - 2 * NB, va, ba);
-    if (j0 - NB >= 0) apply(vb, bb2);  // (uniform)
+  // reflectors j = m - 3 down to 0; slot q holds j = m - 3 - (step mod AH)
+#pragma unroll
+  for (int q = 0; q < AH; ++q) fetch(m - 3 - q, vq[q], bq[q]);
+  for (int64_t j0 = m - 3; j0 >= 0; j0 -= AH) {
+#pragma unroll
+    for (int q = 0; q < AH; ++q) {
+      const int64_t j = j0 - q;
+      if (j >= 0) apply(vq[q], bq[q]);  // (uniform)
+      fetch(j - AH, vq[q], bq[q]);
+    }
   }
 #pragma unroll
   for (int cc = 0; cc < CPW; ++cc)
@@ -1498,9 +1464,8 @@ void launch_tridiag_topk(const double* M, int64_t m, int64_t ldm, int k, double*
     tridiag_back_wg_kernel<4, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
   else if (m <= 2048)
     tridiag_back_wg_kernel<8, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
-  else  // m <= kTridiagMax = 256 * 10: three columns per workgroup (registers)
-    tridiag_back_wg_kernel<10, 3><<<static_cast<unsigned>(cdiv(k, 3)), 256, 0, s>>>(
-        Vh, beta, m, k, X, Uk, ldu, theta, ritz);
+  else  // m <= kTridiagMax = 256 * 10
+    tridiag_back_wg_kernel<10, 4><<<gb, 256, 0, s>>>(Vh, beta, m, k, X, Uk, ldu, theta, ritz);
 }
 
 }  // namespace bk
