@@ -1321,6 +1321,36 @@ int64_t mfma_pack_bytes(int64_t lred, int64_t cols, int type) {
          (lp / 128) * 4 + 256;
 }
 
+// Splits of the limb X^T Y kernel: whole rounds of resident workgroups (one
+// per CU with 256-column workgroups, whose staged limbs take 122 KB of LDS,
+// two with 128-column ones), one round when the FP32 sum length allows: a
+// count just past a round leaves a second round nearly empty (a 1792 x 256
+// projection Gram over 131072 rows: 19 splits made 266 workgroups, two
+// rounds; 18 make 252).  Never more than tn_mfma_splits, which sizes the
+// partials.
+static int x3_tn_splits(int64_t L, int64_t p, int r, hipStream_t s) {
+  static int cus_cached[64] = {0};
+  int dev = 0;
+  int cus = 256;
+  if (hipStreamGetDevice(s, &dev) == hipSuccess && dev >= 0 && dev < 64) {
+    if (cus_cached[dev] == 0) {
+      int c = 0;
+      cus_cached[dev] =
+          (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+           c > 0) ? c : 256;
+    }
+    cus = cus_cached[dev];
+  }
+  const int wn = r > 128 ? 2 : 1;
+  const int64_t slots = static_cast<int64_t>(cus) * (wn == 2 ? 1 : 2);
+  const int64_t nwg = cdiv(p, 128) * cdiv(r, 128 * wn);
+  int64_t S = std::max<int64_t>(1, slots / nwg);
+  S = std::max<int64_t>(S, cdiv(L, kX3SplitRows));
+  S = std::min<int64_t>(S, tn_mfma_splits(L, p, r));
+  const int64_t Ls = align_up(static_cast<size_t>(cdiv(L, S)), 128);
+  return static_cast<int>(cdiv(L, Ls));
+}
+
 int tn_mfma_splits(int64_t L, int64_t p, int r) {
   const int64_t tiles = cdiv(p, 128) * cdiv(r, 128);
   int64_t S = cdiv(512, tiles);
@@ -1562,13 +1592,16 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
              (a.p + a.ldx) * 4 >= (int64_t(1) << 32) || 32 * a.ldy * 4 >= (int64_t(1) << 32)) {
     return;  // (FP32: lane offsets in bytes must fit 32 bits)
   }
-  const int S = tn_mfma_splits(a.L, a.p, a.r);
-  const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
+  int S = tn_mfma_splits(a.L, a.p, a.r);
   // FP32: below two workgroups per CU the vector kernel is faster (a 256 x
   // 256 Gram over 131072 rows: 390 us against 660 us on the FP32 matrix
   // cores and 486 us as BF16 limbs, whose limb packing of Y alone writes
   // 200 MB there)
   if (!packed && cdiv(a.p, 128) * cdiv(a.r, 128) * S < 512) return;
+  if (!packed && !a.fp32_cores && a.work &&
+      static_cast<int64_t>(a.work_bytes) >= x3_pack_bytes(a.L, a.r))
+    S = x3_tn_splits(a.L, a.p, a.r, s);
+  const int64_t Ls = align_up(static_cast<size_t>(cdiv(a.L, S)), 128);
   switch (a.x_type) {
     case BK_F32:
       tn_run<float, false>(a, S, Ls, s);
