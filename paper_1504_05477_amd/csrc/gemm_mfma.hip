@@ -180,8 +180,8 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
   // X^T chunk goes through LDS one chunk ahead; FP8 chunk scales travel with
   // the A chunks.  No load is conditional and no branch separates the
   // chunks (either would make the wait-count pass assume the prefetches
-  // unfinished): chunks go in rounds of R, a chunk past the split's last
-  // re-reads the last one and stages zeros for X^T, so it adds nothing.
+  // unfinished): chunks go in rounds of R, and a chunk past the split's
+  // last re-reads the last one and is not multiplied.
   constexpr int R = PD + 1;
   uint4 abuf[R][4], bst[4];
   float scr[R];
@@ -200,12 +200,15 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
 #pragma unroll
     for (int i = 0; i < 4; ++i) bst[i] = xrow[cc * 8 + i];
   };
+  // (no masking: a chunk past the split's last is never multiplied, and a
+  // column past the valid ones, which holds column 0's values, only feeds
+  // output columns that are not stored)
   auto bstore = [&](int buf, int64_t c) {
-    const uint32_t mk = (bload && c < nch) ? 0xFFFFFFFFu : 0u;
+    (void)c;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       *reinterpret_cast<uint4*>(&Bs[buf][bc * LDS_ROW + 16 * bh + 4 * i]) =
-          make_uint4(bst[i].x & mk, bst[i].y & mk, bst[i].z & mk, bst[i].w & mk);
+          make_uint4(bst[i].x, bst[i].y, bst[i].z, bst[i].w);
   };
 #pragma unroll
   for (int u = 0; u < PD; ++u) aload(u, u);
@@ -1449,7 +1452,7 @@ static int nn_run(const NNArgs& a, int type, hipStream_t s) {
   // chunks of A in flight: one for FP32 (a chunk is ~4000 cycles of
   // matrix-core work), three for BF16, two for FP8 (whose scaled partial
   // sums take the registers of the third)
-  constexpr int PD = sizeof(T) == 4 ? 1 : (sizeof(T) == 2 ? 3 : 2);
+  constexpr int PD = sizeof(T) == 4 ? 1 : 3;
 #define BK_NN_LAUNCH(NTV)                                                                  \
   nn_mfma_kernel<T, SCALED, PD, NTV><<<grid, 256, 0, s>>>(                                 \
       a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,             \
