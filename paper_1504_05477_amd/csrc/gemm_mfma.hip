@@ -137,17 +137,23 @@ __device__ __forceinline__ int out_row(int lane, int v) {
 // rows of A go straight from memory into the operand registers (the next
 // chunk in flight while the current one is multiplied), the packed X^T
 // chunk (128 columns x 128 bytes) is staged in LDS, double-buffered.
-template <typename T, bool SCALED, int PD, int NT>
-__global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
+// WN = 2 (N > 128, BF16 / FP8): 512 threads, 256 columns of C, wavefront
+// (w, cw) with cw = t / 256 taking columns 128 cw ..: every row of A is then
+// fetched from memory once (with two 128-column workgroups per row block
+// the second fetch only partly hits L2: 6.1 GB read per FP8 A^T.Y of 4.3 GB).
+template <typename T, bool SCALED, int PD, int NT, int WN>
+__global__ __launch_bounds__(256 * WN, WN == 1 ? 2 : 1) void nn_mfma_kernel(
     int64_t n, int64_t K, int N, const T* __restrict__ A, int64_t lda,
     const float* __restrict__ ascale, int64_t ascale_ld, const T* __restrict__ Xt,
     int64_t ldxt, const float* __restrict__ xscale, float* __restrict__ C, int64_t ldc,
     int64_t cps, float alpha, float beta) {
   constexpr int KC = Mf<T>::KC, STEPS = Mf<T>::STEPS, LW = Mf<T>::LW;
-  __shared__ uint32_t Bs[2][128 * LDS_ROW];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6, h = lane >> 5, r32 = lane & 31;
+  constexpr int CB = 128 * WN;  // columns of C per workgroup
+  __shared__ uint32_t Bs[2][CB * LDS_ROW];
+  const int t = threadIdx.x, lane = t & 63, w = (t >> 6) & 3, h = lane >> 5, r32 = lane & 31;
+  const int cw = t >> 8;
   int64_t rb, cb;
-  if (!xcd_tile(blockIdx.x, (n + 127) / 128, (N + 127) / 128, &rb, &cb)) return;
+  if (!xcd_tile(blockIdx.x, (n + 127) / 128, (N + CB - 1) / CB, &rb, &cb)) return;
   // split blockIdx.y takes chunks [c0, c0 + nch) of K; with several splits
   // C is its n x N (ld N) slice of FP32 partials
   const int64_t nall = K / KC;
@@ -159,18 +165,19 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
     ldc = N;
   }
   const int64_t row0 = rb * 128;
-  const int64_t col0 = cb * 128;
+  const int64_t col0 = cb * CB + 128 * cw;  // the wavefront's first column
   // NT output tiles of 32 columns (compile time: no branch between the
-  // matrix-core steps); tiles past the valid columns multiply the zeros
+  // matrix-core steps); tiles past the valid columns multiply what is
   // staged for them and are not stored
-  const int nt = static_cast<int>((N - col0 + 31) / 32 < NT ? (N - col0 + 31) / 32 : NT);
+  const int64_t vtb = (N - cb * CB + 31) / 32;
+  const int ntb = static_cast<int>(vtb < NT * WN ? vtb : NT * WN);  // the workgroup's
   const int64_t row = row0 + 32 * w + r32;
   const uint4* arow =
       reinterpret_cast<const uint4*>(A + (row < n ? row : n - 1) * lda) + 4 * h + c0 * 8;
   const int bc = t >> 1, bh = t & 1;  // staging: packed column bc, half bh
-  const bool bload = bc < 32 * nt;
+  const bool bload = bc < 32 * ntb;
   const uint4* xrow =
-      reinterpret_cast<const uint4*>(Xt + (col0 + (bload ? bc : 0)) * ldxt) + 4 * bh + c0 * 8;
+      reinterpret_cast<const uint4*>(Xt + (cb * CB + (bload ? bc : 0)) * ldxt) + 4 * bh + c0 * 8;
   f32x16 acc[4];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x16{};
@@ -244,7 +251,7 @@ __global__ __launch_bounds__(256, 2) void nn_mfma_kernel(
 #pragma unroll
         for (int tt = 0; tt < NT; ++tt) {
           uint32_t bw[LW];
-          lds_operand<T>(tile, 32 * tt + r32, h, q, bw);
+          lds_operand<T>(tile, 128 * cw + 32 * tt + r32, h, q, bw);
           if (SCALED) tmp[tt] = mfma_step<T>(aw + q * LW, bw, tmp[tt]);
           else acc[tt] = mfma_step<T>(aw + q * LW, bw, acc[tt]);
         }
@@ -312,15 +319,6 @@ __device__ __forceinline__ void split3(const float* x, bf16x8& l1, bf16x8& l2, b
   l3 = __builtin_bit_cast(bf16x8, make_uint4(w3[0], w3[1], w3[2], w3[3]));
 }
 
-// acc += a b over one 16-value step from limbs (smallest products first)
-__device__ __forceinline__ f32x16 mfma_x3(const bf16x8* a, const bf16x8* b, f32x16 acc) {
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[2], b[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[1], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[2], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[1], b[0], acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[1], acc, 0, 0, 0);
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[0], b[0], acc, 0, 0, 0);
-}
 
 // Words per staged column of one limb: 32 BF16 (one 32-value chunk) + 16
 // bytes of padding, so that the 8 lanes of a 16-byte LDS read pass hit
@@ -1446,21 +1444,27 @@ static int nn_run(const NNArgs& a, int type, hipStream_t s) {
   float* part = S > 1 ? reinterpret_cast<float*>(static_cast<char*>(a.work) +
                                                  mfma_pack_bytes(a.K, a.N, type))
                       : static_cast<float*>(a.C);
-  const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128))),
-                  static_cast<unsigned>(S));
   const float al = static_cast<float>(a.alpha), be = static_cast<float>(a.beta);
   // chunks of A in flight: one for FP32 (a chunk is ~4000 cycles of
-  // matrix-core work), three for BF16, two for FP8 (whose scaled partial
-  // sums take the registers of the third)
+  // matrix-core work), three for BF16 and FP8
   constexpr int PD = sizeof(T) == 4 ? 1 : 3;
-#define BK_NN_LAUNCH(NTV)                                                                  \
-  nn_mfma_kernel<T, SCALED, PD, NTV><<<grid, 256, 0, s>>>(                                 \
+  // BF16 / FP8 with N > 128: 256-column workgroups (A read once)
+  const int wn = (sizeof(T) < 4 && a.N > 128) ? 2 : 1;
+  const dim3 grid(static_cast<unsigned>(xcd_grid(cdiv(a.n, 128), cdiv(a.N, 128 * wn))),
+                  static_cast<unsigned>(S));
+#define BK_NN_LAUNCH(NTV, WNV)                                                             \
+  nn_mfma_kernel<T, SCALED, PD, NTV, WNV><<<grid, 256 * WNV, 0, s>>>(                      \
       a.n, a.K, a.N, static_cast<const T*>(a.A), a.lda, a.ascale, a.ascale_ld,             \
       static_cast<const T*>(a.work), kp, xs, part, S > 1 ? a.N : a.ldc, cps,               \
       S > 1 ? 1.0f : al, S > 1 ? 0.0f : be)
-  if (a.N <= 32) BK_NN_LAUNCH(1);
-  else if (a.N <= 64) BK_NN_LAUNCH(2);
-  else BK_NN_LAUNCH(4);
+  if (a.N <= 32) BK_NN_LAUNCH(1, 1);
+  else if (a.N <= 64) BK_NN_LAUNCH(2, 1);
+  else if constexpr (sizeof(T) < 4) {
+    if (wn == 2) BK_NN_LAUNCH(4, 2);
+    else BK_NN_LAUNCH(4, 1);
+  } else {
+    BK_NN_LAUNCH(4, 1);
+  }
 #undef BK_NN_LAUNCH
   if (S == 1) return 2;
   nn_split_reduce_kernel<<<static_cast<unsigned>(cdiv(a.n * a.N, 256)), 256, 0, s>>>(

@@ -54,13 +54,16 @@ def _operands(prec, A, X):
     return codes, sc, Ad, _rows_fp8(X)
 
 
+# k = 200: A X on 256-column workgroups (N > 128), the second column half
+# ragged (72 of its 128 columns valid)
 @pytest.mark.parametrize("prec", ["f32", "bf16", "fp8"])
 @pytest.mark.parametrize("trans", [False, True])
-def test_mfma_block_products(prec, trans):
+@pytest.mark.parametrize("k", [52, 200])
+def test_mfma_block_products(prec, trans, k):
     rng = np.random.default_rng(17)
     # A^T X: 16 column tiles x 32 row splits = 512 workgroups, the smallest
     # FP32 grid that stays on the matrix cores
-    n, d, k = (20000, 2048, 52) if trans else (1500, 1024, 52)
+    n, d = (20000, 2048) if trans else (1500, 1024)
     A = rng.standard_normal((n, d)).astype(np.float32)
     X = rng.standard_normal((n if trans else d, k)).astype(np.float32)
     Aq, sc, Ad, Xd = _operands(prec, A, X)
