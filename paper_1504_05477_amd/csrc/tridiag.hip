@@ -1091,7 +1091,7 @@ __global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
     TcoSync* sy) {
   __shared__ double spv[TCO_E * TCO_THREADS], spw[TCO_E * TCO_THREADS];
   __shared__ double redA[TCO_THREADS / 64], redB[TCO_THREADS / 64];
-  __shared__ double redR[TCO_RL][TCO_THREADS / 64];
+  __shared__ double prow[TCO_RL * TCO_THREADS];  // the rows' per-thread partials of M' v
   __shared__ double bc[2];
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int G = static_cast<int>(gridDim.x), g = static_cast<int>(blockIdx.x);
@@ -1174,8 +1174,7 @@ __global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
             ps += a[r][e] * vv[e];
           }
         }
-        ps = wave_sum(ps);
-        if (lane == 0) redR[r][wv] = ps;
+        prow[r * TCO_THREADS + t] = ps;
         if (i == j1) {  // the owner publishes row j+1
 #pragma unroll
           for (int e = 0; e < TCO_E; ++e) {
@@ -1186,13 +1185,17 @@ __global__ __launch_bounds__(TCO_THREADS) void tri_coop_kernel(
       }
     }
     __syncthreads();
-    if (t < TCO_RL) {
-      const int64_t i = g + static_cast<int64_t>(t) * G;
-      if (i > j && i < m) {
+    // wavefront r sums row r's 1024 partials: lane l adds entries l, l + 64,
+    // ... in order, then the wave sum (one reduction per row instead of a
+    // wave sum per row in every wavefront, which took most of this phase)
+    if (wv < TCO_RL) {
+      const int64_t i = g + static_cast<int64_t>(wv) * G;
+      if (i > j && i < m) {  // (uniform per wavefront)
         double sum = 0.0;
 #pragma unroll
-        for (int w = 0; w < TCO_THREADS / 64; ++w) sum += redR[t][w];
-        tco_put(pbuf + par * m + i, b * sum);
+        for (int q = 0; q < TCO_THREADS / 64; ++q) sum += prow[wv * TCO_THREADS + lane + 64 * q];
+        sum = wave_sum(sum);
+        if (lane == 0) tco_put(pbuf + par * m + i, b * sum);
       }
     }
     // (3)
