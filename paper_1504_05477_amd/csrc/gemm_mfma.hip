@@ -1151,7 +1151,7 @@ int chunk_vals(int type) { return 128 / esize(type); }
 // ------------------------------------------------------------ M = W^T W --
 // Symmetric Gram of a narrow FP32 block (m <= 384 columns, long L): the
 // upper triangle in 32 x 32 tiles; a workgroup of 8 wavefronts takes a tile
-// group (up to 32 tiles, 4 per wavefront) over one of S contiguous row
+// group (up to 40 tiles, 5 per wavefront) over one of S contiguous row
 // splits.  Rows arrive in 32-row chunks (contiguous 16-byte loads when m,
 // ldw and W allow) into two LDS buffers: while chunk c is multiplied,
 // chunk c + 1 goes from registers into the other buffer and chunk c + 2 is
@@ -1161,7 +1161,7 @@ int chunk_vals(int type) { return 128 / esize(type); }
 // their re-reads of the rows hit its L2.  Output: part[(split T + tile)
 // 1024 + v 64 + lane], accumulator register v of lane `lane` (see out_row).
 constexpr int GS_CH = 32;    // rows per chunk
-constexpr int GS_TPW = 4;    // tiles per wavefront
+constexpr int GS_TPW = 5;    // tiles per wavefront
 constexpr int GS_WAVES = 8;  // wavefronts per workgroup
 constexpr int GS_TPG = GS_TPW * GS_WAVES;
 
@@ -1623,7 +1623,10 @@ void launch_tn_mfma_if(const TNArgs& a, hipStream_t s, int* splits) {
   *splits = S;
 }
 
-// Splits and tile groups of the symmetric Gram: up to 32 tiles per group,
+// Splits and tile groups of the symmetric Gram: up to 40 tiles per group
+// (the 36 tiles of m = 256 in one group: the 8 wavefronts take 5 or 4, so
+// each SIMD's pair takes 9; with 32 per group a second group of 4 tiles
+// left half of the workgroups nearly idle),
 // enough splits for ~256 workgroups (one per CU), at least 128 rows per
 // split.
 static void gram_sym_plan(int64_t L, int m, int* S, int* G, int64_t* per) {

@@ -522,16 +522,19 @@ __global__ __launch_bounds__(256) void cholm_rank_kernel(int k, const double* __
 // current matrix to LDS, reads it back whole (one round trip), forms
 // 1 / sqrt(pivot) from the hardware estimate and two Newton steps, keeps
 // row j of R in LDS and applies the rank-1 update while shifting.  The
-// inverse follows by back substitution over the rows of R in LDS, a column
-// of R_pp^-1 per lane, x_i = (delta_ic - sum_{l > i} R_il x_l) / R_ii with
-// the sum in increasing l, the same operations as an unrolled solve.
+// inverse X = R_pp^-1 is formed in the same loop from X R = I, a row of X
+// per lane: lane i keeps acc_c = sum_{l < j} X_il R_lc for the columns
+// c >= j (shifted like the column), takes X_ij = (delta_ij - acc_j) / R_jj
+// once row j of R is known and adds X_ij R_jc to the rest (a back
+// substitution after the loop, with its own register shifts, took as long
+// as the factorization).
 __global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const double* __restrict__ S,
                                                         double* __restrict__ R,
                                                         double* __restrict__ Rinv,
                                                         CholMState* st) {
   __shared__ __align__(16) double rb[64];            // row j of the current matrix
   __shared__ __align__(16) double Rs[CM][2 * CM];   // rows of R_pp, zero past column CM
-  __shared__ double rdiag[CM];
+  __shared__ double Xs[CM][CM + 1];                  // rows of R_pp^-1
   if (st->decision || st->fail) return;
   const int c = threadIdx.x;  // lanes 0..31: columns; 32..63 hold zeros
   const int bs = (k - o < CM) ? k - o : CM;
@@ -544,6 +547,9 @@ __global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const doub
     else if (c < CM && r == c) g = 1.0;
     a[r] = g;
   }
+  double acc[CM];  // acc[r] = sum_{l < j} X_cl R_l,j+r for this lane's row c of X
+#pragma unroll
+  for (int r = 0; r < CM; ++r) acc[r] = 0.0;
   bool ok = true;
   double mp = INFINITY;
 #pragma unroll 1
@@ -567,38 +573,28 @@ __global__ __launch_bounds__(64) void cholm_diag_kernel(int k, int o, const doub
     if (j < bs) mp = fmin(mp, rd);
     const double rjc = (c == j) ? rd : a[0] * inv;  // R[j][c] (zero for c < j)
     Rs[j][c] = (c >= j && c < CM) ? rjc : 0.0;
-    if (c == 0) rdiag[j] = inv;
+    // row c of X: X_cj = (delta_cj - acc_j) / R_jj, then acc_l += X_cj R_jl
+    // for l > j, with R_jl = bv[l - j] / R_jj
+    const double xcj = ((c == j ? 1.0 : 0.0) - acc[0]) * inv;
+    if (c < CM) Xs[c][j] = xcj;
+    const double wj = xcj * inv;
     const double tj = a[0] * inv * inv;  // S[j][c] / pivot
 #pragma unroll
-    for (int r = 0; r + 1 < CM; ++r) a[r] = a[r + 1] - bv[r + 1] * tj;
+    for (int r = 0; r + 1 < CM; ++r) {
+      a[r] = a[r + 1] - bv[r + 1] * tj;
+      acc[r] = fma(wj, bv[r + 1], acc[r + 1]);
+    }
     a[CM - 1] = 0.0;
+    acc[CM - 1] = 0.0;
     wave_lds_sync();  // (row j's reads come before the next post)
   }
   wave_lds_sync();
-  // back substitution: xs[m] = x_{i+1+m} while row i is solved
-  double xs[CM];
-#pragma unroll
-  for (int m = 0; m < CM; ++m) xs[m] = 0.0;
-#pragma unroll 1
-  for (int i = CM - 1; i >= 0; --i) {
-    double rr[CM];
-#pragma unroll
-    for (int m = 0; m < CM; ++m) rr[m] = Rs[i][i + 1 + m];
-    const double ri = rdiag[i];
-    double sum = 0.0;
-#pragma unroll
-    for (int m = 0; m < CM; ++m) sum += rr[m] * xs[m];
-    const double xi = ((i == c ? 1.0 : 0.0) - sum) * ri;
-#pragma unroll
-    for (int m = CM - 1; m > 0; --m) xs[m] = xs[m - 1];
-    xs[0] = xi;
-  }
   if (ok && c < bs) {
 #pragma unroll
     for (int r = 0; r < CM; ++r) {
       if (r <= c) {
         R[static_cast<int64_t>(o + r) * k + o + c] = Rs[r][c];
-        Rinv[static_cast<int64_t>(o + r) * k + o + c] = xs[r];
+        Rinv[static_cast<int64_t>(o + r) * k + o + c] = Xs[r][c];
       }
     }
   }
