@@ -626,30 +626,35 @@ __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
     ++ti;
   }
   const int tj = ti + e;
-  for (int idx = t; idx < CM * CM; idx += 256) {
+  // all 12 loads in flight: addresses clamped into the k x k arrays, the
+  // values outside the blocks replaced by zero after the load
+#pragma unroll
+  for (int q = 0; q < CM * CM / 256; ++q) {
+    const int idx = t + 256 * q;
     const int r = idx / CM, c = idx % CM;
     const int gi = base + CM * ti + c, gj = base + CM * tj + c;
-    const int64_t row = static_cast<int64_t>(o + r) * k;
-    Ri[r][c] = (r < bs && c < bs && r <= c) ? Rinv[row + o + c] : 0.0;  // R_pp^-1 (upper)
-    Pi[r][c] = (r < bs && gi < k) ? S[row + gi] : 0.0;
-    Pj[r][c] = (r < bs && gj < k) ? S[row + gj] : 0.0;
+    const int64_t row = static_cast<int64_t>(min(o + r, k - 1)) * k;
+    const double vr = Rinv[row + min(o + c, k - 1)];
+    const double vi = S[row + min(gi, k - 1)];
+    const double vj = S[row + min(gj, k - 1)];
+    Ri[r][c] = (r < bs && c < bs && r <= c) ? vr : 0.0;  // R_pp^-1 (upper)
+    Pi[r][c] = (r < bs && gi < k) ? vi : 0.0;
+    Pj[r][c] = (r < bs && gj < k) ? vj : 0.0;
   }
   __syncthreads();
-  // panel rows: X[r][c] = sum_{l <= r} Rinv_pp[l][r] P[l][c], four per thread
+  // panel rows: X[r][c] = sum_{l <= r} Rinv_pp[l][r] P[l][c], four per
+  // thread (each sum in increasing l; P's entries read once per l)
   const int tx = t & 31, ty = t >> 5;
-  double xi[4], xj[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = ty + 8 * u;
-    double si = 0.0, sj = 0.0;
+  double xi[4] = {0.0, 0.0, 0.0, 0.0}, xj[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-    for (int l = 0; l < CM; ++l) {
-      const double w = Ri[l][r];
-      si += w * Pi[l][tx];
-      sj += w * Pj[l][tx];
+  for (int l = 0; l < CM; ++l) {
+    const double pi = Pi[l][tx], pj = Pj[l][tx];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double w = Ri[l][ty + 8 * u];
+      xi[u] += w * pi;
+      xj[u] += w * pj;
     }
-    xi[u] = si;
-    xj[u] = sj;
   }
   __syncthreads();
 #pragma unroll
@@ -666,16 +671,25 @@ __global__ __launch_bounds__(256) void cholm_update_kernel(int k, int o, int bs,
       if (r < bs && gc < k) R[static_cast<int64_t>(o + r) * k + gc] = Pi[r][tx];
     }
   }
+  // S_ti,tj -= X_i^T X_j (each sum in increasing r), the four rows' entries
+  // of S loaded before the sums
+  const int j = base + CM * tj + tx;
+  double sv[4], sum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int ii = ty + 8 * u;
-    const int i = base + CM * ti + ii, j = base + CM * tj + tx;
-    if (i < k && j < k && i <= j) {
-      double sum = 0.0;
+    const int i = base + CM * ti + ty + 8 * u;
+    sv[u] = S[static_cast<int64_t>(min(i, k - 1)) * k + min(j, k - 1)];
+  }
 #pragma unroll 8
-      for (int r = 0; r < CM; ++r) sum += Pi[r][ii] * Pj[r][tx];
-      S[static_cast<int64_t>(i) * k + j] -= sum;
-    }
+  for (int r = 0; r < CM; ++r) {
+    const double pj = Pj[r][tx];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) sum[u] += Pi[r][ty + 8 * u] * pj;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + CM * ti + ty + 8 * u;
+    if (i < k && j < k && i <= j) S[static_cast<int64_t>(i) * k + j] = sv[u] - sum[u];
   }
 }
 
@@ -705,33 +719,48 @@ __global__ __launch_bounds__(256) void cholm_invlevel_kernel(int k, int nbb,
   // PHASE 1: sum over L in [I, b2) of Rinv[I][L] T[L][J]
   const int l0 = PHASE == 0 ? b2 : I;
   const int l1 = PHASE == 0 ? J : b2 - 1;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int L = l0; L <= l1; ++L) {
-    for (int e = t; e < CM * CM; e += 256) {
+  const double* Asrc = PHASE == 0 ? R : Rinv;
+  const double* Bsrc = PHASE == 0 ? Rinv : T;
+  // block pair L's 8 entries per thread, loaded (clamped addresses, entries
+  // outside the blocks or below a diagonal block's diagonal zeroed after the
+  // load) while pair L - 1 is multiplied
+  double av[CM * CM / 256], bv[CM * CM / 256];
+  auto fetch = [&](int L) {
+#pragma unroll
+    for (int q = 0; q < CM * CM / 256; ++q) {
+      const int e = t + 256 * q;
       const int r = e / CM, c = e - (e / CM) * CM;
-      const int ga = I * CM + r, gl = L * CM + c;   // left block (I, L)
-      const int gb = L * CM + r, gj = J * CM + c;   // right block (L, J)
-      double av = 0.0, bv = 0.0;
-      if (ga < k && gl < k) {
-        if (PHASE == 0) av = R[static_cast<int64_t>(ga) * k + gl];
-        else if (L != I || r <= c) av = Rinv[static_cast<int64_t>(ga) * k + gl];
-      }
-      if (gb < k && gj < k) {
-        if (PHASE == 0) bv = (L != J || r <= c) ? Rinv[static_cast<int64_t>(gb) * k + gj] : 0.0;
-        else bv = T[static_cast<int64_t>(gb) * k + gj];
-      }
-      Ab[r][c] = av;
-      Bb[r][c] = bv;
+      const int ga = I * CM + r, gl = L * CM + c;  // left block (I, L)
+      const int gb = L * CM + r, gj = J * CM + c;  // right block (L, J)
+      const double a = Asrc[static_cast<int64_t>(min(ga, k - 1)) * k + min(gl, k - 1)];
+      const double b = Bsrc[static_cast<int64_t>(min(gb, k - 1)) * k + min(gj, k - 1)];
+      const bool aok = ga < k && gl < k && (PHASE == 0 || L != I || r <= c);
+      const bool bok = gb < k && gj < k && (PHASE == 1 || L != J || r <= c);
+      av[q] = aok ? a : 0.0;
+      bv[q] = bok ? b : 0.0;
+    }
+  };
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  fetch(l0);
+  for (int L = l0; L <= l1; ++L) {
+#pragma unroll
+    for (int q = 0; q < CM * CM / 256; ++q) {
+      const int e = t + 256 * q;
+      Ab[e / CM][e % CM] = av[q];
+      Bb[e / CM][e % CM] = bv[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int r = ty + 8 * u;
-      double sum = 0.0;
+    if (L < l1) fetch(L + 1);
+    // (each block's sum in increasing l, then added to the running sum)
+    double sum[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-      for (int l = 0; l < CM; ++l) sum += Ab[r][l] * Bb[l][tx];
-      acc[u] += sum;
+    for (int l = 0; l < CM; ++l) {
+      const double b = Bb[l][tx];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sum[u] += Ab[ty + 8 * u][l] * b;
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += sum[u];
     __syncthreads();
   }
 #pragma unroll
