@@ -137,7 +137,8 @@ def test_eigh_psd(m):
     assert np.abs(M @ V - V * theta).max() <= 1e-12 * ref[0] * max(1, np.sqrt(m))
 
 
-@pytest.mark.parametrize("m_k", [(220, 20), (90, 10), (12, 3), (480, 40), (640, 64), (1300, 100)])
+@pytest.mark.parametrize("m_k", [(220, 20), (224, 32), (225, 25), (90, 10), (12, 3), (3, 1),
+                                 (480, 40), (640, 64), (1300, 100)])
 def test_eigen_solvers_agree(m_k):
     """The Rayleigh-Ritz step through the tridiagonal reduction (default for
     moderate m) and through one-sided Jacobi (jacobi_block set) agree."""
