@@ -137,6 +137,30 @@ def test_eigh_psd(m):
     assert np.abs(M @ V - V * theta).max() <= 1e-12 * ref[0] * max(1, np.sqrt(m))
 
 
+def test_jacobi_sweep_cap_reports_enoconv():
+    """A sweep cap below what the matrix needs (forced from the host: the
+    kernels all end normally): the call returns BK_ENOCONV, through
+    eigh_psd and through the Jacobi route of a solve, and the next call with
+    the default cap converges."""
+    from paper_1504_05477_amd import _lib as L
+    rng = np.random.default_rng(11)
+    B = rng.standard_normal((95, 90)) * np.logspace(0, -3, 90)
+    M = B.T @ B
+    with pytest.raises(L.BKError) as e:
+        bk.eigh_psd(_cuda(M), max_sweeps=1)
+    assert e.value.status == L.ENOCONV
+    theta, V, sweeps = bk.eigh_psd(_cuda(M))
+    assert sweeps > 1
+    ref = np.linalg.eigvalsh(M)[::-1]
+    assert np.all(np.abs(theta.cpu().numpy() - ref) <= 1e-12 * ref[0])
+    A = workloads.planted_dense(300, 200, workloads.spectrum("inv_sqrt", 200), 12)
+    with pytest.raises(L.BKError) as e:
+        bk.svd_dense(_cuda(A), 10, 8, seed=3, jacobi_block=16, max_sweeps=1)
+    assert e.value.status == L.ENOCONV
+    res = bk.svd_dense(_cuda(A), 10, 8, seed=3, jacobi_block=16)
+    assert res.info["jacobi_sweeps"] > 1
+
+
 @pytest.mark.parametrize("m_k", [(220, 20), (224, 32), (225, 25), (90, 10), (12, 3), (3, 1),
                                  (480, 40), (640, 64), (1300, 100)])
 def test_eigen_solvers_agree(m_k):
